@@ -1,0 +1,279 @@
+"""ctypes front end of the C oracle plus the ACE algebra (TEST INFRASTRUCTURE).
+
+Conventions (shared with the inputs, not with any GPU code):
+  * grid point (ix, iy, iz) sits at h*(ix, iy, iz), x fastest;
+  * orbital arrays are orbital-major, shape (n_occ, Nz, Ny, Nx);
+  * <f, g> = h^3 sum f g (grid quadrature of the integral);
+  * pairs are (i <= j) with a cube domain {lo[3], n[3]} and the multipole
+    origin (Sec. II.B pair selection and domain truncation).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sea_oracle.c")
+_LIB = os.path.join(_HERE, "build", "libsea_oracle.so")
+_lib = None
+
+FD_HALF_ORDER = 6   # O(h^12) Laplacian (App. C)
+LMAX = 6            # multipole order (App. C)
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (OpenMP)."""
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                        "-Wall", "-Wno-unused-variable", "-o", tmp, _SRC, "-lm"],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        P = C.POINTER
+        d, i32, i = C.c_double, C.c_int32, C.c_int
+        lib.orc_fd_weights.argtypes = [i, P(d)]
+        lib.orc_build_pairs.argtypes = [P(i32), P(d), i, P(d), d, d, i, P(i32), P(d), P(i)]
+        lib.orc_real_ylm.argtypes = [i, d, d, d, P(d)]
+        lib.orc_real_ylm.restype = None
+        lib.orc_moments_points.argtypes = [i, i, P(d), P(d), P(d), P(d)]
+        lib.orc_moments_points.restype = None
+        lib.orc_me_eval.argtypes = [i, P(d), P(d), P(d)]
+        lib.orc_me_eval.restype = d
+        lib.orc_neg_lap_padded.argtypes = [P(i32), P(d), i, P(d), P(d)]
+        lib.orc_cg.argtypes = [P(i32), P(d), i, P(d), P(d), d, i, P(d)]
+        lib.orc_pair_potential.argtypes = [P(i32), P(d), i, P(d), P(i32), P(d), i, i, d, i,
+                                           P(d), P(d), P(d), P(d)]
+        lib.orc_exx.argtypes = [P(i32), P(d), i, P(d), i, P(i32), P(d), i, i, d, i, i,
+                                P(d), P(d), P(i32), P(d), P(d)]
+        lib.orc_cholesky.argtypes = [i, P(d), P(d)]
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _grid(N, L):
+    N3 = np.ascontiguousarray(np.broadcast_to(np.asarray(N, dtype=np.int32), (3,)))
+    L3 = np.ascontiguousarray(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)))
+    return N3, L3
+
+
+# ---------------------------------------------------------------------------
+
+def fd_weights(M: int = FD_HALF_ORDER) -> np.ndarray:
+    c = np.zeros(M + 1)
+    if _load().orc_fd_weights(M, _dp(c)):
+        raise ValueError("bad half order")
+    return c
+
+
+@dataclasses.dataclass
+class PairList:
+    ij: np.ndarray       # (n, 2) int32
+    lo: np.ndarray       # (n, 3) int32
+    n: np.ndarray        # (n, 3) int32
+    origin: np.ndarray   # (n, 3) float64
+
+    def __len__(self):
+        return self.ij.shape[0]
+
+    def packed(self) -> np.ndarray:
+        return np.ascontiguousarray(np.concatenate([self.ij, self.lo, self.n], axis=1).astype(np.int32))
+
+    def subset(self, idx) -> "PairList":
+        idx = np.asarray(idx)
+        return PairList(self.ij[idx].copy(), self.lo[idx].copy(), self.n[idx].copy(),
+                        self.origin[idx].copy())
+
+
+def build_pairs(N, L, centres, r_pair=6.0, half_width=6.0) -> PairList:
+    """Pair selection and pair domains (Sec. II.B; cube reading of the domain)."""
+    lib = _load()
+    N3, L3 = _grid(N, L)
+    cen = np.ascontiguousarray(centres, dtype=np.float64)
+    n_occ = cen.shape[0]
+    cap = n_occ * (n_occ + 1) // 2
+    out = np.zeros((max(cap, 1), 8), dtype=np.int32)
+    org = np.zeros((max(cap, 1), 3))
+    cnt = C.c_int(0)
+    st = lib.orc_build_pairs(_ip(N3), _dp(L3), n_occ, _dp(cen), r_pair, half_width, cap,
+                             _ip(out), _dp(org), C.byref(cnt))
+    if st != 0:
+        raise ValueError(f"orc_build_pairs failed ({st})")
+    k = cnt.value
+    return PairList(out[:k, 0:2].copy(), out[:k, 2:5].copy(), out[:k, 5:8].copy(), org[:k].copy())
+
+
+def real_ylm(lmax: int, v) -> np.ndarray:
+    out = np.zeros((lmax + 1) ** 2)
+    _load().orc_real_ylm(lmax, float(v[0]), float(v[1]), float(v[2]), _dp(out))
+    return out
+
+
+def moments_points(lmax, pos, q, origin) -> np.ndarray:
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    Q = np.zeros((lmax + 1) ** 2)
+    _load().orc_moments_points(lmax, pos.shape[0], _dp(pos), _dp(q), _dp(o), _dp(Q))
+    return Q
+
+
+def me_eval(lmax, Q, origin, target) -> float:
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    t = np.ascontiguousarray(target, dtype=np.float64)
+    return _load().orc_me_eval(lmax, _dp(Q), _dp(o), _dp(t))
+
+
+def neg_lap_padded(f_padded: np.ndarray, h, M: int = FD_HALF_ORDER) -> np.ndarray:
+    """-Lap_h on the interior of a padded (nz+2M, ny+2M, nx+2M) array."""
+    f = np.ascontiguousarray(f_padded, dtype=np.float64)
+    n = np.array([f.shape[2] - 2 * M, f.shape[1] - 2 * M, f.shape[0] - 2 * M], dtype=np.int32)
+    h3 = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (3,)))
+    out = np.zeros((n[2], n[1], n[0]))
+    if _load().orc_neg_lap_padded(_ip(n), _dp(h3), M, _dp(f), _dp(out)):
+        raise ValueError("bad half order")
+    return out
+
+
+def cg(b: np.ndarray, h, M: int = FD_HALF_ORDER, tol=1e-12, max_iter=10000, x0=None):
+    """Plain CG on -Lap_h x = b with zero values outside the interior (Eq. 9)."""
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    n = np.array([b.shape[2], b.shape[1], b.shape[0]], dtype=np.int32)
+    h3 = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (3,)))
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    info = np.zeros(2)
+    st = _load().orc_cg(_ip(n), _dp(h3), M, _dp(b), _dp(x), tol, max_iter, _dp(info))
+    return x, int(info[0]), float(info[1]), st
+
+
+def pair_potential(phi, N, L, pairs: PairList, k: int, tol=1e-12, max_iter=10000,
+                   M=FD_HALF_ORDER, lmax=LMAX, x0=None):
+    """Potential of pair k on its interior, plus (Q_lm, info dict)."""
+    lib = _load()
+    N3, L3 = _grid(N, L)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    pk = np.ascontiguousarray(pairs.packed()[k])
+    org = np.ascontiguousarray(pairs.origin[k])
+    n = pairs.n[k]
+    v = np.zeros((n[2], n[1], n[0]))
+    Q = np.zeros((lmax + 1) ** 2)
+    info = np.zeros(8)
+    x0p = None
+    if x0 is not None:
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        x0p = _dp(x0)
+    st = lib.orc_pair_potential(_ip(N3), _dp(L3), phi.shape[0], _dp(phi), _ip(pk), _dp(org), M,
+                                lmax, tol, max_iter, x0p, _dp(v), _dp(Q), _dp(info))
+    if st < 0:
+        raise ValueError("bad pair")
+    return v, Q, dict(iters=int(info[0]), rel_res=info[1], e=info[2], s_abs=info[3],
+                      q=info[4], bnorm=info[5], status=int(info[6]))
+
+
+@dataclasses.dataclass
+class ExxResult:
+    E: float
+    W: np.ndarray
+    e_pairs: np.ndarray
+    iters: np.ndarray
+    rel_res: np.ndarray
+    n_unconverged: int
+
+
+def exx(phi, N, L, pairs: PairList, tol=1e-12, max_iter=10000, M=FD_HALF_ORDER, lmax=LMAX,
+        n_threads=0) -> ExxResult:
+    """The whole V_xx action: W = D_xx (Eq. 13-14 on the pair domains), E (Eq. 8)."""
+    lib = _load()
+    N3, L3 = _grid(N, L)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    n_occ = phi.shape[0]
+    npairs = len(pairs)
+    packed = pairs.packed() if npairs else np.zeros((1, 8), np.int32)
+    org = np.ascontiguousarray(pairs.origin) if npairs else np.zeros((1, 3))
+    W = np.zeros_like(phi)
+    e = np.zeros(max(npairs, 1))
+    it = np.zeros(max(npairs, 1), dtype=np.int32)
+    rr = np.zeros(max(npairs, 1))
+    E = C.c_double(0.0)
+    st = lib.orc_exx(_ip(N3), _dp(L3), n_occ, _dp(phi), npairs, _ip(packed), _dp(org), M, lmax,
+                     tol, max_iter, n_threads, _dp(W), _dp(e), _ip(it), _dp(rr), C.byref(E))
+    if st < 0:
+        raise ValueError("bad pair list")
+    return ExxResult(E.value, W, e[:npairs], it[:npairs], rr[:npairs], st)
+
+
+def cholesky(A: np.ndarray):
+    """Lower Cholesky factor (own unblocked loops); returns (L, failed_pivot)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    Lo = np.zeros_like(A)
+    st = _load().orc_cholesky(n, _dp(A), _dp(Lo))
+    return Lo, int(st)
+
+
+# --------------------------- ACE (Eq. 18-19) -------------------------------
+
+@dataclasses.dataclass
+class AceResult:
+    M: np.ndarray      # h^3 Phi^T W (unsymmetrized)
+    Mbar: np.ndarray   # (M + M^T)/2
+    L: np.ndarray      # lower Cholesky factor of Mbar
+    xi: np.ndarray     # orbital-major (n_occ, Ng): xi = W L^{-T}
+    failed_pivot: int
+
+
+def ace_build(phi, W, dV) -> AceResult:
+    """M = <phi_i, W_j>, symmetrize (App. A), Cholesky, xi = W L^{-T} (Eq. 18)."""
+    import scipy.linalg as sla
+    P = phi.reshape(phi.shape[0], -1)
+    Wm = W.reshape(W.shape[0], -1)
+    M = dV * (P @ Wm.T)
+    Mbar = 0.5 * (M + M.T)
+    Lo, fail = cholesky(Mbar)
+    if fail:
+        return AceResult(M, Mbar, Lo, np.zeros_like(Wm), fail)
+    # xi (grid-major) = W L^{-T}  <=>  xi^T = L^{-1} W^T (orbital-major)
+    xi = sla.solve_triangular(Lo, Wm, lower=True, check_finite=False)
+    return AceResult(M, Mbar, Lo, xi, 0)
+
+
+def ace_apply(xi, psi, dV) -> np.ndarray:
+    """K psi = -xi (h^3 xi^T psi), orbital-major in and out (Eq. 18)."""
+    X = xi.reshape(xi.shape[0], -1)
+    Pm = psi.reshape(psi.shape[0], -1)
+    Cm = dV * (X @ Pm.T)            # (n_occ, n_vec)
+    return -(Cm.T @ X).reshape(psi.shape)
+
+
+def ace_energy(phi, xi, dV) -> float:
+    """E = -sum_ik <phi_i, xi_k>^2 (Eq. 19)."""
+    P = phi.reshape(phi.shape[0], -1)
+    X = xi.reshape(xi.shape[0], -1)
+    S = dV * (P @ X.T)
+    return -float(np.sum(S * S))
