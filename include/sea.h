@@ -1,0 +1,210 @@
+/*
+ * sea.h - C ABI of the MI355X (gfx950) library for the exact-exchange action
+ * on localized orbitals and the ACE low-rank build (the "exx" and "decomp"
+ * steps of the SeA approach, arXiv 2208.06097).
+ *
+ * Conventions used by every call
+ *   - Grid: periodic orthorhombic cell of n[0] x n[1] x n[2] points, spacing
+ *     h[a] = L[a]/n[a], point (ix,iy,iz) at (ix*h0, iy*h1, iz*h2), x fastest.
+ *   - Orbital arrays (phi, W, xi, psi) are orbital-major device arrays:
+ *     element (k, iz, iy, ix) at k*Ng + (iz*n1 + iy)*n0 + ix, Ng = n0*n1*n2.
+ *   - Inner product <f,g> = dV * sum f g, dV = h0*h1*h2 (grid quadrature).
+ *   - Atomic units (hartree, bohr); Poisson equation Lap v = -4 pi rho.
+ *   - Device pointers are plain HIP device addresses owned by the caller; the
+ *     library never frees them and allocates no device memory on the exx or
+ *     ACE paths: scratch space is the caller's workspace, sized by the
+ *     *_workspace_bytes calls.
+ *   - All device work is enqueued on opts.hip_stream (NULL = default stream).
+ *     A call blocks the host only when it returns host results (exx_host,
+ *     stats_host, loss_host, failed_pivot).
+ *   - Every call returns sea_status: 0 = OK, > 0 = warning (outputs written),
+ *     < 0 = error (nothing reliable written).  sea_last_error() gives the
+ *     context's last message.  Arguments are validated before any launch.
+ */
+#ifndef SEA_H
+#define SEA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SEA_OK = 0,
+    SEA_W_NOT_CONVERGED = 1, /* some pair hit max_iter; outputs still written */
+    SEA_E_ARG = -1,          /* invalid argument (message says which)          */
+    SEA_E_HIP = -2,          /* HIP runtime error                               */
+    SEA_E_NOMEM = -3,        /* workspace smaller than *_workspace_bytes        */
+    SEA_E_NOT_PD = -4,       /* symmetrized M not positive definite (ACE)       */
+    SEA_E_NONFINITE = -5     /* NaN/Inf in an input or a reduction              */
+} sea_status;
+
+typedef enum { SEA_F64 = 0, SEA_F32 = 1, SEA_BF16 = 2 } sea_dtype;
+
+/* Initial guess of each pair's CG solve.  The stopping rule (relative true
+ * residual) does not depend on the start. */
+typedef enum {
+    SEA_START_ZERO = 0,      /* x0 = 0                                          */
+    SEA_START_MULTIPOLE = 1, /* x0 = regularized multipole potential (Eq. 10)   */
+    SEA_START_LEARNED = 2    /* x0 from the 3-D convolutional network           */
+} sea_start;
+
+typedef struct {
+    int32_t n[3];
+    double L[3];
+} sea_grid;
+
+/* One kept orbital pair <ij> (Sec. II.B): i <= j, and its truncated domain,
+ * the box of n[0] x n[1] x n[2] interior points starting at grid index lo[]
+ * (lo may be negative or beyond the cell: indices wrap periodically), plus
+ * the multipole origin (bohr, unwrapped coordinates). */
+typedef struct {
+    int32_t i, j;
+    int32_t lo[3];
+    int32_t n[3];
+    double origin[3];
+} sea_pair;
+
+typedef struct {
+    int32_t fd_half_order;  /* 6: O(h^12) Laplacian (App. C); only 6 accepted  */
+    int32_t lmax;           /* 6: multipole order (App. C); 0..6 accepted      */
+    double rel_tol;         /* CG stop: |b - A x|_2 <= rel_tol |b|_2           */
+    int32_t max_iter;       /* CG iteration cap per pair                       */
+    sea_dtype stencil_dtype;/* CG state precision: SEA_F64 or SEA_F32          */
+    sea_dtype ace_dtype;    /* xi / K psi GEMM inputs: F64, F32 or BF16        */
+    sea_start start;        /* CG initial guess                                */
+    int32_t refine_period;  /* F32 state: FP64 true-residual refresh period    */
+    int32_t profile;        /* non-zero: time each stage with HIP events       */
+    void *hip_stream;       /* hipStream_t; NULL = default stream              */
+} sea_opts;
+
+/* Stages timed when opts.profile is set (indices into sea_stage_times). */
+typedef enum {
+    SEA_STAGE_GATHER = 0,   /* pair density, b = 4 pi rho, multipole moments   */
+    SEA_STAGE_BOUNDARY = 1, /* multipole boundary values folded into b         */
+    SEA_STAGE_GUESS = 2,    /* initial guess (multipole or learned start)      */
+    SEA_STAGE_CG = 3,       /* CG solves (the hot loop)                        */
+    SEA_STAGE_SCATTER = 4,  /* W accumulation                                  */
+    SEA_STAGE_ENERGY = 5,   /* E_xx reduction                                  */
+    SEA_STAGE_ACE_M = 6,    /* M = dV Phi^T W and symmetrization               */
+    SEA_STAGE_ACE_CHOL = 7, /* Cholesky and L^{-1}                             */
+    SEA_STAGE_ACE_XI = 8,   /* xi = W L^{-T}                                   */
+    SEA_STAGE_ACE_APPLY = 9,/* K psi                                           */
+    SEA_STAGE_COUNT = 10
+} sea_stage;
+
+/* Per-pair diagnostics (Eq. 8 and Eq. 17 quantities on the pair domain). */
+typedef struct {
+    int32_t iters;          /* CG iterations                                   */
+    int32_t converged;      /* 1 if the true residual met rel_tol              */
+    double rel_res;         /* final true relative residual                    */
+    double e_ij;            /* dV sum rho_ij v_ij                              */
+    double s_abs;           /* dV sum |rho_ij|  (Eq. 17)                       */
+    double q;               /* dV sum rho_ij (pair charge)                     */
+} sea_pair_stat;
+
+typedef struct sea_ctx sea_ctx;
+
+/* Library version string (static storage). */
+const char *sea_version(void);
+
+/* Fill *o with the defaults: half order 6, lmax 6, rel_tol 1e-8,
+ * max_iter 10000, F64 stencil and ACE, zero start, refine_period 50,
+ * profiling off. */
+void sea_opts_default(sea_opts *o);
+
+/* Create a context on the current HIP device.  The context owns only host
+ * state (options, error text, tuning cache, network weights).  Errors:
+ * SEA_E_ARG for a NULL out pointer or unsupported options, SEA_E_HIP when no
+ * gfx950 device is current. */
+sea_status sea_create(const sea_opts *opts, sea_ctx **out);
+sea_status sea_destroy(sea_ctx *ctx);
+const char *sea_last_error(const sea_ctx *ctx);
+/* Replace the options of an existing context (validated as in sea_create). */
+sea_status sea_set_opts(sea_ctx *ctx, const sea_opts *opts);
+
+/* Pair selection and pair domains (Sec. II.B), host only.  Keeps (i <= j)
+ * when the minimum-image distance |c_j - c_i| < r_pair (self pairs always);
+ * the domain is the cube of w = ceil(half_width/h) points on each side of the
+ * grid point nearest to the minimum-image midpoint c_i + (c_j - c_i)/2
+ * (floor(m/h + 0.5) per axis, not wrapped), and the multipole origin is that
+ * grid point.  Pairs are written in (i, j) lexicographic order.
+ * centers_host: n_occ x 3 doubles.  Returns SEA_E_NOMEM (with *n_out set to
+ * the full count) when cap is too small. */
+sea_status sea_build_pairs(const sea_grid *grid, int n_occ, const double *centers_host,
+                           double r_pair, double half_width, sea_pair *out, int cap,
+                           int *n_out);
+
+/* Device workspace needed by sea_exx_action / sea_exx_pair_solve for this
+ * pair list (bytes, 256-byte aligned). */
+sea_status sea_exx_workspace_bytes(sea_ctx *ctx, const sea_grid *grid, int n_occ, int n_pairs,
+                                   const sea_pair *pairs_host, size_t *bytes);
+
+/* The V_xx action on localized orbitals (Eq. 8-14): for every pair, the pair
+ * density rho_ij = phi_i phi_j on its domain (wrapped indices), its multipole
+ * moments (Eq. 11, l <= lmax), boundary values on the ghost layers the
+ * stencil reaches (Eq. 10), the CG solve of -Lap_h v = 4 pi rho (Eq. 9) to
+ * the relative true residual rel_tol, then
+ *     W_i = sum_{j in <ij>} v_ij phi_j  on the pair domains (Eq. 14),
+ *     E_xx = -sum_i e_ii - 2 sum_{i<j} e_ij  (Eq. 8 over ordered pairs).
+ * phi_dev: n_occ x Ng of phi_dtype (SEA_F64 or SEA_F32).  W_dev: n_occ x Ng
+ * FP64, overwritten.  exx_dev: device FP64 scalar (nullable).  exx_host and
+ * stats_host (n_pairs entries) are nullable; when given the call syncs the
+ * stream.  The scatter is owner-computes in pair order: W is bit-identical
+ * run to run.  Returns SEA_W_NOT_CONVERGED if any pair hit max_iter. */
+sea_status sea_exx_action(sea_ctx *ctx, const sea_grid *grid, int n_occ, const void *phi_dev,
+                          sea_dtype phi_dtype, int n_pairs, const sea_pair *pairs_host,
+                          void *ws_dev, size_t ws_bytes, double *W_dev, double *exx_dev,
+                          double *exx_host, sea_pair_stat *stats_host);
+
+/* Per-pair potentials without the scatter (same solve as sea_exx_action):
+ * v_dev receives, for pair k, its interior potential at offset k*stride
+ * doubles (stride = max over pairs of n0*n1*n2 rounded up to a multiple of
+ * 32, layout [z][y][x]); Q_dev
+ * (nullable) receives 49 real orthonormal multipole moments per pair
+ * (index l*l + l + m, Eq. 11 with real Y_lm); e_dev (nullable) e_ij. */
+sea_status sea_exx_pair_solve(sea_ctx *ctx, const sea_grid *grid, int n_occ, const void *phi_dev,
+                              sea_dtype phi_dtype, int n_pairs, const sea_pair *pairs_host,
+                              void *ws_dev, size_t ws_bytes, double *v_dev, double *Q_dev,
+                              double *e_dev, sea_pair_stat *stats_host);
+
+/* ACE build (Eq. 18, App. A): M = dV Phi^T W (FP64), Mbar = (M + M^T)/2,
+ * Mbar = L L^T (FP64 Cholesky, no pivoting), xi = W L^{-T} stored
+ * orbital-major in ace_dtype.  M_dev, L_dev: n_occ x n_occ row-major FP64
+ * (L lower, upper triangle zero).  On a non-positive pivot returns
+ * SEA_E_NOT_PD and *failed_pivot = 1-based pivot index (0 on success).
+ * ws_dev: sea_ace_workspace_bytes bytes. */
+sea_status sea_ace_workspace_bytes(sea_ctx *ctx, int64_t n_grid, int n_occ, int n_vec,
+                                   size_t *bytes);
+sea_status sea_ace_build(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, const double *phi_dev,
+                         const double *W_dev, void *ws_dev, size_t ws_bytes, double *M_dev,
+                         double *L_dev, void *xi_dev, int *failed_pivot);
+
+/* K psi = -xi (dV xi^T psi)  (Eq. 18): psi_dev, out_dev n_vec x n_grid in
+ * ace_dtype (BF16 uses FP32 output), xi_dev from sea_ace_build.  FP32
+ * accumulation for F32/BF16, FP64 for F64. */
+sea_status sea_ace_apply(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, const void *xi_dev,
+                         int n_vec, const void *psi_dev, void *ws_dev, size_t ws_bytes,
+                         void *out_dev);
+
+/* E_xx = -sum_ik <phi_i, xi_k>^2 (Eq. 19), FP64 result on the host. */
+sea_status sea_ace_energy(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, const double *phi_dev,
+                          const void *xi_dev, void *ws_dev, size_t ws_bytes, double *exx_host);
+
+/* Milliseconds spent in each stage by the most recent profiled call that
+ * ran it (HIP events on opts.hip_stream; waits for those events).  ms_out
+ * holds SEA_STAGE_COUNT floats; stages not run by that call read 0. */
+sea_status sea_stage_times(sea_ctx *ctx, float *ms_out);
+
+/* Host evaluation of r^l Y_lm (real orthonormal, index l*l + l + m) at the
+ * vector (x, y, z) by the same Cartesian recurrence the GPU kernels use;
+ * out holds (lmax+1)^2 doubles.  lmax <= 6. */
+sea_status sea_solid_harmonics_host(int lmax, double x, double y, double z, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEA_H */

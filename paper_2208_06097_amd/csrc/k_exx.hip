@@ -1,0 +1,460 @@
+// exx kernels for gfx950: pair-density gather with multipole moments,
+// ghost-layer boundary values, CG Poisson solve per pair, owner-computes
+// scatter of the action, and the energy sum.
+//
+// Pair-domain arrays (b, v and the CG state) are stored compactly as
+// [z][y][x] over the interior (n0*n1*n2 points), one array of `stride`
+// doubles per pair (b, v) or per CG slot (r, p, q).
+#include "harmonics.h"
+#include "sea_internal.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// O(h^12) central second-difference weights (half order 6):
+// f'' ~ h^-2 (c0 f0 + sum_k ck (f_k + f_-k)).
+__constant__ double kC[7] = {-5369.0 / 1800.0, 12.0 / 7.0,      -15.0 / 56.0,     10.0 / 189.0,
+                             -1.0 / 112.0,     2.0 / 1925.0,    -1.0 / 16632.0};
+
+__device__ __forceinline__ int wrap_idx(int k, int N) {
+    int m = k % N;
+    return m < 0 ? m + N : m;
+}
+
+__device__ __forceinline__ double load_phi(const void* phi, int f32, size_t off) {
+    return f32 ? (double)(((const float*)phi)[off]) : ((const double*)phi)[off];
+}
+
+// Deterministic block sum of one double (fixed shuffle tree, then LDS).
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+        double t = (lane < BS / 64) ? lds[lane] : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        if (lane == 0) lds[BS / 64] = t;
+    }
+    __syncthreads();
+    const double r = lds[BS / 64];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// 1. gather rho_ij, write b = 4 pi rho, partial Racah moments per chunk
+
+constexpr int GM_BS = 256;
+constexpr int GM_CHUNK = 4096;
+
+template <int LM>
+__global__ __launch_bounds__(GM_BS) void k_gather_moments(ExxArgs a) {
+    __shared__ double red[GM_BS / 64 + 1];
+    const int pid = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const long n_int = (long)nx * ny * nz;
+    const long beg = (long)chunk * GM_CHUNK;
+    double acc[SEA_NACC];
+#pragma unroll
+    for (int k = 0; k < SEA_NACC; ++k) acc[k] = 0.0;
+    if (beg < n_int) {
+        const long end = min(beg + GM_CHUNK, n_int);
+        const size_t oi = (size_t)P.i * a.Ng, oj = (size_t)P.j * a.Ng;
+        double* b = a.b + (size_t)pid * a.stride;
+        for (long id = beg + threadIdx.x; id < end; id += GM_BS) {
+            const int x = (int)(id % nx);
+            const int y = (int)((id / nx) % ny);
+            const int z = (int)(id / ((long)nx * ny));
+            const size_t g = ((size_t)wrap_idx(P.lo[2] + z, a.N[2]) * a.N[1] + wrap_idx(P.lo[1] + y, a.N[1])) * a.N[0]
+                             + wrap_idx(P.lo[0] + x, a.N[0]);
+            const double rho = load_phi(a.phi, a.phi_f32, oi + g) * load_phi(a.phi, a.phi_f32, oj + g);
+            b[id] = 4.0 * kPi * rho;
+            const double dx = (P.lo[0] + x) * a.h[0] - P.origin[0];
+            const double dy = (P.lo[1] + y) * a.h[1] - P.origin[1];
+            const double dz = (P.lo[2] + z) * a.h[2] - P.origin[2];
+            double R[(LM + 1) * (LM + 1)];
+            racah_solid<LM>(dx, dy, dz, R);
+#pragma unroll
+            for (int k = 0; k < (LM + 1) * (LM + 1); ++k) acc[k] += rho * R[k];
+            acc[SEA_NMOM] += fabs(rho);
+            acc[SEA_NMOM + 1] += rho;
+            acc[SEA_NMOM + 2] += fabs(rho) * (dx * dx + dy * dy + dz * dz);
+        }
+    }
+    double* out = a.partial + ((size_t)pid * a.n_chunks + chunk) * SEA_NACC;
+#pragma unroll
+    for (int k = 0; k < SEA_NACC; ++k) {
+        const double s = block_sum<GM_BS>(acc[k], red);
+        if (threadIdx.x == 0) out[k] = s;
+    }
+}
+
+// 2. sum the chunk partials in chunk order; optional orthonormal copy
+__global__ void k_moments_final(ExxArgs a, double* Q_orth) {
+    const int pid = blockIdx.x;
+    const int k = threadIdx.x;
+    if (k >= SEA_NACC) return;
+    const sea_pair P = a.pairs[pid];
+    const long n_int = (long)P.n[0] * P.n[1] * P.n[2];
+    const int used = (int)((n_int + GM_CHUNK - 1) / GM_CHUNK);
+    double s = 0.0;
+    for (int c = 0; c < used; ++c) s += a.partial[((size_t)pid * a.n_chunks + c) * SEA_NACC + k];
+    s *= a.dV;
+    if (k < SEA_NMOM) {
+        int l = 0;
+        while ((l + 1) * (l + 1) <= k) ++l;
+        if (l > a.lmax) s = 0.0;
+    }
+    a.mom[(size_t)pid * SEA_NACC + k] = s;
+    if (Q_orth && k < SEA_NMOM) {
+        int l = 0;
+        while ((l + 1) * (l + 1) <= k) ++l;
+        const int m = k - l * l - l;
+        Q_orth[(size_t)pid * SEA_NMOM + k] = s * racah_to_orthonormal(l, m);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. boundary values: b += sum over ghost taps (c_k / h_a^2) v_ME(ghost)
+
+constexpr int BF_BS = 256;
+
+template <int LM>
+__global__ __launch_bounds__(BF_BS) void k_boundary_fold(ExxArgs a) {
+    __shared__ double Q[SEA_NMOM];
+    const int pid = blockIdx.y;
+    const int z = blockIdx.x;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    if (threadIdx.x < SEA_NMOM) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
+    __syncthreads();
+    if (z >= nz) return;
+    const bool zface = (z < SEA_HALO) || (z >= nz - SEA_HALO);
+    double* b = a.b + (size_t)pid * a.stride + (size_t)z * nx * ny;
+    const double ih2[3] = {1.0 / (a.h[0] * a.h[0]), 1.0 / (a.h[1] * a.h[1]), 1.0 / (a.h[2] * a.h[2])};
+    for (int t = threadIdx.x; t < nx * ny; t += BF_BS) {
+        const int x = t % nx, y = t / nx;
+        const bool near = zface || x < SEA_HALO || x >= nx - SEA_HALO || y < SEA_HALO || y >= ny - SEA_HALO;
+        if (!near) continue;
+        const int pos[3] = {x, y, z};
+        const int nn[3] = {nx, ny, nz};
+        double acc = 0.0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+            for (int k = 1; k <= SEA_HALO; ++k) {
+#pragma unroll
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    const int q = pos[ax] + sg * k;
+                    if (q >= 0 && q < nn[ax]) continue;
+                    int gp[3] = {x, y, z};
+                    gp[ax] = q;
+                    const double dx = (P.lo[0] + gp[0]) * a.h[0] - P.origin[0];
+                    const double dy = (P.lo[1] + gp[1]) * a.h[1] - P.origin[1];
+                    const double dz = (P.lo[2] + gp[2]) * a.h[2] - P.origin[2];
+                    acc += kC[k] * ih2[ax] * racah_me_potential<LM>(Q, a.lmax, dx, dy, dz);
+                }
+            }
+        }
+        b[t] += acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. CG on A v = b, A = -Lap_h on the interior (zero outside), one workgroup
+//    per pair, persistent over the pair list.
+
+constexpr int CG_BS = 256;
+
+struct StencilW {
+    double diag;
+    double wx[7], wy[7], wz[7];
+};
+
+__device__ __forceinline__ StencilW make_weights(const double* h) {
+    StencilW w;
+    const double ix = 1.0 / (h[0] * h[0]), iy = 1.0 / (h[1] * h[1]), iz = 1.0 / (h[2] * h[2]);
+    w.diag = -kC[0] * (ix + iy + iz);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        w.wx[k] = -kC[k] * ix;
+        w.wy[k] = -kC[k] * iy;
+        w.wz[k] = -kC[k] * iz;
+    }
+    return w;
+}
+
+__device__ __forceinline__ double apply_A_pt(const double* __restrict__ p, long id, int x, int y, int z,
+                                             int nx, int ny, int nz, const StencilW& w) {
+    const long sy = nx, sz = (long)nx * ny;
+    double s = w.diag * p[id];
+#pragma unroll
+    for (int k = 1; k <= SEA_HALO; ++k) {
+        const double ax = (x - k >= 0 ? p[id - k] : 0.0) + (x + k < nx ? p[id + k] : 0.0);
+        const double ay = (y - k >= 0 ? p[id - k * sy] : 0.0) + (y + k < ny ? p[id + k * sy] : 0.0);
+        const double az = (z - k >= 0 ? p[id - k * sz] : 0.0) + (z + k < nz ? p[id + k * sz] : 0.0);
+        s += w.wx[k] * ax + w.wy[k] * ay + w.wz[k] * az;
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(CG_BS) void k_cg_f64(ExxArgs a) {
+    __shared__ double red[CG_BS / 64 + 1];
+    const StencilW w = make_weights(a.h);
+    double* r = a.slots + (size_t)blockIdx.x * 3 * a.stride;
+    double* p = r + a.stride;
+    double* q = p + a.stride;
+    const double tol2 = a.rel_tol * a.rel_tol;
+    for (int pid = blockIdx.x; pid < a.n_pairs; pid += gridDim.x) {
+        const sea_pair P = a.pairs[pid];
+        const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+        const long n = (long)nx * ny * nz;
+        const long nxy = (long)nx * ny;
+        const double* b = a.b + (size_t)pid * a.stride;
+        double* x = a.v + (size_t)pid * a.stride;
+
+        // bnorm^2, and x0 = 0
+        double bb = 0.0;
+        for (long id = threadIdx.x; id < n; id += CG_BS) {
+            const double t = b[id];
+            bb += t * t;
+            x[id] = 0.0;
+        }
+        bb = block_sum<CG_BS>(bb, red);
+        int it = 0;
+        double rel = 0.0;
+        int conv = 0;
+        if (!(bb > 0.0)) {
+            conv = (bb == 0.0) ? 1 : -1;
+        } else {
+            bool restart = true;
+            double rr = 0.0;
+            for (;;) {
+                if (restart) {
+                    // r = b - A x, p = r
+                    double t2 = 0.0;
+                    for (long id = threadIdx.x; id < n; id += CG_BS) {
+                        const int xx = (int)(id % nx), yy = (int)((id / nx) % ny), zz = (int)(id / nxy);
+                        const double ri = b[id] - apply_A_pt(x, id, xx, yy, zz, nx, ny, nz, w);
+                        r[id] = ri;
+                        p[id] = ri;
+                        t2 += ri * ri;
+                    }
+                    rr = block_sum<CG_BS>(t2, red);
+                    rel = sqrt(rr / bb);
+                    if (!(rr == rr)) { conv = -1; break; }
+                    if (rr <= tol2 * bb) { conv = 1; break; }
+                    if (it >= a.max_iter) { conv = 0; break; }
+                    restart = false;
+                }
+                // q = A p, pq
+                double pq = 0.0;
+                for (long id = threadIdx.x; id < n; id += CG_BS) {
+                    const int xx = (int)(id % nx), yy = (int)((id / nx) % ny), zz = (int)(id / nxy);
+                    const double qi = apply_A_pt(p, id, xx, yy, zz, nx, ny, nz, w);
+                    q[id] = qi;
+                    pq += p[id] * qi;
+                }
+                pq = block_sum<CG_BS>(pq, red);
+                const double alpha = rr / pq;
+                double rn = 0.0;
+                for (long id = threadIdx.x; id < n; id += CG_BS) {
+                    x[id] += alpha * p[id];
+                    const double ri = r[id] - alpha * q[id];
+                    r[id] = ri;
+                    rn += ri * ri;
+                }
+                rn = block_sum<CG_BS>(rn, red);
+                ++it;
+                if (rn <= tol2 * bb || it >= a.max_iter || !(rn == rn)) {
+                    restart = true;   // verify with the true residual
+                    continue;
+                }
+                const double beta = rn / rr;
+                rr = rn;
+                for (long id = threadIdx.x; id < n; id += CG_BS) p[id] = r[id] + beta * p[id];
+                __syncthreads();
+            }
+        }
+        // e_ij = dV sum rho v with rho gathered again
+        const size_t oi = (size_t)P.i * a.Ng, oj = (size_t)P.j * a.Ng;
+        double e = 0.0;
+        for (long id = threadIdx.x; id < n; id += CG_BS) {
+            const int xx = (int)(id % nx), yy = (int)((id / nx) % ny), zz = (int)(id / nxy);
+            const size_t g = ((size_t)wrap_idx(P.lo[2] + zz, a.N[2]) * a.N[1] + wrap_idx(P.lo[1] + yy, a.N[1])) * a.N[0]
+                             + wrap_idx(P.lo[0] + xx, a.N[0]);
+            e += load_phi(a.phi, a.phi_f32, oi + g) * load_phi(a.phi, a.phi_f32, oj + g) * x[id];
+        }
+        e = block_sum<CG_BS>(e, red);
+        if (threadIdx.x == 0) {
+            DevStat st;
+            st.iters = it;
+            st.converged = conv;
+            st.rel_res = rel;
+            st.e_ij = a.dV * e;
+            st.s_abs = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM];
+            st.q = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM + 1];
+            a.stats[pid] = st;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 5. owner-computes scatter: W_o(g) = sum over o's pairs (pair order) of
+//    v_pair(g - lo) phi_other(g), every domain duplicate of g included.
+
+constexpr int SC_BS = 256;
+constexpr int SC_TX = 64, SC_TY = 4, SC_TZ = 4;
+constexpr int SC_MAXE = 512;
+
+__device__ __forceinline__ bool axis_hits(int t0, int T, int lo, int n, int N) {
+    if (n >= N) return true;
+    const int s = wrap_idx(t0 - lo, N);
+    return s < n || s + T > N;
+}
+
+__global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const int* __restrict__ off,
+                                                   const int2* __restrict__ ent, double* __restrict__ W) {
+    __shared__ int list[SC_MAXE];
+    __shared__ int cnt;
+    const int o = blockIdx.y;
+    const int tiles_x = (a.N[0] + SC_TX - 1) / SC_TX;
+    const int tiles_y = (a.N[1] + SC_TY - 1) / SC_TY;
+    const int t = blockIdx.x;
+    const int tx0 = (t % tiles_x) * SC_TX;
+    const int ty0 = ((t / tiles_x) % tiles_y) * SC_TY;
+    const int tz0 = (t / (tiles_x * tiles_y)) * SC_TZ;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int e0 = off[o], e1 = off[o + 1];
+    // cull in chunks of SC_BS, preserving pair order
+    double acc[SC_TX * SC_TY * SC_TZ / SC_BS];
+#pragma unroll
+    for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) acc[k] = 0.0;
+    for (int c0 = e0; c0 < e1; c0 += SC_MAXE) {
+        const int c1 = min(e1, c0 + SC_MAXE);
+        // ordered compaction: thread 0 walks the entries (lists are short)
+        if (threadIdx.x == 0) {
+            int m = 0;
+            for (int e = c0; e < c1; ++e) {
+                const sea_pair P = a.pairs[ent[e].x];
+                if (axis_hits(tx0, SC_TX, P.lo[0], P.n[0], a.N[0]) && axis_hits(ty0, SC_TY, P.lo[1], P.n[1], a.N[1]) &&
+                    axis_hits(tz0, SC_TZ, P.lo[2], P.n[2], a.N[2]))
+                    list[m++] = e;
+            }
+            cnt = m;
+        }
+        __syncthreads();
+        const int m = cnt;
+#pragma unroll
+        for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) {
+            const int lid = threadIdx.x + k * SC_BS;
+            const int gx = tx0 + lid % SC_TX, gy = ty0 + (lid / SC_TX) % SC_TY, gz = tz0 + lid / (SC_TX * SC_TY);
+            if (gx >= a.N[0] || gy >= a.N[1] || gz >= a.N[2]) continue;
+            const size_t g = ((size_t)gz * a.N[1] + gy) * a.N[0] + gx;
+            double s = acc[k];
+            for (int q = 0; q < m; ++q) {
+                const int2 en = ent[list[q]];
+                const sea_pair P = a.pairs[en.x];
+                const double* v = a.v + (size_t)en.x * a.stride;
+                const double ph = load_phi(a.phi, a.phi_f32, (size_t)en.y * a.Ng + g);
+                for (int lz = wrap_idx(gz - P.lo[2], a.N[2]); lz < P.n[2]; lz += a.N[2])
+                    for (int ly = wrap_idx(gy - P.lo[1], a.N[1]); ly < P.n[1]; ly += a.N[1])
+                        for (int lx = wrap_idx(gx - P.lo[0], a.N[0]); lx < P.n[0]; lx += a.N[0])
+                            s += v[((size_t)lz * P.n[1] + ly) * P.n[0] + lx] * ph;
+            }
+            acc[k] = s;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) {
+        const int lid = threadIdx.x + k * SC_BS;
+        const int gx = tx0 + lid % SC_TX, gy = ty0 + (lid / SC_TX) % SC_TY, gz = tz0 + lid / (SC_TX * SC_TY);
+        if (gx >= a.N[0] || gy >= a.N[1] || gz >= a.N[2]) continue;
+        W[(size_t)o * a.Ng + ((size_t)gz * a.N[1] + gy) * a.N[0] + gx] = acc[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 6. E = -sum_i e_ii - 2 sum_{i<j} e_ij, plus counters, in a fixed order.
+//    out[0] = E, out[1] = #not converged, out[2] = #nonfinite.
+
+constexpr int ES_BS = 256;
+
+__global__ __launch_bounds__(ES_BS) void k_energy_sum(ExxArgs a, double* out, double* exx_dev, double* e_dev) {
+    __shared__ double red[ES_BS / 64 + 1];
+    double e = 0.0, nc = 0.0, nf = 0.0;
+    for (int k = threadIdx.x; k < a.n_pairs; k += ES_BS) {
+        const DevStat st = a.stats[k];
+        const sea_pair P = a.pairs[k];
+        e -= (P.i == P.j ? 1.0 : 2.0) * st.e_ij;
+        nc += (st.converged == 0) ? 1.0 : 0.0;
+        nf += (st.converged < 0 || !(st.e_ij == st.e_ij)) ? 1.0 : 0.0;
+        if (e_dev) e_dev[k] = st.e_ij;
+    }
+    e = block_sum<ES_BS>(e, red);
+    nc = block_sum<ES_BS>(nc, red);
+    nf = block_sum<ES_BS>(nf, red);
+    if (threadIdx.x == 0) {
+        out[0] = e;
+        out[1] = nc;
+        out[2] = nf;
+        if (exx_dev) *exx_dev = e;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+
+int exx_n_chunks(long n_int_max) { return (int)((n_int_max + GM_CHUNK - 1) / GM_CHUNK); }
+
+hipError_t launch_gather_moments(const ExxArgs& a, hipStream_t s) {
+    dim3 grid(a.n_chunks, a.n_pairs);
+    hipLaunchKernelGGL(k_gather_moments<SEA_LMAX>, grid, dim3(GM_BS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments_final, dim3(a.n_pairs), dim3(64), 0, s, a, Q_orth);
+    return hipGetLastError();
+}
+
+hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s) {
+    dim3 grid(nz_max, a.n_pairs);
+    hipLaunchKernelGGL(k_boundary_fold<SEA_LMAX>, grid, dim3(BF_BS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg(const ExxArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_f64, dim3(a.n_slots), dim3(CG_BS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const ExxArgs& a, const int* csr_off, const int2* csr_ent, double* W, hipStream_t s) {
+    const int tiles = ((a.N[0] + SC_TX - 1) / SC_TX) * ((a.N[1] + SC_TY - 1) / SC_TY) * ((a.N[2] + SC_TZ - 1) / SC_TZ);
+    dim3 grid(tiles, a.n_occ);
+    hipLaunchKernelGGL(k_scatter, grid, dim3(SC_BS), 0, s, a, csr_off, csr_ent, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_sum(const ExxArgs& a, double* out_scalars, double* exx_dev, double* e_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(ES_BS), 0, s, a, out_scalars, exx_dev, e_dev);
+    return hipGetLastError();
+}
+
+void solid_harmonics_orthonormal_host(int lmax, double x, double y, double z, double* out) {
+    double R[SEA_NMOM];
+    racah_solid<SEA_LMAX>(x, y, z, R);
+    for (int l = 0; l <= lmax; ++l)
+        for (int m = -l; m <= l; ++m) out[l * l + l + m] = R[l * l + l + m] * racah_to_orthonormal(l, m);
+}

@@ -1,0 +1,551 @@
+// C ABI of libsea: argument validation, workspace layout, orchestration of
+// the exx kernels on the caller's stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "sea_internal.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+sea_status fail(sea_ctx* ctx, sea_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+sea_status fail(sea_ctx* ctx, sea_status st, const char* fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+#define SEA_HIP_CHECK(ctx, expr)                                                                 \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(ctx, SEA_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+double minimg(double d, double L) { return d - L * std::nearbyint(d / L); }
+
+sea_status check_opts(sea_ctx* ctx, const sea_opts* o) {
+    if (!o) return fail(ctx, SEA_E_ARG, "opts is NULL");
+    if (o->fd_half_order != 6) return fail(ctx, SEA_E_ARG, "fd_half_order must be 6 (O(h^12) Laplacian)");
+    if (o->lmax < 0 || o->lmax > SEA_LMAX) return fail(ctx, SEA_E_ARG, "lmax must be in 0..%d", SEA_LMAX);
+    if (!(o->rel_tol > 0.0) || !std::isfinite(o->rel_tol)) return fail(ctx, SEA_E_ARG, "rel_tol must be > 0");
+    if (o->max_iter < 0) return fail(ctx, SEA_E_ARG, "max_iter must be >= 0");
+    if (o->stencil_dtype != SEA_F64) return fail(ctx, SEA_E_ARG, "stencil_dtype: only SEA_F64 is available");
+    if (o->ace_dtype != SEA_F64 && o->ace_dtype != SEA_F32 && o->ace_dtype != SEA_BF16)
+        return fail(ctx, SEA_E_ARG, "bad ace_dtype");
+    if (o->start != SEA_START_ZERO) return fail(ctx, SEA_E_ARG, "start: only SEA_START_ZERO is available");
+    if (o->refine_period < 1) return fail(ctx, SEA_E_ARG, "refine_period must be >= 1");
+    return SEA_OK;
+}
+
+sea_status check_grid(sea_ctx* ctx, const sea_grid* g) {
+    if (!g) return fail(ctx, SEA_E_ARG, "grid is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] < 1) return fail(ctx, SEA_E_ARG, "grid n[%d] = %d < 1", a, g->n[a]);
+        if (!(g->L[a] > 0.0) || !std::isfinite(g->L[a])) return fail(ctx, SEA_E_ARG, "grid L[%d] not positive", a);
+    }
+    return SEA_OK;
+}
+
+sea_status check_pairs(sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair* pairs) {
+    if (n_pairs < 0) return fail(ctx, SEA_E_ARG, "n_pairs < 0");
+    if (n_pairs > 0 && !pairs) return fail(ctx, SEA_E_ARG, "pairs is NULL");
+    for (int k = 0; k < n_pairs; ++k) {
+        const sea_pair& p = pairs[k];
+        if (p.i < 0 || p.j < p.i || p.j >= n_occ)
+            return fail(ctx, SEA_E_ARG, "pair %d: need 0 <= i <= j < n_occ (i=%d j=%d n_occ=%d)", k, p.i, p.j, n_occ);
+        for (int a = 0; a < 3; ++a) {
+            if (p.n[a] < 1 || p.n[a] > 4096) return fail(ctx, SEA_E_ARG, "pair %d: domain n[%d]=%d out of range", k, a, p.n[a]);
+            if (!std::isfinite(p.origin[a])) return fail(ctx, SEA_E_ARG, "pair %d: origin not finite", k);
+        }
+        if ((long long)p.n[0] * p.n[1] * p.n[2] > (1LL << 30))
+            return fail(ctx, SEA_E_ARG, "pair %d: domain too large", k);
+    }
+    return SEA_OK;
+}
+
+}  // namespace
+
+ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair* pairs, bool with_v) {
+    ExxLayout L{};
+    size_t stride = 1;
+    for (int k = 0; k < n_pairs; ++k) {
+        size_t n = (size_t)pairs[k].n[0] * pairs[k].n[1] * pairs[k].n[2];
+        if (n > stride) stride = n;
+    }
+    stride = (stride + 31) / 32 * 32;
+    L.stride = stride;
+    L.n_chunks = exx_n_chunks((long)stride);
+    L.n_slots = n_pairs < ctx->n_cu * 4 ? (n_pairs > 0 ? n_pairs : 1) : ctx->n_cu * 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t np = n_pairs > 0 ? n_pairs : 1;
+    L.pairs = take(np * sizeof(sea_pair));
+    L.partial = take(np * L.n_chunks * SEA_NACC * sizeof(double));
+    L.mom = take(np * SEA_NACC * sizeof(double));
+    L.b = take(np * stride * sizeof(double));
+    L.v = with_v ? take(np * stride * sizeof(double)) : 0;
+    L.slots = take((size_t)L.n_slots * 3 * stride * sizeof(double));
+    L.stats = take(np * sizeof(DevStat));
+    L.csr_off = take((size_t)(n_occ + 1) * sizeof(int));
+    L.csr_ent = take(2 * np * sizeof(int2));
+    L.scal = take(8 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+extern "C" {
+
+const char* sea_version(void) { return "sea-mi355x 0.1 (gfx950)"; }
+
+void sea_opts_default(sea_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->fd_half_order = 6;
+    o->lmax = 6;
+    o->rel_tol = 1e-8;
+    o->max_iter = 10000;
+    o->stencil_dtype = SEA_F64;
+    o->ace_dtype = SEA_F64;
+    o->start = SEA_START_ZERO;
+    o->refine_period = 50;
+    o->profile = 0;
+    o->hip_stream = nullptr;
+}
+
+sea_status sea_create(const sea_opts* opts, sea_ctx** out) {
+    if (!out) return SEA_E_ARG;
+    *out = nullptr;
+    sea_ctx* ctx = new (std::nothrow) sea_ctx();
+    if (!ctx) return SEA_E_NOMEM;
+    sea_opts def;
+    sea_opts_default(&def);
+    sea_status st = check_opts(ctx, opts ? opts : &def);
+    if (st != SEA_OK) {
+        delete ctx;
+        return st;
+    }
+    ctx->opts = opts ? *opts : def;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        delete ctx;
+        return SEA_E_HIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete ctx;
+        return SEA_E_HIP;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        delete ctx;
+        return SEA_E_HIP;
+    }
+    ctx->device = dev;
+    ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    bool ok = true;
+    for (int k = 0; k < SEA_STAGE_COUNT; ++k)
+        for (int e = 0; e < 2; ++e) ok = ok && hipEventCreate(&ctx->ev[k][e]) == hipSuccess;
+    ctx->ev_ready = ok;
+    *out = ctx;
+    return SEA_OK;
+}
+
+sea_status sea_destroy(sea_ctx* ctx) {
+    if (ctx && ctx->ev_ready)
+        for (int k = 0; k < SEA_STAGE_COUNT; ++k)
+            for (int e = 0; e < 2; ++e) hipEventDestroy(ctx->ev[k][e]);
+    delete ctx;
+    return SEA_OK;
+}
+
+sea_status sea_stage_times(sea_ctx* ctx, float* ms_out) {
+    if (!ctx || !ms_out) return SEA_E_ARG;
+    for (int k = 0; k < SEA_STAGE_COUNT; ++k) {
+        ms_out[k] = 0.0f;
+        if (!ctx->ev_used[k]) continue;
+        SEA_HIP_CHECK(ctx, hipEventSynchronize(ctx->ev[k][1]));
+        float ms = 0.0f;
+        SEA_HIP_CHECK(ctx, hipEventElapsedTime(&ms, ctx->ev[k][0], ctx->ev[k][1]));
+        ms_out[k] = ms;
+    }
+    return SEA_OK;
+}
+
+const char* sea_last_error(const sea_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+sea_status sea_set_opts(sea_ctx* ctx, const sea_opts* opts) {
+    if (!ctx) return SEA_E_ARG;
+    sea_status st = check_opts(ctx, opts);
+    if (st != SEA_OK) return st;
+    ctx->opts = *opts;
+    return SEA_OK;
+}
+
+sea_status sea_build_pairs(const sea_grid* grid, int n_occ, const double* c, double r_pair, double half_width,
+                           sea_pair* out, int cap, int* n_out) {
+    if (check_grid(nullptr, grid) != SEA_OK || n_occ < 0 || (n_occ > 0 && !c) || !n_out || cap < 0 ||
+        (cap > 0 && !out) || !(r_pair >= 0.0) || !(half_width >= 0.0))
+        return SEA_E_ARG;
+    int cnt = 0;
+    for (int i = 0; i < n_occ; ++i) {
+        for (int j = i; j < n_occ; ++j) {
+            double d[3], d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                d[a] = minimg(c[3 * j + a] - c[3 * i + a], grid->L[a]);
+                d2 += d[a] * d[a];
+            }
+            if (i != j && !(std::sqrt(d2) < r_pair)) continue;
+            if (cnt < cap) {
+                sea_pair& p = out[cnt];
+                p.i = i;
+                p.j = j;
+                for (int a = 0; a < 3; ++a) {
+                    const double h = grid->L[a] / grid->n[a];
+                    const double m = c[3 * i + a] + 0.5 * d[a];
+                    const int kc = (int)std::floor(m / h + 0.5);
+                    const int w = (int)std::ceil(half_width / h - 1e-12);
+                    p.lo[a] = kc - w;
+                    p.n[a] = 2 * w + 1;
+                    p.origin[a] = kc * h;
+                }
+            }
+            ++cnt;
+        }
+    }
+    *n_out = cnt;
+    return cnt > cap ? SEA_E_NOMEM : SEA_OK;
+}
+
+sea_status sea_exx_workspace_bytes(sea_ctx* ctx, const sea_grid* grid, int n_occ, int n_pairs, const sea_pair* pairs,
+                                   size_t* bytes) {
+    if (!ctx || !bytes) return SEA_E_ARG;
+    sea_status st = check_grid(ctx, grid);
+    if (st != SEA_OK) return st;
+    if (n_occ < 1) return fail(ctx, SEA_E_ARG, "n_occ < 1");
+    st = check_pairs(ctx, n_occ, n_pairs, pairs);
+    if (st != SEA_OK) return st;
+    *bytes = exx_layout(ctx, n_occ, n_pairs, pairs, true).total;
+    return SEA_OK;
+}
+
+static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev, sea_dtype phi_dtype,
+                          int n_pairs, const sea_pair* pairs, void* ws_dev, size_t ws_bytes, double* W_dev,
+                          double* exx_dev, double* exx_host, double* v_ext, double* Q_dev, double* e_dev,
+                          sea_pair_stat* stats_host) {
+    if (!ctx) return SEA_E_ARG;
+    sea_status st = check_grid(ctx, grid);
+    if (st != SEA_OK) return st;
+    if (n_occ < 1) return fail(ctx, SEA_E_ARG, "n_occ < 1");
+    if (!phi_dev) return fail(ctx, SEA_E_ARG, "phi_dev is NULL");
+    if (phi_dtype != SEA_F64 && phi_dtype != SEA_F32) return fail(ctx, SEA_E_ARG, "phi_dtype must be SEA_F64 or SEA_F32");
+    st = check_pairs(ctx, n_occ, n_pairs, pairs);
+    if (st != SEA_OK) return st;
+    if (!ws_dev) return fail(ctx, SEA_E_ARG, "workspace is NULL");
+    const bool action = (W_dev != nullptr);
+    const ExxLayout Ly = exx_layout(ctx, n_occ, n_pairs, pairs, true);
+    if (ws_bytes < Ly.total)
+        return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, Ly.total);
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    char* base = (char*)ws_dev;
+    const size_t Ng = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
+
+    if (n_pairs == 0) {
+        if (action) SEA_HIP_CHECK(ctx, hipMemsetAsync(W_dev, 0, sizeof(double) * Ng * n_occ, s));
+        double zero = 0.0;
+        if (exx_dev) SEA_HIP_CHECK(ctx, hipMemcpyAsync(exx_dev, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+        if (exx_host) *exx_host = 0.0;
+        if (exx_dev) SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+        return SEA_OK;
+    }
+
+    // upload the pair table and (for the action) the per-orbital pair lists
+    std::vector<int> off(n_occ + 1, 0);
+    std::vector<int2> ent;
+    if (action) {
+        for (int k = 0; k < n_pairs; ++k) {
+            off[pairs[k].i + 1]++;
+            if (pairs[k].j != pairs[k].i) off[pairs[k].j + 1]++;
+        }
+        for (int o = 0; o < n_occ; ++o) off[o + 1] += off[o];
+        ent.resize(off[n_occ]);
+        std::vector<int> fill(off.begin(), off.end() - 1);
+        for (int k = 0; k < n_pairs; ++k) {
+            ent[fill[pairs[k].i]++] = make_int2(k, pairs[k].j);
+            if (pairs[k].j != pairs[k].i) ent[fill[pairs[k].j]++] = make_int2(k, pairs[k].i);
+        }
+    }
+    SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.pairs, pairs, sizeof(sea_pair) * n_pairs, hipMemcpyHostToDevice, s));
+    if (action) {
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.csr_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
+        if (!ent.empty())
+            SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.csr_ent, ent.data(), sizeof(int2) * ent.size(), hipMemcpyHostToDevice, s));
+    }
+    // the host tables must outlive the copies
+    SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+
+    ExxArgs a{};
+    a.pairs = (const sea_pair*)(base + Ly.pairs);
+    a.n_pairs = n_pairs;
+    a.n_occ = n_occ;
+    for (int k = 0; k < 3; ++k) {
+        a.N[k] = grid->n[k];
+        a.h[k] = grid->L[k] / grid->n[k];
+    }
+    a.dV = a.h[0] * a.h[1] * a.h[2];
+    a.phi = phi_dev;
+    a.phi_f32 = (phi_dtype == SEA_F32);
+    a.Ng = Ng;
+    a.partial = (double*)(base + Ly.partial);
+    a.n_chunks = Ly.n_chunks;
+    a.mom = (double*)(base + Ly.mom);
+    a.b = (double*)(base + Ly.b);
+    a.v = v_ext ? v_ext : (double*)(base + Ly.v);
+    a.stride = Ly.stride;
+    a.slots = (double*)(base + Ly.slots);
+    a.n_slots = Ly.n_slots;
+    a.stats = (DevStat*)(base + Ly.stats);
+    a.rel_tol = ctx->opts.rel_tol;
+    a.max_iter = ctx->opts.max_iter;
+    a.lmax = ctx->opts.lmax;
+    int nz_max = 1;
+    for (int k = 0; k < n_pairs; ++k) nz_max = pairs[k].n[2] > nz_max ? pairs[k].n[2] : nz_max;
+
+    for (int k = SEA_STAGE_GATHER; k <= SEA_STAGE_ENERGY; ++k) ctx->ev_used[k] = false;
+    {
+        StageTimer t(ctx, SEA_STAGE_GATHER, s);
+        SEA_HIP_CHECK(ctx, launch_gather_moments(a, s));
+        SEA_HIP_CHECK(ctx, launch_moments_final(a, Q_dev, s));
+    }
+    {
+        StageTimer t(ctx, SEA_STAGE_BOUNDARY, s);
+        SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
+    }
+    {
+        StageTimer t(ctx, SEA_STAGE_CG, s);
+        SEA_HIP_CHECK(ctx, launch_cg(a, s));
+    }
+    if (action) {
+        StageTimer t(ctx, SEA_STAGE_SCATTER, s);
+        SEA_HIP_CHECK(ctx, launch_scatter(a, (const int*)(base + Ly.csr_off), (const int2*)(base + Ly.csr_ent), W_dev, s));
+    }
+    double* scal = (double*)(base + Ly.scal);
+    {
+        StageTimer t(ctx, SEA_STAGE_ENERGY, s);
+        SEA_HIP_CHECK(ctx, launch_energy_sum(a, scal, exx_dev, e_dev, s));
+    }
+
+    sea_status ret = SEA_OK;
+    if (exx_host || stats_host) {
+        double hs[3];
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(hs, scal, sizeof hs, hipMemcpyDeviceToHost, s));
+        if (stats_host)
+            SEA_HIP_CHECK(ctx, hipMemcpyAsync(stats_host, a.stats, sizeof(DevStat) * n_pairs, hipMemcpyDeviceToHost, s));
+        SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+        if (exx_host) *exx_host = hs[0];
+        if (hs[2] > 0.0 || !std::isfinite(hs[0]))
+            return fail(ctx, SEA_E_NONFINITE, "%d pair solves produced non-finite values", (int)hs[2]);
+        if (hs[1] > 0.0) {
+            fail(ctx, SEA_W_NOT_CONVERGED, "%d pairs did not reach rel_tol within max_iter", (int)hs[1]);
+            ret = SEA_W_NOT_CONVERGED;
+        }
+    }
+    return ret;
+}
+
+sea_status sea_exx_action(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev, sea_dtype phi_dtype,
+                          int n_pairs, const sea_pair* pairs_host, void* ws_dev, size_t ws_bytes, double* W_dev,
+                          double* exx_dev, double* exx_host, sea_pair_stat* stats_host) {
+    if (!ctx) return SEA_E_ARG;
+    if (!W_dev) return fail(ctx, SEA_E_ARG, "W_dev is NULL");
+    return exx_run(ctx, grid, n_occ, phi_dev, phi_dtype, n_pairs, pairs_host, ws_dev, ws_bytes, W_dev, exx_dev,
+                   exx_host, nullptr, nullptr, nullptr, stats_host);
+}
+
+sea_status sea_exx_pair_solve(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev, sea_dtype phi_dtype,
+                              int n_pairs, const sea_pair* pairs_host, void* ws_dev, size_t ws_bytes, double* v_dev,
+                              double* Q_dev, double* e_dev, sea_pair_stat* stats_host) {
+    if (!ctx) return SEA_E_ARG;
+    if (!v_dev) return fail(ctx, SEA_E_ARG, "v_dev is NULL");
+    return exx_run(ctx, grid, n_occ, phi_dev, phi_dtype, n_pairs, pairs_host, ws_dev, ws_bytes, nullptr, nullptr,
+                   nullptr, v_dev, Q_dev, e_dev, stats_host);
+}
+
+sea_status sea_solid_harmonics_host(int lmax, double x, double y, double z, double* out) {
+    if (lmax < 0 || lmax > SEA_LMAX || !out) return SEA_E_ARG;
+    solid_harmonics_orthonormal_host(lmax, x, y, z, out);
+    return SEA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// ACE entry points (k_ace.hip provides the kernels)
+
+#include "k_ace.h"
+
+namespace {
+
+struct AceLayout {
+    size_t part, mbar, linv, cmat, smat, flag, total;
+};
+
+AceLayout ace_layout(long n_grid, int n_occ, int n_vec) {
+    AceLayout L{};
+    const int nv = n_vec > n_occ ? n_vec : n_occ;
+    // split-K partials for every product this workspace serves:
+    // (n_occ x n_occ) for M and the energy, (n_occ x n_vec) for K psi
+    size_t part_elems = (size_t)ace_splits(n_grid, n_occ, n_occ) * n_occ * n_occ;
+    if (n_vec > 0) {
+        const size_t pv = (size_t)ace_splits(n_grid, n_occ, n_vec) * n_occ * n_vec;
+        if (pv > part_elems) part_elems = pv;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.part = take(part_elems * sizeof(double));
+    L.mbar = take((size_t)n_occ * n_occ * sizeof(double));
+    L.linv = take((size_t)n_occ * n_occ * sizeof(double));
+    L.cmat = take((size_t)n_occ * nv * sizeof(double));
+    L.smat = take((size_t)n_occ * n_occ * sizeof(double));
+    L.flag = take(16 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+sea_status check_ace(sea_ctx* ctx, long n_grid, int n_occ, double dV, size_t ws_bytes, const AceLayout& Ly,
+                     const void* ws) {
+    if (n_grid < 1) return fail(ctx, SEA_E_ARG, "n_grid < 1");
+    if (n_occ < 1 || n_occ > 4096) return fail(ctx, SEA_E_ARG, "n_occ out of range");
+    if (!(dV > 0.0) || !std::isfinite(dV)) return fail(ctx, SEA_E_ARG, "dV must be positive and finite");
+    if (!ws) return fail(ctx, SEA_E_ARG, "workspace is NULL");
+    if (ws_bytes < Ly.total) return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, Ly.total);
+    if (ctx->opts.ace_dtype == SEA_BF16) return fail(ctx, SEA_E_ARG, "ace_dtype SEA_BF16 is not available");
+    return SEA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sea_status sea_ace_workspace_bytes(sea_ctx* ctx, int64_t n_grid, int n_occ, int n_vec, size_t* bytes) {
+    if (!ctx || !bytes) return SEA_E_ARG;
+    if (n_grid < 1 || n_occ < 1 || n_vec < 0) return fail(ctx, SEA_E_ARG, "bad sizes");
+    *bytes = ace_layout(n_grid, n_occ, n_vec).total;
+    return SEA_OK;
+}
+
+sea_status sea_ace_build(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, const double* phi_dev,
+                         const double* W_dev, void* ws_dev, size_t ws_bytes, double* M_dev, double* L_dev,
+                         void* xi_dev, int* failed_pivot) {
+    if (!ctx) return SEA_E_ARG;
+    const AceLayout Ly = ace_layout(n_grid, n_occ, n_occ);
+    sea_status st = check_ace(ctx, n_grid, n_occ, dV, ws_bytes, Ly, ws_dev);
+    if (st != SEA_OK) return st;
+    if (!phi_dev || !W_dev || !M_dev || !L_dev || !xi_dev) return fail(ctx, SEA_E_ARG, "NULL array argument");
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    char* base = (char*)ws_dev;
+    double* part = (double*)(base + Ly.part);
+    double* Mb = (double*)(base + Ly.mbar);
+    double* Li = (double*)(base + Ly.linv);
+    int* flag = (int*)(base + Ly.flag);
+    for (int k = SEA_STAGE_ACE_M; k <= SEA_STAGE_ACE_XI; ++k) ctx->ev_used[k] = false;
+    {
+        StageTimer t(ctx, SEA_STAGE_ACE_M, s);
+        SEA_HIP_CHECK(ctx, (ace_gemm_nt<double, double>(phi_dev, W_dev, n_occ, n_occ, n_grid, dV, part, M_dev, s)));
+        SEA_HIP_CHECK(ctx, ace_symmetrize(M_dev, n_occ, Mb, s));
+    }
+    {
+        StageTimer t(ctx, SEA_STAGE_ACE_CHOL, s);
+        SEA_HIP_CHECK(ctx, ace_cholesky(Mb, n_occ, L_dev, flag, s));
+    }
+    int hflag = 0;
+    SEA_HIP_CHECK(ctx, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+    if (failed_pivot) *failed_pivot = hflag;
+    if (hflag) return fail(ctx, SEA_E_NOT_PD, "symmetrized M is not positive definite at pivot %d", hflag);
+    StageTimer t(ctx, SEA_STAGE_ACE_XI, s);
+    SEA_HIP_CHECK(ctx, ace_trtri(L_dev, n_occ, Li, s));
+    // xi (orbital-major) = L^{-1} W
+    if (ctx->opts.ace_dtype == SEA_F64)
+        SEA_HIP_CHECK(ctx, (ace_gemm_nn<double, double>(Li, n_occ, 1, W_dev, n_occ, n_occ, n_grid, 1.0,
+                                                         (double*)xi_dev, s)));
+    else
+        SEA_HIP_CHECK(ctx, (ace_gemm_nn<double, float>(Li, n_occ, 1, W_dev, n_occ, n_occ, n_grid, 1.0,
+                                                        (float*)xi_dev, s)));
+    return SEA_OK;
+}
+
+sea_status sea_ace_apply(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, const void* xi_dev, int n_vec,
+                         const void* psi_dev, void* ws_dev, size_t ws_bytes, void* out_dev) {
+    if (!ctx) return SEA_E_ARG;
+    if (n_vec < 1) return fail(ctx, SEA_E_ARG, "n_vec < 1");
+    const AceLayout Ly = ace_layout(n_grid, n_occ, n_vec);
+    sea_status st = check_ace(ctx, n_grid, n_occ, dV, ws_bytes, Ly, ws_dev);
+    if (st != SEA_OK) return st;
+    if (!xi_dev || !psi_dev || !out_dev) return fail(ctx, SEA_E_ARG, "NULL array argument");
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    char* base = (char*)ws_dev;
+    double* part = (double*)(base + Ly.part);
+    double* Cm = (double*)(base + Ly.cmat);
+    ctx->ev_used[SEA_STAGE_ACE_APPLY] = false;
+    StageTimer t(ctx, SEA_STAGE_ACE_APPLY, s);
+    // C (n_occ x n_vec) = dV xi psi^T ; out (n_vec x n_grid) = -C^T xi
+    if (ctx->opts.ace_dtype == SEA_F64) {
+        SEA_HIP_CHECK(ctx, (ace_gemm_nt<double, double>((const double*)xi_dev, (const double*)psi_dev, n_occ, n_vec,
+                                                         n_grid, dV, part, Cm, s)));
+        SEA_HIP_CHECK(ctx, (ace_gemm_nn<double, double>(Cm, 1, n_vec, (const double*)xi_dev, n_vec, n_occ, n_grid,
+                                                         -1.0, (double*)out_dev, s)));
+    } else {
+        SEA_HIP_CHECK(ctx, (ace_gemm_nt<float, float>((const float*)xi_dev, (const float*)psi_dev, n_occ, n_vec,
+                                                       n_grid, dV, part, Cm, s)));
+        SEA_HIP_CHECK(ctx, (ace_gemm_nn<float, float>(Cm, 1, n_vec, (const float*)xi_dev, n_vec, n_occ, n_grid,
+                                                       -1.0, (float*)out_dev, s)));
+    }
+    return SEA_OK;
+}
+
+sea_status sea_ace_energy(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, const double* phi_dev,
+                          const void* xi_dev, void* ws_dev, size_t ws_bytes, double* exx_host) {
+    if (!ctx) return SEA_E_ARG;
+    const AceLayout Ly = ace_layout(n_grid, n_occ, n_occ);
+    sea_status st = check_ace(ctx, n_grid, n_occ, dV, ws_bytes, Ly, ws_dev);
+    if (st != SEA_OK) return st;
+    if (!phi_dev || !xi_dev || !exx_host) return fail(ctx, SEA_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    char* base = (char*)ws_dev;
+    double* part = (double*)(base + Ly.part);
+    double* S = (double*)(base + Ly.smat);
+    double* out = (double*)(base + Ly.flag);
+    if (ctx->opts.ace_dtype == SEA_F64)
+        SEA_HIP_CHECK(ctx, (ace_gemm_nt<double, double>(phi_dev, (const double*)xi_dev, n_occ, n_occ, n_grid, dV,
+                                                         part, S, s)));
+    else
+        SEA_HIP_CHECK(ctx, (ace_gemm_nt<double, float>(phi_dev, (const float*)xi_dev, n_occ, n_occ, n_grid, dV,
+                                                        part, S, s)));
+    SEA_HIP_CHECK(ctx, ace_neg_sum_squares(S, n_occ * n_occ, out, s));
+    SEA_HIP_CHECK(ctx, hipMemcpyAsync(exx_host, out, sizeof(double), hipMemcpyDeviceToHost, s));
+    SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+    if (!std::isfinite(*exx_host)) return fail(ctx, SEA_E_NONFINITE, "non-finite ACE energy");
+    return SEA_OK;
+}
+
+}  // extern "C"

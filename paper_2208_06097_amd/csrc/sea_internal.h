@@ -1,0 +1,105 @@
+// Internal declarations shared by the HIP translation units of libsea.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sea.h"
+
+#define SEA_LMAX 6
+#define SEA_NMOM 49        // (lmax+1)^2 real moments
+#define SEA_NACC 52        // moments + s_abs + q + sum |rho| r^2
+#define SEA_HALO 6         // stencil radius (half order of the O(h^12) Laplacian)
+
+// Device-side per-pair record written by the solve kernels.
+struct DevStat {
+    int32_t iters;
+    int32_t converged;   // 1 converged, 0 not, -1 nonfinite
+    double rel_res;
+    double e_ij;
+    double s_abs;
+    double q;
+};
+static_assert(sizeof(DevStat) == sizeof(sea_pair_stat), "stat layout");
+
+struct sea_ctx {
+    sea_opts opts;
+    std::string err;
+    int device = 0;
+    int n_cu = 256;
+    // stage timing (opts.profile): begin/end events per stage
+    hipEvent_t ev[SEA_STAGE_COUNT][2] = {};
+    bool ev_used[SEA_STAGE_COUNT] = {};
+    bool ev_ready = false;
+};
+
+// Records the begin/end event of a stage when profiling is on.
+struct StageTimer {
+    sea_ctx* ctx;
+    int stage;
+    hipStream_t s;
+    StageTimer(sea_ctx* c, int st, hipStream_t str) : ctx(c), stage(st), s(str) {
+        if (ctx->opts.profile && ctx->ev_ready) {
+            hipEventRecord(ctx->ev[stage][0], s);
+            ctx->ev_used[stage] = true;
+        }
+    }
+    ~StageTimer() {
+        if (ctx->opts.profile && ctx->ev_ready) hipEventRecord(ctx->ev[stage][1], s);
+    }
+};
+
+// Byte layout of the exx workspace (offsets from the workspace base).
+struct ExxLayout {
+    size_t pairs, partial, mom, b, v, slots, stats, csr_off, csr_ent, scal, total;
+    int n_chunks;
+    int n_slots;
+    size_t stride;        // doubles per pair-domain array (max interior size)
+};
+
+ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair* pairs, bool with_v);
+
+// Arguments shared by the exx kernels (passed by value).
+struct ExxArgs {
+    const sea_pair* pairs;
+    int n_pairs;
+    int n_occ;
+    int N[3];
+    double h[3];
+    double dV;
+    const void* phi;      // n_occ x Ng, double or float
+    int phi_f32;
+    size_t Ng;
+    double* partial;      // n_pairs x n_chunks x SEA_NACC
+    int n_chunks;
+    double* mom;          // n_pairs x SEA_NACC (Racah moments, dV applied)
+    double* b;            // n_pairs x stride
+    double* v;            // n_pairs x stride
+    size_t stride;
+    double* slots;        // n_slots x 3 x stride
+    int n_slots;
+    DevStat* stats;
+    double rel_tol;
+    int max_iter;
+    int lmax;
+};
+
+// Kernel launchers (k_exx.hip).  All enqueue on `s`.
+int exx_n_chunks(long n_int_max);
+hipError_t launch_gather_moments(const ExxArgs& a, hipStream_t s);
+hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s);
+hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s);
+hipError_t launch_cg(const ExxArgs& a, hipStream_t s);
+hipError_t launch_scatter(const ExxArgs& a, const int* csr_off, const int2* csr_ent, double* W,
+                          hipStream_t s);
+hipError_t launch_energy_sum(const ExxArgs& a, double* out_scalars, double* exx_dev, double* e_dev,
+                             hipStream_t s);
+
+// Host evaluation of the solid-harmonic recurrence (orthonormal real form).
+void solid_harmonics_orthonormal_host(int lmax, double x, double y, double z, double* out);
+
+// ACE launchers (k_ace.hip).
+struct AceWs;

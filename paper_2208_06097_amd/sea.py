@@ -1,0 +1,295 @@
+"""ctypes binding of ``libsea.so`` (the C ABI in ``include/sea.h``).
+
+Argument marshalling only: every step of the exx action and the ACE build
+runs in the library's HIP kernels.  PyTorch provides device memory and the
+current stream.  The library must have been built (``build.build()``); a
+missing library is an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsea.so")
+
+SEA_OK, SEA_W_NOT_CONVERGED = 0, 1
+SEA_E_ARG, SEA_E_HIP, SEA_E_NOMEM, SEA_E_NOT_PD, SEA_E_NONFINITE = -1, -2, -3, -4, -5
+SEA_F64, SEA_F32, SEA_BF16 = 0, 1, 2
+SEA_START_ZERO, SEA_START_MULTIPOLE, SEA_START_LEARNED = 0, 1, 2
+
+# exported symbols declared in include/sea.h
+EXPORTS = [
+    "sea_version", "sea_opts_default", "sea_create", "sea_destroy", "sea_last_error",
+    "sea_set_opts", "sea_build_pairs", "sea_exx_workspace_bytes", "sea_exx_action",
+    "sea_exx_pair_solve", "sea_ace_workspace_bytes", "sea_ace_build", "sea_ace_apply",
+    "sea_ace_energy", "sea_solid_harmonics_host", "sea_stage_times",
+]
+
+PAIR_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("lo", "<i4", 3), ("n", "<i4", 3),
+                       ("origin", "<f8", 3)])
+STAT_DTYPE = np.dtype([("iters", "<i4"), ("converged", "<i4"), ("rel_res", "<f8"),
+                       ("e_ij", "<f8"), ("s_abs", "<f8"), ("q", "<f8")])
+
+
+class SeaGrid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("L", C.c_double * 3)]
+
+
+class SeaOpts(C.Structure):
+    _fields_ = [("fd_half_order", C.c_int32), ("lmax", C.c_int32), ("rel_tol", C.c_double),
+                ("max_iter", C.c_int32), ("stencil_dtype", C.c_int), ("ace_dtype", C.c_int),
+                ("start", C.c_int), ("refine_period", C.c_int32), ("profile", C.c_int32),
+                ("hip_stream", C.c_void_p)]
+
+
+STAGES = ["gather", "boundary", "guess", "cg", "scatter", "energy", "ace_m", "ace_chol", "ace_xi",
+          "ace_apply"]
+
+
+class SeaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"sea status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libsea.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2208_06097_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, vp, i, d, sz = C.POINTER, C.c_void_p, C.c_int, C.c_double, C.c_size_t
+    lib.sea_version.restype = C.c_char_p
+    lib.sea_opts_default.argtypes = [P(SeaOpts)]
+    lib.sea_opts_default.restype = None
+    lib.sea_create.argtypes = [P(SeaOpts), P(vp)]
+    lib.sea_destroy.argtypes = [vp]
+    lib.sea_last_error.argtypes = [vp]
+    lib.sea_last_error.restype = C.c_char_p
+    lib.sea_set_opts.argtypes = [vp, P(SeaOpts)]
+    lib.sea_build_pairs.argtypes = [P(SeaGrid), i, vp, d, d, vp, i, P(i)]
+    lib.sea_exx_workspace_bytes.argtypes = [vp, P(SeaGrid), i, i, vp, P(sz)]
+    lib.sea_exx_action.argtypes = [vp, P(SeaGrid), i, vp, i, i, vp, vp, sz, vp, vp, vp, vp]
+    lib.sea_exx_pair_solve.argtypes = [vp, P(SeaGrid), i, vp, i, i, vp, vp, sz, vp, vp, vp, vp]
+    lib.sea_ace_workspace_bytes.argtypes = [vp, C.c_int64, i, i, P(sz)]
+    lib.sea_ace_build.argtypes = [vp, C.c_int64, i, d, vp, vp, vp, sz, vp, vp, vp, P(i)]
+    lib.sea_ace_apply.argtypes = [vp, C.c_int64, i, d, vp, i, vp, vp, sz, vp]
+    lib.sea_ace_energy.argtypes = [vp, C.c_int64, i, d, vp, vp, vp, sz, P(d)]
+    lib.sea_solid_harmonics_host.argtypes = [i, d, d, d, vp]
+    lib.sea_stage_times.argtypes = [vp, vp]
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load().sea_version().decode()
+
+
+def _grid(N, L) -> SeaGrid:
+    g = SeaGrid()
+    Ns = np.broadcast_to(np.asarray(N, dtype=np.int64), (3,))
+    Ls = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+    for k in range(3):
+        g.n[k] = int(Ns[k])
+        g.L[k] = float(Ls[k])
+    return g
+
+
+def build_pairs(N, L, centres, r_pair=6.0, half_width=6.0) -> np.ndarray:
+    """Host pair selection and domains (sea_build_pairs)."""
+    lib = load()
+    g = _grid(N, L)
+    c = np.ascontiguousarray(centres, dtype=np.float64)
+    n_occ = c.shape[0]
+    cap = max(1, n_occ * (n_occ + 1) // 2)
+    out = np.zeros(cap, dtype=PAIR_DTYPE)
+    n = C.c_int(0)
+    st = lib.sea_build_pairs(C.byref(g), n_occ, c.ctypes.data, r_pair, half_width,
+                             out.ctypes.data, cap, C.byref(n))
+    if st != SEA_OK:
+        raise SeaError(st, "sea_build_pairs failed")
+    return out[:n.value].copy()
+
+
+def solid_harmonics_host(lmax, v) -> np.ndarray:
+    out = np.zeros((lmax + 1) ** 2)
+    st = load().sea_solid_harmonics_host(lmax, float(v[0]), float(v[1]), float(v[2]), out.ctypes.data)
+    if st != SEA_OK:
+        raise SeaError(st, "bad lmax")
+    return out
+
+
+def pair_stride(pairs: np.ndarray) -> int:
+    n = int(np.max(np.prod(pairs["n"].astype(np.int64), axis=1))) if len(pairs) else 1
+    return (n + 31) // 32 * 32
+
+
+class Context:
+    """A library context bound to the current torch CUDA device and stream."""
+
+    def __init__(self, rel_tol=1e-8, max_iter=10000, lmax=6, stencil_dtype=SEA_F64,
+                 ace_dtype=SEA_F64, start=SEA_START_ZERO, refine_period=50, profile=False, stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        o = SeaOpts()
+        self.lib.sea_opts_default(C.byref(o))
+        o.rel_tol, o.max_iter, o.lmax = rel_tol, max_iter, lmax
+        o.stencil_dtype, o.ace_dtype, o.start, o.refine_period = stencil_dtype, ace_dtype, start, refine_period
+        o.profile = 1 if profile else 0
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        o.hip_stream = C.c_void_p(stream.cuda_stream)
+        self.opts = o
+        h = C.c_void_p()
+        st = self.lib.sea_create(C.byref(o), C.byref(h))
+        if st != SEA_OK:
+            raise SeaError(st, "sea_create failed (no gfx950 device current, or bad options)")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sea_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow_warn=True):
+        if st == SEA_OK or (allow_warn and st > 0):
+            return st
+        raise SeaError(st, self.lib.sea_last_error(self.h).decode())
+
+    def set_opts(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opts, k, v)
+        self._check(self.lib.sea_set_opts(self.h, C.byref(self.opts)))
+
+    def stage_times(self) -> dict:
+        """Per-stage milliseconds of the latest profiled calls (HIP events)."""
+        ms = np.zeros(len(STAGES), dtype=np.float32)
+        self._check(self.lib.sea_stage_times(self.h, ms.ctypes.data))
+        return {k: float(v) for k, v in zip(STAGES, ms)}
+
+    # ---------------------------------------------------------------- exx
+    def exx_workspace_bytes(self, N, L, n_occ, pairs) -> int:
+        g = _grid(N, L)
+        b = C.c_size_t(0)
+        p = np.ascontiguousarray(pairs, dtype=PAIR_DTYPE)
+        self._check(self.lib.sea_exx_workspace_bytes(self.h, C.byref(g), n_occ, len(p),
+                                                     p.ctypes.data if len(p) else None, C.byref(b)))
+        return b.value
+
+    def workspace(self, nbytes):
+        return self._torch.empty(max(int(nbytes), 256), dtype=self._torch.uint8, device="cuda")
+
+    @staticmethod
+    def _phi_dtype(phi):
+        import torch
+        if phi.dtype == torch.float64:
+            return SEA_F64
+        if phi.dtype == torch.float32:
+            return SEA_F32
+        raise TypeError("phi must be float64 or float32")
+
+    def exx_action(self, phi, N, L, pairs, ws=None, W=None, exx_dev=None, want_host=True):
+        """Returns (W, E_host or None, stats or None, status)."""
+        torch = self._torch
+        assert phi.is_cuda and phi.is_contiguous()
+        n_occ = phi.shape[0]
+        p = np.ascontiguousarray(pairs, dtype=PAIR_DTYPE)
+        if ws is None:
+            ws = self.workspace(self.exx_workspace_bytes(N, L, n_occ, p))
+        if W is None:
+            W = torch.empty(phi.shape, dtype=torch.float64, device=phi.device)
+        g = _grid(N, L)
+        E = C.c_double(0.0)
+        stats = np.zeros(max(len(p), 1), dtype=STAT_DTYPE)
+        st = self.lib.sea_exx_action(self.h, C.byref(g), n_occ, phi.data_ptr(), self._phi_dtype(phi), len(p),
+                                     p.ctypes.data if len(p) else None, ws.data_ptr(), ws.numel(), W.data_ptr(),
+                                     exx_dev.data_ptr() if exx_dev is not None else None,
+                                     C.byref(E) if want_host else None,
+                                     stats.ctypes.data if want_host else None)
+        st = self._check(st)
+        return W, (E.value if want_host else None), (stats[:len(p)] if want_host else None), st
+
+    def pair_solve(self, phi, N, L, pairs, ws=None, want_Q=True):
+        """Per-pair potentials: returns (v (n_pairs x stride), Q or None, e, stats, status)."""
+        torch = self._torch
+        n_occ = phi.shape[0]
+        p = np.ascontiguousarray(pairs, dtype=PAIR_DTYPE)
+        if ws is None:
+            ws = self.workspace(self.exx_workspace_bytes(N, L, n_occ, p))
+        stride = pair_stride(p)
+        v = torch.empty((max(len(p), 1), stride), dtype=torch.float64, device=phi.device)
+        Q = torch.empty((max(len(p), 1), 49), dtype=torch.float64, device=phi.device) if want_Q else None
+        e = torch.empty(max(len(p), 1), dtype=torch.float64, device=phi.device)
+        g = _grid(N, L)
+        stats = np.zeros(max(len(p), 1), dtype=STAT_DTYPE)
+        st = self.lib.sea_exx_pair_solve(self.h, C.byref(g), n_occ, phi.data_ptr(), self._phi_dtype(phi), len(p),
+                                         p.ctypes.data if len(p) else None, ws.data_ptr(), ws.numel(), v.data_ptr(),
+                                         Q.data_ptr() if want_Q else None, e.data_ptr(), stats.ctypes.data)
+        st = self._check(st)
+        return v, Q, e, stats[:len(p)], st
+
+    # ---------------------------------------------------------------- ACE
+    def ace_workspace_bytes(self, n_grid, n_occ, n_vec=0) -> int:
+        b = C.c_size_t(0)
+        self._check(self.lib.sea_ace_workspace_bytes(self.h, int(n_grid), n_occ, n_vec, C.byref(b)))
+        return b.value
+
+    def _xi_torch_dtype(self):
+        torch = self._torch
+        return {SEA_F64: torch.float64, SEA_F32: torch.float32, SEA_BF16: torch.bfloat16}[self.opts.ace_dtype]
+
+    def ace_build(self, phi, W, dV, ws=None):
+        """Returns (M, L, xi, failed_pivot); raises SeaError on a non-PD M."""
+        torch = self._torch
+        n_occ = phi.shape[0]
+        ng = phi.numel() // n_occ
+        if ws is None:
+            ws = self.workspace(self.ace_workspace_bytes(ng, n_occ, n_occ))
+        M = torch.empty((n_occ, n_occ), dtype=torch.float64, device=phi.device)
+        Lm = torch.empty_like(M)
+        xi = torch.empty(phi.shape, dtype=self._xi_torch_dtype(), device=phi.device)
+        fp = C.c_int(0)
+        st = self.lib.sea_ace_build(self.h, ng, n_occ, dV, phi.data_ptr(), W.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    M.data_ptr(), Lm.data_ptr(), xi.data_ptr(), C.byref(fp))
+        self._check(st)
+        return M, Lm, xi, fp.value
+
+    def ace_apply(self, xi, psi, dV, ws=None):
+        torch = self._torch
+        n_occ = xi.shape[0]
+        n_vec = psi.shape[0]
+        ng = xi.numel() // n_occ
+        if ws is None:
+            ws = self.workspace(self.ace_workspace_bytes(ng, n_occ, n_vec))
+        out_dtype = torch.float32 if self.opts.ace_dtype == SEA_BF16 else self._xi_torch_dtype()
+        out = torch.empty(psi.shape, dtype=out_dtype, device=psi.device)
+        st = self.lib.sea_ace_apply(self.h, ng, n_occ, dV, xi.data_ptr(), n_vec, psi.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), out.data_ptr())
+        self._check(st)
+        return out
+
+    def ace_energy(self, phi, xi, dV, ws=None) -> float:
+        n_occ = phi.shape[0]
+        ng = phi.numel() // n_occ
+        if ws is None:
+            ws = self.workspace(self.ace_workspace_bytes(ng, n_occ, n_occ))
+        E = C.c_double(0.0)
+        st = self.lib.sea_ace_energy(self.h, ng, n_occ, dV, phi.data_ptr(), xi.data_ptr(), ws.data_ptr(),
+                                     ws.numel(), C.byref(E))
+        self._check(st)
+        return E.value
