@@ -38,7 +38,7 @@ def cpu_baseline(cell, pairs_np, n_pairs_total, seed=1234):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = max(1, min(cores, os.cpu_count() or 1))
     rng = np.random.default_rng(seed)
-    k = min(len(pairs_np), 2 * cores)
+    k = min(len(pairs_np), 10 * cores)
     idx = np.sort(rng.choice(len(pairs_np), size=k, replace=False))
     pl = oracle.PairList(np.stack([pairs_np["i"], pairs_np["j"]], 1)[idx].astype(np.int32),
                          pairs_np["lo"][idx].astype(np.int32), pairs_np["n"][idx].astype(np.int32),
@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 2 GiB device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the pair solves of one cell "
@@ -87,6 +89,13 @@ def main():
     phi = torch.from_numpy(cell.phi).cuda()
     psi = torch.from_numpy(trial).cuda()
     del trial
+    if args.copy_probe:
+        src = torch.ones(2 ** 28, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 2 GiB read + 2 GiB written")
+        del src, dst
     ctx = sea.Context(rel_tol=1e-8, profile=True)
     ws = ctx.workspace(ctx.exx_workspace_bytes(cell.N, cell.L, cell.n_occ, pairs))
     ws_ace = ctx.workspace(ctx.ace_workspace_bytes(cell.N ** 3, cell.n_occ, psi.shape[0]))
