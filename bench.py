@@ -64,6 +64,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--form", default="f32", choices=["f32", "f64"],
+                    help="CG state precision of the timed form (FP64 refinement either way)")
+    ap.add_argument("--other-forms", action="store_true",
+                    help="also time the V_xx action of the other plain form")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 2 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -96,7 +100,8 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 2 GiB read + 2 GiB written")
         del src, dst
-    ctx = sea.Context(rel_tol=1e-8, profile=True)
+    sdt = sea.SEA_F32 if args.form == "f32" else sea.SEA_F64
+    ctx = sea.Context(rel_tol=1e-8, profile=True, stencil_dtype=sdt)
     ws = ctx.workspace(ctx.exx_workspace_bytes(cell.N, cell.L, cell.n_occ, pairs))
     ws_ace = ctx.workspace(ctx.ace_workspace_bytes(cell.N ** 3, cell.n_occ, psi.shape[0]))
     W = torch.empty_like(phi)
@@ -132,8 +137,9 @@ def main():
     vxx_ms = sum(stages[k] for k in ("gather", "boundary", "guess", "cg", "scatter", "energy"))
     n_int = int(np.prod(pairs["n"].astype(np.int64), axis=1).mean())
     it_sum = int(stats["iters"].sum())
+    wbytes = 4.0 if args.form == "f32" else 8.0
     cg_bytes = float(np.sum(stats["iters"].astype(np.float64) * 6.0
-                            * np.prod(pairs["n"].astype(np.float64), axis=1) * 8.0))
+                            * np.prod(pairs["n"].astype(np.float64), axis=1) * wbytes))
     cg_ms = stages["cg"]
     achieved = cg_bytes / (cg_ms * 1e-3) / 1e9
     out = {
@@ -150,19 +156,32 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if args.form == "f32" else "f64",
         "data": "synthetic",
         "config": {"workload": "64-molecule water-like cell, 1.0 g/cm^3, L=23.5 bohr, 120^3 grid, "
-                               "256 orbitals, 63^3 pair domains, CG rel_tol 1e-8, zero start, FP64 "
-                               "(plain form); ACE with K applied to 256 trial vectors",
+                               "256 orbitals, 63^3 pair domains, CG rel_tol 1e-8 (true FP64 residual), zero "
+                               "start, plain form; ACE (FP64) with K applied to 256 trial vectors",
                    "n_pairs": n_pairs, "n_int": n_int, "cg_iters_total": it_sum,
                    "cg_iters_mean": float(stats["iters"].mean()), "E_xx": E, "E_ace": E_ace,
-                   "form": "plain-f64-zero"},
-        "roofline": {"bound": "hbm", "kernel": "k_cg_f64", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                   "form": f"plain-{args.form}-zero"},
+        "roofline": {"bound": "hbm", "kernel": f"k_cg_zm<{'float' if args.form == 'f32' else 'double'}>",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": cg_bytes,
-                     "per_unit": "6 words x 8 B per interior point per CG iteration"},
+                     "per_unit": f"6 words x {int(wbytes)} B per interior point per CG iteration"},
     }
+    if args.other_forms:
+        other = "f64" if args.form == "f32" else "f32"
+        ctx.set_opts(stencil_dtype=sea.SEA_F64 if other == "f64" else sea.SEA_F32)
+        r2 = ctx.exx_action(phi, cell.N, cell.L, pairs, ws=ws, W=W, exx_dev=exx_dev, want_host=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.exx_action(phi, cell.N, cell.L, pairs, ws=ws, W=W, exx_dev=exx_dev, want_host=False)
+        torch.cuda.synchronize()
+        st2 = ctx.stage_times()
+        out["other_forms"] = {f"plain-{other}-zero": {
+            "vxx_ms_per_call": 1000 * (time.perf_counter() - t1),
+            "cg_ms": st2["cg"], "E_xx": r2[1], "cg_iters_mean": float(r2[2]["iters"].mean())}}
     if rank == 0 and not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(cell, pairs, n_pairs)

@@ -1,0 +1,440 @@
+// CG Poisson solves (Eq. 9) on the pair domains, one workgroup per pair,
+// persistent over a pair queue.
+//
+// Each workgroup owns a whole pair: the domain (nx, ny <= 64) is marched
+// plane by plane in z.  A wavefront covers one x-row of 64 points; every
+// thread owns COLS (x, y) columns and keeps the 13 values p(z-6..z+6) of
+// each column in registers.  x neighbours come from wavefront DPP shifts
+// (zero fill at the wave edge is the zero boundary), y neighbours from the
+// current plane in LDS (rows of 64 with 6 zero halo rows each side).  One
+// LDS barrier per plane (double-buffered plane); no halo re-reads from HBM.
+//
+// One CG iteration is two sweeps (8 words of state traffic per point):
+//   A: p = r + beta p (in place), d = <p, A p>           reads r, p; writes p
+//   B: c += alpha p, r -= alpha A p, rr = <r, r>          reads p, c, r; writes c, r
+// where A p is recomputed in B instead of being stored.
+//
+// Precision: the CG state (c, r, p) is T (double or float).  Around it sits
+// an FP64 refinement loop ("reliable update"): the FP64 residual r64 starts
+// at b, each inner CG solves A c = (T) r64 to the relative tolerance the
+// outer target still needs (never below the state precision's floor), then
+// one more sweep applies r64 -= A c with FP64 arithmetic and x += c in FP64.
+// Residual norms and dot products accumulate in FP64.  A separate kernel
+// recomputes the true residual b - A x in FP64 at exit and the pair energy.
+#include "sea_internal.h"
+
+namespace {
+
+__constant__ double kCw[7] = {-5369.0 / 1800.0, 12.0 / 7.0,      -15.0 / 56.0,     10.0 / 189.0,
+                              -1.0 / 112.0,     2.0 / 1925.0,    -1.0 / 16632.0};
+
+constexpr int LW = 64;                 // LDS row length (x)
+constexpr int LH = 64 + 2 * SEA_HALO;  // LDS rows per plane (y with halo)
+constexpr int PL = 64 * 64;            // slot-array plane pitch (elements)
+
+// Cubic grid: -Lap_h f = w0 f + sum_k wk (six neighbours at distance k).
+template <typename T>
+struct SW {
+    T w[7];
+};
+
+template <typename T>
+__device__ __forceinline__ SW<T> make_sw(double ih2) {
+    SW<T> w;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) w.w[k] = (T)(-kCw[k] * ih2 * (k == 0 ? 3.0 : 1.0));
+    return w;
+}
+
+// LDS-only barrier: waits for this thread's LDS traffic, not for global loads
+// in flight, then synchronizes the workgroup.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Wavefront shifts by one lane with zero fill at the edge (DPP wave_shl:1 /
+// wave_shr:1).  The stencil only uses sums f(x+k) + f(x-k), so it does not
+// depend on which of the two is the left shift.
+__device__ __forceinline__ float wshl1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float wshr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double wshl1(double v) {
+    int2 t = *reinterpret_cast<int2*>(&v);
+    t.x = __builtin_amdgcn_update_dpp(0, t.x, 0x130, 0xF, 0xF, true);
+    t.y = __builtin_amdgcn_update_dpp(0, t.y, 0x130, 0xF, 0xF, true);
+    return *reinterpret_cast<double*>(&t);
+}
+__device__ __forceinline__ double wshr1(double v) {
+    int2 t = *reinterpret_cast<int2*>(&v);
+    t.x = __builtin_amdgcn_update_dpp(0, t.x, 0x138, 0xF, 0xF, true);
+    t.y = __builtin_amdgcn_update_dpp(0, t.y, 0x138, 0xF, 0xF, true);
+    return *reinterpret_cast<double*>(&t);
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+        double t = (lane < NT / 64) ? lds[lane] : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        if (lane == 0) lds[NT / 64] = t;
+    }
+    __syncthreads();
+    const double r = lds[NT / 64];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int wrap_idx(int k, int N) {
+    int m = k % N;
+    return m < 0 ? m + N : m;
+}
+
+__device__ __forceinline__ double load_phi(const void* phi, int f32, size_t off) {
+    return f32 ? (double)(((const float*)phi)[off]) : ((const double*)phi)[off];
+}
+
+struct Empty {};
+
+// z-march of A applied to a field f.  The input of plane z is produced in
+// two steps so its global loads overlap a whole plane of work: fetch(c, z)
+// issues the loads at the start of step z-7, make(c, z, F) turns them into
+// f at the end of that step.  pre(c, z) prefetches per-column data for the
+// output plane z before the barrier; out(c, z, A f, f, PV) consumes it.
+// Column c of this thread is (x, y) = (tx, ty + TY c).  The slot arrays
+// hold 7 zero planes beyond nz, so every fetch is unconditional.
+template <typename T, typename TC, int NT, int COLS, typename F, typename PV, typename FetchF, typename MakeF,
+          typename PreF, typename OutF>
+__device__ __forceinline__ void zmarch(int nz, T* lds, const SW<TC>& w, FetchF&& fetch, MakeF&& make, PreF&& pre,
+                                       OutF&& out) {
+    constexpr int TY = NT / 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    T q[COLS][13];
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) q[c][k] = T(0);
+#pragma unroll
+        for (int s = 0; s < 7; ++s) q[c][6 + s] = make(c, s, fetch(c, s));
+    }
+    for (int z = 0; z < nz; ++z) {
+        F nxt[COLS];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) nxt[c] = fetch(c, z + 7);
+        PV pv[COLS];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) pv[c] = pre(c, z);
+        T* pl = lds + (z & 1) * (LW * LH) + (ty + SEA_HALO) * LW + tx;
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) pl[TY * c * LW] = q[c][6];
+        lds_sync();
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            __builtin_amdgcn_sched_barrier(0);
+            const T* row = pl + TY * c * LW;
+            TC s = w.w[0] * (TC)q[c][6];
+            T u = q[c][6], d = q[c][6];
+#pragma unroll
+            for (int k = 1; k <= SEA_HALO; ++k) {
+                u = wshl1(u);
+                d = wshr1(d);
+                s += w.w[k] * (((TC)u + (TC)d) + ((TC)row[k * LW] + (TC)row[-k * LW]) +
+                               ((TC)q[c][6 + k] + (TC)q[c][6 - k]));
+            }
+            out(c, z, s, q[c][6], pv[c]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) q[c][k] = q[c][k + 1];
+            q[c][12] = make(c, z + 7, nxt[c]);
+        }
+    }
+}
+
+// -Lap_h x at interior point (x,y,z) read straight from global memory (zero
+// outside the interior); used for the FP64 outer residual only.
+__device__ __forceinline__ double apply_A_global(const double* __restrict__ p, int id, int x, int y, int z, int nx,
+                                                 int ny, int nz, double ih2) {
+    const int sy = nx, sz = nx * ny;
+    double s = -3.0 * kCw[0] * ih2 * p[id];
+#pragma unroll
+    for (int k = 1; k <= SEA_HALO; ++k) {
+        const double ax = (x - k >= 0 ? p[id - k] : 0.0) + (x + k < nx ? p[id + k] : 0.0);
+        const double ay = (y - k >= 0 ? p[id - k * sy] : 0.0) + (y + k < ny ? p[id + k * sy] : 0.0);
+        const double az = (z - k >= 0 ? p[id - k * sz] : 0.0) + (z + k < nz ? p[id + k * sz] : 0.0);
+        s += -kCw[k] * ih2 * (ax + ay + az);
+    }
+    return s;
+}
+
+template <typename T>
+struct Floor;
+template <>
+struct Floor<double> {
+    static constexpr double v = 0.0;
+};
+template <>
+struct Floor<float> {
+    static constexpr double v = 1e-5;
+};
+
+template <typename T>
+struct F2 {
+    T a, b;
+};
+template <typename T>
+struct PVsel {
+    using type = F2<T>;
+};
+
+template <typename T, int NT, int COLS, bool PREFETCH>
+__device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, const SW<T>& w, const SW<double>& wd,
+                           T* __restrict__ cc, T* __restrict__ rr, T* __restrict__ pp, double* __restrict__ r64) {
+    // Slot arrays (cc, rr, pp, r64) use a padded 64 x 64 plane: element
+    // (x,y,z) at (z*64 + y)*64 + x, planes 0..nz+6; cells outside the domain
+    // stay zero in rr, pp and r64.
+    constexpr int TY = NT / 64;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int npad = PL * (nz + 7);
+    const double* __restrict__ b = a.b + (size_t)pid * a.stride;
+    const double* __restrict__ b0 = a.x_nonzero ? a.bres + (size_t)pid * a.stride : b;
+    double* __restrict__ x = a.v + (size_t)pid * a.stride;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const double tol2 = 0.81 * a.rel_tol * a.rel_tol;   // 10% margin for the exit check
+    const double floor2 = Floor<T>::v * Floor<T>::v;
+    T msk[COLS];
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) msk[c] = (tx < nx && ty + TY * c < ny) ? T(1) : T(0);
+    const int col0 = ty * 64 + tx;  // column c at col0 + c*TY*64 within a plane
+
+    // r64 = b0 on the padded grid; x = 0 unless a start guess is present
+    double bb = 0.0, r2 = 0.0;
+    for (int q = threadIdx.x; q < npad; q += NT) {
+        const int xx = q & 63, yy = (q >> 6) & 63, zz = q >> 12;
+        double rv = 0.0;
+        if (xx < nx && yy < ny && zz < nz) {
+            const int id = (zz * ny + yy) * nx + xx;
+            const double bv = b[id];
+            bb += bv * bv;
+            rv = b0[id];
+            if (!a.x_nonzero) x[id] = 0.0;
+        }
+        r64[q] = rv;
+        r2 += rv * rv;
+    }
+    bb = block_sum<NT>(bb, red);
+    r2 = block_sum<NT>(r2, red);
+
+    int it = 0, conv = 0;
+    for (;;) {
+        if (!(r2 == r2) || !(bb == bb)) { conv = -1; break; }
+        if (r2 <= tol2 * bb) { conv = 1; break; }
+        if (it >= a.max_iter) { conv = 0; break; }
+        // inner right-hand side in T
+        double r2t = 0.0;
+        for (int q = threadIdx.x; q < npad; q += NT) {
+            const T rt = (T)r64[q];
+            rr[q] = rt;
+            cc[q] = T(0);
+            pp[q] = T(0);
+            r2t += (double)rt * (double)rt;
+        }
+        r2t = block_sum<NT>(r2t, red);
+        double tau2 = tol2 * bb / r2;
+        if (tau2 < floor2) tau2 = floor2;
+        const double stop2 = tau2 * r2t;
+
+        // inner CG on A c = r (c0 = 0)
+        double rho = r2t;
+        T beta = T(0);
+        for (;;) {
+            // sweep A: p = r + beta p, <p, A p>
+            double dacc = 0.0;
+            zmarch<T, T, NT, COLS, F2<T>, Empty>(
+                nz, lds, w,
+                [&](int c, int z) -> F2<T> {
+                    const int id = z * PL + col0 + c * TY * 64;
+                    return F2<T>{rr[id], pp[id]};
+                },
+                [&](int c, int z, F2<T> f) -> T {
+                    const T pn = f.a + beta * f.b;
+                    pp[z * PL + col0 + c * TY * 64] = pn;
+                    return pn;
+                },
+                [&](int, int) { return Empty{}; },
+                [&](int, int, T s, T ctr, Empty) { dacc += (double)ctr * (double)s; });
+            const double pAp = block_sum<NT>(dacc, red);
+            const T al = (T)(rho / pAp);
+            // sweep B: c += alpha p, r -= alpha A p, <r, r>
+            using PV = typename PVsel<T>::type;
+            double racc = 0.0;
+            auto fetch_p = [&](int c, int z) -> T { return pp[z * PL + col0 + c * TY * 64]; };
+            auto make_p = [&](int, int, T v) -> T { return v; };
+            if constexpr (PREFETCH) {
+                zmarch<T, T, NT, COLS, T, PV>(
+                    nz, lds, w, fetch_p, make_p,
+                    [&](int c, int z) -> PV {
+                        const int id = z * PL + col0 + c * TY * 64;
+                        return PV{cc[id], rr[id]};
+                    },
+                    [&](int c, int z, T s, T ctr, PV v) {
+                        const int id = z * PL + col0 + c * TY * 64;
+                        const T rn = msk[c] * (v.b - al * s);
+                        cc[id] = v.a + al * ctr;
+                        rr[id] = rn;
+                        racc += (double)rn * (double)rn;
+                    });
+            } else {
+                zmarch<T, T, NT, COLS, T, Empty>(
+                    nz, lds, w, fetch_p, make_p, [&](int, int) { return Empty{}; },
+                    [&](int c, int z, T s, T ctr, Empty) {
+                        const int id = z * PL + col0 + c * TY * 64;
+                        const T rn = msk[c] * (rr[id] - al * s);
+                        cc[id] = cc[id] + al * ctr;
+                        rr[id] = rn;
+                        racc += (double)rn * (double)rn;
+                    });
+            }
+            const double rn2 = block_sum<NT>(racc, red);
+            ++it;
+            if (rn2 <= stop2 || it >= a.max_iter || !(rn2 == rn2)) break;
+            beta = (T)(rn2 / rho);
+            rho = rn2;
+        }
+        // reliable update in FP64: r64 -= A c, x += c
+        double racc = 0.0;
+        zmarch<T, double, NT, COLS, T, double>(
+            nz, lds, wd, [&](int c, int z) -> T { return cc[z * PL + col0 + c * TY * 64]; },
+            [&](int, int, T v) -> T { return v; },
+            [&](int c, int z) -> double { return r64[z * PL + col0 + c * TY * 64]; },
+            [&](int c, int z, double s, T ctr, double rv) {
+                const int id = z * PL + col0 + c * TY * 64;
+                const double rn = (double)msk[c] * (rv - s);
+                r64[id] = rn;
+                racc += rn * rn;
+                if (msk[c] != T(0)) x[(z * ny + ty + TY * c) * nx + tx] += (double)ctr;
+            });
+        r2 = block_sum<NT>(racc, red);
+    }
+    if (threadIdx.x == 0) {
+        a.stats[pid].iters = it;
+        a.stats[pid].converged = conv;
+    }
+}
+
+template <typename T, int NT, int COLS, bool PREFETCH>
+__global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
+    extern __shared__ unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    __shared__ double red[NT / 64 + 1];
+    __shared__ int pid_sh;
+    const double ih2 = 1.0 / (a.h[0] * a.h[0]);
+    const SW<T> w = make_sw<T>(ih2);
+    const SW<double> wd = make_sw<double>(ih2);
+    for (int i = threadIdx.x; i < 2 * LW * LH; i += NT) lds[i] = T(0);
+    char* slot = reinterpret_cast<char*>(a.slots) + (size_t)blockIdx.x * 4 * a.slot_stride * sizeof(double);
+    T* cc = reinterpret_cast<T*>(slot);
+    T* rr = cc + a.slot_stride;
+    T* pp = rr + a.slot_stride;
+    double* r64 = reinterpret_cast<double*>(slot + 3 * a.slot_stride * sizeof(double));
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) pid_sh = atomicAdd(a.queue_ctr, 1);
+        __syncthreads();
+        const int pid = pid_sh;
+        if (pid >= a.n_pairs) break;
+        solve_pair<T, NT, COLS, PREFETCH>(a, pid, lds, red, w, wd, cc, rr, pp, r64);
+    }
+}
+
+// True FP64 residual b - A x and e_ij = dV sum rho x, one workgroup per pair.
+constexpr int FIN_BS = 512;
+
+__global__ __launch_bounds__(FIN_BS) void k_cg_finish(ExxArgs a) {
+    __shared__ double red[FIN_BS / 64 + 1];
+    const int pid = blockIdx.x;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int n = nx * ny * nz, nxy = nx * ny;
+    const double ih2 = 1.0 / (a.h[0] * a.h[0]);
+    const double* b = a.b + (size_t)pid * a.stride;
+    const double* x = a.v + (size_t)pid * a.stride;
+    const size_t oi = (size_t)P.i * a.Ng, oj = (size_t)P.j * a.Ng;
+    double bb = 0.0, rr = 0.0, e = 0.0;
+    for (int id = threadIdx.x; id < n; id += FIN_BS) {
+        const int xx = id % nx, yy = (id / nx) % ny, zz = id / nxy;
+        const double r = b[id] - apply_A_global(x, id, xx, yy, zz, nx, ny, nz, ih2);
+        bb += b[id] * b[id];
+        rr += r * r;
+        const size_t g = ((size_t)wrap_idx(P.lo[2] + zz, a.N[2]) * a.N[1] + wrap_idx(P.lo[1] + yy, a.N[1])) * a.N[0] +
+                         wrap_idx(P.lo[0] + xx, a.N[0]);
+        e += load_phi(a.phi, a.phi_f32, oi + g) * load_phi(a.phi, a.phi_f32, oj + g) * x[id];
+    }
+    bb = block_sum<FIN_BS>(bb, red);
+    rr = block_sum<FIN_BS>(rr, red);
+    e = block_sum<FIN_BS>(e, red);
+    if (threadIdx.x == 0) {
+        DevStat st = a.stats[pid];
+        st.rel_res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+        if (st.converged >= 0 && !(bb > 0.0)) st.converged = 1;
+        else if (st.converged >= 0) st.converged = (st.rel_res <= a.rel_tol) ? 1 : 0;
+        if (!(st.rel_res == st.rel_res)) st.converged = -1;
+        st.e_ij = a.dV * e;
+        st.s_abs = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM];
+        st.q = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM + 1];
+        a.stats[pid] = st;
+    }
+}
+
+}  // namespace
+
+bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h) {
+    if (h[0] != h[1] || h[0] != h[2]) return false;
+    for (int k = 0; k < n_pairs; ++k)
+        if (pairs[k].n[0] > 64 || pairs[k].n[1] > 64) return false;
+    return true;
+}
+
+size_t cg_zm_lds_bytes(int state_f32) { return (size_t)2 * LW * LH * (state_f32 ? sizeof(float) : sizeof(double)); }
+
+#ifndef SEA_CG_F32_NT
+#define SEA_CG_F32_NT 1024
+#endif
+#ifndef SEA_CG_F64_NT
+#define SEA_CG_F64_NT 1024
+#endif
+#ifndef SEA_CG_F32_PF
+#define SEA_CG_F32_PF true
+#endif
+#ifndef SEA_CG_F64_PF
+#define SEA_CG_F64_PF false
+#endif
+
+hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_finish, dim3(a.n_pairs), dim3(FIN_BS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_zm(const ExxArgs& a, int state_f32, hipStream_t s) {
+    if (state_f32) {
+        constexpr int NT = SEA_CG_F32_NT;
+        auto k = k_cg_zm<float, NT, 64 / (NT / 64), SEA_CG_F32_PF>;
+        hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cg_zm_lds_bytes(1));
+        hipLaunchKernelGGL(k, dim3(a.n_slots), dim3(NT), cg_zm_lds_bytes(1), s, a);
+    } else {
+        constexpr int NT = SEA_CG_F64_NT;
+        auto k = k_cg_zm<double, NT, 64 / (NT / 64), SEA_CG_F64_PF>;
+        hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cg_zm_lds_bytes(0));
+        hipLaunchKernelGGL(k, dim3(a.n_slots), dim3(NT), cg_zm_lds_bytes(0), s, a);
+    }
+    return hipGetLastError();
+}

@@ -100,6 +100,7 @@ __global__ __launch_bounds__(GM_BS) void k_gather_moments(ExxArgs a) {
 __global__ void k_moments_final(ExxArgs a, double* Q_orth) {
     const int pid = blockIdx.x;
     const int k = threadIdx.x;
+    if (pid == 0 && k == 0 && a.queue_ctr) *a.queue_ctr = 0;
     if (k >= SEA_NACC) return;
     const sea_pair P = a.pairs[pid];
     const long n_int = (long)P.n[0] * P.n[1] * P.n[2];
@@ -208,7 +209,7 @@ __device__ __forceinline__ double apply_A_pt(const double* __restrict__ p, long 
 __global__ __launch_bounds__(CG_BS) void k_cg_f64(ExxArgs a) {
     __shared__ double red[CG_BS / 64 + 1];
     const StencilW w = make_weights(a.h);
-    double* r = a.slots + (size_t)blockIdx.x * 3 * a.stride;
+    double* r = a.slots + (size_t)blockIdx.x * 3 * a.slot_stride;
     double* p = r + a.stride;
     double* q = p + a.stride;
     const double tol2 = a.rel_tol * a.rel_tol;

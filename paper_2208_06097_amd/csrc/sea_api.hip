@@ -42,7 +42,8 @@ sea_status check_opts(sea_ctx* ctx, const sea_opts* o) {
     if (o->lmax < 0 || o->lmax > SEA_LMAX) return fail(ctx, SEA_E_ARG, "lmax must be in 0..%d", SEA_LMAX);
     if (!(o->rel_tol > 0.0) || !std::isfinite(o->rel_tol)) return fail(ctx, SEA_E_ARG, "rel_tol must be > 0");
     if (o->max_iter < 0) return fail(ctx, SEA_E_ARG, "max_iter must be >= 0");
-    if (o->stencil_dtype != SEA_F64) return fail(ctx, SEA_E_ARG, "stencil_dtype: only SEA_F64 is available");
+    if (o->stencil_dtype != SEA_F64 && o->stencil_dtype != SEA_F32)
+        return fail(ctx, SEA_E_ARG, "stencil_dtype must be SEA_F64 or SEA_F32");
     if (o->ace_dtype != SEA_F64 && o->ace_dtype != SEA_F32 && o->ace_dtype != SEA_BF16)
         return fail(ctx, SEA_E_ARG, "bad ace_dtype");
     if (o->start != SEA_START_ZERO) return fail(ctx, SEA_E_ARG, "start: only SEA_START_ZERO is available");
@@ -87,6 +88,10 @@ ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair*
     }
     stride = (stride + 31) / 32 * 32;
     L.stride = stride;
+    int nz_max = 1;
+    for (int k = 0; k < n_pairs; ++k) nz_max = pairs[k].n[2] > nz_max ? pairs[k].n[2] : nz_max;
+    L.slot_stride = (size_t)64 * 64 * (nz_max + 7);
+    if (L.slot_stride < stride) L.slot_stride = stride;
     L.n_chunks = exx_n_chunks((long)stride);
     L.n_slots = n_pairs < ctx->n_cu * 4 ? (n_pairs > 0 ? n_pairs : 1) : ctx->n_cu * 4;
     size_t off = 0;
@@ -101,7 +106,7 @@ ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair*
     L.mom = take(np * SEA_NACC * sizeof(double));
     L.b = take(np * stride * sizeof(double));
     L.v = with_v ? take(np * stride * sizeof(double)) : 0;
-    L.slots = take((size_t)L.n_slots * 3 * stride * sizeof(double));
+    L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
     L.csr_off = take((size_t)(n_occ + 1) * sizeof(int));
     L.csr_ent = take(2 * np * sizeof(int2));
@@ -158,6 +163,7 @@ sea_status sea_create(const sea_opts* opts, sea_ctx** out) {
     }
     ctx->device = dev;
     ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    ctx->max_lds = prop.sharedMemPerBlock;
     bool ok = true;
     for (int k = 0; k < SEA_STAGE_COUNT; ++k)
         for (int e = 0; e < 2; ++e) ok = ok && hipEventCreate(&ctx->ev[k][e]) == hipSuccess;
@@ -318,11 +324,17 @@ static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const v
     a.v = v_ext ? v_ext : (double*)(base + Ly.v);
     a.stride = Ly.stride;
     a.slots = (double*)(base + Ly.slots);
+    a.slot_stride = Ly.slot_stride;
     a.n_slots = Ly.n_slots;
     a.stats = (DevStat*)(base + Ly.stats);
     a.rel_tol = ctx->opts.rel_tol;
     a.max_iter = ctx->opts.max_iter;
     a.lmax = ctx->opts.lmax;
+    a.queue_ctr = (int*)(base + Ly.scal + 4 * sizeof(double));
+    a.x_nonzero = 0;
+    const bool zm = cg_zm_fits(pairs, n_pairs, a.h) && cg_zm_lds_bytes(ctx->opts.stencil_dtype == SEA_F32) <= ctx->max_lds;
+    if (!zm && ctx->opts.stencil_dtype != SEA_F64)
+        return fail(ctx, SEA_E_ARG, "SEA_F32 state needs every pair domain with n[0], n[1] <= 64");
     int nz_max = 1;
     for (int k = 0; k < n_pairs; ++k) nz_max = pairs[k].n[2] > nz_max ? pairs[k].n[2] : nz_max;
 
@@ -338,7 +350,11 @@ static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const v
     }
     {
         StageTimer t(ctx, SEA_STAGE_CG, s);
-        SEA_HIP_CHECK(ctx, launch_cg(a, s));
+        if (zm) {
+            SEA_HIP_CHECK(ctx, launch_cg_zm(a, ctx->opts.stencil_dtype == SEA_F32, s));
+            SEA_HIP_CHECK(ctx, launch_cg_finish(a, s));
+        } else
+            SEA_HIP_CHECK(ctx, launch_cg(a, s));
     }
     if (action) {
         StageTimer t(ctx, SEA_STAGE_SCATTER, s);

@@ -30,6 +30,7 @@ struct sea_ctx {
     std::string err;
     int device = 0;
     int n_cu = 256;
+    size_t max_lds = 65536;   // LDS bytes one workgroup may allocate
     // stage timing (opts.profile): begin/end events per stage
     hipEvent_t ev[SEA_STAGE_COUNT][2] = {};
     bool ev_used[SEA_STAGE_COUNT] = {};
@@ -58,6 +59,7 @@ struct ExxLayout {
     int n_chunks;
     int n_slots;
     size_t stride;        // doubles per pair-domain array (max interior size)
+    size_t slot_stride;   // elements per CG slot array
 };
 
 ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair* pairs, bool with_v);
@@ -79,12 +81,16 @@ struct ExxArgs {
     double* b;            // n_pairs x stride
     double* v;            // n_pairs x stride
     size_t stride;
-    double* slots;        // n_slots x 3 x stride
+    double* slots;        // n_slots x 3 x slot_stride elements (state precision)
+    size_t slot_stride;   // elements per slot array (64 x 64 x max nz for the z-march)
     int n_slots;
     DevStat* stats;
     double rel_tol;
     int max_iter;
     int lmax;
+    int* queue_ctr;       // persistent-kernel pair counter (zeroed before the CG launch)
+    int x_nonzero;        // v holds a start guess on entry to the CG
+    double* bres;         // n_pairs x stride: b - A x0 when x_nonzero
 };
 
 // Kernel launchers (k_exx.hip).  All enqueue on `s`.
@@ -93,6 +99,11 @@ hipError_t launch_gather_moments(const ExxArgs& a, hipStream_t s);
 hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s);
 hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s);
 hipError_t launch_cg(const ExxArgs& a, hipStream_t s);
+// z-marching CG (k_cg.hip): needs every pair with n[0], n[1] <= 64.
+bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h);
+size_t cg_zm_lds_bytes(int state_f32);
+hipError_t launch_cg_zm(const ExxArgs& a, int state_f32, hipStream_t s);
+hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s);
 hipError_t launch_scatter(const ExxArgs& a, const int* csr_off, const int2* csr_ent, double* W,
                           hipStream_t s);
 hipError_t launch_energy_sum(const ExxArgs& a, double* out_scalars, double* exx_dev, double* e_dev,

@@ -79,6 +79,63 @@ def test_exx_action_mini(ctx, mini):
     assert np.all(stats["converged"] == 1) and np.all(stats["rel_res"] <= 1e-8)
 
 
+@pytest.fixture(scope="module")
+def ctx32():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = sea.Context(rel_tol=1e-8, stencil_dtype=sea.SEA_F32)
+    yield c
+    c.close()
+
+
+def test_exx_action_fp32_state_mini(ctx32, mini):
+    """FP32 CG state with FP64 refinement reaches the same 1e-8 true residual."""
+    cell, pl, ref, pairs = mini
+    print("case mini exx_action fp32 state", flush=True)
+    W, E, stats, st = ctx32.exx_action(_dev(cell.phi), cell.N, cell.L, pairs)
+    assert st == sea.SEA_OK
+    assert np.all(stats["converged"] == 1) and np.all(stats["rel_res"] <= 1e-8)
+    assert abs(E - ref.E) < 1e-6
+    assert np.max(np.abs(W.cpu().numpy() - ref.W)) < 1e-5
+
+
+def test_exx_action_fp32_state_wrap(ctx32):
+    cell = synth.mini(n_mol=2)
+    print("case mini-wrap fp32 state", flush=True)
+    pl = oracle.build_pairs(cell.N, cell.L, cell.centres, 6.0, 5.0)
+    ref = oracle.exx(cell.phi, cell.N, cell.L, pl, tol=1e-12)
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, 5.0)
+    W, E, stats, st = ctx32.exx_action(_dev(cell.phi), cell.N, cell.L, pairs)
+    assert np.all(stats["converged"] == 1)
+    assert abs(E - ref.E) < 1e-6
+    assert np.max(np.abs(W.cpu().numpy() - ref.W)) < 1e-5
+
+
+def test_non_cubic_grid_generic_path(ctx):
+    """Unequal spacings take the generic (global-memory stencil) CG kernel."""
+    cell = synth.mini(n_mol=2)
+    print("case non-cubic", flush=True)
+    N = np.array([30, 30, 30])
+    L = np.array([cell.L, cell.L, cell.L * 1.04])
+    # re-sample the orbitals on the stretched grid through the generator's formula
+    cell2 = synth.make_centres(2, cell.L, 30, cell.seed, dmin=3.5)
+    phi = np.empty((cell2.n_occ, 30, 30, 30))
+    for i in range(cell2.n_occ):
+        ax = [np.arange(30) * (L[k] / 30) for k in range(3)]
+        d = [ax[k] - cell2.centres[i, k] - L[k] * np.round((ax[k] - cell2.centres[i, k]) / L[k]) for k in range(3)]
+        g = np.exp(-(d[2][:, None, None] ** 2 + d[1][None, :, None] ** 2 + d[0][None, None, :] ** 2) / (2 * synth.SIGMA ** 2))
+        f = (1 + cell2.a[i, 0] * d[0][None, None, :] + cell2.a[i, 1] * d[1][None, :, None]
+             + cell2.a[i, 2] * d[2][:, None, None]) * g
+        phi[i] = f / np.sqrt(np.prod(L / N) * np.sum(f * f))
+    pl = oracle.build_pairs(N, L, cell2.centres, 6.0, 4.0)
+    ref = oracle.exx(phi, N, L, pl, tol=1e-12)
+    pairs = sea.build_pairs(N, L, cell2.centres, 6.0, 4.0)
+    W, E, stats, st = ctx.exx_action(_dev(phi), N, L, pairs)
+    assert st == sea.SEA_OK
+    assert abs(E - ref.E) < 1e-6
+    assert np.max(np.abs(W.cpu().numpy() - ref.W)) < 1e-5
+
+
 def test_exx_action_deterministic(ctx, mini):
     cell, pl, ref, pairs = mini
     print("case mini determinism", flush=True)
@@ -196,3 +253,16 @@ def test_c1_full_against_golden(ctx):
     assert np.max(np.abs(got - np.array(g["W_val"]))) < 1e-5
     e = stats["e_ij"]
     assert np.max(np.abs(e - np.array(g["e_pairs"]))) < 1e-7
+
+
+def test_c1_full_fp32_state_against_golden(ctx32):
+    g = json.load(open(os.path.join(GOLDEN, "c1.json")))
+    cell = synth.config1(seed=g["seed"])
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, g["r_pair"], g["half_width"])
+    print("case c1 full fp32 state", flush=True)
+    W, E, stats, st = ctx32.exx_action(_dev(cell.phi), cell.N, cell.L, pairs)
+    assert st == sea.SEA_OK and np.all(stats["rel_res"] <= 1e-8)
+    assert abs(E - g["E"]) < 1e-6
+    Wf = W.reshape(cell.n_occ, -1)
+    got = Wf[torch.tensor(g["W_orb"], device="cuda"), torch.tensor(g["W_pt"], device="cuda")].cpu().numpy()
+    assert np.max(np.abs(got - np.array(g["W_val"]))) < 1e-5
