@@ -14,13 +14,15 @@
 //   B: c += alpha p, r -= alpha A p, rr = <r, r>          reads p, c, r; writes c, r
 // where A p is recomputed in B instead of being stored.
 //
-// Precision: the CG state (c, r, p) is T (double or float).  Around it sits
-// an FP64 refinement loop ("reliable update"): the FP64 residual r64 starts
-// at b, each inner CG solves A c = (T) r64 to the relative tolerance the
-// outer target still needs (never below the state precision's floor), then
-// one more sweep applies r64 -= A c with FP64 arithmetic and x += c in FP64.
-// Residual norms and dot products accumulate in FP64.  A separate kernel
-// recomputes the true residual b - A x in FP64 at exit and the pair energy.
+// Precision: the CG state (c, r, p) is T (double or float), with reliable
+// updates (residual replacement, as in mixed-precision CG of Sleijpen and
+// van der Vorst): the FP64 residual r64 starts at b; whenever the recursive
+// residual has dropped by another decade (FP32 state) or has met the target,
+// one more sweep applies r64 -= A c with FP64 arithmetic and x += c in FP64,
+// and the recursive residual is replaced by (T) r64 while the search
+// direction p is kept, so the Krylov process is never restarted.  Residual
+// norms and dot products accumulate in FP64.  A separate kernel recomputes
+// the true residual b - A x in FP64 at exit and the pair energy.
 #include "sea_internal.h"
 
 namespace {
@@ -175,15 +177,18 @@ __device__ __forceinline__ double apply_A_global(const double* __restrict__ p, i
     return s;
 }
 
+// Reliable-update trigger: replace the recursive residual by the FP64 one
+// whenever it has dropped by another factor Delta (squared here); FP64 state
+// only replaces at convergence.
 template <typename T>
-struct Floor;
+struct Delta;
 template <>
-struct Floor<double> {
-    static constexpr double v = 0.0;
+struct Delta<double> {
+    static constexpr double v2 = 0.0;
 };
 template <>
-struct Floor<float> {
-    static constexpr double v = 1e-5;
+struct Delta<float> {
+    static constexpr double v2 = 1e-2;
 };
 
 template <typename T>
@@ -210,7 +215,6 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, const
     double* __restrict__ x = a.v + (size_t)pid * a.stride;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const double tol2 = 0.81 * a.rel_tol * a.rel_tol;   // 10% margin for the exit check
-    const double floor2 = Floor<T>::v * Floor<T>::v;
     T msk[COLS];
 #pragma unroll
     for (int c = 0; c < COLS; ++c) msk[c] = (tx < nx && ty + TY * c < ny) ? T(1) : T(0);
@@ -235,83 +239,82 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, const
     r2 = block_sum<NT>(r2, red);
 
     int it = 0, conv = 0;
-    for (;;) {
-        if (!(r2 == r2) || !(bb == bb)) { conv = -1; break; }
-        if (r2 <= tol2 * bb) { conv = 1; break; }
-        if (it >= a.max_iter) { conv = 0; break; }
-        // inner right-hand side in T
+    // inner state from r64: r = (T) r64, c = 0 (p is kept across replacements)
+    auto reset = [&](bool zero_p) -> double {
         double r2t = 0.0;
         for (int q = threadIdx.x; q < npad; q += NT) {
             const T rt = (T)r64[q];
             rr[q] = rt;
             cc[q] = T(0);
-            pp[q] = T(0);
+            if (zero_p) pp[q] = T(0);
             r2t += (double)rt * (double)rt;
         }
-        r2t = block_sum<NT>(r2t, red);
-        double tau2 = tol2 * bb / r2;
-        if (tau2 < floor2) tau2 = floor2;
-        const double stop2 = tau2 * r2t;
-
-        // inner CG on A c = r (c0 = 0)
-        double rho = r2t;
-        T beta = T(0);
-        for (;;) {
-            // sweep A: p = r + beta p, <p, A p>
-            double dacc = 0.0;
-            zmarch<T, T, NT, COLS, F2<T>, Empty>(
-                nz, lds, w,
-                [&](int c, int z) -> F2<T> {
+        return block_sum<NT>(r2t, red);
+    };
+    double rho = 0.0, rupd = r2;
+    T beta = T(0);
+    if (!(r2 == r2) || !(bb == bb)) conv = -1;
+    else if (r2 <= tol2 * bb) conv = 1;
+    else if (a.max_iter <= 0) conv = 0;
+    else rho = reset(true);
+    while (conv == 0 && rho > 0.0) {
+        // sweep A: p = r + beta p, <p, A p>
+        double dacc = 0.0;
+        zmarch<T, T, NT, COLS, F2<T>, Empty>(
+            nz, lds, w,
+            [&](int c, int z) -> F2<T> {
+                const int id = z * PL + col0 + c * TY * 64;
+                return F2<T>{rr[id], pp[id]};
+            },
+            [&](int c, int z, F2<T> f) -> T {
+                const T pn = f.a + beta * f.b;
+                pp[z * PL + col0 + c * TY * 64] = pn;
+                return pn;
+            },
+            [&](int, int) { return Empty{}; },
+            [&](int, int, T s, T ctr, Empty) { dacc += (double)ctr * (double)s; });
+        const double pAp = block_sum<NT>(dacc, red);
+        const T al = (T)(rho / pAp);
+        // sweep B: c += alpha p, r -= alpha A p, <r, r>
+        using PV = typename PVsel<T>::type;
+        double racc = 0.0;
+        auto fetch_p = [&](int c, int z) -> T { return pp[z * PL + col0 + c * TY * 64]; };
+        auto make_p = [&](int, int, T v) -> T { return v; };
+        if constexpr (PREFETCH) {
+            zmarch<T, T, NT, COLS, T, PV>(
+                nz, lds, w, fetch_p, make_p,
+                [&](int c, int z) -> PV {
                     const int id = z * PL + col0 + c * TY * 64;
-                    return F2<T>{rr[id], pp[id]};
+                    return PV{cc[id], rr[id]};
                 },
-                [&](int c, int z, F2<T> f) -> T {
-                    const T pn = f.a + beta * f.b;
-                    pp[z * PL + col0 + c * TY * 64] = pn;
-                    return pn;
-                },
-                [&](int, int) { return Empty{}; },
-                [&](int, int, T s, T ctr, Empty) { dacc += (double)ctr * (double)s; });
-            const double pAp = block_sum<NT>(dacc, red);
-            const T al = (T)(rho / pAp);
-            // sweep B: c += alpha p, r -= alpha A p, <r, r>
-            using PV = typename PVsel<T>::type;
-            double racc = 0.0;
-            auto fetch_p = [&](int c, int z) -> T { return pp[z * PL + col0 + c * TY * 64]; };
-            auto make_p = [&](int, int, T v) -> T { return v; };
-            if constexpr (PREFETCH) {
-                zmarch<T, T, NT, COLS, T, PV>(
-                    nz, lds, w, fetch_p, make_p,
-                    [&](int c, int z) -> PV {
-                        const int id = z * PL + col0 + c * TY * 64;
-                        return PV{cc[id], rr[id]};
-                    },
-                    [&](int c, int z, T s, T ctr, PV v) {
-                        const int id = z * PL + col0 + c * TY * 64;
-                        const T rn = msk[c] * (v.b - al * s);
-                        cc[id] = v.a + al * ctr;
-                        rr[id] = rn;
-                        racc += (double)rn * (double)rn;
-                    });
-            } else {
-                zmarch<T, T, NT, COLS, T, Empty>(
-                    nz, lds, w, fetch_p, make_p, [&](int, int) { return Empty{}; },
-                    [&](int c, int z, T s, T ctr, Empty) {
-                        const int id = z * PL + col0 + c * TY * 64;
-                        const T rn = msk[c] * (rr[id] - al * s);
-                        cc[id] = cc[id] + al * ctr;
-                        rr[id] = rn;
-                        racc += (double)rn * (double)rn;
-                    });
-            }
-            const double rn2 = block_sum<NT>(racc, red);
-            ++it;
-            if (rn2 <= stop2 || it >= a.max_iter || !(rn2 == rn2)) break;
+                [&](int c, int z, T s, T ctr, PV v) {
+                    const int id = z * PL + col0 + c * TY * 64;
+                    const T rn = msk[c] * (v.b - al * s);
+                    cc[id] = v.a + al * ctr;
+                    rr[id] = rn;
+                    racc += (double)rn * (double)rn;
+                });
+        } else {
+            zmarch<T, T, NT, COLS, T, Empty>(
+                nz, lds, w, fetch_p, make_p, [&](int, int) { return Empty{}; },
+                [&](int c, int z, T s, T ctr, Empty) {
+                    const int id = z * PL + col0 + c * TY * 64;
+                    const T rn = msk[c] * (rr[id] - al * s);
+                    cc[id] = cc[id] + al * ctr;
+                    rr[id] = rn;
+                    racc += (double)rn * (double)rn;
+                });
+        }
+        const double rn2 = block_sum<NT>(racc, red);
+        ++it;
+        const bool nan = !(rn2 == rn2);
+        if (!nan && rn2 > tol2 * bb && rn2 > Delta<T>::v2 * rupd && it < a.max_iter) {
             beta = (T)(rn2 / rho);
             rho = rn2;
+            continue;
         }
         // reliable update in FP64: r64 -= A c, x += c
-        double racc = 0.0;
+        double uacc = 0.0;
         zmarch<T, double, NT, COLS, T, double>(
             nz, lds, wd, [&](int c, int z) -> T { return cc[z * PL + col0 + c * TY * 64]; },
             [&](int, int, T v) -> T { return v; },
@@ -320,10 +323,18 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, const
                 const int id = z * PL + col0 + c * TY * 64;
                 const double rn = (double)msk[c] * (rv - s);
                 r64[id] = rn;
-                racc += rn * rn;
+                uacc += rn * rn;
                 if (msk[c] != T(0)) x[(z * ny + ty + TY * c) * nx + tx] += (double)ctr;
             });
-        r2 = block_sum<NT>(racc, red);
+        r2 = block_sum<NT>(uacc, red);
+        if (!(r2 == r2)) { conv = -1; break; }
+        if (r2 <= tol2 * bb) { conv = 1; break; }
+        if (it >= a.max_iter) break;
+        // continue the same Krylov process from the replaced residual
+        const double r2t = reset(false);
+        beta = (T)(r2t / rho);
+        rho = r2t;
+        rupd = r2;
     }
     if (threadIdx.x == 0) {
         a.stats[pid].iters = it;

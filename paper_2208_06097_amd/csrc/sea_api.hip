@@ -332,9 +332,13 @@ static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const v
     a.lmax = ctx->opts.lmax;
     a.queue_ctr = (int*)(base + Ly.scal + 4 * sizeof(double));
     a.x_nonzero = 0;
-    const bool zm = cg_zm_fits(pairs, n_pairs, a.h) && cg_zm_lds_bytes(ctx->opts.stencil_dtype == SEA_F32) <= ctx->max_lds;
+    // FP32 state: z-marching kernel (cubic grids, domains up to 64 x 64 in
+    // x-y).  FP64 state: the generic kernel (the FP64 z-queue does not fit
+    // the register file at this tile shape).
+    const bool zm = ctx->opts.stencil_dtype == SEA_F32 && cg_zm_fits(pairs, n_pairs, a.h) &&
+                    cg_zm_lds_bytes(1) <= ctx->max_lds;
     if (!zm && ctx->opts.stencil_dtype != SEA_F64)
-        return fail(ctx, SEA_E_ARG, "SEA_F32 state needs every pair domain with n[0], n[1] <= 64");
+        return fail(ctx, SEA_E_ARG, "SEA_F32 state needs a cubic grid and pair domains with n[0], n[1] <= 64");
     int nz_max = 1;
     for (int k = 0; k < n_pairs; ++k) nz_max = pairs[k].n[2] > nz_max ? pairs[k].n[2] : nz_max;
 

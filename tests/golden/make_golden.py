@@ -30,6 +30,9 @@ def make(name):
     if name == "c1":
         cell = synth.config1(seed=101)
         hw = 6.0
+    elif name == "c2":
+        cell = synth.config2(seed=2000)
+        hw = 6.0
     else:
         raise SystemExit(f"unknown case {name}")
     pl = oracle.build_pairs(cell.N, cell.L, cell.centres, 6.0, hw)
@@ -40,13 +43,15 @@ def make(name):
     # samples: every orbital at points where W is non-negligible, plus random points
     oi, gi = sample_points(cell.n_occ, Ng, 512, 7)
     Wf = res.W.reshape(cell.n_occ, -1)
-    big = np.argsort(-np.abs(Wf), axis=1)[:, :8]
+    big = np.argpartition(-np.abs(Wf), 8, axis=1)[:, :8]
     oi = np.concatenate([oi, np.repeat(np.arange(cell.n_occ), 8)])
     gi = np.concatenate([gi, big.ravel()])
+    W_val = Wf[oi, gi].tolist()
     ace = oracle.ace_build(cell.phi, res.W, cell.h ** 3)
+    del res.W
     out = dict(case=name, seed=cell.seed, N=cell.N, L=cell.L, half_width=hw, r_pair=6.0, tol=TOL,
                n_pairs=len(pl), E=res.E, e_pairs=res.e_pairs.tolist(), iters=res.iters.tolist(),
-               W_orb=oi.tolist(), W_pt=gi.tolist(), W_val=Wf[oi, gi].tolist(),
+               W_orb=oi.tolist(), W_pt=gi.tolist(), W_val=W_val,
                trace_M=float(np.trace(ace.M)), E_ace=oracle.ace_energy(cell.phi, ace.xi, cell.h ** 3),
                oracle_seconds=dt)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}.json")
