@@ -430,6 +430,27 @@ size_t cg_zm_lds_bytes(int state_f32) { return (size_t)2 * LW * LH * (state_f32 
 #define SEA_CG_F64_PF false
 #endif
 
+// b - A x0 for a start guess x0 (FP64), one workgroup per pair.
+__global__ __launch_bounds__(FIN_BS) void k_start_residual(ExxArgs a) {
+    const int pid = blockIdx.x;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int n = nx * ny * nz, nxy = nx * ny;
+    const double ih2 = 1.0 / (a.h[0] * a.h[0]);
+    const double* b = a.b + (size_t)pid * a.stride;
+    const double* x = a.v + (size_t)pid * a.stride;
+    double* br = a.bres + (size_t)pid * a.stride;
+    for (int id = threadIdx.x; id < n; id += FIN_BS) {
+        const int xx = id % nx, yy = (id / nx) % ny, zz = id / nxy;
+        br[id] = b[id] - apply_A_global(x, id, xx, yy, zz, nx, ny, nz, ih2);
+    }
+}
+
+hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_start_residual, dim3(a.n_pairs), dim3(FIN_BS), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_finish, dim3(a.n_pairs), dim3(FIN_BS), 0, s, a);
     return hipGetLastError();

@@ -123,48 +123,128 @@ __global__ void k_moments_final(ExxArgs a, double* Q_orth) {
 }
 
 // ---------------------------------------------------------------------------
-// 3. boundary values: b += sum over ghost taps (c_k / h_a^2) v_ME(ghost)
+// 3. boundary values (Eq. 10) on the ghost layers, then folded into b:
+//    b += sum over ghost taps (c_k / h_a^2) v_ME(ghost)
+//
+// Ghost buffer of a pair: 6 faces (x-, x+, y-, y+, z-, z+) x 6 layers x
+// (n_u x n_v) values, face stride nmax^2, (u, v) = the two other axes.
+
+constexpr int GE_BS = 256;
+
+template <int LM>
+__global__ __launch_bounds__(GE_BS) void k_ghost_eval(ExxArgs a) {
+    __shared__ double Q[SEA_NMOM];
+    const int pid = blockIdx.y;
+    if (threadIdx.x < SEA_NMOM) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
+    __syncthreads();
+    const sea_pair P = a.pairs[pid];
+    const int nm = a.nmax, FS = nm * nm;
+    const long t = (long)blockIdx.x * GE_BS + threadIdx.x;
+    if (t >= 36L * FS) return;
+    const int f = (int)(t / (6L * FS));
+    const int L = (int)((t / FS) % 6) + 1;
+    const int rem = (int)(t % FS);
+    const int au = rem % nm, av = rem / nm;
+    const int ax = f >> 1, plus = f & 1;
+    const int u = (ax + 1) % 3, v = (ax + 2) % 3;
+    if (au >= P.n[u] || av >= P.n[v]) return;
+    int pos[3];
+    pos[ax] = plus ? P.n[ax] - 1 + L : -L;
+    pos[u] = au;
+    pos[v] = av;
+    const double dx = (P.lo[0] + pos[0]) * a.h[0] - P.origin[0];
+    const double dy = (P.lo[1] + pos[1]) * a.h[1] - P.origin[1];
+    const double dz = (P.lo[2] + pos[2]) * a.h[2] - P.origin[2];
+    a.gbuf[(size_t)pid * a.gstride + (size_t)(f * 6 + (L - 1)) * FS + (size_t)av * nm + au] =
+        racah_me_potential<LM>(Q, a.lmax, dx, dy, dz);
+}
 
 constexpr int BF_BS = 256;
 
-template <int LM>
-__global__ __launch_bounds__(BF_BS) void k_boundary_fold(ExxArgs a) {
-    __shared__ double Q[SEA_NMOM];
+__global__ __launch_bounds__(BF_BS) void k_ghost_fold(ExxArgs a) {
     const int pid = blockIdx.y;
     const int z = blockIdx.x;
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    if (threadIdx.x < SEA_NMOM) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
-    __syncthreads();
     if (z >= nz) return;
+    const int nm = a.nmax, FS = nm * nm;
+    const double* g = a.gbuf + (size_t)pid * a.gstride;
     const bool zface = (z < SEA_HALO) || (z >= nz - SEA_HALO);
     double* b = a.b + (size_t)pid * a.stride + (size_t)z * nx * ny;
     const double ih2[3] = {1.0 / (a.h[0] * a.h[0]), 1.0 / (a.h[1] * a.h[1]), 1.0 / (a.h[2] * a.h[2])};
     for (int t = threadIdx.x; t < nx * ny; t += BF_BS) {
         const int x = t % nx, y = t / nx;
-        const bool near = zface || x < SEA_HALO || x >= nx - SEA_HALO || y < SEA_HALO || y >= ny - SEA_HALO;
-        if (!near) continue;
+        if (!(zface || x < SEA_HALO || x >= nx - SEA_HALO || y < SEA_HALO || y >= ny - SEA_HALO)) continue;
         const int pos[3] = {x, y, z};
         const int nn[3] = {nx, ny, nz};
         double acc = 0.0;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
+            const int u = (ax + 1) % 3, v = (ax + 2) % 3;
+            const size_t uv = (size_t)pos[v] * nm + pos[u];
 #pragma unroll
             for (int k = 1; k <= SEA_HALO; ++k) {
-#pragma unroll
-                for (int sg = -1; sg <= 1; sg += 2) {
-                    const int q = pos[ax] + sg * k;
-                    if (q >= 0 && q < nn[ax]) continue;
-                    int gp[3] = {x, y, z};
-                    gp[ax] = q;
-                    const double dx = (P.lo[0] + gp[0]) * a.h[0] - P.origin[0];
-                    const double dy = (P.lo[1] + gp[1]) * a.h[1] - P.origin[1];
-                    const double dz = (P.lo[2] + gp[2]) * a.h[2] - P.origin[2];
-                    acc += kC[k] * ih2[ax] * racah_me_potential<LM>(Q, a.lmax, dx, dy, dz);
-                }
+                if (pos[ax] - k < 0) acc += kC[k] * ih2[ax] * g[(size_t)((2 * ax) * 6 + (k - pos[ax] - 1)) * FS + uv];
+                if (pos[ax] + k >= nn[ax])
+                    acc += kC[k] * ih2[ax] * g[(size_t)((2 * ax + 1) * 6 + (pos[ax] + k - nn[ax])) * FS + uv];
             }
         }
         b[t] += acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3b. multipole start: x0 = regularized multipole potential on the interior.
+//     l = 0: q erf(r/r_s)/r; l >= 1: the l-th term times (1 - exp(-r^2/r_s^2))^{l+1};
+//     r_s = sqrt(2 <r^2>/3) from the |rho|-weighted second moment (the
+//     exact width for a spherical Gaussian density).
+
+template <int LM>
+__global__ __launch_bounds__(GM_BS) void k_me_guess(ExxArgs a) {
+    __shared__ double Q[SEA_NACC];
+    const int pid = blockIdx.y;
+    if (threadIdx.x < SEA_NACC) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
+    __syncthreads();
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const long n_int = (long)nx * ny * nz;
+    const long beg = (long)blockIdx.x * GM_CHUNK;
+    if (beg >= n_int) return;
+    const long end = min(beg + GM_CHUNK, n_int);
+    const double r2m = Q[SEA_NMOM] > 0.0 ? Q[SEA_NMOM + 2] / Q[SEA_NMOM] : 1.0;
+    const double rs = sqrt(fmax(2.0 * r2m / 3.0, 1e-6));
+    double* x = a.v + (size_t)pid * a.stride;
+    for (long id = beg + threadIdx.x; id < end; id += GM_BS) {
+        const int xx = (int)(id % nx), yy = (int)((id / nx) % ny), zz = (int)(id / ((long)nx * ny));
+        const double dx = (P.lo[0] + xx) * a.h[0] - P.origin[0];
+        const double dy = (P.lo[1] + yy) * a.h[1] - P.origin[1];
+        const double dz = (P.lo[2] + zz) * a.h[2] - P.origin[2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double r = sqrt(r2);
+        double val;
+        if (r < 1e-12) {
+            val = Q[0] * 2.0 / (rs * sqrt(kPi));
+        } else {
+            double R[(LM + 1) * (LM + 1)];
+            racah_solid<LM>(dx, dy, dz, R);
+            const double rinv = 1.0 / r, rinv2 = rinv * rinv;
+            const double damp = 1.0 - exp(-r2 / (rs * rs));
+            val = Q[0] * erf(r / rs) * rinv;
+            double pw = rinv * rinv2, dl = damp;
+#pragma unroll
+            for (int l = 1; l <= LM; ++l) {
+                dl *= damp;
+                if (l <= a.lmax) {
+                    const int base = l * l + l;
+                    double acc = Q[base] * R[base];
+#pragma unroll
+                    for (int m = 1; m <= l; ++m) acc += 2.0 * (Q[base + m] * R[base + m] + Q[base - m] * R[base - m]);
+                    val += acc * pw * dl;
+                }
+                pw *= rinv2;
+            }
+        }
+        x[id] = val;
     }
 }
 
@@ -226,7 +306,7 @@ __global__ __launch_bounds__(CG_BS) void k_cg_f64(ExxArgs a) {
         for (long id = threadIdx.x; id < n; id += CG_BS) {
             const double t = b[id];
             bb += t * t;
-            x[id] = 0.0;
+            if (!a.x_nonzero) x[id] = 0.0;
         }
         bb = block_sum<CG_BS>(bb, red);
         int it = 0;
@@ -431,8 +511,17 @@ hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s)
 }
 
 hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s) {
-    dim3 grid(nz_max, a.n_pairs);
-    hipLaunchKernelGGL(k_boundary_fold<SEA_LMAX>, grid, dim3(BF_BS), 0, s, a);
+    const long nghost = 36L * a.nmax * a.nmax;
+    hipLaunchKernelGGL(k_ghost_eval<SEA_LMAX>, dim3((unsigned)((nghost + GE_BS - 1) / GE_BS), a.n_pairs), dim3(GE_BS),
+                       0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ghost_fold, dim3(nz_max, a.n_pairs), dim3(BF_BS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_me_guess<SEA_LMAX>, dim3(a.n_chunks, a.n_pairs), dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -46,7 +46,8 @@ sea_status check_opts(sea_ctx* ctx, const sea_opts* o) {
         return fail(ctx, SEA_E_ARG, "stencil_dtype must be SEA_F64 or SEA_F32");
     if (o->ace_dtype != SEA_F64 && o->ace_dtype != SEA_F32 && o->ace_dtype != SEA_BF16)
         return fail(ctx, SEA_E_ARG, "bad ace_dtype");
-    if (o->start != SEA_START_ZERO) return fail(ctx, SEA_E_ARG, "start: only SEA_START_ZERO is available");
+    if (o->start != SEA_START_ZERO && o->start != SEA_START_MULTIPOLE)
+        return fail(ctx, SEA_E_ARG, "start must be SEA_START_ZERO or SEA_START_MULTIPOLE");
     if (o->refine_period < 1) return fail(ctx, SEA_E_ARG, "refine_period must be >= 1");
     return SEA_OK;
 }
@@ -94,6 +95,11 @@ ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair*
     if (L.slot_stride < stride) L.slot_stride = stride;
     L.n_chunks = exx_n_chunks((long)stride);
     L.n_slots = n_pairs < ctx->n_cu * 4 ? (n_pairs > 0 ? n_pairs : 1) : ctx->n_cu * 4;
+    int nmax = 1;
+    for (int k = 0; k < n_pairs; ++k)
+        for (int d = 0; d < 3; ++d) nmax = pairs[k].n[d] > nmax ? pairs[k].n[d] : nmax;
+    L.nmax = nmax;
+    L.gstride = (size_t)36 * nmax * nmax;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -106,6 +112,8 @@ ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair*
     L.mom = take(np * SEA_NACC * sizeof(double));
     L.b = take(np * stride * sizeof(double));
     L.v = with_v ? take(np * stride * sizeof(double)) : 0;
+    L.bres = take(np * stride * sizeof(double));
+    L.gbuf = take(np * L.gstride * sizeof(double));
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
     L.csr_off = take((size_t)(n_occ + 1) * sizeof(int));
@@ -331,7 +339,11 @@ static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const v
     a.max_iter = ctx->opts.max_iter;
     a.lmax = ctx->opts.lmax;
     a.queue_ctr = (int*)(base + Ly.scal + 4 * sizeof(double));
-    a.x_nonzero = 0;
+    a.x_nonzero = ctx->opts.start != SEA_START_ZERO;
+    a.bres = (double*)(base + Ly.bres);
+    a.gbuf = (double*)(base + Ly.gbuf);
+    a.gstride = Ly.gstride;
+    a.nmax = Ly.nmax;
     // FP32 state: z-marching kernel (cubic grids, domains up to 64 x 64 in
     // x-y).  FP64 state: the generic kernel (the FP64 z-queue does not fit
     // the register file at this tile shape).
@@ -351,6 +363,11 @@ static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const v
     {
         StageTimer t(ctx, SEA_STAGE_BOUNDARY, s);
         SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
+    }
+    if (a.x_nonzero) {
+        StageTimer t(ctx, SEA_STAGE_GUESS, s);
+        SEA_HIP_CHECK(ctx, launch_me_guess(a, s));
+        SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
     }
     {
         StageTimer t(ctx, SEA_STAGE_CG, s);

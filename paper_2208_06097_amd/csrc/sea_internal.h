@@ -55,7 +55,9 @@ struct StageTimer {
 
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
-    size_t pairs, partial, mom, b, v, slots, stats, csr_off, csr_ent, scal, total;
+    size_t pairs, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, total;
+    size_t gstride;
+    int nmax;
     int n_chunks;
     int n_slots;
     size_t stride;        // doubles per pair-domain array (max interior size)
@@ -91,6 +93,9 @@ struct ExxArgs {
     int* queue_ctr;       // persistent-kernel pair counter (zeroed before the CG launch)
     int x_nonzero;        // v holds a start guess on entry to the CG
     double* bres;         // n_pairs x stride: b - A x0 when x_nonzero
+    double* gbuf;         // ghost-layer multipole values, n_pairs x gstride
+    size_t gstride;       // 36 x nmax^2
+    int nmax;             // largest domain extent over pairs and axes
 };
 
 // Kernel launchers (k_exx.hip).  All enqueue on `s`.
@@ -99,6 +104,8 @@ hipError_t launch_gather_moments(const ExxArgs& a, hipStream_t s);
 hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s);
 hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s);
 hipError_t launch_cg(const ExxArgs& a, hipStream_t s);
+hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s);
+hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
 // z-marching CG (k_cg.hip): needs every pair with n[0], n[1] <= 64.
 bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h);
 size_t cg_zm_lds_bytes(int state_f32);

@@ -266,3 +266,23 @@ def test_c1_full_fp32_state_against_golden(ctx32):
     Wf = W.reshape(cell.n_occ, -1)
     got = Wf[torch.tensor(g["W_orb"], device="cuda"), torch.tensor(g["W_pt"], device="cuda")].cpu().numpy()
     assert np.max(np.abs(got - np.array(g["W_val"]))) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_multipole_start_same_result_fewer_iterations(mini, dtype):
+    """The multipole start changes only the CG start: the same 1e-8 true
+    residual, the same E and W within the bars, fewer iterations."""
+    cell, pl, ref, pairs = mini
+    print(f"case mini multipole start {dtype}", flush=True)
+    sdt = sea.SEA_F64 if dtype == "f64" else sea.SEA_F32
+    c0 = sea.Context(rel_tol=1e-8, stencil_dtype=sdt)
+    c1 = sea.Context(rel_tol=1e-8, stencil_dtype=sdt, start=sea.SEA_START_MULTIPOLE)
+    phi = _dev(cell.phi)
+    W0, E0, s0, _ = c0.exx_action(phi, cell.N, cell.L, pairs)
+    W1, E1, s1, st = c1.exx_action(phi, cell.N, cell.L, pairs)
+    c0.close()
+    c1.close()
+    assert st == sea.SEA_OK and np.all(s1["converged"] == 1) and np.all(s1["rel_res"] <= 1e-8)
+    assert abs(E1 - ref.E) < 1e-6
+    assert np.max(np.abs(W1.cpu().numpy() - ref.W)) < 1e-5
+    assert s1["iters"].mean() < s0["iters"].mean()
