@@ -48,7 +48,7 @@ typedef enum { SEA_F64 = 0, SEA_F32 = 1, SEA_BF16 = 2 } sea_dtype;
 typedef enum {
     SEA_START_ZERO = 0,      /* x0 = 0                                          */
     SEA_START_MULTIPOLE = 1, /* x0 = regularized multipole potential (Eq. 10)   */
-    SEA_START_LEARNED = 2    /* x0 from the 3-D convolutional network           */
+    SEA_START_LEARNED = 2    /* x0 from the 3-D convolutional network (attached) */
 } sea_start;
 
 typedef struct {
@@ -77,6 +77,7 @@ typedef struct {
     sea_start start;        /* CG initial guess                                */
     int32_t refine_period;  /* F32 state: FP64 true-residual refresh period    */
     int32_t profile;        /* non-zero: time each stage with HIP events       */
+    sea_dtype nn_weight_dtype; /* learned start: network weights F32 or BF16   */
     void *hip_stream;       /* hipStream_t; NULL = default stream              */
 } sea_opts;
 
@@ -192,6 +193,51 @@ sea_status sea_ace_apply(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, con
 /* E_xx = -sum_ik <phi_i, xi_k>^2 (Eq. 19), FP64 result on the host. */
 sea_status sea_ace_energy(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, const double *phi_dev,
                           const void *xi_dev, void *ws_dev, size_t ws_bytes, double *exx_host);
+
+/* ---------------------------------------------------------------------
+ * Learned CG warm start (an extension of the CG initial guess of Eq. 9; the
+ * solve still runs to the same true residual).  A 3-D U-Net (16 channels,
+ * levels D, D/2, D/4, D/8, 3x3x3 convolutions with ReLU, average-pool down,
+ * nearest up, skip concatenation, 15 convolutions: e0a e0b e1a e1b e2a e2b
+ * e3a e3b d2a d2b d1a d1b d0a d0b head) maps x = rho/s resampled to D^3
+ * (corner-aligned trilinear, s = dV sum |rho|) to the correction
+ * (v - v_ME)/s of the multipole start; the start is v_ME + s up(net(x)).
+ * Parameters are one flat FP32 array, per layer weights [O][C][3][3][3] then
+ * bias [O].  Activations FP32; weights FP32 or BF16 (opts.nn_weight_dtype),
+ * FP32 accumulation.
+ * --------------------------------------------------------------------- */
+
+/* Number of FP32 parameters of the network. */
+size_t sea_nn_param_count(void);
+/* Bytes of the device state: FP32 parameters, their BF16 copy, Adam m, v. */
+sea_status sea_nn_state_bytes(sea_ctx *ctx, size_t *bytes);
+/* Upload parameters (host FP32, sea_nn_param_count floats), zero the Adam
+ * moments and refresh the BF16 copy. */
+sea_status sea_nn_set_params(sea_ctx *ctx, void *state_dev, const float *params_host);
+/* Download the FP32 parameters (synchronizes). */
+sea_status sea_nn_get_params(sea_ctx *ctx, const void *state_dev, float *params_host);
+/* Workspace for a batch of `batch` inputs of D^3 (D a multiple of 8, <= 64). */
+sea_status sea_nn_workspace_bytes(sea_ctx *ctx, int batch, int D, size_t *bytes);
+/* y = net(x); x, y: batch x D^3 FP32 device arrays. */
+sea_status sea_nn_forward(sea_ctx *ctx, const void *state_dev, int batch, int D, const float *x_dev,
+                          float *y_dev, void *ws_dev, size_t ws_bytes);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, `step`
+ * 1-based) on the mean squared error between net(x) and t.  loss_host
+ * (nullable) receives the loss before the step (synchronizes); grad_dev
+ * (nullable, sea_nn_param_count floats) receives the gradient. */
+sea_status sea_nn_train_step(sea_ctx *ctx, void *state_dev, int batch, int D, const float *x_dev,
+                             const float *t_dev, float lr, int step, void *ws_dev, size_t ws_bytes,
+                             double *loss_host, float *grad_dev);
+/* Network used by SEA_START_LEARNED (the state must outlive those calls). */
+sea_status sea_nn_attach(sea_ctx *ctx, const void *state_dev);
+/* Training samples from converged pair solves (the solve of
+ * sea_exx_pair_solve with the context's options): for pair k,
+ * x_dev[k*D^3..] = resample(rho/s) and t_dev[k*D^3..] = resample((v - v_ME)/s)
+ * on D^3, s = dV sum |rho|; s_dev (nullable) receives s. */
+sea_status sea_exx_nn_samples(sea_ctx *ctx, const sea_grid *grid, int n_occ, const void *phi_dev,
+                              sea_dtype phi_dtype, int n_pairs, const sea_pair *pairs_host,
+                              void *ws_dev, size_t ws_bytes, int D, float *x_dev, float *t_dev,
+                              double *s_dev, sea_pair_stat *stats_host);
 
 /* Milliseconds spent in each stage by the most recent profiled call that
  * ran it (HIP events on opts.hip_stream; waits for those events).  ms_out

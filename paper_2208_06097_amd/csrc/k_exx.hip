@@ -199,6 +199,36 @@ __global__ __launch_bounds__(BF_BS) void k_ghost_fold(ExxArgs a) {
 //     r_s = sqrt(2 <r^2>/3) from the |rho|-weighted second moment (the
 //     exact width for a spherical Gaussian density).
 
+// Regularized multipole potential at displacement (dx,dy,dz); Q = the 52
+// accumulators of a pair (Racah moments, |rho| sum, q, |rho| r^2 sum).
+template <int LM>
+__device__ __forceinline__ double me_start_value(const double* Q, int lmax, double dx, double dy, double dz) {
+    const double r2m = Q[SEA_NMOM] > 0.0 ? Q[SEA_NMOM + 2] / Q[SEA_NMOM] : 1.0;
+    const double rs = sqrt(fmax(2.0 * r2m / 3.0, 1e-6));
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r = sqrt(r2);
+    if (r < 1e-12) return Q[0] * 2.0 / (rs * sqrt(kPi));
+    double R[(LM + 1) * (LM + 1)];
+    racah_solid<LM>(dx, dy, dz, R);
+    const double rinv = 1.0 / r, rinv2 = rinv * rinv;
+    const double damp = 1.0 - exp(-r2 / (rs * rs));
+    double val = Q[0] * erf(r / rs) * rinv;
+    double pw = rinv * rinv2, dl = damp;
+#pragma unroll
+    for (int l = 1; l <= LM; ++l) {
+        dl *= damp;
+        if (l <= lmax) {
+            const int base = l * l + l;
+            double acc = Q[base] * R[base];
+#pragma unroll
+            for (int m = 1; m <= l; ++m) acc += 2.0 * (Q[base + m] * R[base + m] + Q[base - m] * R[base - m]);
+            val += acc * pw * dl;
+        }
+        pw *= rinv2;
+    }
+    return val;
+}
+
 template <int LM>
 __global__ __launch_bounds__(GM_BS) void k_me_guess(ExxArgs a) {
     __shared__ double Q[SEA_NACC];
@@ -211,40 +241,100 @@ __global__ __launch_bounds__(GM_BS) void k_me_guess(ExxArgs a) {
     const long beg = (long)blockIdx.x * GM_CHUNK;
     if (beg >= n_int) return;
     const long end = min(beg + GM_CHUNK, n_int);
-    const double r2m = Q[SEA_NMOM] > 0.0 ? Q[SEA_NMOM + 2] / Q[SEA_NMOM] : 1.0;
-    const double rs = sqrt(fmax(2.0 * r2m / 3.0, 1e-6));
     double* x = a.v + (size_t)pid * a.stride;
     for (long id = beg + threadIdx.x; id < end; id += GM_BS) {
         const int xx = (int)(id % nx), yy = (int)((id / nx) % ny), zz = (int)(id / ((long)nx * ny));
-        const double dx = (P.lo[0] + xx) * a.h[0] - P.origin[0];
-        const double dy = (P.lo[1] + yy) * a.h[1] - P.origin[1];
-        const double dz = (P.lo[2] + zz) * a.h[2] - P.origin[2];
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const double r = sqrt(r2);
-        double val;
-        if (r < 1e-12) {
-            val = Q[0] * 2.0 / (rs * sqrt(kPi));
+        x[id] = me_start_value<LM>(Q, a.lmax, (P.lo[0] + xx) * a.h[0] - P.origin[0],
+                                   (P.lo[1] + yy) * a.h[1] - P.origin[1], (P.lo[2] + zz) * a.h[2] - P.origin[2]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3c. learned start: corner-aligned trilinear maps between a pair domain
+//     (n per axis) and the network grid (D per axis).  Sample k of D sits at
+//     fine coordinate k (n-1)/(D-1); fine point i sits at coarse i (D-1)/(n-1).
+
+struct Lerp {
+    int i0;
+    double t;
+};
+
+__device__ __forceinline__ Lerp lerp_at(int k, int from, int to) {
+    // position of sample k of a `to`-grid on a `from`-grid
+    if (from < 2) return Lerp{0, 0.0};
+    const double u = (double)k * (double)(from - 1) / (double)(to - 1);
+    int i0 = (int)floor(u);
+    if (i0 > from - 2) i0 = from - 2;
+    return Lerp{i0, u - i0};
+}
+
+constexpr int NNS_BS = 256;
+
+// mode 0: x32 = resample(rho / s); mode 1: t32 = resample((v - v_ME) / s)
+template <int LM>
+__global__ __launch_bounds__(NNS_BS) void k_nn_sample(ExxArgs a, int D, float* __restrict__ out, double* s_out,
+                                                      int mode) {
+    __shared__ double Q[SEA_NACC];
+    const int pid = blockIdx.y;
+    if (threadIdx.x < SEA_NACC) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
+    __syncthreads();
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int D3 = D * D * D;
+    const int k = blockIdx.x * NNS_BS + threadIdx.x;
+    const double s = Q[SEA_NMOM];
+    if (k == 0 && s_out) s_out[pid] = s;
+    if (k >= D3) return;
+    const Lerp lx = lerp_at(k % D, nx, D), ly = lerp_at((k / D) % D, ny, D), lz = lerp_at(k / (D * D), nz, D);
+    const size_t oi = (size_t)P.i * a.Ng, oj = (size_t)P.j * a.Ng;
+    const double* v = a.v + (size_t)pid * a.stride;
+    double acc = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const int cx = lx.i0 + (c & 1), cy = ly.i0 + ((c >> 1) & 1), cz = lz.i0 + (c >> 2);
+        const double wgt = ((c & 1) ? lx.t : 1.0 - lx.t) * (((c >> 1) & 1) ? ly.t : 1.0 - ly.t) *
+                           ((c >> 2) ? lz.t : 1.0 - lz.t);
+        if (wgt == 0.0 || cx >= nx || cy >= ny || cz >= nz) continue;
+        double f;
+        if (mode == 0) {
+            const size_t g = ((size_t)wrap_idx(P.lo[2] + cz, a.N[2]) * a.N[1] + wrap_idx(P.lo[1] + cy, a.N[1])) *
+                                 a.N[0] +
+                             wrap_idx(P.lo[0] + cx, a.N[0]);
+            f = load_phi(a.phi, a.phi_f32, oi + g) * load_phi(a.phi, a.phi_f32, oj + g);
         } else {
-            double R[(LM + 1) * (LM + 1)];
-            racah_solid<LM>(dx, dy, dz, R);
-            const double rinv = 1.0 / r, rinv2 = rinv * rinv;
-            const double damp = 1.0 - exp(-r2 / (rs * rs));
-            val = Q[0] * erf(r / rs) * rinv;
-            double pw = rinv * rinv2, dl = damp;
-#pragma unroll
-            for (int l = 1; l <= LM; ++l) {
-                dl *= damp;
-                if (l <= a.lmax) {
-                    const int base = l * l + l;
-                    double acc = Q[base] * R[base];
-#pragma unroll
-                    for (int m = 1; m <= l; ++m) acc += 2.0 * (Q[base + m] * R[base + m] + Q[base - m] * R[base - m]);
-                    val += acc * pw * dl;
-                }
-                pw *= rinv2;
-            }
+            f = v[((size_t)cz * ny + cy) * nx + cx] -
+                me_start_value<LM>(Q, a.lmax, (P.lo[0] + cx) * a.h[0] - P.origin[0],
+                                   (P.lo[1] + cy) * a.h[1] - P.origin[1], (P.lo[2] + cz) * a.h[2] - P.origin[2]);
         }
-        x[id] = val;
+        acc += wgt * f;
+    }
+    out[(size_t)pid * D3 + k] = s > 0.0 ? (float)(acc / s) : 0.0f;
+}
+
+// x += s * upsample(y32) on the pair domain
+__global__ __launch_bounds__(GM_BS) void k_nn_apply(ExxArgs a, int D, const float* __restrict__ y32) {
+    const int pid = blockIdx.y;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const long n_int = (long)nx * ny * nz;
+    const long beg = (long)blockIdx.x * GM_CHUNK;
+    if (beg >= n_int) return;
+    const long end = min(beg + GM_CHUNK, n_int);
+    const double s = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM];
+    if (!(s > 0.0)) return;
+    const float* y = y32 + (size_t)pid * D * D * D;
+    double* x = a.v + (size_t)pid * a.stride;
+    for (long id = beg + threadIdx.x; id < end; id += GM_BS) {
+        const int ix = (int)(id % nx), iy = (int)((id / nx) % ny), iz = (int)(id / ((long)nx * ny));
+        const Lerp lx = lerp_at(ix, D, nx), ly = lerp_at(iy, D, ny), lz = lerp_at(iz, D, nz);
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int cx = lx.i0 + (c & 1), cy = ly.i0 + ((c >> 1) & 1), cz = lz.i0 + (c >> 2);
+            const double wgt = ((c & 1) ? lx.t : 1.0 - lx.t) * (((c >> 1) & 1) ? ly.t : 1.0 - ly.t) *
+                               ((c >> 2) ? lz.t : 1.0 - lz.t);
+            acc += wgt * (double)y[(cz * D + cy) * D + cx];
+        }
+        x[id] += s * acc;
     }
 }
 
@@ -522,6 +612,17 @@ hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s) {
 
 hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_me_guess<SEA_LMAX>, dim3(a.n_chunks, a.n_pairs), dim3(GM_BS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_nn_sample<SEA_LMAX>, dim3((D * D * D + NNS_BS - 1) / NNS_BS, a.n_pairs), dim3(NNS_BS), 0, s,
+                       a, D, out, s_out, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s) {
+    hipLaunchKernelGGL(k_nn_apply, dim3(a.n_chunks, a.n_pairs), dim3(GM_BS), 0, s, a, D, y32);
     return hipGetLastError();
 }
 

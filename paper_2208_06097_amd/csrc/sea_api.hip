@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 
+#include "nn_internal.h"
 #include "sea_internal.h"
 
 namespace {
@@ -46,8 +47,10 @@ sea_status check_opts(sea_ctx* ctx, const sea_opts* o) {
         return fail(ctx, SEA_E_ARG, "stencil_dtype must be SEA_F64 or SEA_F32");
     if (o->ace_dtype != SEA_F64 && o->ace_dtype != SEA_F32 && o->ace_dtype != SEA_BF16)
         return fail(ctx, SEA_E_ARG, "bad ace_dtype");
-    if (o->start != SEA_START_ZERO && o->start != SEA_START_MULTIPOLE)
-        return fail(ctx, SEA_E_ARG, "start must be SEA_START_ZERO or SEA_START_MULTIPOLE");
+    if (o->start != SEA_START_ZERO && o->start != SEA_START_MULTIPOLE && o->start != SEA_START_LEARNED)
+        return fail(ctx, SEA_E_ARG, "bad start");
+    if (o->nn_weight_dtype != SEA_F32 && o->nn_weight_dtype != SEA_BF16)
+        return fail(ctx, SEA_E_ARG, "nn_weight_dtype must be SEA_F32 or SEA_BF16");
     if (o->refine_period < 1) return fail(ctx, SEA_E_ARG, "refine_period must be >= 1");
     return SEA_OK;
 }
@@ -119,8 +122,38 @@ ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair*
     L.csr_off = take((size_t)(n_occ + 1) * sizeof(int));
     L.csr_ent = take(2 * np * sizeof(int2));
     L.scal = take(8 * sizeof(double));
+    if (ctx->opts.start == SEA_START_LEARNED) {
+        const size_t d3 = (size_t)kNnGrid * kNnGrid * kNnGrid;
+        L.nnx = take(np * d3 * sizeof(float));
+        L.nny = take(np * d3 * sizeof(float));
+        L.nnact = take(nn_act_layout(kNnInferBatch, kNnGrid).total_floats * sizeof(float));
+    }
     L.total = off;
     return L;
+}
+
+// Pointers into the network state: FP32 parameters, BF16 copy, Adam m, v.
+struct NnState {
+    float* p;
+    uint16_t* p16;
+    float* m;
+    float* v;
+};
+static size_t nn_state_total(size_t P) {
+    size_t off = align_up(P * sizeof(float));
+    off += align_up(P * sizeof(uint16_t));
+    off += 2 * align_up(P * sizeof(float));
+    return off;
+}
+static NnState nn_state_ptrs(const void* base) {
+    const size_t P = nn_param_count();
+    char* b = (char*)base;
+    NnState st;
+    st.p = (float*)b;
+    st.p16 = (uint16_t*)(b + align_up(P * sizeof(float)));
+    st.m = (float*)(b + align_up(P * sizeof(float)) + align_up(P * sizeof(uint16_t)));
+    st.v = (float*)((char*)st.m + align_up(P * sizeof(float)));
+    return st;
 }
 
 extern "C" {
@@ -139,6 +172,7 @@ void sea_opts_default(sea_opts* o) {
     o->start = SEA_START_ZERO;
     o->refine_period = 50;
     o->profile = 0;
+    o->nn_weight_dtype = SEA_BF16;
     o->hip_stream = nullptr;
 }
 
@@ -261,7 +295,8 @@ sea_status sea_exx_workspace_bytes(sea_ctx* ctx, const sea_grid* grid, int n_occ
 static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev, sea_dtype phi_dtype,
                           int n_pairs, const sea_pair* pairs, void* ws_dev, size_t ws_bytes, double* W_dev,
                           double* exx_dev, double* exx_host, double* v_ext, double* Q_dev, double* e_dev,
-                          sea_pair_stat* stats_host) {
+                          sea_pair_stat* stats_host, int nn_D = 0, float* nn_x = nullptr, float* nn_t = nullptr,
+                          double* nn_s = nullptr) {
     if (!ctx) return SEA_E_ARG;
     sea_status st = check_grid(ctx, grid);
     if (st != SEA_OK) return st;
@@ -271,6 +306,8 @@ static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const v
     st = check_pairs(ctx, n_occ, n_pairs, pairs);
     if (st != SEA_OK) return st;
     if (!ws_dev) return fail(ctx, SEA_E_ARG, "workspace is NULL");
+    if (ctx->opts.start == SEA_START_LEARNED && !ctx->nn_state)
+        return fail(ctx, SEA_E_ARG, "SEA_START_LEARNED needs a network (sea_nn_attach)");
     const bool action = (W_dev != nullptr);
     const ExxLayout Ly = exx_layout(ctx, n_occ, n_pairs, pairs, true);
     if (ws_bytes < Ly.total)
@@ -367,6 +404,21 @@ static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const v
     if (a.x_nonzero) {
         StageTimer t(ctx, SEA_STAGE_GUESS, s);
         SEA_HIP_CHECK(ctx, launch_me_guess(a, s));
+        if (ctx->opts.start == SEA_START_LEARNED) {
+            float* x32 = (float*)(base + Ly.nnx);
+            float* y32 = (float*)(base + Ly.nny);
+            float* act = (float*)(base + Ly.nnact);
+            const NnActLayout AL = nn_act_layout(kNnInferBatch, kNnGrid);
+            const NnState st = nn_state_ptrs(ctx->nn_state);
+            const size_t d3 = (size_t)kNnGrid * kNnGrid * kNnGrid;
+            SEA_HIP_CHECK(ctx, launch_nn_sample(a, kNnGrid, x32, nullptr, 0, s));
+            for (int p0 = 0; p0 < n_pairs; p0 += kNnInferBatch) {
+                const int nb = n_pairs - p0 < kNnInferBatch ? n_pairs - p0 : kNnInferBatch;
+                SEA_HIP_CHECK(ctx, nn_forward(st.p, ctx->opts.nn_weight_dtype == SEA_BF16 ? st.p16 : nullptr,
+                                              x32 + p0 * d3, act, AL, nb, kNnGrid, y32 + p0 * d3, s));
+            }
+            SEA_HIP_CHECK(ctx, launch_nn_apply(a, kNnGrid, y32, s));
+        }
         SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
     }
     {
@@ -385,6 +437,10 @@ static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const v
     {
         StageTimer t(ctx, SEA_STAGE_ENERGY, s);
         SEA_HIP_CHECK(ctx, launch_energy_sum(a, scal, exx_dev, e_dev, s));
+    }
+    if (nn_x) {
+        SEA_HIP_CHECK(ctx, launch_nn_sample(a, nn_D, nn_x, nn_s, 0, s));
+        SEA_HIP_CHECK(ctx, launch_nn_sample(a, nn_D, nn_t, nullptr, 1, s));
     }
 
     sea_status ret = SEA_OK;
@@ -421,6 +477,124 @@ sea_status sea_exx_pair_solve(sea_ctx* ctx, const sea_grid* grid, int n_occ, con
     if (!v_dev) return fail(ctx, SEA_E_ARG, "v_dev is NULL");
     return exx_run(ctx, grid, n_occ, phi_dev, phi_dtype, n_pairs, pairs_host, ws_dev, ws_bytes, nullptr, nullptr,
                    nullptr, v_dev, Q_dev, e_dev, stats_host);
+}
+
+sea_status sea_exx_nn_samples(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev, sea_dtype phi_dtype,
+                              int n_pairs, const sea_pair* pairs_host, void* ws_dev, size_t ws_bytes, int D,
+                              float* x_dev, float* t_dev, double* s_dev, sea_pair_stat* stats_host) {
+    if (!ctx) return SEA_E_ARG;
+    if (D < 2 || !x_dev || !t_dev) return fail(ctx, SEA_E_ARG, "need D >= 2 and x_dev, t_dev");
+    for (int k = 0; k < n_pairs && pairs_host; ++k)
+        for (int d = 0; d < 3; ++d)
+            if (pairs_host[k].n[d] < 2) return fail(ctx, SEA_E_ARG, "pair %d: domain extent < 2", k);
+    // the solution lives in the workspace v array (pair_solve layout)
+    return exx_run(ctx, grid, n_occ, phi_dev, phi_dtype, n_pairs, pairs_host, ws_dev, ws_bytes, nullptr, nullptr,
+                   nullptr, nullptr, nullptr, nullptr, stats_host, D, x_dev, t_dev, s_dev);
+}
+
+size_t sea_nn_param_count(void) { return nn_param_count(); }
+
+sea_status sea_nn_state_bytes(sea_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return SEA_E_ARG;
+    *bytes = nn_state_total(nn_param_count());
+    return SEA_OK;
+}
+
+sea_status sea_nn_set_params(sea_ctx* ctx, void* state_dev, const float* params_host) {
+    if (!ctx) return SEA_E_ARG;
+    if (!state_dev || !params_host) return fail(ctx, SEA_E_ARG, "NULL argument");
+    const size_t P = nn_param_count();
+    for (size_t i = 0; i < P; ++i)
+        if (!std::isfinite(params_host[i])) return fail(ctx, SEA_E_NONFINITE, "parameter %zu is not finite", i);
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    const NnState st = nn_state_ptrs(state_dev);
+    SEA_HIP_CHECK(ctx, hipMemcpyAsync(st.p, params_host, P * sizeof(float), hipMemcpyHostToDevice, s));
+    SEA_HIP_CHECK(ctx, hipMemsetAsync(st.m, 0, P * sizeof(float), s));
+    SEA_HIP_CHECK(ctx, hipMemsetAsync(st.v, 0, P * sizeof(float), s));
+    SEA_HIP_CHECK(ctx, nn_to_bf16(st.p, st.p16, (long)P, s));
+    SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+    return SEA_OK;
+}
+
+sea_status sea_nn_get_params(sea_ctx* ctx, const void* state_dev, float* params_host) {
+    if (!ctx) return SEA_E_ARG;
+    if (!state_dev || !params_host) return fail(ctx, SEA_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    const NnState st = nn_state_ptrs(state_dev);
+    SEA_HIP_CHECK(ctx, hipMemcpyAsync(params_host, st.p, nn_param_count() * sizeof(float), hipMemcpyDeviceToHost, s));
+    SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+    return SEA_OK;
+}
+
+static sea_status nn_check(sea_ctx* ctx, int batch, int D) {
+    if (batch < 1) return fail(ctx, SEA_E_ARG, "batch < 1");
+    if (D < 8 || D > 64 || D % 8) return fail(ctx, SEA_E_ARG, "D must be a multiple of 8 in 8..64");
+    return SEA_OK;
+}
+
+static size_t nn_ws_total(int batch, int D) {
+    return align_up(nn_act_layout(batch, D).total_floats * sizeof(float)) + 256;
+}
+
+sea_status sea_nn_workspace_bytes(sea_ctx* ctx, int batch, int D, size_t* bytes) {
+    if (!ctx || !bytes) return SEA_E_ARG;
+    sea_status st = nn_check(ctx, batch, D);
+    if (st != SEA_OK) return st;
+    *bytes = nn_ws_total(batch, D);
+    return SEA_OK;
+}
+
+sea_status sea_nn_forward(sea_ctx* ctx, const void* state_dev, int batch, int D, const float* x_dev, float* y_dev,
+                          void* ws_dev, size_t ws_bytes) {
+    if (!ctx) return SEA_E_ARG;
+    sea_status st = nn_check(ctx, batch, D);
+    if (st != SEA_OK) return st;
+    if (!state_dev || !x_dev || !y_dev || !ws_dev) return fail(ctx, SEA_E_ARG, "NULL argument");
+    if (ws_bytes < nn_ws_total(batch, D)) return fail(ctx, SEA_E_NOMEM, "workspace too small");
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    const NnState ns = nn_state_ptrs(state_dev);
+    const NnActLayout L = nn_act_layout(batch, D);
+    SEA_HIP_CHECK(ctx, nn_forward(ns.p, ctx->opts.nn_weight_dtype == SEA_BF16 ? ns.p16 : nullptr, x_dev,
+                                  (float*)ws_dev, L, batch, D, y_dev, s));
+    return SEA_OK;
+}
+
+sea_status sea_nn_train_step(sea_ctx* ctx, void* state_dev, int batch, int D, const float* x_dev, const float* t_dev,
+                             float lr, int step, void* ws_dev, size_t ws_bytes, double* loss_host, float* grad_dev) {
+    if (!ctx) return SEA_E_ARG;
+    sea_status st = nn_check(ctx, batch, D);
+    if (st != SEA_OK) return st;
+    if (!state_dev || !x_dev || !t_dev || !ws_dev) return fail(ctx, SEA_E_ARG, "NULL argument");
+    if (step < 1 || !(lr > 0.0f)) return fail(ctx, SEA_E_ARG, "need step >= 1 and lr > 0");
+    if (ws_bytes < nn_ws_total(batch, D)) return fail(ctx, SEA_E_NOMEM, "workspace too small");
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    const NnState ns = nn_state_ptrs(state_dev);
+    const NnActLayout L = nn_act_layout(batch, D);
+    float* act = (float*)ws_dev;
+    double* loss_dev = (double*)((char*)ws_dev + align_up(L.total_floats * sizeof(float)));
+    const uint16_t* w16 = ctx->opts.nn_weight_dtype == SEA_BF16 ? ns.p16 : nullptr;
+    const long n = (long)batch * D * D * D;
+    SEA_HIP_CHECK(ctx, nn_forward(ns.p, w16, x_dev, act, L, batch, D, nullptr, s));
+    float* y = act + L.out[kNnNumLayers - 1];
+    float* g = act + L.g2;
+    SEA_HIP_CHECK(ctx, nn_mse(y, t_dev, n, g, (double*)(act + L.mse_part), loss_dev, s));
+    SEA_HIP_CHECK(ctx, nn_backward(ns.p, w16, x_dev, act, L, batch, D, g, s));
+    const long P = (long)nn_param_count();
+    if (grad_dev)
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(grad_dev, act + L.grad, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+    SEA_HIP_CHECK(ctx, nn_adam(ns.p, ns.p16, ns.m, ns.v, act + L.grad, P, lr, step, s));
+    if (loss_host) {
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(loss_host, loss_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+        SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+        if (!std::isfinite(*loss_host)) return fail(ctx, SEA_E_NONFINITE, "non-finite loss");
+    }
+    return SEA_OK;
+}
+
+sea_status sea_nn_attach(sea_ctx* ctx, const void* state_dev) {
+    if (!ctx) return SEA_E_ARG;
+    ctx->nn_state = state_dev;
+    return SEA_OK;
 }
 
 sea_status sea_solid_harmonics_host(int lmax, double x, double y, double z, double* out) {

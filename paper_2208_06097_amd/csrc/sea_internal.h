@@ -35,6 +35,7 @@ struct sea_ctx {
     hipEvent_t ev[SEA_STAGE_COUNT][2] = {};
     bool ev_used[SEA_STAGE_COUNT] = {};
     bool ev_ready = false;
+    const void* nn_state = nullptr;   // attached network (learned start)
 };
 
 // Records the begin/end event of a stage when profiling is on.
@@ -44,18 +45,18 @@ struct StageTimer {
     hipStream_t s;
     StageTimer(sea_ctx* c, int st, hipStream_t str) : ctx(c), stage(st), s(str) {
         if (ctx->opts.profile && ctx->ev_ready) {
-            hipEventRecord(ctx->ev[stage][0], s);
+            (void)hipEventRecord(ctx->ev[stage][0], s);
             ctx->ev_used[stage] = true;
         }
     }
     ~StageTimer() {
-        if (ctx->opts.profile && ctx->ev_ready) hipEventRecord(ctx->ev[stage][1], s);
+        if (ctx->opts.profile && ctx->ev_ready) (void)hipEventRecord(ctx->ev[stage][1], s);
     }
 };
 
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
-    size_t pairs, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, total;
+    size_t pairs, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, nnx, nny, nnact, total;
     size_t gstride;
     int nmax;
     int n_chunks;
@@ -105,6 +106,8 @@ hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s)
 hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s);
 hipError_t launch_cg(const ExxArgs& a, hipStream_t s);
 hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s);
+hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s);
+hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s);
 hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
 // z-marching CG (k_cg.hip): needs every pair with n[0], n[1] <= 64.
 bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h);

@@ -26,7 +26,38 @@ EXPORTS = [
     "sea_set_opts", "sea_build_pairs", "sea_exx_workspace_bytes", "sea_exx_action",
     "sea_exx_pair_solve", "sea_ace_workspace_bytes", "sea_ace_build", "sea_ace_apply",
     "sea_ace_energy", "sea_solid_harmonics_host", "sea_stage_times",
+    "sea_nn_param_count", "sea_nn_state_bytes", "sea_nn_set_params", "sea_nn_get_params",
+    "sea_nn_workspace_bytes", "sea_nn_forward", "sea_nn_train_step", "sea_nn_attach",
+    "sea_exx_nn_samples",
 ]
+
+# the network's layers (name, c_in, c_out, relu), in parameter order
+NN_LAYERS = [
+    ("e0a", 1, 16, True), ("e0b", 16, 16, True), ("e1a", 16, 16, True), ("e1b", 16, 16, True),
+    ("e2a", 16, 16, True), ("e2b", 16, 16, True), ("e3a", 16, 16, True), ("e3b", 16, 16, True),
+    ("d2a", 32, 16, True), ("d2b", 16, 16, True), ("d1a", 32, 16, True), ("d1b", 16, 16, True),
+    ("d0a", 32, 16, True), ("d0b", 16, 16, True), ("head", 16, 1, False),
+]
+
+
+def nn_pack(params: dict) -> np.ndarray:
+    """Flatten {name.w: (O, C, 3, 3, 3), name.b: (O,)} into the library's order."""
+    parts = []
+    for name, _, _, _ in NN_LAYERS:
+        parts.append(np.asarray(params[name + ".w"], dtype=np.float32).ravel())
+        parts.append(np.asarray(params[name + ".b"], dtype=np.float32).ravel())
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
+def nn_unpack(flat: np.ndarray) -> dict:
+    out, off = {}, 0
+    for name, ci, co, _ in NN_LAYERS:
+        nw = co * ci * 27
+        out[name + ".w"] = flat[off:off + nw].reshape(co, ci, 3, 3, 3)
+        off += nw
+        out[name + ".b"] = flat[off:off + co]
+        off += co
+    return out
 
 PAIR_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("lo", "<i4", 3), ("n", "<i4", 3),
                        ("origin", "<f8", 3)])
@@ -42,7 +73,7 @@ class SeaOpts(C.Structure):
     _fields_ = [("fd_half_order", C.c_int32), ("lmax", C.c_int32), ("rel_tol", C.c_double),
                 ("max_iter", C.c_int32), ("stencil_dtype", C.c_int), ("ace_dtype", C.c_int),
                 ("start", C.c_int), ("refine_period", C.c_int32), ("profile", C.c_int32),
-                ("hip_stream", C.c_void_p)]
+                ("nn_weight_dtype", C.c_int), ("hip_stream", C.c_void_p)]
 
 
 STAGES = ["gather", "boundary", "guess", "cg", "scatter", "energy", "ace_m", "ace_chol", "ace_xi",
@@ -85,6 +116,15 @@ def load() -> C.CDLL:
     lib.sea_ace_energy.argtypes = [vp, C.c_int64, i, d, vp, vp, vp, sz, P(d)]
     lib.sea_solid_harmonics_host.argtypes = [i, d, d, d, vp]
     lib.sea_stage_times.argtypes = [vp, vp]
+    lib.sea_nn_param_count.restype = C.c_size_t
+    lib.sea_nn_state_bytes.argtypes = [vp, P(sz)]
+    lib.sea_nn_set_params.argtypes = [vp, vp, vp]
+    lib.sea_nn_get_params.argtypes = [vp, vp, vp]
+    lib.sea_nn_workspace_bytes.argtypes = [vp, i, i, P(sz)]
+    lib.sea_nn_forward.argtypes = [vp, vp, i, i, vp, vp, vp, sz]
+    lib.sea_nn_train_step.argtypes = [vp, vp, i, i, vp, vp, C.c_float, i, vp, sz, vp, vp]
+    lib.sea_nn_attach.argtypes = [vp, vp]
+    lib.sea_exx_nn_samples.argtypes = [vp, P(SeaGrid), i, vp, i, i, vp, vp, sz, i, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -136,7 +176,8 @@ class Context:
     """A library context bound to the current torch CUDA device and stream."""
 
     def __init__(self, rel_tol=1e-8, max_iter=10000, lmax=6, stencil_dtype=SEA_F64,
-                 ace_dtype=SEA_F64, start=SEA_START_ZERO, refine_period=50, profile=False, stream=None):
+                 ace_dtype=SEA_F64, start=SEA_START_ZERO, refine_period=50, profile=False,
+                 nn_weight_dtype=SEA_BF16, stream=None):
         import torch
         self._torch = torch
         self.lib = load()
@@ -145,6 +186,7 @@ class Context:
         o.rel_tol, o.max_iter, o.lmax = rel_tol, max_iter, lmax
         o.stencil_dtype, o.ace_dtype, o.start, o.refine_period = stencil_dtype, ace_dtype, start, refine_period
         o.profile = 1 if profile else 0
+        o.nn_weight_dtype = nn_weight_dtype
         if stream is None:
             stream = torch.cuda.current_stream()
         o.hip_stream = C.c_void_p(stream.cuda_stream)
@@ -293,3 +335,73 @@ class Context:
                                      ws.numel(), C.byref(E))
         self._check(st)
         return E.value
+
+    # ---------------------------------------------------------------- network
+    def nn_param_count(self) -> int:
+        return int(self.lib.sea_nn_param_count())
+
+    def nn_state(self, params_flat=None):
+        """Device state (FP32 params, BF16 copy, Adam moments); optionally loaded."""
+        b = C.c_size_t(0)
+        self._check(self.lib.sea_nn_state_bytes(self.h, C.byref(b)))
+        st = self._torch.zeros(b.value, dtype=self._torch.uint8, device="cuda")
+        if params_flat is not None:
+            self.nn_set_params(st, params_flat)
+        return st
+
+    def nn_set_params(self, state, params_flat):
+        p = np.ascontiguousarray(params_flat, dtype=np.float32)
+        assert p.size == self.nn_param_count()
+        self._check(self.lib.sea_nn_set_params(self.h, state.data_ptr(), p.ctypes.data))
+
+    def nn_get_params(self, state) -> np.ndarray:
+        p = np.zeros(self.nn_param_count(), dtype=np.float32)
+        self._check(self.lib.sea_nn_get_params(self.h, state.data_ptr(), p.ctypes.data))
+        return p
+
+    def nn_workspace(self, batch, D):
+        b = C.c_size_t(0)
+        self._check(self.lib.sea_nn_workspace_bytes(self.h, batch, D, C.byref(b)))
+        return self.workspace(b.value)
+
+    def nn_forward(self, state, x, ws=None):
+        """x: (B, D, D, D) float32 cuda tensor -> y of the same shape."""
+        B, D = x.shape[0], x.shape[-1]
+        if ws is None:
+            ws = self.nn_workspace(B, D)
+        y = self._torch.empty_like(x)
+        self._check(self.lib.sea_nn_forward(self.h, state.data_ptr(), B, D, x.data_ptr(), y.data_ptr(),
+                                            ws.data_ptr(), ws.numel()))
+        return y
+
+    def nn_train_step(self, state, x, t, lr, step, ws=None, want_loss=True, grad=None):
+        B, D = x.shape[0], x.shape[-1]
+        if ws is None:
+            ws = self.nn_workspace(B, D)
+        loss = C.c_double(0.0)
+        self._check(self.lib.sea_nn_train_step(self.h, state.data_ptr(), B, D, x.data_ptr(), t.data_ptr(),
+                                               float(lr), int(step), ws.data_ptr(), ws.numel(),
+                                               C.byref(loss) if want_loss else None,
+                                               grad.data_ptr() if grad is not None else None))
+        return loss.value if want_loss else None
+
+    def nn_attach(self, state):
+        self._nn_state_ref = state
+        self._check(self.lib.sea_nn_attach(self.h, state.data_ptr() if state is not None else None))
+
+    def exx_nn_samples(self, phi, N, L, pairs, D=32, ws=None):
+        """Solve the pairs and return (x, t, s, stats): x = resample(rho/s), t = resample((v - v_ME)/s)."""
+        torch = self._torch
+        n_occ = phi.shape[0]
+        p = np.ascontiguousarray(pairs, dtype=PAIR_DTYPE)
+        if ws is None:
+            ws = self.workspace(self.exx_workspace_bytes(N, L, n_occ, p))
+        x = torch.empty((len(p), D, D, D), dtype=torch.float32, device=phi.device)
+        t = torch.empty_like(x)
+        s = torch.empty(len(p), dtype=torch.float64, device=phi.device)
+        g = _grid(N, L)
+        stats = np.zeros(max(len(p), 1), dtype=STAT_DTYPE)
+        self._check(self.lib.sea_exx_nn_samples(self.h, C.byref(g), n_occ, phi.data_ptr(), self._phi_dtype(phi),
+                                                len(p), p.ctypes.data, ws.data_ptr(), ws.numel(), D,
+                                                x.data_ptr(), t.data_ptr(), s.data_ptr(), stats.ctypes.data))
+        return x, t, s, stats[:len(p)]
