@@ -2,12 +2,18 @@
 """Benchmark of the hot path on one MI355X.
 
 One step = the whole path on the 64-molecule water-like cell (1.0 g/cm^3,
-L = 23.5 bohr, 120^3 grid, 256 orbitals, ~2.4k pairs with 63^3 domains,
-CG to a relative residual of 1e-8): the V_xx action (pair densities,
-multipoles, boundary values, CG solves, scatter, E_xx), the ACE build
-(M = dV Phi^T W, Cholesky, xi = W L^-T), K applied to 256 trial vectors and
-the Eq. 19 energy.  Inputs are synthetic (seeded generator) and resident in
-HBM before the timed region.  Prints one JSON line.
+L = 23.5 bohr, 120^3 grid, 256 orbitals, 2396 pairs with 63^3 domains, CG to
+a relative true residual of 1e-8): the V_xx action (pair densities,
+multipoles, boundary values, initial guess, CG solves, scatter, E_xx), the
+ACE build (M = dV Phi^T W, Cholesky, xi = W L^-T), K applied to 256 trial
+vectors and the Eq. 19 energy.  Inputs are synthetic (seeded generator) and
+resident in HBM before the timed region.  Prints one JSON line.
+
+Forms of the V_xx action (CG state precision / start):
+  plain-f64      FP64 state, zero start
+  plain-f32      FP32 state + FP64 reliable updates, zero start
+  multipole-f32  FP32 state, regularized multipole start
+  learned-f32    FP32 state, learned start (trained network checkpoint)
 """
 from __future__ import annotations
 
@@ -21,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2208_06097_amd", "weights", "unet_f32cg.npy")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "c2.json")
 
 
 def log(*a):
@@ -57,17 +65,26 @@ def cpu_baseline(cell, pairs_np, n_pairs_total, seed=1234):
             "mean_iters": float(np.mean([i["iters"] for i in infos]))}
 
 
+FORMS = {
+    "plain-f64": dict(stencil="f64", start="zero"),
+    "plain-f32": dict(stencil="f32", start="zero"),
+    "multipole-f32": dict(stencil="f32", start="multipole"),
+    "learned-f32": dict(stencil="f32", start="learned"),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2000)
+    ap.add_argument("--form", default=None, choices=list(FORMS),
+                    help="timed form (default: learned-f32 when a checkpoint exists, else plain-f32)")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--other-forms", action="store_true", help="also time one V_xx action of every other form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", default="f32", choices=["f32", "f64"],
-                    help="CG state precision of the timed form (FP64 refinement either way)")
-    ap.add_argument("--other-forms", action="store_true",
-                    help="also time the V_xx action of the other plain form")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 2 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -80,6 +97,17 @@ def main():
     import torch
 
     from paper_2208_06097_amd import sea, synth
+
+    have_w = os.path.exists(args.weights)
+    form = args.form or ("learned-f32" if have_w else "plain-f32")
+    if FORMS[form]["start"] == "learned" and not have_w:
+        print(f"no network checkpoint at {args.weights}", file=sys.stderr)
+        sys.exit(2)
+    golden = None
+    if os.path.exists(GOLDEN):
+        g = json.load(open(GOLDEN))
+        if g.get("seed") == args.seed:
+            golden = g
 
     rank = int(os.environ.get("RANK", "0"))
     torch.cuda.set_device(0)
@@ -100,13 +128,24 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 2 GiB read + 2 GiB written")
         del src, dst
-    sdt = sea.SEA_F32 if args.form == "f32" else sea.SEA_F64
-    ctx = sea.Context(rel_tol=1e-8, profile=True, stencil_dtype=sdt)
+
+    def make_ctx(fname):
+        f = FORMS[fname]
+        start = {"zero": sea.SEA_START_ZERO, "multipole": sea.SEA_START_MULTIPOLE,
+                 "learned": sea.SEA_START_LEARNED}[f["start"]]
+        c = sea.Context(rel_tol=args.tol, profile=True, start=start,
+                        stencil_dtype=sea.SEA_F32 if f["stencil"] == "f32" else sea.SEA_F64)
+        if f["start"] == "learned":
+            c._nn = c.nn_state(np.load(args.weights))
+            c.nn_attach(c._nn)
+        return c
+
+    ctx = make_ctx(form)
     ws = ctx.workspace(ctx.exx_workspace_bytes(cell.N, cell.L, cell.n_occ, pairs))
     ws_ace = ctx.workspace(ctx.ace_workspace_bytes(cell.N ** 3, cell.n_occ, psi.shape[0]))
     W = torch.empty_like(phi)
     exx_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-    log(f"pairs: {n_pairs}; workspace {ws.numel() / 2**30:.2f} GiB")
+    log(f"form {form}; pairs: {n_pairs}; workspace {ws.numel() / 2**30:.2f} GiB")
 
     def step(host=False):
         r = ctx.exx_action(phi, cell.N, cell.L, pairs, ws=ws, W=W, exx_dev=exx_dev, want_host=host)
@@ -115,7 +154,6 @@ def main():
         E_ace = ctx.ace_energy(phi, xi, dV, ws=ws_ace)
         return r, E_ace, Kpsi
 
-    # warmup (the first one also returns host diagnostics)
     (Wr, E, stats, st), E_ace, _ = step(host=True)
     log(f"warmup: E_xx = {E:.9f}  E_ACE = {E_ace:.9f}  iters min/mean/max = "
         f"{stats['iters'].min()}/{stats['iters'].mean():.1f}/{stats['iters'].max()}  status {st}")
@@ -126,8 +164,7 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         step()
-        st_ms = ctx.stage_times()
-        for kk, v in st_ms.items():
+        for kk, v in ctx.stage_times().items():
             stage_acc[kk] += v
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
@@ -135,13 +172,33 @@ def main():
     ms_step = 1000 * dt / args.steps
     stages = {k: v / args.steps for k, v in stage_acc.items()}
     vxx_ms = sum(stages[k] for k in ("gather", "boundary", "guess", "cg", "scatter", "energy"))
-    n_int = int(np.prod(pairs["n"].astype(np.int64), axis=1).mean())
-    it_sum = int(stats["iters"].sum())
-    wbytes = 4.0 if args.form == "f32" else 8.0
+    wbytes = 4.0 if FORMS[form]["stencil"] == "f32" else 8.0
     cg_bytes = float(np.sum(stats["iters"].astype(np.float64) * 6.0
                             * np.prod(pairs["n"].astype(np.float64), axis=1) * wbytes))
-    cg_ms = stages["cg"]
-    achieved = cg_bytes / (cg_ms * 1e-3) / 1e9
+    achieved = cg_bytes / (stages["cg"] * 1e-3) / 1e9
+    kname = "k_cg_zm<float>" if FORMS[form]["stencil"] == "f32" else "k_cg_f64"
+    forms = {form: {"vxx_ms_per_call": vxx_ms, "cg_ms": stages["cg"], "guess_ms": stages["guess"],
+                    "cg_iters_mean": float(stats["iters"].mean()), "E_xx": E, "E_ace": E_ace,
+                    "dE_vs_oracle": (E - golden["E"]) if golden else None,
+                    "dE_ace_vs_oracle": (E_ace - golden["E"]) if golden else None}}
+    if args.other_forms:
+        for fname in FORMS:
+            if fname == form or (FORMS[fname]["start"] == "learned" and not have_w):
+                continue
+            c2 = make_ctx(fname)
+            ws2 = c2.workspace(c2.exx_workspace_bytes(cell.N, cell.L, cell.n_occ, pairs))
+            r2 = c2.exx_action(phi, cell.N, cell.L, pairs, ws=ws2, W=W, exx_dev=exx_dev, want_host=True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            c2.exx_action(phi, cell.N, cell.L, pairs, ws=ws2, W=W, exx_dev=exx_dev, want_host=False)
+            torch.cuda.synchronize()
+            s2 = c2.stage_times()
+            forms[fname] = {"vxx_ms_per_call": 1000 * (time.perf_counter() - t1), "cg_ms": s2["cg"],
+                            "guess_ms": s2["guess"], "cg_iters_mean": float(r2[2]["iters"].mean()), "E_xx": r2[1],
+                            "dE_vs_oracle": (r2[1] - golden["E"]) if golden else None}
+            log(f"form {fname}: {forms[fname]['vxx_ms_per_call']:.1f} ms, iters {forms[fname]['cg_iters_mean']:.1f}")
+            del ws2
+            c2.close()
     out = {
         "metric": "V_xx action ms/call + pair Poisson solves/s, 64-mol cell, learned vs plain",
         "value": n_pairs * args.steps / dt,
@@ -156,32 +213,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.form == "f32" else "f64",
+        "dtype": "f32+f64" if wbytes == 4.0 else "f64",
         "data": "synthetic",
-        "config": {"workload": "64-molecule water-like cell, 1.0 g/cm^3, L=23.5 bohr, 120^3 grid, "
-                               "256 orbitals, 63^3 pair domains, CG rel_tol 1e-8 (true FP64 residual), zero "
-                               "start, plain form; ACE (FP64) with K applied to 256 trial vectors",
-                   "n_pairs": n_pairs, "n_int": n_int, "cg_iters_total": it_sum,
-                   "cg_iters_mean": float(stats["iters"].mean()), "E_xx": E, "E_ace": E_ace,
-                   "form": f"plain-{args.form}-zero"},
-        "roofline": {"bound": "hbm", "kernel": f"k_cg_zm<{'float' if args.form == 'f32' else 'double'}>",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "config": {"workload": "64-molecule water-like cell, 1.0 g/cm^3, L=23.5 bohr, 120^3 grid, 256 orbitals, "
+                               "63^3 pair domains, CG to a relative true FP64 residual; ACE (FP64) with K applied "
+                               "to 256 trial vectors",
+                   "form": form, "rel_tol": args.tol, "n_pairs": n_pairs,
+                   "cg_iters_total": int(stats["iters"].sum())},
+        "forms": forms,
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": cg_bytes,
                      "per_unit": f"6 words x {int(wbytes)} B per interior point per CG iteration"},
     }
-    if args.other_forms:
-        other = "f64" if args.form == "f32" else "f32"
-        ctx.set_opts(stencil_dtype=sea.SEA_F64 if other == "f64" else sea.SEA_F32)
-        r2 = ctx.exx_action(phi, cell.N, cell.L, pairs, ws=ws, W=W, exx_dev=exx_dev, want_host=True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ctx.exx_action(phi, cell.N, cell.L, pairs, ws=ws, W=W, exx_dev=exx_dev, want_host=False)
-        torch.cuda.synchronize()
-        st2 = ctx.stage_times()
-        out["other_forms"] = {f"plain-{other}-zero": {
-            "vxx_ms_per_call": 1000 * (time.perf_counter() - t1),
-            "cg_ms": st2["cg"], "E_xx": r2[1], "cg_iters_mean": float(r2[2]["iters"].mean())}}
     if rank == 0 and not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(cell, pairs, n_pairs)
