@@ -160,6 +160,46 @@ sea_status sea_exx_action(sea_ctx *ctx, const sea_grid *grid, int n_occ, const v
                           void *ws_dev, size_t ws_bytes, double *W_dev, double *exx_dev,
                           double *exx_host, sea_pair_stat *stats_host);
 
+/* One cell of a batched call (pairs of every cell are solved together in
+ * one persistent launch; cells may differ in grid, orbitals and pairs).
+ * phi_dev, W_dev and exx_dev are caller-owned device buffers as in
+ * sea_exx_action; exx_dev is nullable. */
+typedef struct {
+    sea_grid grid;
+    int32_t n_occ;
+    sea_dtype phi_dtype;
+    const void *phi_dev;
+    int32_t n_pairs;
+    const sea_pair *pairs_host;
+    double *W_dev;
+    double *exx_dev;
+} sea_cell;
+
+/* Workspace for sea_exx_action_batched / a plan over these cells. */
+sea_status sea_exx_batched_workspace_bytes(sea_ctx *ctx, int n_cells, const sea_cell *cells, size_t *bytes);
+
+/* The V_xx action of every cell (same definition as sea_exx_action), all
+ * pairs of all cells in one queue: one persistent CG launch for the whole
+ * batch.  Per cell W_dev and exx_dev are written; exx_host (n_cells,
+ * nullable) and stats_host (sum of n_pairs, in cell order, nullable) make
+ * the call synchronize.  Results are bit-identical to per-cell calls. */
+sea_status sea_exx_action_batched(sea_ctx *ctx, int n_cells, const sea_cell *cells, void *ws_dev,
+                                  size_t ws_bytes, double *exx_host, sea_pair_stat *stats_host);
+
+/* A plan fixes the cells, pair tables and workspace once (tables are
+ * uploaded at creation) and records the whole kernel sequence of the batched
+ * action into a HIP graph; sea_exx_plan_launch replays it on `hip_stream`
+ * with no host work and no allocation.  The cells' device buffers and the
+ * workspace must stay valid while the plan is used.  sea_exx_plan_results
+ * waits for the last launch and copies E_xx per cell and the per-pair stats
+ * (both nullable).  Stage profiling is not recorded in a plan. */
+typedef struct sea_plan sea_plan;
+sea_status sea_exx_plan_create(sea_ctx *ctx, int n_cells, const sea_cell *cells, void *ws_dev,
+                               size_t ws_bytes, sea_plan **out);
+sea_status sea_exx_plan_launch(sea_plan *plan, void *hip_stream);
+sea_status sea_exx_plan_results(sea_plan *plan, double *exx_host, sea_pair_stat *stats_host);
+sea_status sea_exx_plan_destroy(sea_plan *plan);
+
 /* Per-pair potentials without the scatter (same solve as sea_exx_action):
  * v_dev receives, for pair k, its interior potential at offset k*stride
  * doubles (stride = max over pairs of n0*n1*n2 rounded up to a multiple of

@@ -210,8 +210,12 @@ struct PVsel {
 };
 
 template <typename T, int NT, int COLS, bool PREFETCH>
-__device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, const SW<T>& w, const SW<double>& wd,
-                           T* __restrict__ cc, T* __restrict__ rr, T* __restrict__ pp, double* __restrict__ r64) {
+__device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __restrict__ cc, T* __restrict__ rr,
+                           T* __restrict__ pp, double* __restrict__ r64) {
+    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const double ih2 = 1.0 / (C.h[0] * C.h[0]);
+    const SW<T> w = make_sw<T>(ih2);
+    const SW<double> wd = make_sw<double>(ih2);
     // Slot arrays (cc, rr, pp, r64) use a padded 64 x 64 plane: element
     // (x,y,z) at (z*64 + y)*64 + x, planes 0..nz+6; cells outside the domain
     // stay zero in rr, pp and r64.
@@ -357,9 +361,6 @@ __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
     T* lds = reinterpret_cast<T*>(smem);
     __shared__ double red[NT / 64 + 1];
     __shared__ int pid_sh;
-    const double ih2 = 1.0 / (a.h[0] * a.h[0]);
-    const SW<T> w = make_sw<T>(ih2);
-    const SW<double> wd = make_sw<double>(ih2);
     for (int i = threadIdx.x; i < 2 * LW * LH; i += NT) lds[i] = T(0);
     char* slot = reinterpret_cast<char*>(a.slots) + (size_t)blockIdx.x * 4 * a.slot_stride * sizeof(double);
     T* cc = reinterpret_cast<T*>(slot);
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
         __syncthreads();
         const int pid = pid_sh;
         if (pid >= a.n_pairs) break;
-        solve_pair<T, NT, COLS, PREFETCH>(a, pid, lds, red, w, wd, cc, rr, pp, r64);
+        solve_pair<T, NT, COLS, PREFETCH>(a, pid, lds, red, cc, rr, pp, r64);
     }
 }
 
@@ -382,22 +383,23 @@ constexpr int FIN_BS = 512;
 __global__ __launch_bounds__(FIN_BS) void k_cg_finish(ExxArgs a) {
     __shared__ double red[FIN_BS / 64 + 1];
     const int pid = blockIdx.x;
+    const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const int n = nx * ny * nz, nxy = nx * ny;
-    const double ih2 = 1.0 / (a.h[0] * a.h[0]);
+    const double ih2 = 1.0 / (C.h[0] * C.h[0]);
     const double* b = a.b + (size_t)pid * a.stride;
     const double* x = a.v + (size_t)pid * a.stride;
-    const size_t oi = (size_t)P.i * a.Ng, oj = (size_t)P.j * a.Ng;
+    const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
     double bb = 0.0, rr = 0.0, e = 0.0;
     for (int id = threadIdx.x; id < n; id += FIN_BS) {
         const int xx = id % nx, yy = (id / nx) % ny, zz = id / nxy;
         const double r = b[id] - apply_A_global(x, id, xx, yy, zz, nx, ny, nz, ih2);
         bb += b[id] * b[id];
         rr += r * r;
-        const size_t g = ((size_t)wrap_idx(P.lo[2] + zz, a.N[2]) * a.N[1] + wrap_idx(P.lo[1] + yy, a.N[1])) * a.N[0] +
-                         wrap_idx(P.lo[0] + xx, a.N[0]);
-        e += load_phi(a.phi, a.phi_f32, oi + g) * load_phi(a.phi, a.phi_f32, oj + g) * x[id];
+        const size_t g = ((size_t)wrap_idx(P.lo[2] + zz, C.N[2]) * C.N[1] + wrap_idx(P.lo[1] + yy, C.N[1])) * C.N[0] +
+                         wrap_idx(P.lo[0] + xx, C.N[0]);
+        e += load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g) * x[id];
     }
     bb = block_sum<FIN_BS>(bb, red);
     rr = block_sum<FIN_BS>(rr, red);
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(FIN_BS) void k_cg_finish(ExxArgs a) {
         if (st.converged >= 0 && !(bb > 0.0)) st.converged = 1;
         else if (st.converged >= 0) st.converged = (st.rel_res <= a.rel_tol) ? 1 : 0;
         if (!(st.rel_res == st.rel_res)) st.converged = -1;
-        st.e_ij = a.dV * e;
+        st.e_ij = C.dV * e;
         st.s_abs = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM];
         st.q = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM + 1];
         a.stats[pid] = st;
@@ -418,7 +420,7 @@ __global__ __launch_bounds__(FIN_BS) void k_cg_finish(ExxArgs a) {
 }  // namespace
 
 bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h) {
-    if (h[0] != h[1] || h[0] != h[2]) return false;
+    if (h && (h[0] != h[1] || h[0] != h[2])) return false;
     for (int k = 0; k < n_pairs; ++k)
         if (pairs[k].n[0] > 64 || pairs[k].n[1] > 64) return false;
     return true;
@@ -442,10 +444,11 @@ size_t cg_zm_lds_bytes(int state_f32) { return (size_t)2 * LW * LH * (state_f32 
 // b - A x0 for a start guess x0 (FP64), one workgroup per pair.
 __global__ __launch_bounds__(FIN_BS) void k_start_residual(ExxArgs a) {
     const int pid = blockIdx.x;
+    const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const int n = nx * ny * nz, nxy = nx * ny;
-    const double ih2 = 1.0 / (a.h[0] * a.h[0]);
+    const double ih2 = 1.0 / (C.h[0] * C.h[0]);
     const double* b = a.b + (size_t)pid * a.stride;
     const double* x = a.v + (size_t)pid * a.stride;
     double* br = a.bres + (size_t)pid * a.stride;

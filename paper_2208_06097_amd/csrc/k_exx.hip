@@ -55,8 +55,9 @@ constexpr int GM_CHUNK = 4096;
 template <int LM>
 __global__ __launch_bounds__(GM_BS) void k_gather_moments(ExxArgs a) {
     __shared__ double red[GM_BS / 64 + 1];
-    const int pid = blockIdx.y;
-    const int chunk = blockIdx.x;
+    const int pid = blockIdx.x;
+    const int chunk = blockIdx.y;
+    const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const long n_int = (long)nx * ny * nz;
@@ -66,19 +67,19 @@ __global__ __launch_bounds__(GM_BS) void k_gather_moments(ExxArgs a) {
     for (int k = 0; k < SEA_NACC; ++k) acc[k] = 0.0;
     if (beg < n_int) {
         const long end = min(beg + GM_CHUNK, n_int);
-        const size_t oi = (size_t)P.i * a.Ng, oj = (size_t)P.j * a.Ng;
+        const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
         double* b = a.b + (size_t)pid * a.stride;
         for (long id = beg + threadIdx.x; id < end; id += GM_BS) {
             const int x = (int)(id % nx);
             const int y = (int)((id / nx) % ny);
             const int z = (int)(id / ((long)nx * ny));
-            const size_t g = ((size_t)wrap_idx(P.lo[2] + z, a.N[2]) * a.N[1] + wrap_idx(P.lo[1] + y, a.N[1])) * a.N[0]
-                             + wrap_idx(P.lo[0] + x, a.N[0]);
-            const double rho = load_phi(a.phi, a.phi_f32, oi + g) * load_phi(a.phi, a.phi_f32, oj + g);
+            const size_t g = ((size_t)wrap_idx(P.lo[2] + z, C.N[2]) * C.N[1] + wrap_idx(P.lo[1] + y, C.N[1])) * C.N[0]
+                             + wrap_idx(P.lo[0] + x, C.N[0]);
+            const double rho = load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g);
             b[id] = 4.0 * kPi * rho;
-            const double dx = (P.lo[0] + x) * a.h[0] - P.origin[0];
-            const double dy = (P.lo[1] + y) * a.h[1] - P.origin[1];
-            const double dz = (P.lo[2] + z) * a.h[2] - P.origin[2];
+            const double dx = (P.lo[0] + x) * C.h[0] - P.origin[0];
+            const double dy = (P.lo[1] + y) * C.h[1] - P.origin[1];
+            const double dz = (P.lo[2] + z) * C.h[2] - P.origin[2];
             double R[(LM + 1) * (LM + 1)];
             racah_solid<LM>(dx, dy, dz, R);
 #pragma unroll
@@ -102,12 +103,13 @@ __global__ void k_moments_final(ExxArgs a, double* Q_orth) {
     const int k = threadIdx.x;
     if (pid == 0 && k == 0 && a.queue_ctr) *a.queue_ctr = 0;
     if (k >= SEA_NACC) return;
+    const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
     const long n_int = (long)P.n[0] * P.n[1] * P.n[2];
     const int used = (int)((n_int + GM_CHUNK - 1) / GM_CHUNK);
     double s = 0.0;
     for (int c = 0; c < used; ++c) s += a.partial[((size_t)pid * a.n_chunks + c) * SEA_NACC + k];
-    s *= a.dV;
+    s *= C.dV;
     if (k < SEA_NMOM) {
         int l = 0;
         while ((l + 1) * (l + 1) <= k) ++l;
@@ -134,12 +136,13 @@ constexpr int GE_BS = 256;
 template <int LM>
 __global__ __launch_bounds__(GE_BS) void k_ghost_eval(ExxArgs a) {
     __shared__ double Q[SEA_NMOM];
-    const int pid = blockIdx.y;
+    const int pid = blockIdx.x;
     if (threadIdx.x < SEA_NMOM) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
     __syncthreads();
+    const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
     const int nm = a.nmax, FS = nm * nm;
-    const long t = (long)blockIdx.x * GE_BS + threadIdx.x;
+    const long t = (long)blockIdx.y * GE_BS + threadIdx.x;
     if (t >= 36L * FS) return;
     const int f = (int)(t / (6L * FS));
     const int L = (int)((t / FS) % 6) + 1;
@@ -152,9 +155,9 @@ __global__ __launch_bounds__(GE_BS) void k_ghost_eval(ExxArgs a) {
     pos[ax] = plus ? P.n[ax] - 1 + L : -L;
     pos[u] = au;
     pos[v] = av;
-    const double dx = (P.lo[0] + pos[0]) * a.h[0] - P.origin[0];
-    const double dy = (P.lo[1] + pos[1]) * a.h[1] - P.origin[1];
-    const double dz = (P.lo[2] + pos[2]) * a.h[2] - P.origin[2];
+    const double dx = (P.lo[0] + pos[0]) * C.h[0] - P.origin[0];
+    const double dy = (P.lo[1] + pos[1]) * C.h[1] - P.origin[1];
+    const double dz = (P.lo[2] + pos[2]) * C.h[2] - P.origin[2];
     a.gbuf[(size_t)pid * a.gstride + (size_t)(f * 6 + (L - 1)) * FS + (size_t)av * nm + au] =
         racah_me_potential<LM>(Q, a.lmax, dx, dy, dz);
 }
@@ -162,8 +165,9 @@ __global__ __launch_bounds__(GE_BS) void k_ghost_eval(ExxArgs a) {
 constexpr int BF_BS = 256;
 
 __global__ __launch_bounds__(BF_BS) void k_ghost_fold(ExxArgs a) {
-    const int pid = blockIdx.y;
-    const int z = blockIdx.x;
+    const int pid = blockIdx.x;
+    const int z = blockIdx.y;
+    const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     if (z >= nz) return;
@@ -171,7 +175,7 @@ __global__ __launch_bounds__(BF_BS) void k_ghost_fold(ExxArgs a) {
     const double* g = a.gbuf + (size_t)pid * a.gstride;
     const bool zface = (z < SEA_HALO) || (z >= nz - SEA_HALO);
     double* b = a.b + (size_t)pid * a.stride + (size_t)z * nx * ny;
-    const double ih2[3] = {1.0 / (a.h[0] * a.h[0]), 1.0 / (a.h[1] * a.h[1]), 1.0 / (a.h[2] * a.h[2])};
+    const double ih2[3] = {1.0 / (C.h[0] * C.h[0]), 1.0 / (C.h[1] * C.h[1]), 1.0 / (C.h[2] * C.h[2])};
     for (int t = threadIdx.x; t < nx * ny; t += BF_BS) {
         const int x = t % nx, y = t / nx;
         if (!(zface || x < SEA_HALO || x >= nx - SEA_HALO || y < SEA_HALO || y >= ny - SEA_HALO)) continue;
@@ -232,20 +236,21 @@ __device__ __forceinline__ double me_start_value(const double* Q, int lmax, doub
 template <int LM>
 __global__ __launch_bounds__(GM_BS) void k_me_guess(ExxArgs a) {
     __shared__ double Q[SEA_NACC];
-    const int pid = blockIdx.y;
+    const int pid = blockIdx.x;
     if (threadIdx.x < SEA_NACC) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
     __syncthreads();
+    const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const long n_int = (long)nx * ny * nz;
-    const long beg = (long)blockIdx.x * GM_CHUNK;
+    const long beg = (long)blockIdx.y * GM_CHUNK;
     if (beg >= n_int) return;
     const long end = min(beg + GM_CHUNK, n_int);
     double* x = a.v + (size_t)pid * a.stride;
     for (long id = beg + threadIdx.x; id < end; id += GM_BS) {
         const int xx = (int)(id % nx), yy = (int)((id / nx) % ny), zz = (int)(id / ((long)nx * ny));
-        x[id] = me_start_value<LM>(Q, a.lmax, (P.lo[0] + xx) * a.h[0] - P.origin[0],
-                                   (P.lo[1] + yy) * a.h[1] - P.origin[1], (P.lo[2] + zz) * a.h[2] - P.origin[2]);
+        x[id] = me_start_value<LM>(Q, a.lmax, (P.lo[0] + xx) * C.h[0] - P.origin[0],
+                                   (P.lo[1] + yy) * C.h[1] - P.origin[1], (P.lo[2] + zz) * C.h[2] - P.origin[2]);
     }
 }
 
@@ -275,18 +280,19 @@ template <int LM>
 __global__ __launch_bounds__(NNS_BS) void k_nn_sample(ExxArgs a, int D, float* __restrict__ out, double* s_out,
                                                       int mode) {
     __shared__ double Q[SEA_NACC];
-    const int pid = blockIdx.y;
+    const int pid = blockIdx.x;
     if (threadIdx.x < SEA_NACC) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
     __syncthreads();
+    const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const int D3 = D * D * D;
-    const int k = blockIdx.x * NNS_BS + threadIdx.x;
+    const int k = blockIdx.y * NNS_BS + threadIdx.x;
     const double s = Q[SEA_NMOM];
     if (k == 0 && s_out) s_out[pid] = s;
     if (k >= D3) return;
     const Lerp lx = lerp_at(k % D, nx, D), ly = lerp_at((k / D) % D, ny, D), lz = lerp_at(k / (D * D), nz, D);
-    const size_t oi = (size_t)P.i * a.Ng, oj = (size_t)P.j * a.Ng;
+    const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
     const double* v = a.v + (size_t)pid * a.stride;
     double acc = 0.0;
     for (int c = 0; c < 8; ++c) {
@@ -296,14 +302,14 @@ __global__ __launch_bounds__(NNS_BS) void k_nn_sample(ExxArgs a, int D, float* _
         if (wgt == 0.0 || cx >= nx || cy >= ny || cz >= nz) continue;
         double f;
         if (mode == 0) {
-            const size_t g = ((size_t)wrap_idx(P.lo[2] + cz, a.N[2]) * a.N[1] + wrap_idx(P.lo[1] + cy, a.N[1])) *
-                                 a.N[0] +
-                             wrap_idx(P.lo[0] + cx, a.N[0]);
-            f = load_phi(a.phi, a.phi_f32, oi + g) * load_phi(a.phi, a.phi_f32, oj + g);
+            const size_t g = ((size_t)wrap_idx(P.lo[2] + cz, C.N[2]) * C.N[1] + wrap_idx(P.lo[1] + cy, C.N[1])) *
+                                 C.N[0] +
+                             wrap_idx(P.lo[0] + cx, C.N[0]);
+            f = load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g);
         } else {
             f = v[((size_t)cz * ny + cy) * nx + cx] -
-                me_start_value<LM>(Q, a.lmax, (P.lo[0] + cx) * a.h[0] - P.origin[0],
-                                   (P.lo[1] + cy) * a.h[1] - P.origin[1], (P.lo[2] + cz) * a.h[2] - P.origin[2]);
+                me_start_value<LM>(Q, a.lmax, (P.lo[0] + cx) * C.h[0] - P.origin[0],
+                                   (P.lo[1] + cy) * C.h[1] - P.origin[1], (P.lo[2] + cz) * C.h[2] - P.origin[2]);
         }
         acc += wgt * f;
     }
@@ -312,11 +318,12 @@ __global__ __launch_bounds__(NNS_BS) void k_nn_sample(ExxArgs a, int D, float* _
 
 // x += s * upsample(y32) on the pair domain
 __global__ __launch_bounds__(GM_BS) void k_nn_apply(ExxArgs a, int D, const float* __restrict__ y32) {
-    const int pid = blockIdx.y;
+    const int pid = blockIdx.x;
+    const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const long n_int = (long)nx * ny * nz;
-    const long beg = (long)blockIdx.x * GM_CHUNK;
+    const long beg = (long)blockIdx.y * GM_CHUNK;
     if (beg >= n_int) return;
     const long end = min(beg + GM_CHUNK, n_int);
     const double s = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM];
@@ -378,12 +385,13 @@ __device__ __forceinline__ double apply_A_pt(const double* __restrict__ p, long 
 
 __global__ __launch_bounds__(CG_BS) void k_cg_f64(ExxArgs a) {
     __shared__ double red[CG_BS / 64 + 1];
-    const StencilW w = make_weights(a.h);
     double* r = a.slots + (size_t)blockIdx.x * 3 * a.slot_stride;
     double* p = r + a.stride;
     double* q = p + a.stride;
     const double tol2 = a.rel_tol * a.rel_tol;
     for (int pid = blockIdx.x; pid < a.n_pairs; pid += gridDim.x) {
+        const DevCell& C = a.cells[a.pair_cell[pid]];
+        const StencilW w = make_weights(C.h);
         const sea_pair P = a.pairs[pid];
         const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
         const long n = (long)nx * ny * nz;
@@ -455,13 +463,13 @@ __global__ __launch_bounds__(CG_BS) void k_cg_f64(ExxArgs a) {
             }
         }
         // e_ij = dV sum rho v with rho gathered again
-        const size_t oi = (size_t)P.i * a.Ng, oj = (size_t)P.j * a.Ng;
+        const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
         double e = 0.0;
         for (long id = threadIdx.x; id < n; id += CG_BS) {
             const int xx = (int)(id % nx), yy = (int)((id / nx) % ny), zz = (int)(id / nxy);
-            const size_t g = ((size_t)wrap_idx(P.lo[2] + zz, a.N[2]) * a.N[1] + wrap_idx(P.lo[1] + yy, a.N[1])) * a.N[0]
-                             + wrap_idx(P.lo[0] + xx, a.N[0]);
-            e += load_phi(a.phi, a.phi_f32, oi + g) * load_phi(a.phi, a.phi_f32, oj + g) * x[id];
+            const size_t g = ((size_t)wrap_idx(P.lo[2] + zz, C.N[2]) * C.N[1] + wrap_idx(P.lo[1] + yy, C.N[1])) * C.N[0]
+                             + wrap_idx(P.lo[0] + xx, C.N[0]);
+            e += load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g) * x[id];
         }
         e = block_sum<CG_BS>(e, red);
         if (threadIdx.x == 0) {
@@ -469,7 +477,7 @@ __global__ __launch_bounds__(CG_BS) void k_cg_f64(ExxArgs a) {
             st.iters = it;
             st.converged = conv;
             st.rel_res = rel;
-            st.e_ij = a.dV * e;
+            st.e_ij = C.dV * e;
             st.s_abs = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM];
             st.q = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM + 1];
             a.stats[pid] = st;
@@ -491,13 +499,16 @@ __device__ __forceinline__ bool axis_hits(int t0, int T, int lo, int n, int N) {
     return s < n || s + T > N;
 }
 
-__global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const int* __restrict__ off,
-                                                   const int2* __restrict__ ent, double* __restrict__ W) {
+__global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const int* __restrict__ off_all,
+                                                   const int2* __restrict__ ent) {
     __shared__ int list[SC_MAXE];
     __shared__ int cnt;
+    const DevCell& C = a.cells[cell];
+    const int* off = off_all + C.csr_base;
+    double* __restrict__ W = C.W;
     const int o = blockIdx.y;
-    const int tiles_x = (a.N[0] + SC_TX - 1) / SC_TX;
-    const int tiles_y = (a.N[1] + SC_TY - 1) / SC_TY;
+    const int tiles_x = (C.N[0] + SC_TX - 1) / SC_TX;
+    const int tiles_y = (C.N[1] + SC_TY - 1) / SC_TY;
     const int t = blockIdx.x;
     const int tx0 = (t % tiles_x) * SC_TX;
     const int ty0 = ((t / tiles_x) % tiles_y) * SC_TY;
@@ -516,8 +527,8 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const int* __restr
             int m = 0;
             for (int e = c0; e < c1; ++e) {
                 const sea_pair P = a.pairs[ent[e].x];
-                if (axis_hits(tx0, SC_TX, P.lo[0], P.n[0], a.N[0]) && axis_hits(ty0, SC_TY, P.lo[1], P.n[1], a.N[1]) &&
-                    axis_hits(tz0, SC_TZ, P.lo[2], P.n[2], a.N[2]))
+                if (axis_hits(tx0, SC_TX, P.lo[0], P.n[0], C.N[0]) && axis_hits(ty0, SC_TY, P.lo[1], P.n[1], C.N[1]) &&
+                    axis_hits(tz0, SC_TZ, P.lo[2], P.n[2], C.N[2]))
                     list[m++] = e;
             }
             cnt = m;
@@ -528,17 +539,17 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const int* __restr
         for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) {
             const int lid = threadIdx.x + k * SC_BS;
             const int gx = tx0 + lid % SC_TX, gy = ty0 + (lid / SC_TX) % SC_TY, gz = tz0 + lid / (SC_TX * SC_TY);
-            if (gx >= a.N[0] || gy >= a.N[1] || gz >= a.N[2]) continue;
-            const size_t g = ((size_t)gz * a.N[1] + gy) * a.N[0] + gx;
+            if (gx >= C.N[0] || gy >= C.N[1] || gz >= C.N[2]) continue;
+            const size_t g = ((size_t)gz * C.N[1] + gy) * C.N[0] + gx;
             double s = acc[k];
             for (int q = 0; q < m; ++q) {
                 const int2 en = ent[list[q]];
                 const sea_pair P = a.pairs[en.x];
                 const double* v = a.v + (size_t)en.x * a.stride;
-                const double ph = load_phi(a.phi, a.phi_f32, (size_t)en.y * a.Ng + g);
-                for (int lz = wrap_idx(gz - P.lo[2], a.N[2]); lz < P.n[2]; lz += a.N[2])
-                    for (int ly = wrap_idx(gy - P.lo[1], a.N[1]); ly < P.n[1]; ly += a.N[1])
-                        for (int lx = wrap_idx(gx - P.lo[0], a.N[0]); lx < P.n[0]; lx += a.N[0])
+                const double ph = load_phi(C.phi, C.phi_f32, (size_t)en.y * C.Ng + g);
+                for (int lz = wrap_idx(gz - P.lo[2], C.N[2]); lz < P.n[2]; lz += C.N[2])
+                    for (int ly = wrap_idx(gy - P.lo[1], C.N[1]); ly < P.n[1]; ly += C.N[1])
+                        for (int lx = wrap_idx(gx - P.lo[0], C.N[0]); lx < P.n[0]; lx += C.N[0])
                             s += v[((size_t)lz * P.n[1] + ly) * P.n[0] + lx] * ph;
             }
             acc[k] = s;
@@ -549,8 +560,8 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const int* __restr
     for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) {
         const int lid = threadIdx.x + k * SC_BS;
         const int gx = tx0 + lid % SC_TX, gy = ty0 + (lid / SC_TX) % SC_TY, gz = tz0 + lid / (SC_TX * SC_TY);
-        if (gx >= a.N[0] || gy >= a.N[1] || gz >= a.N[2]) continue;
-        W[(size_t)o * a.Ng + ((size_t)gz * a.N[1] + gy) * a.N[0] + gx] = acc[k];
+        if (gx >= C.N[0] || gy >= C.N[1] || gz >= C.N[2]) continue;
+        W[(size_t)o * C.Ng + ((size_t)gz * C.N[1] + gy) * C.N[0] + gx] = acc[k];
     }
 }
 
@@ -560,10 +571,11 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const int* __restr
 
 constexpr int ES_BS = 256;
 
-__global__ __launch_bounds__(ES_BS) void k_energy_sum(ExxArgs a, double* out, double* exx_dev, double* e_dev) {
+__global__ __launch_bounds__(ES_BS) void k_energy_sum(ExxArgs a, double* out, double* e_dev) {
     __shared__ double red[ES_BS / 64 + 1];
+    const DevCell& C = a.cells[blockIdx.x];
     double e = 0.0, nc = 0.0, nf = 0.0;
-    for (int k = threadIdx.x; k < a.n_pairs; k += ES_BS) {
+    for (int k = C.pair_begin + threadIdx.x; k < C.pair_end; k += ES_BS) {
         const DevStat st = a.stats[k];
         const sea_pair P = a.pairs[k];
         e -= (P.i == P.j ? 1.0 : 2.0) * st.e_ij;
@@ -575,10 +587,10 @@ __global__ __launch_bounds__(ES_BS) void k_energy_sum(ExxArgs a, double* out, do
     nc = block_sum<ES_BS>(nc, red);
     nf = block_sum<ES_BS>(nf, red);
     if (threadIdx.x == 0) {
-        out[0] = e;
-        out[1] = nc;
-        out[2] = nf;
-        if (exx_dev) *exx_dev = e;
+        out[3 * blockIdx.x] = e;
+        out[3 * blockIdx.x + 1] = nc;
+        out[3 * blockIdx.x + 2] = nf;
+        if (C.exx) *C.exx = e;
     }
 }
 
@@ -590,7 +602,7 @@ __global__ __launch_bounds__(ES_BS) void k_energy_sum(ExxArgs a, double* out, do
 int exx_n_chunks(long n_int_max) { return (int)((n_int_max + GM_CHUNK - 1) / GM_CHUNK); }
 
 hipError_t launch_gather_moments(const ExxArgs& a, hipStream_t s) {
-    dim3 grid(a.n_chunks, a.n_pairs);
+    dim3 grid(a.n_pairs, a.n_chunks);
     hipLaunchKernelGGL(k_gather_moments<SEA_LMAX>, grid, dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }
@@ -602,27 +614,27 @@ hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s)
 
 hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s) {
     const long nghost = 36L * a.nmax * a.nmax;
-    hipLaunchKernelGGL(k_ghost_eval<SEA_LMAX>, dim3((unsigned)((nghost + GE_BS - 1) / GE_BS), a.n_pairs), dim3(GE_BS),
+    hipLaunchKernelGGL(k_ghost_eval<SEA_LMAX>, dim3(a.n_pairs, (unsigned)((nghost + GE_BS - 1) / GE_BS)), dim3(GE_BS),
                        0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ghost_fold, dim3(nz_max, a.n_pairs), dim3(BF_BS), 0, s, a);
+    hipLaunchKernelGGL(k_ghost_fold, dim3(a.n_pairs, nz_max), dim3(BF_BS), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_me_guess<SEA_LMAX>, dim3(a.n_chunks, a.n_pairs), dim3(GM_BS), 0, s, a);
+    hipLaunchKernelGGL(k_me_guess<SEA_LMAX>, dim3(a.n_pairs, a.n_chunks), dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_nn_sample<SEA_LMAX>, dim3((D * D * D + NNS_BS - 1) / NNS_BS, a.n_pairs), dim3(NNS_BS), 0, s,
+    hipLaunchKernelGGL(k_nn_sample<SEA_LMAX>, dim3(a.n_pairs, (D * D * D + NNS_BS - 1) / NNS_BS), dim3(NNS_BS), 0, s,
                        a, D, out, s_out, mode);
     return hipGetLastError();
 }
 
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s) {
-    hipLaunchKernelGGL(k_nn_apply, dim3(a.n_chunks, a.n_pairs), dim3(GM_BS), 0, s, a, D, y32);
+    hipLaunchKernelGGL(k_nn_apply, dim3(a.n_pairs, a.n_chunks), dim3(GM_BS), 0, s, a, D, y32);
     return hipGetLastError();
 }
 
@@ -631,15 +643,16 @@ hipError_t launch_cg(const ExxArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const ExxArgs& a, const int* csr_off, const int2* csr_ent, double* W, hipStream_t s) {
-    const int tiles = ((a.N[0] + SC_TX - 1) / SC_TX) * ((a.N[1] + SC_TY - 1) / SC_TY) * ((a.N[2] + SC_TZ - 1) / SC_TZ);
-    dim3 grid(tiles, a.n_occ);
-    hipLaunchKernelGGL(k_scatter, grid, dim3(SC_BS), 0, s, a, csr_off, csr_ent, W);
+hipError_t launch_scatter(const ExxArgs& a, int cell, const int* N, int n_occ, const int* csr_off, const int2* csr_ent,
+                          hipStream_t s) {
+    const int tiles = ((N[0] + SC_TX - 1) / SC_TX) * ((N[1] + SC_TY - 1) / SC_TY) * ((N[2] + SC_TZ - 1) / SC_TZ);
+    dim3 grid(tiles, n_occ);
+    hipLaunchKernelGGL(k_scatter, grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
     return hipGetLastError();
 }
 
-hipError_t launch_energy_sum(const ExxArgs& a, double* out_scalars, double* exx_dev, double* e_dev, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(ES_BS), 0, s, a, out_scalars, exx_dev, e_dev);
+hipError_t launch_energy_sum(const ExxArgs& a, double* out_scalars, double* e_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_sum, dim3(a.n_cells), dim3(ES_BS), 0, s, a, out_scalars, e_dev);
     return hipGetLastError();
 }
 

@@ -404,9 +404,6 @@ hipError_t nn_forward(const float* params, const uint16_t* params16, const float
         NN_CHECK(conv_launch(ly.co, inA, cA, inB, cB, params16 ? nullptr : params + off,
                              params16 ? params16 + off : nullptr, params + off + nw, out, ly.co, nullptr, B, d,
                              ly.relu, 0, s));
-        if (k == kNnNumLayers - 1 && y_out)
-            NN_CHECK(hipMemcpyAsync(act + L.out[k], y_out, sizeof(float) * (size_t)B * d * d * d,
-                                    hipMemcpyDeviceToDevice, s));
     }
     return hipSuccess;
 }

@@ -83,24 +83,97 @@ sea_status check_pairs(sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair* pai
 
 }  // namespace
 
-ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair* pairs, bool with_v) {
+// Host view of the cells of one call: concatenated pairs, the cell of each
+// pair, per-cell CSR lists (pair, partner) in pair order, device cell table.
+struct CellSet {
+    std::vector<sea_cell> cells;
+    std::vector<sea_pair> pairs;
+    std::vector<int> pair_cell;
+    std::vector<int> csr_off;
+    std::vector<int2> csr_ent;
+    std::vector<DevCell> dev;
+    bool cubic = true;
+};
+
+static sea_status build_cellset(sea_ctx* ctx, int n_cells, const sea_cell* cells, bool action, CellSet& S) {
+    if (n_cells < 1 || !cells) return fail(ctx, SEA_E_ARG, "need n_cells >= 1 and a cell array");
+    S = CellSet{};
+    S.cells.assign(cells, cells + n_cells);
+    int csr_base = 0;
+    for (int c = 0; c < n_cells; ++c) {
+        const sea_cell& C = cells[c];
+        sea_status st = check_grid(ctx, &C.grid);
+        if (st != SEA_OK) return st;
+        if (C.n_occ < 1) return fail(ctx, SEA_E_ARG, "cell %d: n_occ < 1", c);
+        if (!C.phi_dev) return fail(ctx, SEA_E_ARG, "cell %d: phi_dev is NULL", c);
+        if (C.phi_dtype != SEA_F64 && C.phi_dtype != SEA_F32)
+            return fail(ctx, SEA_E_ARG, "cell %d: phi_dtype must be SEA_F64 or SEA_F32", c);
+        if (action && !C.W_dev) return fail(ctx, SEA_E_ARG, "cell %d: W_dev is NULL", c);
+        st = check_pairs(ctx, C.n_occ, C.n_pairs, C.pairs_host);
+        if (st != SEA_OK) return st;
+        DevCell D{};
+        D.phi = C.phi_dev;
+        D.phi_f32 = C.phi_dtype == SEA_F32;
+        D.n_occ = C.n_occ;
+        for (int k = 0; k < 3; ++k) {
+            D.N[k] = C.grid.n[k];
+            D.h[k] = C.grid.L[k] / C.grid.n[k];
+        }
+        if (D.h[0] != D.h[1] || D.h[0] != D.h[2]) S.cubic = false;
+        D.dV = D.h[0] * D.h[1] * D.h[2];
+        D.Ng = (size_t)D.N[0] * D.N[1] * D.N[2];
+        D.W = C.W_dev;
+        D.exx = C.exx_dev;
+        D.pair_begin = (int)S.pairs.size();
+        D.csr_base = csr_base;
+        for (int k = 0; k < C.n_pairs; ++k) {
+            S.pairs.push_back(C.pairs_host[k]);
+            S.pair_cell.push_back(c);
+        }
+        D.pair_end = (int)S.pairs.size();
+        if (action) {
+            std::vector<int> off(C.n_occ + 1, 0);
+            for (int k = 0; k < C.n_pairs; ++k) {
+                off[C.pairs_host[k].i + 1]++;
+                if (C.pairs_host[k].j != C.pairs_host[k].i) off[C.pairs_host[k].j + 1]++;
+            }
+            for (int o = 0; o < C.n_occ; ++o) off[o + 1] += off[o];
+            const int ent0 = (int)S.csr_ent.size();
+            S.csr_ent.resize(ent0 + off[C.n_occ]);
+            std::vector<int> fill(off.begin(), off.end() - 1);
+            for (int k = 0; k < C.n_pairs; ++k) {
+                const int gk = D.pair_begin + k;
+                S.csr_ent[ent0 + fill[C.pairs_host[k].i]++] = make_int2(gk, C.pairs_host[k].j);
+                if (C.pairs_host[k].j != C.pairs_host[k].i)
+                    S.csr_ent[ent0 + fill[C.pairs_host[k].j]++] = make_int2(gk, C.pairs_host[k].i);
+            }
+            for (int o = 0; o <= C.n_occ; ++o) S.csr_off.push_back(ent0 + off[o]);
+            csr_base += C.n_occ + 1;
+        }
+        S.dev.push_back(D);
+    }
+    if ((long long)S.pairs.size() > (1LL << 30)) return fail(ctx, SEA_E_ARG, "too many pairs");
+    return SEA_OK;
+}
+
+ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     ExxLayout L{};
+    const int n_pairs = (int)S.pairs.size();
+    const sea_pair* pairs = S.pairs.data();
     size_t stride = 1;
+    int nz_max = 1, nmax = 1;
     for (int k = 0; k < n_pairs; ++k) {
         size_t n = (size_t)pairs[k].n[0] * pairs[k].n[1] * pairs[k].n[2];
         if (n > stride) stride = n;
+        nz_max = pairs[k].n[2] > nz_max ? pairs[k].n[2] : nz_max;
+        for (int d = 0; d < 3; ++d) nmax = pairs[k].n[d] > nmax ? pairs[k].n[d] : nmax;
     }
     stride = (stride + 31) / 32 * 32;
     L.stride = stride;
-    int nz_max = 1;
-    for (int k = 0; k < n_pairs; ++k) nz_max = pairs[k].n[2] > nz_max ? pairs[k].n[2] : nz_max;
     L.slot_stride = (size_t)64 * 64 * (nz_max + 7);
     if (L.slot_stride < stride) L.slot_stride = stride;
     L.n_chunks = exx_n_chunks((long)stride);
     L.n_slots = n_pairs < ctx->n_cu * 4 ? (n_pairs > 0 ? n_pairs : 1) : ctx->n_cu * 4;
-    int nmax = 1;
-    for (int k = 0; k < n_pairs; ++k)
-        for (int d = 0; d < 3; ++d) nmax = pairs[k].n[d] > nmax ? pairs[k].n[d] : nmax;
     L.nmax = nmax;
     L.gstride = (size_t)36 * nmax * nmax;
     size_t off = 0;
@@ -110,18 +183,22 @@ ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair*
         return o;
     };
     const size_t np = n_pairs > 0 ? n_pairs : 1;
+    const size_t nc = S.cells.size();
     L.pairs = take(np * sizeof(sea_pair));
+    L.pair_cell = take(np * sizeof(int));
+    L.cells = take(nc * sizeof(DevCell));
     L.partial = take(np * L.n_chunks * SEA_NACC * sizeof(double));
     L.mom = take(np * SEA_NACC * sizeof(double));
     L.b = take(np * stride * sizeof(double));
     L.v = with_v ? take(np * stride * sizeof(double)) : 0;
-    L.bres = take(np * stride * sizeof(double));
+    L.bres = ctx->opts.start != SEA_START_ZERO ? take(np * stride * sizeof(double)) : 0;
     L.gbuf = take(np * L.gstride * sizeof(double));
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
-    L.csr_off = take((size_t)(n_occ + 1) * sizeof(int));
-    L.csr_ent = take(2 * np * sizeof(int2));
-    L.scal = take(8 * sizeof(double));
+    L.csr_off = take((S.csr_off.size() + 1) * sizeof(int));
+    L.csr_ent = take((S.csr_ent.size() + 1) * sizeof(int2));
+    L.scal = take((3 * nc + 8) * sizeof(double));
+    L.counter = take(256);
     if (ctx->opts.start == SEA_START_LEARNED) {
         const size_t d3 = (size_t)kNnGrid * kNnGrid * kNnGrid;
         L.nnx = take(np * d3 * sizeof(float));
@@ -280,88 +357,81 @@ sea_status sea_build_pairs(const sea_grid* grid, int n_occ, const double* c, dou
     return cnt > cap ? SEA_E_NOMEM : SEA_OK;
 }
 
+static sea_cell one_cell(const sea_grid* grid, int n_occ, const void* phi, sea_dtype dt, int n_pairs,
+                         const sea_pair* pairs, double* W, double* exx_dev) {
+    sea_cell c{};
+    if (grid) c.grid = *grid;
+    c.n_occ = n_occ;
+    c.phi_dtype = dt;
+    c.phi_dev = phi;
+    c.n_pairs = n_pairs;
+    c.pairs_host = pairs;
+    c.W_dev = W;
+    c.exx_dev = exx_dev;
+    return c;
+}
+
 sea_status sea_exx_workspace_bytes(sea_ctx* ctx, const sea_grid* grid, int n_occ, int n_pairs, const sea_pair* pairs,
                                    size_t* bytes) {
     if (!ctx || !bytes) return SEA_E_ARG;
-    sea_status st = check_grid(ctx, grid);
+    if (!grid) return fail(ctx, SEA_E_ARG, "grid is NULL");
+    sea_cell c = one_cell(grid, n_occ, (const void*)1, SEA_F64, n_pairs, pairs, (double*)1, nullptr);
+    CellSet S;
+    sea_status st = build_cellset(ctx, 1, &c, true, S);
     if (st != SEA_OK) return st;
-    if (n_occ < 1) return fail(ctx, SEA_E_ARG, "n_occ < 1");
-    st = check_pairs(ctx, n_occ, n_pairs, pairs);
-    if (st != SEA_OK) return st;
-    *bytes = exx_layout(ctx, n_occ, n_pairs, pairs, true).total;
+    *bytes = exx_layout(ctx, S, true).total;
     return SEA_OK;
 }
 
-static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev, sea_dtype phi_dtype,
-                          int n_pairs, const sea_pair* pairs, void* ws_dev, size_t ws_bytes, double* W_dev,
-                          double* exx_dev, double* exx_host, double* v_ext, double* Q_dev, double* e_dev,
-                          sea_pair_stat* stats_host, int nn_D = 0, float* nn_x = nullptr, float* nn_t = nullptr,
-                          double* nn_s = nullptr) {
-    if (!ctx) return SEA_E_ARG;
-    sea_status st = check_grid(ctx, grid);
+sea_status sea_exx_batched_workspace_bytes(sea_ctx* ctx, int n_cells, const sea_cell* cells, size_t* bytes) {
+    if (!ctx || !bytes) return SEA_E_ARG;
+    std::vector<sea_cell> cs(cells, cells + (n_cells > 0 && cells ? n_cells : 0));
+    for (auto& c : cs) {
+        if (!c.phi_dev) c.phi_dev = (const void*)1;  // sizing does not read buffers
+        if (!c.W_dev) c.W_dev = (double*)1;
+    }
+    CellSet S;
+    sea_status st = build_cellset(ctx, n_cells, cs.data(), true, S);
     if (st != SEA_OK) return st;
-    if (n_occ < 1) return fail(ctx, SEA_E_ARG, "n_occ < 1");
-    if (!phi_dev) return fail(ctx, SEA_E_ARG, "phi_dev is NULL");
-    if (phi_dtype != SEA_F64 && phi_dtype != SEA_F32) return fail(ctx, SEA_E_ARG, "phi_dtype must be SEA_F64 or SEA_F32");
-    st = check_pairs(ctx, n_occ, n_pairs, pairs);
-    if (st != SEA_OK) return st;
-    if (!ws_dev) return fail(ctx, SEA_E_ARG, "workspace is NULL");
-    if (ctx->opts.start == SEA_START_LEARNED && !ctx->nn_state)
-        return fail(ctx, SEA_E_ARG, "SEA_START_LEARNED needs a network (sea_nn_attach)");
-    const bool action = (W_dev != nullptr);
-    const ExxLayout Ly = exx_layout(ctx, n_occ, n_pairs, pairs, true);
-    if (ws_bytes < Ly.total)
-        return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, Ly.total);
-    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
-    char* base = (char*)ws_dev;
-    const size_t Ng = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
+    *bytes = exx_layout(ctx, S, true).total;
+    return SEA_OK;
+}
 
-    if (n_pairs == 0) {
-        if (action) SEA_HIP_CHECK(ctx, hipMemsetAsync(W_dev, 0, sizeof(double) * Ng * n_occ, s));
-        double zero = 0.0;
-        if (exx_dev) SEA_HIP_CHECK(ctx, hipMemcpyAsync(exx_dev, &zero, sizeof zero, hipMemcpyHostToDevice, s));
-        if (exx_host) *exx_host = 0.0;
-        if (exx_dev) SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
-        return SEA_OK;
-    }
+// Options of one enqueue of the exx kernel sequence.
+struct ExxFlags {
+    bool action = true;         // scatter W
+    double* Q_dev = nullptr;    // orthonormal moments out
+    double* e_dev = nullptr;    // per-pair energies out
+    int nn_D = 0;               // training samples out
+    float* nn_x = nullptr;
+    float* nn_t = nullptr;
+    double* nn_s = nullptr;
+    bool profile = false;
+};
 
-    // upload the pair table and (for the action) the per-orbital pair lists
-    std::vector<int> off(n_occ + 1, 0);
-    std::vector<int2> ent;
-    if (action) {
-        for (int k = 0; k < n_pairs; ++k) {
-            off[pairs[k].i + 1]++;
-            if (pairs[k].j != pairs[k].i) off[pairs[k].j + 1]++;
-        }
-        for (int o = 0; o < n_occ; ++o) off[o + 1] += off[o];
-        ent.resize(off[n_occ]);
-        std::vector<int> fill(off.begin(), off.end() - 1);
-        for (int k = 0; k < n_pairs; ++k) {
-            ent[fill[pairs[k].i]++] = make_int2(k, pairs[k].j);
-            if (pairs[k].j != pairs[k].i) ent[fill[pairs[k].j]++] = make_int2(k, pairs[k].i);
-        }
+static sea_status exx_upload(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, char* base, hipStream_t s) {
+    const size_t np = S.pairs.size();
+    if (np) {
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.pairs, S.pairs.data(), sizeof(sea_pair) * np, hipMemcpyHostToDevice, s));
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.pair_cell, S.pair_cell.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
     }
-    SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.pairs, pairs, sizeof(sea_pair) * n_pairs, hipMemcpyHostToDevice, s));
-    if (action) {
-        SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.csr_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
-        if (!ent.empty())
-            SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.csr_ent, ent.data(), sizeof(int2) * ent.size(), hipMemcpyHostToDevice, s));
-    }
+    SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.cells, S.dev.data(), sizeof(DevCell) * S.dev.size(), hipMemcpyHostToDevice, s));
+    if (!S.csr_off.empty())
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.csr_off, S.csr_off.data(), sizeof(int) * S.csr_off.size(), hipMemcpyHostToDevice, s));
+    if (!S.csr_ent.empty())
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.csr_ent, S.csr_ent.data(), sizeof(int2) * S.csr_ent.size(), hipMemcpyHostToDevice, s));
     // the host tables must outlive the copies
     SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+    return SEA_OK;
+}
 
+static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, char* base, double* v_ext) {
     ExxArgs a{};
     a.pairs = (const sea_pair*)(base + Ly.pairs);
-    a.n_pairs = n_pairs;
-    a.n_occ = n_occ;
-    for (int k = 0; k < 3; ++k) {
-        a.N[k] = grid->n[k];
-        a.h[k] = grid->L[k] / grid->n[k];
-    }
-    a.dV = a.h[0] * a.h[1] * a.h[2];
-    a.phi = phi_dev;
-    a.phi_f32 = (phi_dtype == SEA_F32);
-    a.Ng = Ng;
+    a.n_pairs = (int)S.pairs.size();
+    a.cells = (const DevCell*)(base + Ly.cells);
+    a.pair_cell = (const int*)(base + Ly.pair_cell);
+    a.n_cells = (int)S.cells.size();
     a.partial = (double*)(base + Ly.partial);
     a.n_chunks = Ly.n_chunks;
     a.mom = (double*)(base + Ly.mom);
@@ -375,121 +445,192 @@ static sea_status exx_run(sea_ctx* ctx, const sea_grid* grid, int n_occ, const v
     a.rel_tol = ctx->opts.rel_tol;
     a.max_iter = ctx->opts.max_iter;
     a.lmax = ctx->opts.lmax;
-    a.queue_ctr = (int*)(base + Ly.scal + 4 * sizeof(double));
+    a.queue_ctr = (int*)(base + Ly.counter);
     a.x_nonzero = ctx->opts.start != SEA_START_ZERO;
-    a.bres = (double*)(base + Ly.bres);
+    a.bres = Ly.bres ? (double*)(base + Ly.bres) : nullptr;
     a.gbuf = (double*)(base + Ly.gbuf);
     a.gstride = Ly.gstride;
     a.nmax = Ly.nmax;
-    // FP32 state: z-marching kernel (cubic grids, domains up to 64 x 64 in
-    // x-y).  FP64 state: the generic kernel (the FP64 z-queue does not fit
-    // the register file at this tile shape).
-    const bool zm = ctx->opts.stencil_dtype == SEA_F32 && cg_zm_fits(pairs, n_pairs, a.h) &&
+    return a;
+}
+
+// The whole kernel sequence of one call, on stream s (capturable).
+static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, char* base, const ExxArgs& a,
+                              const ExxFlags& f, hipStream_t s) {
+    const int n_pairs = a.n_pairs;
+    const bool prof = f.profile && ctx->opts.profile;
+    auto timer_on = [&](int st) {
+        if (prof && ctx->ev_ready) {
+            (void)hipEventRecord(ctx->ev[st][0], s);
+            ctx->ev_used[st] = true;
+        }
+    };
+    auto timer_off = [&](int st) {
+        if (prof && ctx->ev_ready) (void)hipEventRecord(ctx->ev[st][1], s);
+    };
+    for (int k = SEA_STAGE_GATHER; k <= SEA_STAGE_ENERGY; ++k) ctx->ev_used[k] = false;
+    const bool zm = ctx->opts.stencil_dtype == SEA_F32 && S.cubic && cg_zm_fits(S.pairs.data(), n_pairs, nullptr) &&
                     cg_zm_lds_bytes(1) <= ctx->max_lds;
     if (!zm && ctx->opts.stencil_dtype != SEA_F64)
-        return fail(ctx, SEA_E_ARG, "SEA_F32 state needs a cubic grid and pair domains with n[0], n[1] <= 64");
+        return fail(ctx, SEA_E_ARG, "SEA_F32 state needs cubic grids and pair domains with n[0], n[1] <= 64");
     int nz_max = 1;
-    for (int k = 0; k < n_pairs; ++k) nz_max = pairs[k].n[2] > nz_max ? pairs[k].n[2] : nz_max;
-
-    for (int k = SEA_STAGE_GATHER; k <= SEA_STAGE_ENERGY; ++k) ctx->ev_used[k] = false;
-    {
-        StageTimer t(ctx, SEA_STAGE_GATHER, s);
+    for (const auto& p : S.pairs) nz_max = p.n[2] > nz_max ? p.n[2] : nz_max;
+    if (n_pairs > 0) {
+        timer_on(SEA_STAGE_GATHER);
         SEA_HIP_CHECK(ctx, launch_gather_moments(a, s));
-        SEA_HIP_CHECK(ctx, launch_moments_final(a, Q_dev, s));
-    }
-    {
-        StageTimer t(ctx, SEA_STAGE_BOUNDARY, s);
+        SEA_HIP_CHECK(ctx, launch_moments_final(a, f.Q_dev, s));
+        timer_off(SEA_STAGE_GATHER);
+        timer_on(SEA_STAGE_BOUNDARY);
         SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
-    }
-    if (a.x_nonzero) {
-        StageTimer t(ctx, SEA_STAGE_GUESS, s);
-        SEA_HIP_CHECK(ctx, launch_me_guess(a, s));
-        if (ctx->opts.start == SEA_START_LEARNED) {
-            float* x32 = (float*)(base + Ly.nnx);
-            float* y32 = (float*)(base + Ly.nny);
-            float* act = (float*)(base + Ly.nnact);
-            const NnActLayout AL = nn_act_layout(kNnInferBatch, kNnGrid);
-            const NnState st = nn_state_ptrs(ctx->nn_state);
-            const size_t d3 = (size_t)kNnGrid * kNnGrid * kNnGrid;
-            SEA_HIP_CHECK(ctx, launch_nn_sample(a, kNnGrid, x32, nullptr, 0, s));
-            for (int p0 = 0; p0 < n_pairs; p0 += kNnInferBatch) {
-                const int nb = n_pairs - p0 < kNnInferBatch ? n_pairs - p0 : kNnInferBatch;
-                SEA_HIP_CHECK(ctx, nn_forward(st.p, ctx->opts.nn_weight_dtype == SEA_BF16 ? st.p16 : nullptr,
-                                              x32 + p0 * d3, act, AL, nb, kNnGrid, y32 + p0 * d3, s));
+        timer_off(SEA_STAGE_BOUNDARY);
+        if (a.x_nonzero) {
+            timer_on(SEA_STAGE_GUESS);
+            SEA_HIP_CHECK(ctx, launch_me_guess(a, s));
+            if (ctx->opts.start == SEA_START_LEARNED) {
+                float* x32 = (float*)(base + Ly.nnx);
+                float* y32 = (float*)(base + Ly.nny);
+                float* act = (float*)(base + Ly.nnact);
+                const NnActLayout AL = nn_act_layout(kNnInferBatch, kNnGrid);
+                const NnState st = nn_state_ptrs(ctx->nn_state);
+                const size_t d3 = (size_t)kNnGrid * kNnGrid * kNnGrid;
+                SEA_HIP_CHECK(ctx, launch_nn_sample(a, kNnGrid, x32, nullptr, 0, s));
+                for (int p0 = 0; p0 < n_pairs; p0 += kNnInferBatch) {
+                    const int nb = n_pairs - p0 < kNnInferBatch ? n_pairs - p0 : kNnInferBatch;
+                    SEA_HIP_CHECK(ctx, nn_forward(st.p, ctx->opts.nn_weight_dtype == SEA_BF16 ? st.p16 : nullptr,
+                                                  x32 + p0 * d3, act, AL, nb, kNnGrid, y32 + p0 * d3, s));
+                }
+                SEA_HIP_CHECK(ctx, launch_nn_apply(a, kNnGrid, y32, s));
             }
-            SEA_HIP_CHECK(ctx, launch_nn_apply(a, kNnGrid, y32, s));
+            SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
+            timer_off(SEA_STAGE_GUESS);
         }
-        SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
-    }
-    {
-        StageTimer t(ctx, SEA_STAGE_CG, s);
+        timer_on(SEA_STAGE_CG);
         if (zm) {
-            SEA_HIP_CHECK(ctx, launch_cg_zm(a, ctx->opts.stencil_dtype == SEA_F32, s));
+            SEA_HIP_CHECK(ctx, launch_cg_zm(a, 1, s));
             SEA_HIP_CHECK(ctx, launch_cg_finish(a, s));
-        } else
+        } else {
             SEA_HIP_CHECK(ctx, launch_cg(a, s));
-    }
-    if (action) {
-        StageTimer t(ctx, SEA_STAGE_SCATTER, s);
-        SEA_HIP_CHECK(ctx, launch_scatter(a, (const int*)(base + Ly.csr_off), (const int2*)(base + Ly.csr_ent), W_dev, s));
-    }
-    double* scal = (double*)(base + Ly.scal);
-    {
-        StageTimer t(ctx, SEA_STAGE_ENERGY, s);
-        SEA_HIP_CHECK(ctx, launch_energy_sum(a, scal, exx_dev, e_dev, s));
-    }
-    if (nn_x) {
-        SEA_HIP_CHECK(ctx, launch_nn_sample(a, nn_D, nn_x, nn_s, 0, s));
-        SEA_HIP_CHECK(ctx, launch_nn_sample(a, nn_D, nn_t, nullptr, 1, s));
-    }
-
-    sea_status ret = SEA_OK;
-    if (exx_host || stats_host) {
-        double hs[3];
-        SEA_HIP_CHECK(ctx, hipMemcpyAsync(hs, scal, sizeof hs, hipMemcpyDeviceToHost, s));
-        if (stats_host)
-            SEA_HIP_CHECK(ctx, hipMemcpyAsync(stats_host, a.stats, sizeof(DevStat) * n_pairs, hipMemcpyDeviceToHost, s));
-        SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
-        if (exx_host) *exx_host = hs[0];
-        if (hs[2] > 0.0 || !std::isfinite(hs[0]))
-            return fail(ctx, SEA_E_NONFINITE, "%d pair solves produced non-finite values", (int)hs[2]);
-        if (hs[1] > 0.0) {
-            fail(ctx, SEA_W_NOT_CONVERGED, "%d pairs did not reach rel_tol within max_iter", (int)hs[1]);
-            ret = SEA_W_NOT_CONVERGED;
         }
+        timer_off(SEA_STAGE_CG);
     }
-    return ret;
+    if (f.action) {
+        timer_on(SEA_STAGE_SCATTER);
+        for (size_t c = 0; c < S.cells.size(); ++c)
+            SEA_HIP_CHECK(ctx, launch_scatter(a, (int)c, S.dev[c].N, S.dev[c].n_occ, (const int*)(base + Ly.csr_off),
+                                              (const int2*)(base + Ly.csr_ent), s));
+        timer_off(SEA_STAGE_SCATTER);
+    }
+    timer_on(SEA_STAGE_ENERGY);
+    SEA_HIP_CHECK(ctx, launch_energy_sum(a, (double*)(base + Ly.scal), f.e_dev, s));
+    timer_off(SEA_STAGE_ENERGY);
+    if (f.nn_x && n_pairs > 0) {
+        SEA_HIP_CHECK(ctx, launch_nn_sample(a, f.nn_D, f.nn_x, f.nn_s, 0, s));
+        SEA_HIP_CHECK(ctx, launch_nn_sample(a, f.nn_D, f.nn_t, nullptr, 1, s));
+    }
+    return SEA_OK;
+}
+
+// Read E per cell and per-pair stats after the stream has drained; sets the
+// warning/error status from the per-cell counters.
+static sea_status exx_results(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, char* base, hipStream_t s,
+                              double* exx_host, sea_pair_stat* stats_host) {
+    const size_t nc = S.cells.size();
+    std::vector<double> hs(3 * nc);
+    SEA_HIP_CHECK(ctx, hipMemcpyAsync(hs.data(), base + Ly.scal, sizeof(double) * 3 * nc, hipMemcpyDeviceToHost, s));
+    if (stats_host && !S.pairs.empty())
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(stats_host, base + Ly.stats, sizeof(DevStat) * S.pairs.size(),
+                                          hipMemcpyDeviceToHost, s));
+    SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+    double nconv = 0.0, nbad = 0.0;
+    for (size_t c = 0; c < nc; ++c) {
+        if (exx_host) exx_host[c] = hs[3 * c];
+        nconv += hs[3 * c + 1];
+        nbad += hs[3 * c + 2];
+        if (!std::isfinite(hs[3 * c])) nbad += 1.0;
+    }
+    if (nbad > 0.0) return fail(ctx, SEA_E_NONFINITE, "%d pair solves produced non-finite values", (int)nbad);
+    if (nconv > 0.0) {
+        fail(ctx, SEA_W_NOT_CONVERGED, "%d pairs did not reach rel_tol within max_iter", (int)nconv);
+        return SEA_W_NOT_CONVERGED;
+    }
+    return SEA_OK;
+}
+
+static sea_status exx_run(sea_ctx* ctx, int n_cells, const sea_cell* cells, void* ws_dev, size_t ws_bytes,
+                          double* v_ext, const ExxFlags& f, double* exx_host, sea_pair_stat* stats_host) {
+    if (!ctx) return SEA_E_ARG;
+    if (!ws_dev) return fail(ctx, SEA_E_ARG, "workspace is NULL");
+    if (ctx->opts.start == SEA_START_LEARNED && !ctx->nn_state)
+        return fail(ctx, SEA_E_ARG, "SEA_START_LEARNED needs a network (sea_nn_attach)");
+    CellSet S;
+    sea_status st = build_cellset(ctx, n_cells, cells, f.action, S);
+    if (st != SEA_OK) return st;
+    const ExxLayout Ly = exx_layout(ctx, S, true);
+    if (ws_bytes < Ly.total) return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, Ly.total);
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    char* base = (char*)ws_dev;
+    st = exx_upload(ctx, S, Ly, base, s);
+    if (st != SEA_OK) return st;
+    const ExxArgs a = exx_args(ctx, S, Ly, base, v_ext);
+    st = exx_enqueue(ctx, S, Ly, base, a, f, s);
+    if (st != SEA_OK) return st;
+    if (exx_host || stats_host) return exx_results(ctx, S, Ly, base, s, exx_host, stats_host);
+    return SEA_OK;
 }
 
 sea_status sea_exx_action(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev, sea_dtype phi_dtype,
                           int n_pairs, const sea_pair* pairs_host, void* ws_dev, size_t ws_bytes, double* W_dev,
                           double* exx_dev, double* exx_host, sea_pair_stat* stats_host) {
     if (!ctx) return SEA_E_ARG;
+    if (!grid) return fail(ctx, SEA_E_ARG, "grid is NULL");
     if (!W_dev) return fail(ctx, SEA_E_ARG, "W_dev is NULL");
-    return exx_run(ctx, grid, n_occ, phi_dev, phi_dtype, n_pairs, pairs_host, ws_dev, ws_bytes, W_dev, exx_dev,
-                   exx_host, nullptr, nullptr, nullptr, stats_host);
+    const sea_cell c = one_cell(grid, n_occ, phi_dev, phi_dtype, n_pairs, pairs_host, W_dev, exx_dev);
+    ExxFlags f;
+    f.profile = true;
+    return exx_run(ctx, 1, &c, ws_dev, ws_bytes, nullptr, f, exx_host, stats_host);
+}
+
+sea_status sea_exx_action_batched(sea_ctx* ctx, int n_cells, const sea_cell* cells, void* ws_dev, size_t ws_bytes,
+                                  double* exx_host, sea_pair_stat* stats_host) {
+    if (!ctx) return SEA_E_ARG;
+    ExxFlags f;
+    f.profile = true;
+    return exx_run(ctx, n_cells, cells, ws_dev, ws_bytes, nullptr, f, exx_host, stats_host);
 }
 
 sea_status sea_exx_pair_solve(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev, sea_dtype phi_dtype,
                               int n_pairs, const sea_pair* pairs_host, void* ws_dev, size_t ws_bytes, double* v_dev,
                               double* Q_dev, double* e_dev, sea_pair_stat* stats_host) {
     if (!ctx) return SEA_E_ARG;
+    if (!grid) return fail(ctx, SEA_E_ARG, "grid is NULL");
     if (!v_dev) return fail(ctx, SEA_E_ARG, "v_dev is NULL");
-    return exx_run(ctx, grid, n_occ, phi_dev, phi_dtype, n_pairs, pairs_host, ws_dev, ws_bytes, nullptr, nullptr,
-                   nullptr, v_dev, Q_dev, e_dev, stats_host);
+    const sea_cell c = one_cell(grid, n_occ, phi_dev, phi_dtype, n_pairs, pairs_host, nullptr, nullptr);
+    ExxFlags f;
+    f.action = false;
+    f.Q_dev = Q_dev;
+    f.e_dev = e_dev;
+    f.profile = true;
+    return exx_run(ctx, 1, &c, ws_dev, ws_bytes, v_dev, f, nullptr, stats_host);
 }
 
 sea_status sea_exx_nn_samples(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev, sea_dtype phi_dtype,
                               int n_pairs, const sea_pair* pairs_host, void* ws_dev, size_t ws_bytes, int D,
                               float* x_dev, float* t_dev, double* s_dev, sea_pair_stat* stats_host) {
     if (!ctx) return SEA_E_ARG;
+    if (!grid) return fail(ctx, SEA_E_ARG, "grid is NULL");
     if (D < 2 || !x_dev || !t_dev) return fail(ctx, SEA_E_ARG, "need D >= 2 and x_dev, t_dev");
     for (int k = 0; k < n_pairs && pairs_host; ++k)
         for (int d = 0; d < 3; ++d)
             if (pairs_host[k].n[d] < 2) return fail(ctx, SEA_E_ARG, "pair %d: domain extent < 2", k);
-    // the solution lives in the workspace v array (pair_solve layout)
-    return exx_run(ctx, grid, n_occ, phi_dev, phi_dtype, n_pairs, pairs_host, ws_dev, ws_bytes, nullptr, nullptr,
-                   nullptr, nullptr, nullptr, nullptr, stats_host, D, x_dev, t_dev, s_dev);
+    const sea_cell c = one_cell(grid, n_occ, phi_dev, phi_dtype, n_pairs, pairs_host, nullptr, nullptr);
+    ExxFlags f;
+    f.action = false;
+    f.nn_D = D;
+    f.nn_x = x_dev;
+    f.nn_t = t_dev;
+    f.nn_s = s_dev;
+    f.profile = true;
+    return exx_run(ctx, 1, &c, ws_dev, ws_bytes, nullptr, f, nullptr, stats_host);
 }
 
 size_t sea_nn_param_count(void) { return nn_param_count(); }
@@ -756,6 +897,100 @@ sea_status sea_ace_energy(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, co
     SEA_HIP_CHECK(ctx, hipMemcpyAsync(exx_host, out, sizeof(double), hipMemcpyDeviceToHost, s));
     SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
     if (!std::isfinite(*exx_host)) return fail(ctx, SEA_E_NONFINITE, "non-finite ACE energy");
+    return SEA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// plans: tables uploaded once, kernel sequence captured into a HIP graph
+
+struct sea_plan {
+    sea_ctx* ctx = nullptr;
+    CellSet S;
+    ExxLayout Ly{};
+    char* base = nullptr;
+    ExxArgs a{};
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last = nullptr;
+};
+
+extern "C" {
+
+sea_status sea_exx_plan_create(sea_ctx* ctx, int n_cells, const sea_cell* cells, void* ws_dev, size_t ws_bytes,
+                               sea_plan** out) {
+    if (!ctx || !out) return SEA_E_ARG;
+    *out = nullptr;
+    if (!ws_dev) return fail(ctx, SEA_E_ARG, "workspace is NULL");
+    if (ctx->opts.start == SEA_START_LEARNED && !ctx->nn_state)
+        return fail(ctx, SEA_E_ARG, "SEA_START_LEARNED needs a network (sea_nn_attach)");
+    sea_plan* P = new (std::nothrow) sea_plan();
+    if (!P) return SEA_E_NOMEM;
+    P->ctx = ctx;
+    sea_status st = build_cellset(ctx, n_cells, cells, true, P->S);
+    if (st != SEA_OK) { delete P; return st; }
+    P->Ly = exx_layout(ctx, P->S, true);
+    if (ws_bytes < P->Ly.total) {
+        delete P;
+        return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, P->Ly.total);
+    }
+    P->base = (char*)ws_dev;
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    st = exx_upload(ctx, P->S, P->Ly, P->base, s);
+    if (st != SEA_OK) { delete P; return st; }
+    P->a = exx_args(ctx, P->S, P->Ly, P->base, nullptr);
+    if (hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete P;
+        return fail(ctx, SEA_E_HIP, "stream creation failed");
+    }
+    ExxFlags f;  // action, no profiling inside a graph
+    if (hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(P->cap);
+        delete P;
+        return fail(ctx, SEA_E_HIP, "graph capture could not start");
+    }
+    st = exx_enqueue(ctx, P->S, P->Ly, P->base, P->a, f, P->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(P->cap, &g);
+    if (st != SEA_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(P->cap);
+        delete P;
+        return st != SEA_OK ? st : fail(ctx, SEA_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    P->graph = g;
+    e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(P->cap);
+        delete P;
+        return fail(ctx, SEA_E_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    *out = P;
+    return SEA_OK;
+}
+
+sea_status sea_exx_plan_launch(sea_plan* P, void* hip_stream) {
+    if (!P) return SEA_E_ARG;
+    hipStream_t s = (hipStream_t)hip_stream;
+    SEA_HIP_CHECK(P->ctx, hipGraphLaunch(P->exec, s));
+    P->last = s;
+    return SEA_OK;
+}
+
+sea_status sea_exx_plan_results(sea_plan* P, double* exx_host, sea_pair_stat* stats_host) {
+    if (!P) return SEA_E_ARG;
+    return exx_results(P->ctx, P->S, P->Ly, P->base, P->last, exx_host, stats_host);
+}
+
+sea_status sea_exx_plan_destroy(sea_plan* P) {
+    if (!P) return SEA_OK;
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->cap) (void)hipStreamDestroy(P->cap);
+    delete P;
     return SEA_OK;
 }
 

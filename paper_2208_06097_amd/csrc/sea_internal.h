@@ -56,7 +56,8 @@ struct StageTimer {
 
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
-    size_t pairs, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, nnx, nny, nnact, total;
+    size_t pairs, pair_cell, cells, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, counter;
+    size_t nnx, nny, nnact, total;
     size_t gstride;
     int nmax;
     int n_chunks;
@@ -65,19 +66,30 @@ struct ExxLayout {
     size_t slot_stride;   // elements per CG slot array
 };
 
-ExxLayout exx_layout(const sea_ctx* ctx, int n_occ, int n_pairs, const sea_pair* pairs, bool with_v);
+
+// One cell of a (possibly batched) call: orbitals, grid, outputs, and the
+// contiguous range of the global pair list that belongs to it.
+struct DevCell {
+    const void* phi;      // n_occ x Ng, double or float
+    int phi_f32;
+    int n_occ;
+    int N[3];
+    double h[3];
+    double dV;
+    size_t Ng;
+    double* W;            // n_occ x Ng (nullptr: no scatter)
+    double* exx;          // device scalar (nullable)
+    int pair_begin, pair_end;
+    int csr_base;         // offset of this cell's orbital lists in the CSR arrays
+};
 
 // Arguments shared by the exx kernels (passed by value).
 struct ExxArgs {
     const sea_pair* pairs;
     int n_pairs;
-    int n_occ;
-    int N[3];
-    double h[3];
-    double dV;
-    const void* phi;      // n_occ x Ng, double or float
-    int phi_f32;
-    size_t Ng;
+    const DevCell* cells; // device cell table
+    const int* pair_cell; // cell index of every pair
+    int n_cells;
     double* partial;      // n_pairs x n_chunks x SEA_NACC
     int n_chunks;
     double* mom;          // n_pairs x SEA_NACC (Racah moments, dV applied)
@@ -114,10 +126,9 @@ bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h);
 size_t cg_zm_lds_bytes(int state_f32);
 hipError_t launch_cg_zm(const ExxArgs& a, int state_f32, hipStream_t s);
 hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s);
-hipError_t launch_scatter(const ExxArgs& a, const int* csr_off, const int2* csr_ent, double* W,
-                          hipStream_t s);
-hipError_t launch_energy_sum(const ExxArgs& a, double* out_scalars, double* exx_dev, double* e_dev,
-                             hipStream_t s);
+hipError_t launch_scatter(const ExxArgs& a, int cell, const int* N, int n_occ, const int* csr_off,
+                          const int2* csr_ent, hipStream_t s);
+hipError_t launch_energy_sum(const ExxArgs& a, double* out_scalars, double* e_dev, hipStream_t s);
 
 // Host evaluation of the solid-harmonic recurrence (orthonormal real form).
 void solid_harmonics_orthonormal_host(int lmax, double x, double y, double z, double* out);

@@ -28,7 +28,8 @@ EXPORTS = [
     "sea_ace_energy", "sea_solid_harmonics_host", "sea_stage_times",
     "sea_nn_param_count", "sea_nn_state_bytes", "sea_nn_set_params", "sea_nn_get_params",
     "sea_nn_workspace_bytes", "sea_nn_forward", "sea_nn_train_step", "sea_nn_attach",
-    "sea_exx_nn_samples",
+    "sea_exx_nn_samples", "sea_exx_batched_workspace_bytes", "sea_exx_action_batched",
+    "sea_exx_plan_create", "sea_exx_plan_launch", "sea_exx_plan_results", "sea_exx_plan_destroy",
 ]
 
 # the network's layers (name, c_in, c_out, relu), in parameter order
@@ -74,6 +75,12 @@ class SeaOpts(C.Structure):
                 ("max_iter", C.c_int32), ("stencil_dtype", C.c_int), ("ace_dtype", C.c_int),
                 ("start", C.c_int), ("refine_period", C.c_int32), ("profile", C.c_int32),
                 ("nn_weight_dtype", C.c_int), ("hip_stream", C.c_void_p)]
+
+
+class SeaCell(C.Structure):
+    _fields_ = [("grid", SeaGrid), ("n_occ", C.c_int32), ("phi_dtype", C.c_int), ("phi_dev", C.c_void_p),
+                ("n_pairs", C.c_int32), ("pairs_host", C.c_void_p), ("W_dev", C.c_void_p),
+                ("exx_dev", C.c_void_p)]
 
 
 STAGES = ["gather", "boundary", "guess", "cg", "scatter", "energy", "ace_m", "ace_chol", "ace_xi",
@@ -125,6 +132,12 @@ def load() -> C.CDLL:
     lib.sea_nn_train_step.argtypes = [vp, vp, i, i, vp, vp, C.c_float, i, vp, sz, vp, vp]
     lib.sea_nn_attach.argtypes = [vp, vp]
     lib.sea_exx_nn_samples.argtypes = [vp, P(SeaGrid), i, vp, i, i, vp, vp, sz, i, vp, vp, vp, vp]
+    lib.sea_exx_batched_workspace_bytes.argtypes = [vp, i, vp, P(sz)]
+    lib.sea_exx_action_batched.argtypes = [vp, i, vp, vp, sz, vp, vp]
+    lib.sea_exx_plan_create.argtypes = [vp, i, vp, vp, sz, P(vp)]
+    lib.sea_exx_plan_launch.argtypes = [vp, vp]
+    lib.sea_exx_plan_results.argtypes = [vp, vp, vp]
+    lib.sea_exx_plan_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -266,6 +279,58 @@ class Context:
         st = self._check(st)
         return W, (E.value if want_host else None), (stats[:len(p)] if want_host else None), st
 
+    def _cells(self, cells, need_W=True):
+        """Marshal [(phi, N, L, pairs, W or None, exx_dev or None), ...] into a
+        sea_cell array; allocates W where it is None.  Keeps the pair tables
+        alive in the returned tuple."""
+        torch = self._torch
+        arr = (SeaCell * len(cells))()
+        keep, Ws = [], []
+        for k, c in enumerate(cells):
+            phi, N, L, pairs = c[0], c[1], c[2], c[3]
+            W = c[4] if len(c) > 4 else None
+            exx_dev = c[5] if len(c) > 5 else None
+            assert phi.is_cuda and phi.is_contiguous()
+            p = np.ascontiguousarray(pairs, dtype=PAIR_DTYPE)
+            keep.append(p)
+            if W is None and need_W:
+                W = torch.empty(phi.shape, dtype=torch.float64, device=phi.device)
+            Ws.append(W)
+            arr[k].grid = _grid(N, L)
+            arr[k].n_occ = phi.shape[0]
+            arr[k].phi_dtype = self._phi_dtype(phi)
+            arr[k].phi_dev = phi.data_ptr()
+            arr[k].n_pairs = len(p)
+            arr[k].pairs_host = p.ctypes.data if len(p) else None
+            arr[k].W_dev = W.data_ptr() if W is not None else None
+            arr[k].exx_dev = exx_dev.data_ptr() if exx_dev is not None else None
+        return arr, Ws, keep
+
+    def exx_batched_workspace_bytes(self, cells) -> int:
+        arr, _, keep = self._cells(cells, need_W=False)
+        b = C.c_size_t(0)
+        self._check(self.lib.sea_exx_batched_workspace_bytes(self.h, len(cells), arr, C.byref(b)))
+        return b.value
+
+    def exx_action_batched(self, cells, ws=None, want_host=True):
+        """All pairs of all cells in one launch sequence.
+        Returns (list of W, E per cell or None, stats of all pairs or None, status)."""
+        arr, Ws, keep = self._cells(cells)
+        if ws is None:
+            ws = self.workspace(self.exx_batched_workspace_bytes(cells))
+        n_all = sum(len(k) for k in keep)
+        E = np.zeros(len(cells))
+        stats = np.zeros(max(n_all, 1), dtype=STAT_DTYPE)
+        st = self.lib.sea_exx_action_batched(self.h, len(cells), arr, ws.data_ptr(), ws.numel(),
+                                             E.ctypes.data if want_host else None,
+                                             stats.ctypes.data if want_host else None)
+        st = self._check(st)
+        return Ws, (E if want_host else None), (stats[:n_all] if want_host else None), st
+
+    def exx_plan(self, cells, ws=None):
+        """A replayable HIP-graph plan of the batched action (see Plan)."""
+        return Plan(self, cells, ws)
+
     def pair_solve(self, phi, N, L, pairs, ws=None, want_Q=True):
         """Per-pair potentials: returns (v (n_pairs x stride), Q or None, e, stats, status)."""
         torch = self._torch
@@ -405,3 +470,46 @@ class Context:
                                                 len(p), p.ctypes.data, ws.data_ptr(), ws.numel(), D,
                                                 x.data_ptr(), t.data_ptr(), s.data_ptr(), stats.ctypes.data))
         return x, t, s, stats[:len(p)]
+
+
+class Plan:
+    """Tables uploaded once, the batched action captured into a HIP graph.
+
+    ``launch(stream)`` replays it (default: torch's current stream);
+    ``results()`` waits and returns (E per cell, stats of all pairs, status).
+    ``W`` holds the per-cell output tensors."""
+
+    def __init__(self, ctx: Context, cells, ws=None):
+        self.ctx = ctx
+        arr, self.W, self._keep = ctx._cells(cells)
+        self._cells = arr
+        self._n_pairs = sum(len(k) for k in self._keep)
+        self.ws = ws if ws is not None else ctx.workspace(ctx.exx_batched_workspace_bytes(cells))
+        h = C.c_void_p()
+        ctx._check(ctx.lib.sea_exx_plan_create(ctx.h, len(cells), arr, self.ws.data_ptr(), self.ws.numel(),
+                                               C.byref(h)))
+        self.h = h
+        self.n_cells = len(cells)
+
+    def launch(self, stream=None):
+        if stream is None:
+            stream = self.ctx._torch.cuda.current_stream()
+        self.ctx._check(self.ctx.lib.sea_exx_plan_launch(self.h, C.c_void_p(stream.cuda_stream)))
+
+    def results(self):
+        E = np.zeros(self.n_cells)
+        stats = np.zeros(max(self._n_pairs, 1), dtype=STAT_DTYPE)
+        st = self.ctx.lib.sea_exx_plan_results(self.h, E.ctypes.data, stats.ctypes.data)
+        st = self.ctx._check(st)
+        return E, stats[:self._n_pairs], st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.sea_exx_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
