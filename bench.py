@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--other-forms", action="store_true", help="also time one V_xx action of every other form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-pairs", type=int, default=2048, help="pairs sampled by the CG kernel autotuner")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 2 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -146,6 +147,10 @@ def main():
     W = torch.empty_like(phi)
     exx_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     log(f"form {form}; pairs: {n_pairs}; workspace {ws.numel() / 2**30:.2f} GiB")
+    tune = None
+    if FORMS[form]["stencil"] == "f32":
+        tune = ctx.autotune([(phi, cell.N, cell.L, pairs)], sample_pairs=args.tune_pairs, iters=20, ws=ws)
+        log(f"autotune: {tune['variant']}  " + "  ".join(f"{k} {v:.1f} ms" for k, v in tune["ms"].items()))
 
     def step(host=False):
         r = ctx.exx_action(phi, cell.N, cell.L, pairs, ws=ws, W=W, exx_dev=exx_dev, want_host=host)
@@ -171,7 +176,7 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = 1000 * dt / args.steps
     stages = {k: v / args.steps for k, v in stage_acc.items()}
-    vxx_ms = sum(stages[k] for k in ("gather", "boundary", "guess", "cg", "scatter", "energy"))
+    vxx_ms = sum(stages[k] for k in ("gather", "boundary", "guess", "cg", "finish", "scatter", "energy"))
     wbytes = 4.0 if FORMS[form]["stencil"] == "f32" else 8.0
     cg_bytes = float(np.sum(stats["iters"].astype(np.float64) * 6.0
                             * np.prod(pairs["n"].astype(np.float64), axis=1) * wbytes))
@@ -187,6 +192,8 @@ def main():
                 continue
             c2 = make_ctx(fname)
             ws2 = c2.workspace(c2.exx_workspace_bytes(cell.N, cell.L, cell.n_occ, pairs))
+            if FORMS[fname]["stencil"] == "f32":
+                c2.autotune([(phi, cell.N, cell.L, pairs)], sample_pairs=args.tune_pairs, iters=20, ws=ws2)
             r2 = c2.exx_action(phi, cell.N, cell.L, pairs, ws=ws2, W=W, exx_dev=exx_dev, want_host=True)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -219,6 +226,8 @@ def main():
                                "63^3 pair domains, CG to a relative true FP64 residual; ACE (FP64) with K applied "
                                "to 256 trial vectors",
                    "form": form, "rel_tol": args.tol, "n_pairs": n_pairs,
+                   "cg_variant": tune["variant"] if tune else "k_cg_f64 (generic FP64)",
+                   "autotune_ms": tune["ms"] if tune else None,
                    "cg_iters_total": int(stats["iters"].sum())},
         "forms": forms,
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -75,7 +75,9 @@ typedef struct {
     sea_dtype stencil_dtype;/* CG state precision: SEA_F64 or SEA_F32          */
     sea_dtype ace_dtype;    /* xi / K psi GEMM inputs: F64, F32 or BF16        */
     sea_start start;        /* CG initial guess                                */
-    int32_t refine_period;  /* F32 state: FP64 true-residual refresh period    */
+    int32_t cg_variant;     /* F32 state: z-march kernel variant; -1 = the     */
+                            /* context's autotuned choice, else the default;  */
+                            /* 0..sea_cg_variant_count()-1 = that variant     */
     int32_t profile;        /* non-zero: time each stage with HIP events       */
     sea_dtype nn_weight_dtype; /* learned start: network weights F32 or BF16   */
     void *hip_stream;       /* hipStream_t; NULL = default stream              */
@@ -86,14 +88,15 @@ typedef enum {
     SEA_STAGE_GATHER = 0,   /* pair density, b = 4 pi rho, multipole moments   */
     SEA_STAGE_BOUNDARY = 1, /* multipole boundary values folded into b         */
     SEA_STAGE_GUESS = 2,    /* initial guess (multipole or learned start)      */
-    SEA_STAGE_CG = 3,       /* CG solves (the hot loop)                        */
+    SEA_STAGE_CG = 3,       /* CG solves (the hot loop; one kernel launch)     */
     SEA_STAGE_SCATTER = 4,  /* W accumulation                                  */
     SEA_STAGE_ENERGY = 5,   /* E_xx reduction                                  */
     SEA_STAGE_ACE_M = 6,    /* M = dV Phi^T W and symmetrization               */
     SEA_STAGE_ACE_CHOL = 7, /* Cholesky and L^{-1}                             */
     SEA_STAGE_ACE_XI = 8,   /* xi = W L^{-T}                                   */
     SEA_STAGE_ACE_APPLY = 9,/* K psi                                           */
-    SEA_STAGE_COUNT = 10
+    SEA_STAGE_FINISH = 10,  /* FP32 state: true FP64 residual and e_ij per pair */
+    SEA_STAGE_COUNT = 11
 } sea_stage;
 
 /* Per-pair diagnostics (Eq. 8 and Eq. 17 quantities on the pair domain). */
@@ -112,8 +115,8 @@ typedef struct sea_ctx sea_ctx;
 const char *sea_version(void);
 
 /* Fill *o with the defaults: half order 6, lmax 6, rel_tol 1e-8,
- * max_iter 10000, F64 stencil and ACE, zero start, refine_period 50,
- * profiling off. */
+ * max_iter 10000, F64 stencil and ACE, zero start, cg_variant -1,
+ * BF16 network weights, profiling off. */
 void sea_opts_default(sea_opts *o);
 
 /* Create a context on the current HIP device.  The context owns only host
@@ -185,6 +188,25 @@ sea_status sea_exx_batched_workspace_bytes(sea_ctx *ctx, int n_cells, const sea_
  * the call synchronize.  Results are bit-identical to per-cell calls. */
 sea_status sea_exx_action_batched(sea_ctx *ctx, int n_cells, const sea_cell *cells, void *ws_dev,
                                   size_t ws_bytes, double *exx_host, sea_pair_stat *stats_host);
+
+/* Kernel variants of the FP32-state CG solve (workgroup size, prefetch of
+ * the output plane, planes in flight).  Names are static strings; NULL for an
+ * index out of range. */
+int sea_cg_variant_count(void);
+const char *sea_cg_variant_name(int variant);
+
+/* Autotuner for the FP32-state CG solve (the batching workload's tile and
+ * schedule choice): runs the CG of a strided sample of `sample_pairs` pairs
+ * of these cells (zero start, exactly `iters` iterations each, so every
+ * variant does the same work) once per variant, times each launch with HIP
+ * events, and keeps the fastest as the context's choice (used while
+ * opts.cg_variant is -1).  ms_host (sea_cg_variant_count() floats, nullable)
+ * receives the times and *best the chosen index.  The workspace must hold
+ * sea_exx_batched_workspace_bytes of the same cells; W_dev may be NULL.
+ * Synchronizes.  SEA_E_ARG for cells that the FP32 state cannot run (grids
+ * not cubic, domains wider than 64 points in x or y). */
+sea_status sea_exx_autotune(sea_ctx *ctx, int n_cells, const sea_cell *cells, void *ws_dev, size_t ws_bytes,
+                            int sample_pairs, int iters, float *ms_host, int *best);
 
 /* A plan fixes the cells, pair tables and workspace once (tables are
  * uploaded at creation) and records the whole kernel sequence of the batched

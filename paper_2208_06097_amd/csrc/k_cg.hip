@@ -105,16 +105,20 @@ __device__ __forceinline__ double load_phi(const void* phi, int f32, size_t off)
 struct Empty {};
 
 // z-march of A applied to a field f.  The input of plane z is produced in
-// two steps so its global loads overlap a whole plane of work: fetch(c, z)
-// issues the loads at the start of step z-7, make(c, z, F) turns them into
-// f at the end of that step.  pre(c, z) prefetches per-column data for the
-// output plane z before the barrier; out(c, z, A f, f, PV) consumes it.
-// Column c of this thread is (x, y) = (tx, ty + TY c).  The slot arrays
-// hold 7 zero planes beyond nz, so every fetch is unconditional.
-template <typename T, typename TC, int NT, int COLS, typename F, typename PV, typename FetchF, typename MakeF,
-          typename PreF, typename OutF>
+// two steps so its global loads overlap plane work: fetch(c, z) issues the
+// loads DEPTH steps before plane z enters the register queue, make(c, z, F)
+// turns them into f when it does (DEPTH = 1: loads issued at the start of
+// the step that consumes them; DEPTH = 2: one step earlier, twice the bytes
+// in flight for more registers).  pre(c, z) prefetches per-column data for
+// the output plane z before the barrier; out(c, z, A f, f, PV) consumes it.
+// Column c of this thread is (x, y) = (tx, ty + TY c).  Plane nz of every
+// slot array is zero and every fetch beyond the domain reads it (it stays in
+// cache), so the march never moves padding through HBM.
+template <typename T, typename TC, int NT, int COLS, int DEPTH, typename F, typename PV, typename FetchF,
+          typename MakeF, typename PreF, typename OutF>
 __device__ __forceinline__ void zmarch(int nz, T* lds, const SW<TC>& w, FetchF&& fetch, MakeF&& make, PreF&& pre,
                                        OutF&& out) {
+    static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
     constexpr int TY = NT / 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     T q[COLS][13];
@@ -123,12 +127,25 @@ __device__ __forceinline__ void zmarch(int nz, T* lds, const SW<TC>& w, FetchF&&
 #pragma unroll
         for (int k = 0; k < 6; ++k) q[c][k] = T(0);
 #pragma unroll
-        for (int s = 0; s < 7; ++s) q[c][6 + s] = make(c, s, fetch(c, s));
+        for (int s = 0; s < 7; ++s) q[c][6 + s] = make(c, s, fetch(c, min(s, nz)));
+    }
+    F nb[COLS];
+    if constexpr (DEPTH == 2) {
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) nb[c] = fetch(c, min(7, nz));
     }
     for (int z = 0; z < nz; ++z) {
         F nxt[COLS];
+        if constexpr (DEPTH == 1) {
 #pragma unroll
-        for (int c = 0; c < COLS; ++c) nxt[c] = fetch(c, z + 7);
+            for (int c = 0; c < COLS; ++c) nxt[c] = fetch(c, min(z + 7, nz));
+        } else {
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                nxt[c] = nb[c];
+                nb[c] = fetch(c, min(z + 8, nz));
+            }
+        }
         PV pv[COLS];
 #pragma unroll
         for (int c = 0; c < COLS; ++c) pv[c] = pre(c, z);
@@ -209,7 +226,7 @@ struct PVsel {
     using type = F2<T>;
 };
 
-template <typename T, int NT, int COLS, bool PREFETCH>
+template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH>
 __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __restrict__ cc, T* __restrict__ rr,
                            T* __restrict__ pp, double* __restrict__ r64) {
     const DevCell& C = a.cells[a.pair_cell[pid]];
@@ -217,12 +234,12 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     const SW<T> w = make_sw<T>(ih2);
     const SW<double> wd = make_sw<double>(ih2);
     // Slot arrays (cc, rr, pp, r64) use a padded 64 x 64 plane: element
-    // (x,y,z) at (z*64 + y)*64 + x, planes 0..nz+6; cells outside the domain
-    // stay zero in rr, pp and r64.
+    // (x,y,z) at (z*64 + y)*64 + x, planes 0..nz; cells outside the domain
+    // (including all of plane nz) stay zero in cc, rr, pp and r64.
     constexpr int TY = NT / 64;
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    const int npad = PL * (nz + 7);
+    const int npad = PL * (nz + 1);
     const double* __restrict__ b = a.b + (size_t)pid * a.stride;
     const double* __restrict__ b0 = a.x_nonzero ? a.bres + (size_t)pid * a.stride : b;
     double* __restrict__ x = a.v + (size_t)pid * a.stride;
@@ -273,7 +290,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     while (conv == 0 && rho > 0.0) {
         // sweep A: p = r + beta p, <p, A p>
         double dacc = 0.0;
-        zmarch<T, T, NT, COLS, F2<T>, Empty>(
+        zmarch<T, T, NT, COLS, DEPTH, F2<T>, Empty>(
             nz, lds, w,
             [&](int c, int z) -> F2<T> {
                 const int id = z * PL + col0 + c * TY * 64;
@@ -281,7 +298,9 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
             },
             [&](int c, int z, F2<T> f) -> T {
                 const T pn = f.a + beta * f.b;
-                pp[z * PL + col0 + c * TY * 64] = pn;
+                // beyond the domain pn = 0 (r and p read the zero plane):
+                // the store lands on plane nz, which stays zero
+                pp[min(z, nz) * PL + col0 + c * TY * 64] = pn;
                 return pn;
             },
             [&](int, int) { return Empty{}; },
@@ -294,7 +313,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
         auto fetch_p = [&](int c, int z) -> T { return pp[z * PL + col0 + c * TY * 64]; };
         auto make_p = [&](int, int, T v) -> T { return v; };
         if constexpr (PREFETCH) {
-            zmarch<T, T, NT, COLS, T, PV>(
+            zmarch<T, T, NT, COLS, DEPTH, T, PV>(
                 nz, lds, w, fetch_p, make_p,
                 [&](int c, int z) -> PV {
                     const int id = z * PL + col0 + c * TY * 64;
@@ -308,7 +327,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
                     racc += (double)rn * (double)rn;
                 });
         } else {
-            zmarch<T, T, NT, COLS, T, Empty>(
+            zmarch<T, T, NT, COLS, DEPTH, T, Empty>(
                 nz, lds, w, fetch_p, make_p, [&](int, int) { return Empty{}; },
                 [&](int c, int z, T s, T ctr, Empty) {
                     const int id = z * PL + col0 + c * TY * 64;
@@ -328,7 +347,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
         }
         // reliable update in FP64: r64 -= A c, x += c
         double uacc = 0.0;
-        zmarch<T, double, NT, COLS, T, double>(
+        zmarch<T, double, NT, COLS, 1, T, double>(
             nz, lds, wd, [&](int c, int z) -> T { return cc[z * PL + col0 + c * TY * 64]; },
             [&](int, int, T v) -> T { return v; },
             [&](int c, int z) -> double { return r64[z * PL + col0 + c * TY * 64]; },
@@ -355,7 +374,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     }
 }
 
-template <typename T, int NT, int COLS, bool PREFETCH>
+template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH>
 __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
     extern __shared__ unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
@@ -373,7 +392,7 @@ __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
         __syncthreads();
         const int pid = pid_sh;
         if (pid >= a.n_pairs) break;
-        solve_pair<T, NT, COLS, PREFETCH>(a, pid, lds, red, cc, rr, pp, r64);
+        solve_pair<T, NT, COLS, PREFETCH, DEPTH>(a, pid, lds, red, cc, rr, pp, r64);
     }
 }
 
@@ -428,19 +447,6 @@ bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h) {
 
 size_t cg_zm_lds_bytes(int state_f32) { return (size_t)2 * LW * LH * (state_f32 ? sizeof(float) : sizeof(double)); }
 
-#ifndef SEA_CG_F32_NT
-#define SEA_CG_F32_NT 1024
-#endif
-#ifndef SEA_CG_F64_NT
-#define SEA_CG_F64_NT 1024
-#endif
-#ifndef SEA_CG_F32_PF
-#define SEA_CG_F32_PF true
-#endif
-#ifndef SEA_CG_F64_PF
-#define SEA_CG_F64_PF false
-#endif
-
 // b - A x0 for a start guess x0 (FP64), one workgroup per pair.
 __global__ __launch_bounds__(FIN_BS) void k_start_residual(ExxArgs a) {
     const int pid = blockIdx.x;
@@ -468,17 +474,38 @@ hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_cg_zm(const ExxArgs& a, int state_f32, hipStream_t s) {
-    if (state_f32) {
-        constexpr int NT = SEA_CG_F32_NT;
-        auto k = k_cg_zm<float, NT, 64 / (NT / 64), SEA_CG_F32_PF>;
-        hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cg_zm_lds_bytes(1));
-        hipLaunchKernelGGL(k, dim3(a.n_slots), dim3(NT), cg_zm_lds_bytes(1), s, a);
-    } else {
-        constexpr int NT = SEA_CG_F64_NT;
-        auto k = k_cg_zm<double, NT, 64 / (NT / 64), SEA_CG_F64_PF>;
-        hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cg_zm_lds_bytes(0));
-        hipLaunchKernelGGL(k, dim3(a.n_slots), dim3(NT), cg_zm_lds_bytes(0), s, a);
-    }
+// Compiled z-march variants (FP32 state); the autotuner picks one per
+// workload.  nt: workgroup size (rows of the 64 x 64 plane per thread =
+// 4096 / nt; smaller workgroups need more queue registers than the 128 a
+// lane may hold at this size and spill in the plane loop); pf: prefetch c
+// and r of the output plane before the barrier; d: planes of p in flight
+// ahead of the register queue.
+namespace {
+using CgKernel = void (*)(ExxArgs);
+struct CgVariant {
+    const char* name;
+    CgKernel fn;
+    int nt;
+};
+const CgVariant kCgVariants[] = {
+    {"nt1024-pf-d1", k_cg_zm<float, 1024, 4, true, 1>, 1024},
+    {"nt1024-pf-d2", k_cg_zm<float, 1024, 4, true, 2>, 1024},
+    {"nt1024-d1", k_cg_zm<float, 1024, 4, false, 1>, 1024},
+    {"nt1024-d2", k_cg_zm<float, 1024, 4, false, 2>, 1024},
+};
+constexpr int kNumCgVariants = sizeof(kCgVariants) / sizeof(kCgVariants[0]);
+}  // namespace
+
+int cg_variant_count() { return kNumCgVariants; }
+
+const char* cg_variant_name(int v) { return (v >= 0 && v < kNumCgVariants) ? kCgVariants[v].name : nullptr; }
+
+hipError_t launch_cg_zm(const ExxArgs& a, int variant, hipStream_t s) {
+    if (variant < 0 || variant >= kNumCgVariants) return hipErrorInvalidValue;
+    const CgVariant& v = kCgVariants[variant];
+    const int lds = (int)cg_zm_lds_bytes(1);
+    hipError_t e = hipFuncSetAttribute((const void*)v.fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(v.fn, dim3(a.n_slots), dim3(v.nt), lds, s, a);
     return hipGetLastError();
 }

@@ -51,7 +51,8 @@ sea_status check_opts(sea_ctx* ctx, const sea_opts* o) {
         return fail(ctx, SEA_E_ARG, "bad start");
     if (o->nn_weight_dtype != SEA_F32 && o->nn_weight_dtype != SEA_BF16)
         return fail(ctx, SEA_E_ARG, "nn_weight_dtype must be SEA_F32 or SEA_BF16");
-    if (o->refine_period < 1) return fail(ctx, SEA_E_ARG, "refine_period must be >= 1");
+    if (o->cg_variant < -1 || o->cg_variant >= cg_variant_count())
+        return fail(ctx, SEA_E_ARG, "cg_variant must be -1 or 0..%d", cg_variant_count() - 1);
     return SEA_OK;
 }
 
@@ -170,7 +171,7 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     }
     stride = (stride + 31) / 32 * 32;
     L.stride = stride;
-    L.slot_stride = (size_t)64 * 64 * (nz_max + 7);
+    L.slot_stride = (size_t)64 * 64 * (nz_max + 1);
     if (L.slot_stride < stride) L.slot_stride = stride;
     L.n_chunks = exx_n_chunks((long)stride);
     L.n_slots = n_pairs < ctx->n_cu * 4 ? (n_pairs > 0 ? n_pairs : 1) : ctx->n_cu * 4;
@@ -247,7 +248,7 @@ void sea_opts_default(sea_opts* o) {
     o->stencil_dtype = SEA_F64;
     o->ace_dtype = SEA_F64;
     o->start = SEA_START_ZERO;
-    o->refine_period = 50;
+    o->cg_variant = -1;
     o->profile = 0;
     o->nn_weight_dtype = SEA_BF16;
     o->hip_stream = nullptr;
@@ -469,6 +470,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         if (prof && ctx->ev_ready) (void)hipEventRecord(ctx->ev[st][1], s);
     };
     for (int k = SEA_STAGE_GATHER; k <= SEA_STAGE_ENERGY; ++k) ctx->ev_used[k] = false;
+    ctx->ev_used[SEA_STAGE_FINISH] = false;
     const bool zm = ctx->opts.stencil_dtype == SEA_F32 && S.cubic && cg_zm_fits(S.pairs.data(), n_pairs, nullptr) &&
                     cg_zm_lds_bytes(1) <= ctx->max_lds;
     if (!zm && ctx->opts.stencil_dtype != SEA_F64)
@@ -506,12 +508,16 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         }
         timer_on(SEA_STAGE_CG);
         if (zm) {
-            SEA_HIP_CHECK(ctx, launch_cg_zm(a, 1, s));
+            const int var = ctx->opts.cg_variant >= 0 ? ctx->opts.cg_variant : (ctx->cg_tuned >= 0 ? ctx->cg_tuned : 0);
+            SEA_HIP_CHECK(ctx, launch_cg_zm(a, var, s));
+            timer_off(SEA_STAGE_CG);
+            timer_on(SEA_STAGE_FINISH);
             SEA_HIP_CHECK(ctx, launch_cg_finish(a, s));
+            timer_off(SEA_STAGE_FINISH);
         } else {
             SEA_HIP_CHECK(ctx, launch_cg(a, s));
+            timer_off(SEA_STAGE_CG);
         }
-        timer_off(SEA_STAGE_CG);
     }
     if (f.action) {
         timer_on(SEA_STAGE_SCATTER);
@@ -901,6 +907,91 @@ sea_status sea_ace_energy(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, co
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuner of the FP32-state CG kernel
+
+extern "C" int sea_cg_variant_count(void) { return cg_variant_count(); }
+extern "C" const char* sea_cg_variant_name(int v) { return cg_variant_name(v); }
+
+extern "C" sea_status sea_exx_autotune(sea_ctx* ctx, int n_cells, const sea_cell* cells, void* ws_dev,
+                                       size_t ws_bytes, int sample_pairs, int iters, float* ms_host, int* best) {
+    if (!ctx) return SEA_E_ARG;
+    if (!ws_dev) return fail(ctx, SEA_E_ARG, "workspace is NULL");
+    if (sample_pairs < 1 || iters < 1) return fail(ctx, SEA_E_ARG, "need sample_pairs >= 1 and iters >= 1");
+    if (n_cells < 1 || !cells) return fail(ctx, SEA_E_ARG, "need n_cells >= 1 and a cell array");
+    // strided sample of all pairs, kept per cell
+    long total = 0;
+    for (int c = 0; c < n_cells; ++c) total += cells[c].n_pairs > 0 ? cells[c].n_pairs : 0;
+    if (total < 1) return fail(ctx, SEA_E_ARG, "no pairs to tune on");
+    const long step = total > sample_pairs ? (total + sample_pairs - 1) / sample_pairs : 1;
+    std::vector<std::vector<sea_pair>> keep(n_cells);
+    std::vector<sea_cell> sc(cells, cells + n_cells);
+    long g = 0;
+    for (int c = 0; c < n_cells; ++c) {
+        for (int k = 0; k < cells[c].n_pairs; ++k, ++g)
+            if (g % step == 0 && cells[c].pairs_host) keep[c].push_back(cells[c].pairs_host[k]);
+        sc[c].n_pairs = (int)keep[c].size();
+        sc[c].pairs_host = keep[c].data();
+    }
+    CellSet S;
+    sea_status st = build_cellset(ctx, n_cells, sc.data(), false, S);
+    if (st != SEA_OK) return st;
+    if (!S.cubic || !cg_zm_fits(S.pairs.data(), (int)S.pairs.size(), nullptr) || cg_zm_lds_bytes(1) > ctx->max_lds)
+        return fail(ctx, SEA_E_ARG, "the FP32 state needs cubic grids and pair domains with n[0], n[1] <= 64");
+    sea_opts saved = ctx->opts;
+    ctx->opts.start = SEA_START_ZERO;
+    const ExxLayout Ly = exx_layout(ctx, S, true);
+    if (ws_bytes < Ly.total) {
+        ctx->opts = saved;
+        return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, Ly.total);
+    }
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    char* base = (char*)ws_dev;
+    st = exx_upload(ctx, S, Ly, base, s);
+    ExxArgs a = exx_args(ctx, S, Ly, base, nullptr);
+    ctx->opts = saved;
+    if (st != SEA_OK) return st;
+    a.max_iter = iters;
+    a.rel_tol = 1e-300;  // never met: every pair runs exactly `iters` iterations
+    int nz_max = 1;
+    for (const auto& p : S.pairs) nz_max = p.n[2] > nz_max ? p.n[2] : nz_max;
+    SEA_HIP_CHECK(ctx, launch_gather_moments(a, s));
+    SEA_HIP_CHECK(ctx, launch_moments_final(a, nullptr, s));
+    SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
+    hipEvent_t e0, e1;
+    SEA_HIP_CHECK(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, SEA_E_HIP, "event creation failed");
+    }
+    const int nv = cg_variant_count();
+    int arg = 0;
+    float tbest = 0.0f;
+    hipError_t err = hipSuccess;
+    for (int v = 0; v < nv && err == hipSuccess; ++v) {
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {  // rep 0 warms the code object
+            err = launch_moments_final(a, nullptr, s);            // resets the pair queue
+            if (err == hipSuccess) err = hipEventRecord(e0, s);
+            if (err == hipSuccess) err = launch_cg_zm(a, v, s);
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (ms_host) ms_host[v] = ms;
+        if (v == 0 || ms < tbest) {
+            tbest = ms;
+            arg = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(ctx, SEA_E_HIP, "autotune: %s", hipGetErrorString(err));
+    ctx->cg_tuned = arg;
+    if (best) *best = arg;
+    return SEA_OK;
+}
 
 // ---------------------------------------------------------------------------
 // plans: tables uploaded once, kernel sequence captured into a HIP graph

@@ -36,6 +36,7 @@ struct sea_ctx {
     bool ev_used[SEA_STAGE_COUNT] = {};
     bool ev_ready = false;
     const void* nn_state = nullptr;   // attached network (learned start)
+    int cg_tuned = -1;                // z-march variant chosen by sea_exx_autotune
 };
 
 // Records the begin/end event of a stage when profiling is on.
@@ -124,7 +125,9 @@ hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
 // z-marching CG (k_cg.hip): needs every pair with n[0], n[1] <= 64.
 bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h);
 size_t cg_zm_lds_bytes(int state_f32);
-hipError_t launch_cg_zm(const ExxArgs& a, int state_f32, hipStream_t s);
+int cg_variant_count();
+const char* cg_variant_name(int v);
+hipError_t launch_cg_zm(const ExxArgs& a, int variant, hipStream_t s);
 hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s);
 hipError_t launch_scatter(const ExxArgs& a, int cell, const int* N, int n_occ, const int* csr_off,
                           const int2* csr_ent, hipStream_t s);

@@ -30,6 +30,7 @@ EXPORTS = [
     "sea_nn_workspace_bytes", "sea_nn_forward", "sea_nn_train_step", "sea_nn_attach",
     "sea_exx_nn_samples", "sea_exx_batched_workspace_bytes", "sea_exx_action_batched",
     "sea_exx_plan_create", "sea_exx_plan_launch", "sea_exx_plan_results", "sea_exx_plan_destroy",
+    "sea_cg_variant_count", "sea_cg_variant_name", "sea_exx_autotune",
 ]
 
 # the network's layers (name, c_in, c_out, relu), in parameter order
@@ -73,7 +74,7 @@ class SeaGrid(C.Structure):
 class SeaOpts(C.Structure):
     _fields_ = [("fd_half_order", C.c_int32), ("lmax", C.c_int32), ("rel_tol", C.c_double),
                 ("max_iter", C.c_int32), ("stencil_dtype", C.c_int), ("ace_dtype", C.c_int),
-                ("start", C.c_int), ("refine_period", C.c_int32), ("profile", C.c_int32),
+                ("start", C.c_int), ("cg_variant", C.c_int32), ("profile", C.c_int32),
                 ("nn_weight_dtype", C.c_int), ("hip_stream", C.c_void_p)]
 
 
@@ -84,7 +85,7 @@ class SeaCell(C.Structure):
 
 
 STAGES = ["gather", "boundary", "guess", "cg", "scatter", "energy", "ace_m", "ace_chol", "ace_xi",
-          "ace_apply"]
+          "ace_apply", "finish"]
 
 
 class SeaError(RuntimeError):
@@ -138,6 +139,11 @@ def load() -> C.CDLL:
     lib.sea_exx_plan_launch.argtypes = [vp, vp]
     lib.sea_exx_plan_results.argtypes = [vp, vp, vp]
     lib.sea_exx_plan_destroy.argtypes = [vp]
+    lib.sea_cg_variant_count.argtypes = []
+    lib.sea_cg_variant_count.restype = i
+    lib.sea_cg_variant_name.argtypes = [i]
+    lib.sea_cg_variant_name.restype = C.c_char_p
+    lib.sea_exx_autotune.argtypes = [vp, i, vp, vp, sz, i, i, vp, P(i)]
     _lib = lib
     return lib
 
@@ -189,7 +195,7 @@ class Context:
     """A library context bound to the current torch CUDA device and stream."""
 
     def __init__(self, rel_tol=1e-8, max_iter=10000, lmax=6, stencil_dtype=SEA_F64,
-                 ace_dtype=SEA_F64, start=SEA_START_ZERO, refine_period=50, profile=False,
+                 ace_dtype=SEA_F64, start=SEA_START_ZERO, cg_variant=-1, profile=False,
                  nn_weight_dtype=SEA_BF16, stream=None):
         import torch
         self._torch = torch
@@ -197,7 +203,7 @@ class Context:
         o = SeaOpts()
         self.lib.sea_opts_default(C.byref(o))
         o.rel_tol, o.max_iter, o.lmax = rel_tol, max_iter, lmax
-        o.stencil_dtype, o.ace_dtype, o.start, o.refine_period = stencil_dtype, ace_dtype, start, refine_period
+        o.stencil_dtype, o.ace_dtype, o.start, o.cg_variant = stencil_dtype, ace_dtype, start, cg_variant
         o.profile = 1 if profile else 0
         o.nn_weight_dtype = nn_weight_dtype
         if stream is None:
@@ -326,6 +332,46 @@ class Context:
                                              stats.ctypes.data if want_host else None)
         st = self._check(st)
         return Ws, (E if want_host else None), (stats[:n_all] if want_host else None), st
+
+    def cg_variants(self) -> list:
+        return [self.lib.sea_cg_variant_name(k).decode() for k in range(self.lib.sea_cg_variant_count())]
+
+    def autotune(self, cells, sample_pairs=2048, iters=20, ws=None, cache=None):
+        """Pick the FP32-state CG kernel variant for this workload.
+
+        Times every variant on a strided sample of the cells' pairs (same
+        work for each) and keeps the fastest for this context.  With
+        ``cache`` (a JSON path), a stored choice for the same device, variant
+        set and domain shapes is reused without timing, and new results are
+        stored.  Returns {"variant": name, "ms": {name: ms} or None, "cached": bool}."""
+        import json
+        torch = self._torch
+        names = self.cg_variants()
+        shapes = sorted({tuple(int(v) for v in n) for c in cells for n in np.asarray(c[3]["n"]).reshape(-1, 3)})
+        key = "|".join([torch.cuda.get_device_name(), ",".join(names), f"sample={sample_pairs}", f"iters={iters}",
+                        ";".join("x".join(map(str, t)) for t in shapes[:8])])
+        store = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                store = json.load(f)
+            hit = store.get(key)
+            if hit and hit.get("variant") in names:
+                self.set_opts(cg_variant=names.index(hit["variant"]))
+                return {"variant": hit["variant"], "ms": hit.get("ms"), "cached": True}
+        arr, _, keep = self._cells(cells, need_W=False)
+        if ws is None:
+            ws = self.workspace(self.exx_batched_workspace_bytes(cells))
+        ms = np.zeros(len(names), dtype=np.float32)
+        best = C.c_int(-1)
+        self._check(self.lib.sea_exx_autotune(self.h, len(cells), arr, ws.data_ptr(), ws.numel(), sample_pairs,
+                                              iters, ms.ctypes.data, C.byref(best)))
+        self.set_opts(cg_variant=-1)
+        out = {"variant": names[best.value], "ms": {n: float(t) for n, t in zip(names, ms)}, "cached": False}
+        if cache:
+            store[key] = {"variant": out["variant"], "ms": out["ms"]}
+            with open(cache, "w") as f:
+                json.dump(store, f, indent=1)
+        return out
 
     def exx_plan(self, cells, ws=None):
         """A replayable HIP-graph plan of the batched action (see Plan)."""

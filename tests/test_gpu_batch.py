@@ -152,3 +152,39 @@ def test_plan_device_energy_without_host_sync(cells):
     assert np.array_equal(e_dev.cpu().numpy(), E)
     plan.close()
     ctx.close()
+
+
+def test_autotune_picks_fastest_and_variants_agree(cells, tmp_path):
+    """Every CG kernel variant computes the same arithmetic in the same order
+    (they differ in load scheduling only): W and E are bit-identical.  The
+    tuner's choice is the argmin of its timings and is cached by key."""
+    print("case autotune", flush=True)
+    phis = _phis(cells, np.float32)
+    batch = [(phi, c.N, c.L, pairs) for (c, pairs), phi in zip(cells, phis)]
+    ctx = sea.Context(rel_tol=1e-8, stencil_dtype=sea.SEA_F32)
+    names = ctx.cg_variants()
+    assert len(names) >= 2
+    ref = None
+    for v in range(len(names)):
+        ctx.set_opts(cg_variant=v)
+        Ws, Es, stats, st = ctx.exx_action_batched(batch)
+        assert st == sea.SEA_OK
+        if ref is None:
+            ref = ([w.clone() for w in Ws], Es.copy(), stats.copy())
+        else:
+            assert np.array_equal(Es, ref[1]), names[v]
+            assert np.array_equal(stats, ref[2]), names[v]
+            for a, b in zip(Ws, ref[0]):
+                assert torch.equal(a, b), names[v]
+    ctx.set_opts(cg_variant=-1)
+    cache = str(tmp_path / "tune.json")
+    res = ctx.autotune(batch, sample_pairs=64, iters=10, cache=cache)
+    assert not res["cached"]
+    ms = res["ms"]
+    assert set(ms) == set(names) and all(t > 0 for t in ms.values())
+    assert res["variant"] == min(ms, key=ms.get)
+    again = ctx.autotune(batch, sample_pairs=64, iters=10, cache=cache)
+    assert again["cached"] and again["variant"] == res["variant"]
+    Ws, Es, _, st = ctx.exx_action_batched(batch)
+    assert np.array_equal(Es, ref[1])
+    ctx.close()
