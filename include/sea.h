@@ -283,6 +283,15 @@ sea_status sea_nn_workspace_bytes(sea_ctx *ctx, int batch, int D, size_t *bytes)
 /* y = net(x); x, y: batch x D^3 FP32 device arrays. */
 sea_status sea_nn_forward(sea_ctx *ctx, const void *state_dev, int batch, int D, const float *x_dev,
                           float *y_dev, void *ws_dev, size_t ws_bytes);
+/* Inference of the same network on the matrix cores: BF16 weights (the
+ * state's BF16 copy) and BF16 activations with FP32 accumulation
+ * (v_mfma_f32_16x16x32_bf16), network grid 32^3 only.  x_dev, y_dev:
+ * batch x 32^3 floats.  This is what the learned start uses when
+ * opts.nn_weight_dtype is SEA_BF16; sea_nn_forward keeps FP32 activations. */
+sea_status sea_nn_infer_workspace_bytes(sea_ctx *ctx, int batch, size_t *bytes);
+sea_status sea_nn_infer(sea_ctx *ctx, const void *state_dev, int batch, const float *x_dev, float *y_dev,
+                        void *ws_dev, size_t ws_bytes);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, `step`
  * 1-based) on the mean squared error between net(x) and t.  loss_host
  * (nullable) receives the loss before the step (synchronizes); grad_dev

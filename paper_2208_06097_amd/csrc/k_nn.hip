@@ -350,12 +350,6 @@ static hipError_t conv_launch(int O, const float* inA, int cA, const float* inB,
     return hipGetLastError();
 }
 
-#define NN_CHECK(x)                        \
-    do {                                   \
-        hipError_t e_ = (x);               \
-        if (e_ != hipSuccess) return e_;   \
-    } while (0)
-
 // Inputs of layer k (A and B sources) given the activation buffers.
 static void layer_inputs(int k, float* act, const NnActLayout& L, const float* x, const float** inA, int* cA,
                          const float** inB, int* cB) {

@@ -42,3 +42,23 @@ hipError_t nn_mse(const float* y, const float* t, long n, float* g, double* part
 hipError_t nn_adam(float* p, uint16_t* p16, float* m, float* v, const float* g, long n, float lr, int step,
                    hipStream_t s);
 hipError_t nn_to_bf16(const float* p, uint16_t* p16, long n, hipStream_t s);
+
+// Inference on the matrix cores (BF16 weights and activations, FP32
+// accumulation), network grid kNnGrid: offsets (bf16 elements) into its
+// workspace for batch B: packed weights, and per level three channels-last
+// tensors (ta, skip, tb) of B x d^3 x 16.
+constexpr int kNnMfmaBatch = 512;   // pairs per inference launch sequence
+struct NnInferLayout {
+    size_t wpack;
+    size_t ta[4], skip[4], tb[4];
+    size_t total_bytes;
+};
+NnInferLayout nn_infer_layout(int B);
+hipError_t nn_infer(const float* params, const uint16_t* params16, const float* x, void* ws, const NnInferLayout& L,
+                    int B, float* y, hipStream_t s);
+
+#define NN_CHECK(x)                        \
+    do {                                   \
+        hipError_t e_ = (x);               \
+        if (e_ != hipSuccess) return e_;   \
+    } while (0)

@@ -204,7 +204,8 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
         const size_t d3 = (size_t)kNnGrid * kNnGrid * kNnGrid;
         L.nnx = take(np * d3 * sizeof(float));
         L.nny = take(np * d3 * sizeof(float));
-        L.nnact = take(nn_act_layout(kNnInferBatch, kNnGrid).total_floats * sizeof(float));
+        L.nnact = ctx->opts.nn_weight_dtype == SEA_BF16 ? take(nn_infer_layout(kNnMfmaBatch).total_bytes)
+                                                         : take(nn_act_layout(kNnInferBatch, kNnGrid).total_floats * sizeof(float));
     }
     L.total = off;
     return L;
@@ -491,15 +492,24 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
             if (ctx->opts.start == SEA_START_LEARNED) {
                 float* x32 = (float*)(base + Ly.nnx);
                 float* y32 = (float*)(base + Ly.nny);
-                float* act = (float*)(base + Ly.nnact);
-                const NnActLayout AL = nn_act_layout(kNnInferBatch, kNnGrid);
                 const NnState st = nn_state_ptrs(ctx->nn_state);
                 const size_t d3 = (size_t)kNnGrid * kNnGrid * kNnGrid;
                 SEA_HIP_CHECK(ctx, launch_nn_sample(a, kNnGrid, x32, nullptr, 0, s));
-                for (int p0 = 0; p0 < n_pairs; p0 += kNnInferBatch) {
-                    const int nb = n_pairs - p0 < kNnInferBatch ? n_pairs - p0 : kNnInferBatch;
-                    SEA_HIP_CHECK(ctx, nn_forward(st.p, ctx->opts.nn_weight_dtype == SEA_BF16 ? st.p16 : nullptr,
-                                                  x32 + p0 * d3, act, AL, nb, kNnGrid, y32 + p0 * d3, s));
+                if (ctx->opts.nn_weight_dtype == SEA_BF16) {  // matrix cores, BF16 activations
+                    const NnInferLayout IL = nn_infer_layout(kNnMfmaBatch);
+                    for (int p0 = 0; p0 < n_pairs; p0 += kNnMfmaBatch) {
+                        const int nb = n_pairs - p0 < kNnMfmaBatch ? n_pairs - p0 : kNnMfmaBatch;
+                        SEA_HIP_CHECK(ctx, nn_infer(st.p, st.p16, x32 + p0 * d3, base + Ly.nnact, IL, nb,
+                                                    y32 + p0 * d3, s));
+                    }
+                } else {  // FP32 weights and activations (vector ALUs)
+                    float* act = (float*)(base + Ly.nnact);
+                    const NnActLayout AL = nn_act_layout(kNnInferBatch, kNnGrid);
+                    for (int p0 = 0; p0 < n_pairs; p0 += kNnInferBatch) {
+                        const int nb = n_pairs - p0 < kNnInferBatch ? n_pairs - p0 : kNnInferBatch;
+                        SEA_HIP_CHECK(ctx, nn_forward(st.p, nullptr, x32 + p0 * d3, act, AL, nb, kNnGrid,
+                                                      y32 + p0 * d3, s));
+                    }
                 }
                 SEA_HIP_CHECK(ctx, launch_nn_apply(a, kNnGrid, y32, s));
             }
@@ -703,6 +713,25 @@ sea_status sea_nn_forward(sea_ctx* ctx, const void* state_dev, int batch, int D,
     const NnActLayout L = nn_act_layout(batch, D);
     SEA_HIP_CHECK(ctx, nn_forward(ns.p, ctx->opts.nn_weight_dtype == SEA_BF16 ? ns.p16 : nullptr, x_dev,
                                   (float*)ws_dev, L, batch, D, y_dev, s));
+    return SEA_OK;
+}
+
+sea_status sea_nn_infer_workspace_bytes(sea_ctx* ctx, int batch, size_t* bytes) {
+    if (!ctx || !bytes) return SEA_E_ARG;
+    if (batch < 1) return fail(ctx, SEA_E_ARG, "batch must be >= 1");
+    *bytes = nn_infer_layout(batch).total_bytes;
+    return SEA_OK;
+}
+
+sea_status sea_nn_infer(sea_ctx* ctx, const void* state_dev, int batch, const float* x_dev, float* y_dev,
+                        void* ws_dev, size_t ws_bytes) {
+    if (!ctx) return SEA_E_ARG;
+    if (batch < 1) return fail(ctx, SEA_E_ARG, "batch must be >= 1");
+    if (!state_dev || !x_dev || !y_dev || !ws_dev) return fail(ctx, SEA_E_ARG, "NULL argument");
+    if (ws_bytes < nn_infer_layout(batch).total_bytes) return fail(ctx, SEA_E_NOMEM, "workspace too small");
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    const NnState ns = nn_state_ptrs(state_dev);
+    SEA_HIP_CHECK(ctx, nn_infer(ns.p, ns.p16, x_dev, ws_dev, nn_infer_layout(batch), batch, y_dev, s));
     return SEA_OK;
 }
 

@@ -31,6 +31,7 @@ EXPORTS = [
     "sea_exx_nn_samples", "sea_exx_batched_workspace_bytes", "sea_exx_action_batched",
     "sea_exx_plan_create", "sea_exx_plan_launch", "sea_exx_plan_results", "sea_exx_plan_destroy",
     "sea_cg_variant_count", "sea_cg_variant_name", "sea_exx_autotune",
+    "sea_nn_infer_workspace_bytes", "sea_nn_infer",
 ]
 
 # the network's layers (name, c_in, c_out, relu), in parameter order
@@ -144,6 +145,8 @@ def load() -> C.CDLL:
     lib.sea_cg_variant_name.argtypes = [i]
     lib.sea_cg_variant_name.restype = C.c_char_p
     lib.sea_exx_autotune.argtypes = [vp, i, vp, vp, sz, i, i, vp, P(i)]
+    lib.sea_nn_infer_workspace_bytes.argtypes = [vp, i, P(sz)]
+    lib.sea_nn_infer.argtypes = [vp, vp, i, vp, vp, vp, sz]
     _lib = lib
     return lib
 
@@ -483,6 +486,20 @@ class Context:
         y = self._torch.empty_like(x)
         self._check(self.lib.sea_nn_forward(self.h, state.data_ptr(), B, D, x.data_ptr(), y.data_ptr(),
                                             ws.data_ptr(), ws.numel()))
+        return y
+
+    def nn_infer(self, state, x, ws=None):
+        """Matrix-core inference (BF16 weights/activations, FP32 accumulation), 32^3 only."""
+        torch = self._torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and tuple(x.shape[1:]) == (32, 32, 32)
+        B = x.shape[0]
+        if ws is None:
+            b = C.c_size_t(0)
+            self._check(self.lib.sea_nn_infer_workspace_bytes(self.h, B, C.byref(b)))
+            ws = self.workspace(b.value)
+        y = torch.empty_like(x)
+        self._check(self.lib.sea_nn_infer(self.h, state.data_ptr(), B, x.data_ptr(), y.data_ptr(), ws.data_ptr(),
+                                          ws.numel()))
         return y
 
     def nn_train_step(self, state, x, t, lr, step, ws=None, want_loss=True, grad=None):

@@ -94,6 +94,37 @@ def test_nn_gradient_and_adam_match_oracle(net_case, wdt):
     ctx.close()
 
 
+def test_nn_infer_matrix_cores_matches_oracle():
+    """Matrix-core inference (BF16 weights and activations, FP32 accumulation)
+    on the 32^3 grid against the FP64 oracle fed the same BF16 weights.  Bar:
+    every activation is rounded to BF16 (relative 2^-9) once per layer, 15
+    layers in sequence: relative L2 error < 15 * 2^-9 ~ 3e-2."""
+    print("case nn infer (matrix cores) D=32", flush=True)
+    rng = np.random.default_rng(12)
+    p = nn.init_params(5)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.05 * rng.standard_normal(p[k].shape)
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    x = rng.standard_normal((2, 1, 32, 32, 32)).astype(np.float32).astype(np.float64)
+    ctx = _ctx(sea.SEA_BF16)
+    st = ctx.nn_state(sea.nn_pack(p))
+    xd = torch.from_numpy(x[:, 0].astype(np.float32)).cuda()
+    y = ctx.nn_infer(st, xd).cpu().numpy()
+    y_valu = ctx.nn_forward(st, xd).cpu().numpy()
+    pw = {k: (_bf16_round(v) if k.endswith(".w") else v) for k, v in p.items()}
+    yo, _ = nn.forward(pw, x)
+    err = _rel(y, yo[:, 0])
+    print(f"matrix-core inference rel err vs oracle {err:.2e}, vs FP32-activation path "
+          f"{_rel(y, y_valu):.2e}", flush=True)
+    assert np.all(np.isfinite(y))
+    assert err < 3e-2
+    # a batch that is not a multiple of anything and a second call reuse
+    y1 = ctx.nn_infer(st, xd[1:].contiguous()).cpu().numpy()
+    assert np.array_equal(y1[0], y[1])
+    ctx.close()
+
+
 @pytest.fixture(scope="module")
 def samples():
     """Training samples from converged solves of two small cells (29^3 domains)."""
