@@ -160,6 +160,7 @@ def main():
         return r, E_ace, Kpsi
 
     (Wr, E, stats, st), E_ace, _ = step(host=True)
+    step_out = None
     log(f"warmup: E_xx = {E:.9f}  E_ACE = {E_ace:.9f}  iters min/mean/max = "
         f"{stats['iters'].min()}/{stats['iters'].mean():.1f}/{stats['iters'].max()}  status {st}")
     for _ in range(args.warmup - 1):
@@ -168,7 +169,7 @@ def main():
     stage_acc = {k: 0.0 for k in sea.STAGES}
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step()
+        step_out = step()
         for kk, v in ctx.stage_times().items():
             stage_acc[kk] += v
         log(f"step {k + 1}/{args.steps} done")
@@ -186,6 +187,28 @@ def main():
                     "cg_iters_mean": float(stats["iters"].mean()), "E_xx": E, "E_ace": E_ace,
                     "dE_vs_oracle": (E - golden["E"]) if golden else None,
                     "dE_ace_vs_oracle": (E_ace - golden["E"]) if golden else None}}
+    # ACE precision sweep on this step's W: xi and K psi on the matrix cores in
+    # FP32 and BF16 (M, Cholesky and energy stay FP64), errors vs the FP64 path
+    # and E vs the oracle's E_xx
+    _, _, Kpsi64 = step_out
+    ace = {}
+    for name, adt, tdt in (("f64", sea.SEA_F64, torch.float64), ("f32", sea.SEA_F32, torch.float32),
+                           ("bf16", sea.SEA_BF16, torch.bfloat16)):
+        ca = sea.Context(profile=True, ace_dtype=adt)
+        psi_t = psi.to(tdt)
+        ca.ace_build(phi, W, dV, ws=ws_ace)
+        torch.cuda.synchronize()
+        M_, L_, xi_t, _ = ca.ace_build(phi, W, dV, ws=ws_ace)
+        K_t = ca.ace_apply(xi_t, psi_t, dV, ws=ws_ace)
+        E_t = ca.ace_energy(phi, xi_t, dV, ws=ws_ace)
+        st_ms = ca.stage_times()
+        kerr = float(torch.linalg.vector_norm(K_t.double() - Kpsi64.double()) / torch.linalg.vector_norm(Kpsi64.double()))
+        ace[name] = {"ms": {k: st_ms[k] for k in ("ace_m", "ace_chol", "ace_xi", "ace_apply")},
+                     "E_ace": E_t, "dE_vs_oracle": (E_t - golden["E"]) if golden else None,
+                     "Kpsi_rel_err_vs_f64": kerr}
+        log(f"ace {name}: E {E_t:.9f}  |dKpsi|/|Kpsi| {kerr:.2e}  ms {ace[name]['ms']}")
+        del xi_t, K_t, psi_t
+        ca.close()
     if args.other_forms:
         for fname in FORMS:
             if fname == form or (FORMS[fname]["start"] == "learned" and not have_w):
@@ -230,6 +253,7 @@ def main():
                    "autotune_ms": tune["ms"] if tune else None,
                    "cg_iters_total": int(stats["iters"].sum())},
         "forms": forms,
+        "ace_precision": ace,
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": cg_bytes,

@@ -233,9 +233,10 @@ sea_status sea_exx_pair_solve(sea_ctx *ctx, const sea_grid *grid, int n_occ, con
                               void *ws_dev, size_t ws_bytes, double *v_dev, double *Q_dev,
                               double *e_dev, sea_pair_stat *stats_host);
 
-/* ACE build (Eq. 18, App. A): M = dV Phi^T W (FP64), Mbar = (M + M^T)/2,
- * Mbar = L L^T (FP64 Cholesky, no pivoting), xi = W L^{-T} stored
- * orbital-major in ace_dtype.  M_dev, L_dev: n_occ x n_occ row-major FP64
+/* ACE build (Eq. 18, App. A): M = dV Phi^T W (FP64 matrix cores, FP64
+ * accumulation), Mbar = (M + M^T)/2, Mbar = L L^T (FP64 Cholesky, no
+ * pivoting), xi = W L^{-T} on the matrix cores with operands in ace_dtype
+ * (FP32 accumulation for F32/BF16), stored orbital-major in ace_dtype.  M_dev, L_dev: n_occ x n_occ row-major FP64
  * (L lower, upper triangle zero).  On a non-positive pivot returns
  * SEA_E_NOT_PD and *failed_pivot = 1-based pivot index (0 on success).
  * ws_dev: sea_ace_workspace_bytes bytes. */
@@ -245,14 +246,17 @@ sea_status sea_ace_build(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, con
                          const double *W_dev, void *ws_dev, size_t ws_bytes, double *M_dev,
                          double *L_dev, void *xi_dev, int *failed_pivot);
 
-/* K psi = -xi (dV xi^T psi)  (Eq. 18): psi_dev, out_dev n_vec x n_grid in
- * ace_dtype (BF16 uses FP32 output), xi_dev from sea_ace_build.  FP32
- * accumulation for F32/BF16, FP64 for F64. */
+/* K psi = -xi (dV xi^T psi)  (Eq. 18): psi_dev n_vec x n_grid in ace_dtype,
+ * out_dev n_vec x n_grid in ace_dtype (FP32 for BF16), xi_dev from
+ * sea_ace_build.  Both products run on the matrix cores with operands in
+ * ace_dtype: FP64 accumulation for F64, FP32 for F32/BF16 (the K-slice
+ * partials of dV xi^T psi are summed in FP64). */
 sea_status sea_ace_apply(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, const void *xi_dev,
                          int n_vec, const void *psi_dev, void *ws_dev, size_t ws_bytes,
                          void *out_dev);
 
-/* E_xx = -sum_ik <phi_i, xi_k>^2 (Eq. 19), FP64 result on the host. */
+/* E_xx = -sum_ik <phi_i, xi_k>^2 (Eq. 19): FP64 products (xi of any
+ * ace_dtype converts exactly), FP64 result on the host. */
 sea_status sea_ace_energy(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, const double *phi_dev,
                           const void *xi_dev, void *ws_dev, size_t ws_bytes, double *exx_host);
 

@@ -797,9 +797,9 @@ AceLayout ace_layout(long n_grid, int n_occ, int n_vec) {
     const int nv = n_vec > n_occ ? n_vec : n_occ;
     // split-K partials for every product this workspace serves:
     // (n_occ x n_occ) for M and the energy, (n_occ x n_vec) for K psi
-    size_t part_elems = (size_t)ace_splits(n_grid, n_occ, n_occ) * n_occ * n_occ;
+    size_t part_elems = (size_t)ace_mfma_splits(n_grid, n_occ, n_occ) * n_occ * n_occ;
     if (n_vec > 0) {
-        const size_t pv = (size_t)ace_splits(n_grid, n_occ, n_vec) * n_occ * n_vec;
+        const size_t pv = (size_t)ace_mfma_splits(n_grid, n_occ, n_vec) * n_occ * n_vec;
         if (pv > part_elems) part_elems = pv;
     }
     size_t off = 0;
@@ -825,7 +825,6 @@ sea_status check_ace(sea_ctx* ctx, long n_grid, int n_occ, double dV, size_t ws_
     if (!(dV > 0.0) || !std::isfinite(dV)) return fail(ctx, SEA_E_ARG, "dV must be positive and finite");
     if (!ws) return fail(ctx, SEA_E_ARG, "workspace is NULL");
     if (ws_bytes < Ly.total) return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, Ly.total);
-    if (ctx->opts.ace_dtype == SEA_BF16) return fail(ctx, SEA_E_ARG, "ace_dtype SEA_BF16 is not available");
     return SEA_OK;
 }
 
@@ -857,7 +856,8 @@ sea_status sea_ace_build(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, con
     for (int k = SEA_STAGE_ACE_M; k <= SEA_STAGE_ACE_XI; ++k) ctx->ev_used[k] = false;
     {
         StageTimer t(ctx, SEA_STAGE_ACE_M, s);
-        SEA_HIP_CHECK(ctx, (ace_gemm_nt<double, double>(phi_dev, W_dev, n_occ, n_occ, n_grid, dV, part, M_dev, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_F64, double, double>(phi_dev, W_dev, n_occ, n_occ, n_grid, dV, part, M_dev,
+                                                               s)));
         SEA_HIP_CHECK(ctx, ace_symmetrize(M_dev, n_occ, Mb, s));
     }
     {
@@ -873,11 +873,14 @@ sea_status sea_ace_build(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, con
     SEA_HIP_CHECK(ctx, ace_trtri(L_dev, n_occ, Li, s));
     // xi (orbital-major) = L^{-1} W
     if (ctx->opts.ace_dtype == SEA_F64)
-        SEA_HIP_CHECK(ctx, (ace_gemm_nn<double, double>(Li, n_occ, 1, W_dev, n_occ, n_occ, n_grid, 1.0,
-                                                         (double*)xi_dev, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_F64, double, double>(Li, n_occ, 1, W_dev, n_occ, n_occ, n_grid, 1.0,
+                                                               (double*)xi_dev, s)));
+    else if (ctx->opts.ace_dtype == SEA_F32)
+        SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_F32, double, float>(Li, n_occ, 1, W_dev, n_occ, n_occ, n_grid, 1.0,
+                                                              (float*)xi_dev, s)));
     else
-        SEA_HIP_CHECK(ctx, (ace_gemm_nn<double, float>(Li, n_occ, 1, W_dev, n_occ, n_occ, n_grid, 1.0,
-                                                        (float*)xi_dev, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_BF16, double, uint16_t>(Li, n_occ, 1, W_dev, n_occ, n_occ, n_grid, 1.0,
+                                                                  (uint16_t*)xi_dev, s)));
     return SEA_OK;
 }
 
@@ -897,15 +900,21 @@ sea_status sea_ace_apply(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, con
     StageTimer t(ctx, SEA_STAGE_ACE_APPLY, s);
     // C (n_occ x n_vec) = dV xi psi^T ; out (n_vec x n_grid) = -C^T xi
     if (ctx->opts.ace_dtype == SEA_F64) {
-        SEA_HIP_CHECK(ctx, (ace_gemm_nt<double, double>((const double*)xi_dev, (const double*)psi_dev, n_occ, n_vec,
-                                                         n_grid, dV, part, Cm, s)));
-        SEA_HIP_CHECK(ctx, (ace_gemm_nn<double, double>(Cm, 1, n_vec, (const double*)xi_dev, n_vec, n_occ, n_grid,
-                                                         -1.0, (double*)out_dev, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_F64, double, double>((const double*)xi_dev, (const double*)psi_dev, n_occ,
+                                                               n_vec, n_grid, dV, part, Cm, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_F64, double, double>(Cm, 1, n_vec, (const double*)xi_dev, n_vec, n_occ,
+                                                               n_grid, -1.0, (double*)out_dev, s)));
+    } else if (ctx->opts.ace_dtype == SEA_F32) {
+        SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_F32, float, float>((const float*)xi_dev, (const float*)psi_dev, n_occ,
+                                                             n_vec, n_grid, dV, part, Cm, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_F32, float, float>(Cm, 1, n_vec, (const float*)xi_dev, n_vec, n_occ,
+                                                             n_grid, -1.0, (float*)out_dev, s)));
     } else {
-        SEA_HIP_CHECK(ctx, (ace_gemm_nt<float, float>((const float*)xi_dev, (const float*)psi_dev, n_occ, n_vec,
-                                                       n_grid, dV, part, Cm, s)));
-        SEA_HIP_CHECK(ctx, (ace_gemm_nn<float, float>(Cm, 1, n_vec, (const float*)xi_dev, n_vec, n_occ, n_grid,
-                                                       -1.0, (float*)out_dev, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_BF16, uint16_t, uint16_t>((const uint16_t*)xi_dev,
+                                                                    (const uint16_t*)psi_dev, n_occ, n_vec, n_grid,
+                                                                    dV, part, Cm, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_BF16, uint16_t, float>(Cm, 1, n_vec, (const uint16_t*)xi_dev, n_vec,
+                                                                 n_occ, n_grid, -1.0, (float*)out_dev, s)));
     }
     return SEA_OK;
 }
@@ -922,12 +931,16 @@ sea_status sea_ace_energy(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, co
     double* part = (double*)(base + Ly.part);
     double* S = (double*)(base + Ly.smat);
     double* out = (double*)(base + Ly.flag);
+    // FP64 reduction whatever ace_dtype is (xi converts to FP64 exactly)
     if (ctx->opts.ace_dtype == SEA_F64)
-        SEA_HIP_CHECK(ctx, (ace_gemm_nt<double, double>(phi_dev, (const double*)xi_dev, n_occ, n_occ, n_grid, dV,
-                                                         part, S, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_F64, double, double>(phi_dev, (const double*)xi_dev, n_occ, n_occ, n_grid,
+                                                               dV, part, S, s)));
+    else if (ctx->opts.ace_dtype == SEA_F32)
+        SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_F64, double, float>(phi_dev, (const float*)xi_dev, n_occ, n_occ, n_grid,
+                                                              dV, part, S, s)));
     else
-        SEA_HIP_CHECK(ctx, (ace_gemm_nt<double, float>(phi_dev, (const float*)xi_dev, n_occ, n_occ, n_grid, dV,
-                                                        part, S, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_F64, double, uint16_t>(phi_dev, (const uint16_t*)xi_dev, n_occ, n_occ,
+                                                                 n_grid, dV, part, S, s)));
     SEA_HIP_CHECK(ctx, ace_neg_sum_squares(S, n_occ * n_occ, out, s));
     SEA_HIP_CHECK(ctx, hipMemcpyAsync(exx_host, out, sizeof(double), hipMemcpyDeviceToHost, s));
     SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));

@@ -433,6 +433,7 @@ class Context:
         if ws is None:
             ws = self.workspace(self.ace_workspace_bytes(ng, n_occ, n_vec))
         out_dtype = torch.float32 if self.opts.ace_dtype == SEA_BF16 else self._xi_torch_dtype()
+        assert psi.dtype == self._xi_torch_dtype(), "psi must be in the context's ace_dtype"
         out = torch.empty(psi.shape, dtype=out_dtype, device=psi.device)
         st = self.lib.sea_ace_apply(self.h, ng, n_occ, dV, xi.data_ptr(), n_vec, psi.data_ptr(), ws.data_ptr(),
                                     ws.numel(), out.data_ptr())

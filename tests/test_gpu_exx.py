@@ -189,6 +189,48 @@ def test_ace_build_apply_energy_mini(ctx, mini):
     assert abs(E - ref.E) < 1e-6
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_ace_matrix_core_dtypes_multi_tile(dt):
+    """ACE build / apply / energy on the matrix cores at sizes that span
+    several output tiles with ragged edges (150 orbitals over 128-row tiles,
+    70 trial vectors, 21^3 grid points over 128-column tiles and uneven K
+    slices), per ace_dtype against the FP64 oracle.  M, its Cholesky factor
+    and the energy reduction are FP64 in every dtype; xi and K psi carry the
+    dtype's rounding: bars are FP64 1e-10, FP32 (2^-24 per operand, FP32
+    accumulation) 1e-5, BF16 (2^-9 per operand) 1e-2 relative."""
+    print(f"case ace matrix cores {dt}", flush=True)
+    rng = np.random.default_rng(3)
+    n_occ, N, n_vec = 150, 21, 70
+    ng, dV = N ** 3, 0.3 ** 3
+    phi = rng.standard_normal((n_occ, ng)) / np.sqrt(ng * dV)
+    A = rng.standard_normal((n_occ, n_occ))
+    G = A @ A.T / n_occ + np.eye(n_occ)
+    W = G @ phi
+    psi = rng.standard_normal((n_vec, ng)) / np.sqrt(ng * dV)
+    want = oracle.ace_build(phi, W, dV)
+    adt = {"f64": sea.SEA_F64, "f32": sea.SEA_F32, "bf16": sea.SEA_BF16}[dt]
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dt]
+    bar = {"f64": 1e-10, "f32": 1e-5, "bf16": 1e-2}[dt]
+    ctx = sea.Context(ace_dtype=adt)
+    M, Lm, xi, fp = ctx.ace_build(_dev(phi), _dev(W), dV)
+    assert fp == 0
+    assert np.max(np.abs(M.cpu().numpy() - want.M)) <= 1e-12 * np.max(np.abs(want.M))
+    assert np.max(np.abs(Lm.cpu().numpy() - want.L)) <= 1e-10 * np.max(np.abs(want.L))
+    xi_h = xi.double().cpu().numpy()
+    assert np.linalg.norm(xi_h - want.xi) <= bar * np.linalg.norm(want.xi)
+    psi_d = _dev(psi).to(tdt)
+    K = ctx.ace_apply(xi, psi_d, dV).double().cpu().numpy()
+    Kw = oracle.ace_apply(want.xi, psi_d.double().cpu().numpy(), dV)
+    rel_k = np.linalg.norm(K - Kw) / np.linalg.norm(Kw)
+    E = ctx.ace_energy(_dev(phi), xi, dV)
+    Ew = oracle.ace_energy(phi, want.xi, dV)
+    print(f"ace {dt}: |dxi|/|xi| {np.linalg.norm(xi_h - want.xi) / np.linalg.norm(want.xi):.2e}  "
+          f"|dKpsi|/|Kpsi| {rel_k:.2e}  |dE|/|E| {abs(E - Ew) / abs(Ew):.2e}", flush=True)
+    assert rel_k <= bar
+    assert abs(E - Ew) <= bar * abs(Ew)
+    ctx.close()
+
+
 def test_ace_not_positive_definite(ctx, mini):
     cell, pl, ref, pairs = mini
     print("case ace not-PD", flush=True)
