@@ -136,17 +136,36 @@ __global__ __launch_bounds__(NT) void k_nt_mfma(const TA* __restrict__ A, const 
     for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[p][q] = typename Kd::Acc{0, 0, 0, 0};
-    for (long k0 = kb; k0 < ke; k0 += KT) {
-        // rows along k are contiguous in memory: 32 consecutive threads per row
-        for (int t = threadIdx.x; t < BM * KT; t += NT) {
-            const int rr = t / KT, kk = t % KT;
+    // Software pipeline: the global loads of the next K stage are in flight
+    // (in registers) while the current stage is multiplied out of LDS.
+    // Stage element e of thread t: row (t + NT e) / KT, k (t + NT e) % KT;
+    // 32 consecutive threads read 32 consecutive k of one row.
+    constexpr int PER = BM * KT / NT;
+    TA ra[PER];
+    TB rb[PER];
+    auto load = [&](long k0) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = threadIdx.x + NT * e;
+            const int rr = idx / KT, kk = idx % KT;
             const long k = k0 + kk;
-            As[rr * Kd::PITCH + kk] = (i0 + rr < m && k < ke) ? Kd::cvt(A[(size_t)(i0 + rr) * K + k]) : E(0);
-            Bs[rr * Kd::PITCH + kk] = (j0 + rr < n && k < ke) ? Kd::cvt(B[(size_t)(j0 + rr) * K + k]) : E(0);
+            ra[e] = (i0 + rr < m && k < ke) ? A[(size_t)(i0 + rr) * K + k] : TA(0);
+            rb[e] = (j0 + rr < n && k < ke) ? B[(size_t)(j0 + rr) * K + k] : TB(0);
+        }
+    };
+    if (kb < ke) load(kb);
+    for (long k0 = kb; k0 < ke; k0 += KT) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = threadIdx.x + NT * e;
+            const int rr = idx / KT, kk = idx % KT;
+            As[rr * Kd::PITCH + kk] = Kd::cvt(ra[e]);
+            Bs[rr * Kd::PITCH + kk] = Kd::cvt(rb[e]);
         }
         __syncthreads();
+        if (k0 + KT < ke) load(k0 + KT);
         tile_mma<KIND>(As, Bs, acc);
-        __syncthreads();
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -196,18 +215,34 @@ __global__ __launch_bounds__(NT) void k_nn_mfma(const double* __restrict__ A, lo
     for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[p][q] = typename Kd::Acc{0, 0, 0, 0};
-    for (int k0 = 0; k0 < K; k0 += KT) {
-        for (int t = threadIdx.x; t < BM * KT; t += NT) {
-            const int rr = t / KT, kk = t % KT;  // small A: any order (cache-resident)
-            As[rr * Kd::PITCH + kk] =
-                (i0 + rr < m && k0 + kk < K) ? Kd::cvt(A[(i0 + rr) * sai + (long)(k0 + kk) * sak]) : E(0);
-            const int jj = t % BN, kb = t / BN;  // B rows are contiguous along the grid
+    // Same pipeline as the NT kernel.  A (small, cache-resident): row
+    // idx / KT, k idx % KT; B: 128 consecutive threads read one grid row.
+    constexpr int PER = BM * KT / NT;
+    double ra[PER];
+    TB rb[PER];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = threadIdx.x + NT * e;
+            const int rr = idx / KT, kk = idx % KT;
+            ra[e] = (i0 + rr < m && k0 + kk < K) ? A[(i0 + rr) * sai + (long)(k0 + kk) * sak] : 0.0;
+            const int jj = idx % BN, kr = idx / BN;
             const long j = j0 + jj;
-            Bs[jj * Kd::PITCH + kb] = (j < ncol && k0 + kb < K) ? Kd::cvt(B[(size_t)(k0 + kb) * ncol + j]) : E(0);
+            rb[e] = (j < ncol && k0 + kr < K) ? B[(size_t)(k0 + kr) * ncol + j] : TB(0);
+        }
+    };
+    load(0);
+    for (int k0 = 0; k0 < K; k0 += KT) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = threadIdx.x + NT * e;
+            As[(idx / KT) * Kd::PITCH + idx % KT] = Kd::cvt(ra[e]);
+            Bs[(idx % BN) * Kd::PITCH + idx / BN] = Kd::cvt(rb[e]);
         }
         __syncthreads();
+        if (k0 + KT < K) load(k0 + KT);
         tile_mma<KIND>(As, Bs, acc);
-        __syncthreads();
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1;

@@ -127,6 +127,34 @@ def fill_orbitals(cell: Cell, dtype=np.float64) -> Cell:
     return cell
 
 
+def fill_orbitals_device(cell: Cell, device="cuda", dtype=None, chunk: int = 32):
+    """Same orbitals as fill_orbitals, assembled on a torch device.
+
+    The seeded draws and the per-axis factors are the same NumPy values; only
+    the outer products and the normalization sums run on the device (FP64), so
+    the result equals fill_orbitals up to the order of the normalization sum.
+    Used for large cells whose host-side evaluation would dominate a run.
+    Returns a contiguous (n_occ, N, N, N) tensor of ``dtype`` (default FP64)."""
+    import torch
+    dtype = dtype or torch.float64
+    N, L = cell.N, cell.L
+    h3 = cell.h ** 3
+    out = torch.empty((cell.n_occ, N, N, N), dtype=dtype, device=device)
+    for i0 in range(0, cell.n_occ, chunk):
+        i1 = min(cell.n_occ, i0 + chunk)
+        fac = [[_axis_factors(cell.centres[i, ax], cell.a[i, ax], L, N) for ax in range(3)] for i in range(i0, i1)]
+        t = lambda ax, k: torch.from_numpy(np.stack([f[ax][k] for f in fac])).to(device)  # noqa: E731
+        gx, ax_ = t(0, 0), t(0, 1)
+        gy, ay = t(1, 0), t(1, 1)
+        gz, az = t(2, 0), t(2, 1)
+        f = (gz[:, :, None, None] * (gy[:, None, :, None] * (gx + ax_)[:, None, None, :]
+                                     + ay[:, None, :, None] * gx[:, None, None, :])
+             + az[:, :, None, None] * (gy[:, None, :, None] * gx[:, None, None, :]))
+        norm = torch.sqrt(h3 * torch.sum(f * f, dim=(1, 2, 3)))
+        out[i0:i1] = (f / norm[:, None, None, None]).to(dtype)
+    return out
+
+
 # ---- the five workload recipes -------------------------------------------
 
 def config1(seed: int = 101, with_phi: bool = True) -> Cell:
