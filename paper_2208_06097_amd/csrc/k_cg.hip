@@ -226,7 +226,36 @@ struct PVsel {
     using type = F2<T>;
 };
 
-template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH>
+// Access to one slot array at element col0 + off, off uniform across the
+// workgroup (plane and column offsets).  BUF: raw buffer instructions with
+// the array in a buffer resource (scalar registers), the lane's column in
+// one 32-bit VGPR and the uniform offset in a scalar register, so the state
+// arrays cost no 64-bit address registers; otherwise plain global pointers.
+template <typename T, bool BUF>
+struct SlotIO;
+template <typename T>
+struct SlotIO<T, false> {
+    T* p;
+    __device__ SlotIO(T* base, int, int col0) : p(base + col0) {}
+    __device__ __forceinline__ T ld(int off) const { return p[off]; }
+    __device__ __forceinline__ void st(int off, T v) const { p[off] = v; }
+};
+template <>
+struct SlotIO<float, true> {
+    __amdgpu_buffer_rsrc_t rs;
+    int voff;
+    __device__ SlotIO(float* base, int n_elems, int col0)
+        : rs(__builtin_amdgcn_make_buffer_rsrc(base, 0, n_elems * (int)sizeof(float), 0x00020000)),
+          voff(col0 * (int)sizeof(float)) {}
+    __device__ __forceinline__ float ld(int off) const {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, off * (int)sizeof(float), 0));
+    }
+    __device__ __forceinline__ void st(int off, float v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, voff, off * (int)sizeof(float), 0);
+    }
+};
+
+template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH, bool BUF>
 __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __restrict__ cc, T* __restrict__ rr,
                            T* __restrict__ pp, double* __restrict__ r64) {
     const DevCell& C = a.cells[a.pair_cell[pid]];
@@ -249,6 +278,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
 #pragma unroll
     for (int c = 0; c < COLS; ++c) msk[c] = (tx < nx && ty + TY * c < ny) ? T(1) : T(0);
     const int col0 = ty * 64 + tx;  // column c at col0 + c*TY*64 within a plane
+    const SlotIO<T, BUF> io_c(cc, npad, col0), io_r(rr, npad, col0), io_p(pp, npad, col0);
 
     // r64 = b0 on the padded grid; x = 0 unless a start guess is present
     double bb = 0.0, r2 = 0.0;
@@ -293,14 +323,14 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
         zmarch<T, T, NT, COLS, DEPTH, F2<T>, Empty>(
             nz, lds, w,
             [&](int c, int z) -> F2<T> {
-                const int id = z * PL + col0 + c * TY * 64;
-                return F2<T>{rr[id], pp[id]};
+                const int o = z * PL + c * TY * 64;
+                return F2<T>{io_r.ld(o), io_p.ld(o)};
             },
             [&](int c, int z, F2<T> f) -> T {
                 const T pn = f.a + beta * f.b;
                 // beyond the domain pn = 0 (r and p read the zero plane):
                 // the store lands on plane nz, which stays zero
-                pp[min(z, nz) * PL + col0 + c * TY * 64] = pn;
+                io_p.st(min(z, nz) * PL + c * TY * 64, pn);
                 return pn;
             },
             [&](int, int) { return Empty{}; },
@@ -310,30 +340,30 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
         // sweep B: c += alpha p, r -= alpha A p, <r, r>
         using PV = typename PVsel<T>::type;
         double racc = 0.0;
-        auto fetch_p = [&](int c, int z) -> T { return pp[z * PL + col0 + c * TY * 64]; };
+        auto fetch_p = [&](int c, int z) -> T { return io_p.ld(z * PL + c * TY * 64); };
         auto make_p = [&](int, int, T v) -> T { return v; };
         if constexpr (PREFETCH) {
             zmarch<T, T, NT, COLS, DEPTH, T, PV>(
                 nz, lds, w, fetch_p, make_p,
                 [&](int c, int z) -> PV {
-                    const int id = z * PL + col0 + c * TY * 64;
-                    return PV{cc[id], rr[id]};
+                    const int o = z * PL + c * TY * 64;
+                    return PV{io_c.ld(o), io_r.ld(o)};
                 },
                 [&](int c, int z, T s, T ctr, PV v) {
-                    const int id = z * PL + col0 + c * TY * 64;
+                    const int o = z * PL + c * TY * 64;
                     const T rn = msk[c] * (v.b - al * s);
-                    cc[id] = v.a + al * ctr;
-                    rr[id] = rn;
+                    io_c.st(o, v.a + al * ctr);
+                    io_r.st(o, rn);
                     racc += (double)rn * (double)rn;
                 });
         } else {
             zmarch<T, T, NT, COLS, DEPTH, T, Empty>(
                 nz, lds, w, fetch_p, make_p, [&](int, int) { return Empty{}; },
                 [&](int c, int z, T s, T ctr, Empty) {
-                    const int id = z * PL + col0 + c * TY * 64;
-                    const T rn = msk[c] * (rr[id] - al * s);
-                    cc[id] = cc[id] + al * ctr;
-                    rr[id] = rn;
+                    const int o = z * PL + c * TY * 64;
+                    const T rn = msk[c] * (io_r.ld(o) - al * s);
+                    io_c.st(o, io_c.ld(o) + al * ctr);
+                    io_r.st(o, rn);
                     racc += (double)rn * (double)rn;
                 });
         }
@@ -348,7 +378,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
         // reliable update in FP64: r64 -= A c, x += c
         double uacc = 0.0;
         zmarch<T, double, NT, COLS, 1, T, double>(
-            nz, lds, wd, [&](int c, int z) -> T { return cc[z * PL + col0 + c * TY * 64]; },
+            nz, lds, wd, [&](int c, int z) -> T { return io_c.ld(z * PL + c * TY * 64); },
             [&](int, int, T v) -> T { return v; },
             [&](int c, int z) -> double { return r64[z * PL + col0 + c * TY * 64]; },
             [&](int c, int z, double s, T ctr, double rv) {
@@ -374,7 +404,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     }
 }
 
-template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH>
+template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH, bool BUF>
 __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
     extern __shared__ unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
@@ -392,7 +422,7 @@ __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
         __syncthreads();
         const int pid = pid_sh;
         if (pid >= a.n_pairs) break;
-        solve_pair<T, NT, COLS, PREFETCH, DEPTH>(a, pid, lds, red, cc, rr, pp, r64);
+        solve_pair<T, NT, COLS, PREFETCH, DEPTH, BUF>(a, pid, lds, red, cc, rr, pp, r64);
     }
 }
 
@@ -479,7 +509,8 @@ hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s) {
 // 4096 / nt; smaller workgroups need more queue registers than the 128 a
 // lane may hold at this size and spill in the plane loop); pf: prefetch c
 // and r of the output plane before the barrier; d: planes of p in flight
-// ahead of the register queue.
+// ahead of the register queue; buf: state arrays through buffer
+// instructions (32-bit offsets) instead of 64-bit global addresses.
 namespace {
 using CgKernel = void (*)(ExxArgs);
 struct CgVariant {
@@ -488,10 +519,13 @@ struct CgVariant {
     int nt;
 };
 const CgVariant kCgVariants[] = {
-    {"nt1024-pf-d1", k_cg_zm<float, 1024, 4, true, 1>, 1024},
-    {"nt1024-pf-d2", k_cg_zm<float, 1024, 4, true, 2>, 1024},
-    {"nt1024-d1", k_cg_zm<float, 1024, 4, false, 1>, 1024},
-    {"nt1024-d2", k_cg_zm<float, 1024, 4, false, 2>, 1024},
+    {"nt1024-pf-d1", k_cg_zm<float, 1024, 4, true, 1, false>, 1024},
+    {"nt1024-pf-d2", k_cg_zm<float, 1024, 4, true, 2, false>, 1024},
+    {"nt1024-d1", k_cg_zm<float, 1024, 4, false, 1, false>, 1024},
+    {"nt1024-d2", k_cg_zm<float, 1024, 4, false, 2, false>, 1024},
+    {"buf-pf-d1", k_cg_zm<float, 1024, 4, true, 1, true>, 1024},
+    {"buf-pf-d2", k_cg_zm<float, 1024, 4, true, 2, true>, 1024},
+    {"buf-d2", k_cg_zm<float, 1024, 4, false, 2, true>, 1024},
 };
 constexpr int kNumCgVariants = sizeof(kCgVariants) / sizeof(kCgVariants[0]);
 }  // namespace
