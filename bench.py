@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--other-forms", action="store_true", help="also time one V_xx action of every other form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune-pairs", type=int, default=2048, help="pairs sampled by the CG kernel autotuner")
+    ap.add_argument("--cg-variant", default=None,
+                    help="fixed FP32 CG kernel variant (skips the autotuner; for profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 2 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -148,7 +150,10 @@ def main():
     exx_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     log(f"form {form}; pairs: {n_pairs}; workspace {ws.numel() / 2**30:.2f} GiB")
     tune = None
-    if FORMS[form]["stencil"] == "f32":
+    if FORMS[form]["stencil"] == "f32" and args.cg_variant:
+        ctx.set_opts(cg_variant=ctx.cg_variants().index(args.cg_variant))
+        tune = {"variant": args.cg_variant, "ms": None}
+    elif FORMS[form]["stencil"] == "f32":
         tune = ctx.autotune([(phi, cell.N, cell.L, pairs)], sample_pairs=args.tune_pairs, iters=20, ws=ws)
         log(f"autotune: {tune['variant']}  " + "  ".join(f"{k} {v:.1f} ms" for k, v in tune["ms"].items()))
 

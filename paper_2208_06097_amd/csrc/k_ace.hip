@@ -20,54 +20,74 @@ __global__ void k_symmetrize(const double* __restrict__ M, int n, double* __rest
 
 constexpr int CH_BS = 1024;
 
-// Left-looking unblocked Cholesky (lower, row-major) of A into L; flag[0] =
-// 1-based index of the first non-positive pivot, 0 on success.
+// Wave-wide sum (64 lanes).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Left-looking Cholesky (lower, row-major) of A into L, one workgroup of 16
+// wavefronts: for column j, wavefront 0 forms the pivot from row j, then the
+// 16 wavefronts take the rows below it in turn, each row's dot product over
+// k < j split across the 64 lanes.  flag[0] = 1-based index of the first
+// non-positive pivot, 0 on success.
 __global__ __launch_bounds__(CH_BS) void k_cholesky(const double* __restrict__ A, int n, double* __restrict__ L,
                                                     int* __restrict__ flag) {
-    __shared__ double red[CH_BS / 64 + 1];
+    __shared__ double piv;
     __shared__ int bad;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int t = threadIdx.x; t < n * n; t += CH_BS) L[t] = 0.0;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int k = threadIdx.x; k < j; k += CH_BS) s += L[(size_t)j * n + k] * L[(size_t)j * n + k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < CH_BS / 64; ++w) t += red[w];
-            const double d = A[(size_t)j * n + j] - t;
-            if (!(d > 0.0)) {
-                bad = j + 1;
-            } else {
-                L[(size_t)j * n + j] = sqrt(d);
+        if (wave == 0) {
+            double s = 0.0;
+            for (int k = lane; k < j; k += 64) s += L[(size_t)j * n + k] * L[(size_t)j * n + k];
+            s = wave_sum(s);
+            if (lane == 0) {
+                const double d = A[(size_t)j * n + j] - s;
+                if (d > 0.0) {
+                    piv = sqrt(d);
+                    L[(size_t)j * n + j] = piv;
+                } else {
+                    bad = j + 1;
+                }
             }
         }
         __syncthreads();
         if (bad) break;
-        const double ljj = L[(size_t)j * n + j];
-        for (int i = j + 1 + threadIdx.x; i < n; i += CH_BS) {
-            double t = A[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
-            L[(size_t)i * n + j] = t / ljj;
+        const double ljj = piv;
+        for (int i = j + 1 + wave; i < n; i += CH_BS / 64) {
+            double s = 0.0;
+            for (int k = lane; k < j; k += 64) s += L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            s = wave_sum(s);
+            if (lane == 0) L[(size_t)i * n + j] = (A[(size_t)i * n + j] - s) / ljj;
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) flag[0] = bad;
 }
 
-// X = L^{-1} (lower), one thread per column, forward substitution.
-__global__ void k_trtri_lower(const double* __restrict__ L, int n, double* __restrict__ X) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    for (int i = 0; i < c; ++i) X[(size_t)i * n + c] = 0.0;
+// X = L^{-1} (lower): workgroup c (one wavefront) forms column c by forward
+// substitution, x_i = (delta_ic - sum_{c<=k<i} L[i][k] x_k) / L[i][i], with
+// the column kept in LDS and each dot product split across the lanes.
+constexpr int TR_MAX = 4096;
+__global__ __launch_bounds__(64) void k_trtri_lower(const double* __restrict__ L, int n, double* __restrict__ X) {
+    __shared__ double x[TR_MAX];
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < c; i += 64) X[(size_t)i * n + c] = 0.0;
     for (int i = c; i < n; ++i) {
-        double t = (i == c) ? 1.0 : 0.0;
-        for (int k = c; k < i; ++k) t -= L[(size_t)i * n + k] * X[(size_t)k * n + c];
-        X[(size_t)i * n + c] = t / L[(size_t)i * n + i];
+        double s = 0.0;
+        for (int k = c + lane; k < i; k += 64) s += L[(size_t)i * n + k] * x[k];
+        s = wave_sum(s);
+        const double xi = ((i == c ? 1.0 : 0.0) - s) / L[(size_t)i * n + i];
+        if (lane == 0) {
+            x[i] = xi;
+            X[(size_t)i * n + c] = xi;
+        }
+        __syncthreads();
     }
 }
 
@@ -103,7 +123,8 @@ hipError_t ace_cholesky(const double* A, int n, double* L, int* flag, hipStream_
 }
 
 hipError_t ace_trtri(const double* L, int n, double* X, hipStream_t s) {
-    hipLaunchKernelGGL(k_trtri_lower, dim3((n + 63) / 64), dim3(64), 0, s, L, n, X);
+    if (n > TR_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_trtri_lower, dim3(n), dim3(64), 0, s, L, n, X);
     return hipGetLastError();
 }
 
