@@ -11,7 +11,9 @@ same shapes stand in for them):
 
 * ``n_mol`` "molecules": oxygen centres drawn by random sequential addition
   (uniform proposals in the periodic cube [0, L)^3, accepted when the
-  minimum-image distance to every earlier centre is >= d_min).
+  minimum-image distance to every earlier centre is >= d_min, by default
+  4.7 bohr scaled with the mean spacing L / n_mol^(1/3) relative to 64
+  molecules in 23.5 bohr).
 * 4 localized orbitals per molecule (a water molecule has 4 doubly occupied
   valence orbitals), centred at O + 1.0 bohr along a direction drawn uniformly
   on the sphere (a normalized standard-normal 3-vector), wrapped into [0, L).
@@ -88,8 +90,10 @@ def make_centres(n_mol: int, L: float, N: int, seed: int,
                  dmin: float | None = None) -> Cell:
     """Draw O centres, orbital centres and a-vectors (no grid work)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    if dmin is None:
-        dmin = REF_DMIN * L / REF_L
+    if dmin is None:  # same packing fraction as 64 molecules in REF_L with REF_DMIN
+        cb = n_mol ** (1.0 / 3.0)
+        cb = float(round(cb)) if abs(cb - round(cb)) < 1e-9 else cb
+        dmin = REF_DMIN * L / REF_L * (4.0 / cb)
     o = _rsa(rng, n_mol, L, dmin)
     dirs = rng.standard_normal((n_mol, 4, 3))
     dirs /= np.linalg.norm(dirs, axis=2, keepdims=True)
