@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--other-forms", action="store_true", help="also time one V_xx action of every other form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-eps-rule", action="store_true", help="skip the eps-driven-domain context measurement")
     ap.add_argument("--tune-pairs", type=int, default=2048, help="pairs sampled by the CG kernel autotuner")
     ap.add_argument("--cg-variant", default=None,
                     help="fixed FP32 CG kernel variant (skips the autotuner; for profiling runs)")
@@ -234,6 +235,33 @@ def main():
             log(f"form {fname}: {forms[fname]['vxx_ms_per_call']:.1f} ms, iters {forms[fname]['cg_iters_mean']:.1f}")
             del ws2
             c2.close()
+    # the paper's own truncation (eps-driven boxes, Eq. 16-17) on the same cell, for
+    # context: eps = 10^-3.5 (the paper's production setting), delta = eps, boxes
+    # grown by 6 points, FP32 state, multipole start
+    eps_rule = None
+    if not args.no_eps_rule:
+        ce = make_ctx("multipole-f32")
+        eps = 10 ** -3.5
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pe, _ = ce.build_pairs_eps(phi, cell.N, cell.L, eps, eps, pad=6)
+        t_pairs = 1000 * (time.perf_counter() - t1)
+        wse = ce.workspace(ce.exx_workspace_bytes(cell.N, cell.L, cell.n_occ, pe))
+        ce.autotune([(phi, cell.N, cell.L, pe)], sample_pairs=args.tune_pairs, iters=20, ws=wse)
+        re_ = ce.exx_action(phi, cell.N, cell.L, pe, ws=wse, W=W, exx_dev=exx_dev, want_host=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ce.exx_action(phi, cell.N, cell.L, pe, ws=wse, W=W, exx_dev=exx_dev, want_host=False)
+        torch.cuda.synchronize()
+        se = ce.stage_times()
+        eps_rule = {"eps": eps, "delta": eps, "pad": 6, "form": "multipole-f32", "n_pairs": int(len(pe)),
+                    "mean_box_points": float(np.prod(pe["n"].astype(np.float64), axis=1).mean()),
+                    "pair_build_ms": t_pairs, "vxx_ms_per_call": 1000 * (time.perf_counter() - t1),
+                    "cg_ms": se["cg"], "cg_iters_mean": float(re_[2]["iters"].mean()), "E_xx": re_[1],
+                    "dE_vs_cube_rule_oracle": (re_[1] - golden["E"]) if golden else None}
+        log(f"eps rule: {len(pe)} pairs, {eps_rule['vxx_ms_per_call']:.1f} ms, dE {eps_rule['dE_vs_cube_rule_oracle']}")
+        del wse
+        ce.close()
     out = {
         "metric": "V_xx action ms/call + pair Poisson solves/s, 64-mol cell, learned vs plain",
         "value": n_pairs * args.steps / dt,
@@ -259,6 +287,7 @@ def main():
                    "cg_iters_total": int(stats["iters"].sum())},
         "forms": forms,
         "ace_precision": ace,
+        "eps_rule": eps_rule,
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": cg_bytes,

@@ -141,6 +141,28 @@ sea_status sea_build_pairs(const sea_grid *grid, int n_occ, const double *center
                            double r_pair, double half_width, sea_pair *out, int cap,
                            int *n_out);
 
+/* The paper's own truncation (Sec. II.B, Eq. 16-17), device part.  Each
+ * orbital's box Omega_ii holds >= 1 - eps of |phi_i|^2: per axis, the
+ * shortest cyclic run of grid indices whose marginal mass is >= (1 - eps/3)
+ * of the total (ties: largest mass, then smallest start), so the mass
+ * outside the product box is <= eps.  Pair boxes are Omega_ii intersect
+ * Omega_jj per axis (the longer piece if the runs overlap twice); a pair
+ * (i <= j) is kept when its box is non-empty and
+ * S_ij = dV sum_box |phi_i phi_j| >= delta (Eq. 17; the paper derives delta
+ * from eps elsewhere, the caller chooses it here).  The box written out, on
+ * which rho_ij is taken and the Poisson equation solved, is Omega_ij grown
+ * by `pad` >= 0 points on each side (at most the cell per axis), which moves
+ * the multipole boundary away from the pair density.  Output in (i, j)
+ * order: lo = box start (boxes may run past the cell edge and wrap), n = box
+ * extents, origin = box centre (lo + (n - 1)/2) h.  s_out (nullable)
+ * receives S_ij (over the unpadded Omega_ij).  phi_dev: n_occ x Ng, F64 or
+ * F32.  Synchronizes.  SEA_E_NOMEM with *n_out = full count when cap is too
+ * small. */
+sea_status sea_eps_workspace_bytes(sea_ctx *ctx, const sea_grid *grid, int n_occ, size_t *bytes);
+sea_status sea_build_pairs_eps(sea_ctx *ctx, const sea_grid *grid, int n_occ, const void *phi_dev,
+                               sea_dtype phi_dtype, double eps, double delta, int pad, void *ws_dev,
+                               size_t ws_bytes, sea_pair *out, double *s_out, int cap, int *n_out);
+
 /* Device workspace needed by sea_exx_action / sea_exx_pair_solve for this
  * pair list (bytes, 256-byte aligned). */
 sea_status sea_exx_workspace_bytes(sea_ctx *ctx, const sea_grid *grid, int n_occ, int n_pairs,

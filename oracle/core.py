@@ -64,6 +64,8 @@ def _load():
         lib.orc_exx.argtypes = [P(i32), P(d), i, P(d), i, P(i32), P(d), i, i, d, i, i,
                                 P(d), P(d), P(i32), P(d), P(d)]
         lib.orc_cholesky.argtypes = [i, P(d), P(d)]
+        lib.orc_eps_boxes.argtypes = [P(i32), i, P(d), d, P(i32), P(i32)]
+        lib.orc_eps_pairs.argtypes = [P(i32), P(d), i, P(d), P(i32), P(i32), d, i, i, P(i32), P(d), P(d), P(i)]
         _lib = lib
     return _lib
 
@@ -126,6 +128,42 @@ def build_pairs(N, L, centres, r_pair=6.0, half_width=6.0) -> PairList:
         raise ValueError(f"orc_build_pairs failed ({st})")
     k = cnt.value
     return PairList(out[:k, 0:2].copy(), out[:k, 2:5].copy(), out[:k, 5:8].copy(), org[:k].copy())
+
+
+def eps_boxes(phi, N, eps):
+    """Orbital boxes at 1 - eps coverage (Eq. 16): (lo, len), each (n_occ, 3)."""
+    lib = _load()
+    N3, _ = _grid(N, 1.0)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    n_occ = phi.shape[0]
+    lo = np.zeros((n_occ, 3), dtype=np.int32)
+    ln = np.zeros((n_occ, 3), dtype=np.int32)
+    st = lib.orc_eps_boxes(_ip(N3), n_occ, _dp(phi), eps, _ip(lo), _ip(ln))
+    if st != 0:
+        raise ValueError(f"orc_eps_boxes failed ({st})")
+    return lo, ln
+
+
+def eps_pairs(phi, N, L, lo, ln, delta, pad=0):
+    """Pair boxes Omega_ii ∩ Omega_jj screened by S_ij >= delta (Eq. 17),
+    written out grown by ``pad`` points a side: (PairList, S)."""
+    lib = _load()
+    N3, L3 = _grid(N, L)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    n_occ = phi.shape[0]
+    cap = n_occ * (n_occ + 1) // 2
+    out = np.zeros((max(cap, 1), 8), dtype=np.int32)
+    org = np.zeros((max(cap, 1), 3))
+    S = np.zeros(max(cap, 1))
+    cnt = C.c_int(0)
+    st = lib.orc_eps_pairs(_ip(N3), _dp(L3), n_occ, _dp(phi), _ip(np.ascontiguousarray(lo, dtype=np.int32)),
+                           _ip(np.ascontiguousarray(ln, dtype=np.int32)), delta, int(pad), cap, _ip(out), _dp(org),
+                           _dp(S),
+                           C.byref(cnt))
+    if st != 0:
+        raise ValueError(f"orc_eps_pairs failed ({st})")
+    k = cnt.value
+    return PairList(out[:k, 0:2].copy(), out[:k, 2:5].copy(), out[:k, 5:8].copy(), org[:k].copy()), S[:k].copy()
 
 
 def real_ylm(lmax: int, v) -> np.ndarray:

@@ -30,6 +30,9 @@
  *              (Eq. 8 over ordered pairs);
  *   action     W_i += v phi_j and, for i != j, W_j += v phi_i on the pair
  *              domain (Eq. 13-14);
+ *   eps rule   orbital boxes at 1 - eps coverage, pair boxes as their
+ *              intersection, pairs screened by the absolute overlap
+ *              (Eq. 16-17; readings at orc_eps_boxes);
  *   Cholesky   unblocked lower Cholesky of the symmetrized M (Eq. 18, App. A).
  *
  * Grid: point (ix,iy,iz) at (ix*hx, iy*hy, iz*hz), x fastest.  Orbital arrays
@@ -317,6 +320,148 @@ done:
 static inline int orc_wrap(int k, int N) {
     int m = k % N;
     return m < 0 ? m + N : m;
+}
+
+/* ---- epsilon-driven domains and pair screening (Eq. 16-17) --------------
+ *
+ * Omega_ii (Eq. 16) is a box on the grid that holds at least 1 - eps of
+ * |phi_i|^2.  Reading: per axis, the shortest cyclic run of grid indices
+ * whose marginal mass (sum of |phi_i|^2 over the other two axes) is at least
+ * (1 - eps/3) of the orbital's total; among runs of that length the one with
+ * the largest mass, then the smallest start.  The mass outside the product
+ * box is at most the sum of the three per-axis tails, i.e. at most eps.
+ * lo_out[3i+a] in [0, N[a]), len_out[3i+a] in [1, N[a]]. */
+int orc_eps_boxes(const int32_t *N, int n_occ, const double *phi, double eps, int32_t *lo_out,
+                  int32_t *len_out) {
+    if (n_occ < 0 || !(eps >= 0.0) || !(eps < 1.0)) return -1;
+    const size_t Ng = (size_t)N[0] * N[1] * N[2];
+    int nmax = N[0] > N[1] ? N[0] : N[1];
+    nmax = nmax > N[2] ? nmax : N[2];
+    double *m = (double *)malloc(sizeof(double) * nmax);
+    if (!m) return -3;
+    for (int i = 0; i < n_occ; ++i) {
+        const double *f = phi + (size_t)i * Ng;
+        for (int a = 0; a < 3; ++a) {
+            for (int k = 0; k < N[a]; ++k) m[k] = 0.0;
+            for (int iz = 0; iz < N[2]; ++iz)
+                for (int iy = 0; iy < N[1]; ++iy)
+                    for (int ix = 0; ix < N[0]; ++ix) {
+                        const double v = f[((size_t)iz * N[1] + iy) * N[0] + ix];
+                        const int k = a == 0 ? ix : (a == 1 ? iy : iz);
+                        m[k] += v * v;
+                    }
+            double T = 0.0;
+            for (int k = 0; k < N[a]; ++k) T += m[k];
+            const double target = (1.0 - eps / 3.0) * T;
+            int best_s = 0, best_len = N[a];
+            for (int len = 1; len < N[a]; ++len) {
+                int found = 0;
+                double best_mass = -1.0;
+                for (int s0 = 0; s0 < N[a]; ++s0) {
+                    double mass = 0.0;
+                    for (int t = 0; t < len; ++t) mass += m[(s0 + t) % N[a]];
+                    if (mass >= target && mass > best_mass) {
+                        best_mass = mass;
+                        best_s = s0;
+                        found = 1;
+                    }
+                }
+                if (found) {
+                    best_len = len;
+                    break;
+                }
+            }
+            if (best_len == N[a]) best_s = 0;
+            lo_out[3 * i + a] = best_s;
+            len_out[3 * i + a] = best_len;
+        }
+    }
+    free(m);
+    return 0;
+}
+
+/* Intersection of two cyclic index runs [a, a+la) and [b, b+lb) on Z_N.
+ * A run of length N is the whole axis.  When the intersection has two
+ * pieces (runs longer than half the axis), the longer piece is kept (the
+ * first one on a tie).  Returns the length (0 if empty) and the start,
+ * unwrapped so that it lies in [a, a + la). */
+static int orc_cyc_intersect(int a, int la, int b, int lb, int N, int *start) {
+    if (la >= N) {
+        *start = b;
+        return lb;
+    }
+    if (lb >= N) {
+        *start = a;
+        return la;
+    }
+    int best = 0;
+    for (int k = -1; k <= 1; ++k) {
+        const int s = a > b + k * N ? a : b + k * N;
+        const int e = a + la < b + k * N + lb ? a + la : b + k * N + lb;
+        if (e - s > best) {
+            best = e - s;
+            *start = s;
+        }
+    }
+    return best;
+}
+
+/* Pair domains Omega_ij = Omega_ii intersect Omega_jj and pair screening
+ * (Eq. 17): keep (i <= j) when the intersection is non-empty on every axis
+ * and S_ij = h^3 sum over Omega_ij of |phi_i phi_j| >= delta (wrapped
+ * indices).  The box written out (where rho_ij is taken and the Poisson
+ * equation solved) is Omega_ij grown by `pad` points on each side, at most
+ * the cell per axis (reading: the paper leaves the margin between the pair
+ * density and the multipole boundary open).  Output as orc_build_pairs,
+ * plus S per kept pair; the multipole origin is the box centre,
+ * (lo + (n - 1)/2) h per axis. */
+int orc_eps_pairs(const int32_t *N, const double *L, int n_occ, const double *phi, const int32_t *lo,
+                  const int32_t *len, double delta, int pad, int cap, int32_t *pairs_out, double *origin_out,
+                  double *s_out, int *n_out) {
+    if (n_occ < 0) return -1;
+    const size_t Ng = (size_t)N[0] * N[1] * N[2];
+    double h[3];
+    for (int a = 0; a < 3; ++a) h[a] = L[a] / N[a];
+    const double dV = h[0] * h[1] * h[2];
+    int cnt = 0;
+    for (int i = 0; i < n_occ; ++i) {
+        for (int j = i; j < n_occ; ++j) {
+            int st[3] = {0, 0, 0}, n[3], empty = 0;
+            for (int a = 0; a < 3; ++a) {
+                n[a] = orc_cyc_intersect(lo[3 * i + a], len[3 * i + a], lo[3 * j + a], len[3 * j + a], N[a], &st[a]);
+                if (n[a] == 0) empty = 1;
+            }
+            if (empty) continue;
+            double S = 0.0;
+            for (int z = 0; z < n[2]; ++z)
+                for (int y = 0; y < n[1]; ++y)
+                    for (int x = 0; x < n[0]; ++x) {
+                        const size_t g = ((size_t)orc_wrap(st[2] + z, N[2]) * N[1] + orc_wrap(st[1] + y, N[1])) * N[0] +
+                                         orc_wrap(st[0] + x, N[0]);
+                        S += fabs(phi[(size_t)i * Ng + g] * phi[(size_t)j * Ng + g]);
+                    }
+            S *= dV;
+            if (!(S >= delta)) continue;
+            if (cnt < cap) {
+                int32_t *o = pairs_out + 8 * cnt;
+                o[0] = i;
+                o[1] = j;
+                for (int a = 0; a < 3; ++a) {
+                    /* solve box: Omega_ij grown by pad points a side, at most the cell */
+                    int np = n[a] + 2 * pad;
+                    if (np > N[a]) np = N[a];
+                    const int sp = st[a] - (np - n[a]) / 2;
+                    o[2 + a] = sp;
+                    o[5 + a] = np;
+                    origin_out[3 * cnt + a] = (sp + 0.5 * (np - 1)) * h[a];
+                }
+                s_out[cnt] = S;
+            }
+            ++cnt;
+        }
+    }
+    *n_out = cnt;
+    return cnt > cap ? -2 : 0;
 }
 
 /* v_out: n0*n1*n2 interior potential.  info (8 doubles): iterations,

@@ -420,8 +420,9 @@ __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
         __syncthreads();
         if (threadIdx.x == 0) pid_sh = atomicAdd(a.queue_ctr, 1);
         __syncthreads();
-        const int pid = pid_sh;
-        if (pid >= a.n_pairs) break;
+        const int qi = pid_sh;
+        if (qi >= a.n_pairs) break;
+        const int pid = a.order ? a.order[qi] : qi;  // largest domains first
         solve_pair<T, NT, COLS, PREFETCH, DEPTH, BUF>(a, pid, lds, red, cc, rr, pp, r64);
     }
 }

@@ -389,7 +389,8 @@ __global__ __launch_bounds__(CG_BS) void k_cg_f64(ExxArgs a) {
     double* p = r + a.stride;
     double* q = p + a.stride;
     const double tol2 = a.rel_tol * a.rel_tol;
-    for (int pid = blockIdx.x; pid < a.n_pairs; pid += gridDim.x) {
+    for (int qi = blockIdx.x; qi < a.n_pairs; qi += gridDim.x) {
+        const int pid = a.order ? a.order[qi] : qi;  // largest domains first
         const DevCell& C = a.cells[a.pair_cell[pid]];
         const StencilW w = make_weights(C.h);
         const sea_pair P = a.pairs[pid];

@@ -1,5 +1,6 @@
 // C ABI of libsea: argument validation, workspace layout, orchestration of
 // the exx kernels on the caller's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -93,6 +94,7 @@ struct CellSet {
     std::vector<int> csr_off;
     std::vector<int2> csr_ent;
     std::vector<DevCell> dev;
+    std::vector<int> order;  // CG queue: pair ids by decreasing interior size (ties: id order)
     bool cubic = true;
 };
 
@@ -154,6 +156,11 @@ static sea_status build_cellset(sea_ctx* ctx, int n_cells, const sea_cell* cells
         S.dev.push_back(D);
     }
     if ((long long)S.pairs.size() > (1LL << 30)) return fail(ctx, SEA_E_ARG, "too many pairs");
+    // longest-processing-time-first queue for the persistent CG kernels
+    S.order.resize(S.pairs.size());
+    for (size_t k = 0; k < S.pairs.size(); ++k) S.order[k] = (int)k;
+    auto vol = [&](int k) { return (long long)S.pairs[k].n[0] * S.pairs[k].n[1] * S.pairs[k].n[2]; };
+    std::stable_sort(S.order.begin(), S.order.end(), [&](int x, int y) { return vol(x) > vol(y); });
     return SEA_OK;
 }
 
@@ -187,6 +194,7 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     const size_t nc = S.cells.size();
     L.pairs = take(np * sizeof(sea_pair));
     L.pair_cell = take(np * sizeof(int));
+    L.order = take(np * sizeof(int));
     L.cells = take(nc * sizeof(DevCell));
     L.partial = take(np * L.n_chunks * SEA_NACC * sizeof(double));
     L.mom = take(np * SEA_NACC * sizeof(double));
@@ -416,6 +424,7 @@ static sea_status exx_upload(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly
     if (np) {
         SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.pairs, S.pairs.data(), sizeof(sea_pair) * np, hipMemcpyHostToDevice, s));
         SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.pair_cell, S.pair_cell.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.order, S.order.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
     }
     SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.cells, S.dev.data(), sizeof(DevCell) * S.dev.size(), hipMemcpyHostToDevice, s));
     if (!S.csr_off.empty())
@@ -433,6 +442,7 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.n_pairs = (int)S.pairs.size();
     a.cells = (const DevCell*)(base + Ly.cells);
     a.pair_cell = (const int*)(base + Ly.pair_cell);
+    a.order = S.pairs.empty() ? nullptr : (const int*)(base + Ly.order);
     a.n_cells = (int)S.cells.size();
     a.partial = (double*)(base + Ly.partial);
     a.n_chunks = Ly.n_chunks;
@@ -949,6 +959,157 @@ sea_status sea_ace_energy(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, co
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// epsilon-driven domains and pair screening (Eq. 16-17)
+
+namespace {
+
+// Shortest cyclic run of m[0..N) with mass >= target; among runs of that
+// length the largest mass, then the smallest start.  Direct sums, in the
+// order the runs are listed.
+void eps_run(const double* m, int N, double eps, int* lo, int* len) {
+    double T = 0.0;
+    for (int k = 0; k < N; ++k) T += m[k];
+    const double target = (1.0 - eps / 3.0) * T;
+    for (int ln = 1; ln < N; ++ln) {
+        double best = -1.0;
+        int bs = -1;
+        for (int s0 = 0; s0 < N; ++s0) {
+            double mass = 0.0;
+            for (int t = 0; t < ln; ++t) mass += m[(s0 + t) % N];
+            if (mass >= target && mass > best) {
+                best = mass;
+                bs = s0;
+            }
+        }
+        if (bs >= 0) {
+            *lo = bs;
+            *len = ln;
+            return;
+        }
+    }
+    *lo = 0;
+    *len = N;
+}
+
+// Intersection of cyclic runs [a, a+la) and [b, b+lb) on Z_N; the longer
+// piece when there are two; start unwrapped into [a, a+la).
+int cyc_intersect(int a, int la, int b, int lb, int N, int* start) {
+    if (la >= N) {
+        *start = b;
+        return lb;
+    }
+    if (lb >= N) {
+        *start = a;
+        return la;
+    }
+    int best = 0;
+    for (int k = -1; k <= 1; ++k) {
+        const int s0 = std::max(a, b + k * N);
+        const int e0 = std::min(a + la, b + k * N + lb);
+        if (e0 - s0 > best) {
+            best = e0 - s0;
+            *start = s0;
+        }
+    }
+    return best;
+}
+
+}  // namespace
+
+extern "C" sea_status sea_eps_workspace_bytes(sea_ctx* ctx, const sea_grid* grid, int n_occ, size_t* bytes) {
+    if (!ctx || !bytes) return SEA_E_ARG;
+    sea_status st = check_grid(ctx, grid);
+    if (st != SEA_OK) return st;
+    if (n_occ < 1) return fail(ctx, SEA_E_ARG, "n_occ < 1");
+    const int nmax = std::max(grid->n[0], std::max(grid->n[1], grid->n[2]));
+    const size_t np = (size_t)n_occ * (n_occ + 1) / 2;
+    *bytes = align_up((size_t)n_occ * 3 * nmax * sizeof(double)) + align_up(np * sizeof(sea_pair)) +
+             align_up(np * sizeof(double));
+    return SEA_OK;
+}
+
+extern "C" sea_status sea_build_pairs_eps(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev,
+                                          sea_dtype phi_dtype, double eps, double delta, int pad, void* ws_dev,
+                                          size_t ws_bytes, sea_pair* out, double* s_out, int cap, int* n_out) {
+    if (!ctx) return SEA_E_ARG;
+    size_t need = 0;
+    sea_status st = sea_eps_workspace_bytes(ctx, grid, n_occ, &need);
+    if (st != SEA_OK) return st;
+    if (!phi_dev || !ws_dev || !n_out || (cap > 0 && !out)) return fail(ctx, SEA_E_ARG, "NULL argument");
+    if (phi_dtype != SEA_F64 && phi_dtype != SEA_F32) return fail(ctx, SEA_E_ARG, "phi_dtype must be F64 or F32");
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(ctx, SEA_E_ARG, "eps must be in [0, 1)");
+    if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(ctx, SEA_E_ARG, "delta must be >= 0");
+    if (pad < 0) return fail(ctx, SEA_E_ARG, "pad must be >= 0");
+    if (ws_bytes < need) return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    const int N[3] = {grid->n[0], grid->n[1], grid->n[2]};
+    double h[3];
+    for (int a = 0; a < 3; ++a) h[a] = grid->L[a] / N[a];
+    const double dV = h[0] * h[1] * h[2];
+    const int nmax = std::max(N[0], std::max(N[1], N[2]));
+    const size_t np_max = (size_t)n_occ * (n_occ + 1) / 2;
+    char* base = (char*)ws_dev;
+    double* m_dev = (double*)base;
+    sea_pair* cand_dev = (sea_pair*)(base + align_up((size_t)n_occ * 3 * nmax * sizeof(double)));
+    double* S_dev = (double*)((char*)cand_dev + align_up(np_max * sizeof(sea_pair)));
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    const int f32 = phi_dtype == SEA_F32;
+    // 1. per-orbital, per-axis marginals of |phi|^2; boxes on the host
+    SEA_HIP_CHECK(ctx, launch_eps_marginals(phi_dev, f32, N, n_occ, nmax, m_dev, s));
+    std::vector<double> m((size_t)n_occ * 3 * nmax);
+    SEA_HIP_CHECK(ctx, hipMemcpyAsync(m.data(), m_dev, m.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+    std::vector<int> lo((size_t)n_occ * 3), ln((size_t)n_occ * 3);
+    for (int o = 0; o < n_occ; ++o)
+        for (int a = 0; a < 3; ++a)
+            eps_run(&m[((size_t)o * 3 + a) * nmax], N[a], eps, &lo[3 * o + a], &ln[3 * o + a]);
+    // 2. candidate pairs: non-empty box intersection on every axis
+    std::vector<sea_pair> cand;
+    for (int i = 0; i < n_occ; ++i)
+        for (int j = i; j < n_occ; ++j) {
+            sea_pair p{};
+            p.i = i;
+            p.j = j;
+            bool empty = false;
+            for (int a = 0; a < 3 && !empty; ++a) {
+                int st0 = 0;
+                p.n[a] = cyc_intersect(lo[3 * i + a], ln[3 * i + a], lo[3 * j + a], ln[3 * j + a], N[a], &st0);
+                p.lo[a] = st0;
+                p.origin[a] = (st0 + 0.5 * (p.n[a] - 1)) * h[a];
+                empty = p.n[a] == 0;
+            }
+            if (!empty) cand.push_back(p);
+        }
+    // 3. absolute overlaps on the device, screening on the host
+    std::vector<double> S(cand.size());
+    if (!cand.empty()) {
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(cand_dev, cand.data(), cand.size() * sizeof(sea_pair),
+                                          hipMemcpyHostToDevice, s));
+        SEA_HIP_CHECK(ctx, launch_eps_overlap(phi_dev, f32, N, dV, cand_dev, (int)cand.size(), S_dev, s));
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(S.data(), S_dev, S.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+    }
+    int cnt = 0;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        if (!(S[k] >= delta)) continue;
+        if (cnt < cap) {
+            sea_pair p = cand[k];
+            for (int a = 0; a < 3; ++a) {  // solve box: Omega_ij grown by pad points a side, at most the cell
+                const int np = std::min(p.n[a] + 2 * pad, N[a]);
+                p.lo[a] -= (np - p.n[a]) / 2;
+                p.n[a] = np;
+                p.origin[a] = (p.lo[a] + 0.5 * (p.n[a] - 1)) * h[a];
+            }
+            out[cnt] = p;
+            if (s_out) s_out[cnt] = S[k];
+        }
+        ++cnt;
+    }
+    *n_out = cnt;
+    if (cnt > cap) return fail(ctx, SEA_E_NOMEM, "pair capacity %d < %d pairs", cap, cnt);
+    return SEA_OK;
+}
 
 // ---------------------------------------------------------------------------
 // autotuner of the FP32-state CG kernel

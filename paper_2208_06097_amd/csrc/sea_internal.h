@@ -57,7 +57,7 @@ struct StageTimer {
 
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
-    size_t pairs, pair_cell, cells, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, counter;
+    size_t pairs, pair_cell, order, cells, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, counter;
     size_t nnx, nny, nnact, total;
     size_t gstride;
     int nmax;
@@ -105,6 +105,7 @@ struct ExxArgs {
     int max_iter;
     int lmax;
     int* queue_ctr;       // persistent-kernel pair counter (zeroed before the CG launch)
+    const int* order;     // CG queue order: pair ids by decreasing domain size (nullable)
     int x_nonzero;        // v holds a start guess on entry to the CG
     double* bres;         // n_pairs x stride: b - A x0 when x_nonzero
     double* gbuf;         // ghost-layer multipole values, n_pairs x gstride
@@ -125,6 +126,10 @@ hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
 // z-marching CG (k_cg.hip): needs every pair with n[0], n[1] <= 64.
 bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h);
 size_t cg_zm_lds_bytes(int state_f32);
+hipError_t launch_eps_marginals(const void* phi, int f32, const int* N, int n_occ, int nmax, double* m,
+                                hipStream_t s);
+hipError_t launch_eps_overlap(const void* phi, int f32, const int* N, double dV, const sea_pair* pairs, int n_pairs,
+                              double* S, hipStream_t s);
 int cg_variant_count();
 const char* cg_variant_name(int v);
 hipError_t launch_cg_zm(const ExxArgs& a, int variant, hipStream_t s);

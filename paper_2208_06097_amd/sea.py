@@ -31,7 +31,7 @@ EXPORTS = [
     "sea_exx_nn_samples", "sea_exx_batched_workspace_bytes", "sea_exx_action_batched",
     "sea_exx_plan_create", "sea_exx_plan_launch", "sea_exx_plan_results", "sea_exx_plan_destroy",
     "sea_cg_variant_count", "sea_cg_variant_name", "sea_exx_autotune",
-    "sea_nn_infer_workspace_bytes", "sea_nn_infer",
+    "sea_nn_infer_workspace_bytes", "sea_nn_infer", "sea_eps_workspace_bytes", "sea_build_pairs_eps",
 ]
 
 # the network's layers (name, c_in, c_out, relu), in parameter order
@@ -147,6 +147,8 @@ def load() -> C.CDLL:
     lib.sea_exx_autotune.argtypes = [vp, i, vp, vp, sz, i, i, vp, P(i)]
     lib.sea_nn_infer_workspace_bytes.argtypes = [vp, i, P(sz)]
     lib.sea_nn_infer.argtypes = [vp, vp, i, vp, vp, vp, sz]
+    lib.sea_eps_workspace_bytes.argtypes = [vp, P(SeaGrid), i, P(sz)]
+    lib.sea_build_pairs_eps.argtypes = [vp, P(SeaGrid), i, vp, i, d, d, i, vp, sz, vp, vp, i, P(i)]
     _lib = lib
     return lib
 
@@ -379,6 +381,24 @@ class Context:
     def exx_plan(self, cells, ws=None):
         """A replayable HIP-graph plan of the batched action (see Plan)."""
         return Plan(self, cells, ws)
+
+    def build_pairs_eps(self, phi, N, L, eps, delta, pad=0):
+        """Pairs and boxes of the epsilon rule (Eq. 16-17), boxes grown by
+        ``pad`` points a side: (pairs, S)."""
+        assert phi.is_cuda and phi.is_contiguous()
+        n_occ = phi.shape[0]
+        g = _grid(N, L)
+        b = C.c_size_t(0)
+        self._check(self.lib.sea_eps_workspace_bytes(self.h, C.byref(g), n_occ, C.byref(b)))
+        ws = self.workspace(b.value)
+        cap = n_occ * (n_occ + 1) // 2
+        out = np.zeros(max(cap, 1), dtype=PAIR_DTYPE)
+        S = np.zeros(max(cap, 1))
+        n = C.c_int(0)
+        self._check(self.lib.sea_build_pairs_eps(self.h, C.byref(g), n_occ, phi.data_ptr(), self._phi_dtype(phi),
+                                                 eps, delta, int(pad), ws.data_ptr(), ws.numel(), out.ctypes.data,
+                                                 S.ctypes.data, cap, C.byref(n)))
+        return out[:n.value].copy(), S[:n.value].copy()
 
     def pair_solve(self, phi, N, L, pairs, ws=None, want_Q=True):
         """Per-pair potentials: returns (v (n_pairs x stride), Q or None, e, stats, status)."""
