@@ -35,15 +35,22 @@ def main():
     ap.add_argument("--cells", type=int, default=200)
     ap.add_argument("--first", type=int, default=0, help="index of the first cell of the recipe")
     ap.add_argument("--group", type=int, default=4, help="cells per plan (memory: about 25 GB per cell)")
-    ap.add_argument("--start", default="multipole", choices=["zero", "multipole"])
+    ap.add_argument("--start", default="multipole", choices=["zero", "multipole", "learned"])
+    ap.add_argument("--weights", default=None, help="network checkpoint for the learned start")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--replays", type=int, default=1, help="timed graph replays per group")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
-    start = sea.SEA_START_MULTIPOLE if args.start == "multipole" else sea.SEA_START_ZERO
+    start = {"zero": sea.SEA_START_ZERO, "multipole": sea.SEA_START_MULTIPOLE,
+             "learned": sea.SEA_START_LEARNED}[args.start]
     ctx = sea.Context(rel_tol=args.tol, stencil_dtype=sea.SEA_F32, start=start)
+    if start == sea.SEA_START_LEARNED:
+        import os
+        w = args.weights or os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_f32cg.npy")
+        net = ctx.nn_state(np.load(w))
+        ctx.nn_attach(net)
     ids = list(range(args.first, args.first + args.cells))
     dens = synth.config3_densities()
     per_cell, tuned = [], None

@@ -12,7 +12,9 @@
 // One CG iteration is two sweeps (8 words of state traffic per point):
 //   A: p = r + beta p (in place), d = <p, A p>           reads r, p; writes p
 //   B: c += alpha p, r -= alpha A p, rr = <r, r>          reads p, c, r; writes c, r
-// where A p is recomputed in B instead of being stored.
+// where A p is recomputed in B instead of being stored.  A start guess
+// enters as the first FP64 residual update, so no separate start-residual
+// pass is needed.
 //
 // Precision: the CG state (c, r, p) is T (double or float), with reliable
 // updates (residual replacement, as in mixed-precision CG of Sleijpen and
@@ -270,7 +272,6 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const int npad = PL * (nz + 1);
     const double* __restrict__ b = a.b + (size_t)pid * a.stride;
-    const double* __restrict__ b0 = a.x_nonzero ? a.bres + (size_t)pid * a.stride : b;
     double* __restrict__ x = a.v + (size_t)pid * a.stride;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const double tol2 = Delta<T>::target * Delta<T>::target * a.rel_tol * a.rel_tol;
@@ -280,23 +281,45 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     const int col0 = ty * 64 + tx;  // column c at col0 + c*TY*64 within a plane
     const SlotIO<T, BUF> io_c(cc, npad, col0), io_r(rr, npad, col0), io_p(pp, npad, col0);
 
-    // r64 = b0 on the padded grid; x = 0 unless a start guess is present
+    // FP64 residual update: r64 -= A c and x += c, one z-march; returns |r64|^2
+    auto refresh = [&]() -> double {
+        double uacc = 0.0;
+        zmarch<T, double, NT, COLS, 1, T, double>(
+            nz, lds, wd, [&](int c, int z) -> T { return io_c.ld(z * PL + c * TY * 64); },
+            [&](int, int, T v) -> T { return v; },
+            [&](int c, int z) -> double { return r64[z * PL + col0 + c * TY * 64]; },
+            [&](int c, int z, double s, T ctr, double rv) {
+                const int id = z * PL + col0 + c * TY * 64;
+                const double rn = (double)msk[c] * (rv - s);
+                r64[id] = rn;
+                uacc += rn * rn;
+                if (msk[c] != T(0)) x[(z * ny + ty + TY * c) * nx + tx] += (double)ctr;
+            });
+        return block_sum<NT>(uacc, red);
+    };
+
+    // r64 = b on the padded grid, x = 0.  A start guess x0 (in x on entry)
+    // enters as the first increment c = (T) x0, so that x and r64 = b - A x
+    // stay consistent in FP64 from the start.
     double bb = 0.0, r2 = 0.0;
     for (int q = threadIdx.x; q < npad; q += NT) {
         const int xx = q & 63, yy = (q >> 6) & 63, zz = q >> 12;
         double rv = 0.0;
+        T c0 = T(0);
         if (xx < nx && yy < ny && zz < nz) {
             const int id = (zz * ny + yy) * nx + xx;
-            const double bv = b[id];
-            bb += bv * bv;
-            rv = b0[id];
-            if (!a.x_nonzero) x[id] = 0.0;
+            rv = b[id];
+            bb += rv * rv;
+            if (a.x_nonzero) c0 = (T)x[id];
+            x[id] = 0.0;
         }
         r64[q] = rv;
+        if (a.x_nonzero) cc[q] = c0;
         r2 += rv * rv;
     }
     bb = block_sum<NT>(bb, red);
     r2 = block_sum<NT>(r2, red);
+    if (a.x_nonzero) r2 = refresh();
 
     int it = 0, conv = 0;
     // inner state from r64: r = (T) r64, c = 0 (p is kept across replacements)
@@ -376,19 +399,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
             continue;
         }
         // reliable update in FP64: r64 -= A c, x += c
-        double uacc = 0.0;
-        zmarch<T, double, NT, COLS, 1, T, double>(
-            nz, lds, wd, [&](int c, int z) -> T { return io_c.ld(z * PL + c * TY * 64); },
-            [&](int, int, T v) -> T { return v; },
-            [&](int c, int z) -> double { return r64[z * PL + col0 + c * TY * 64]; },
-            [&](int c, int z, double s, T ctr, double rv) {
-                const int id = z * PL + col0 + c * TY * 64;
-                const double rn = (double)msk[c] * (rv - s);
-                r64[id] = rn;
-                uacc += rn * rn;
-                if (msk[c] != T(0)) x[(z * ny + ty + TY * c) * nx + tx] += (double)ctr;
-            });
-        r2 = block_sum<NT>(uacc, red);
+        r2 = refresh();
         if (!(r2 == r2)) { conv = -1; break; }
         if (r2 <= tol2 * bb) { conv = 1; break; }
         if (it >= a.max_iter) break;
@@ -398,9 +409,12 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
         rho = r2t;
         rupd = r2;
     }
+    // r64 = b - A x up to the FP64 rounding of the increments: it is the
+    // residual reported for this pair
     if (threadIdx.x == 0) {
         a.stats[pid].iters = it;
         a.stats[pid].converged = conv;
+        a.stats[pid].rel_res = bb > 0.0 ? sqrt(r2 / bb) : 0.0;
     }
 }
 
@@ -427,7 +441,7 @@ __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
     }
 }
 
-// True FP64 residual b - A x and e_ij = dV sum rho x, one workgroup per pair.
+// Pair energy e_ij = dV sum rho x and the final flags, one workgroup per pair.
 constexpr int FIN_BS = 512;
 
 __global__ __launch_bounds__(FIN_BS) void k_cg_finish(ExxArgs a) {
@@ -437,29 +451,20 @@ __global__ __launch_bounds__(FIN_BS) void k_cg_finish(ExxArgs a) {
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const int n = nx * ny * nz, nxy = nx * ny;
-    const double ih2 = 1.0 / (C.h[0] * C.h[0]);
-    const double* b = a.b + (size_t)pid * a.stride;
     const double* x = a.v + (size_t)pid * a.stride;
     const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
-    double bb = 0.0, rr = 0.0, e = 0.0;
+    double e = 0.0;
     for (int id = threadIdx.x; id < n; id += FIN_BS) {
         const int xx = id % nx, yy = (id / nx) % ny, zz = id / nxy;
-        const double r = b[id] - apply_A_global(x, id, xx, yy, zz, nx, ny, nz, ih2);
-        bb += b[id] * b[id];
-        rr += r * r;
         const size_t g = ((size_t)wrap_idx(P.lo[2] + zz, C.N[2]) * C.N[1] + wrap_idx(P.lo[1] + yy, C.N[1])) * C.N[0] +
                          wrap_idx(P.lo[0] + xx, C.N[0]);
         e += load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g) * x[id];
     }
-    bb = block_sum<FIN_BS>(bb, red);
-    rr = block_sum<FIN_BS>(rr, red);
     e = block_sum<FIN_BS>(e, red);
     if (threadIdx.x == 0) {
         DevStat st = a.stats[pid];
-        st.rel_res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-        if (st.converged >= 0 && !(bb > 0.0)) st.converged = 1;
-        else if (st.converged >= 0) st.converged = (st.rel_res <= a.rel_tol) ? 1 : 0;
-        if (!(st.rel_res == st.rel_res)) st.converged = -1;
+        if (st.converged >= 0) st.converged = (st.rel_res <= a.rel_tol) ? 1 : 0;
+        if (!(st.rel_res == st.rel_res) || !(e == e)) st.converged = -1;
         st.e_ij = C.dV * e;
         st.s_abs = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM];
         st.q = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM + 1];

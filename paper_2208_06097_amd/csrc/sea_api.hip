@@ -200,7 +200,10 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.mom = take(np * SEA_NACC * sizeof(double));
     L.b = take(np * stride * sizeof(double));
     L.v = with_v ? take(np * stride * sizeof(double)) : 0;
-    L.bres = ctx->opts.start != SEA_START_ZERO ? take(np * stride * sizeof(double)) : 0;
+    // b - A x0 of a start guess: the generic FP64 kernel only (the FP32 z-march
+    // folds the guess into its first FP64 residual update)
+    L.bres = (ctx->opts.start != SEA_START_ZERO && ctx->opts.stencil_dtype == SEA_F64)
+                 ? take(np * stride * sizeof(double)) : 0;
     L.gbuf = take(np * L.gstride * sizeof(double));
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
@@ -523,7 +526,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                 }
                 SEA_HIP_CHECK(ctx, launch_nn_apply(a, kNnGrid, y32, s));
             }
-            SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
+            if (!zm) SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
             timer_off(SEA_STAGE_GUESS);
         }
         timer_on(SEA_STAGE_CG);
