@@ -260,21 +260,26 @@ def main():
         eps = 10 ** -3.5
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        pe, _ = ce.build_pairs_eps(phi, cell.N, cell.L, eps, eps, pad=6)
+        pe, _, dbe = ce.build_pairs_eps(phi, cell.N, cell.L, eps, eps, pad=6, with_dbox=True)
         t_pairs = 1000 * (time.perf_counter() - t1)
-        wse = ce.workspace(ce.exx_workspace_bytes(cell.N, cell.L, cell.n_occ, pe))
+        wse = ce.workspace(ce.exx_batched_workspace_bytes([(phi, cell.N, cell.L, pe, W, exx_dev, dbe)]))
         ce.autotune([(phi, cell.N, cell.L, pe)], sample_pairs=args.tune_pairs, iters=20, ws=wse)
-        re_ = ce.exx_action(phi, cell.N, cell.L, pe, ws=wse, W=W, exx_dev=exx_dev, want_host=True)
+        re_ = ce.exx_action(phi, cell.N, cell.L, pe, ws=wse, W=W, exx_dev=exx_dev, want_host=True, dbox=dbe)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        ce.exx_action(phi, cell.N, cell.L, pe, ws=wse, W=W, exx_dev=exx_dev, want_host=False)
+        ce.exx_action(phi, cell.N, cell.L, pe, ws=wse, W=W, exx_dev=exx_dev, want_host=False, dbox=dbe)
         torch.cuda.synchronize()
         se = ce.stage_times()
+        _, _, xi_e, _ = ctx.ace_build(phi, W, dV, ws=ws_ace)
+        E_ace_eps = ctx.ace_energy(phi, xi_e, dV, ws=ws_ace)
+        del xi_e
         eps_rule = {"eps": eps, "delta": eps, "pad": 6, "form": "multipole-f32", "n_pairs": int(len(pe)),
                     "mean_box_points": float(np.prod(pe["n"].astype(np.float64), axis=1).mean()),
                     "pair_build_ms": t_pairs, "vxx_ms_per_call": 1000 * (time.perf_counter() - t1),
                     "cg_ms": se["cg"], "cg_iters_mean": float(re_[2]["iters"].mean()), "E_xx": re_[1],
-                    "dE_vs_cube_rule_oracle": (re_[1] - golden["E"]) if golden else None}
+                    "dE_vs_cube_rule_oracle": (re_[1] - golden["E"]) if golden else None,
+                    "W_boxes": "Omega^D joined with the pair domain",
+                    "E_ace": E_ace_eps, "dE_ace_vs_cube_rule_oracle": (E_ace_eps - golden["E"]) if golden else None}
         log(f"eps rule: {len(pe)} pairs, {eps_rule['vxx_ms_per_call']:.1f} ms, dE {eps_rule['dE_vs_cube_rule_oracle']}")
         del wse
         ce.close()

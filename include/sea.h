@@ -155,13 +155,19 @@ sea_status sea_build_pairs(const sea_grid *grid, int n_occ, const double *center
  * the multipole boundary away from the pair density.  Output in (i, j)
  * order: lo = box start (boxes may run past the cell edge and wrap), n = box
  * extents, origin = box centre (lo + (n - 1)/2) h.  s_out (nullable)
- * receives S_ij (over the unpadded Omega_ij).  phi_dev: n_occ x Ng, F64 or
- * F32.  Synchronizes.  SEA_E_NOMEM with *n_out = full count when cap is too
- * small. */
+ * receives S_ij (over the unpadded Omega_ij).  dbox_out (nullable, 12 int32
+ * per pair) receives the paper's Omega^D boxes for sea_cell.dbox_host: for
+ * W_i the box of phi_j (i != j) or Omega_ii doubled about its centre
+ * (i == j, at most the cell), for W_j the box of phi_i, each shifted by a
+ * multiple of the cell to lie nearest the pair's domain and grown to cover
+ * that domain (so W takes the pair wherever e_ij does; at most the cell).  phi_dev:
+ * n_occ x Ng, F64 or F32.  Synchronizes.  SEA_E_NOMEM with *n_out = full
+ * count when cap is too small. */
 sea_status sea_eps_workspace_bytes(sea_ctx *ctx, const sea_grid *grid, int n_occ, size_t *bytes);
 sea_status sea_build_pairs_eps(sea_ctx *ctx, const sea_grid *grid, int n_occ, const void *phi_dev,
                                sea_dtype phi_dtype, double eps, double delta, int pad, void *ws_dev,
-                               size_t ws_bytes, sea_pair *out, double *s_out, int cap, int *n_out);
+                               size_t ws_bytes, sea_pair *out, double *s_out, int32_t *dbox_out, int cap,
+                               int *n_out);
 
 /* Device workspace needed by sea_exx_action / sea_exx_pair_solve for this
  * pair list (bytes, 256-byte aligned). */
@@ -198,6 +204,13 @@ typedef struct {
     const sea_pair *pairs_host;
     double *W_dev;
     double *exx_dev;
+    /* Nullable: n_pairs x 12 int32, for pair k the box where W_i takes v_ij
+     * phi_j (lo[3], n[3]) and then the box where W_j takes v_ij phi_i, both in
+     * the unwrapped frame of the pair's domain; v_ij outside the domain is the
+     * multipole potential (Eq. 10).  This is the paper's Omega^D (end of
+     * Sec. II.B); sea_build_pairs_eps writes it.  NULL: both boxes are the
+     * pair's domain (Eq. 13-14 on the domain). */
+    const int32_t *dbox_host;
 } sea_cell;
 
 /* Workspace for sea_exx_action_batched / a plan over these cells. */

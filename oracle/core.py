@@ -61,11 +61,12 @@ def _load():
         lib.orc_cg.argtypes = [P(i32), P(d), i, P(d), P(d), d, i, P(d)]
         lib.orc_pair_potential.argtypes = [P(i32), P(d), i, P(d), P(i32), P(d), i, i, d, i,
                                            P(d), P(d), P(d), P(d)]
-        lib.orc_exx.argtypes = [P(i32), P(d), i, P(d), i, P(i32), P(d), i, i, d, i, i,
+        lib.orc_exx.argtypes = [P(i32), P(d), i, P(d), i, P(i32), P(d), P(i32), i, i, d, i, i,
                                 P(d), P(d), P(i32), P(d), P(d)]
         lib.orc_cholesky.argtypes = [i, P(d), P(d)]
         lib.orc_eps_boxes.argtypes = [P(i32), i, P(d), d, P(i32), P(i32)]
-        lib.orc_eps_pairs.argtypes = [P(i32), P(d), i, P(d), P(i32), P(i32), d, i, i, P(i32), P(d), P(d), P(i)]
+        lib.orc_eps_pairs.argtypes = [P(i32), P(d), i, P(d), P(i32), P(i32), d, i, i, P(i32), P(d), P(d),
+                                      P(i32), P(i)]
         _lib = lib
     return _lib
 
@@ -144,9 +145,10 @@ def eps_boxes(phi, N, eps):
     return lo, ln
 
 
-def eps_pairs(phi, N, L, lo, ln, delta, pad=0):
+def eps_pairs(phi, N, L, lo, ln, delta, pad=0, with_dbox=False):
     """Pair boxes Omega_ii ∩ Omega_jj screened by S_ij >= delta (Eq. 17),
-    written out grown by ``pad`` points a side: (PairList, S)."""
+    written out grown by ``pad`` points a side: (PairList, S) or, with
+    ``with_dbox``, (PairList, S, dbox) with the boxes where W takes each pair."""
     lib = _load()
     N3, L3 = _grid(N, L)
     phi = np.ascontiguousarray(phi, dtype=np.float64)
@@ -155,15 +157,16 @@ def eps_pairs(phi, N, L, lo, ln, delta, pad=0):
     out = np.zeros((max(cap, 1), 8), dtype=np.int32)
     org = np.zeros((max(cap, 1), 3))
     S = np.zeros(max(cap, 1))
+    db = np.zeros((max(cap, 1), 12), dtype=np.int32)
     cnt = C.c_int(0)
     st = lib.orc_eps_pairs(_ip(N3), _dp(L3), n_occ, _dp(phi), _ip(np.ascontiguousarray(lo, dtype=np.int32)),
                            _ip(np.ascontiguousarray(ln, dtype=np.int32)), delta, int(pad), cap, _ip(out), _dp(org),
-                           _dp(S),
-                           C.byref(cnt))
+                           _dp(S), _ip(db), C.byref(cnt))
     if st != 0:
         raise ValueError(f"orc_eps_pairs failed ({st})")
     k = cnt.value
-    return PairList(out[:k, 0:2].copy(), out[:k, 2:5].copy(), out[:k, 5:8].copy(), org[:k].copy()), S[:k].copy()
+    pl = PairList(out[:k, 0:2].copy(), out[:k, 2:5].copy(), out[:k, 5:8].copy(), org[:k].copy())
+    return (pl, S[:k].copy(), db[:k].copy()) if with_dbox else (pl, S[:k].copy())
 
 
 def real_ylm(lmax: int, v) -> np.ndarray:
@@ -245,8 +248,11 @@ class ExxResult:
 
 
 def exx(phi, N, L, pairs: PairList, tol=1e-12, max_iter=10000, M=FD_HALF_ORDER, lmax=LMAX,
-        n_threads=0) -> ExxResult:
-    """The whole V_xx action: W = D_xx (Eq. 13-14 on the pair domains), E (Eq. 8)."""
+        n_threads=0, dbox=None) -> ExxResult:
+    """The whole V_xx action: W = D_xx (Eq. 13-14), E (Eq. 8).  W is taken on
+    the pair domains, or with ``dbox`` ((n_pairs, 12) int32: for W_i the box
+    lo[3], n[3], then for W_j) on those boxes with the multipole potential
+    outside the pair domain."""
     lib = _load()
     N3, L3 = _grid(N, L)
     phi = np.ascontiguousarray(phi, dtype=np.float64)
@@ -259,7 +265,11 @@ def exx(phi, N, L, pairs: PairList, tol=1e-12, max_iter=10000, M=FD_HALF_ORDER, 
     it = np.zeros(max(npairs, 1), dtype=np.int32)
     rr = np.zeros(max(npairs, 1))
     E = C.c_double(0.0)
-    st = lib.orc_exx(_ip(N3), _dp(L3), n_occ, _dp(phi), npairs, _ip(packed), _dp(org), M, lmax,
+    db = None
+    if dbox is not None and npairs:
+        db = np.ascontiguousarray(dbox, dtype=np.int32).reshape(npairs, 12)
+    st = lib.orc_exx(_ip(N3), _dp(L3), n_occ, _dp(phi), npairs, _ip(packed), _dp(org),
+                     _ip(db) if db is not None else None, M, lmax,
                      tol, max_iter, n_threads, _dp(W), _dp(e), _ip(it), _dp(rr), C.byref(E))
     if st < 0:
         raise ValueError("bad pair list")

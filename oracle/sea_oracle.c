@@ -415,9 +415,24 @@ static int orc_cyc_intersect(int a, int la, int b, int lb, int N, int *start) {
  * density and the multipole boundary open).  Output as orc_build_pairs,
  * plus S per kept pair; the multipole origin is the box centre,
  * (lo + (n - 1)/2) h per axis. */
+/* Box of an orbital run shifted by a multiple of N to lie nearest (by its
+ * centre) to the reference start r0 with length rn. */
+static int orc_near_start(int lo, int ln, int r0, int rn, int N) {
+    int best = lo, bd = -1;
+    for (int k = -1; k <= 1; ++k) {
+        const int c2 = 2 * (lo + k * N) + ln, r2 = 2 * r0 + rn;
+        const int d = c2 > r2 ? c2 - r2 : r2 - c2;
+        if (bd < 0 || d < bd) {
+            bd = d;
+            best = lo + k * N;
+        }
+    }
+    return best;
+}
+
 int orc_eps_pairs(const int32_t *N, const double *L, int n_occ, const double *phi, const int32_t *lo,
                   const int32_t *len, double delta, int pad, int cap, int32_t *pairs_out, double *origin_out,
-                  double *s_out, int *n_out) {
+                  double *s_out, int32_t *dbox_out, int *n_out) {
     if (n_occ < 0) return -1;
     const size_t Ng = (size_t)N[0] * N[1] * N[2];
     double h[3];
@@ -456,6 +471,36 @@ int orc_eps_pairs(const int32_t *N, const double *L, int n_occ, const double *ph
                     origin_out[3 * cnt + a] = (sp + 0.5 * (np - 1)) * h[a];
                 }
                 s_out[cnt] = S;
+                if (dbox_out) {
+                    /* boxes where W takes this pair (the paper's Omega^D): for
+                     * W_i the box of phi_j (i != j) or Omega_ii doubled about its
+                     * centre (i == j); for W_j the box of phi_i; each placed in
+                     * the frame of the pair's domain and grown to cover it */
+                    int32_t *d = dbox_out + 12 * cnt;
+                    for (int a = 0; a < 3; ++a) {
+                        int l0, n0;
+                        if (i == j) {
+                            n0 = 2 * len[3 * i + a] < N[a] ? 2 * len[3 * i + a] : N[a];
+                            l0 = lo[3 * i + a] - (n0 - len[3 * i + a]) / 2;
+                        } else {
+                            n0 = len[3 * j + a];
+                            l0 = lo[3 * j + a];
+                        }
+                        d[a] = orc_near_start(l0, n0, o[2 + a], o[5 + a], N[a]);
+                        d[3 + a] = n0;
+                        d[6 + a] = orc_near_start(lo[3 * i + a], len[3 * i + a], o[2 + a], o[5 + a], N[a]);
+                        d[9 + a] = len[3 * i + a];
+                        /* each box also covers the pair's domain, so that W takes
+                         * the pair wherever e_ij does (at most the cell) */
+                        for (int sd = 0; sd < 2; ++sd) {
+                            int32_t *bl = d + 6 * sd + a, *bn = d + 6 * sd + 3 + a;
+                            const int l1 = *bl < o[2 + a] ? *bl : o[2 + a];
+                            const int e1 = *bl + *bn > o[2 + a] + o[5 + a] ? *bl + *bn : o[2 + a] + o[5 + a];
+                            *bl = l1;
+                            *bn = e1 - l1 < N[a] ? e1 - l1 : N[a];
+                        }
+                    }
+                }
             }
             ++cnt;
         }
@@ -568,8 +613,8 @@ int orc_pair_potential(const int32_t *N, const double *L, int n_occ, const doubl
  * pair order afterwards so the result does not depend on the thread count.
  * Returns the number of pairs that did not converge, or -1 on bad input. */
 int orc_exx(const int32_t *N, const double *L, int n_occ, const double *phi, int n_pairs,
-            const int32_t *pairs, const double *origins, int M, int lmax, double tol,
-            int max_iter, int n_threads, double *W, double *e_pairs, int32_t *iters,
+            const int32_t *pairs, const double *origins, const int32_t *dbox, int M, int lmax,
+            double tol, int max_iter, int n_threads, double *W, double *e_pairs, int32_t *iters,
             double *relres, double *E_out) {
     size_t Ng = (size_t)N[0] * N[1] * N[2];
     for (int p = 0; p < n_pairs; ++p) {
@@ -583,6 +628,8 @@ int orc_exx(const int32_t *N, const double *L, int n_occ, const double *phi, int
         off[p + 1] = off[p] + (size_t)n[0] * n[1] * n[2];
     }
     double *v = malloc(sizeof(double) * (off[n_pairs] ? off[n_pairs] : 1));
+    const int nq = (lmax + 1) * (lmax + 1);
+    double *Qall = malloc(sizeof(double) * (size_t)nq * (n_pairs ? n_pairs : 1));
     int bad = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -591,7 +638,7 @@ int orc_exx(const int32_t *N, const double *L, int n_occ, const double *phi, int
     for (int p = 0; p < n_pairs; ++p) {
         double info[8];
         int st = orc_pair_potential(N, L, n_occ, phi, pairs + 8 * p, origins + 3 * p, M, lmax,
-                                    tol, max_iter, NULL, v + off[p], NULL, info);
+                                    tol, max_iter, NULL, v + off[p], Qall + (size_t)nq * p, info);
         e_pairs[p] = info[2];
         iters[p] = (int32_t)info[0];
         relres[p] = info[1];
@@ -599,24 +646,53 @@ int orc_exx(const int32_t *N, const double *L, int n_occ, const double *phi, int
     }
     memset(W, 0, sizeof(double) * Ng * n_occ);
     double E = 0.0;
+    double h[3];
+    for (int a = 0; a < 3; ++a) h[a] = L[a] / N[a];
     for (int p = 0; p < n_pairs; ++p) {
         const int32_t *pp = pairs + 8 * p;
         int i = pp[0], j = pp[1];
         const int32_t *lo = pp + 2, *n = pp + 5;
         const double *vp = v + off[p];
-        for (int z = 0; z < n[2]; ++z)
-            for (int y = 0; y < n[1]; ++y)
-                for (int x = 0; x < n[0]; ++x) {
-                    size_t g = ((size_t)orc_wrap(lo[2] + z, N[2]) * N[1] + orc_wrap(lo[1] + y, N[1])) * N[0]
-                               + orc_wrap(lo[0] + x, N[0]);
-                    double vv = vp[((size_t)z * n[1] + y) * n[0] + x];
-                    W[(size_t)i * Ng + g] += vv * phi[(size_t)j * Ng + g];
-                    if (i != j) W[(size_t)j * Ng + g] += vv * phi[(size_t)i * Ng + g];
-                }
+        if (!dbox) {
+            /* W on the pair's own domain */
+            for (int z = 0; z < n[2]; ++z)
+                for (int y = 0; y < n[1]; ++y)
+                    for (int x = 0; x < n[0]; ++x) {
+                        size_t g = ((size_t)orc_wrap(lo[2] + z, N[2]) * N[1] + orc_wrap(lo[1] + y, N[1])) * N[0]
+                                   + orc_wrap(lo[0] + x, N[0]);
+                        double vv = vp[((size_t)z * n[1] + y) * n[0] + x];
+                        W[(size_t)i * Ng + g] += vv * phi[(size_t)j * Ng + g];
+                        if (i != j) W[(size_t)j * Ng + g] += vv * phi[(size_t)i * Ng + g];
+                    }
+        } else {
+            /* W_i += v phi_j on box side 0 and, for i != j, W_j += v phi_i on
+             * box side 1; v is the solution inside the pair's domain and the
+             * multipole potential (Eq. 10) outside it */
+            for (int side = 0; side < (i == j ? 1 : 2); ++side) {
+                const int32_t *dl = dbox + 12 * p + 6 * side, *dn = dl + 3;
+                const int o = side == 0 ? i : j, q = side == 0 ? j : i;
+                for (int z = 0; z < dn[2]; ++z)
+                    for (int y = 0; y < dn[1]; ++y)
+                        for (int x = 0; x < dn[0]; ++x) {
+                            const int P3[3] = {dl[0] + x, dl[1] + y, dl[2] + z};
+                            const int s0 = P3[0] - lo[0], s1 = P3[1] - lo[1], s2 = P3[2] - lo[2];
+                            double vv;
+                            if (s0 >= 0 && s0 < n[0] && s1 >= 0 && s1 < n[1] && s2 >= 0 && s2 < n[2]) {
+                                vv = vp[((size_t)s2 * n[1] + s1) * n[0] + s0];
+                            } else {
+                                const double t[3] = {P3[0] * h[0], P3[1] * h[1], P3[2] * h[2]};
+                                vv = orc_me_eval(lmax, Qall + (size_t)nq * p, origins + 3 * p, t);
+                            }
+                            size_t g = ((size_t)orc_wrap(P3[2], N[2]) * N[1] + orc_wrap(P3[1], N[1])) * N[0] +
+                                       orc_wrap(P3[0], N[0]);
+                            W[(size_t)o * Ng + g] += vv * phi[(size_t)q * Ng + g];
+                        }
+            }
+        }
         E -= (i == j ? 1.0 : 2.0) * e_pairs[p];
     }
     *E_out = E;
-    free(v); free(off);
+    free(v); free(off); free(Qall);
     return bad;
 }
 

@@ -500,6 +500,12 @@ __device__ __forceinline__ bool axis_hits(int t0, int T, int lo, int n, int N) {
     return s < n || s + T > N;
 }
 
+// W gathered per (orbital, tile): every pair of the orbital whose W box
+// touches the tile adds v * phi_partner at the tile's points, in pair order.
+// The box is the pair's W box for this orbital's side (lo[3], n[3] in the
+// pair domain's unwrapped frame); inside the pair's domain v is the solution,
+// outside it the multipole potential of the pair (Eq. 10).
+template <int LM>
 __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const int* __restrict__ off_all,
                                                    const int2* __restrict__ ent) {
     __shared__ int list[SC_MAXE];
@@ -517,7 +523,6 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     const int e0 = off[o], e1 = off[o + 1];
-    // cull in chunks of SC_BS, preserving pair order
     double acc[SC_TX * SC_TY * SC_TZ / SC_BS];
 #pragma unroll
     for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) acc[k] = 0.0;
@@ -527,9 +532,10 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
         if (threadIdx.x == 0) {
             int m = 0;
             for (int e = c0; e < c1; ++e) {
-                const sea_pair P = a.pairs[ent[e].x];
-                if (axis_hits(tx0, SC_TX, P.lo[0], P.n[0], C.N[0]) && axis_hits(ty0, SC_TY, P.lo[1], P.n[1], C.N[1]) &&
-                    axis_hits(tz0, SC_TZ, P.lo[2], P.n[2], C.N[2]))
+                const int pid = ent[e].x;
+                const int* D = a.dbox + 12 * (size_t)pid + (o == a.pairs[pid].i ? 0 : 6);
+                if (axis_hits(tx0, SC_TX, D[0], D[3], C.N[0]) && axis_hits(ty0, SC_TY, D[1], D[4], C.N[1]) &&
+                    axis_hits(tz0, SC_TZ, D[2], D[5], C.N[2]))
                     list[m++] = e;
             }
             cnt = m;
@@ -546,12 +552,23 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
             for (int q = 0; q < m; ++q) {
                 const int2 en = ent[list[q]];
                 const sea_pair P = a.pairs[en.x];
+                const int* D = a.dbox + 12 * (size_t)en.x + (o == P.i ? 0 : 6);
                 const double* v = a.v + (size_t)en.x * a.stride;
+                const double* Q = a.mom + (size_t)en.x * SEA_NACC;
                 const double ph = load_phi(C.phi, C.phi_f32, (size_t)en.y * C.Ng + g);
-                for (int lz = wrap_idx(gz - P.lo[2], C.N[2]); lz < P.n[2]; lz += C.N[2])
-                    for (int ly = wrap_idx(gy - P.lo[1], C.N[1]); ly < P.n[1]; ly += C.N[1])
-                        for (int lx = wrap_idx(gx - P.lo[0], C.N[0]); lx < P.n[0]; lx += C.N[0])
-                            s += v[((size_t)lz * P.n[1] + ly) * P.n[0] + lx] * ph;
+                for (int lz = wrap_idx(gz - D[2], C.N[2]); lz < D[5]; lz += C.N[2])
+                    for (int ly = wrap_idx(gy - D[1], C.N[1]); ly < D[4]; ly += C.N[1])
+                        for (int lx = wrap_idx(gx - D[0], C.N[0]); lx < D[3]; lx += C.N[0]) {
+                            const int px = D[0] + lx, py = D[1] + ly, pz = D[2] + lz;  // unwrapped point
+                            const int sx = px - P.lo[0], sy = py - P.lo[1], sz = pz - P.lo[2];
+                            double val;
+                            if (sx >= 0 && sx < P.n[0] && sy >= 0 && sy < P.n[1] && sz >= 0 && sz < P.n[2])
+                                val = v[((size_t)sz * P.n[1] + sy) * P.n[0] + sx];
+                            else
+                                val = racah_me_potential<LM>(Q, a.lmax, px * C.h[0] - P.origin[0],
+                                                             py * C.h[1] - P.origin[1], pz * C.h[2] - P.origin[2]);
+                            s += val * ph;
+                        }
             }
             acc[k] = s;
         }
@@ -648,7 +665,7 @@ hipError_t launch_scatter(const ExxArgs& a, int cell, const int* N, int n_occ, c
                           hipStream_t s) {
     const int tiles = ((N[0] + SC_TX - 1) / SC_TX) * ((N[1] + SC_TY - 1) / SC_TY) * ((N[2] + SC_TZ - 1) / SC_TZ);
     dim3 grid(tiles, n_occ);
-    hipLaunchKernelGGL(k_scatter, grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
+    hipLaunchKernelGGL(k_scatter<SEA_LMAX>, grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
     return hipGetLastError();
 }
 

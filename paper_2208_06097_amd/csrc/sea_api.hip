@@ -95,6 +95,7 @@ struct CellSet {
     std::vector<int2> csr_ent;
     std::vector<DevCell> dev;
     std::vector<int> order;  // CG queue: pair ids by decreasing interior size (ties: id order)
+    std::vector<int> dbox;   // 12 per pair: W_i box, W_j box (default: the pair's domain twice)
     bool cubic = true;
 };
 
@@ -130,8 +131,19 @@ static sea_status build_cellset(sea_ctx* ctx, int n_cells, const sea_cell* cells
         D.pair_begin = (int)S.pairs.size();
         D.csr_base = csr_base;
         for (int k = 0; k < C.n_pairs; ++k) {
-            S.pairs.push_back(C.pairs_host[k]);
+            const sea_pair& P = C.pairs_host[k];
+            S.pairs.push_back(P);
             S.pair_cell.push_back(c);
+            for (int side = 0; side < 2; ++side) {  // lo[3] then n[3] per side
+                int box[6];
+                for (int a2 = 0; a2 < 3; ++a2) {
+                    box[a2] = C.dbox_host ? C.dbox_host[12 * k + 6 * side + a2] : P.lo[a2];
+                    box[3 + a2] = C.dbox_host ? C.dbox_host[12 * k + 6 * side + 3 + a2] : P.n[a2];
+                    if (box[3 + a2] < 1 || box[3 + a2] > 4096 || box[a2] < -(1 << 24) || box[a2] > (1 << 24))
+                        return fail(ctx, SEA_E_ARG, "cell %d pair %d: W box out of range", c, k);
+                }
+                S.dbox.insert(S.dbox.end(), box, box + 6);
+            }
         }
         D.pair_end = (int)S.pairs.size();
         if (action) {
@@ -195,6 +207,7 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.pairs = take(np * sizeof(sea_pair));
     L.pair_cell = take(np * sizeof(int));
     L.order = take(np * sizeof(int));
+    L.dbox = take(np * 12 * sizeof(int));
     L.cells = take(nc * sizeof(DevCell));
     L.partial = take(np * L.n_chunks * SEA_NACC * sizeof(double));
     L.mom = take(np * SEA_NACC * sizeof(double));
@@ -428,6 +441,7 @@ static sea_status exx_upload(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly
         SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.pairs, S.pairs.data(), sizeof(sea_pair) * np, hipMemcpyHostToDevice, s));
         SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.pair_cell, S.pair_cell.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
         SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.order, S.order.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.dbox, S.dbox.data(), sizeof(int) * 12 * np, hipMemcpyHostToDevice, s));
     }
     SEA_HIP_CHECK(ctx, hipMemcpyAsync(base + Ly.cells, S.dev.data(), sizeof(DevCell) * S.dev.size(), hipMemcpyHostToDevice, s));
     if (!S.csr_off.empty())
@@ -446,6 +460,7 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.cells = (const DevCell*)(base + Ly.cells);
     a.pair_cell = (const int*)(base + Ly.pair_cell);
     a.order = S.pairs.empty() ? nullptr : (const int*)(base + Ly.order);
+    a.dbox = (const int*)(base + Ly.dbox);
     a.n_cells = (int)S.cells.size();
     a.partial = (double*)(base + Ly.partial);
     a.n_chunks = Ly.n_chunks;
@@ -1019,6 +1034,20 @@ int cyc_intersect(int a, int la, int b, int lb, int N, int* start) {
     return best;
 }
 
+// Start of a run of length ln shifted by a multiple of N so that its centre
+// is nearest the centre of the reference run [r0, r0 + rn).
+int near_start(int lo, int ln, int r0, int rn, int N) {
+    int best = lo, bd = -1;
+    for (int k = -1; k <= 1; ++k) {
+        const int d = std::abs(2 * (lo + k * N) + ln - (2 * r0 + rn));
+        if (bd < 0 || d < bd) {
+            bd = d;
+            best = lo + k * N;
+        }
+    }
+    return best;
+}
+
 }  // namespace
 
 extern "C" sea_status sea_eps_workspace_bytes(sea_ctx* ctx, const sea_grid* grid, int n_occ, size_t* bytes) {
@@ -1035,7 +1064,8 @@ extern "C" sea_status sea_eps_workspace_bytes(sea_ctx* ctx, const sea_grid* grid
 
 extern "C" sea_status sea_build_pairs_eps(sea_ctx* ctx, const sea_grid* grid, int n_occ, const void* phi_dev,
                                           sea_dtype phi_dtype, double eps, double delta, int pad, void* ws_dev,
-                                          size_t ws_bytes, sea_pair* out, double* s_out, int cap, int* n_out) {
+                                          size_t ws_bytes, sea_pair* out, double* s_out, int32_t* dbox_out, int cap,
+                                          int* n_out) {
     if (!ctx) return SEA_E_ARG;
     size_t need = 0;
     sea_status st = sea_eps_workspace_bytes(ctx, grid, n_occ, &need);
@@ -1106,6 +1136,33 @@ extern "C" sea_status sea_build_pairs_eps(sea_ctx* ctx, const sea_grid* grid, in
             }
             out[cnt] = p;
             if (s_out) s_out[cnt] = S[k];
+            if (dbox_out) {
+                // W_i: box of phi_j, or Omega_ii doubled about its centre for a self
+                // pair; W_j: box of phi_i; both in the frame of the pair's domain and
+                // grown to cover it
+                const int i = p.i, j = p.j;
+                int32_t* d = dbox_out + 12 * (size_t)cnt;
+                for (int a = 0; a < 3; ++a) {
+                    int l0, n0;
+                    if (i == j) {
+                        n0 = std::min(2 * ln[3 * i + a], N[a]);
+                        l0 = lo[3 * i + a] - (n0 - ln[3 * i + a]) / 2;
+                    } else {
+                        n0 = ln[3 * j + a];
+                        l0 = lo[3 * j + a];
+                    }
+                    d[a] = near_start(l0, n0, p.lo[a], p.n[a], N[a]);
+                    d[3 + a] = n0;
+                    d[6 + a] = near_start(lo[3 * i + a], ln[3 * i + a], p.lo[a], p.n[a], N[a]);
+                    d[9 + a] = ln[3 * i + a];
+                    for (int sd = 0; sd < 2; ++sd) {  // cover the pair's domain too (at most the cell)
+                        const int l1 = std::min(d[6 * sd + a], p.lo[a]);
+                        const int e1 = std::max(d[6 * sd + a] + d[6 * sd + 3 + a], p.lo[a] + p.n[a]);
+                        d[6 * sd + a] = l1;
+                        d[6 * sd + 3 + a] = std::min(e1 - l1, N[a]);
+                    }
+                }
+            }
         }
         ++cnt;
     }

@@ -57,7 +57,7 @@ struct StageTimer {
 
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
-    size_t pairs, pair_cell, order, cells, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, counter;
+    size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, counter;
     size_t nnx, nny, nnact, total;
     size_t gstride;
     int nmax;
@@ -106,6 +106,7 @@ struct ExxArgs {
     int lmax;
     int* queue_ctr;       // persistent-kernel pair counter (zeroed before the CG launch)
     const int* order;     // CG queue order: pair ids by decreasing domain size (nullable)
+    const int* dbox;      // per pair 12 ints: boxes where W_i and W_j take the pair
     int x_nonzero;        // v holds a start guess on entry to the CG
     double* bres;         // n_pairs x stride: b - A x0 when x_nonzero
     double* gbuf;         // ghost-layer multipole values, n_pairs x gstride

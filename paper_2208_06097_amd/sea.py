@@ -82,7 +82,7 @@ class SeaOpts(C.Structure):
 class SeaCell(C.Structure):
     _fields_ = [("grid", SeaGrid), ("n_occ", C.c_int32), ("phi_dtype", C.c_int), ("phi_dev", C.c_void_p),
                 ("n_pairs", C.c_int32), ("pairs_host", C.c_void_p), ("W_dev", C.c_void_p),
-                ("exx_dev", C.c_void_p)]
+                ("exx_dev", C.c_void_p), ("dbox_host", C.c_void_p)]
 
 
 STAGES = ["gather", "boundary", "guess", "cg", "scatter", "energy", "ace_m", "ace_chol", "ace_xi",
@@ -148,7 +148,7 @@ def load() -> C.CDLL:
     lib.sea_nn_infer_workspace_bytes.argtypes = [vp, i, P(sz)]
     lib.sea_nn_infer.argtypes = [vp, vp, i, vp, vp, vp, sz]
     lib.sea_eps_workspace_bytes.argtypes = [vp, P(SeaGrid), i, P(sz)]
-    lib.sea_build_pairs_eps.argtypes = [vp, P(SeaGrid), i, vp, i, d, d, i, vp, sz, vp, vp, i, P(i)]
+    lib.sea_build_pairs_eps.argtypes = [vp, P(SeaGrid), i, vp, i, d, d, i, vp, sz, vp, vp, vp, i, P(i)]
     _lib = lib
     return lib
 
@@ -269,9 +269,14 @@ class Context:
             return SEA_F32
         raise TypeError("phi must be float64 or float32")
 
-    def exx_action(self, phi, N, L, pairs, ws=None, W=None, exx_dev=None, want_host=True):
-        """Returns (W, E_host or None, stats or None, status)."""
+    def exx_action(self, phi, N, L, pairs, ws=None, W=None, exx_dev=None, want_host=True, dbox=None):
+        """Returns (W, E_host or None, stats or None, status).  ``dbox``
+        (n_pairs x 12): the boxes where W takes each pair (see sea_cell)."""
         torch = self._torch
+        if dbox is not None:
+            Ws, Es, stats, st = self.exx_action_batched([(phi, N, L, pairs, W, exx_dev, dbox)], ws=ws,
+                                                        want_host=want_host)
+            return Ws[0], (float(Es[0]) if want_host else None), stats, st
         assert phi.is_cuda and phi.is_contiguous()
         n_occ = phi.shape[0]
         p = np.ascontiguousarray(pairs, dtype=PAIR_DTYPE)
@@ -291,9 +296,9 @@ class Context:
         return W, (E.value if want_host else None), (stats[:len(p)] if want_host else None), st
 
     def _cells(self, cells, need_W=True):
-        """Marshal [(phi, N, L, pairs, W or None, exx_dev or None), ...] into a
-        sea_cell array; allocates W where it is None.  Keeps the pair tables
-        alive in the returned tuple."""
+        """Marshal [(phi, N, L, pairs, W or None, exx_dev or None, dbox or None), ...]
+        into a sea_cell array; allocates W where it is None.  Keeps the pair
+        tables alive in the returned tuple."""
         torch = self._torch
         arr = (SeaCell * len(cells))()
         keep, Ws = [], []
@@ -301,6 +306,7 @@ class Context:
             phi, N, L, pairs = c[0], c[1], c[2], c[3]
             W = c[4] if len(c) > 4 else None
             exx_dev = c[5] if len(c) > 5 else None
+            dbox = c[6] if len(c) > 6 else None
             assert phi.is_cuda and phi.is_contiguous()
             p = np.ascontiguousarray(pairs, dtype=PAIR_DTYPE)
             keep.append(p)
@@ -315,6 +321,10 @@ class Context:
             arr[k].pairs_host = p.ctypes.data if len(p) else None
             arr[k].W_dev = W.data_ptr() if W is not None else None
             arr[k].exx_dev = exx_dev.data_ptr() if exx_dev is not None else None
+            if dbox is not None:
+                db = np.ascontiguousarray(dbox, dtype=np.int32).reshape(len(p), 12)
+                keep.append(db)
+                arr[k].dbox_host = db.ctypes.data if len(p) else None
         return arr, Ws, keep
 
     def exx_batched_workspace_bytes(self, cells) -> int:
@@ -329,7 +339,7 @@ class Context:
         arr, Ws, keep = self._cells(cells)
         if ws is None:
             ws = self.workspace(self.exx_batched_workspace_bytes(cells))
-        n_all = sum(len(k) for k in keep)
+        n_all = sum(len(c[3]) for c in cells)
         E = np.zeros(len(cells))
         stats = np.zeros(max(n_all, 1), dtype=STAT_DTYPE)
         st = self.lib.sea_exx_action_batched(self.h, len(cells), arr, ws.data_ptr(), ws.numel(),
@@ -382,9 +392,10 @@ class Context:
         """A replayable HIP-graph plan of the batched action (see Plan)."""
         return Plan(self, cells, ws)
 
-    def build_pairs_eps(self, phi, N, L, eps, delta, pad=0):
+    def build_pairs_eps(self, phi, N, L, eps, delta, pad=0, with_dbox=False):
         """Pairs and boxes of the epsilon rule (Eq. 16-17), boxes grown by
-        ``pad`` points a side: (pairs, S)."""
+        ``pad`` points a side: (pairs, S), or (pairs, S, dbox) with the boxes
+        where W takes each pair (the paper's Omega^D)."""
         assert phi.is_cuda and phi.is_contiguous()
         n_occ = phi.shape[0]
         g = _grid(N, L)
@@ -394,11 +405,13 @@ class Context:
         cap = n_occ * (n_occ + 1) // 2
         out = np.zeros(max(cap, 1), dtype=PAIR_DTYPE)
         S = np.zeros(max(cap, 1))
+        db = np.zeros((max(cap, 1), 12), dtype=np.int32)
         n = C.c_int(0)
         self._check(self.lib.sea_build_pairs_eps(self.h, C.byref(g), n_occ, phi.data_ptr(), self._phi_dtype(phi),
                                                  eps, delta, int(pad), ws.data_ptr(), ws.numel(), out.ctypes.data,
-                                                 S.ctypes.data, cap, C.byref(n)))
-        return out[:n.value].copy(), S[:n.value].copy()
+                                                 S.ctypes.data, db.ctypes.data, cap, C.byref(n)))
+        k = n.value
+        return (out[:k].copy(), S[:k].copy(), db[:k].copy()) if with_dbox else (out[:k].copy(), S[:k].copy())
 
     def pair_solve(self, phi, N, L, pairs, ws=None, want_Q=True):
         """Per-pair potentials: returns (v (n_pairs x stride), Q or None, e, stats, status)."""
@@ -567,7 +580,7 @@ class Plan:
         self.ctx = ctx
         arr, self.W, self._keep = ctx._cells(cells)
         self._cells = arr
-        self._n_pairs = sum(len(k) for k in self._keep)
+        self._n_pairs = sum(len(c[3]) for c in cells)
         self.ws = ws if ws is not None else ctx.workspace(ctx.exx_batched_workspace_bytes(cells))
         h = C.c_void_p()
         ctx._check(ctx.lib.sea_exx_plan_create(ctx.h, len(cells), arr, self.ws.data_ptr(), self.ws.numel(),

@@ -29,7 +29,7 @@ def test_struct_layouts():
     assert sea.PAIR_DTYPE.itemsize == 56
     assert sea.STAT_DTYPE.itemsize == 40
     assert ctypes.sizeof(sea.SeaGrid) == 40
-    assert ctypes.sizeof(sea.SeaCell) == 88
+    assert ctypes.sizeof(sea.SeaCell) == 96
 
 
 @pytest.mark.parametrize("cfg", ["c1", "mini", "c3_dense"])

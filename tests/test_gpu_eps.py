@@ -28,9 +28,11 @@ def test_eps_pairs_match_oracle(case, eps, pad):
     print(f"case eps pairs {case} eps={eps:.2e} pad={pad}", flush=True)
     cell = synth.config1() if case == "c1" else synth.mini(seed=int(case[4:]))
     ctx = _ctx()
-    pairs, S = ctx.build_pairs_eps(torch.from_numpy(cell.phi).cuda(), cell.N, cell.L, eps, eps, pad=pad)
+    pairs, S, db = ctx.build_pairs_eps(torch.from_numpy(cell.phi).cuda(), cell.N, cell.L, eps, eps, pad=pad,
+                                       with_dbox=True)
     lo, ln = oracle.eps_boxes(cell.phi, cell.N, eps)
-    pl, So = oracle.eps_pairs(cell.phi, cell.N, cell.L, lo, ln, eps, pad=pad)
+    pl, So, dbo = oracle.eps_pairs(cell.phi, cell.N, cell.L, lo, ln, eps, pad=pad, with_dbox=True)
+    assert np.array_equal(db, dbo)
     assert len(pairs) == len(pl)
     assert np.array_equal(np.stack([pairs["i"], pairs["j"]], 1), pl.ij)
     assert np.array_equal(pairs["lo"], pl.lo) and np.array_equal(pairs["n"], pl.n)
@@ -58,6 +60,29 @@ def test_exx_on_eps_pairs_matches_oracle(sdt, pad):
     ref = oracle.exx(cell.phi, cell.N, cell.L, pl, tol=1e-12)
     assert abs(E - ref.E) < 1e-6
     assert np.max(np.abs(W.cpu().numpy() - ref.W)) < 1e-5
+    ctx.close()
+
+
+@pytest.mark.parametrize("sdt", ["f64", "f32"])
+def test_exx_with_w_boxes_matches_oracle(sdt):
+    """W on the paper's Omega^D boxes (v outside the pair domain from the
+    multipole expansion) against the oracle's action with the same boxes."""
+    cell = synth.mini(seed=8)
+    eps = 1e-3
+    print(f"case exx with W boxes {sdt}", flush=True)
+    ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F64 if sdt == "f64" else sea.SEA_F32,
+               start=sea.SEA_START_MULTIPOLE)
+    phi = torch.from_numpy(cell.phi).cuda()
+    pairs, _, db = ctx.build_pairs_eps(phi, cell.N, cell.L, eps, eps, pad=2, with_dbox=True)
+    W, E, stats, st = ctx.exx_action(phi, cell.N, cell.L, pairs, dbox=db)
+    assert st == sea.SEA_OK and np.all(stats["converged"] == 1)
+    lo, ln = oracle.eps_boxes(cell.phi, cell.N, eps)
+    pl, _, dbo = oracle.eps_pairs(cell.phi, cell.N, cell.L, lo, ln, eps, pad=2, with_dbox=True)
+    ref = oracle.exx(cell.phi, cell.N, cell.L, pl, tol=1e-12, dbox=dbo)
+    plain = oracle.exx(cell.phi, cell.N, cell.L, pl, tol=1e-12)
+    assert abs(E - ref.E) < 1e-6
+    assert np.max(np.abs(W.cpu().numpy() - ref.W)) < 1e-5
+    assert np.max(np.abs(ref.W - plain.W)) > 1e-4      # the boxes do change W
     ctx.close()
 
 

@@ -143,3 +143,74 @@ def test_padding_grows_boxes_symmetrically_within_the_cell():
         assert np.array_equal(p.lo, p0.lo - (want_n - p0.n) // 2)
         assert np.all(p.lo <= p0.lo) and np.all(p.lo + p.n >= p0.lo + p0.n)
         assert np.allclose(p.origin / c.h, p.lo + 0.5 * (p.n - 1), atol=1e-12)
+
+
+def test_dboxes_are_the_orbital_boxes_in_the_pair_frame():
+    c = synth.mini(seed=7)
+    lo, ln = oracle.eps_boxes(c.phi, c.N, 1e-3)
+    pl, S, db = oracle.eps_pairs(c.phi, c.N, c.L, lo, ln, 1e-3, pad=2, with_dbox=True)
+    for k in range(len(pl)):
+        i, j = pl.ij[k]
+        for a in range(3):
+            # each W box = the orbital box (in some frame) joined with the pair domain
+            if i == j:
+                n0 = min(2 * ln[i, a], c.N)
+                l0 = lo[i, a] - (n0 - ln[i, a]) // 2
+            else:
+                n0, l0 = ln[j, a], lo[j, a]
+            for side, (ll, nn) in enumerate(((l0, n0), (lo[i, a], ln[i, a]))):
+                b0, bn = db[k, 6 * side + a], db[k, 6 * side + 3 + a]
+                shifts = [ll + m * c.N for m in (-1, 0, 1)]
+                ok = any(b0 == min(sh, pl.lo[k, a]) and
+                         bn == min(max(sh + nn, pl.lo[k, a] + pl.n[k, a]) - min(sh, pl.lo[k, a]), c.N)
+                         for sh in shifts)
+                assert ok, (k, a, side)
+                assert b0 <= pl.lo[k, a] and b0 + bn >= min(pl.lo[k, a] + pl.n[k, a], b0 + c.N)
+            # nearest frame: centres within half a cell of the pair box centre
+            for side in (0, 1):
+                cen = db[k, 6 * side + a] + 0.5 * db[k, 6 * side + 3 + a]
+                assert abs(cen - (pl.lo[k, a] + 0.5 * pl.n[k, a])) <= c.N / 2
+
+
+def test_exx_with_dboxes_equal_to_the_domains_is_the_plain_action():
+    c = synth.mini(seed=7)
+    lo, ln = oracle.eps_boxes(c.phi, c.N, 1e-3)
+    pl, S = oracle.eps_pairs(c.phi, c.N, c.L, lo, ln, 1e-3, pad=2)
+    db = np.concatenate([pl.lo, pl.n, pl.lo, pl.n], axis=1).astype(np.int32)
+    r0 = oracle.exx(c.phi, c.N, c.L, pl, tol=1e-10)
+    r1 = oracle.exx(c.phi, c.N, c.L, pl, tol=1e-10, dbox=db)
+    assert r1.E == r0.E and np.array_equal(r1.W, r0.W)
+
+
+def test_far_field_of_a_spherical_orbital_is_the_monopole():
+    """One spherical orbital (a = 0): on the doubled box, outside the pair
+    domain, W = (q / r) phi with q = h^3 sum rho over the domain.  The density
+    cut to a box keeps the box's l = 4, 6 (and, for a box of even extent
+    around the centre, odd) moments, all carried by the mass the cut removed
+    (<= eps), so the far field is the monopole to a relative eps."""
+    N, L = 48, 9.6
+    h = L / N
+    c = synth.make_centres(1, L, N, seed=2, dmin=1.0)
+    c.centres = c.centres[:1].copy()
+    c.a = np.zeros((1, 3))
+    c.centres[0] = [24 * h, 24 * h, 24 * h]
+    c = synth.fill_orbitals(c)
+    lo, ln = oracle.eps_boxes(c.phi, N, 1e-3)
+    pl, S, db = oracle.eps_pairs(c.phi, N, L, lo, ln, 1e-3, pad=0, with_dbox=True)
+    assert len(pl) == 1
+    r = oracle.exx(c.phi, N, L, pl, tol=1e-12, dbox=db)
+    box = [np.arange(pl.lo[0, a], pl.lo[0, a] + pl.n[0, a]) for a in range(3)]
+    rho = c.phi[0][np.ix_(box[2] % N, box[1] % N, box[0] % N)] ** 2
+    q = h ** 3 * rho.sum()
+    checked = 0
+    for z in range(db[0, 2], db[0, 2] + db[0, 5], 3):
+        for y in range(db[0, 1], db[0, 1] + db[0, 4], 3):
+            for x in range(db[0, 0], db[0, 0] + db[0, 3], 3):
+                inside = all(pl.lo[0, a] <= p < pl.lo[0, a] + pl.n[0, a] for a, p in enumerate((x, y, z)))
+                if inside:
+                    continue
+                d = np.array([x, y, z]) * h - pl.origin[0]
+                want = q / np.linalg.norm(d) * c.phi[0][z % N, y % N, x % N]
+                assert abs(r.W[0][z % N, y % N, x % N] - want) <= 1e-3 * abs(want) + 1e-14
+                checked += 1
+    assert checked > 100
