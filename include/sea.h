@@ -34,6 +34,8 @@ extern "C" {
 typedef enum {
     SEA_OK = 0,
     SEA_W_NOT_CONVERGED = 1, /* some pair hit max_iter; outputs still written */
+    SEA_W_EIGEN_FALLBACK = 2,/* Mbar not positive definite: the eigen scheme of
+                              * App. A was used instead of Cholesky             */
     SEA_E_ARG = -1,          /* invalid argument (message says which)          */
     SEA_E_HIP = -2,          /* HIP runtime error                               */
     SEA_E_NOMEM = -3,        /* workspace smaller than *_workspace_bytes        */
@@ -55,6 +57,13 @@ typedef struct {
     int32_t n[3];
     double L[3];
 } sea_grid;
+
+/* Low-rank decomposition of Mbar in the ACE build (Eq. 18, App. A). */
+typedef enum {
+    SEA_DECOMP_CHOLESKY = 0, /* Mbar = L L^T; a non-positive pivot is an error   */
+    SEA_DECOMP_EIGEN = 1,    /* Mbar = Q Lambda Q^T, zeta = W Q |Lambda|^{-1/2}  */
+    SEA_DECOMP_AUTO = 2      /* Cholesky, the eigen scheme if Mbar is not PD     */
+} sea_decomp;
 
 /* One kept orbital pair <ij> (Sec. II.B): i <= j, and its truncated domain,
  * the box of n[0] x n[1] x n[2] interior points starting at grid index lo[]
@@ -81,6 +90,7 @@ typedef struct {
     int32_t profile;        /* non-zero: time each stage with HIP events       */
     sea_dtype nn_weight_dtype; /* learned start: network weights F32 or BF16   */
     void *hip_stream;       /* hipStream_t; NULL = default stream              */
+    sea_decomp ace_decomp;  /* ACE decomposition (default Cholesky)            */
 } sea_opts;
 
 /* Stages timed when opts.profile is set (indices into sea_stage_times). */
@@ -271,7 +281,13 @@ sea_status sea_exx_pair_solve(sea_ctx *ctx, const sea_grid *grid, int n_occ, con
 /* ACE build (Eq. 18, App. A): M = dV Phi^T W (FP64 matrix cores, FP64
  * accumulation), Mbar = (M + M^T)/2, Mbar = L L^T (FP64 Cholesky, no
  * pivoting), xi = W L^{-T} on the matrix cores with operands in ace_dtype
- * (FP32 accumulation for F32/BF16), stored orbital-major in ace_dtype.  M_dev, L_dev: n_occ x n_occ row-major FP64
+ * (FP32 accumulation for F32/BF16), stored orbital-major in ace_dtype.
+ * With opts.ace_decomp = SEA_DECOMP_EIGEN (or AUTO after a failed pivot):
+ * Mbar = Q Lambda Q^T (FP64 Jacobi) and xi = zeta = W Q |Lambda|^{-1/2}
+ * (App. A: the imaginary factor of a negative eigenvalue cancels against
+ * its conjugate, so K = -W Q |Lambda|^{-1} Q^T W^T), null eigenvalues
+ * dropped; L_dev then receives Q |Lambda|^{-1/2} and AUTO returns
+ * SEA_W_EIGEN_FALLBACK.  M_dev, L_dev: n_occ x n_occ row-major FP64
  * (L lower, upper triangle zero).  On a non-positive pivot returns
  * SEA_E_NOT_PD and *failed_pivot = 1-based pivot index (0 on success).
  * ws_dev: sea_ace_workspace_bytes bytes. */
@@ -294,6 +310,14 @@ sea_status sea_ace_apply(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, con
  * ace_dtype converts exactly), FP64 result on the host. */
 sea_status sea_ace_energy(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, const double *phi_dev,
                           const void *xi_dev, void *ws_dev, size_t ws_bytes, double *exx_host);
+
+/* Outer-loop convergence by successive idempotency (App. B):
+ * dI = 1 - sum_ij <phi_new_i, phi_old_j>^2 / n_occ, the inner products in FP64
+ * on the matrix cores.  phi_new_dev, phi_old_dev: n_occ x n_grid FP64.
+ * Workspace: sea_ace_workspace_bytes(n_grid, n_occ, 0).  Synchronizes. */
+sea_status sea_successive_idempotency(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV,
+                                      const double *phi_new_dev, const double *phi_old_dev, void *ws_dev,
+                                      size_t ws_bytes, double *dI_host);
 
 /* ---------------------------------------------------------------------
  * Learned CG warm start (an extension of the CG initial guess of Eq. 9; the

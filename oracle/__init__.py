@@ -18,10 +18,10 @@ the oracle's own reading.
 from .core import (build, lib_path, fd_weights, build_pairs, real_ylm,
                    moments_points, me_eval, neg_lap_padded, cg, pair_potential,
                    exx, cholesky, ace_build, ace_apply, ace_energy,
-                   eps_boxes, eps_pairs, PairList, ExxResult, AceResult)
+                   eps_boxes, eps_pairs, successive_idempotency, PairList, ExxResult, AceResult)
 
 __all__ = ["build", "lib_path", "fd_weights", "build_pairs", "real_ylm",
            "moments_points", "me_eval", "neg_lap_padded", "cg",
            "pair_potential", "exx", "cholesky", "ace_build", "ace_apply",
-           "ace_energy", "eps_boxes", "eps_pairs", "PairList", "ExxResult",
+           "ace_energy", "eps_boxes", "eps_pairs", "successive_idempotency", "PairList", "ExxResult",
            "AceResult"]

@@ -131,6 +131,15 @@ def build_pairs(N, L, centres, r_pair=6.0, half_width=6.0) -> PairList:
     return PairList(out[:k, 0:2].copy(), out[:k, 2:5].copy(), out[:k, 5:8].copy(), org[:k].copy())
 
 
+def successive_idempotency(phi_new, phi_old, dV) -> float:
+    """dI = 1 - Tr[P_new P_old] / Tr[P_new P_new] for the orbital projectors,
+    = 1 - sum_ij <phi_new_i, phi_old_j>^2 / n_occ for orthonormal orbitals (App. B)."""
+    A = phi_new.reshape(phi_new.shape[0], -1)
+    B = phi_old.reshape(phi_old.shape[0], -1)
+    S = dV * (A @ B.T)
+    return 1.0 - float(np.sum(S * S)) / A.shape[0]
+
+
 def eps_boxes(phi, N, eps):
     """Orbital boxes at 1 - eps coverage (Eq. 16): (lo, len), each (n_occ, 3)."""
     lib = _load()
@@ -296,13 +305,26 @@ class AceResult:
     failed_pivot: int
 
 
-def ace_build(phi, W, dV) -> AceResult:
-    """M = <phi_i, W_j>, symmetrize (App. A), Cholesky, xi = W L^{-T} (Eq. 18)."""
+def ace_build(phi, W, dV, decomp="cholesky") -> AceResult:
+    """M = <phi_i, W_j>, symmetrize (App. A), Cholesky, xi = W L^{-T} (Eq. 18).
+
+    decomp="eigen" (App. A): Mbar = Q Lambda Q^T (numpy's symmetric
+    eigensolver), zeta = W Q Lambda^{-1/2} with the imaginary factor of a
+    negative eigenvalue cancelling against its conjugate in |zeta><zeta|, i.e.
+    xi = W Q |Lambda|^{-1/2} and K = -xi xi^T; null eigenvalues (<= 1e-14 of
+    the largest) are dropped.  The L field then holds Q |Lambda|^{-1/2}."""
     import scipy.linalg as sla
     P = phi.reshape(phi.shape[0], -1)
     Wm = W.reshape(W.shape[0], -1)
     M = dV * (P @ Wm.T)
     Mbar = 0.5 * (M + M.T)
+    if decomp == "eigen":
+        lam, Q = np.linalg.eigh(Mbar)
+        a = np.abs(lam)
+        keep = a > 1e-14 * a.max()
+        Zit = np.where(keep[None, :], Q / np.sqrt(np.where(keep, a, 1.0))[None, :], 0.0)
+        # xi (orbital-major): xi_k = sum_i W_i (Q |Lambda|^{-1/2})_ik
+        return AceResult(M, Mbar, Zit, Zit.T @ Wm, 0)
     Lo, fail = cholesky(Mbar)
     if fail:
         return AceResult(M, Mbar, Lo, np.zeros_like(Wm), fail)

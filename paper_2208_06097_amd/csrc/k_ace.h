@@ -7,6 +7,12 @@ hipError_t ace_symmetrize(const double* M, int n, double* Mb, hipStream_t s);
 hipError_t ace_cholesky(const double* A, int n, double* L, int* flag, hipStream_t s);
 hipError_t ace_trtri(const double* L, int n, double* X, hipStream_t s);
 hipError_t ace_neg_sum_squares(const double* S, int mn, double* out, hipStream_t s);
+// Symmetric eigendecomposition (parallel Jacobi, one workgroup): A is
+// overwritten, V gets the eigenvectors in columns, lam the eigenvalues.
+hipError_t ace_eig(double* A, int n, double* V, double* lam, hipStream_t s);
+// T = (Q |Lambda|^{-1/2})^T, null directions dropped.
+hipError_t ace_eig_transform(const double* Q, const double* lam, int n, double* T, hipStream_t s);
+hipError_t ace_transpose(const double* X, int n, double* Y, hipStream_t s);
 
 // Matrix-core versions (k_ace_mfma.hip).  KIND selects the operand type:
 // FP64 (FP64 accumulation), FP32 or BF16 (FP32 accumulation within a K

@@ -91,6 +91,125 @@ __global__ __launch_bounds__(64) void k_trtri_lower(const double* __restrict__ L
     }
 }
 
+// Symmetric eigendecomposition A = Q diag(lambda) Q^T (App. A) by parallel
+// cyclic Jacobi in one workgroup: each round rotates n/2 disjoint (p, q)
+// planes chosen by a round-robin tournament (index 0 fixed, the others
+// rotating), so every pair of indices meets once per sweep; rows, then
+// columns and the eigenvector matrix are updated in separate phases.  The
+// rotation zeroing A[p][q] uses t = tan(angle) = sgn(th)/(|th| + sqrt(th^2
+// + 1)), th = (A[q][q] - A[p][p]) / (2 A[p][q]).  Sweeps stop when the
+// off-diagonal Frobenius norm is below 1e-15 of the whole, or after 40.
+// A (n x n, overwritten), V (n x n, eigenvectors in columns), lam (n).
+constexpr int JB_BS = 1024;
+constexpr int JB_MAXP = 2048;   // pairs per round (n <= 4096)
+
+__global__ __launch_bounds__(JB_BS) void k_jacobi_eig(double* __restrict__ A, int n, double* __restrict__ V,
+                                                      double* __restrict__ lam) {
+    __shared__ double cs[JB_MAXP], sn[JB_MAXP];
+    __shared__ int pp[JB_MAXP], qq[JB_MAXP];
+    __shared__ double red[JB_BS / 64];
+    __shared__ int done;
+    const int m = n + (n & 1);      // even count; index n (if any) is a dummy
+    const int np = m / 2;
+    for (int t = threadIdx.x; t < n * n; t += JB_BS) V[t] = (t / n == t % n) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        // convergence test on the off-diagonal part
+        double off = 0.0, tot = 0.0;
+        for (int t = threadIdx.x; t < n * n; t += JB_BS) {
+            const double v = A[t] * A[t];
+            tot += v;
+            if (t / n != t % n) off += v;
+        }
+        off = wave_sum(off);
+        tot = wave_sum(tot);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = off;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double o2 = 0.0;
+            for (int w = 0; w < JB_BS / 64; ++w) o2 += red[w];
+            red[0] = o2;
+        }
+        __syncthreads();
+        const double offs = red[0];
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tot;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t2 = 0.0;
+            for (int w = 0; w < JB_BS / 64; ++w) t2 += red[w];
+            done = !(offs > 1e-30 * t2);
+        }
+        __syncthreads();
+        if (done) break;
+        for (int r = 0; r < m - 1; ++r) {
+            for (int k = threadIdx.x; k < np; k += JB_BS) {
+                auto idx = [&](int t) { return t == 0 ? 0 : ((t - 1 + r) % (m - 1)) + 1; };
+                int p = idx(k), q = idx(m - 1 - k);
+                if (p > q) { const int tmp = p; p = q; q = tmp; }
+                double c = 1.0, sv = 0.0;
+                if (q < n) {
+                    const double apq = A[(size_t)p * n + q];
+                    if (apq != 0.0) {
+                        const double th = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2.0 * apq);
+                        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        sv = t * c;
+                    }
+                }
+                cs[k] = c;
+                sn[k] = sv;
+                pp[k] = p;
+                qq[k] = q;
+            }
+            __syncthreads();
+            // rows p, q <- P^T A
+            for (int t = threadIdx.x; t < np * n; t += JB_BS) {
+                const int k = t / n, j = t % n;
+                const int p = pp[k], q = qq[k];
+                if (q >= n || sn[k] == 0.0) continue;
+                const double a = A[(size_t)p * n + j], b = A[(size_t)q * n + j];
+                A[(size_t)p * n + j] = cs[k] * a - sn[k] * b;
+                A[(size_t)q * n + j] = sn[k] * a + cs[k] * b;
+            }
+            __syncthreads();
+            // columns p, q <- A P and V P
+            for (int t = threadIdx.x; t < np * n; t += JB_BS) {
+                const int k = t / n, i = t % n;
+                const int p = pp[k], q = qq[k];
+                if (q >= n || sn[k] == 0.0) continue;
+                const double a = A[(size_t)i * n + p], b = A[(size_t)i * n + q];
+                A[(size_t)i * n + p] = cs[k] * a - sn[k] * b;
+                A[(size_t)i * n + q] = sn[k] * a + cs[k] * b;
+                const double va = V[(size_t)i * n + p], vb = V[(size_t)i * n + q];
+                V[(size_t)i * n + p] = cs[k] * va - sn[k] * vb;
+                V[(size_t)i * n + q] = sn[k] * va + cs[k] * vb;
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += JB_BS) lam[i] = A[(size_t)i * n + i];
+}
+
+__global__ void k_transpose(const double* __restrict__ X, int n, double* __restrict__ Y) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * n) return;
+    Y[(size_t)(t % n) * n + t / n] = X[t];
+}
+
+// T[k][i] = Q[i][k] / sqrt(|lambda_k|) (zero for |lambda_k| <= 1e-14 max|lambda|),
+// the map W -> zeta = W Q |Lambda|^{-1/2} in the layout of the xi product.
+__global__ void k_eig_transform(const double* __restrict__ Q, const double* __restrict__ lam, int n,
+                                double* __restrict__ T) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * n) return;
+    const int k = t / n, i = t % n;
+    double lmax = 0.0;
+    for (int q = 0; q < n; ++q) lmax = fmax(lmax, fabs(lam[q]));
+    const double l = fabs(lam[k]);
+    T[t] = l > 1e-14 * lmax ? Q[(size_t)i * n + k] / sqrt(l) : 0.0;
+}
+
 constexpr int SQ_BS = 256;
 
 __global__ __launch_bounds__(SQ_BS) void k_neg_sum_squares(const double* __restrict__ S, int mn, double* out) {
@@ -125,6 +244,22 @@ hipError_t ace_cholesky(const double* A, int n, double* L, int* flag, hipStream_
 hipError_t ace_trtri(const double* L, int n, double* X, hipStream_t s) {
     if (n > TR_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_trtri_lower, dim3(n), dim3(64), 0, s, L, n, X);
+    return hipGetLastError();
+}
+
+hipError_t ace_eig(double* A, int n, double* V, double* lam, hipStream_t s) {
+    if (n > 2 * JB_MAXP) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(JB_BS), 0, s, A, n, V, lam);
+    return hipGetLastError();
+}
+
+hipError_t ace_transpose(const double* X, int n, double* Y, hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose, dim3((n * n + 255) / 256), dim3(256), 0, s, X, n, Y);
+    return hipGetLastError();
+}
+
+hipError_t ace_eig_transform(const double* Q, const double* lam, int n, double* T, hipStream_t s) {
+    hipLaunchKernelGGL(k_eig_transform, dim3((n * n + 255) / 256), dim3(256), 0, s, Q, lam, n, T);
     return hipGetLastError();
 }
 

@@ -52,6 +52,8 @@ sea_status check_opts(sea_ctx* ctx, const sea_opts* o) {
         return fail(ctx, SEA_E_ARG, "bad start");
     if (o->nn_weight_dtype != SEA_F32 && o->nn_weight_dtype != SEA_BF16)
         return fail(ctx, SEA_E_ARG, "nn_weight_dtype must be SEA_F32 or SEA_BF16");
+    if (o->ace_decomp != SEA_DECOMP_CHOLESKY && o->ace_decomp != SEA_DECOMP_EIGEN && o->ace_decomp != SEA_DECOMP_AUTO)
+        return fail(ctx, SEA_E_ARG, "bad ace_decomp");
     if (o->cg_variant < -1 || o->cg_variant >= cg_variant_count())
         return fail(ctx, SEA_E_ARG, "cg_variant must be -1 or 0..%d", cg_variant_count() - 1);
     return SEA_OK;
@@ -274,6 +276,7 @@ void sea_opts_default(sea_opts* o) {
     o->ace_dtype = SEA_F64;
     o->start = SEA_START_ZERO;
     o->cg_variant = -1;
+    o->ace_decomp = SEA_DECOMP_CHOLESKY;
     o->profile = 0;
     o->nn_weight_dtype = SEA_BF16;
     o->hip_stream = nullptr;
@@ -817,7 +820,7 @@ sea_status sea_solid_harmonics_host(int lmax, double x, double y, double z, doub
 namespace {
 
 struct AceLayout {
-    size_t part, mbar, linv, cmat, smat, flag, total;
+    size_t part, mbar, linv, cmat, smat, lam, flag, total;
 };
 
 AceLayout ace_layout(long n_grid, int n_occ, int n_vec) {
@@ -841,6 +844,7 @@ AceLayout ace_layout(long n_grid, int n_occ, int n_vec) {
     L.linv = take((size_t)n_occ * n_occ * sizeof(double));
     L.cmat = take((size_t)n_occ * nv * sizeof(double));
     L.smat = take((size_t)n_occ * n_occ * sizeof(double));
+    L.lam = take((size_t)n_occ * sizeof(double));
     L.flag = take(16 * sizeof(double));
     L.total = off;
     return L;
@@ -888,17 +892,33 @@ sea_status sea_ace_build(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, con
                                                                s)));
         SEA_HIP_CHECK(ctx, ace_symmetrize(M_dev, n_occ, Mb, s));
     }
-    {
-        StageTimer t(ctx, SEA_STAGE_ACE_CHOL, s);
-        SEA_HIP_CHECK(ctx, ace_cholesky(Mb, n_occ, L_dev, flag, s));
-    }
     int hflag = 0;
-    SEA_HIP_CHECK(ctx, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
-    if (failed_pivot) *failed_pivot = hflag;
-    if (hflag) return fail(ctx, SEA_E_NOT_PD, "symmetrized M is not positive definite at pivot %d", hflag);
+    bool eigen = ctx->opts.ace_decomp == SEA_DECOMP_EIGEN;
+    if (!eigen) {
+        {
+            StageTimer t(ctx, SEA_STAGE_ACE_CHOL, s);
+            SEA_HIP_CHECK(ctx, ace_cholesky(Mb, n_occ, L_dev, flag, s));
+        }
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+        if (failed_pivot) *failed_pivot = hflag;
+        if (hflag && ctx->opts.ace_decomp != SEA_DECOMP_AUTO)
+            return fail(ctx, SEA_E_NOT_PD, "symmetrized M is not positive definite at pivot %d", hflag);
+        eigen = hflag != 0;
+    } else if (failed_pivot) {
+        *failed_pivot = 0;
+    }
     StageTimer t(ctx, SEA_STAGE_ACE_XI, s);
-    SEA_HIP_CHECK(ctx, ace_trtri(L_dev, n_occ, Li, s));
+    if (eigen) {
+        // App. A: Mbar = Q Lambda Q^T; the xi product takes (Q |Lambda|^{-1/2})^T
+        double* lam = (double*)(base + Ly.lam);
+        SEA_HIP_CHECK(ctx, ace_eig(Mb, n_occ, L_dev, lam, s));
+        SEA_HIP_CHECK(ctx, ace_eig_transform(L_dev, lam, n_occ, Li, s));
+        // L_dev <- Q |Lambda|^{-1/2} (transpose of Li)
+        SEA_HIP_CHECK(ctx, ace_transpose(Li, n_occ, L_dev, s));
+    } else {
+        SEA_HIP_CHECK(ctx, ace_trtri(L_dev, n_occ, Li, s));
+    }
     // xi (orbital-major) = L^{-1} W
     if (ctx->opts.ace_dtype == SEA_F64)
         SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_F64, double, double>(Li, n_occ, 1, W_dev, n_occ, n_occ, n_grid, 1.0,
@@ -909,6 +929,10 @@ sea_status sea_ace_build(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, con
     else
         SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_BF16, double, uint16_t>(Li, n_occ, 1, W_dev, n_occ, n_occ, n_grid, 1.0,
                                                                   (uint16_t*)xi_dev, s)));
+    if (eigen && ctx->opts.ace_decomp == SEA_DECOMP_AUTO) {
+        fail(ctx, SEA_W_EIGEN_FALLBACK, "Mbar not positive definite (pivot %d): eigen decomposition used", hflag);
+        return SEA_W_EIGEN_FALLBACK;
+    }
     return SEA_OK;
 }
 
@@ -973,6 +997,29 @@ sea_status sea_ace_energy(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, co
     SEA_HIP_CHECK(ctx, hipMemcpyAsync(exx_host, out, sizeof(double), hipMemcpyDeviceToHost, s));
     SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
     if (!std::isfinite(*exx_host)) return fail(ctx, SEA_E_NONFINITE, "non-finite ACE energy");
+    return SEA_OK;
+}
+
+sea_status sea_successive_idempotency(sea_ctx* ctx, int64_t n_grid, int n_occ, double dV, const double* phi_new_dev,
+                                      const double* phi_old_dev, void* ws_dev, size_t ws_bytes, double* dI_host) {
+    if (!ctx) return SEA_E_ARG;
+    const AceLayout Ly = ace_layout(n_grid, n_occ, n_occ);
+    sea_status st = check_ace(ctx, n_grid, n_occ, dV, ws_bytes, Ly, ws_dev);
+    if (st != SEA_OK) return st;
+    if (!phi_new_dev || !phi_old_dev || !dI_host) return fail(ctx, SEA_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    char* base = (char*)ws_dev;
+    double* part = (double*)(base + Ly.part);
+    double* S = (double*)(base + Ly.smat);
+    double* out = (double*)(base + Ly.flag);
+    SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_F64, double, double>(phi_new_dev, phi_old_dev, n_occ, n_occ, n_grid, dV, part,
+                                                           S, s)));
+    SEA_HIP_CHECK(ctx, ace_neg_sum_squares(S, n_occ * n_occ, out, s));
+    double neg = 0.0;
+    SEA_HIP_CHECK(ctx, hipMemcpyAsync(&neg, out, sizeof(double), hipMemcpyDeviceToHost, s));
+    SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+    *dI_host = 1.0 + neg / n_occ;
+    if (!std::isfinite(*dI_host)) return fail(ctx, SEA_E_NONFINITE, "non-finite idempotency change");
     return SEA_OK;
 }
 

@@ -15,10 +15,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsea.so")
 
-SEA_OK, SEA_W_NOT_CONVERGED = 0, 1
+SEA_OK, SEA_W_NOT_CONVERGED, SEA_W_EIGEN_FALLBACK = 0, 1, 2
 SEA_E_ARG, SEA_E_HIP, SEA_E_NOMEM, SEA_E_NOT_PD, SEA_E_NONFINITE = -1, -2, -3, -4, -5
 SEA_F64, SEA_F32, SEA_BF16 = 0, 1, 2
 SEA_START_ZERO, SEA_START_MULTIPOLE, SEA_START_LEARNED = 0, 1, 2
+SEA_DECOMP_CHOLESKY, SEA_DECOMP_EIGEN, SEA_DECOMP_AUTO = 0, 1, 2
 
 # exported symbols declared in include/sea.h
 EXPORTS = [
@@ -32,6 +33,7 @@ EXPORTS = [
     "sea_exx_plan_create", "sea_exx_plan_launch", "sea_exx_plan_results", "sea_exx_plan_destroy",
     "sea_cg_variant_count", "sea_cg_variant_name", "sea_exx_autotune",
     "sea_nn_infer_workspace_bytes", "sea_nn_infer", "sea_eps_workspace_bytes", "sea_build_pairs_eps",
+    "sea_successive_idempotency",
 ]
 
 # the network's layers (name, c_in, c_out, relu), in parameter order
@@ -76,7 +78,7 @@ class SeaOpts(C.Structure):
     _fields_ = [("fd_half_order", C.c_int32), ("lmax", C.c_int32), ("rel_tol", C.c_double),
                 ("max_iter", C.c_int32), ("stencil_dtype", C.c_int), ("ace_dtype", C.c_int),
                 ("start", C.c_int), ("cg_variant", C.c_int32), ("profile", C.c_int32),
-                ("nn_weight_dtype", C.c_int), ("hip_stream", C.c_void_p)]
+                ("nn_weight_dtype", C.c_int), ("hip_stream", C.c_void_p), ("ace_decomp", C.c_int)]
 
 
 class SeaCell(C.Structure):
@@ -148,6 +150,7 @@ def load() -> C.CDLL:
     lib.sea_nn_infer_workspace_bytes.argtypes = [vp, i, P(sz)]
     lib.sea_nn_infer.argtypes = [vp, vp, i, vp, vp, vp, sz]
     lib.sea_eps_workspace_bytes.argtypes = [vp, P(SeaGrid), i, P(sz)]
+    lib.sea_successive_idempotency.argtypes = [vp, C.c_int64, i, d, vp, vp, vp, sz, P(d)]
     lib.sea_build_pairs_eps.argtypes = [vp, P(SeaGrid), i, vp, i, d, d, i, vp, sz, vp, vp, vp, i, P(i)]
     _lib = lib
     return lib
@@ -201,7 +204,7 @@ class Context:
 
     def __init__(self, rel_tol=1e-8, max_iter=10000, lmax=6, stencil_dtype=SEA_F64,
                  ace_dtype=SEA_F64, start=SEA_START_ZERO, cg_variant=-1, profile=False,
-                 nn_weight_dtype=SEA_BF16, stream=None):
+                 nn_weight_dtype=SEA_BF16, stream=None, ace_decomp=SEA_DECOMP_CHOLESKY):
         import torch
         self._torch = torch
         self.lib = load()
@@ -211,6 +214,7 @@ class Context:
         o.stencil_dtype, o.ace_dtype, o.start, o.cg_variant = stencil_dtype, ace_dtype, start, cg_variant
         o.profile = 1 if profile else 0
         o.nn_weight_dtype = nn_weight_dtype
+        o.ace_decomp = ace_decomp
         if stream is None:
             stream = torch.cuda.current_stream()
         o.hip_stream = C.c_void_p(stream.cuda_stream)
@@ -443,7 +447,9 @@ class Context:
         return {SEA_F64: torch.float64, SEA_F32: torch.float32, SEA_BF16: torch.bfloat16}[self.opts.ace_dtype]
 
     def ace_build(self, phi, W, dV, ws=None):
-        """Returns (M, L, xi, failed_pivot); raises SeaError on a non-PD M."""
+        """Returns (M, L, xi, failed_pivot); raises SeaError on a non-PD M
+        with the Cholesky decomposition.  self.last_status holds the status
+        (SEA_W_EIGEN_FALLBACK when the AUTO decomposition fell back)."""
         torch = self._torch
         n_occ = phi.shape[0]
         ng = phi.numel() // n_occ
@@ -455,7 +461,7 @@ class Context:
         fp = C.c_int(0)
         st = self.lib.sea_ace_build(self.h, ng, n_occ, dV, phi.data_ptr(), W.data_ptr(), ws.data_ptr(), ws.numel(),
                                     M.data_ptr(), Lm.data_ptr(), xi.data_ptr(), C.byref(fp))
-        self._check(st)
+        self.last_status = self._check(st)
         return M, Lm, xi, fp.value
 
     def ace_apply(self, xi, psi, dV, ws=None):
@@ -483,6 +489,18 @@ class Context:
                                      ws.numel(), C.byref(E))
         self._check(st)
         return E.value
+
+    def successive_idempotency(self, phi_new, phi_old, dV, ws=None) -> float:
+        """dI = 1 - sum_ij <phi_new_i, phi_old_j>^2 / n_occ (App. B)."""
+        n_occ = phi_new.shape[0]
+        ng = phi_new.numel() // n_occ
+        if ws is None:
+            ws = self.workspace(self.ace_workspace_bytes(ng, n_occ, 0))
+        dI = C.c_double(0.0)
+        self._check(self.lib.sea_successive_idempotency(self.h, ng, n_occ, dV, phi_new.data_ptr(),
+                                                        phi_old.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                        C.byref(dI)))
+        return dI.value
 
     # ---------------------------------------------------------------- network
     def nn_param_count(self) -> int:

@@ -328,3 +328,73 @@ def test_multipole_start_same_result_fewer_iterations(mini, dtype):
     assert abs(E1 - ref.E) < 1e-6
     assert np.max(np.abs(W1.cpu().numpy() - ref.W)) < 1e-5
     assert s1["iters"].mean() < s0["iters"].mean()
+
+
+def _eig_case(n=150, N=21, dV=0.3 ** 3, seed=6, mixed=True):
+    rng = np.random.default_rng(seed)
+    ng = N ** 3
+    Qf, _ = np.linalg.qr(rng.standard_normal((ng, n)))
+    phi = Qf.T / np.sqrt(dV)
+    lam = rng.uniform(0.2, 3.0, n)
+    if mixed:
+        lam[rng.choice(n, n // 5, replace=False)] *= -1.0
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    G = U @ np.diag(lam) @ U.T
+    return phi, G @ phi, dV, rng.standard_normal((40, ng)) / np.sqrt(ng * dV)
+
+
+@pytest.mark.parametrize("decomp", ["eigen", "auto"])
+def test_ace_eigen_scheme_matches_oracle(decomp):
+    """App. A on the GPU (parallel Jacobi) for a symmetrized M with negative
+    eigenvalues: K psi and E_ACE against the oracle's eigen scheme (invariant
+    to eigenvector order and signs); AUTO reports the fallback."""
+    print(f"case ace eigen scheme {decomp}", flush=True)
+    phi, W, dV, psi = _eig_case()
+    want = oracle.ace_build(phi, W, dV, decomp="eigen")
+    dc = sea.SEA_DECOMP_EIGEN if decomp == "eigen" else sea.SEA_DECOMP_AUTO
+    c = sea.Context(ace_decomp=dc)
+    M, Lm, xi, fp = c.ace_build(_dev(phi), _dev(W), dV)
+    assert c.last_status == (sea.SEA_OK if decomp == "eigen" else sea.SEA_W_EIGEN_FALLBACK)
+    K = c.ace_apply(xi, _dev(psi), dV).cpu().numpy()
+    Kw = oracle.ace_apply(want.xi, psi, dV)
+    assert np.linalg.norm(K - Kw) <= 1e-10 * np.linalg.norm(Kw)
+    E = c.ace_energy(_dev(phi), xi, dV)
+    assert abs(E - oracle.ace_energy(phi, want.xi, dV)) <= 1e-10 * abs(E)
+    # L_dev holds Q |Lambda|^{-1/2}: (Q|L|^-1/2)(Q|L|^-1/2)^T = Q |Lambda|^-1 Q^T = |Mbar|^-1
+    Z = Lm.cpu().numpy()
+    lam, Q = np.linalg.eigh(want.Mbar)
+    assert np.allclose(Z @ Z.T, Q @ np.diag(1 / np.abs(lam)) @ Q.T, atol=1e-9)
+    c.close()
+
+
+def test_ace_eigen_scheme_equals_cholesky_when_positive_definite():
+    print("case ace eigen vs cholesky (PD)", flush=True)
+    phi, W, dV, psi = _eig_case(mixed=False)
+    out = []
+    for dc in (sea.SEA_DECOMP_CHOLESKY, sea.SEA_DECOMP_EIGEN, sea.SEA_DECOMP_AUTO):
+        c = sea.Context(ace_decomp=dc)
+        _, _, xi, fp = c.ace_build(_dev(phi), _dev(W), dV)
+        assert fp == 0 and c.last_status == sea.SEA_OK
+        out.append(c.ace_apply(xi, _dev(psi), dV).cpu().numpy())
+        c.close()
+    assert np.linalg.norm(out[1] - out[0]) <= 1e-10 * np.linalg.norm(out[0])
+    assert np.array_equal(out[2], out[0])
+
+
+def test_successive_idempotency():
+    """App. B: dI = 0 for the same occupied space in any orthonormal basis,
+    the oracle's value otherwise."""
+    print("case successive idempotency", flush=True)
+    rng = np.random.default_rng(8)
+    n, ng, dV = 150, 21 ** 3, 0.3 ** 3
+    Q, _ = np.linalg.qr(rng.standard_normal((ng, n)))
+    phi = Q.T / np.sqrt(dV)
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    c = sea.Context()
+    assert abs(c.successive_idempotency(_dev(phi), _dev(phi), dV)) < 1e-12
+    assert abs(c.successive_idempotency(_dev(U @ phi), _dev(phi), dV)) < 1e-12
+    Q2, _ = np.linalg.qr(Q + 0.05 * rng.standard_normal((ng, n)))
+    phi2 = Q2.T / np.sqrt(dV)
+    d = c.successive_idempotency(_dev(phi2), _dev(phi), dV)
+    assert abs(d - oracle.successive_idempotency(phi2, phi, dV)) < 1e-12 and d > 1e-4
+    c.close()

@@ -446,3 +446,34 @@ def test_exx_wrapped_domain_wider_than_cell():
     res = oracle.exx(cell.phi, cell.N, cell.L, pl, tol=1e-11)
     M = cell.h ** 3 * cell.phi.reshape(cell.n_occ, -1) @ res.W.reshape(cell.n_occ, -1).T
     assert abs(res.E / -np.trace(M) - 1) < 1e-12
+
+
+def test_ace_eigen_scheme_closed_form():
+    """App. A scheme on a constructed case: orthonormal orbitals Phi and
+    W = G Phi with G symmetric of mixed-sign spectrum give Mbar = G, and
+    K = -xi xi^T acts on u_k = sum_m Q_mk phi_m as -|lambda_k| (eigen
+    scheme); the Cholesky scheme reports the non-positive pivot.  For a
+    positive definite G both schemes give the same K."""
+    rng = np.random.default_rng(5)
+    n, ng, dV = 12, 400, 0.5
+    A = rng.standard_normal((ng, n))
+    Qf, _ = np.linalg.qr(A)
+    phi = Qf.T / np.sqrt(dV)                       # dV phi phi^T = I
+    lam = np.array([3.0, 2.5, 2.0, 1.5, 1.0, 0.8, 0.5, 0.3, -0.2, -0.7, -1.1, 0.05])
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    G = U @ np.diag(lam) @ U.T
+    W = G @ phi
+    res = oracle.ace_build(phi, W, dV, decomp="eigen")
+    assert np.allclose(res.Mbar, G, atol=1e-12)
+    K = lambda v: -res.xi.T @ (dV * (res.xi @ v))   # noqa: E731
+    for k in range(n):
+        u = U[:, k] @ phi
+        assert np.allclose(K(u), -abs(lam[k]) * u, atol=1e-10)
+    assert oracle.ace_build(phi, W, dV).failed_pivot > 0
+    Gp = U @ np.diag(np.abs(lam)) @ U.T
+    Wp = Gp @ phi
+    r1 = oracle.ace_build(phi, Wp, dV, decomp="eigen")
+    r2 = oracle.ace_build(phi, Wp, dV)
+    K1 = r1.xi.T @ r1.xi
+    K2 = r2.xi.T @ r2.xi
+    assert np.allclose(K1, K2, atol=1e-10)
