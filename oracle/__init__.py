@@ -8,7 +8,9 @@ product path: it shares only the seeded input generator.
 The heavy part (pair density, multipoles, boundary values, CG, scatter) is
 plain C in ``sea_oracle.c`` (built with gcc by ``build()``); the ACE algebra
 is written here with NumPy/SciPy library primitives (matmul, triangular
-solve) around the oracle's own Cholesky.
+solve) around the oracle's own Cholesky, and so is SCDM (its pivoted QR
+written out as the greedy column choice, numpy's eigensolver for the inverse
+square root).
 
 Every pinned function is checked in ``tests/test_oracle_*.py`` against closed
 forms, brute force or textbook library routines.  Parity unpinned: the C1
@@ -18,10 +20,11 @@ the oracle's own reading.
 from .core import (build, lib_path, fd_weights, build_pairs, real_ylm,
                    moments_points, me_eval, neg_lap_padded, cg, pair_potential,
                    exx, cholesky, ace_build, ace_apply, ace_energy,
-                   eps_boxes, eps_pairs, successive_idempotency, PairList, ExxResult, AceResult)
+                   eps_boxes, eps_pairs, successive_idempotency, scdm_pivots, scdm, back_rotate,
+                   qrcp_residual_norms, PairList, ExxResult, AceResult, ScdmResult)
 
 __all__ = ["build", "lib_path", "fd_weights", "build_pairs", "real_ylm",
            "moments_points", "me_eval", "neg_lap_padded", "cg",
            "pair_potential", "exx", "cholesky", "ace_build", "ace_apply",
-           "ace_energy", "eps_boxes", "eps_pairs", "successive_idempotency", "PairList", "ExxResult",
-           "AceResult"]
+           "ace_energy", "eps_boxes", "eps_pairs", "successive_idempotency", "scdm_pivots", "scdm",
+           "back_rotate", "qrcp_residual_norms", "PairList", "ExxResult", "AceResult", "ScdmResult"]

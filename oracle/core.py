@@ -347,3 +347,80 @@ def ace_energy(phi, xi, dV) -> float:
     X = xi.reshape(xi.shape[0], -1)
     S = dV * (P @ X.T)
     return -float(np.sum(S * S))
+
+
+@dataclasses.dataclass
+class ScdmResult:
+    piv: np.ndarray      # (n_occ,) selected grid columns C, in pivot order
+    rdiag: np.ndarray    # (n_occ,) |R_kk|: norm of the pivot column after the earlier ones are removed
+    U: np.ndarray        # (n_occ, n_occ) Eq. 5
+    phi_loc: np.ndarray  # orbital-major, Eq. 6: phi_loc_k = sum_j phi_j U_jk
+
+
+def scdm_pivots(phi):
+    """Column-pivoted QR of Phi^T (Eq. 1), pivots only.
+
+    Phi^T is n_occ x N_grid (row i = orbital i, column g = grid point g).  At
+    step k the pivot is the column whose part orthogonal to the k columns
+    already chosen is longest (first index on ties); that part, normalized,
+    becomes the k-th column of Q, and its length is |R_kk|.  Written with an
+    explicit residual matrix: every remaining column loses its component
+    along the new Q column, and the norms are summed afresh each step."""
+    A = np.asarray(phi, dtype=np.float64).reshape(phi.shape[0], -1)
+    n, ng = A.shape
+    if ng < n:
+        raise ValueError("fewer grid points than orbitals")
+    res = A.copy()
+    chosen = np.zeros(ng, dtype=bool)
+    piv = np.zeros(n, dtype=np.int64)
+    rdiag = np.zeros(n)
+    for k in range(n):
+        norms = np.einsum("ij,ij->j", res, res)
+        norms[chosen] = -1.0
+        c = int(np.argmax(norms))
+        r = float(np.sqrt(norms[c]))
+        if not r > 0.0:
+            raise ValueError(f"Phi^T has rank {k} < n_occ")
+        q = res[:, c] / r
+        res -= np.outer(q, q @ res)
+        chosen[c] = True
+        piv[k], rdiag[k] = c, r
+    return piv, rdiag
+
+
+def scdm(phi) -> ScdmResult:
+    """SCDM localization (Eq. 1-6).
+
+    B = (Phi^T)_{:,C} holds the orbitals at the selected points; the proto
+    orbitals X = Phi B (Eq. 2) are orthogonalized with P_CC^{-1/2} (Eq. 3),
+    where P_CC is the density matrix at the selected points, B^T B (equal to
+    X^T X for orbitals orthonormal as grid vectors); then U = B P_CC^{-1/2}
+    (Eq. 5) is orthogonal for any Phi of full rank, and phi_loc = Phi U
+    (Eq. 6).  The inverse square root uses numpy's symmetric eigensolver."""
+    A = np.asarray(phi, dtype=np.float64).reshape(phi.shape[0], -1)
+    piv, rdiag = scdm_pivots(A)
+    B = A[:, piv]
+    lam, V = np.linalg.eigh(B.T @ B)
+    P_mhalf = (V / np.sqrt(lam)[None, :]) @ V.T
+    U = B @ P_mhalf
+    phi_loc = (U.T @ A).reshape(phi.shape)
+    return ScdmResult(piv, rdiag, U, phi_loc)
+
+
+def back_rotate(D_loc, U):
+    """D^i = sum_j D_loc^j (U^{-1})_ji (Eq. 15), orbital-major in and out;
+    U^{-1} by numpy's general inverse."""
+    Dm = np.asarray(D_loc, dtype=np.float64).reshape(D_loc.shape[0], -1)
+    return (np.linalg.inv(U).T @ Dm).reshape(D_loc.shape)
+
+
+def qrcp_residual_norms(phi, prefix):
+    """Squared norms of every column of Phi^T after removing its components
+    along the columns ``prefix`` (brute force: orthonormal basis of the
+    prefix columns by numpy's QR, then a projection)."""
+    A = np.asarray(phi, dtype=np.float64).reshape(phi.shape[0], -1)
+    if len(prefix) == 0:
+        return np.einsum("ij,ij->j", A, A)
+    Qp, _ = np.linalg.qr(A[:, np.asarray(prefix)])
+    R = A - Qp @ (Qp.T @ A)
+    return np.einsum("ij,ij->j", R, R)

@@ -203,6 +203,24 @@ def mini(seed: int = 7, n_mol: int = 3, L: float = 9.0, N: int = 30,
     return fill_orbitals(cell) if with_phi else cell
 
 
+def random_rotation(n: int, seed: int) -> np.ndarray:
+    """Seeded dense orthogonal n x n matrix: the Cayley transform
+    (I - S)^{-1} (I + S) of an antisymmetric S with standard-normal entries.
+    Rotating localized orbitals by it gives delocalized orbitals that span
+    the same space (the stand-in for canonical orbitals)."""
+    rng = np.random.default_rng(seed)
+    R = rng.standard_normal((n, n))
+    S = 0.5 * (R - R.T)
+    eye = np.eye(n)
+    return np.linalg.solve(eye - S, eye + S)
+
+
+def rotate(phi: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """Orbital-major rotation: out_k = sum_j phi_j G_jk."""
+    A = phi.reshape(phi.shape[0], -1)
+    return (G.T @ A).reshape(phi.shape).astype(phi.dtype)
+
+
 def trial_vectors(cell: Cell, seed: int) -> np.ndarray:
     """Fresh orbitals of the same recipe (another seed) used as ACE trial vectors."""
     other = make_centres(cell.o_centres.shape[0], cell.L, cell.N, seed)
