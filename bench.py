@@ -263,7 +263,10 @@ def main():
         pe, _, dbe = ce.build_pairs_eps(phi, cell.N, cell.L, eps, eps, pad=6, with_dbox=True)
         t_pairs = 1000 * (time.perf_counter() - t1)
         wse = ce.workspace(ce.exx_batched_workspace_bytes([(phi, cell.N, cell.L, pe, W, exx_dev, dbe)]))
-        ce.autotune([(phi, cell.N, cell.L, pe)], sample_pairs=args.tune_pairs, iters=20, ws=wse)
+        if args.cg_variant:
+            ce.set_opts(cg_variant=ce.cg_variants().index(args.cg_variant))
+        else:
+            ce.autotune([(phi, cell.N, cell.L, pe)], sample_pairs=args.tune_pairs, iters=20, ws=wse)
         re_ = ce.exx_action(phi, cell.N, cell.L, pe, ws=wse, W=W, exx_dev=exx_dev, want_host=True, dbox=dbe)
         torch.cuda.synchronize()
         t1 = time.perf_counter()

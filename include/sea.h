@@ -40,7 +40,8 @@ typedef enum {
     SEA_E_HIP = -2,          /* HIP runtime error                               */
     SEA_E_NOMEM = -3,        /* workspace smaller than *_workspace_bytes        */
     SEA_E_NOT_PD = -4,       /* symmetrized M not positive definite (ACE)       */
-    SEA_E_NONFINITE = -5     /* NaN/Inf in an input or a reduction              */
+    SEA_E_NONFINITE = -5,    /* NaN/Inf in an input or a reduction              */
+    SEA_E_RANK = -6          /* Phi^T has rank < n_occ (SCDM pivoted QR)        */
 } sea_status;
 
 typedef enum { SEA_F64 = 0, SEA_F32 = 1, SEA_BF16 = 2 } sea_dtype;
@@ -106,7 +107,9 @@ typedef enum {
     SEA_STAGE_ACE_XI = 8,   /* xi = W L^{-T}                                   */
     SEA_STAGE_ACE_APPLY = 9,/* K psi                                           */
     SEA_STAGE_FINISH = 10,  /* FP32 state: true FP64 residual and e_ij per pair */
-    SEA_STAGE_COUNT = 11
+    SEA_STAGE_SCDM = 11,    /* SCDM pivoted QR, P_CC^{-1/2} and U              */
+    SEA_STAGE_ROTATE = 12,  /* orbital rotation by U or U^{-1}                 */
+    SEA_STAGE_COUNT = 13
 } sea_stage;
 
 /* Per-pair diagnostics (Eq. 8 and Eq. 17 quantities on the pair domain). */
@@ -318,6 +321,48 @@ sea_status sea_ace_energy(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, co
 sea_status sea_successive_idempotency(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV,
                                       const double *phi_new_dev, const double *phi_old_dev, void *ws_dev,
                                       size_t ws_bytes, double *dI_host);
+
+/* ---------------------------------------------------------------------
+ * SCDM localization (Sec. II.A) and the rotations between orbital sets.
+ * --------------------------------------------------------------------- */
+
+/* Workspace of sea_scdm for n_occ orbitals on n_grid points. */
+sea_status sea_scdm_workspace_bytes(sea_ctx *ctx, int64_t n_grid, int n_occ, size_t *bytes);
+
+/* Selected columns of the density matrix (Eq. 1-6).  phi_dev: n_occ x
+ * n_grid orbital-major (row i = orbital i), phi_dtype F64 or F32, read as
+ * the rows of Phi^T.  Eq. 1: column-pivoted QR of Phi^T, pivots only, in
+ * FP64 (each pivot is the column whose part orthogonal to the columns
+ * already chosen is longest, first grid index on ties); Eq. 3-5 with
+ * B = (Phi^T)_{:,C} and P_CC = B^T B (the density matrix at the selected
+ * points; X^T X for orbitals orthonormal as grid vectors), so that
+ * U = B P_CC^{-1/2} is orthogonal; P_CC^{-1/2} by FP64 Jacobi.
+ * Outputs:
+ *   U_dev       n_occ x n_occ FP64 row-major, U[j*n_occ + k] = U_jk;
+ *   phi_loc_dev (nullable) n_occ x n_grid in phi_dtype, Eq. 6:
+ *               phi_loc_k = sum_j phi_j U_jk (FP64 matrix cores for F64,
+ *               FP32 for F32); must not overlap phi_dev;
+ *   piv_host    (nullable) n_occ int32 grid indices C in pivot order;
+ *   rdiag_host  (nullable) n_occ doubles |R_kk|;
+ *   rounds_host (nullable) number of passes over Phi^T (pivots are chosen
+ *               in rounds: each round ends when the best candidate no
+ *               longer provably beats every column outside the candidate
+ *               set, then all column norms are brought up to date).
+ * n_occ <= 2048, n_grid >= n_occ.  SEA_E_RANK when a residual column
+ * norm^2 drops below 1e-26 of the largest initial one.  ws_dev:
+ * sea_scdm_workspace_bytes bytes.  Synchronizes once per round. */
+sea_status sea_scdm(sea_ctx *ctx, int64_t n_grid, int n_occ, const void *phi_dev, sea_dtype phi_dtype,
+                    void *ws_dev, size_t ws_bytes, double *U_dev, void *phi_loc_dev, int32_t *piv_host,
+                    double *rdiag_host, int *rounds_host);
+
+/* Orbital rotation, orbital-major X and Y (n_occ x n_grid, dtype F64 or
+ * F32, not overlapping), U from sea_scdm (orthogonal):
+ *   inverse = 0:  Y_k = sum_j X_j U_jk             (Eq. 6, into the SCDM set)
+ *   inverse = 1:  Y_i = sum_j X_j (U^{-1})_ji      (Eq. 15, back-rotation
+ *                 of W or D_xx to the input set; U^{-1} = U^T).
+ * Matrix cores, FP64 for F64 and FP32 for F32.  Asynchronous. */
+sea_status sea_rotate(sea_ctx *ctx, int64_t n_grid, int n_occ, sea_dtype dtype, const double *U_dev,
+                      int inverse, const void *X_dev, void *Y_dev);
 
 /* ---------------------------------------------------------------------
  * Learned CG warm start (an extension of the CG initial guess of Eq. 9; the

@@ -1026,6 +1026,158 @@ sea_status sea_successive_idempotency(sea_ctx* ctx, int64_t n_grid, int n_occ, d
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// SCDM localization (Eq. 1-6) and the rotations of Eq. 6 and Eq. 15
+
+#include "k_scdm.h"
+
+namespace {
+
+struct ScdmFull {
+    ScdmLayout piv;          // pivot search (k_scdm.hip)
+    size_t G, P, V, lam, T, Pmh, part, total;
+};
+
+ScdmFull scdm_full_layout(long Ng, int n) {
+    ScdmFull L{};
+    L.piv = scdm_layout(Ng, n);
+    size_t off = L.piv.total;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t nn = (size_t)n * n * sizeof(double);
+    L.G = take(nn);
+    L.P = take(nn);
+    L.V = take(nn);
+    L.lam = take((size_t)n * sizeof(double));
+    L.T = take(nn);
+    L.Pmh = take(nn);
+    L.part = take((size_t)ace_mfma_splits(n, n, n) * nn);
+    L.total = off;
+    return L;
+}
+
+sea_status check_rot(sea_ctx* ctx, int64_t n_grid, int n_occ, sea_dtype dt) {
+    if (n_occ < 1 || n_occ > SC_NMAX) return fail(ctx, SEA_E_ARG, "n_occ must be in [1, %d]", SC_NMAX);
+    if (n_grid < n_occ) return fail(ctx, SEA_E_ARG, "n_grid < n_occ: Phi^T cannot have full row rank");
+    if (n_grid > 0x7fffffffLL) return fail(ctx, SEA_E_ARG, "n_grid beyond 2^31 - 1");
+    if (dt != SEA_F64 && dt != SEA_F32) return fail(ctx, SEA_E_ARG, "orbitals must be F64 or F32");
+    return SEA_OK;
+}
+
+// Y = A X with A(r, c) = U[r*sr + c*sc] (n x n) and X, Y orbital-major.
+hipError_t rotate_rows(const double* U, long sr, long sc, sea_dtype dt, int n, long Ng, const void* X, void* Y,
+                       hipStream_t s) {
+    if (dt == SEA_F64)
+        return ace_mm_nn<ACE_F64, double, double>(U, sr, sc, (const double*)X, n, n, Ng, 1.0, (double*)Y, s);
+    return ace_mm_nn<ACE_F32, float, float>(U, sr, sc, (const float*)X, n, n, Ng, 1.0, (float*)Y, s);
+}
+
+}  // namespace
+
+extern "C" sea_status sea_scdm_workspace_bytes(sea_ctx* ctx, int64_t n_grid, int n_occ, size_t* bytes) {
+    if (!ctx || !bytes) return SEA_E_ARG;
+    sea_status st = check_rot(ctx, n_grid, n_occ, SEA_F64);
+    if (st != SEA_OK) return st;
+    *bytes = scdm_full_layout(n_grid, n_occ).total;
+    return SEA_OK;
+}
+
+extern "C" sea_status sea_scdm(sea_ctx* ctx, int64_t n_grid, int n_occ, const void* phi_dev, sea_dtype phi_dtype,
+                               void* ws_dev, size_t ws_bytes, double* U_dev, void* phi_loc_dev, int32_t* piv_host,
+                               double* rdiag_host, int* rounds_host) {
+    if (!ctx) return SEA_E_ARG;
+    sea_status st = check_rot(ctx, n_grid, n_occ, phi_dtype);
+    if (st != SEA_OK) return st;
+    if (!phi_dev || !U_dev || !ws_dev) return fail(ctx, SEA_E_ARG, "NULL array argument");
+    const ScdmFull L = scdm_full_layout(n_grid, n_occ);
+    if (ws_bytes < L.total) return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    if (phi_loc_dev) {
+        const size_t es = phi_dtype == SEA_F64 ? 8 : 4;
+        const char *a = (const char*)phi_dev, *b = (const char*)phi_loc_dev;
+        const size_t len = (size_t)n_grid * n_occ * es;
+        if (a < b + len && b < a + len) return fail(ctx, SEA_E_ARG, "phi_loc_dev overlaps phi_dev");
+    }
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    char* ws = (char*)ws_dev;
+    const int f32 = phi_dtype == SEA_F32;
+    const int n = n_occ;
+    const long Ng = (long)n_grid;
+    ctx->ev_used[SEA_STAGE_SCDM] = false;
+    ctx->ev_used[SEA_STAGE_ROTATE] = false;
+    int k = 0, fl = 0, rounds = 0;
+    {
+        StageTimer t(ctx, SEA_STAGE_SCDM, s);
+        // Eq. 1: pivots, one pass over Phi^T per round
+        SEA_HIP_CHECK(ctx, scdm_init(phi_dev, f32, Ng, n, ws, L.piv, s));
+        int k0 = 0;
+        for (;;) {
+            SEA_HIP_CHECK(ctx, scdm_round(phi_dev, f32, Ng, n, rounds == 0, ws, L.piv, s));
+            SEA_HIP_CHECK(ctx, scdm_read_state(ws, L.piv, &k, &fl, s));
+            ++rounds;
+            if (fl) break;
+            if (k >= n) break;
+            if (k <= k0 || k - k0 > SC_RB)
+                return fail(ctx, SEA_E_HIP, "SCDM round made no progress (pivots %d -> %d)", k0, k);
+            SEA_HIP_CHECK(ctx, scdm_update(phi_dev, f32, Ng, n, k0, k - k0, ws, L.piv, s));
+            k0 = k;
+        }
+        if (fl)
+            return fail(ctx, SEA_E_RANK, "Phi^T is rank deficient: no independent column left at pivot %d", fl);
+        // Eq. 3-5: G = B^T (row a = orbitals at point c_a), P_CC = G G^T,
+        // P_CC^{-1/2} = V (V |Lambda|^{-1/2})^T, U = B P_CC^{-1/2}
+        const int* piv = (const int*)(ws + L.piv.piv);
+        double* G = (double*)(ws + L.G);
+        double* P = (double*)(ws + L.P);
+        double* V = (double*)(ws + L.V);
+        double* lam = (double*)(ws + L.lam);
+        double* T = (double*)(ws + L.T);
+        double* Pmh = (double*)(ws + L.Pmh);
+        double* part = (double*)(ws + L.part);
+        SEA_HIP_CHECK(ctx, scdm_pivot_rows(phi_dev, f32, Ng, n, piv, G, s));
+        SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_F64, double, double>(G, G, n, n, n, 1.0, part, P, s)));
+        SEA_HIP_CHECK(ctx, ace_eig(P, n, V, lam, s));
+        SEA_HIP_CHECK(ctx, ace_eig_transform(V, lam, n, T, s));
+        SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_F64, double, double>(V, n, 1, T, n, n, n, 1.0, Pmh, s)));
+        SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_F64, double, double>(G, 1, n, Pmh, n, n, n, 1.0, U_dev, s)));
+    }
+    if (phi_loc_dev) {
+        StageTimer t(ctx, SEA_STAGE_ROTATE, s);
+        // Eq. 6: phi_loc_k = sum_j phi_j U_jk
+        SEA_HIP_CHECK(ctx, rotate_rows(U_dev, 1, n, phi_dtype, n, Ng, phi_dev, phi_loc_dev, s));
+    }
+    if (piv_host)
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(piv_host, ws + L.piv.piv, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (rdiag_host)
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(rdiag_host, ws + L.piv.rdiag, (size_t)n * sizeof(double),
+                                          hipMemcpyDeviceToHost, s));
+    if (piv_host || rdiag_host) SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+    if (rounds_host) *rounds_host = rounds;
+    return SEA_OK;
+}
+
+extern "C" sea_status sea_rotate(sea_ctx* ctx, int64_t n_grid, int n_occ, sea_dtype dtype, const double* U_dev,
+                                 int inverse, const void* X_dev, void* Y_dev) {
+    if (!ctx) return SEA_E_ARG;
+    sea_status st = check_rot(ctx, n_grid, n_occ, dtype);
+    if (st != SEA_OK) return st;
+    if (!U_dev || !X_dev || !Y_dev) return fail(ctx, SEA_E_ARG, "NULL array argument");
+    if (inverse != 0 && inverse != 1) return fail(ctx, SEA_E_ARG, "inverse must be 0 or 1");
+    const size_t len = (size_t)n_grid * n_occ * (dtype == SEA_F64 ? 8 : 4);
+    const char *a = (const char*)X_dev, *b = (const char*)Y_dev;
+    if (a < b + len && b < a + len) return fail(ctx, SEA_E_ARG, "Y_dev overlaps X_dev");
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    ctx->ev_used[SEA_STAGE_ROTATE] = false;
+    StageTimer t(ctx, SEA_STAGE_ROTATE, s);
+    const int n = n_occ;
+    // inverse: Y_i = sum_j U_ij X_j (U^{-1} = U^T); forward: Y_k = sum_j U_jk X_j
+    SEA_HIP_CHECK(ctx, inverse ? rotate_rows(U_dev, n, 1, dtype, n, n_grid, X_dev, Y_dev, s)
+                               : rotate_rows(U_dev, 1, n, dtype, n, n_grid, X_dev, Y_dev, s));
+    return SEA_OK;
+}
+
+// ---------------------------------------------------------------------------
 // epsilon-driven domains and pair screening (Eq. 16-17)
 
 namespace {

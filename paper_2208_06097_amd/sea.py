@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsea.so")
 
 SEA_OK, SEA_W_NOT_CONVERGED, SEA_W_EIGEN_FALLBACK = 0, 1, 2
-SEA_E_ARG, SEA_E_HIP, SEA_E_NOMEM, SEA_E_NOT_PD, SEA_E_NONFINITE = -1, -2, -3, -4, -5
+SEA_E_ARG, SEA_E_HIP, SEA_E_NOMEM, SEA_E_NOT_PD, SEA_E_NONFINITE, SEA_E_RANK = -1, -2, -3, -4, -5, -6
 SEA_F64, SEA_F32, SEA_BF16 = 0, 1, 2
 SEA_START_ZERO, SEA_START_MULTIPOLE, SEA_START_LEARNED = 0, 1, 2
 SEA_DECOMP_CHOLESKY, SEA_DECOMP_EIGEN, SEA_DECOMP_AUTO = 0, 1, 2
@@ -33,7 +33,7 @@ EXPORTS = [
     "sea_exx_plan_create", "sea_exx_plan_launch", "sea_exx_plan_results", "sea_exx_plan_destroy",
     "sea_cg_variant_count", "sea_cg_variant_name", "sea_exx_autotune",
     "sea_nn_infer_workspace_bytes", "sea_nn_infer", "sea_eps_workspace_bytes", "sea_build_pairs_eps",
-    "sea_successive_idempotency",
+    "sea_successive_idempotency", "sea_scdm_workspace_bytes", "sea_scdm", "sea_rotate",
 ]
 
 # the network's layers (name, c_in, c_out, relu), in parameter order
@@ -88,7 +88,7 @@ class SeaCell(C.Structure):
 
 
 STAGES = ["gather", "boundary", "guess", "cg", "scatter", "energy", "ace_m", "ace_chol", "ace_xi",
-          "ace_apply", "finish"]
+          "ace_apply", "finish", "scdm", "rotate"]
 
 
 class SeaError(RuntimeError):
@@ -152,6 +152,9 @@ def load() -> C.CDLL:
     lib.sea_eps_workspace_bytes.argtypes = [vp, P(SeaGrid), i, P(sz)]
     lib.sea_successive_idempotency.argtypes = [vp, C.c_int64, i, d, vp, vp, vp, sz, P(d)]
     lib.sea_build_pairs_eps.argtypes = [vp, P(SeaGrid), i, vp, i, d, d, i, vp, sz, vp, vp, vp, i, P(i)]
+    lib.sea_scdm_workspace_bytes.argtypes = [vp, C.c_int64, i, P(sz)]
+    lib.sea_scdm.argtypes = [vp, C.c_int64, i, vp, i, vp, sz, vp, vp, vp, vp, P(i)]
+    lib.sea_rotate.argtypes = [vp, C.c_int64, i, i, vp, i, vp, vp]
     _lib = lib
     return lib
 
@@ -501,6 +504,40 @@ class Context:
                                                         phi_old.data_ptr(), ws.data_ptr(), ws.numel(),
                                                         C.byref(dI)))
         return dI.value
+
+    # ---------------------------------------------------------------- SCDM
+    def scdm_workspace_bytes(self, n_grid, n_occ) -> int:
+        b = C.c_size_t(0)
+        self._check(self.lib.sea_scdm_workspace_bytes(self.h, int(n_grid), int(n_occ), C.byref(b)))
+        return b.value
+
+    def scdm(self, phi, ws=None, want_loc=True):
+        """SCDM of orbital-major phi (Eq. 1-6): dict with U (device FP64,
+        U[j, k] = U_jk), phi_loc (device, phi's dtype; None without
+        want_loc), piv and rdiag (host) and the number of pivot rounds."""
+        torch = self._torch
+        n_occ = phi.shape[0]
+        ng = phi.numel() // n_occ
+        if ws is None:
+            ws = self.workspace(self.scdm_workspace_bytes(ng, n_occ))
+        U = torch.empty((n_occ, n_occ), dtype=torch.float64, device="cuda")
+        loc = torch.empty_like(phi) if want_loc else None
+        piv = np.zeros(n_occ, dtype=np.int32)
+        rdiag = np.zeros(n_occ)
+        rounds = C.c_int(0)
+        self._check(self.lib.sea_scdm(self.h, ng, n_occ, phi.data_ptr(), self._phi_dtype(phi), ws.data_ptr(),
+                                      ws.numel(), U.data_ptr(), loc.data_ptr() if loc is not None else None,
+                                      piv.ctypes.data, rdiag.ctypes.data, C.byref(rounds)))
+        return {"U": U, "phi_loc": loc, "piv": piv, "rdiag": rdiag, "rounds": rounds.value}
+
+    def rotate(self, X, U, inverse=False, out=None):
+        """Y_k = sum_j X_j U_jk (Eq. 6) or, inverse, Y_i = sum_j X_j (U^-1)_ji (Eq. 15)."""
+        n_occ = X.shape[0]
+        ng = X.numel() // n_occ
+        Y = self._torch.empty_like(X) if out is None else out
+        self._check(self.lib.sea_rotate(self.h, ng, n_occ, self._phi_dtype(X), U.data_ptr(), int(bool(inverse)),
+                                        X.data_ptr(), Y.data_ptr()))
+        return Y
 
     # ---------------------------------------------------------------- network
     def nn_param_count(self) -> int:

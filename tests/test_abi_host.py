@@ -25,6 +25,12 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(sea.EXPORTS) | {"sea_version"}
 
 
+def test_stage_names_cover_the_stage_enum():
+    txt = open(HEADER).read()
+    count = int(re.search(r"SEA_STAGE_COUNT\s*=\s*(\d+)", txt).group(1))
+    assert len(sea.STAGES) == count
+
+
 def test_struct_layouts():
     assert sea.PAIR_DTYPE.itemsize == 56
     assert sea.STAT_DTYPE.itemsize == 40
