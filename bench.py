@@ -18,6 +18,7 @@ Forms of the V_xx action (CG state precision / start):
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -73,6 +74,34 @@ FORMS = {
 }
 
 
+CG_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_cg_zm_buf_learned_c2.md")
+
+
+def measured_traffic(variant, form, iters_total):
+    """HBM bytes per launch of the CG kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (calibrated against a plain copy), or None unless
+    those runs were taken on this kernel source, variant, start and CG
+    iteration count."""
+    if not os.path.exists(CG_PROFILE):
+        return None
+    rec = None
+    with open(CG_PROFILE) as f:
+        for line in f:
+            if line.startswith("traffic_json: "):
+                rec = json.loads(line[len("traffic_json: "):])
+    if rec is None:
+        return None
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for name in rec["source_files"]:
+        with open(os.path.join(root, name), "rb") as f:
+            h.update(f.read())
+    if (h.hexdigest() != rec["source_sha256"] or rec["cg_variant"] != variant or rec["form"] != form
+            or rec["cg_iters_total"] != iters_total):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +115,7 @@ def main():
     ap.add_argument("--other-forms", action="store_true", help="also time one V_xx action of every other form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eps-rule", action="store_true", help="skip the eps-driven-domain context measurement")
+    ap.add_argument("--no-scdm", action="store_true", help="skip the SCDM chain measurement")
     ap.add_argument("--tune-pairs", type=int, default=2048, help="pairs sampled by the CG kernel autotuner")
     ap.add_argument("--cg-variant", default=None,
                     help="fixed FP32 CG kernel variant (skips the autotuner; for profiling runs)")
@@ -286,6 +316,61 @@ def main():
         log(f"eps rule: {len(pe)} pairs, {eps_rule['vxx_ms_per_call']:.1f} ms, dE {eps_rule['dE_vs_cube_rule_oracle']}")
         del wse
         ce.close()
+    # the SeA chain on delocalized orbitals (a dense rotation of the synthetic
+    # localized set, standing in for canonical orbitals): SCDM (Eq. 1-6), eps
+    # pairs of the SCDM orbitals, exx, back-rotation of W (Eq. 15), ACE
+    sea_chain = None
+    if not args.no_scdm:
+        cs = make_ctx("multipole-f32")
+        n = cell.n_occ
+        G = torch.from_numpy(synth.random_rotation(n, args.seed + 7)).cuda()
+        phid = (G.T @ phi.view(n, -1)).view_as(phi).contiguous()
+        del G
+        wss = cs.workspace(cs.scdm_workspace_bytes(cell.N ** 3, n))
+        cs.scdm(phid, ws=wss)                       # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = cs.scdm(phid, ws=wss)
+        t_scdm = 1000 * (time.perf_counter() - t1)
+        ss = cs.stage_times()
+        loc = r["phi_loc"]
+        eps = 10 ** -3.5
+        t1 = time.perf_counter()
+        pl_, _, dbl = cs.build_pairs_eps(loc, cell.N, cell.L, eps, eps, pad=6, with_dbox=True)
+        t_pairs = 1000 * (time.perf_counter() - t1)
+        wsl = cs.workspace(cs.exx_batched_workspace_bytes([(loc, cell.N, cell.L, pl_, W, exx_dev, dbl)]))
+        if args.cg_variant:
+            cs.set_opts(cg_variant=cs.cg_variants().index(args.cg_variant))
+        else:
+            cs.autotune([(loc, cell.N, cell.L, pl_)], sample_pairs=args.tune_pairs, iters=20, ws=wsl)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rl = cs.exx_action(loc, cell.N, cell.L, pl_, ws=wsl, W=W, exx_dev=exx_dev, want_host=True, dbox=dbl)
+        t_exx = 1000 * (time.perf_counter() - t1)
+        del wsl
+        Wd = torch.empty_like(W)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cs.rotate(W.view(n, -1), r["U"], inverse=True, out=Wd.view(n, -1))
+        torch.cuda.synchronize()
+        t_back = 1000 * (time.perf_counter() - t1)
+        _, _, xi_d, _ = ctx.ace_build(phid, Wd, dV, ws=ws_ace)
+        E_ace_d = ctx.ace_energy(phid, xi_d, dV, ws=ws_ace)
+        del xi_d, Wd
+        sea_chain = {
+            "input": "dense seeded rotation of the 256 synthetic orbitals (delocalized stand-in for canonical orbitals)",
+            "scdm_ms": t_scdm, "scdm_stage_ms": {"pivots_and_U": ss["scdm"], "rotate_phi": ss["rotate"]},
+            "pivot_rounds": r["rounds"], "eps": eps, "pair_build_ms": t_pairs, "n_pairs": int(len(pl_)),
+            "exx_ms": t_exx, "cg_iters_mean": float(rl[2]["iters"].mean()), "back_rotation_ms": t_back,
+            "chain_ms": t_scdm + t_pairs + t_exx + t_back, "E_xx": rl[1],
+            "dE_vs_cube_rule_oracle": (rl[1] - golden["E"]) if golden else None,
+            "E_ace_delocalized": E_ace_d,
+            "dE_ace_vs_cube_rule_oracle": (E_ace_d - golden["E"]) if golden else None}
+        log(f"SeA chain: scdm {t_scdm:.1f} ms ({r['rounds']} rounds), pairs {t_pairs:.1f} ms ({len(pl_)}), "
+            f"exx {t_exx:.1f} ms, back {t_back:.1f} ms; dE {sea_chain['dE_vs_cube_rule_oracle']}, "
+            f"dE_ace {sea_chain['dE_ace_vs_cube_rule_oracle']}")
+        del phid, loc, r, wss
+        cs.close()
     out = {
         "metric": "V_xx action ms/call + pair Poisson solves/s, 64-mol cell, learned vs plain",
         "value": n_pairs * args.steps / dt,
@@ -313,8 +398,12 @@ def main():
         "forms": forms,
         "ace_precision": ace,
         "eps_rule": eps_rule,
+        "sea_chain": sea_chain,
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(tune["variant"] if tune else None, form,
+                                                 int(stats["iters"].sum())),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes_per_launch": cg_bytes,
                      "per_unit": f"6 words x {int(wbytes)} B per interior point per CG iteration"},
     }

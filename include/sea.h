@@ -336,7 +336,8 @@ sea_status sea_scdm_workspace_bytes(sea_ctx *ctx, int64_t n_grid, int n_occ, siz
  * already chosen is longest, first grid index on ties); Eq. 3-5 with
  * B = (Phi^T)_{:,C} and P_CC = B^T B (the density matrix at the selected
  * points; X^T X for orbitals orthonormal as grid vectors), so that
- * U = B P_CC^{-1/2} is orthogonal; P_CC^{-1/2} by FP64 Jacobi.
+ * U = B P_CC^{-1/2} is orthogonal: U is the polar factor of B, computed by
+ * the FP64 Newton-Schulz iteration on the matrix cores.
  * Outputs:
  *   U_dev       n_occ x n_occ FP64 row-major, U[j*n_occ + k] = U_jk;
  *   phi_loc_dev (nullable) n_occ x n_grid in phi_dtype, Eq. 6:
@@ -349,7 +350,8 @@ sea_status sea_scdm_workspace_bytes(sea_ctx *ctx, int64_t n_grid, int n_occ, siz
  *               longer provably beats every column outside the candidate
  *               set, then all column norms are brought up to date).
  * n_occ <= 2048, n_grid >= n_occ.  SEA_E_RANK when a residual column
- * norm^2 drops below 1e-26 of the largest initial one.  ws_dev:
+ * norm^2 drops below 1e-26 of the largest initial one, or when the polar
+ * iteration has not converged in 120 steps.  ws_dev:
  * sea_scdm_workspace_bytes bytes.  Synchronizes once per round. */
 sea_status sea_scdm(sea_ctx *ctx, int64_t n_grid, int n_occ, const void *phi_dev, sea_dtype phi_dtype,
                     void *ws_dev, size_t ws_bytes, double *U_dev, void *phi_loc_dev, int32_t *piv_host,

@@ -30,3 +30,7 @@ hipError_t scdm_round(const void* phi, int f32, long Ng, int n, int first, char*
 hipError_t scdm_pivot_rows(const void* phi, int f32, long Ng, int n, const int* piv, double* G, hipStream_t s);
 // Synchronizing read of the pivot count and the rank flag.
 hipError_t scdm_read_state(const char* ws, const ScdmLayout& L, int* k, int* fail, hipStream_t s);
+// Newton-Schulz helpers (one workgroup each): Y = G / |G|_F, and
+// S <- 1.5 I - 0.5 S with *err = |S - I|_F^2 of the incoming S.
+hipError_t scdm_ns_scale(const double* G, int n, double* Y, hipStream_t s);
+hipError_t scdm_ns_mid(double* S, int n, double* err, hipStream_t s);

@@ -460,7 +460,47 @@ __global__ __launch_bounds__(SC_BS) void k_scdm_pivot_rows(const T* __restrict__
     if (i < n) G[(size_t)a * n + i] = ld(phi, (size_t)i * Ng + piv[a]);
 }
 
+// Newton-Schulz steps for the polar factor (see scdm_polar_*): one workgroup.
+constexpr int NS_BS = 1024;
+
+// Y = G / |G|_F
+__global__ __launch_bounds__(NS_BS) void k_ns_scale(const double* __restrict__ G, int n, double* __restrict__ Y) {
+    __shared__ double red[NS_BS / 64];
+    const long nn = (long)n * n;
+    double s = 0.0;
+    for (long t = threadIdx.x; t < nn; t += NS_BS) s += G[t] * G[t];
+    s = block_sum<NS_BS>(s, red);
+    const double inv = 1.0 / sqrt(s);
+    for (long t = threadIdx.x; t < nn; t += NS_BS) Y[t] = G[t] * inv;
+}
+
+// S <- 1.5 I - 0.5 S, err = |S - I|_F^2 of the incoming S
+__global__ __launch_bounds__(NS_BS) void k_ns_mid(double* __restrict__ S, int n, double* __restrict__ err) {
+    __shared__ double red[NS_BS / 64];
+    const long nn = (long)n * n;
+    double e = 0.0;
+    for (long t = threadIdx.x; t < nn; t += NS_BS) {
+        const bool diag = (t / n) == (t % n);
+        const double v = S[t];
+        const double d = diag ? v - 1.0 : v;
+        e += d * d;
+        S[t] = (diag ? 1.5 : 0.0) - 0.5 * v;
+    }
+    e = block_sum<NS_BS>(e, red);
+    if (threadIdx.x == 0) *err = e;
+}
+
 }  // namespace
+
+hipError_t scdm_ns_scale(const double* G, int n, double* Y, hipStream_t s) {
+    hipLaunchKernelGGL(k_ns_scale, dim3(1), dim3(NS_BS), 0, s, G, n, Y);
+    return hipGetLastError();
+}
+
+hipError_t scdm_ns_mid(double* S, int n, double* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_ns_mid, dim3(1), dim3(NS_BS), 0, s, S, n, err);
+    return hipGetLastError();
+}
 
 ScdmLayout scdm_layout(long Ng, int n) {
     ScdmLayout L{};

@@ -1029,12 +1029,13 @@ sea_status sea_successive_idempotency(sea_ctx* ctx, int64_t n_grid, int n_occ, d
 // SCDM localization (Eq. 1-6) and the rotations of Eq. 6 and Eq. 15
 
 #include "k_scdm.h"
+#include <utility>
 
 namespace {
 
 struct ScdmFull {
     ScdmLayout piv;          // pivot search (k_scdm.hip)
-    size_t G, P, V, lam, T, Pmh, part, total;
+    size_t G, P, Ya, Yb, err, part, total;
 };
 
 ScdmFull scdm_full_layout(long Ng, int n) {
@@ -1049,10 +1050,9 @@ ScdmFull scdm_full_layout(long Ng, int n) {
     const size_t nn = (size_t)n * n * sizeof(double);
     L.G = take(nn);
     L.P = take(nn);
-    L.V = take(nn);
-    L.lam = take((size_t)n * sizeof(double));
-    L.T = take(nn);
-    L.Pmh = take(nn);
+    L.Ya = take(nn);
+    L.Yb = take(nn);
+    L.err = take(64);
     L.part = take((size_t)ace_mfma_splits(n, n, n) * nn);
     L.total = off;
     return L;
@@ -1125,22 +1125,37 @@ extern "C" sea_status sea_scdm(sea_ctx* ctx, int64_t n_grid, int n_occ, const vo
         }
         if (fl)
             return fail(ctx, SEA_E_RANK, "Phi^T is rank deficient: no independent column left at pivot %d", fl);
-        // Eq. 3-5: G = B^T (row a = orbitals at point c_a), P_CC = G G^T,
-        // P_CC^{-1/2} = V (V |Lambda|^{-1/2})^T, U = B P_CC^{-1/2}
+        // Eq. 3-5: U = B P_CC^{-1/2} with P_CC = B^T B is the orthogonal polar
+        // factor of B = (Phi^T)_{:,C}.  It is computed by the Newton-Schulz
+        // iteration X <- X (3 I - X^T X) / 2 from X = B / |B|_F (every singular
+        // value in (0, 1], each step moving it towards 1; quadratic near 1),
+        // on the matrix cores, carried as Y = X^T with G = B^T (about 16 steps
+        // for condition numbers near 20; 120 allow for 1e12).
         const int* piv = (const int*)(ws + L.piv.piv);
         double* G = (double*)(ws + L.G);
         double* P = (double*)(ws + L.P);
-        double* V = (double*)(ws + L.V);
-        double* lam = (double*)(ws + L.lam);
-        double* T = (double*)(ws + L.T);
-        double* Pmh = (double*)(ws + L.Pmh);
         double* part = (double*)(ws + L.part);
         SEA_HIP_CHECK(ctx, scdm_pivot_rows(phi_dev, f32, Ng, n, piv, G, s));
-        SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_F64, double, double>(G, G, n, n, n, 1.0, part, P, s)));
-        SEA_HIP_CHECK(ctx, ace_eig(P, n, V, lam, s));
-        SEA_HIP_CHECK(ctx, ace_eig_transform(V, lam, n, T, s));
-        SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_F64, double, double>(V, n, 1, T, n, n, n, 1.0, Pmh, s)));
-        SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_F64, double, double>(G, 1, n, Pmh, n, n, n, 1.0, U_dev, s)));
+        double* cur = (double*)(ws + L.Ya);
+        double* nxt = (double*)(ws + L.Yb);
+        double* errd = (double*)(ws + L.err);
+        SEA_HIP_CHECK(ctx, scdm_ns_scale(G, n, cur, s));
+        bool conv = false;
+        for (int it = 0; it < 120 && !conv; ++it) {
+            SEA_HIP_CHECK(ctx, (ace_mm_nt<ACE_F64, double, double>(cur, cur, n, n, n, 1.0, part, P, s)));
+            SEA_HIP_CHECK(ctx, scdm_ns_mid(P, n, errd, s));
+            SEA_HIP_CHECK(ctx, (ace_mm_nn<ACE_F64, double, double>(P, n, 1, cur, n, n, n, 1.0, nxt, s)));
+            std::swap(cur, nxt);
+            if (it % 4 == 3) {
+                double e = 0.0;
+                SEA_HIP_CHECK(ctx, hipMemcpyAsync(&e, errd, sizeof(double), hipMemcpyDeviceToHost, s));
+                SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+                conv = e <= 1e-24;   // |X^T X - I|_F <= 1e-12 before the last step
+            }
+        }
+        if (!conv)
+            return fail(ctx, SEA_E_RANK, "B = (Phi^T)_{:,C} too ill-conditioned: its polar factor did not converge");
+        SEA_HIP_CHECK(ctx, ace_transpose(cur, n, U_dev, s));
     }
     if (phi_loc_dev) {
         StageTimer t(ctx, SEA_STAGE_ROTATE, s);
