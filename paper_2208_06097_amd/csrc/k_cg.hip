@@ -16,6 +16,18 @@
 // enters as the first FP64 residual update, so no separate start-residual
 // pass is needed.
 //
+// Paired iterate updates (XC variants, 7 words per iteration on average):
+// c is read and written only every second sweep B.  Iteration k-1 leaves
+// its step alpha_{k-1} p_{k-1} pending; sweep B of iteration k adds both
+// steps at once, recovering p_{k-1} = (p_k - r_k) / beta_{k-1} from the p_k
+// and r_k it reads anyway:
+//   c += (alpha_{k-1} / beta_{k-1} + alpha_k) p_k - (alpha_{k-1} / beta_{k-1}) r_k.
+// When beta_{k-1} is small (the recovery would amplify rounding) the
+// pending step is added to c before sweep A of iteration k, while p still
+// holds p_{k-1}, and before a residual refresh likewise.  Any
+// rounding in c is caught by the FP64 refresh, which recomputes the
+// residual from x.
+//
 // Precision: the CG state (c, r, p) is T (double or float), with reliable
 // updates (residual replacement, as in mixed-precision CG of Sleijpen and
 // van der Vorst): the FP64 residual r64 starts at b; whenever the recursive
@@ -257,7 +269,10 @@ struct SlotIO<float, true> {
     }
 };
 
-template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH, bool BUF>
+// Smallest beta_{k-1} for which a pending step is recovered from p_k and r_k.
+constexpr double kXcBetaMin = 0.25;
+
+template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH, bool BUF, bool XC>
 __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __restrict__ cc, T* __restrict__ rr,
                            T* __restrict__ pp, double* __restrict__ r64) {
     const DevCell& C = a.cells[a.pair_cell[pid]];
@@ -281,9 +296,20 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     const int col0 = ty * 64 + tx;  // column c at col0 + c*TY*64 within a plane
     const SlotIO<T, BUF> io_c(cc, npad, col0), io_r(rr, npad, col0), io_p(pp, npad, col0);
 
+    // step alpha p of the previous iteration not yet added to c (XC)
+    T pend = T(0);
+    // c += pend p over the padded grid (the p array holds the pending step's
+    // direction when this runs)
+    auto flush = [&]() {
+        for (int q = threadIdx.x; q < npad; q += NT) cc[q] += pend * pp[q];
+        pend = T(0);
+        __syncthreads();
+    };
+
     // FP64 residual update: r64 -= A c and x += c, one z-march; returns |r64|^2
     auto refresh = [&]() -> double {
         double uacc = 0.0;
+        if (XC && pend != T(0)) flush();
         zmarch<T, double, NT, COLS, 1, T, double>(
             nz, lds, wd, [&](int c, int z) -> T { return io_c.ld(z * PL + c * TY * 64); },
             [&](int, int, T v) -> T { return v; },
@@ -341,6 +367,9 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     else if (a.max_iter <= 0) conv = 0;
     else rho = reset(true);
     while (conv == 0 && rho > 0.0) {
+        // XC: a pending step whose recovery would need a small beta is
+        // written now, while p still holds its direction
+        if (XC && pend != T(0) && !((double)beta >= kXcBetaMin)) flush();
         // sweep A: p = r + beta p, <p, A p>
         double dacc = 0.0;
         zmarch<T, T, NT, COLS, DEPTH, F2<T>, Empty>(
@@ -360,6 +389,11 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
             [&](int, int, T s, T ctr, Empty) { dacc += (double)ctr * (double)s; });
         const double pAp = block_sum<NT>(dacc, red);
         const T al = (T)(rho / pAp);
+        // coefficients of this sweep's update c += cp p + cr r (XC: none when
+        // this step is left pending)
+        const bool with_c = !XC || pend != T(0);
+        const T cp = XC ? (pend != T(0) ? pend / beta + al : T(0)) : al;
+        const T cr = XC && pend != T(0) ? -(pend / beta) : T(0);
         // sweep B: c += alpha p, r -= alpha A p, <r, r>
         using PV = typename PVsel<T>::type;
         double racc = 0.0;
@@ -370,12 +404,15 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
                 nz, lds, w, fetch_p, make_p,
                 [&](int c, int z) -> PV {
                     const int o = z * PL + c * TY * 64;
-                    return PV{io_c.ld(o), io_r.ld(o)};
+                    return PV{with_c ? io_c.ld(o) : T(0), io_r.ld(o)};
                 },
                 [&](int c, int z, T s, T ctr, PV v) {
                     const int o = z * PL + c * TY * 64;
                     const T rn = msk[c] * (v.b - al * s);
-                    io_c.st(o, v.a + al * ctr);
+                    if (with_c) {
+                        if constexpr (XC) io_c.st(o, v.a + cp * ctr + cr * v.b);
+                        else io_c.st(o, v.a + al * ctr);
+                    }
                     io_r.st(o, rn);
                     racc += (double)rn * (double)rn;
                 });
@@ -384,13 +421,18 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
                 nz, lds, w, fetch_p, make_p, [&](int, int) { return Empty{}; },
                 [&](int c, int z, T s, T ctr, Empty) {
                     const int o = z * PL + c * TY * 64;
-                    const T rn = msk[c] * (io_r.ld(o) - al * s);
-                    io_c.st(o, io_c.ld(o) + al * ctr);
+                    const T rv = io_r.ld(o);
+                    const T rn = msk[c] * (rv - al * s);
+                    if (with_c) {
+                        if constexpr (XC) io_c.st(o, io_c.ld(o) + cp * ctr + cr * rv);
+                        else io_c.st(o, io_c.ld(o) + al * ctr);
+                    }
                     io_r.st(o, rn);
                     racc += (double)rn * (double)rn;
                 });
         }
         const double rn2 = block_sum<NT>(racc, red);
+        if constexpr (XC) pend = with_c ? T(0) : al;
         ++it;
         const bool nan = !(rn2 == rn2);
         if (!nan && rn2 > tol2 * bb && rn2 > Delta<T>::v2 * rupd && it < a.max_iter) {
@@ -418,7 +460,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     }
 }
 
-template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH, bool BUF>
+template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH, bool BUF, bool XC>
 __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
     extern __shared__ unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
@@ -437,7 +479,7 @@ __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
         const int qi = pid_sh;
         if (qi >= a.n_pairs) break;
         const int pid = a.order ? a.order[qi] : qi;  // largest domains first
-        solve_pair<T, NT, COLS, PREFETCH, DEPTH, BUF>(a, pid, lds, red, cc, rr, pp, r64);
+        solve_pair<T, NT, COLS, PREFETCH, DEPTH, BUF, XC>(a, pid, lds, red, cc, rr, pp, r64);
     }
 }
 
@@ -516,7 +558,8 @@ hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s) {
 // lane may hold at this size and spill in the plane loop); pf: prefetch c
 // and r of the output plane before the barrier; d: planes of p in flight
 // ahead of the register queue; buf: state arrays through buffer
-// instructions (32-bit offsets) instead of 64-bit global addresses.
+// instructions (32-bit offsets) instead of 64-bit global addresses; xc:
+// paired iterate updates (c read and written every second iteration).
 namespace {
 using CgKernel = void (*)(ExxArgs);
 struct CgVariant {
@@ -525,13 +568,16 @@ struct CgVariant {
     int nt;
 };
 const CgVariant kCgVariants[] = {
-    {"nt1024-pf-d1", k_cg_zm<float, 1024, 4, true, 1, false>, 1024},
-    {"nt1024-pf-d2", k_cg_zm<float, 1024, 4, true, 2, false>, 1024},
-    {"nt1024-d1", k_cg_zm<float, 1024, 4, false, 1, false>, 1024},
-    {"nt1024-d2", k_cg_zm<float, 1024, 4, false, 2, false>, 1024},
-    {"buf-pf-d1", k_cg_zm<float, 1024, 4, true, 1, true>, 1024},
-    {"buf-pf-d2", k_cg_zm<float, 1024, 4, true, 2, true>, 1024},
-    {"buf-d2", k_cg_zm<float, 1024, 4, false, 2, true>, 1024},
+    {"nt1024-pf-d1", k_cg_zm<float, 1024, 4, true, 1, false, false>, 1024},
+    {"nt1024-pf-d2", k_cg_zm<float, 1024, 4, true, 2, false, false>, 1024},
+    {"nt1024-d1", k_cg_zm<float, 1024, 4, false, 1, false, false>, 1024},
+    {"nt1024-d2", k_cg_zm<float, 1024, 4, false, 2, false, false>, 1024},
+    {"buf-pf-d1", k_cg_zm<float, 1024, 4, true, 1, true, false>, 1024},
+    {"buf-pf-d2", k_cg_zm<float, 1024, 4, true, 2, true, false>, 1024},
+    {"buf-d2", k_cg_zm<float, 1024, 4, false, 2, true, false>, 1024},
+    {"buf-pf-d1-xc", k_cg_zm<float, 1024, 4, true, 1, true, true>, 1024},
+    {"buf-pf-d2-xc", k_cg_zm<float, 1024, 4, true, 2, true, true>, 1024},
+    {"nt1024-pf-d1-xc", k_cg_zm<float, 1024, 4, true, 1, false, true>, 1024},
 };
 constexpr int kNumCgVariants = sizeof(kCgVariants) / sizeof(kCgVariants[0]);
 }  // namespace

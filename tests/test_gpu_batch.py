@@ -155,27 +155,39 @@ def test_plan_device_energy_without_host_sync(cells):
 
 
 def test_autotune_picks_fastest_and_variants_agree(cells, tmp_path):
-    """Every CG kernel variant computes the same arithmetic in the same order
-    (they differ in load scheduling only): W and E are bit-identical.  The
-    tuner's choice is the argmin of its timings and is cached by key."""
+    """CG kernel variants of one arithmetic (they differ in load scheduling
+    only) give bit-identical W and E; the paired-update variants (-xc) form
+    a second such group, whose results agree with the first to the CG
+    tolerance.  The tuner's choice is the argmin of its timings and is
+    cached by key."""
     print("case autotune", flush=True)
     phis = _phis(cells, np.float32)
     batch = [(phi, c.N, c.L, pairs) for (c, pairs), phi in zip(cells, phis)]
     ctx = sea.Context(rel_tol=1e-8, stencil_dtype=sea.SEA_F32)
     names = ctx.cg_variants()
     assert len(names) >= 2
-    ref = None
+    refs = {}
     for v in range(len(names)):
         ctx.set_opts(cg_variant=v)
         Ws, Es, stats, st = ctx.exx_action_batched(batch)
-        assert st == sea.SEA_OK
-        if ref is None:
-            ref = ([w.clone() for w in Ws], Es.copy(), stats.copy())
+        assert st == sea.SEA_OK and np.all(stats["converged"] == 1)
+        group = names[v].endswith("-xc")
+        if group not in refs:
+            refs[group] = ([w.clone() for w in Ws], Es.copy(), stats.copy())
         else:
+            ref = refs[group]
             assert np.array_equal(Es, ref[1]), names[v]
             assert np.array_equal(stats, ref[2]), names[v]
             for a, b in zip(Ws, ref[0]):
                 assert torch.equal(a, b), names[v]
+    ref = refs[False]
+    if True in refs:
+        alt = refs[True]
+        assert np.max(np.abs(alt[1] - ref[1])) < 2e-7
+        assert abs(alt[2]["iters"].mean() - ref[2]["iters"].mean()) < 0.05 * ref[2]["iters"].mean()
+        for a, b in zip(alt[0], ref[0]):
+            assert float((a - b).abs().max()) < 1e-5
+    ref = refs[False]
     ctx.set_opts(cg_variant=-1)
     cache = str(tmp_path / "tune.json")
     res = ctx.autotune(batch, sample_pairs=64, iters=10, cache=cache)
@@ -186,5 +198,5 @@ def test_autotune_picks_fastest_and_variants_agree(cells, tmp_path):
     again = ctx.autotune(batch, sample_pairs=64, iters=10, cache=cache)
     assert again["cached"] and again["variant"] == res["variant"]
     Ws, Es, _, st = ctx.exx_action_batched(batch)
-    assert np.array_equal(Es, ref[1])
+    assert np.array_equal(Es, refs[res["variant"].endswith("-xc")][1])
     ctx.close()

@@ -297,12 +297,25 @@ def test_c1_full_against_golden(ctx):
     assert np.max(np.abs(e - np.array(g["e_pairs"]))) < 1e-7
 
 
-def test_c1_full_fp32_state_against_golden(ctx32):
+CG_VARIANTS = ["nt1024-pf-d1", "nt1024-pf-d2", "nt1024-d1", "nt1024-d2", "buf-pf-d1", "buf-pf-d2", "buf-d2",
+               "buf-pf-d1-xc", "buf-pf-d2-xc", "nt1024-pf-d1-xc"]
+
+
+@pytest.mark.parametrize("variant", CG_VARIANTS)
+def test_c1_full_fp32_state_against_golden(variant):
+    """Every FP32 CG kernel variant on the full config-1 cell against the
+    stored oracle values."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
     g = json.load(open(os.path.join(GOLDEN, "c1.json")))
     cell = synth.config1(seed=g["seed"])
     pairs = sea.build_pairs(cell.N, cell.L, cell.centres, g["r_pair"], g["half_width"])
-    print("case c1 full fp32 state", flush=True)
+    print(f"case c1 full fp32 state, CG variant {variant}", flush=True)
+    ctx32 = sea.Context(rel_tol=1e-8, stencil_dtype=sea.SEA_F32)
+    assert CG_VARIANTS == ctx32.cg_variants()
+    ctx32.set_opts(cg_variant=CG_VARIANTS.index(variant))
     W, E, stats, st = ctx32.exx_action(_dev(cell.phi), cell.N, cell.L, pairs)
+    ctx32.close()
     assert st == sea.SEA_OK and np.all(stats["rel_res"] <= 1e-8)
     assert abs(E - g["E"]) < 1e-6
     Wf = W.reshape(cell.n_occ, -1)
