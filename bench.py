@@ -74,7 +74,7 @@ FORMS = {
 }
 
 
-CG_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_cg_zm_buf_learned_c2.md")
+CG_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_cg_zm_buf_xc_learned_c2.md")
 
 
 def measured_traffic(variant, form, iters_total):
