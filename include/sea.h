@@ -92,6 +92,10 @@ typedef struct {
     sea_dtype nn_weight_dtype; /* learned start: network weights F32 or BF16   */
     void *hip_stream;       /* hipStream_t; NULL = default stream              */
     sea_decomp ace_decomp;  /* ACE decomposition (default Cholesky)            */
+    double cg_xc_beta_min;  /* paired-update CG variants (-xc): smallest      */
+                            /* beta_{k-1} for which a pending step is         */
+                            /* recovered from p_k and r_k, else it is written */
+                            /* by a separate pass; 0 selects 0.25; >= 0       */
 } sea_opts;
 
 /* Stages timed when opts.profile is set (indices into sea_stage_times). */

@@ -269,9 +269,6 @@ struct SlotIO<float, true> {
     }
 };
 
-// Smallest beta_{k-1} for which a pending step is recovered from p_k and r_k.
-constexpr double kXcBetaMin = 0.25;
-
 template <typename T, int NT, int COLS, bool PREFETCH, int DEPTH, bool BUF, bool XC>
 __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __restrict__ cc, T* __restrict__ rr,
                            T* __restrict__ pp, double* __restrict__ r64) {
@@ -369,7 +366,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     while (conv == 0 && rho > 0.0) {
         // XC: a pending step whose recovery would need a small beta is
         // written now, while p still holds its direction
-        if (XC && pend != T(0) && !((double)beta >= kXcBetaMin)) flush();
+        if (XC && pend != T(0) && !((double)beta >= a.xc_beta_min)) flush();
         // sweep A: p = r + beta p, <p, A p>
         double dacc = 0.0;
         zmarch<T, T, NT, COLS, DEPTH, F2<T>, Empty>(

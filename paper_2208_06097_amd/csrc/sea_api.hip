@@ -54,6 +54,8 @@ sea_status check_opts(sea_ctx* ctx, const sea_opts* o) {
         return fail(ctx, SEA_E_ARG, "nn_weight_dtype must be SEA_F32 or SEA_BF16");
     if (o->ace_decomp != SEA_DECOMP_CHOLESKY && o->ace_decomp != SEA_DECOMP_EIGEN && o->ace_decomp != SEA_DECOMP_AUTO)
         return fail(ctx, SEA_E_ARG, "bad ace_decomp");
+    if (!(o->cg_xc_beta_min >= 0.0) || !std::isfinite(o->cg_xc_beta_min))
+        return fail(ctx, SEA_E_ARG, "cg_xc_beta_min must be finite and >= 0");
     if (o->cg_variant < -1 || o->cg_variant >= cg_variant_count())
         return fail(ctx, SEA_E_ARG, "cg_variant must be -1 or 0..%d", cg_variant_count() - 1);
     return SEA_OK;
@@ -277,6 +279,7 @@ void sea_opts_default(sea_opts* o) {
     o->start = SEA_START_ZERO;
     o->cg_variant = -1;
     o->ace_decomp = SEA_DECOMP_CHOLESKY;
+    o->cg_xc_beta_min = 0.0;
     o->profile = 0;
     o->nn_weight_dtype = SEA_BF16;
     o->hip_stream = nullptr;
@@ -476,6 +479,7 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.n_slots = Ly.n_slots;
     a.stats = (DevStat*)(base + Ly.stats);
     a.rel_tol = ctx->opts.rel_tol;
+    a.xc_beta_min = ctx->opts.cg_xc_beta_min > 0.0 ? ctx->opts.cg_xc_beta_min : 0.25;
     a.max_iter = ctx->opts.max_iter;
     a.lmax = ctx->opts.lmax;
     a.queue_ctr = (int*)(base + Ly.counter);

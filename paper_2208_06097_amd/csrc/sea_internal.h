@@ -102,6 +102,7 @@ struct ExxArgs {
     int n_slots;
     DevStat* stats;
     double rel_tol;
+    double xc_beta_min;   // paired-update CG: smallest beta for recovering a pending step
     int max_iter;
     int lmax;
     int* queue_ctr;       // persistent-kernel pair counter (zeroed before the CG launch)

@@ -78,7 +78,8 @@ class SeaOpts(C.Structure):
     _fields_ = [("fd_half_order", C.c_int32), ("lmax", C.c_int32), ("rel_tol", C.c_double),
                 ("max_iter", C.c_int32), ("stencil_dtype", C.c_int), ("ace_dtype", C.c_int),
                 ("start", C.c_int), ("cg_variant", C.c_int32), ("profile", C.c_int32),
-                ("nn_weight_dtype", C.c_int), ("hip_stream", C.c_void_p), ("ace_decomp", C.c_int)]
+                ("nn_weight_dtype", C.c_int), ("hip_stream", C.c_void_p), ("ace_decomp", C.c_int),
+                ("cg_xc_beta_min", C.c_double)]
 
 
 class SeaCell(C.Structure):

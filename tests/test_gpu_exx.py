@@ -301,19 +301,22 @@ CG_VARIANTS = ["nt1024-pf-d1", "nt1024-pf-d2", "nt1024-d1", "nt1024-d2", "buf-pf
                "buf-pf-d1-xc", "buf-pf-d2-xc", "nt1024-pf-d1-xc"]
 
 
-@pytest.mark.parametrize("variant", CG_VARIANTS)
-def test_c1_full_fp32_state_against_golden(variant):
+@pytest.mark.parametrize("variant,beta_min", [(v, 0.0) for v in CG_VARIANTS]
+                         + [("buf-pf-d1-xc", 10.0), ("buf-pf-d1-xc", 1e-300)])
+def test_c1_full_fp32_state_against_golden(variant, beta_min):
     """Every FP32 CG kernel variant on the full config-1 cell against the
-    stored oracle values."""
+    stored oracle values; for the paired-update kernel also with every
+    pending step written by the separate pass (beta_min 10) and with none
+    written that way (beta_min ~ 0: only refreshes flush)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     g = json.load(open(os.path.join(GOLDEN, "c1.json")))
     cell = synth.config1(seed=g["seed"])
     pairs = sea.build_pairs(cell.N, cell.L, cell.centres, g["r_pair"], g["half_width"])
-    print(f"case c1 full fp32 state, CG variant {variant}", flush=True)
+    print(f"case c1 full fp32 state, CG variant {variant}, beta_min {beta_min}", flush=True)
     ctx32 = sea.Context(rel_tol=1e-8, stencil_dtype=sea.SEA_F32)
     assert CG_VARIANTS == ctx32.cg_variants()
-    ctx32.set_opts(cg_variant=CG_VARIANTS.index(variant))
+    ctx32.set_opts(cg_variant=CG_VARIANTS.index(variant), cg_xc_beta_min=beta_min)
     W, E, stats, st = ctx32.exx_action(_dev(cell.phi), cell.N, cell.L, pairs)
     ctx32.close()
     assert st == sea.SEA_OK and np.all(stats["rel_res"] <= 1e-8)
@@ -411,3 +414,14 @@ def test_successive_idempotency():
     d = c.successive_idempotency(_dev(phi2), _dev(phi), dV)
     assert abs(d - oracle.successive_idempotency(phi2, phi, dV)) < 1e-12 and d > 1e-4
     c.close()
+
+
+def test_cg_xc_beta_min_rejects_bad_values():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    for bad in (-1.0, float("nan"), float("inf")):
+        c = sea.Context()
+        with pytest.raises(sea.SeaError) as ei:
+            c.set_opts(cg_xc_beta_min=bad)
+        assert ei.value.status == sea.SEA_E_ARG
+        c.close()
