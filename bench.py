@@ -81,6 +81,7 @@ FORMS = {
     "plain-f32": dict(stencil="f32", start="zero"),
     "multipole-f32": dict(stencil="f32", start="multipole"),
     "learned-f32": dict(stencil="f32", start="learned"),
+    "spectral-f32": dict(stencil="f32", start="spectral"),
 }
 
 
@@ -176,7 +177,7 @@ def main():
     def make_ctx(fname):
         f = FORMS[fname]
         start = {"zero": sea.SEA_START_ZERO, "multipole": sea.SEA_START_MULTIPOLE,
-                 "learned": sea.SEA_START_LEARNED}[f["start"]]
+                 "learned": sea.SEA_START_LEARNED, "spectral": sea.SEA_START_SPECTRAL}[f["start"]]
         c = sea.Context(rel_tol=args.tol, profile=True, start=start,
                         stencil_dtype=sea.SEA_F32 if f["stencil"] == "f32" else sea.SEA_F64)
         if f["start"] == "learned":

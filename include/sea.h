@@ -51,7 +51,12 @@ typedef enum { SEA_F64 = 0, SEA_F32 = 1, SEA_BF16 = 2 } sea_dtype;
 typedef enum {
     SEA_START_ZERO = 0,      /* x0 = 0                                          */
     SEA_START_MULTIPOLE = 1, /* x0 = regularized multipole potential (Eq. 10)   */
-    SEA_START_LEARNED = 2    /* x0 from the 3-D convolutional network (attached) */
+    SEA_START_LEARNED = 2,   /* x0 from the 3-D convolutional network (attached) */
+    SEA_START_SPECTRAL = 3   /* multipole start plus the correction from a fast */
+                             /* sine-transform solve of b - A x0 with the same  */
+                             /* stencil continued oddly past the faces (domains */
+                             /* with every axis <= 64; others keep the          */
+                             /* multipole start)                                */
 } sea_start;
 
 typedef struct {

@@ -323,7 +323,11 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
 
     // r64 = b on the padded grid, x = 0.  A start guess x0 (in x on entry)
     // enters as the first increment c = (T) x0, so that x and r64 = b - A x
-    // stay consistent in FP64 from the start.
+    // stay consistent in FP64 from the start.  With start_res the start is
+    // kept in FP64 in x and r64 = b - A x comes precomputed in bres.
+    const bool sres = a.x_nonzero && a.start_res;
+    const bool fold = a.x_nonzero && !a.start_res;
+    const double* __restrict__ br = sres ? a.bres + (size_t)pid * a.stride : nullptr;
     double bb = 0.0, r2 = 0.0;
     for (int q = threadIdx.x; q < npad; q += NT) {
         const int xx = q & 63, yy = (q >> 6) & 63, zz = q >> 12;
@@ -331,18 +335,19 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
         T c0 = T(0);
         if (xx < nx && yy < ny && zz < nz) {
             const int id = (zz * ny + yy) * nx + xx;
-            rv = b[id];
-            bb += rv * rv;
-            if (a.x_nonzero) c0 = (T)x[id];
-            x[id] = 0.0;
+            const double bv = b[id];
+            bb += bv * bv;
+            rv = sres ? br[id] : bv;
+            if (fold) c0 = (T)x[id];
+            if (!sres) x[id] = 0.0;
         }
         r64[q] = rv;
-        if (a.x_nonzero) cc[q] = c0;
+        if (fold) cc[q] = c0;
         r2 += rv * rv;
     }
     bb = block_sum<NT>(bb, red);
     r2 = block_sum<NT>(r2, red);
-    if (a.x_nonzero) r2 = refresh();
+    if (fold) r2 = refresh();
 
     int it = 0, conv = 0;
     // inner state from r64: r = (T) r64, c = 0 (p is kept across replacements)

@@ -1,0 +1,168 @@
+// Spectral start for the pair Poisson solves (an extension of the CG start
+// guess of Eq. 9; the CG still drives every pair to the same true residual).
+//
+// With x0 the multipole start, the correction e = x - x0 solves A e = r0,
+// r0 = b - A x0, where A is the O(h^12) Laplacian with zero values beyond
+// the domain.  The same stencil with odd (instead of zero) continuation
+// beyond each face is diagonalized exactly by the type-I discrete sine
+// transform: for the mode sin((i+1) theta), theta = pi m / (n+1), one axis
+// contributes -(c0 + 2 sum_k ck cos(k theta)) / h^2.  The two operators
+// differ only where the stencil reaches past a face, i.e. within 6 points
+// of the boundary, and there e is tiny because x0 already carries the
+// multipole potential that sets the boundary values.  So e ~ S^-1 (r0 ./
+// lambda) with S the separable sine transform, and x0 + e leaves a
+// residual many decades below r0.
+//
+// The transform along one axis is a dense product with the symmetric,
+// orthogonal matrix S_n[j][k] = sqrt(2/(n+1)) sin(pi (j+1)(k+1)/(n+1))
+// (n <= 64 here, so a 64 x 64 product beats an FFT of this length on this
+// part).  Each pass transforms the slowest axis of a pair's array (a, b, c)
+// and writes (b, c, a'): the axes rotate, so three passes transform z, y,
+// x and restore the layout.  Forward passes end with the division by
+// lambda, inverse passes (the same matrices: S is its own inverse) with
+// the addition into x.  FP64 throughout; pairs with an axis longer than
+// 64 keep the multipole start.
+#include "sea_internal.h"
+
+namespace {
+
+constexpr int DS_BS = 256;
+constexpr int DS_N = 64;        // longest axis handled
+constexpr int DS_TC = 64;       // columns per workgroup tile
+constexpr double kPiD = 3.14159265358979323846;
+// second-derivative weights of the O(h^12) central difference (App. C)
+constexpr double kW[7] = {-5369.0 / 1800.0, 12.0 / 7.0, -15.0 / 56.0, 10.0 / 189.0,
+                          -1.0 / 112.0, 2.0 / 1925.0, -1.0 / 16632.0};
+
+__host__ __device__ constexpr int tab_off(int n) { return (n - 1) * n * (2 * n - 1) / 6; }  // sum of m^2, m < n
+__host__ __device__ constexpr int mu_off(int n) { return (n - 1) * n / 2; }                  // sum of m, m < n
+
+// S_n and the one-axis eigenvalues (h = 1) for n = blockIdx.x + 1
+__global__ __launch_bounds__(DS_BS) void k_dst_tables(double* __restrict__ S, double* __restrict__ mu) {
+    const int n = blockIdx.x + 1;
+    double* Sn = S + tab_off(n);
+    const double sc = sqrt(2.0 / (n + 1));
+    for (int t = threadIdx.x; t < n * n; t += DS_BS) {
+        const int j = t / n, k = t % n;
+        const int m = ((j + 1) * (k + 1)) % (2 * (n + 1));   // argument reduced to [0, 2 pi)
+        Sn[t] = sc * sin(kPiD * (double)m / (double)(n + 1));
+    }
+    for (int m = threadIdx.x; m < n; m += DS_BS) {
+        const double th = kPiD * (double)(m + 1) / (double)(n + 1);
+        double s = kW[0];
+#pragma unroll
+        for (int k = 1; k <= 6; ++k) s += 2.0 * kW[k] * cos(k * th);
+        mu[mu_off(n) + m] = -s;
+    }
+}
+
+struct DstArgs {
+    const sea_pair* pairs;
+    const DevCell* cells;
+    const int* pair_cell;
+    size_t stride;
+    const double* in;
+    double* out;
+    const double* S;
+    const double* mu;
+    int pass;   // 0: (z,y,x) -> (y,x,z'); 1: (y,x,z) -> (x,z,y'); 2: (x,z,y) -> (z,y,x')
+    int mode;   // 0 plain; 1 divide by lambda; 2 add into out (the start x)
+};
+
+// grid (pairs, column tiles)
+__global__ __launch_bounds__(DS_BS) void k_dst_pass(DstArgs d) {
+    __shared__ double sS[DS_N * DS_N];
+    __shared__ double tin[DS_N * DS_TC];
+    const int pid = blockIdx.x;
+    const sea_pair P = d.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    if (nx > DS_N || ny > DS_N || nz > DS_N) return;   // keeps the multipole start
+    // shape (A, B, C) of this pass's input, A transformed
+    int A, B, C;
+    if (d.pass == 0) { A = nz; B = ny; C = nx; }
+    else if (d.pass == 1) { A = ny; B = nx; C = nz; }
+    else { A = nx; B = nz; C = ny; }
+    const int ncol = B * C;
+    const int col0 = blockIdx.y * DS_TC;
+    if (col0 >= ncol) return;
+    const double* in = d.in + (size_t)pid * d.stride;
+    double* out = d.out + (size_t)pid * d.stride;
+    const double* Sa = d.S + tab_off(A);
+    for (int t = threadIdx.x; t < A * A; t += DS_BS) sS[(t / A) * DS_N + t % A] = Sa[t];
+    for (int t = threadIdx.x; t < A * DS_TC; t += DS_BS) {
+        const int a = t / DS_TC, c = t % DS_TC;
+        tin[a * DS_TC + c] = (col0 + c < ncol) ? in[(size_t)a * ncol + col0 + c] : 0.0;
+    }
+    __syncthreads();
+    // thread: outputs j = jb + 16 u, columns cb + 16 v (u, v < 4)
+    const int jb = threadIdx.x & 15, cb = threadIdx.x >> 4;
+    double acc[4][4] = {};
+    for (int k = 0; k < A; ++k) {
+        double s[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] = sS[k * DS_N + jb + 16 * u];   // S[k][j] = S[j][k]
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = tin[k * DS_TC + cb + 16 * v];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += s[u] * x[v];
+    }
+    const DevCell& Cl = d.cells[d.pair_cell[pid]];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int col = col0 + cb + 16 * v;
+        if (col >= ncol) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = jb + 16 * u;
+            if (j >= A) continue;
+            double val = acc[u][v];
+            const size_t o = (size_t)col * A + j;
+            if (d.mode == 1) {
+                // output (z, y, x) after the third forward pass: col = z * ny + y, j = x
+                const int zz = col / C, yy = col % C;
+                const double lam = d.mu[mu_off(nz) + zz] / (Cl.h[2] * Cl.h[2]) +
+                                   d.mu[mu_off(ny) + yy] / (Cl.h[1] * Cl.h[1]) +
+                                   d.mu[mu_off(nx) + j] / (Cl.h[0] * Cl.h[0]);
+                out[o] = val / lam;
+            } else if (d.mode == 2) {
+                out[o] += val;
+            } else {
+                out[o] = val;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+size_t dst_table_doubles() { return (size_t)tab_off(DS_N + 1); }
+size_t dst_mu_doubles() { return (size_t)mu_off(DS_N + 1); }
+
+// x += S^-1 ((S r) ./ lambda) for every pair whose axes are all <= 64:
+// r (n_pairs x stride) is overwritten, tmp is scratch of the same size.
+hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, double* tmp, double* tab, double* mu,
+                                 hipStream_t s) {
+    if (a.n_pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dst_tables, dim3(DS_N), dim3(DS_BS), 0, s, tab, mu);
+    DstArgs d{};
+    d.pairs = a.pairs;
+    d.cells = a.cells;
+    d.pair_cell = a.pair_cell;
+    d.stride = a.stride;
+    d.S = tab;
+    d.mu = mu;
+    const dim3 grid((unsigned)a.n_pairs, (unsigned)((ncol_max + DS_TC - 1) / DS_TC));
+    // forward: r -> tmp -> r -> tmp (divided by lambda); inverse: tmp -> r -> tmp -> x (added)
+    const double* ins[6] = {r, tmp, r, tmp, r, tmp};
+    double* outs[6] = {tmp, r, tmp, r, tmp, a.v};
+    for (int q = 0; q < 6; ++q) {
+        d.in = ins[q];
+        d.out = outs[q];
+        d.pass = q % 3;
+        d.mode = q == 2 ? 1 : (q == 5 ? 2 : 0);
+        hipLaunchKernelGGL(k_dst_pass, grid, dim3(DS_BS), 0, s, d);
+    }
+    return hipGetLastError();
+}

@@ -48,7 +48,8 @@ sea_status check_opts(sea_ctx* ctx, const sea_opts* o) {
         return fail(ctx, SEA_E_ARG, "stencil_dtype must be SEA_F64 or SEA_F32");
     if (o->ace_dtype != SEA_F64 && o->ace_dtype != SEA_F32 && o->ace_dtype != SEA_BF16)
         return fail(ctx, SEA_E_ARG, "bad ace_dtype");
-    if (o->start != SEA_START_ZERO && o->start != SEA_START_MULTIPOLE && o->start != SEA_START_LEARNED)
+    if (o->start != SEA_START_ZERO && o->start != SEA_START_MULTIPOLE && o->start != SEA_START_LEARNED &&
+        o->start != SEA_START_SPECTRAL)
         return fail(ctx, SEA_E_ARG, "bad start");
     if (o->nn_weight_dtype != SEA_F32 && o->nn_weight_dtype != SEA_BF16)
         return fail(ctx, SEA_E_ARG, "nn_weight_dtype must be SEA_F32 or SEA_BF16");
@@ -217,10 +218,15 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.mom = take(np * SEA_NACC * sizeof(double));
     L.b = take(np * stride * sizeof(double));
     L.v = with_v ? take(np * stride * sizeof(double)) : 0;
-    // b - A x0 of a start guess: the generic FP64 kernel only (the FP32 z-march
-    // folds the guess into its first FP64 residual update)
-    L.bres = (ctx->opts.start != SEA_START_ZERO && ctx->opts.stencil_dtype == SEA_F64)
+    // b - A x0 of a start guess: the generic FP64 kernel and the spectral
+    // start (the FP32 z-march folds the other guesses into its first FP64
+    // residual update)
+    const bool spectral = ctx->opts.start == SEA_START_SPECTRAL;
+    L.bres = ((ctx->opts.start != SEA_START_ZERO && ctx->opts.stencil_dtype == SEA_F64) || spectral)
                  ? take(np * stride * sizeof(double)) : 0;
+    L.dst_tmp = spectral ? take(np * stride * sizeof(double)) : 0;
+    L.dst_tab = spectral ? take(dst_table_doubles() * sizeof(double)) : 0;
+    L.dst_mu = spectral ? take(dst_mu_doubles() * sizeof(double)) : 0;
     L.gbuf = take(np * L.gstride * sizeof(double));
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
@@ -548,13 +554,29 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                 }
                 SEA_HIP_CHECK(ctx, launch_nn_apply(a, kNnGrid, y32, s));
             }
-            if (!zm) SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
+            if (ctx->opts.start == SEA_START_SPECTRAL) {
+                // bres = b - A x0; x += the sine-transform correction; bres = b - A x
+                int ncol_max = 1;
+                for (const auto& p : S.pairs)
+                    if (p.n[0] <= 64 && p.n[1] <= 64 && p.n[2] <= 64) {
+                        const int m = std::max(p.n[0] * p.n[1], std::max(p.n[1] * p.n[2], p.n[0] * p.n[2]));
+                        ncol_max = std::max(ncol_max, m);
+                    }
+                SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
+                SEA_HIP_CHECK(ctx, launch_spectral_start(a, ncol_max, a.bres, (double*)(base + Ly.dst_tmp),
+                                                         (double*)(base + Ly.dst_tab), (double*)(base + Ly.dst_mu), s));
+                SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
+            } else if (!zm) {
+                SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
+            }
             timer_off(SEA_STAGE_GUESS);
         }
         timer_on(SEA_STAGE_CG);
         if (zm) {
             const int var = ctx->opts.cg_variant >= 0 ? ctx->opts.cg_variant : (ctx->cg_tuned >= 0 ? ctx->cg_tuned : 0);
-            SEA_HIP_CHECK(ctx, launch_cg_zm(a, var, s));
+            ExxArgs az = a;
+            az.start_res = ctx->opts.start == SEA_START_SPECTRAL ? 1 : 0;
+            SEA_HIP_CHECK(ctx, launch_cg_zm(az, var, s));
             timer_off(SEA_STAGE_CG);
             timer_on(SEA_STAGE_FINISH);
             SEA_HIP_CHECK(ctx, launch_cg_finish(a, s));

@@ -58,7 +58,7 @@ struct StageTimer {
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
     size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, counter;
-    size_t nnx, nny, nnact, total;
+    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, total;
     size_t gstride;
     int nmax;
     int n_chunks;
@@ -109,6 +109,7 @@ struct ExxArgs {
     const int* order;     // CG queue order: pair ids by decreasing domain size (nullable)
     const int* dbox;      // per pair 12 ints: boxes where W_i and W_j take the pair
     int x_nonzero;        // v holds a start guess on entry to the CG
+    int start_res;        // FP32 z-march: bres already holds b - A x in FP64 (x kept as the FP64 start)
     double* bres;         // n_pairs x stride: b - A x0 when x_nonzero
     double* gbuf;         // ghost-layer multipole values, n_pairs x gstride
     size_t gstride;       // 36 x nmax^2
@@ -125,6 +126,12 @@ hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s);
 hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s);
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s);
 hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
+// Spectral start (k_dst.hip): x += correction from the residual r (overwritten;
+// tmp scratch of the same size); ncol_max = largest product of two axes.
+size_t dst_table_doubles();
+size_t dst_mu_doubles();
+hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, double* tmp, double* tab, double* mu,
+                                 hipStream_t s);
 // z-marching CG (k_cg.hip): needs every pair with n[0], n[1] <= 64.
 bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h);
 size_t cg_zm_lds_bytes(int state_f32);

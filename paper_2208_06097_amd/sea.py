@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsea.so")
 SEA_OK, SEA_W_NOT_CONVERGED, SEA_W_EIGEN_FALLBACK = 0, 1, 2
 SEA_E_ARG, SEA_E_HIP, SEA_E_NOMEM, SEA_E_NOT_PD, SEA_E_NONFINITE, SEA_E_RANK = -1, -2, -3, -4, -5, -6
 SEA_F64, SEA_F32, SEA_BF16 = 0, 1, 2
-SEA_START_ZERO, SEA_START_MULTIPOLE, SEA_START_LEARNED = 0, 1, 2
+SEA_START_ZERO, SEA_START_MULTIPOLE, SEA_START_LEARNED, SEA_START_SPECTRAL = 0, 1, 2, 3
 SEA_DECOMP_CHOLESKY, SEA_DECOMP_EIGEN, SEA_DECOMP_AUTO = 0, 1, 2
 
 # exported symbols declared in include/sea.h

@@ -1,0 +1,128 @@
+"""The spectral start (multipole start plus a sine-transform correction) on
+the GPU against the oracle: the CG still runs to the same true residual, so
+E and W must meet the product bars (1e-6 Ha, 1e-5), with far fewer
+iterations than the multipole start.  FP64 (generic kernel) and FP32
+(z-march, FP64 start residual) states, uneven epsilon boxes, domains longer
+than 64 points (which keep the multipole start), and HIP-graph plans."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_06097_amd import sea, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _ctx(**kw):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return sea.Context(**kw)
+
+
+@pytest.fixture(scope="module")
+def mini():
+    cell = synth.mini()
+    pl = oracle.build_pairs(cell.N, cell.L, cell.centres, 6.0, 4.0)
+    ref = oracle.exx(cell.phi, cell.N, cell.L, pl, tol=1e-12)
+    return cell, ref, sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, 4.0)
+
+
+@pytest.mark.parametrize("sdt", ["f64", "f32"])
+def test_spectral_start_mini_matches_oracle(mini, sdt):
+    cell, ref, pairs = mini
+    print(f"case spectral mini {sdt}", flush=True)
+    dt = sea.SEA_F64 if sdt == "f64" else sea.SEA_F32
+    phi = torch.from_numpy(cell.phi).cuda()
+    res = {}
+    for name, st in (("multipole", sea.SEA_START_MULTIPOLE), ("spectral", sea.SEA_START_SPECTRAL)):
+        ctx = _ctx(rel_tol=1e-8, stencil_dtype=dt, start=st)
+        W, E, stats, s = ctx.exx_action(phi, cell.N, cell.L, pairs)
+        assert s == sea.SEA_OK and np.all(stats["converged"] == 1) and np.all(stats["rel_res"] <= 1e-8)
+        res[name] = (W.cpu().numpy(), E, stats["iters"].astype(float))
+        ctx.close()
+    W, E, it = res["spectral"]
+    print(f"E {E:.10f} oracle {ref.E:.10f}; iterations spectral {it.mean():.1f} multipole "
+          f"{res['multipole'][2].mean():.1f}", flush=True)
+    assert abs(E - ref.E) < 1e-6
+    assert np.max(np.abs(W - ref.W)) < 1e-5
+    assert it.mean() < 0.5 * res["multipole"][2].mean()
+
+
+@pytest.mark.parametrize("sdt", ["f64", "f32"])
+def test_spectral_start_c1_against_golden(sdt):
+    g = json.load(open(os.path.join(GOLDEN, "c1.json")))
+    cell = synth.config1(seed=g["seed"])
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, g["r_pair"], g["half_width"])
+    print(f"case spectral c1 {sdt}", flush=True)
+    ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F64 if sdt == "f64" else sea.SEA_F32,
+               start=sea.SEA_START_SPECTRAL)
+    W, E, stats, st = ctx.exx_action(torch.from_numpy(cell.phi).cuda(), cell.N, cell.L, pairs)
+    assert st == sea.SEA_OK and np.all(stats["rel_res"] <= 1e-8)
+    print(f"iterations mean {stats['iters'].mean():.2f} max {stats['iters'].max()}", flush=True)
+    assert abs(E - g["E"]) < 1e-6
+    Wf = W.reshape(cell.n_occ, -1)
+    got = Wf[torch.tensor(g["W_orb"], device="cuda"), torch.tensor(g["W_pt"], device="cuda")].cpu().numpy()
+    assert np.max(np.abs(got - np.array(g["W_val"]))) < 1e-5
+    assert np.max(np.abs(stats["e_ij"] - np.array(g["e_pairs"]))) < 1e-7
+    ctx.close()
+
+
+def test_spectral_start_on_eps_boxes_matches_oracle():
+    cell = synth.mini(seed=7)
+    eps = 10 ** -3.5
+    print("case spectral eps boxes", flush=True)
+    ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F32, start=sea.SEA_START_SPECTRAL)
+    phi = torch.from_numpy(cell.phi).cuda()
+    pairs, _ = ctx.build_pairs_eps(phi, cell.N, cell.L, eps, eps, pad=6)
+    assert len(set(map(tuple, pairs["n"].tolist()))) > 1          # uneven boxes
+    W, E, stats, st = ctx.exx_action(phi, cell.N, cell.L, pairs)
+    assert st == sea.SEA_OK and np.all(stats["converged"] == 1)
+    lo, ln = oracle.eps_boxes(cell.phi, cell.N, eps)
+    pl, _ = oracle.eps_pairs(cell.phi, cell.N, cell.L, lo, ln, eps, pad=6)
+    ref = oracle.exx(cell.phi, cell.N, cell.L, pl, tol=1e-12)
+    assert abs(E - ref.E) < 1e-6
+    assert np.max(np.abs(W.cpu().numpy() - ref.W)) < 1e-5
+    ctx.close()
+
+
+def test_long_domains_keep_the_multipole_start():
+    """Domains of 73 points per axis (beyond the transform's 64) keep the
+    multipole start: same iterations and result as SEA_START_MULTIPOLE."""
+    cell = synth.config1()
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, 7.0)[:12]
+    assert pairs["n"].max() > 64
+    print("case spectral long domains", flush=True)
+    phi = torch.from_numpy(cell.phi).cuda()
+    out = {}
+    for st in (sea.SEA_START_MULTIPOLE, sea.SEA_START_SPECTRAL):
+        ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F64, start=st)
+        W, E, stats, s = ctx.exx_action(phi, cell.N, cell.L, pairs)
+        assert s == sea.SEA_OK
+        out[st] = (E, stats["iters"].copy())
+        ctx.close()
+    assert np.array_equal(out[sea.SEA_START_MULTIPOLE][1], out[sea.SEA_START_SPECTRAL][1])
+    assert abs(out[sea.SEA_START_MULTIPOLE][0] - out[sea.SEA_START_SPECTRAL][0]) < 1e-9
+
+
+def test_spectral_plan_replays_match_eager():
+    cell = synth.config1()
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, 6.0)
+    phi = torch.from_numpy(cell.phi.astype(np.float32)).cuda()
+    ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F32, start=sea.SEA_START_SPECTRAL)
+    W0, E0, stats0, st = ctx.exx_action(phi, cell.N, cell.L, pairs)
+    W0 = W0.clone()
+    plan = ctx.exx_plan([(phi, cell.N, cell.L, pairs)])
+    for rep in range(3):
+        plan.launch()
+        torch.cuda.synchronize()
+        E, stats, st = plan.results()
+        assert st == sea.SEA_OK and E[0] == E0
+        assert np.array_equal(stats["iters"], stats0["iters"])
+        torch.cuda.synchronize()
+    plan.close()
+    ctx.close()
