@@ -195,7 +195,7 @@ def main():
     if FORMS[form]["stencil"] == "f32" and args.cg_variant:
         ctx.set_opts(cg_variant=ctx.cg_variants().index(args.cg_variant))
         tune = {"variant": args.cg_variant, "ms": None}
-    elif FORMS[form]["stencil"] == "f32":
+    elif FORMS[form]["stencil"] == "f32" and FORMS[form]["start"] != "spectral":
         tune = ctx.autotune([(phi, cell.N, cell.L, pairs)], sample_pairs=args.tune_pairs, iters=20, ws=ws)
         log(f"autotune: {tune['variant']}  " + "  ".join(f"{k} {v:.1f} ms" for k, v in tune["ms"].items()))
 

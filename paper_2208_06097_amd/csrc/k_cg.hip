@@ -327,6 +327,23 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     // kept in FP64 in x and r64 = b - A x comes precomputed in bres.
     const bool sres = a.x_nonzero && a.start_res;
     const bool fold = a.x_nonzero && !a.start_res;
+    if (sres && a.rnorm) {
+        // the residual pass already has both norms: a converged start needs
+        // no work here
+        double b2 = 0.0, q2 = 0.0;
+        for (int t = 0; t < RZ_TILES; ++t) {   // fixed order: deterministic
+            b2 += a.rnorm[((size_t)pid * RZ_TILES + t) * 2];
+            q2 += a.rnorm[((size_t)pid * RZ_TILES + t) * 2 + 1];
+        }
+        if (q2 == q2 && b2 == b2 && q2 <= tol2 * b2) {
+            if (threadIdx.x == 0) {
+                a.stats[pid].iters = 0;
+                a.stats[pid].converged = 1;
+                a.stats[pid].rel_res = b2 > 0.0 ? sqrt(q2 / b2) : 0.0;
+            }
+            return;
+        }
+    }
     const double* __restrict__ br = sres ? a.bres + (size_t)pid * a.stride : nullptr;
     double bb = 0.0, r2 = 0.0;
     for (int q = threadIdx.x; q < npad; q += NT) {
@@ -542,6 +559,84 @@ __global__ __launch_bounds__(FIN_BS) void k_start_residual(ExxArgs a) {
         const int xx = id % nx, yy = (id / nx) % ny, zz = id / nxy;
         br[id] = b[id] - apply_A_global(x, id, xx, yy, zz, nx, ny, nz, ih2);
     }
+}
+
+// b - A x in FP64 for every pair of a cubic grid with nx, ny <= 64: the
+// z-march above on FP64 planes.  A workgroup owns 16 rows (y) of one pair
+// and marches a window of 28 rows (6 more on each side, fetched again by the
+// neighbouring workgroups) so that its register queue (2 rows per thread,
+// 13 planes) fits; rows of the window outside the domain read zero.  Also
+// |b|^2 and |b - A x|^2 of the owned rows into a.rnorm[pair][tile][2].
+constexpr int RZ_NT = 1024;
+constexpr int RZ_COLS = 2;
+constexpr int RZ_ROWS = 16;   // rows owned per workgroup
+static_assert(RZ_TILES * RZ_ROWS >= 64, "row tiles cover 64 rows");
+
+__global__ __launch_bounds__(RZ_NT) void k_residual_zm(ExxArgs a) {
+    extern __shared__ unsigned char smem[];
+    double* lds = reinterpret_cast<double*>(smem);
+    __shared__ double red[RZ_NT / 64 + 1];
+    const int pid = blockIdx.x;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int y0 = blockIdx.y * RZ_ROWS;
+    if (y0 >= ny) {
+        if (threadIdx.x == 0) {
+            a.rnorm[((size_t)pid * RZ_TILES + blockIdx.y) * 2] = 0.0;
+            a.rnorm[((size_t)pid * RZ_TILES + blockIdx.y) * 2 + 1] = 0.0;
+        }
+        return;
+    }
+    for (int i = threadIdx.x; i < 2 * LW * LH; i += RZ_NT) lds[i] = 0.0;
+    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const SW<double> w = make_sw<double>(1.0 / (C.h[0] * C.h[0]));
+    const double* __restrict__ x = a.v + (size_t)pid * a.stride;
+    const double* __restrict__ b = a.b + (size_t)pid * a.stride;
+    double* __restrict__ r = a.bres + (size_t)pid * a.stride;
+    constexpr int TY = RZ_NT / 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    __syncthreads();
+    // window row yw = ty + TY c is grid row y0 - 6 + yw; rows 6..21 are owned
+    auto grow = [&](int c) { return y0 - SEA_HALO + ty + TY * c; };
+    auto owned = [&](int c) {
+        const int yw = ty + TY * c, y = grow(c);
+        return yw >= SEA_HALO && yw < SEA_HALO + RZ_ROWS && y < ny && tx < nx;
+    };
+    double bb = 0.0, rr = 0.0;
+    zmarch<double, double, RZ_NT, RZ_COLS, 1, double, double>(
+        nz, lds, w,
+        [&](int c, int z) -> double {
+            const int yw = ty + TY * c, y = grow(c);
+            return (tx < nx && y >= 0 && y < ny && yw < RZ_ROWS + 2 * SEA_HALO && z < nz)
+                       ? x[((size_t)z * ny + y) * nx + tx] : 0.0;
+        },
+        [&](int, int, double v) -> double { return v; },
+        [&](int c, int z) -> double { return owned(c) ? b[((size_t)z * ny + grow(c)) * nx + tx] : 0.0; },
+        [&](int c, int z, double s, double, double bv) {
+            if (owned(c)) {
+                const double rv = bv - s;
+                r[((size_t)z * ny + grow(c)) * nx + tx] = rv;
+                bb += bv * bv;
+                rr += rv * rv;
+            }
+        });
+    bb = block_sum<RZ_NT>(bb, red);
+    rr = block_sum<RZ_NT>(rr, red);
+    if (threadIdx.x == 0) {
+        a.rnorm[((size_t)pid * RZ_TILES + blockIdx.y) * 2] = bb;
+        a.rnorm[((size_t)pid * RZ_TILES + blockIdx.y) * 2 + 1] = rr;
+    }
+}
+
+size_t residual_zm_lds_bytes() { return (size_t)2 * LW * LH * sizeof(double); }
+
+hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s) {
+    if (a.n_pairs <= 0) return hipSuccess;
+    const int lds = (int)residual_zm_lds_bytes();
+    hipError_t e = hipFuncSetAttribute((const void*)k_residual_zm, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_residual_zm, dim3(a.n_pairs, RZ_TILES), dim3(RZ_NT), lds, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s) {

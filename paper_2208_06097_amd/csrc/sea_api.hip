@@ -227,6 +227,7 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.dst_tmp = spectral ? take(np * stride * sizeof(double)) : 0;
     L.dst_tab = spectral ? take(dst_table_doubles() * sizeof(double)) : 0;
     L.dst_mu = spectral ? take(dst_mu_doubles() * sizeof(double)) : 0;
+    L.rnorm = spectral ? take(np * RZ_TILES * 2 * sizeof(double)) : 0;
     L.gbuf = take(np * L.gstride * sizeof(double));
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
@@ -562,10 +563,14 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                         const int m = std::max(p.n[0] * p.n[1], std::max(p.n[1] * p.n[2], p.n[0] * p.n[2]));
                         ncol_max = std::max(ncol_max, m);
                     }
-                SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
+                const bool rzm = zm && residual_zm_lds_bytes() <= ctx->max_lds;
+                ExxArgs ar = a;
+                ar.rnorm = rzm ? (double*)(base + Ly.rnorm) : nullptr;
+                auto residual = [&]() { return rzm ? launch_residual_zm(ar, s) : launch_start_residual(a, s); };
+                SEA_HIP_CHECK(ctx, residual());
                 SEA_HIP_CHECK(ctx, launch_spectral_start(a, ncol_max, a.bres, (double*)(base + Ly.dst_tmp),
                                                          (double*)(base + Ly.dst_tab), (double*)(base + Ly.dst_mu), s));
-                SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
+                SEA_HIP_CHECK(ctx, residual());
             } else if (!zm) {
                 SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
             }
@@ -576,6 +581,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
             const int var = ctx->opts.cg_variant >= 0 ? ctx->opts.cg_variant : (ctx->cg_tuned >= 0 ? ctx->cg_tuned : 0);
             ExxArgs az = a;
             az.start_res = ctx->opts.start == SEA_START_SPECTRAL ? 1 : 0;
+            az.rnorm = (az.start_res && residual_zm_lds_bytes() <= ctx->max_lds) ? (double*)(base + Ly.rnorm) : nullptr;
             SEA_HIP_CHECK(ctx, launch_cg_zm(az, var, s));
             timer_off(SEA_STAGE_CG);
             timer_on(SEA_STAGE_FINISH);

@@ -58,7 +58,7 @@ struct StageTimer {
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
     size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, counter;
-    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, total;
+    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, total;
     size_t gstride;
     int nmax;
     int n_chunks;
@@ -110,6 +110,7 @@ struct ExxArgs {
     const int* dbox;      // per pair 12 ints: boxes where W_i and W_j take the pair
     int x_nonzero;        // v holds a start guess on entry to the CG
     int start_res;        // FP32 z-march: bres already holds b - A x in FP64 (x kept as the FP64 start)
+    double* rnorm;        // n_pairs x RZ_TILES x 2: |b|^2, |b - A x|^2 per row tile of the FP64 residual z-march (nullable)
     double* bres;         // n_pairs x stride: b - A x0 when x_nonzero
     double* gbuf;         // ghost-layer multipole values, n_pairs x gstride
     size_t gstride;       // 36 x nmax^2
@@ -126,6 +127,11 @@ hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s);
 hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s);
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s);
 hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
+// b - A x in FP64 by z-march (cubic grids, nx, ny <= 64) and the two norms
+// per pair into a.rnorm.
+constexpr int RZ_TILES = 4;   // row tiles of 16 per pair in the residual z-march
+size_t residual_zm_lds_bytes();
+hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s);
 // Spectral start (k_dst.hip): x += correction from the residual r (overwritten;
 // tmp scratch of the same size); ncol_max = largest product of two axes.
 size_t dst_table_doubles();
