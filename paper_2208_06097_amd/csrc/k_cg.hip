@@ -515,10 +515,11 @@ __global__ __launch_bounds__(FIN_BS) void k_cg_finish(ExxArgs a) {
     const double* x = a.v + (size_t)pid * a.stride;
     const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
     double e = 0.0;
-    for (int id = threadIdx.x; id < n; id += FIN_BS) {
-        const int xx = id % nx, yy = (id / nx) % ny, zz = id / nxy;
-        const size_t g = ((size_t)wrap_idx(P.lo[2] + zz, C.N[2]) * C.N[1] + wrap_idx(P.lo[1] + yy, C.N[1])) * C.N[0] +
-                         wrap_idx(P.lo[0] + xx, C.N[0]);
+    BoxWalk wk((int)threadIdx.x, FIN_BS, nx, ny);
+    for (int id = threadIdx.x; id < n; id += FIN_BS, wk.next()) {
+        const int xx = wk.x, yy = wk.y, zz = wk.z;
+        const size_t g = ((size_t)wrap_near(P.lo[2] + zz, C.N[2]) * C.N[1] + wrap_near(P.lo[1] + yy, C.N[1])) * C.N[0] +
+                         wrap_near(P.lo[0] + xx, C.N[0]);
         e += load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g) * x[id];
     }
     e = block_sum<FIN_BS>(e, red);

@@ -69,7 +69,12 @@ struct DstArgs {
     int mode;   // 0 plain; 1 divide by lambda; 2 add into out (the start x)
 };
 
-// grid (pairs, column tiles)
+// grid (pairs, DS_TG): workgroup y takes column tiles y, y + DS_TG, ... of
+// its pair, with S_A staged once.  Staging loads are issued together
+// (registers first, then LDS) so their latencies overlap.
+constexpr int DS_TG = 16;
+constexpr int DS_LD = (DS_N * DS_N) / DS_BS;   // staging loads per thread (16)
+
 __global__ __launch_bounds__(DS_BS) void k_dst_pass(DstArgs d) {
     __shared__ double sS[DS_N * DS_N];
     __shared__ double tin[DS_N * DS_TC];
@@ -83,53 +88,77 @@ __global__ __launch_bounds__(DS_BS) void k_dst_pass(DstArgs d) {
     else if (d.pass == 1) { A = ny; B = nx; C = nz; }
     else { A = nx; B = nz; C = ny; }
     const int ncol = B * C;
-    const int col0 = blockIdx.y * DS_TC;
-    if (col0 >= ncol) return;
+    if ((int)blockIdx.y * DS_TC >= ncol) return;
     const double* in = d.in + (size_t)pid * d.stride;
     double* out = d.out + (size_t)pid * d.stride;
-    const double* Sa = d.S + tab_off(A);
-    for (int t = threadIdx.x; t < A * A; t += DS_BS) sS[(t / A) * DS_N + t % A] = Sa[t];
-    for (int t = threadIdx.x; t < A * DS_TC; t += DS_BS) {
-        const int a = t / DS_TC, c = t % DS_TC;
-        tin[a * DS_TC + c] = (col0 + c < ncol) ? in[(size_t)a * ncol + col0 + c] : 0.0;
-    }
-    __syncthreads();
-    // thread: outputs j = jb + 16 u, columns cb + 16 v (u, v < 4)
-    const int jb = threadIdx.x & 15, cb = threadIdx.x >> 4;
-    double acc[4][4] = {};
-    for (int k = 0; k < A; ++k) {
-        double s[4], x[4];
+    {
+        const double* Sa = d.S + tab_off(A);
+        double t[DS_LD];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s[u] = sS[k * DS_N + jb + 16 * u];   // S[k][j] = S[j][k]
+        for (int u = 0; u < DS_LD; ++u) {
+            const int q = threadIdx.x + u * DS_BS;
+            t[u] = q < A * A ? Sa[q] : 0.0;
+        }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) x[v] = tin[k * DS_TC + cb + 16 * v];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] += s[u] * x[v];
+        for (int u = 0; u < DS_LD; ++u) {
+            const int q = threadIdx.x + u * DS_BS;
+            if (q < A * A) sS[(q / A) * DS_N + q % A] = t[u];
+        }
     }
     const DevCell& Cl = d.cells[d.pair_cell[pid]];
+    // thread: outputs j = jb + 16 u, columns cb + 16 v (u, v < 4)
+    const int jb = threadIdx.x & 15, cb = threadIdx.x >> 4;
+    // the next tile's input is loaded into registers while this one computes
+    double nxt[DS_LD];
+    auto load_tile = [&](int c0) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int col = col0 + cb + 16 * v;
-        if (col >= ncol) continue;
+        for (int u = 0; u < DS_LD; ++u) {
+            const int q = threadIdx.x + u * DS_BS, a = q / DS_TC, c = q % DS_TC;
+            nxt[u] = (a < A && c0 + c < ncol) ? in[(size_t)a * ncol + c0 + c] : 0.0;
+        }
+    };
+    load_tile(blockIdx.y * DS_TC);
+    for (int col0 = blockIdx.y * DS_TC; col0 < ncol; col0 += DS_TG * DS_TC) {
+        __syncthreads();   // the previous tile's products are done with tin
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int j = jb + 16 * u;
-            if (j >= A) continue;
-            double val = acc[u][v];
-            const size_t o = (size_t)col * A + j;
-            if (d.mode == 1) {
-                // output (z, y, x) after the third forward pass: col = z * ny + y, j = x
-                const int zz = col / C, yy = col % C;
-                const double lam = d.mu[mu_off(nz) + zz] / (Cl.h[2] * Cl.h[2]) +
-                                   d.mu[mu_off(ny) + yy] / (Cl.h[1] * Cl.h[1]) +
-                                   d.mu[mu_off(nx) + j] / (Cl.h[0] * Cl.h[0]);
-                out[o] = val / lam;
-            } else if (d.mode == 2) {
-                out[o] += val;
-            } else {
-                out[o] = val;
+        for (int u = 0; u < DS_LD; ++u) tin[threadIdx.x + u * DS_BS] = nxt[u];
+        __syncthreads();
+        if (col0 + DS_TG * DS_TC < ncol) load_tile(col0 + DS_TG * DS_TC);
+        double acc[4][4] = {};
+#pragma unroll 4
+        for (int k = 0; k < A; ++k) {
+            double sv[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sv[u] = sS[k * DS_N + jb + 16 * u];   // S[k][j] = S[j][k]
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xv[v] = tin[k * DS_TC + cb + 16 * v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += sv[u] * xv[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int col = col0 + cb + 16 * v;
+            if (col >= ncol) continue;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = jb + 16 * u;
+                if (j >= A) continue;
+                const double val = acc[u][v];
+                const size_t o = (size_t)col * A + j;
+                if (d.mode == 1) {
+                    // output (z, y, x) after the third forward pass: col = z * ny + y, j = x
+                    const int zz = col / C, yy = col % C;
+                    const double lam = d.mu[mu_off(nz) + zz] / (Cl.h[2] * Cl.h[2]) +
+                                       d.mu[mu_off(ny) + yy] / (Cl.h[1] * Cl.h[1]) +
+                                       d.mu[mu_off(nx) + j] / (Cl.h[0] * Cl.h[0]);
+                    out[o] = val / lam;
+                } else if (d.mode == 2) {
+                    out[o] += val;
+                } else {
+                    out[o] = val;
+                }
             }
         }
     }
@@ -153,7 +182,8 @@ hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, doub
     d.stride = a.stride;
     d.S = tab;
     d.mu = mu;
-    const dim3 grid((unsigned)a.n_pairs, (unsigned)((ncol_max + DS_TC - 1) / DS_TC));
+    const int tiles = (ncol_max + DS_TC - 1) / DS_TC;
+    const dim3 grid((unsigned)a.n_pairs, (unsigned)(tiles < DS_TG ? tiles : DS_TG));
     // forward: r -> tmp -> r -> tmp (divided by lambda); inverse: tmp -> r -> tmp -> x (added)
     const double* ins[6] = {r, tmp, r, tmp, r, tmp};
     double* outs[6] = {tmp, r, tmp, r, tmp, a.v};

@@ -69,12 +69,11 @@ __global__ __launch_bounds__(GM_BS) void k_gather_moments(ExxArgs a) {
         const long end = min(beg + GM_CHUNK, n_int);
         const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
         double* b = a.b + (size_t)pid * a.stride;
-        for (long id = beg + threadIdx.x; id < end; id += GM_BS) {
-            const int x = (int)(id % nx);
-            const int y = (int)((id / nx) % ny);
-            const int z = (int)(id / ((long)nx * ny));
-            const size_t g = ((size_t)wrap_idx(P.lo[2] + z, C.N[2]) * C.N[1] + wrap_idx(P.lo[1] + y, C.N[1])) * C.N[0]
-                             + wrap_idx(P.lo[0] + x, C.N[0]);
+        BoxWalk wk((int)(beg + threadIdx.x), GM_BS, nx, ny);
+        for (long id = beg + threadIdx.x; id < end; id += GM_BS, wk.next()) {
+            const int x = wk.x, y = wk.y, z = wk.z;
+            const size_t g = ((size_t)wrap_near(P.lo[2] + z, C.N[2]) * C.N[1] + wrap_near(P.lo[1] + y, C.N[1])) * C.N[0]
+                             + wrap_near(P.lo[0] + x, C.N[0]);
             const double rho = load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g);
             b[id] = 4.0 * kPi * rho;
             const double dx = (P.lo[0] + x) * C.h[0] - P.origin[0];
@@ -125,75 +124,58 @@ __global__ void k_moments_final(ExxArgs a, double* Q_orth) {
 }
 
 // ---------------------------------------------------------------------------
-// 3. boundary values (Eq. 10) on the ghost layers, then folded into b:
+// 3. boundary values (Eq. 10) on the ghost layers, folded into b:
 //    b += sum over ghost taps (c_k / h_a^2) v_ME(ghost)
 //
-// Ghost buffer of a pair: 6 faces (x-, x+, y-, y+, z-, z+) x 6 layers x
-// (n_u x n_v) values, face stride nmax^2, (u, v) = the two other axes.
-
-constexpr int GE_BS = 256;
+// One axis per launch and one face column per thread: the
+// thread evaluates the 6 ghost values beyond each of the two faces of its
+// (u, v) column and adds their taps to the 6 nearest interior points.  Axes
+// run in separate launches (x, then y, then z), so every b point is updated
+// by one thread at a time, in a fixed order; no ghost buffer is kept.
+constexpr int GA_BS = 256;
 
 template <int LM>
-__global__ __launch_bounds__(GE_BS) void k_ghost_eval(ExxArgs a) {
+__global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a, int ax) {
     __shared__ double Q[SEA_NMOM];
     const int pid = blockIdx.x;
     if (threadIdx.x < SEA_NMOM) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
     __syncthreads();
     const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
-    const int nm = a.nmax, FS = nm * nm;
-    const long t = (long)blockIdx.y * GE_BS + threadIdx.x;
-    if (t >= 36L * FS) return;
-    const int f = (int)(t / (6L * FS));
-    const int L = (int)((t / FS) % 6) + 1;
-    const int rem = (int)(t % FS);
-    const int au = rem % nm, av = rem / nm;
-    const int ax = f >> 1, plus = f & 1;
     const int u = (ax + 1) % 3, v = (ax + 2) % 3;
-    if (au >= P.n[u] || av >= P.n[v]) return;
+    const int t = blockIdx.y * GA_BS + threadIdx.x;
+    const int au = t % a.nmax, av = t / a.nmax;
+    if (av >= a.nmax || au >= P.n[u] || av >= P.n[v]) return;
+    const int n = P.n[ax];
+    const double ih2 = 1.0 / (C.h[ax] * C.h[ax]);
     int pos[3];
-    pos[ax] = plus ? P.n[ax] - 1 + L : -L;
     pos[u] = au;
     pos[v] = av;
-    const double dx = (P.lo[0] + pos[0]) * C.h[0] - P.origin[0];
-    const double dy = (P.lo[1] + pos[1]) * C.h[1] - P.origin[1];
-    const double dz = (P.lo[2] + pos[2]) * C.h[2] - P.origin[2];
-    a.gbuf[(size_t)pid * a.gstride + (size_t)(f * 6 + (L - 1)) * FS + (size_t)av * nm + au] =
-        racah_me_potential<LM>(Q, a.lmax, dx, dy, dz);
-}
-
-constexpr int BF_BS = 256;
-
-__global__ __launch_bounds__(BF_BS) void k_ghost_fold(ExxArgs a) {
-    const int pid = blockIdx.x;
-    const int z = blockIdx.y;
-    const DevCell& C = a.cells[a.pair_cell[pid]];
-    const sea_pair P = a.pairs[pid];
-    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    if (z >= nz) return;
-    const int nm = a.nmax, FS = nm * nm;
-    const double* g = a.gbuf + (size_t)pid * a.gstride;
-    const bool zface = (z < SEA_HALO) || (z >= nz - SEA_HALO);
-    double* b = a.b + (size_t)pid * a.stride + (size_t)z * nx * ny;
-    const double ih2[3] = {1.0 / (C.h[0] * C.h[0]), 1.0 / (C.h[1] * C.h[1]), 1.0 / (C.h[2] * C.h[2])};
-    for (int t = threadIdx.x; t < nx * ny; t += BF_BS) {
-        const int x = t % nx, y = t / nx;
-        if (!(zface || x < SEA_HALO || x >= nx - SEA_HALO || y < SEA_HALO || y >= ny - SEA_HALO)) continue;
-        const int pos[3] = {x, y, z};
-        const int nn[3] = {nx, ny, nz};
-        double acc = 0.0;
+    size_t stride_ax = 1, base = 0;
+    {
+        const size_t st[3] = {1, (size_t)P.n[0], (size_t)P.n[0] * P.n[1]};
+        stride_ax = st[ax];
+        base = pos[u] * st[u] + pos[v] * st[v];
+    }
+    double* b = a.b + (size_t)pid * a.stride + base;
+    for (int plus = 0; plus < 2; ++plus) {
+        double g[SEA_HALO + 1];
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            const int u = (ax + 1) % 3, v = (ax + 2) % 3;
-            const size_t uv = (size_t)pos[v] * nm + pos[u];
-#pragma unroll
-            for (int k = 1; k <= SEA_HALO; ++k) {
-                if (pos[ax] - k < 0) acc += kC[k] * ih2[ax] * g[(size_t)((2 * ax) * 6 + (k - pos[ax] - 1)) * FS + uv];
-                if (pos[ax] + k >= nn[ax])
-                    acc += kC[k] * ih2[ax] * g[(size_t)((2 * ax + 1) * 6 + (pos[ax] + k - nn[ax])) * FS + uv];
-            }
+        for (int L = 1; L <= SEA_HALO; ++L) {
+            pos[ax] = plus ? n - 1 + L : -L;
+            g[L] = racah_me_potential<LM>(Q, a.lmax, (P.lo[0] + pos[0]) * C.h[0] - P.origin[0],
+                                          (P.lo[1] + pos[1]) * C.h[1] - P.origin[1],
+                                          (P.lo[2] + pos[2]) * C.h[2] - P.origin[2]);
         }
-        b[t] += acc;
+#pragma unroll
+        for (int d = 0; d < SEA_HALO; ++d) {
+            if (d >= n) break;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = d + 1; k <= SEA_HALO; ++k) acc += kC[k] * ih2 * g[k - d];
+            const int p = plus ? n - 1 - d : d;
+            b[(size_t)p * stride_ax] += acc;
+        }
     }
 }
 
@@ -247,10 +229,59 @@ __global__ __launch_bounds__(GM_BS) void k_me_guess(ExxArgs a) {
     if (beg >= n_int) return;
     const long end = min(beg + GM_CHUNK, n_int);
     double* x = a.v + (size_t)pid * a.stride;
-    for (long id = beg + threadIdx.x; id < end; id += GM_BS) {
-        const int xx = (int)(id % nx), yy = (int)((id / nx) % ny), zz = (int)(id / ((long)nx * ny));
+    BoxWalk wk((int)(beg + threadIdx.x), GM_BS, nx, ny);
+    for (long id = beg + threadIdx.x; id < end; id += GM_BS, wk.next()) {
+        const int xx = wk.x, yy = wk.y, zz = wk.z;
         x[id] = me_start_value<LM>(Q, a.lmax, (P.lo[0] + xx) * C.h[0] - P.origin[0],
                                    (P.lo[1] + yy) * C.h[1] - P.origin[1], (P.lo[2] + zz) * C.h[2] - P.origin[2]);
+    }
+}
+
+// Multipole start on the 6-point shell inside the faces only, zero deeper
+// in (the spectral start needs the start right only where the stencil's
+// odd continuation past a face differs from its zero continuation, i.e. on
+// the 5 points next to each face).  One
+// workgroup per plane; the shell points of an inner plane (12 full rows and
+// 12 points of every other row) are enumerated densely.
+template <int LM>
+__global__ __launch_bounds__(GM_BS) void k_me_shell(ExxArgs a) {
+    __shared__ double Q[SEA_NACC];
+    const int pid = blockIdx.x, z = blockIdx.y;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    if (z >= nz) return;
+    if (threadIdx.x < SEA_NACC) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
+    __syncthreads();
+    const DevCell& C = a.cells[a.pair_cell[pid]];
+    double* x = a.v + (size_t)pid * a.stride + (size_t)z * nx * ny;
+    auto me = [&](int xx, int yy) {
+        return me_start_value<LM>(Q, a.lmax, (P.lo[0] + xx) * C.h[0] - P.origin[0],
+                                  (P.lo[1] + yy) * C.h[1] - P.origin[1], (P.lo[2] + z) * C.h[2] - P.origin[2]);
+    };
+    constexpr int H = SEA_HALO;
+    // full planes: the faces, thin boxes, and boxes the sine transform does
+    // not take (axes beyond 64 points keep the whole multipole start)
+    if (z < H || z >= nz - H || nx <= 2 * H || ny <= 2 * H || nx > 64 || ny > 64 || nz > 64) {
+        for (int t = threadIdx.x; t < nx * ny; t += GM_BS) x[t] = me(t % nx, t / nx);
+        return;
+    }
+    for (int t = threadIdx.x; t < nx * ny; t += GM_BS) {
+        const int xx = t % nx, yy = t / nx;
+        if (xx >= H && xx < nx - H && yy >= H && yy < ny - H) x[t] = 0.0;
+    }
+    const int nfull = 2 * H * nx, nside = (ny - 2 * H) * 2 * H;
+    for (int t = threadIdx.x; t < nfull + nside; t += GM_BS) {
+        int xx, yy;
+        if (t < nfull) {
+            const int r = t / nx;
+            xx = t % nx;
+            yy = r < H ? r : ny - 2 * H + r;
+        } else {
+            const int j = t - nfull, c = j % (2 * H);
+            yy = H + j / (2 * H);
+            xx = c < H ? c : nx - 2 * H + c;
+        }
+        x[yy * nx + xx] = me(xx, yy);
     }
 }
 
@@ -542,6 +573,54 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
         }
         __syncthreads();
         const int m = cnt;
+        // fast path: this thread's column (gx, gy) and planes tz0 + k; a box no
+        // wider than the cell holds each grid point at most once, found from
+        // per-pair offsets by compare-and-subtract instead of modulo
+        static_assert(SC_TX == 64 && SC_TX * SC_TY == SC_BS, "one (x, y) column per thread");
+        const int gx = tx0 + (threadIdx.x & 63), gy = ty0 + (threadIdx.x >> 6);
+        const bool colin = gx < C.N[0] && gy < C.N[1];
+        for (int q = 0; q < m; ++q) {
+            const int2 en = ent[list[q]];
+            const sea_pair P = a.pairs[en.x];
+            const int* D = a.dbox + 12 * (size_t)en.x + (o == P.i ? 0 : 6);
+            if (D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2]) continue;   // general path below
+            // box coordinates of the tile corner (uniform), then of this column:
+            // gx < N keeps lx below 2N, so one subtraction wraps it
+            int lx = wrap_idx(tx0 - D[0], C.N[0]) + (threadIdx.x & 63);
+            int ly = wrap_idx(ty0 - D[1], C.N[1]) + (threadIdx.x >> 6);
+            lx -= (lx >= C.N[0]) ? C.N[0] : 0;
+            ly -= (ly >= C.N[1]) ? C.N[1] : 0;
+            if (!colin || lx >= D[3] || ly >= D[4]) continue;
+            const int lz0 = wrap_idx(tz0 - D[2], C.N[2]);
+            const int sx = D[0] + lx - P.lo[0], sy = D[1] + ly - P.lo[1];
+            const bool in_xy = sx >= 0 && sx < P.n[0] && sy >= 0 && sy < P.n[1];
+            const double* v = a.v + (size_t)en.x * a.stride;
+            const double* Q = a.mom + (size_t)en.x * SEA_NACC;
+            const size_t gcol = (size_t)gy * C.N[0] + gx;
+            const double* phj = nullptr;
+            const float* phj32 = nullptr;
+            if (C.phi_f32) phj32 = (const float*)C.phi + (size_t)en.y * C.Ng + gcol;
+            else phj = (const double*)C.phi + (size_t)en.y * C.Ng + gcol;
+#pragma unroll
+            for (int k = 0; k < SC_TZ; ++k) {
+                const int gz = tz0 + k;
+                int lz = lz0 + k;
+                lz -= (lz >= C.N[2]) ? C.N[2] : 0;
+                if (gz >= C.N[2] || lz >= D[5]) continue;
+                const int sz = D[2] + lz - P.lo[2];
+                const size_t go = (size_t)gz * C.N[1] * C.N[0];
+                const double ph = C.phi_f32 ? (double)phj32[go] : phj[go];
+                double val;
+                if (in_xy && sz >= 0 && sz < P.n[2])
+                    val = v[((size_t)sz * P.n[1] + sy) * P.n[0] + sx];
+                else
+                    val = racah_me_potential<LM>(Q, a.lmax, (D[0] + lx) * C.h[0] - P.origin[0],
+                                                 (D[1] + ly) * C.h[1] - P.origin[1],
+                                                 (D[2] + lz) * C.h[2] - P.origin[2]);
+                acc[k] += val * ph;
+            }
+        }
+        // general path: boxes wider than the cell (a grid point met several times)
 #pragma unroll
         for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) {
             const int lid = threadIdx.x + k * SC_BS;
@@ -553,6 +632,7 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
                 const int2 en = ent[list[q]];
                 const sea_pair P = a.pairs[en.x];
                 const int* D = a.dbox + 12 * (size_t)en.x + (o == P.i ? 0 : 6);
+                if (!(D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2])) continue;   // fast path above
                 const double* v = a.v + (size_t)en.x * a.stride;
                 const double* Q = a.mom + (size_t)en.x * SEA_NACC;
                 const double ph = load_phi(C.phi, C.phi_f32, (size_t)en.y * C.Ng + g);
@@ -631,17 +711,23 @@ hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s)
 }
 
 hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s) {
-    const long nghost = 36L * a.nmax * a.nmax;
-    hipLaunchKernelGGL(k_ghost_eval<SEA_LMAX>, dim3(a.n_pairs, (unsigned)((nghost + GE_BS - 1) / GE_BS)), dim3(GE_BS),
-                       0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ghost_fold, dim3(a.n_pairs, nz_max), dim3(BF_BS), 0, s, a);
-    return hipGetLastError();
+    (void)nz_max;
+    const unsigned gy = (unsigned)(((long)a.nmax * a.nmax + GA_BS - 1) / GA_BS);
+    for (int ax = 0; ax < 3; ++ax) {
+        hipLaunchKernelGGL(k_ghost_axis<SEA_LMAX>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a, ax);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_me_guess<SEA_LMAX>, dim3(a.n_pairs, a.n_chunks), dim3(GM_BS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_me_shell(const ExxArgs& a, int nz_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_me_shell<SEA_LMAX>, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -200,7 +200,6 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.n_chunks = exx_n_chunks((long)stride);
     L.n_slots = n_pairs < ctx->n_cu * 4 ? (n_pairs > 0 ? n_pairs : 1) : ctx->n_cu * 4;
     L.nmax = nmax;
-    L.gstride = (size_t)36 * nmax * nmax;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -228,7 +227,6 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.dst_tab = spectral ? take(dst_table_doubles() * sizeof(double)) : 0;
     L.dst_mu = spectral ? take(dst_mu_doubles() * sizeof(double)) : 0;
     L.rnorm = spectral ? take(np * RZ_TILES * 2 * sizeof(double)) : 0;
-    L.gbuf = take(np * L.gstride * sizeof(double));
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
     L.csr_off = take((S.csr_off.size() + 1) * sizeof(int));
@@ -492,8 +490,6 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.queue_ctr = (int*)(base + Ly.counter);
     a.x_nonzero = ctx->opts.start != SEA_START_ZERO;
     a.bres = Ly.bres ? (double*)(base + Ly.bres) : nullptr;
-    a.gbuf = (double*)(base + Ly.gbuf);
-    a.gstride = Ly.gstride;
     a.nmax = Ly.nmax;
     return a;
 }
@@ -530,7 +526,10 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         timer_off(SEA_STAGE_BOUNDARY);
         if (a.x_nonzero) {
             timer_on(SEA_STAGE_GUESS);
-            SEA_HIP_CHECK(ctx, launch_me_guess(a, s));
+            if (ctx->opts.start == SEA_START_SPECTRAL)
+                SEA_HIP_CHECK(ctx, launch_me_shell(a, nz_max, s));
+            else
+                SEA_HIP_CHECK(ctx, launch_me_guess(a, s));
             if (ctx->opts.start == SEA_START_LEARNED) {
                 float* x32 = (float*)(base + Ly.nnx);
                 float* y32 = (float*)(base + Ly.nny);

@@ -57,9 +57,8 @@ struct StageTimer {
 
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
-    size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, gbuf, slots, stats, csr_off, csr_ent, scal, counter;
+    size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, slots, stats, csr_off, csr_ent, scal, counter;
     size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, total;
-    size_t gstride;
     int nmax;
     int n_chunks;
     int n_slots;
@@ -112,10 +111,41 @@ struct ExxArgs {
     int start_res;        // FP32 z-march: bres already holds b - A x in FP64 (x kept as the FP64 start)
     double* rnorm;        // n_pairs x RZ_TILES x 2: |b|^2, |b - A x|^2 per row tile of the FP64 residual z-march (nullable)
     double* bres;         // n_pairs x stride: b - A x0 when x_nonzero
-    double* gbuf;         // ghost-layer multipole values, n_pairs x gstride
-    size_t gstride;       // 36 x nmax^2
     int nmax;             // largest domain extent over pairs and axes
 };
+
+// (x, y, z) of a linear index over an nx x ny box (x fastest), advanced by a
+// fixed stride with carries instead of integer divisions.
+struct BoxWalk {
+    int x, y, z, sx, sy, nx, ny;
+    __device__ BoxWalk(int id, int stride, int nx_, int ny_) : nx(nx_), ny(ny_) {
+        x = id % nx;
+        const int r = id / nx;
+        y = r % ny;
+        z = r / ny;
+        sx = stride % nx;
+        sy = stride / nx;
+    }
+    __device__ __forceinline__ void next() {
+        x += sx;
+        y += sy;
+        if (x >= nx) {
+            x -= nx;
+            ++y;
+        }
+        while (y >= ny) {
+            y -= ny;
+            ++z;
+        }
+    }
+};
+
+// m mod N for m a few cells away from [0, N), without a division
+__device__ __forceinline__ int wrap_near(int m, int N) {
+    while (m < 0) m += N;
+    while (m >= N) m -= N;
+    return m;
+}
 
 // Kernel launchers (k_exx.hip).  All enqueue on `s`.
 int exx_n_chunks(long n_int_max);
@@ -124,6 +154,8 @@ hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s)
 hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s);
 hipError_t launch_cg(const ExxArgs& a, hipStream_t s);
 hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s);
+// the multipole start on the 6-point shell inside the faces, zero inside
+hipError_t launch_me_shell(const ExxArgs& a, int nz_max, hipStream_t s);
 hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s);
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s);
 hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
