@@ -9,11 +9,15 @@ ACE build (M = dV Phi^T W, Cholesky, xi = W L^-T), K applied to 256 trial
 vectors and the Eq. 19 energy.  Inputs are synthetic (seeded generator) and
 resident in HBM before the timed region.  Prints one JSON line.
 
-Forms of the V_xx action (CG state precision / start):
+Forms of the V_xx action (CG state precision / start), all timed; the
+step and `value` use the spectral form unless --form says otherwise:
   plain-f64      FP64 state, zero start
   plain-f32      FP32 state + FP64 reliable updates, zero start
   multipole-f32  FP32 state, regularized multipole start
   learned-f32    FP32 state, learned start (trained network checkpoint)
+  spectral-f32   FP32 state, multipole start on the face shell plus the
+                 sine-transform correction (the CG then checks, and if
+                 needed finishes, the same 1e-8 true residual)
 """
 from __future__ import annotations
 
@@ -85,18 +89,20 @@ FORMS = {
 }
 
 
-CG_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_cg_zm_buf_xc_learned_c2.md")
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+CG_PROFILE = os.path.join(PROFILES, "k_cg_zm_buf_xc_learned_c2.md")
+DST_PROFILE = os.path.join(PROFILES, "k_dst_mfma_spectral_c2.md")
 
 
-def measured_traffic(variant, form, iters_total):
-    """HBM bytes per launch of the CG kernel from the committed FETCH_SIZE /
-    WRITE_SIZE counter runs (calibrated against a plain copy), or None unless
-    those runs were taken on this kernel source, variant, start and CG
-    iteration count."""
-    if not os.path.exists(CG_PROFILE):
+def measured_traffic(path, **match):
+    """HBM bytes per launch of a kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (calibrated against a plain copy) summarized in
+    `path`, or None unless those runs were taken on this kernel source and
+    on the same workload (every `match` key equal to the recorded one)."""
+    if not os.path.exists(path):
         return None
     rec = None
-    with open(CG_PROFILE) as f:
+    with open(path) as f:
         for line in f:
             if line.startswith("traffic_json: "):
                 rec = json.loads(line[len("traffic_json: "):])
@@ -107,8 +113,7 @@ def measured_traffic(variant, form, iters_total):
     for name in rec["source_files"]:
         with open(os.path.join(root, name), "rb") as f:
             h.update(f.read())
-    if (h.hexdigest() != rec["source_sha256"] or rec["cg_variant"] != variant or rec["form"] != form
-            or rec["cg_iters_total"] != iters_total):
+    if h.hexdigest() != rec["source_sha256"] or any(rec.get(k) != v for k, v in match.items()):
         return None
     return rec["bytes_per_launch"]
 
@@ -120,10 +125,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2000)
     ap.add_argument("--form", default=None, choices=list(FORMS),
-                    help="timed form (default: learned-f32 when a checkpoint exists, else plain-f32)")
+                    help="timed form (default: spectral-f32, the fastest; every other form is timed too)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
-    ap.add_argument("--other-forms", action="store_true", help="also time one V_xx action of every other form")
+    ap.add_argument("--no-other-forms", action="store_true", help="skip timing one V_xx action of every other form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eps-rule", action="store_true", help="skip the eps-driven-domain context measurement")
     ap.add_argument("--no-scdm", action="store_true", help="skip the SCDM chain measurement")
@@ -144,7 +149,7 @@ def main():
     from paper_2208_06097_amd import sea, synth
 
     have_w = os.path.exists(args.weights)
-    form = args.form or ("learned-f32" if have_w else "plain-f32")
+    form = args.form or "spectral-f32"
     if FORMS[form]["start"] == "learned" and not have_w:
         print(f"no network checkpoint at {args.weights}", file=sys.stderr)
         sys.exit(2)
@@ -245,10 +250,26 @@ def main():
     stages = {k: v / args.steps for k, v in stage_acc.items()}
     vxx_ms = float(np.median(vxx_steps))   # median over the timed steps (HIP events per stage)
     wbytes = 4.0 if FORMS[form]["stencil"] == "f32" else 8.0
-    cg_bytes = float(np.sum(stats["iters"].astype(np.float64) * 6.0
-                            * np.prod(pairs["n"].astype(np.float64), axis=1) * wbytes))
-    achieved = cg_bytes / (stages["cg"] * 1e-3) / 1e9
-    kname = "k_cg_zm<float>" if FORMS[form]["stencil"] == "f32" else "k_cg_f64"
+    npts = np.prod(pairs["n"].astype(np.float64), axis=1)
+    if FORMS[form]["start"] == "spectral":
+        # dominant kernel: the sine-transform pass (six launches per action);
+        # per launch every transformable pair's array is read and written once
+        # in FP64, 2 x axis length flops per point
+        tf = np.all(pairs["n"] <= 64, axis=1)
+        roof = {"kernel": "k_dst_mfma", "launches_per_action": 6,
+                "launch_ms": stages["dst"] / 6.0,
+                "bytes": float(np.sum(npts[tf]) * 16.0),
+                "flops": float(np.sum(npts[tf] * 2.0 * pairs["n"][tf].mean(axis=1))),
+                "per_unit": "16 B (one FP64 read and write) and 2 n_axis flops per pair-domain point per pass",
+                "traffic": measured_traffic(DST_PROFILE, form=form, n_pairs=n_pairs)}
+    else:
+        roof = {"kernel": "k_cg_zm<float>" if FORMS[form]["stencil"] == "f32" else "k_cg_f64",
+                "launches_per_action": 1, "launch_ms": stages["cg"],
+                "bytes": float(np.sum(stats["iters"].astype(np.float64) * 6.0 * npts * wbytes)), "flops": None,
+                "per_unit": f"6 words x {int(wbytes)} B per interior point per CG iteration",
+                "traffic": measured_traffic(CG_PROFILE, cg_variant=tune["variant"] if tune else None, form=form,
+                                            cg_iters_total=int(stats["iters"].sum()))}
+    achieved = roof["bytes"] / (roof["launch_ms"] * 1e-3) / 1e9 if roof["launch_ms"] > 0 else 0.0
     forms = {form: {"vxx_ms_per_call": vxx_ms, "cg_ms": stages["cg"], "guess_ms": stages["guess"],
                     "cg_iters_mean": float(stats["iters"].mean()), "E_xx": E, "E_ace": E_ace,
                     "dE_vs_oracle": (E - golden["E"]) if golden else None,
@@ -275,7 +296,7 @@ def main():
         log(f"ace {name}: E {E_t:.9f}  |dKpsi|/|Kpsi| {kerr:.2e}  ms {ace[name]['ms']}")
         del xi_t, K_t, psi_t
         ca.close()
-    if args.other_forms:
+    if not args.no_other_forms:
         for fname in FORMS:
             if fname == form or (FORMS[fname]["start"] == "learned" and not have_w):
                 continue
@@ -413,13 +434,16 @@ def main():
         "ace_precision": ace,
         "eps_rule": eps_rule,
         "sea_chain": sea_chain,
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": roof["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(tune["variant"] if tune else None, form,
-                                                 int(stats["iters"].sum())),
+                     "launch_ms": roof["launch_ms"], "launches_per_action": roof["launches_per_action"],
+                     "fp64_tflops": (roof["flops"] / (roof["launch_ms"] * 1e-3) / 1e12
+                                     if roof["flops"] and roof["launch_ms"] > 0 else None),
+                     "fp64_peak_tflops": 78.6,
+                     "traffic": roof["traffic"],
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "algorithmic_bytes_per_launch": cg_bytes,
-                     "per_unit": f"6 words x {int(wbytes)} B per interior point per CG iteration"},
+                     "algorithmic_bytes_per_launch": roof["bytes"],
+                     "per_unit": roof["per_unit"]},
     }
     if rank == 0 and not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

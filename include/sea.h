@@ -118,7 +118,9 @@ typedef enum {
     SEA_STAGE_FINISH = 10,  /* FP32 state: true FP64 residual and e_ij per pair */
     SEA_STAGE_SCDM = 11,    /* SCDM pivoted QR, P_CC^{-1/2} and U              */
     SEA_STAGE_ROTATE = 12,  /* orbital rotation by U or U^{-1}                 */
-    SEA_STAGE_COUNT = 13
+    SEA_STAGE_DST = 13,     /* spectral start: the six sine-transform passes   */
+                            /* (inside the GUESS stage)                        */
+    SEA_STAGE_COUNT = 14
 } sea_stage;
 
 /* Per-pair diagnostics (Eq. 8 and Eq. 17 quantities on the pair domain). */

@@ -15,8 +15,8 @@
 //
 // The transform along one axis is a dense product with the symmetric,
 // orthogonal matrix S_n[j][k] = sqrt(2/(n+1)) sin(pi (j+1)(k+1)/(n+1))
-// (n <= 64 here, so a 64 x 64 product beats an FFT of this length on this
-// part).  Each pass transforms the slowest axis of a pair's array (a, b, c)
+// (n <= 64 here, so a 64 x 64 product on the matrix cores beats an FFT of
+// this length on this part).  Each pass transforms the slowest axis of a pair's array (a, b, c)
 // and writes (b, c, a'): the axes rotate, so three passes transform z, y,
 // x and restore the layout.  Forward passes end with the division by
 // lambda, inverse passes (the same matrices: S is its own inverse) with
@@ -70,19 +70,26 @@ struct DstArgs {
 };
 
 // grid (pairs, DS_TG): workgroup y takes column tiles y, y + DS_TG, ... of
-// its pair, with S_A staged once.  Staging loads are issued together
-// (registers first, then LDS) so their latencies overlap.
+// its pair, with S_A staged once; the next tile's input is loaded into
+// registers while the current one is multiplied.
 constexpr int DS_TG = 16;
-constexpr int DS_LD = (DS_N * DS_N) / DS_BS;   // staging loads per thread (16)
 
-__global__ __launch_bounds__(DS_BS) void k_dst_pass(DstArgs d) {
-    __shared__ double sS[DS_N * DS_N];
-    __shared__ double tin[DS_N * DS_TC];
+// One pass on the FP64 matrix cores (v_mfma_f64_16x16x4f64): A = S
+// (j x k, read as S[k][j], S being symmetric), B = the tile (k x columns),
+// the axis zero-padded to 64.  Wave w owns output rows j = 16 w .. 16 w + 15
+// and the tile's four 16-column blocks.  Operand lanes: row/column = lane %
+// 16, k = lane / 16; result item v of a lane is row lane / 16 + 4 v, column
+// lane % 16.
+typedef double dst_f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_dst_mfma(DstArgs d) {
+    __shared__ double sS[DS_N * DS_N];    // sS[k * 64 + j] = S[k][j]
+    __shared__ double tin[DS_N * DS_TC];  // tin[k * 64 + c]
+    constexpr int BS = 256, LD = DS_N * DS_N / BS;
     const int pid = blockIdx.x;
     const sea_pair P = d.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     if (nx > DS_N || ny > DS_N || nz > DS_N) return;   // keeps the multipole start
-    // shape (A, B, C) of this pass's input, A transformed
     int A, B, C;
     if (d.pass == 0) { A = nz; B = ny; C = nx; }
     else if (d.pass == 1) { A = ny; B = nx; C = nz; }
@@ -93,72 +100,63 @@ __global__ __launch_bounds__(DS_BS) void k_dst_pass(DstArgs d) {
     double* out = d.out + (size_t)pid * d.stride;
     {
         const double* Sa = d.S + tab_off(A);
-        double t[DS_LD];
+        double t[LD];
 #pragma unroll
-        for (int u = 0; u < DS_LD; ++u) {
-            const int q = threadIdx.x + u * DS_BS;
-            t[u] = q < A * A ? Sa[q] : 0.0;
+        for (int u = 0; u < LD; ++u) {
+            const int q = threadIdx.x + u * BS, k = q / DS_N, j = q % DS_N;
+            t[u] = (k < A && j < A) ? Sa[k * A + j] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < DS_LD; ++u) {
-            const int q = threadIdx.x + u * DS_BS;
-            if (q < A * A) sS[(q / A) * DS_N + q % A] = t[u];
-        }
+        for (int u = 0; u < LD; ++u) sS[threadIdx.x + u * BS] = t[u];
     }
     const DevCell& Cl = d.cells[d.pair_cell[pid]];
-    // thread: outputs j = jb + 16 u, columns cb + 16 v (u, v < 4)
-    const int jb = threadIdx.x & 15, cb = threadIdx.x >> 4;
-    // the next tile's input is loaded into registers while this one computes
-    double nxt[DS_LD];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    double nxt[LD];
     auto load_tile = [&](int c0) {
 #pragma unroll
-        for (int u = 0; u < DS_LD; ++u) {
-            const int q = threadIdx.x + u * DS_BS, a = q / DS_TC, c = q % DS_TC;
+        for (int u = 0; u < LD; ++u) {
+            const int q = threadIdx.x + u * BS, a = q / DS_TC, c = q % DS_TC;
             nxt[u] = (a < A && c0 + c < ncol) ? in[(size_t)a * ncol + c0 + c] : 0.0;
         }
     };
     load_tile(blockIdx.y * DS_TC);
     for (int col0 = blockIdx.y * DS_TC; col0 < ncol; col0 += DS_TG * DS_TC) {
-        __syncthreads();   // the previous tile's products are done with tin
+        __syncthreads();
 #pragma unroll
-        for (int u = 0; u < DS_LD; ++u) tin[threadIdx.x + u * DS_BS] = nxt[u];
+        for (int u = 0; u < LD; ++u) tin[threadIdx.x + u * BS] = nxt[u];
         __syncthreads();
         if (col0 + DS_TG * DS_TC < ncol) load_tile(col0 + DS_TG * DS_TC);
-        double acc[4][4] = {};
-#pragma unroll 4
-        for (int k = 0; k < A; ++k) {
-            double sv[4], xv[4];
+        dst_f64x4 acc[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) sv[u] = sS[k * DS_N + jb + 16 * u];   // S[k][j] = S[j][k]
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = dst_f64x4{0.0, 0.0, 0.0, 0.0};
+        const int kend = (A + 3) & ~3;
+        for (int k0 = 0; k0 < kend; k0 += 4) {
+            const double av = sS[(k0 + g) * DS_N + 16 * w + r];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) xv[v] = tin[k * DS_TC + cb + 16 * v];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += sv[u] * xv[v];
+            for (int ct = 0; ct < 4; ++ct) {
+                const double bv = tin[(k0 + g) * DS_TC + 16 * ct + r];
+                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+            }
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int col = col0 + cb + 16 * v;
+        for (int ct = 0; ct < 4; ++ct) {
+            const int col = col0 + 16 * ct + r;
             if (col >= ncol) continue;
+            double lam_col = 0.0;
+            if (d.mode == 1) {
+                const int zz = col / C, yy = col % C;
+                lam_col = d.mu[mu_off(nz) + zz] / (Cl.h[2] * Cl.h[2]) + d.mu[mu_off(ny) + yy] / (Cl.h[1] * Cl.h[1]);
+            }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = jb + 16 * u;
+            for (int v = 0; v < 4; ++v) {
+                const int j = 16 * w + g + 4 * v;
                 if (j >= A) continue;
-                const double val = acc[u][v];
+                const double val = acc[ct][v];
                 const size_t o = (size_t)col * A + j;
-                if (d.mode == 1) {
-                    // output (z, y, x) after the third forward pass: col = z * ny + y, j = x
-                    const int zz = col / C, yy = col % C;
-                    const double lam = d.mu[mu_off(nz) + zz] / (Cl.h[2] * Cl.h[2]) +
-                                       d.mu[mu_off(ny) + yy] / (Cl.h[1] * Cl.h[1]) +
-                                       d.mu[mu_off(nx) + j] / (Cl.h[0] * Cl.h[0]);
-                    out[o] = val / lam;
-                } else if (d.mode == 2) {
-                    out[o] += val;
-                } else {
-                    out[o] = val;
-                }
+                if (d.mode == 1) out[o] = val / (lam_col + d.mu[mu_off(nx) + j] / (Cl.h[0] * Cl.h[0]));
+                else if (d.mode == 2) out[o] += val;
+                else out[o] = val;
             }
         }
     }
@@ -172,7 +170,7 @@ size_t dst_mu_doubles() { return (size_t)mu_off(DS_N + 1); }
 // x += S^-1 ((S r) ./ lambda) for every pair whose axes are all <= 64:
 // r (n_pairs x stride) is overwritten, tmp is scratch of the same size.
 hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, double* tmp, double* tab, double* mu,
-                                 hipStream_t s) {
+                                 hipStream_t s, const std::function<void(bool)>& mark) {
     if (a.n_pairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_dst_tables, dim3(DS_N), dim3(DS_BS), 0, s, tab, mu);
     DstArgs d{};
@@ -187,12 +185,14 @@ hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, doub
     // forward: r -> tmp -> r -> tmp (divided by lambda); inverse: tmp -> r -> tmp -> x (added)
     const double* ins[6] = {r, tmp, r, tmp, r, tmp};
     double* outs[6] = {tmp, r, tmp, r, tmp, a.v};
+    mark(true);
     for (int q = 0; q < 6; ++q) {
         d.in = ins[q];
         d.out = outs[q];
         d.pass = q % 3;
         d.mode = q == 2 ? 1 : (q == 5 ? 2 : 0);
-        hipLaunchKernelGGL(k_dst_pass, grid, dim3(DS_BS), 0, s, d);
+        hipLaunchKernelGGL(k_dst_mfma, grid, dim3(256), 0, s, d);
     }
+    mark(false);
     return hipGetLastError();
 }

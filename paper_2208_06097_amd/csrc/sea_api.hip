@@ -510,6 +510,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
     };
     for (int k = SEA_STAGE_GATHER; k <= SEA_STAGE_ENERGY; ++k) ctx->ev_used[k] = false;
     ctx->ev_used[SEA_STAGE_FINISH] = false;
+    ctx->ev_used[SEA_STAGE_DST] = false;
     const bool zm = ctx->opts.stencil_dtype == SEA_F32 && S.cubic && cg_zm_fits(S.pairs.data(), n_pairs, nullptr) &&
                     cg_zm_lds_bytes(1) <= ctx->max_lds;
     if (!zm && ctx->opts.stencil_dtype != SEA_F64)
@@ -568,7 +569,11 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                 auto residual = [&]() { return rzm ? launch_residual_zm(ar, s) : launch_start_residual(a, s); };
                 SEA_HIP_CHECK(ctx, residual());
                 SEA_HIP_CHECK(ctx, launch_spectral_start(a, ncol_max, a.bres, (double*)(base + Ly.dst_tmp),
-                                                         (double*)(base + Ly.dst_tab), (double*)(base + Ly.dst_mu), s));
+                                                         (double*)(base + Ly.dst_tab), (double*)(base + Ly.dst_mu), s,
+                                                         [&](bool begin) {
+                                                             if (begin) timer_on(SEA_STAGE_DST);
+                                                             else timer_off(SEA_STAGE_DST);
+                                                         }));
                 SEA_HIP_CHECK(ctx, residual());
             } else if (!zm) {
                 SEA_HIP_CHECK(ctx, launch_start_residual(a, s));

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -168,8 +169,9 @@ hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s);
 // tmp scratch of the same size); ncol_max = largest product of two axes.
 size_t dst_table_doubles();
 size_t dst_mu_doubles();
+// `mark(true)` / `mark(false)` bracket the six transform passes (stage timing).
 hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, double* tmp, double* tab, double* mu,
-                                 hipStream_t s);
+                                 hipStream_t s, const std::function<void(bool)>& mark);
 // z-marching CG (k_cg.hip): needs every pair with n[0], n[1] <= 64.
 bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h);
 size_t cg_zm_lds_bytes(int state_f32);

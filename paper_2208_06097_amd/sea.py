@@ -89,7 +89,7 @@ class SeaCell(C.Structure):
 
 
 STAGES = ["gather", "boundary", "guess", "cg", "scatter", "energy", "ace_m", "ace_chol", "ace_xi",
-          "ace_apply", "finish", "scdm", "rotate"]
+          "ace_apply", "finish", "scdm", "rotate", "dst"]
 
 
 class SeaError(RuntimeError):

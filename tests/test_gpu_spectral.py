@@ -126,3 +126,24 @@ def test_spectral_plan_replays_match_eager():
         torch.cuda.synchronize()
     plan.close()
     ctx.close()
+
+
+def test_spectral_batched_equals_per_cell():
+    """Two cells in one batched call give the per-cell results bit for bit."""
+    cells = [synth.config1(), synth.mini(seed=8)]
+    batch = []
+    for c in cells:
+        hw = 6.0 if c.N == 60 else 4.0
+        batch.append((torch.from_numpy(c.phi.astype(np.float32)).cuda(), c.N, c.L,
+                      sea.build_pairs(c.N, c.L, c.centres, 6.0, hw)))
+    ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F64, start=sea.SEA_START_SPECTRAL)
+    Ws, Es, stats, st = ctx.exx_action_batched(batch)
+    assert st == sea.SEA_OK
+    off = 0
+    for (phi, N, L, pairs), W, E in zip(batch, Ws, Es):
+        W1, E1, s1, st1 = ctx.exx_action(phi, N, L, pairs)
+        assert st1 == sea.SEA_OK and E1 == E
+        assert torch.equal(W1, W)
+        assert np.array_equal(s1, stats[off:off + len(pairs)])
+        off += len(pairs)
+    ctx.close()
