@@ -196,12 +196,21 @@ def main():
     W = torch.empty_like(phi)
     exx_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     log(f"form {form}; pairs: {n_pairs}; workspace {ws.numel() / 2**30:.2f} GiB")
-    tune = None
-    if FORMS[form]["stencil"] == "f32" and args.cg_variant:
-        ctx.set_opts(cg_variant=ctx.cg_variants().index(args.cg_variant))
-        tune = {"variant": args.cg_variant, "ms": None}
-    elif FORMS[form]["stencil"] == "f32" and FORMS[form]["start"] != "spectral":
-        tune = ctx.autotune([(phi, cell.N, cell.L, pairs)], sample_pairs=args.tune_pairs, iters=20, ws=ws)
+    def pick_variant(c, fname, cells, wsp):
+        """FP32 CG kernel variant: the --cg-variant one, else the autotuner's
+        (not run for the spectral start, whose solves need no iterations,
+        which leaves the default variant)."""
+        if FORMS[fname]["stencil"] != "f32":
+            return None
+        if args.cg_variant:
+            c.set_opts(cg_variant=c.cg_variants().index(args.cg_variant))
+            return {"variant": args.cg_variant, "ms": None}
+        if FORMS[fname]["start"] == "spectral":
+            return {"variant": c.cg_variants()[0], "ms": None}
+        return c.autotune(cells, sample_pairs=args.tune_pairs, iters=20, ws=wsp)
+
+    tune = pick_variant(ctx, form, [(phi, cell.N, cell.L, pairs)], ws)
+    if tune and tune["ms"]:
         log(f"autotune: {tune['variant']}  " + "  ".join(f"{k} {v:.1f} ms" for k, v in tune["ms"].items()))
 
     def step(host=False):
@@ -302,8 +311,7 @@ def main():
                 continue
             c2 = make_ctx(fname)
             ws2 = c2.workspace(c2.exx_workspace_bytes(cell.N, cell.L, cell.n_occ, pairs))
-            if FORMS[fname]["stencil"] == "f32":
-                c2.autotune([(phi, cell.N, cell.L, pairs)], sample_pairs=args.tune_pairs, iters=20, ws=ws2)
+            pick_variant(c2, fname, [(phi, cell.N, cell.L, pairs)], ws2)
             r2 = c2.exx_action(phi, cell.N, cell.L, pairs, ws=ws2, W=W, exx_dev=exx_dev, want_host=True)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -318,20 +326,17 @@ def main():
             c2.close()
     # the paper's own truncation (eps-driven boxes, Eq. 16-17) on the same cell, for
     # context: eps = 10^-3.5 (the paper's production setting), delta = eps, boxes
-    # grown by 6 points, FP32 state, multipole start
+    # grown by 6 points, the timed form's state and start
     eps_rule = None
     if not args.no_eps_rule:
-        ce = make_ctx("multipole-f32")
+        ce = make_ctx(form)
         eps = 10 ** -3.5
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         pe, _, dbe = ce.build_pairs_eps(phi, cell.N, cell.L, eps, eps, pad=6, with_dbox=True)
         t_pairs = 1000 * (time.perf_counter() - t1)
         wse = ce.workspace(ce.exx_batched_workspace_bytes([(phi, cell.N, cell.L, pe, W, exx_dev, dbe)]))
-        if args.cg_variant:
-            ce.set_opts(cg_variant=ce.cg_variants().index(args.cg_variant))
-        else:
-            ce.autotune([(phi, cell.N, cell.L, pe)], sample_pairs=args.tune_pairs, iters=20, ws=wse)
+        pick_variant(ce, form, [(phi, cell.N, cell.L, pe)], wse)
         re_ = ce.exx_action(phi, cell.N, cell.L, pe, ws=wse, W=W, exx_dev=exx_dev, want_host=True, dbox=dbe)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -341,7 +346,7 @@ def main():
         _, _, xi_e, _ = ctx.ace_build(phi, W, dV, ws=ws_ace)
         E_ace_eps = ctx.ace_energy(phi, xi_e, dV, ws=ws_ace)
         del xi_e
-        eps_rule = {"eps": eps, "delta": eps, "pad": 6, "form": "multipole-f32", "n_pairs": int(len(pe)),
+        eps_rule = {"eps": eps, "delta": eps, "pad": 6, "form": form, "n_pairs": int(len(pe)),
                     "mean_box_points": float(np.prod(pe["n"].astype(np.float64), axis=1).mean()),
                     "pair_build_ms": t_pairs, "vxx_ms_per_call": 1000 * (time.perf_counter() - t1),
                     "cg_ms": se["cg"], "cg_iters_mean": float(re_[2]["iters"].mean()), "E_xx": re_[1],
@@ -356,7 +361,7 @@ def main():
     # pairs of the SCDM orbitals, exx, back-rotation of W (Eq. 15), ACE
     sea_chain = None
     if not args.no_scdm:
-        cs = make_ctx("multipole-f32")
+        cs = make_ctx(form)
         n = cell.n_occ
         G = torch.from_numpy(synth.random_rotation(n, args.seed + 7)).cuda()
         phid = (G.T @ phi.view(n, -1)).view_as(phi).contiguous()
@@ -374,10 +379,7 @@ def main():
         pl_, _, dbl = cs.build_pairs_eps(loc, cell.N, cell.L, eps, eps, pad=6, with_dbox=True)
         t_pairs = 1000 * (time.perf_counter() - t1)
         wsl = cs.workspace(cs.exx_batched_workspace_bytes([(loc, cell.N, cell.L, pl_, W, exx_dev, dbl)]))
-        if args.cg_variant:
-            cs.set_opts(cg_variant=cs.cg_variants().index(args.cg_variant))
-        else:
-            cs.autotune([(loc, cell.N, cell.L, pl_)], sample_pairs=args.tune_pairs, iters=20, ws=wsl)
+        pick_variant(cs, form, [(loc, cell.N, cell.L, pl_)], wsl)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         rl = cs.exx_action(loc, cell.N, cell.L, pl_, ws=wsl, W=W, exx_dev=exx_dev, want_host=True, dbox=dbl)
