@@ -35,7 +35,7 @@ def main():
     ap.add_argument("--cells", type=int, default=200)
     ap.add_argument("--first", type=int, default=0, help="index of the first cell of the recipe")
     ap.add_argument("--group", type=int, default=4, help="cells per plan (memory: about 25 GB per cell)")
-    ap.add_argument("--start", default="multipole", choices=["zero", "multipole", "learned"])
+    ap.add_argument("--start", default="multipole", choices=["zero", "multipole", "learned", "spectral"])
     ap.add_argument("--weights", default=None, help="network checkpoint for the learned start")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--replays", type=int, default=1, help="timed graph replays per group")
@@ -44,7 +44,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     start = {"zero": sea.SEA_START_ZERO, "multipole": sea.SEA_START_MULTIPOLE,
-             "learned": sea.SEA_START_LEARNED}[args.start]
+             "learned": sea.SEA_START_LEARNED, "spectral": sea.SEA_START_SPECTRAL}[args.start]
     ctx = sea.Context(rel_tol=args.tol, stencil_dtype=sea.SEA_F32, start=start)
     if start == sea.SEA_START_LEARNED:
         import os

@@ -1,5 +1,5 @@
 """The 256-molecule cell (1024 orbitals, L = 37.3 bohr, 190^3 grid): V_xx action
-from the zero, multipole and learned starts, same 1e-8 true residual.
+from the zero, multipole, learned and spectral starts, same 1e-8 true residual.
 
 Orbitals are assembled on the device (FP32, 28 GB), W is FP64 (56 GB), the
 exx workspace is shared by the three forms.  Reports, per form, the V_xx
@@ -45,9 +45,9 @@ def main():
     log(f"inputs: {cell.n_occ} orbitals on {cell.N}^3, {len(pairs)} pairs, {time.perf_counter() - t0:.1f} s")
     W = torch.empty((cell.n_occ,) + (cell.N,) * 3, dtype=torch.float64, device="cuda")
     forms = {"zero-f32": sea.SEA_START_ZERO, "multipole-f32": sea.SEA_START_MULTIPOLE,
-             "learned-f32": sea.SEA_START_LEARNED}
+             "learned-f32": sea.SEA_START_LEARNED, "spectral-f32": sea.SEA_START_SPECTRAL}
     ws, variant, out = None, None, {}
-    for name in ("learned-f32", "multipole-f32", "zero-f32"):   # largest workspace first
+    for name in ("spectral-f32", "learned-f32", "multipole-f32", "zero-f32"):   # largest workspace first
         ctx = sea.Context(rel_tol=args.tol, stencil_dtype=sea.SEA_F32, start=forms[name], profile=True)
         if name == "learned-f32":
             st = ctx.nn_state(np.load(args.weights))
@@ -77,6 +77,7 @@ def main():
            "seed": args.seed, "n_pairs": len(pairs), "rel_tol": args.tol, "cg_variant": variant, "forms": out,
            "learned_vs_zero": {"iters_saved_frac": 1 - l["iters_mean"] / z["iters_mean"],
                                "time_saved_frac": 1 - l["vxx_ms"] / z["vxx_ms"]},
+           "spectral_vs_zero": {"time_saved_frac": 1 - out["spectral-f32"]["vxx_ms"] / z["vxx_ms"]},
            "max_dE_between_forms": float(max(v["E_xx"] for v in out.values()) - min(v["E_xx"] for v in out.values()))}
     line = json.dumps(res)
     if args.out:
