@@ -601,24 +601,33 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
             const float* phj32 = nullptr;
             if (C.phi_f32) phj32 = (const float*)C.phi + (size_t)en.y * C.Ng + gcol;
             else phj = (const double*)C.phi + (size_t)en.y * C.Ng + gcol;
+            // all loads of the column's points first (independent, in flight
+            // together), then the multipole values of points outside the domain
+            double vv[SC_TZ], pv[SC_TZ];
+            int lzs[SC_TZ];
+            bool me[SC_TZ];
 #pragma unroll
             for (int k = 0; k < SC_TZ; ++k) {
                 const int gz = tz0 + k;
                 int lz = lz0 + k;
                 lz -= (lz >= C.N[2]) ? C.N[2] : 0;
-                if (gz >= C.N[2] || lz >= D[5]) continue;
+                lzs[k] = lz;
+                const bool valid = gz < C.N[2] && lz < D[5];
                 const int sz = D[2] + lz - P.lo[2];
-                const size_t go = (size_t)gz * C.N[1] * C.N[0];
-                const double ph = C.phi_f32 ? (double)phj32[go] : phj[go];
-                double val;
-                if (in_xy && sz >= 0 && sz < P.n[2])
-                    val = v[((size_t)sz * P.n[1] + sy) * P.n[0] + sx];
-                else
-                    val = racah_me_potential<LM>(Q, a.lmax, (D[0] + lx) * C.h[0] - P.origin[0],
-                                                 (D[1] + ly) * C.h[1] - P.origin[1],
-                                                 (D[2] + lz) * C.h[2] - P.origin[2]);
-                acc[k] += val * ph;
+                const bool inside = valid && in_xy && sz >= 0 && sz < P.n[2];
+                me[k] = valid && !inside;
+                const size_t go = (size_t)(valid ? gz : 0) * C.N[1] * C.N[0];
+                pv[k] = valid ? (C.phi_f32 ? (double)phj32[go] : phj[go]) : 0.0;
+                vv[k] = inside ? v[((size_t)sz * P.n[1] + sy) * P.n[0] + sx] : 0.0;
             }
+#pragma unroll
+            for (int k = 0; k < SC_TZ; ++k)
+                if (me[k])
+                    vv[k] = racah_me_potential<LM>(Q, a.lmax, (D[0] + lx) * C.h[0] - P.origin[0],
+                                                   (D[1] + ly) * C.h[1] - P.origin[1],
+                                                   (D[2] + lzs[k]) * C.h[2] - P.origin[2]);
+#pragma unroll
+            for (int k = 0; k < SC_TZ; ++k) acc[k] += vv[k] * pv[k];
         }
         // general path: boxes wider than the cell (a grid point met several times)
 #pragma unroll
