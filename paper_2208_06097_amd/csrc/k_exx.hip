@@ -47,67 +47,232 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 }
 
 // ---------------------------------------------------------------------------
-// 1. gather rho_ij, write b = 4 pi rho, partial Racah moments per chunk
+// 1. gather rho_ij, write b = 4 pi rho, and the multipole moments (Eq. 11).
+//
+// The Racah solid harmonics are homogeneous polynomials of degree l in the
+// displacement (dx, dy, dz) from the pair origin, so the moments Q_lm =
+// dV sum rho R_lm are fixed linear combinations of the 84 Cartesian moments
+// M_abc = sum rho dx^a dy^b dz^c (a + b + c <= 6).  Those separate: a
+// workgroup takes 16 planes of a pair, a thread one x column position; per
+// (y, column) it sums rho dz^c over the planes (7 products), folds them
+// into sum rho dy^b dz^c (28 values) per row, and at the end the x powers
+// make M_abc, summed over the lanes.  The polynomial coefficients of R_lm
+// come from the same recurrence the kernels evaluate (k_racah_poly).
 
 constexpr int GM_BS = 256;
 constexpr int GM_CHUNK = 4096;
+constexpr int GC_NM = 84;   // monomials of degree <= 6
+static_assert(GC_NM + 2 <= GC_N, "chunk record too short");
 
-template <int LM>
-__global__ __launch_bounds__(GM_BS) void k_gather_moments(ExxArgs a) {
-    __shared__ double red[GM_BS / 64 + 1];
-    const int pid = blockIdx.x;
-    const int chunk = blockIdx.y;
-    const DevCell& C = a.cells[a.pair_cell[pid]];
-    const sea_pair P = a.pairs[pid];
-    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    const long n_int = (long)nx * ny * nz;
-    const long beg = (long)chunk * GM_CHUNK;
-    double acc[SEA_NACC];
-#pragma unroll
-    for (int k = 0; k < SEA_NACC; ++k) acc[k] = 0.0;
-    if (beg < n_int) {
-        const long end = min(beg + GM_CHUNK, n_int);
-        const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
-        double* b = a.b + (size_t)pid * a.stride;
-        BoxWalk wk((int)(beg + threadIdx.x), GM_BS, nx, ny);
-        for (long id = beg + threadIdx.x; id < end; id += GM_BS, wk.next()) {
-            const int x = wk.x, y = wk.y, z = wk.z;
-            const size_t g = ((size_t)wrap_near(P.lo[2] + z, C.N[2]) * C.N[1] + wrap_near(P.lo[1] + y, C.N[1])) * C.N[0]
-                             + wrap_near(P.lo[0] + x, C.N[0]);
-            const double rho = load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g);
-            b[id] = 4.0 * kPi * rho;
-            const double dx = (P.lo[0] + x) * C.h[0] - P.origin[0];
-            const double dy = (P.lo[1] + y) * C.h[1] - P.origin[1];
-            const double dz = (P.lo[2] + z) * C.h[2] - P.origin[2];
-            double R[(LM + 1) * (LM + 1)];
-            racah_solid<LM>(dx, dy, dz, R);
-#pragma unroll
-            for (int k = 0; k < (LM + 1) * (LM + 1); ++k) acc[k] += rho * R[k];
-            acc[SEA_NMOM] += fabs(rho);
-            acc[SEA_NMOM + 1] += rho;
-            acc[SEA_NMOM + 2] += fabs(rho) * (dx * dx + dy * dy + dz * dz);
+// position of x^a y^b z^c (a + b + c <= 6) in the order a, then b, then c
+__host__ __device__ constexpr int mono_idx(int a, int b, int c) {
+    int off = 0;
+    for (int a2 = 0; a2 < a; ++a2) off += (7 - a2) * (8 - a2) / 2;
+    for (int b2 = 0; b2 < b; ++b2) off += 7 - a - b2;
+    return off + c;
+}
+// position of y^b z^c (b + c <= 6)
+__host__ __device__ constexpr int bc_idx(int b, int c) { return mono_idx(0, b, c); }
+
+// tab[k * 84 + t]: coefficient of monomial t in the Racah harmonic k (one
+// workgroup; thread t owns monomial t through the recurrence of
+// racah_solid, with products by x, y, z and r^2 read as index shifts)
+__global__ __launch_bounds__(128) void k_racah_poly(double* __restrict__ tab) {
+    __shared__ double P[SEA_NMOM][GC_NM];
+    const int t = threadIdx.x;
+    int ta = 0, tb = 0, tc = 0;
+    for (int a = 0; a <= 6; ++a)
+        for (int b = 0; b <= 6 - a; ++b)
+            for (int c = 0; c <= 6 - a - b; ++c)
+                if (mono_idx(a, b, c) == t) {
+                    ta = a;
+                    tb = b;
+                    tc = c;
+                }
+    const bool live = t < GC_NM;
+    auto shx = [&](int k) { return (live && ta >= 1) ? P[k][mono_idx(ta - 1, tb, tc)] : 0.0; };
+    auto shy = [&](int k) { return (live && tb >= 1) ? P[k][mono_idx(ta, tb - 1, tc)] : 0.0; };
+    auto shz = [&](int k) { return (live && tc >= 1) ? P[k][mono_idx(ta, tb, tc - 1)] : 0.0; };
+    auto shr2 = [&](int k) {
+        double v = 0.0;
+        if (live && ta >= 2) v += P[k][mono_idx(ta - 2, tb, tc)];
+        if (live && tb >= 2) v += P[k][mono_idx(ta, tb - 2, tc)];
+        if (live && tc >= 2) v += P[k][mono_idx(ta, tb, tc - 2)];
+        return v;
+    };
+    if (live)
+        for (int k = 0; k < SEA_NMOM; ++k) P[k][t] = (k == 0 && t == 0) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int l = 0; l < 6; ++l) {
+        double nv[2 * 7 + 1];
+        const int cll = l * l + 2 * l, sll = l * l;
+        const double f = -sqrt((2.0 * l + 1.0) / (2.0 * l + 2.0));
+        nv[l + 1] = f * (shx(cll) - (l == 0 ? 0.0 : shy(sll)));          // C_{l+1,l+1}
+        nv[7 + l + 1] = f * (shy(cll) + (l == 0 ? 0.0 : shx(sll)));      // S_{l+1,l+1}
+        for (int m = 0; m <= l; ++m) {
+            const double den = 1.0 / sqrt((double)((l + m + 1) * (l - m + 1)));
+            const double aa = (2.0 * l + 1.0) * den;
+            const double bb = sqrt((double)((l + m) * (l - m))) * den;
+            const int base = l * l + l, basem = (l - 1) * (l - 1) + (l - 1);
+            double c = aa * shz(base + m), sv = (m > 0) ? aa * shz(base - m) : 0.0;
+            if (m <= l - 1) {
+                c -= bb * shr2(basem + m);
+                if (m > 0) sv -= bb * shr2(basem - m);
+            }
+            nv[m] = c;
+            nv[7 + m] = sv;
         }
+        __syncthreads();
+        const int base1 = (l + 1) * (l + 1) + (l + 1);
+        if (live) {
+            for (int m = 0; m <= l + 1; ++m) {
+                P[base1 + m][t] = nv[m];
+                if (m > 0) P[base1 - m][t] = nv[7 + m];
+            }
+        }
+        __syncthreads();
     }
-    double* out = a.partial + ((size_t)pid * a.n_chunks + chunk) * SEA_NACC;
-#pragma unroll
-    for (int k = 0; k < SEA_NACC; ++k) {
-        const double s = block_sum<GM_BS>(acc[k], red);
-        if (threadIdx.x == 0) out[k] = s;
-    }
+    if (live)
+        for (int k = 0; k < SEA_NMOM; ++k) tab[k * GC_NM + t] = P[k][t];
 }
 
-// 2. sum the chunk partials in chunk order; optional orthonormal copy
+// grid (pairs, plane chunks of GC_ZC); per chunk record of GC_N doubles:
+// M_abc (84), sum |rho|, sum |rho| r^2
+__global__ __launch_bounds__(GM_BS) void k_gather_cart(ExxArgs a) {
+    __shared__ double red[GM_BS / 64][4][64];
+    __shared__ double red2[GM_BS / 64][2][64];
+    __shared__ double tot[GC_N];
+    const int pid = blockIdx.x;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int z0 = blockIdx.y * GC_ZC;
+    if (z0 >= nz) return;
+    const int z1 = min(z0 + GC_ZC, nz);
+    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
+    double* b = a.b + (size_t)pid * a.stride;
+    const int lane = threadIdx.x & 63, yg = threadIdx.x >> 6;
+    constexpr int NG = GM_BS / 64;
+    for (int t = threadIdx.x; t < GC_N; t += GM_BS) tot[t] = 0.0;
+    __syncthreads();
+    for (int xb = 0; xb < nx; xb += 64) {
+        const int x = xb + lane;
+        const bool live = x < nx;
+        const size_t gx = (size_t)wrap_near(P.lo[0] + (live ? x : 0), C.N[0]);
+        const double dx = (P.lo[0] + x) * C.h[0] - P.origin[0];
+        double w[28];
+#pragma unroll
+        for (int q = 0; q < 28; ++q) w[q] = 0.0;
+        double s0 = 0.0, s2 = 0.0;
+        for (int y = yg; y < ny; y += NG) {
+            const size_t gy = (size_t)wrap_near(P.lo[1] + y, C.N[1]);
+            const double dy = (P.lo[1] + y) * C.h[1] - P.origin[1];
+            double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            double t0 = 0.0, t2 = 0.0;
+            for (int z = z0; z < z1; ++z) {
+                const size_t g = ((size_t)wrap_near(P.lo[2] + z, C.N[2]) * C.N[1] + gy) * C.N[0] + gx;
+                const double dz = (P.lo[2] + z) * C.h[2] - P.origin[2];
+                const double rho = live ? load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g) : 0.0;
+                if (live) b[((size_t)z * ny + y) * nx + x] = 4.0 * kPi * rho;
+                double p = rho;
+                v[0] += p;
+#pragma unroll
+                for (int c = 1; c < 7; ++c) {
+                    p *= dz;
+                    v[c] += p;
+                }
+                t0 += fabs(rho);
+                t2 += fabs(rho) * dz * dz;
+            }
+            double yp = 1.0;
+#pragma unroll
+            for (int bb = 0; bb < 7; ++bb) {
+#pragma unroll
+                for (int c = 0; c < 7 - bb; ++c) w[bc_idx(bb, c)] += yp * v[c];
+                yp *= dy;
+            }
+            s0 += t0;
+            s2 += t2 + dy * dy * t0;
+        }
+        // rows of one x summed over the row groups, then x powers over the
+        // lanes: four (b, c) entries per phase, wave g taking entry 4 ph + g
+#pragma unroll
+        for (int ph = 0; ph < 7; ++ph) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[yg][i][lane] = w[4 * ph + i];
+            if (ph == 0) {
+                red2[yg][0][lane] = s0;
+                red2[yg][1][lane] = s2;
+            }
+            __syncthreads();
+            const int q = 4 * ph + yg;
+            int bb = 0, c = q;
+            while (c > 6 - bb) {
+                c -= 7 - bb;
+                ++bb;
+            }
+            double ws = 0.0;
+            for (int g = 0; g < NG; ++g) ws += red[g][yg][lane];
+            double xp = 1.0;
+            for (int aa = 0; aa <= 6 - bb - c; ++aa) {
+                double val = xp * ws;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) val += __shfl_down(val, off, 64);
+                if (lane == 0) tot[mono_idx(aa, bb, c)] += val;
+                xp *= dx;
+            }
+            if (ph == 0 && yg == 0) {
+                double S0 = 0.0, S2 = 0.0;
+                for (int g = 0; g < NG; ++g) {
+                    S0 += red2[g][0][lane];
+                    S2 += red2[g][1][lane];
+                }
+                S2 += dx * dx * S0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    S0 += __shfl_down(S0, off, 64);
+                    S2 += __shfl_down(S2, off, 64);
+                }
+                if (lane == 0) {
+                    tot[GC_NM] += S0;
+                    tot[GC_NM + 1] += S2;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double* out = a.partial + ((size_t)pid * a.n_zchunks + blockIdx.y) * GC_N;
+    for (int t = threadIdx.x; t < GC_NM + 2; t += GM_BS) out[t] = tot[t];
+}
+
+// 2. sum the chunk partials in chunk order, convert to Racah moments with
+//    the polynomial table; optional orthonormal copy
 __global__ void k_moments_final(ExxArgs a, double* Q_orth) {
+    __shared__ double M[GC_NM + 2];
     const int pid = blockIdx.x;
     const int k = threadIdx.x;
     if (pid == 0 && k == 0 && a.queue_ctr) *a.queue_ctr = 0;
-    if (k >= SEA_NACC) return;
     const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
-    const long n_int = (long)P.n[0] * P.n[1] * P.n[2];
-    const int used = (int)((n_int + GM_CHUNK - 1) / GM_CHUNK);
-    double s = 0.0;
-    for (int c = 0; c < used; ++c) s += a.partial[((size_t)pid * a.n_chunks + c) * SEA_NACC + k];
+    const int used = (P.n[2] + GC_ZC - 1) / GC_ZC;
+    for (int t = k; t < GC_NM + 2; t += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < used; ++c) s += a.partial[((size_t)pid * a.n_zchunks + c) * GC_N + t];
+        M[t] = s;
+    }
+    __syncthreads();
+    if (k >= SEA_NACC) return;
+    double s;
+    if (k < SEA_NMOM) {
+        s = 0.0;
+        for (int t = 0; t < GC_NM; ++t) s += a.racah_tab[k * GC_NM + t] * M[t];
+    } else if (k == SEA_NMOM) {
+        s = M[GC_NM];                        // sum |rho|
+    } else if (k == SEA_NMOM + 1) {
+        s = M[0];                            // sum rho
+    } else {
+        s = M[GC_NM + 1];                    // sum |rho| r^2
+    }
     s *= C.dV;
     if (k < SEA_NMOM) {
         int l = 0;
@@ -709,8 +874,8 @@ __global__ __launch_bounds__(ES_BS) void k_energy_sum(ExxArgs a, double* out, do
 int exx_n_chunks(long n_int_max) { return (int)((n_int_max + GM_CHUNK - 1) / GM_CHUNK); }
 
 hipError_t launch_gather_moments(const ExxArgs& a, hipStream_t s) {
-    dim3 grid(a.n_pairs, a.n_chunks);
-    hipLaunchKernelGGL(k_gather_moments<SEA_LMAX>, grid, dim3(GM_BS), 0, s, a);
+    hipLaunchKernelGGL(k_racah_poly, dim3(1), dim3(128), 0, s, a.racah_tab);
+    hipLaunchKernelGGL(k_gather_cart, dim3(a.n_pairs, a.n_zchunks), dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -198,6 +198,7 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.slot_stride = (size_t)64 * 64 * (nz_max + 1);
     if (L.slot_stride < stride) L.slot_stride = stride;
     L.n_chunks = exx_n_chunks((long)stride);
+    L.n_zchunks = (nz_max + GC_ZC - 1) / GC_ZC;
     L.n_slots = n_pairs < ctx->n_cu * 4 ? (n_pairs > 0 ? n_pairs : 1) : ctx->n_cu * 4;
     L.nmax = nmax;
     size_t off = 0;
@@ -213,7 +214,8 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.order = take(np * sizeof(int));
     L.dbox = take(np * 12 * sizeof(int));
     L.cells = take(nc * sizeof(DevCell));
-    L.partial = take(np * L.n_chunks * SEA_NACC * sizeof(double));
+    L.partial = take(np * L.n_zchunks * GC_N * sizeof(double));
+    L.racah_tab = take(GC_TAB * sizeof(double));
     L.mom = take(np * SEA_NACC * sizeof(double));
     L.b = take(np * stride * sizeof(double));
     L.v = with_v ? take(np * stride * sizeof(double)) : 0;
@@ -475,6 +477,8 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.n_cells = (int)S.cells.size();
     a.partial = (double*)(base + Ly.partial);
     a.n_chunks = Ly.n_chunks;
+    a.n_zchunks = Ly.n_zchunks;
+    a.racah_tab = (double*)(base + Ly.racah_tab);
     a.mom = (double*)(base + Ly.mom);
     a.b = (double*)(base + Ly.b);
     a.v = v_ext ? v_ext : (double*)(base + Ly.v);

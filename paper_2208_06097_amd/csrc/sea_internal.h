@@ -59,9 +59,10 @@ struct StageTimer {
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
     size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, slots, stats, csr_off, csr_ent, scal, counter;
-    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, total;
+    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, total;
     int nmax;
     int n_chunks;
+    int n_zchunks;
     int n_slots;
     size_t stride;        // doubles per pair-domain array (max interior size)
     size_t slot_stride;   // elements per CG slot array
@@ -91,8 +92,10 @@ struct ExxArgs {
     const DevCell* cells; // device cell table
     const int* pair_cell; // cell index of every pair
     int n_cells;
-    double* partial;      // n_pairs x n_chunks x SEA_NACC
-    int n_chunks;
+    double* partial;      // n_pairs x n_zchunks x GC_N (Cartesian moments per plane chunk)
+    int n_chunks;         // point chunks of GM_CHUNK (start-guess and network kernels)
+    int n_zchunks;        // plane chunks of GC_ZC (moment gather)
+    double* racah_tab;    // SEA_NMOM x 84 monomial coefficients of the Racah harmonics
     double* mom;          // n_pairs x SEA_NACC (Racah moments, dV applied)
     double* b;            // n_pairs x stride
     double* v;            // n_pairs x stride
@@ -147,6 +150,11 @@ __device__ __forceinline__ int wrap_near(int m, int N) {
     while (m >= N) m -= N;
     return m;
 }
+
+// Moment gather: planes per workgroup and doubles per chunk record.
+constexpr int GC_ZC = 16;
+constexpr int GC_N = 88;
+constexpr int GC_TAB = SEA_NMOM * 84;
 
 // Kernel launchers (k_exx.hip).  All enqueue on `s`.
 int exx_n_chunks(long n_int_max);
