@@ -16,36 +16,56 @@
 // The transform along one axis is a dense product with the symmetric,
 // orthogonal matrix S_n[j][k] = sqrt(2/(n+1)) sin(pi (j+1)(k+1)/(n+1))
 // (n <= 64 here, so a 64 x 64 product on the matrix cores beats an FFT of
-// this length on this part).  Each pass transforms the slowest axis of a pair's array (a, b, c)
-// and writes (b, c, a'): the axes rotate, so three passes transform z, y,
-// x and restore the layout.  Forward passes end with the division by
-// lambda, inverse passes (the same matrices: S is its own inverse) with
-// the addition into x.  FP64 throughout; pairs with an axis longer than
-// 64 keep the multipole start.
+// this length on this part).  Three passes over a pair's array, each one
+// read and one write: the forward 2-D transform of every z plane (two
+// products in LDS), then along z the forward transform, the division by
+// lambda and the inverse transform (S is its own inverse) in one tile, then
+// the inverse 2-D transform of every plane, added into x.  FP64
+// throughout; pairs with an axis longer than 64 keep the multipole start.
 #include "sea_internal.h"
 
 namespace {
 
 constexpr int DS_BS = 256;
 constexpr int DS_N = 64;        // longest axis handled
-constexpr int DS_TC = 64;       // columns per workgroup tile
+constexpr int DS_TC = 64;       // columns per z-line tile
+constexpr int DS_OPN = 2048;    // operand table entries per length n
 constexpr double kPiD = 3.14159265358979323846;
 // second-derivative weights of the O(h^12) central difference (App. C)
 constexpr double kW[7] = {-5369.0 / 1800.0, 12.0 / 7.0, -15.0 / 56.0, 10.0 / 189.0,
                           -1.0 / 112.0, 2.0 / 1925.0, -1.0 / 16632.0};
 
-__host__ __device__ constexpr int tab_off(int n) { return (n - 1) * n * (2 * n - 1) / 6; }  // sum of m^2, m < n
-__host__ __device__ constexpr int mu_off(int n) { return (n - 1) * n / 2; }                  // sum of m, m < n
+__host__ __device__ constexpr int mu_off(int n) { return (n - 1) * n / 2; }   // sum of m, m < n
 
-// S_n and the one-axis eigenvalues (h = 1) for n = blockIdx.x + 1
-__global__ __launch_bounds__(DS_BS) void k_dst_tables(double* __restrict__ S, double* __restrict__ mu) {
+// Even/odd split.  With S[j][n-1-k] = (-1)^j S[j][k], the transform of a
+// vector a of length n is, for h = floor(n/2),
+//   y_{2i}   = sum_{k<h} S[2i][k]   (a_k + a_{n-1-k})  (+ S[2i][h] a_h, n odd)
+//   y_{2i+1} = sum_{k<h} S[2i+1][k] (a_k - a_{n-1-k}),
+// two products of half the size: half the flops of the dense product.
+// The kernels fold a column as p_k = a_k + a_{n-1-k}, m_k = a_k - a_{n-1-k}
+// for k < h and p_k = m_k = a_k beyond; the table below is zero where a
+// folded entry must not count (k > h; k = h unless n is odd and the row
+// even), so both are read with one rule.
+//
+// Operand table of length n: entry ((par * 2 + b) * 8 + kk) * 64 + lane
+// holds S[2 i + par][k] for i = 16 b + lane % 16, k = 4 kk + lane / 16, the
+// matrix-core operand of lane `lane` at k step kk for output block b of
+// parity par (as A: rows i; as B: columns i; the same lanes either way).
+__global__ __launch_bounds__(DS_BS) void k_dst_tables(double* __restrict__ opt, double* __restrict__ mu) {
     const int n = blockIdx.x + 1;
-    double* Sn = S + tab_off(n);
+    double* On = opt + (size_t)(n - 1) * DS_OPN;
     const double sc = sqrt(2.0 / (n + 1));
-    for (int t = threadIdx.x; t < n * n; t += DS_BS) {
-        const int j = t / n, k = t % n;
-        const int m = ((j + 1) * (k + 1)) % (2 * (n + 1));   // argument reduced to [0, 2 pi)
-        Sn[t] = sc * sin(kPiD * (double)m / (double)(n + 1));
+    const int h = n / 2;
+    for (int t = threadIdx.x; t < DS_OPN; t += DS_BS) {
+        const int par = t >> 10, b = (t >> 9) & 1, kk = (t >> 6) & 7, lane = t & 63;
+        const int j = 2 * (16 * b + (lane & 15)) + par, k = 4 * kk + (lane >> 4);
+        const bool use = j < n && (k < h || (k == h && (n & 1) && par == 0));
+        double v = 0.0;
+        if (use) {
+            const int m = ((j + 1) * (k + 1)) % (2 * (n + 1));   // argument reduced to [0, 2 pi)
+            v = sc * sin(kPiD * (double)m / (double)(n + 1));
+        }
+        On[t] = v;
     }
     for (int m = threadIdx.x; m < n; m += DS_BS) {
         const double th = kPiD * (double)(m + 1) / (double)(n + 1);
@@ -63,114 +83,279 @@ struct DstArgs {
     size_t stride;
     const double* in;
     double* out;
-    const double* S;
+    const double* opt;
     const double* mu;
-    int pass;   // 0: (z,y,x) -> (y,x,z'); 1: (y,x,z) -> (x,z,y'); 2: (x,z,y) -> (z,y,x')
-    int mode;   // 0 plain; 1 divide by lambda; 2 add into out (the start x)
 };
 
-// grid (pairs, DS_TG): workgroup y takes column tiles y, y + DS_TG, ... of
-// its pair, with S_A staged once; the next tile's input is loaded into
-// registers while the current one is multiplied.
-constexpr int DS_TG = 16;
-
-// One pass on the FP64 matrix cores (v_mfma_f64_16x16x4f64): A = S
-// (j x k, read as S[k][j], S being symmetric), B = the tile (k x columns),
-// the axis zero-padded to 64.  Wave w owns output rows j = 16 w .. 16 w + 15
-// and the tile's four 16-column blocks.  Operand lanes: row/column = lane %
-// 16, k = lane / 16; result item v of a lane is row lane / 16 + 4 v, column
-// lane % 16.
+// Products on the FP64 matrix cores (v_mfma_f64_16x16x4f64), 4 waves per
+// workgroup, every product a 64 x 64 (folded: 2 x 32 x 32) one.  Operand
+// lanes: row (A) or column (B) = lane % 16, k = lane / 16; result item v of
+// a lane is row lane / 16 + 4 v, column lane % 16.  A wave keeps the table
+// operands of its output block (both parities, all 8 k steps) in registers
+// for the whole kernel, so the products issue no global loads.  One LDS
+// array per workgroup holds the tile through every step (in place, with a
+// barrier before each overwrite), which lets four workgroups share a CU and
+// hide each other's global latency.  Its rows are padded to DP_LD (66
+// doubles): every matrix-core operand read below has the row index on the
+// lanes, which that pitch spreads over all banks.
 typedef double dst_f64x4 __attribute__((ext_vector_type(4)));
+constexpr int DP_LD = 66;
+constexpr int DP_PG = 16;   // workgroups per pair (planes or column tiles strided over them)
+constexpr int DP_BS = 256;  // threads per workgroup
+constexpr int DP_PT = DS_N * DS_N / DP_BS;   // tile elements per thread
 
-__global__ __launch_bounds__(256) void k_dst_mfma(DstArgs d) {
-    __shared__ double sS[DS_N * DS_N];    // sS[k * 64 + j] = S[k][j]
-    __shared__ double tin[DS_N * DS_TC];  // tin[k * 64 + c]
-    constexpr int BS = 256, LD = DS_N * DS_N / BS;
+// p, m of the fold at k for the entries a[k], a[n-1-k] of one row
+__device__ __forceinline__ void dst_fold(const double* row, int n, int k, double& p, double& m) {
+    const double a0 = row[k];
+    const int k2 = n - 1 - k;
+    const double a1 = k2 > k ? row[k2] : 0.0;
+    p = a0 + a1;
+    m = a0 - a1;
+}
+
+// the operands of output block b (both parities) of length n
+__device__ __forceinline__ void dst_ops(const double* opt, int n, int b, int lane, double e[8], double o[8]) {
+    const double* t = opt + (size_t)(n - 1) * DS_OPN + lane;
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        e[kk] = t[((0 + b) * 8 + kk) * 64];
+        o[kk] = t[((2 + b) * 8 + kk) * 64];
+    }
+}
+
+// 2-D transform of every z plane of a pair, Y = S_y X S_x (X[y][x], x
+// contiguous), written in the plane's layout; INV adds Y into out.  Grid
+// (pairs, DP_PG): workgroup y takes planes y, y + DP_PG, ...  The LDS array
+// holds X[y][x], then T transposed (T^T[c][y], c = 32 parity + i for the
+// x mode 2 i + parity), then Y[j][x].  Wave w: output block w % 2 of the
+// transform, row (then column) blocks 2 (w / 2) and 2 (w / 2) + 1.
+template <bool INV>
+__global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
+    __shared__ double B[DS_N * DP_LD];
     const int pid = blockIdx.x;
     const sea_pair P = d.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     if (nx > DS_N || ny > DS_N || nz > DS_N) return;   // keeps the multipole start
-    int A, B, C;
-    if (d.pass == 0) { A = nz; B = ny; C = nx; }
-    else if (d.pass == 1) { A = ny; B = nx; C = nz; }
-    else { A = nx; B = nz; C = ny; }
-    const int ncol = B * C;
-    if ((int)blockIdx.y * DS_TC >= ncol) return;
-    const double* in = d.in + (size_t)pid * d.stride;
-    double* out = d.out + (size_t)pid * d.stride;
-    {
-        const double* Sa = d.S + tab_off(A);
-        double t[LD];
-#pragma unroll
-        for (int u = 0; u < LD; ++u) {
-            const int q = threadIdx.x + u * BS, k = q / DS_N, j = q % DS_N;
-            t[u] = (k < A && j < A) ? Sa[k * A + j] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < LD; ++u) sS[threadIdx.x + u * BS] = t[u];
-    }
-    const DevCell& Cl = d.cells[d.pair_cell[pid]];
+    if ((int)blockIdx.y >= nz) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
-    double nxt[LD];
-    auto load_tile = [&](int c0) {
+    const int hb = w & 1, bp = 2 * (w >> 1);
+    double ex[8], ox[8], ey[8], oy[8];
+    dst_ops(d.opt, nx, hb, lane, ex, ox);
+    dst_ops(d.opt, ny, hb, lane, ey, oy);
+    // entries outside the ny x nx corner only ever meet zero table entries;
+    // they start finite and stay finite
+    for (int t = threadIdx.x; t < DS_N * DP_LD; t += DP_BS) B[t] = 0.0;
+    const int npl = nx * ny;
+    // LDS offset y * DP_LD + x of element e = threadIdx.x + u * DP_BS
+    const int x0 = threadIdx.x % nx, y0 = threadIdx.x / nx, sxs = DP_BS % nx, sys = DP_BS / nx;
+    auto for_elems = [&](auto&& f) {
+        int x = x0, y = y0;
+        asm volatile("" : "+v"(x), "+v"(y));   // walked per plane, not precomputed and held
 #pragma unroll
-        for (int u = 0; u < LD; ++u) {
-            const int q = threadIdx.x + u * BS, a = q / DS_TC, c = q % DS_TC;
-            nxt[u] = (a < A && c0 + c < ncol) ? in[(size_t)a * ncol + c0 + c] : 0.0;
+        for (int u = 0; u < DP_PT; ++u) {
+            const int e = threadIdx.x + u * DP_BS;
+            if (e < npl) f(u, e, y * DP_LD + x);
+            x += sxs;
+            y += sys;
+            if (x >= nx) {
+                x -= nx;
+                ++y;
+            }
         }
     };
-    load_tile(blockIdx.y * DS_TC);
-    for (int col0 = blockIdx.y * DS_TC; col0 < ncol; col0 += DS_TG * DS_TC) {
+    const double* in = d.in + (size_t)pid * d.stride;
+    double* out = d.out + (size_t)pid * d.stride;
+    for (int z = blockIdx.y; z < nz; z += DP_PG) {
+        const size_t zo = (size_t)z * npl;
+        int gk = g;
+        asm volatile("" : "+v"(gk));   // recompute the fold addresses per plane rather than keep them all live
+        double val[DP_PT];
+#pragma unroll
+        for (int u = 0; u < DP_PT; ++u) {
+            const int e = threadIdx.x + u * DP_BS;
+            val[u] = e < npl ? in[zo + e] : 0.0;
+        }
+        __syncthreads();
+        for_elems([&](int u, int, int o) { B[o] = val[u]; });
+        __syncthreads();
+        // T = X S_x: rows y of blocks bp, bp + 1; x modes of block hb
+        dst_f64x4 acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = dst_f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                double p, m;
+                dst_fold(B + (16 * (bp + a) + r) * DP_LD, nx, 4 * kk + gk, p, m);
+                acc[a][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, ex[kk], acc[a][0], 0, 0, 0);
+                acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(m, ox[kk], acc[a][1], 0, 0, 0);
+                if (a == 1 && (kk & 1)) __builtin_amdgcn_sched_barrier(0);   // bounds the reads in flight
+            }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < LD; ++u) tin[threadIdx.x + u * BS] = nxt[u];
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int par = 0; par < 2; ++par)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    B[(32 * par + 16 * hb + r) * DP_LD + 16 * (bp + a) + g + 4 * v] = acc[a][par][v];
         __syncthreads();
-        if (col0 + DS_TG * DS_TC < ncol) load_tile(col0 + DS_TG * DS_TC);
-        dst_f64x4 acc[4];
+        // Y = S_y T: columns c of blocks bp, bp + 1; y modes of block hb
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[ct] = dst_f64x4{0.0, 0.0, 0.0, 0.0};
-        const int kend = (A + 3) & ~3;
-        for (int k0 = 0; k0 < kend; k0 += 4) {
-            const double av = sS[(k0 + g) * DS_N + 16 * w + r];
+        for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = dst_f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                const double bv = tin[(k0 + g) * DS_TC + 16 * ct + r];
-                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                double p, m;
+                dst_fold(B + (16 * (bp + a) + r) * DP_LD, ny, 4 * kk + gk, p, m);
+                acc[a][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey[kk], p, acc[a][0], 0, 0, 0);
+                acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(oy[kk], m, acc[a][1], 0, 0, 0);
+                if (a == 1 && (kk & 1)) __builtin_amdgcn_sched_barrier(0);
+            }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int c = 16 * (bp + a) + r;
+            const int xm = 2 * (c & 31) + (c >> 5);
+#pragma unroll
+            for (int par = 0; par < 2; ++par)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int j = 2 * (16 * hb + g + 4 * v) + par;
+                    if (j < ny && xm < nx) B[j * DP_LD + xm] = acc[a][par][v];
+                }
+        }
+        __syncthreads();
+        for_elems([&](int, int e, int o) {
+            if (INV) out[zo + e] += B[o];
+            else out[zo + e] = B[o];
+        });
+    }
+}
+
+// Along z for each column (y, x): forward transform, division by the
+// eigenvalue of the mode, inverse transform; same layout in and out.  Grid
+// (pairs, DP_PG): workgroup y takes 64-column tiles y, y + DP_PG, ...  The
+// LDS array holds the tile transposed (column-major: U[c][z]), so that the
+// transform along z reads rows.  Wave w: z modes of block w % 2, columns of
+// blocks 2 (w / 2) and 2 (w / 2) + 1.
+__global__ __launch_bounds__(DP_BS, 3) void k_dst_zline(DstArgs d) {
+    __shared__ double U[DS_TC * DP_LD];
+    __shared__ double lxy[DS_TC];   // x and y parts of the eigenvalue of each tile column
+    const int pid = blockIdx.x;
+    const sea_pair P = d.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    if (nx > DS_N || ny > DS_N || nz > DS_N) return;
+    const int ncol = nx * ny;
+    if ((int)blockIdx.y * DS_TC >= ncol) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int hb = w & 1, bp = 2 * (w >> 1);
+    double ez[8], oz[8];
+    dst_ops(d.opt, nz, hb, lane, ez, oz);
+    const DevCell& Cl = d.cells[d.pair_cell[pid]];
+    const double ihx = 1.0 / (Cl.h[0] * Cl.h[0]), ihy = 1.0 / (Cl.h[1] * Cl.h[1]), ihz = 1.0 / (Cl.h[2] * Cl.h[2]);
+    const double* mux = d.mu + mu_off(nx);
+    const double* muy = d.mu + mu_off(ny);
+    const double lzj = lane < nz ? d.mu[mu_off(nz) + lane] * ihz : 0.0;   // z part for mode j = lane
+    const double* in = d.in + (size_t)pid * d.stride;
+    double* out = d.out + (size_t)pid * d.stride;
+    // load element u of a thread: row a = threadIdx.x / 64 + 4 u, column threadIdx.x % 64
+    const int lc = threadIdx.x % DS_TC, la = threadIdx.x / DS_TC;
+    for (int c0 = blockIdx.y * DS_TC; c0 < ncol; c0 += DP_PG * DS_TC) {
+        int gk = g;
+        asm volatile("" : "+v"(gk));   // recompute the fold addresses per tile rather than keep them all live
+        double val[DP_PT];
+        const bool cl = c0 + lc < ncol;
+#pragma unroll
+        for (int u = 0; u < DP_PT; ++u) {
+            const int a = la + 4 * u;
+            val[u] = (cl && a < nz) ? in[(size_t)a * ncol + c0 + lc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < DP_PT; ++u) U[lc * DP_LD + la + 4 * u] = val[u];
+        if (threadIdx.x < DS_TC) {
+            const int col = c0 + threadIdx.x;
+            double l = 0.0;
+            if (col < ncol) {
+                const int yy = col / nx, xx = col - yy * nx;
+                l = muy[yy] * ihy + mux[xx] * ihx;
+            }
+            lxy[threadIdx.x] = l;
+        }
+        __syncthreads();
+        dst_f64x4 acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = dst_f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                double p, m;
+                dst_fold(U + (16 * (bp + a) + r) * DP_LD, nz, 4 * kk + gk, p, m);
+                acc[a][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ez[kk], p, acc[a][0], 0, 0, 0);
+                acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(oz[kk], m, acc[a][1], 0, 0, 0);
+                if (a == 1 && (kk & 1)) __builtin_amdgcn_sched_barrier(0);
+            }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int par = 0; par < 2; ++par)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    U[(16 * (bp + a) + r) * DP_LD + 2 * (16 * hb + g + 4 * v) + par] = acc[a][par][v];
+        __syncthreads();
+        // divide by the eigenvalue: wave w takes columns w + 4 u, lane the mode j
+        if (lane < nz) {
+#pragma unroll
+            for (int u = 0; u < DS_TC / 4; ++u) {
+                const int cc = w + 4 * u;
+                if (c0 + cc < ncol) U[cc * DP_LD + lane] /= lxy[cc] + lzj;
             }
         }
+        __syncthreads();
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-            const int col = col0 + 16 * ct + r;
+        for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = dst_f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                double p, m;
+                dst_fold(U + (16 * (bp + a) + r) * DP_LD, nz, 4 * kk + gk, p, m);
+                acc[a][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ez[kk], p, acc[a][0], 0, 0, 0);
+                acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(oz[kk], m, acc[a][1], 0, 0, 0);
+                if (a == 1 && (kk & 1)) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int col = c0 + 16 * (bp + a) + r;
             if (col >= ncol) continue;
-            double lam_col = 0.0;
-            if (d.mode == 1) {
-                const int zz = col / C, yy = col % C;
-                lam_col = d.mu[mu_off(nz) + zz] / (Cl.h[2] * Cl.h[2]) + d.mu[mu_off(ny) + yy] / (Cl.h[1] * Cl.h[1]);
-            }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int j = 16 * w + g + 4 * v;
-                if (j >= A) continue;
-                const double val = acc[ct][v];
-                const size_t o = (size_t)col * A + j;
-                if (d.mode == 1) out[o] = val / (lam_col + d.mu[mu_off(nx) + j] / (Cl.h[0] * Cl.h[0]));
-                else if (d.mode == 2) out[o] += val;
-                else out[o] = val;
-            }
+            for (int par = 0; par < 2; ++par)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int j = 2 * (16 * hb + g + 4 * v) + par;
+                    if (j < nz) out[(size_t)j * ncol + col] = acc[a][par][v];
+                }
         }
     }
 }
 
 }  // namespace
 
-size_t dst_table_doubles() { return (size_t)tab_off(DS_N + 1); }
+size_t dst_table_doubles() { return (size_t)DS_N * DS_OPN; }
 size_t dst_mu_doubles() { return (size_t)mu_off(DS_N + 1); }
 
 // x += S^-1 ((S r) ./ lambda) for every pair whose axes are all <= 64:
 // r (n_pairs x stride) is overwritten, tmp is scratch of the same size.
 hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, double* tmp, double* tab, double* mu,
                                  hipStream_t s, const std::function<void(bool)>& mark) {
+    (void)ncol_max;
     if (a.n_pairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_dst_tables, dim3(DS_N), dim3(DS_BS), 0, s, tab, mu);
     DstArgs d{};
@@ -178,21 +363,21 @@ hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, doub
     d.cells = a.cells;
     d.pair_cell = a.pair_cell;
     d.stride = a.stride;
-    d.S = tab;
+    d.opt = tab;
     d.mu = mu;
-    const int tiles = (ncol_max + DS_TC - 1) / DS_TC;
-    const dim3 grid((unsigned)a.n_pairs, (unsigned)(tiles < DS_TG ? tiles : DS_TG));
-    // forward: r -> tmp -> r -> tmp (divided by lambda); inverse: tmp -> r -> tmp -> x (added)
-    const double* ins[6] = {r, tmp, r, tmp, r, tmp};
-    double* outs[6] = {tmp, r, tmp, r, tmp, a.v};
+    const dim3 grid((unsigned)a.n_pairs, DP_PG);
     mark(true);
-    for (int q = 0; q < 6; ++q) {
-        d.in = ins[q];
-        d.out = outs[q];
-        d.pass = q % 3;
-        d.mode = q == 2 ? 1 : (q == 5 ? 2 : 0);
-        hipLaunchKernelGGL(k_dst_mfma, grid, dim3(256), 0, s, d);
-    }
+    // planes forward: r -> tmp; z lines forward, divided, inverse: tmp -> r;
+    // planes inverse, added into x
+    d.in = r;
+    d.out = tmp;
+    hipLaunchKernelGGL(k_dst_plane<false>, grid, dim3(DP_BS), 0, s, d);
+    d.in = tmp;
+    d.out = r;
+    hipLaunchKernelGGL(k_dst_zline, grid, dim3(DP_BS), 0, s, d);
+    d.in = r;
+    d.out = a.v;
+    hipLaunchKernelGGL(k_dst_plane<true>, grid, dim3(DP_BS), 0, s, d);
     mark(false);
     return hipGetLastError();
 }
