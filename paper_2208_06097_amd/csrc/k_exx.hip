@@ -297,50 +297,68 @@ __global__ void k_moments_final(ExxArgs a, double* Q_orth) {
 // (u, v) column and adds their taps to the 6 nearest interior points.  Axes
 // run in separate launches (x, then y, then z), so every b point is updated
 // by one thread at a time, in a fixed order; no ghost buffer is kept.
+// Neighbouring lanes take neighbouring x for the y and z faces, so those
+// updates are coalesced; the x faces' targets are 6 contiguous points of a
+// row, so their updates go through LDS and out with a lane per target point.
 constexpr int GA_BS = 256;
 
 template <int LM>
 __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a, int ax) {
     __shared__ double Q[SEA_NMOM];
+    __shared__ double tap[GA_BS][2 * SEA_HALO];
     const int pid = blockIdx.x;
     if (threadIdx.x < SEA_NMOM) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
     __syncthreads();
     const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
-    const int u = (ax + 1) % 3, v = (ax + 2) % 3;
-    const int t = blockIdx.y * GA_BS + threadIdx.x;
-    const int au = t % a.nmax, av = t / a.nmax;
-    if (av >= a.nmax || au >= P.n[u] || av >= P.n[v]) return;
+    const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;   // column coordinates, x first where it is one
     const int n = P.n[ax];
     const double ih2 = 1.0 / (C.h[ax] * C.h[ax]);
-    int pos[3];
-    pos[u] = au;
-    pos[v] = av;
-    size_t stride_ax = 1, base = 0;
-    {
-        const size_t st[3] = {1, (size_t)P.n[0], (size_t)P.n[0] * P.n[1]};
-        stride_ax = st[ax];
-        base = pos[u] * st[u] + pos[v] * st[v];
+    const size_t st[3] = {1, (size_t)P.n[0], (size_t)P.n[0] * P.n[1]};
+    const int c0 = blockIdx.y * GA_BS;
+    auto column = [&](int c, int& au, int& av) {
+        au = c % a.nmax;
+        av = c / a.nmax;
+        return av < a.nmax && au < P.n[u] && av < P.n[v];
+    };
+    int au, av;
+    const bool live = column(c0 + threadIdx.x, au, av);
+    const bool staged = ax == 0 && n >= 2 * SEA_HALO;   // x faces, the two faces' targets disjoint
+    double* b = a.b + (size_t)pid * a.stride;
+    if (live) {
+        int pos[3];
+        pos[u] = au;
+        pos[v] = av;
+        const size_t base = pos[u] * st[u] + pos[v] * st[v];
+        for (int plus = 0; plus < 2; ++plus) {
+            double g[SEA_HALO + 1];
+#pragma unroll
+            for (int L = 1; L <= SEA_HALO; ++L) {
+                pos[ax] = plus ? n - 1 + L : -L;
+                g[L] = racah_me_potential<LM>(Q, a.lmax, (P.lo[0] + pos[0]) * C.h[0] - P.origin[0],
+                                              (P.lo[1] + pos[1]) * C.h[1] - P.origin[1],
+                                              (P.lo[2] + pos[2]) * C.h[2] - P.origin[2]);
+            }
+#pragma unroll
+            for (int d = 0; d < SEA_HALO; ++d) {
+                if (d >= n) break;
+                double acc = 0.0;
+#pragma unroll
+                for (int k = d + 1; k <= SEA_HALO; ++k) acc += kC[k] * ih2 * g[k - d];
+                const int p = plus ? n - 1 - d : d;
+                if (staged) tap[threadIdx.x][plus ? 2 * SEA_HALO - 1 - d : d] = acc;   // slot j: point j or n - 12 + j
+                else b[base + (size_t)p * st[ax]] += acc;
+            }
+        }
     }
-    double* b = a.b + (size_t)pid * a.stride + base;
-    for (int plus = 0; plus < 2; ++plus) {
-        double g[SEA_HALO + 1];
-#pragma unroll
-        for (int L = 1; L <= SEA_HALO; ++L) {
-            pos[ax] = plus ? n - 1 + L : -L;
-            g[L] = racah_me_potential<LM>(Q, a.lmax, (P.lo[0] + pos[0]) * C.h[0] - P.origin[0],
-                                          (P.lo[1] + pos[1]) * C.h[1] - P.origin[1],
-                                          (P.lo[2] + pos[2]) * C.h[2] - P.origin[2]);
-        }
-#pragma unroll
-        for (int d = 0; d < SEA_HALO; ++d) {
-            if (d >= n) break;
-            double acc = 0.0;
-#pragma unroll
-            for (int k = d + 1; k <= SEA_HALO; ++k) acc += kC[k] * ih2 * g[k - d];
-            const int p = plus ? n - 1 - d : d;
-            b[(size_t)p * stride_ax] += acc;
-        }
+    if (!staged) return;
+    __syncthreads();
+    for (int t = threadIdx.x; t < GA_BS * 2 * SEA_HALO; t += GA_BS) {
+        const int c = t / (2 * SEA_HALO), j = t % (2 * SEA_HALO);
+        int cu, cv;
+        if (!column(c0 + c, cu, cv)) continue;
+        const int p = j < SEA_HALO ? j : n - 2 * SEA_HALO + j;
+        b[(size_t)cu * st[1] + (size_t)cv * st[2] + p] += tap[c][j];
     }
 }
 
