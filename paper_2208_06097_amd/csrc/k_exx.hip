@@ -705,7 +705,7 @@ __global__ __launch_bounds__(CG_BS) void k_cg_f64(ExxArgs a) {
 //    v_pair(g - lo) phi_other(g), every domain duplicate of g included.
 
 constexpr int SC_BS = 256;
-constexpr int SC_TX = 64, SC_TY = 4, SC_TZ = 4;
+constexpr int SC_TX = 64, SC_TY = 4, SC_TZ = 8;
 constexpr int SC_MAXE = 512;
 
 __device__ __forceinline__ bool axis_hits(int t0, int T, int lo, int n, int N) {
@@ -723,7 +723,7 @@ template <int LM>
 __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const int* __restrict__ off_all,
                                                    const int2* __restrict__ ent) {
     __shared__ int list[SC_MAXE];
-    __shared__ int cnt;
+    __shared__ int cnt, wide;
     const DevCell& C = a.cells[cell];
     const int* off = off_all + C.csr_base;
     double* __restrict__ W = C.W;
@@ -744,15 +744,18 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
         const int c1 = min(e1, c0 + SC_MAXE);
         // ordered compaction: thread 0 walks the entries (lists are short)
         if (threadIdx.x == 0) {
-            int m = 0;
+            int m = 0, nw = 0;
             for (int e = c0; e < c1; ++e) {
                 const int pid = ent[e].x;
                 const int* D = a.dbox + 12 * (size_t)pid + (o == a.pairs[pid].i ? 0 : 6);
                 if (axis_hits(tx0, SC_TX, D[0], D[3], C.N[0]) && axis_hits(ty0, SC_TY, D[1], D[4], C.N[1]) &&
-                    axis_hits(tz0, SC_TZ, D[2], D[5], C.N[2]))
+                    axis_hits(tz0, SC_TZ, D[2], D[5], C.N[2])) {
                     list[m++] = e;
+                    nw += (D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2]) ? 1 : 0;
+                }
             }
             cnt = m;
+            wide = nw;
         }
         __syncthreads();
         const int m = cnt;
@@ -813,6 +816,7 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
             for (int k = 0; k < SC_TZ; ++k) acc[k] += vv[k] * pv[k];
         }
         // general path: boxes wider than the cell (a grid point met several times)
+        if (wide)
 #pragma unroll
         for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) {
             const int lid = threadIdx.x + k * SC_BS;
