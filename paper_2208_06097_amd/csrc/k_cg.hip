@@ -354,7 +354,11 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
             const int id = (zz * ny + yy) * nx + xx;
             const double bv = b[id];
             bb += bv * bv;
-            rv = sres ? br[id] : bv;
+            if (sres)
+                rv = (a.start_res == 2 && spectral_pair(P) && !near_face(xx, nx) && !near_face(yy, ny) &&
+                      !near_face(zz, nz)) ? 0.0 : br[id];
+            else
+                rv = bv;
             if (fold) c0 = (T)x[id];
             if (!sres) x[id] = 0.0;
         }
@@ -550,6 +554,7 @@ __global__ __launch_bounds__(FIN_BS) void k_start_residual(ExxArgs a) {
     const int pid = blockIdx.x;
     const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
+    if (a.skip_spectral && spectral_pair(P)) return;
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const int n = nx * ny * nz, nxy = nx * ny;
     const double ih2 = 1.0 / (C.h[0] * C.h[0]);
@@ -579,6 +584,7 @@ __global__ __launch_bounds__(RZ_NT) void k_residual_zm(ExxArgs a) {
     __shared__ double red[RZ_NT / 64 + 1];
     const int pid = blockIdx.x;
     const sea_pair P = a.pairs[pid];
+    if (a.skip_spectral && spectral_pair(P)) return;   // the face residual has it
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const int y0 = blockIdx.y * RZ_ROWS;
     if (y0 >= ny) {

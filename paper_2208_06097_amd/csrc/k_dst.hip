@@ -1,17 +1,19 @@
 // Spectral start for the pair Poisson solves (an extension of the CG start
 // guess of Eq. 9; the CG still drives every pair to the same true residual).
 //
-// With x0 the multipole start, the correction e = x - x0 solves A e = r0,
-// r0 = b - A x0, where A is the O(h^12) Laplacian with zero values beyond
-// the domain.  The same stencil with odd (instead of zero) continuation
-// beyond each face is diagonalized exactly by the type-I discrete sine
-// transform: for the mode sin((i+1) theta), theta = pi m / (n+1), one axis
-// contributes -(c0 + 2 sum_k ck cos(k theta)) / h^2.  The two operators
-// differ only where the stencil reaches past a face, i.e. within 6 points
-// of the boundary, and there e is tiny because x0 already carries the
-// multipole potential that sets the boundary values.  So e ~ S^-1 (r0 ./
-// lambda) with S the separable sine transform, and x0 + e leaves a
-// residual many decades below r0.
+// A is the O(h^12) Laplacian (negated) with zero values beyond the domain.
+// The same stencil with odd (instead of zero) continuation beyond each face,
+// A_odd, is diagonalized exactly by the type-I discrete sine transform: for
+// the mode sin((i+1) theta), theta = pi m / (n+1), one axis contributes
+// -(c0 + 2 sum_k ck cos(k theta)) / h^2.  The two differ only where the
+// stencil reaches past a face: D = A - A_odd lives on the 5 points next to
+// each face.  With x0 the multipole start, the start is
+//   x = x0 + A_odd^-1 (b - A x0) = A_odd^-1 (b - D x0),
+// whose right-hand side the gather and the boundary kernel form (D x0 needs
+// x0 on those points only), and its residual is b - A x = -D (x - x0), again
+// a face-points-only quantity.  x leaves a residual many decades below that
+// of x0 because x0 already carries the multipole potential that sets the
+// boundary values.
 //
 // The transform along one axis is a dense product with the symmetric,
 // orthogonal matrix S_n[j][k] = sqrt(2/(n+1)) sin(pi (j+1)(k+1)/(n+1))
@@ -20,8 +22,8 @@
 // read and one write: the forward 2-D transform of every z plane (two
 // products in LDS), then along z the forward transform, the division by
 // lambda and the inverse transform (S is its own inverse) in one tile, then
-// the inverse 2-D transform of every plane, added into x.  FP64
-// throughout; pairs with an axis longer than 64 keep the multipole start.
+// the inverse 2-D transform of every plane into x.  FP64 throughout; pairs
+// with an axis longer than 64 keep the multipole start.
 #include "sea_internal.h"
 
 namespace {
@@ -85,6 +87,9 @@ struct DstArgs {
     double* out;
     const double* opt;
     const double* mu;
+    const double* add;    // plane pass: added to `in` on the face points (nullable)
+    double* bsum;         // plane pass: per workgroup sum of in^2 (nullable; stride fnorm_parts(fn_gy) per pair)
+    int fn_gy;
 };
 
 // Products on the FP64 matrix cores (v_mfma_f64_16x16x4f64), 4 waves per
@@ -100,7 +105,6 @@ struct DstArgs {
 // lanes, which that pitch spreads over all banks.
 typedef double dst_f64x4 __attribute__((ext_vector_type(4)));
 constexpr int DP_LD = 66;
-constexpr int DP_PG = 16;   // workgroups per pair (planes or column tiles strided over them)
 constexpr int DP_BS = 256;  // threads per workgroup
 constexpr int DP_PT = DS_N * DS_N / DP_BS;   // tile elements per thread
 
@@ -124,12 +128,14 @@ __device__ __forceinline__ void dst_ops(const double* opt, int n, int b, int lan
 }
 
 // 2-D transform of every z plane of a pair, Y = S_y X S_x (X[y][x], x
-// contiguous), written in the plane's layout; INV adds Y into out.  Grid
+// contiguous), written in the plane's layout (the same kernel serves the
+// forward and the inverse transform: S is its own inverse).  With `add`,
+// the input is in + add on the points within 5 of a face (in elsewhere),
+// and with `bsum` the workgroup's sum of in^2 goes there.  Grid
 // (pairs, DP_PG): workgroup y takes planes y, y + DP_PG, ...  The LDS array
 // holds X[y][x], then T transposed (T^T[c][y], c = 32 parity + i for the
 // x mode 2 i + parity), then Y[j][x].  Wave w: output block w % 2 of the
 // transform, row (then column) blocks 2 (w / 2) and 2 (w / 2) + 1.
-template <bool INV>
 __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
     __shared__ double B[DS_N * DP_LD];
     const int pid = blockIdx.x;
@@ -166,6 +172,8 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
     };
     const double* in = d.in + (size_t)pid * d.stride;
     double* out = d.out + (size_t)pid * d.stride;
+    const double* add = d.add ? d.add + (size_t)pid * d.stride : nullptr;
+    double bsq = 0.0;
     for (int z = blockIdx.y; z < nz; z += DP_PG) {
         const size_t zo = (size_t)z * npl;
         int gk = g;
@@ -175,6 +183,21 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
         for (int u = 0; u < DP_PT; ++u) {
             const int e = threadIdx.x + u * DP_BS;
             val[u] = e < npl ? in[zo + e] : 0.0;
+        }
+        if (add) {   // the face correction, its loads in flight with the plane's
+            double ad[DP_PT];
+#pragma unroll
+            for (int u = 0; u < DP_PT; ++u) ad[u] = 0.0;
+            const bool zf = near_face(z, nz);
+            for_elems([&](int u, int e, int o) {
+                const int yy = o / DP_LD, xx = o % DP_LD;
+                ad[u] = (zf || near_face(xx, nx) || near_face(yy, ny)) ? add[zo + e] : 0.0;
+            });
+#pragma unroll
+            for (int u = 0; u < DP_PT; ++u) {
+                bsq += val[u] * val[u];
+                val[u] += ad[u];
+            }
         }
         __syncthreads();
         for_elems([&](int u, int, int o) { B[o] = val[u]; });
@@ -229,10 +252,20 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
                 }
         }
         __syncthreads();
-        for_elems([&](int, int e, int o) {
-            if (INV) out[zo + e] += B[o];
-            else out[zo + e] = B[o];
-        });
+        for_elems([&](int, int e, int o) { out[zo + e] = B[o]; });
+    }
+    if (d.bsum) {
+        __shared__ double red[DP_BS / 64];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) bsq += __shfl_down(bsq, off, 64);
+        __syncthreads();
+        if (lane == 0) red[w] = bsq;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int k = 0; k < DP_BS / 64; ++k) t += red[k];
+            d.bsum[(size_t)pid * fnorm_parts(d.fn_gy) + blockIdx.y] = t;
+        }
     }
 }
 
@@ -351,11 +384,12 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_zline(DstArgs d) {
 size_t dst_table_doubles() { return (size_t)DS_N * DS_OPN; }
 size_t dst_mu_doubles() { return (size_t)mu_off(DS_N + 1); }
 
-// x += S^-1 ((S r) ./ lambda) for every pair whose axes are all <= 64:
-// r (n_pairs x stride) is overwritten, tmp is scratch of the same size.
-hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, double* tmp, double* tab, double* mu,
-                                 hipStream_t s, const std::function<void(bool)>& mark) {
-    (void)ncol_max;
+// x = S^-1 ((S (b + fcorr)) ./ lambda) for every pair whose axes are all <=
+// 64 (fcorr added on the face points; it lives in tmp, scratch of the pair
+// arrays' size, which the passes then overwrite); r is scratch of the same
+// size; |b|^2 per workgroup into a.fnorm.
+hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, hipStream_t s,
+                                 const std::function<void(bool)>& mark) {
     if (a.n_pairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_dst_tables, dim3(DS_N), dim3(DS_BS), 0, s, tab, mu);
     DstArgs d{};
@@ -365,19 +399,24 @@ hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, doub
     d.stride = a.stride;
     d.opt = tab;
     d.mu = mu;
+    d.fn_gy = a.fn_gy;
     const dim3 grid((unsigned)a.n_pairs, DP_PG);
     mark(true);
-    // planes forward: r -> tmp; z lines forward, divided, inverse: tmp -> r;
-    // planes inverse, added into x
-    d.in = r;
+    // planes forward: b + fcorr (in tmp) -> tmp; z lines forward, divided,
+    // inverse: tmp -> r; planes inverse: r -> x
+    d.in = a.b;
+    d.add = tmp;
+    d.bsum = a.fnorm;
     d.out = tmp;
-    hipLaunchKernelGGL(k_dst_plane<false>, grid, dim3(DP_BS), 0, s, d);
+    hipLaunchKernelGGL(k_dst_plane, grid, dim3(DP_BS), 0, s, d);
+    d.add = nullptr;
+    d.bsum = nullptr;
     d.in = tmp;
     d.out = r;
     hipLaunchKernelGGL(k_dst_zline, grid, dim3(DP_BS), 0, s, d);
     d.in = r;
     d.out = a.v;
-    hipLaunchKernelGGL(k_dst_plane<true>, grid, dim3(DP_BS), 0, s, d);
+    hipLaunchKernelGGL(k_dst_plane, grid, dim3(DP_BS), 0, s, d);
     mark(false);
     return hipGetLastError();
 }

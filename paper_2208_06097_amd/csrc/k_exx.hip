@@ -301,6 +301,69 @@ __global__ void k_moments_final(ExxArgs a, double* Q_orth) {
 // updates are coalesced; the x faces' targets are 6 contiguous points of a
 // row, so their updates go through LDS and out with a lane per target point.
 constexpr int GA_BS = 256;
+constexpr int FF_S = 2 * FF_W;   // face points of a column (all of it when n < 10)
+
+// slot j of a column's face points: index j (j < 5) or n - 10 + j; false
+// for slots that repeat an index or fall outside (n < 10)
+__device__ __forceinline__ bool face_slot(int j, int n, int& i) {
+    i = j < FF_W ? j : n - FF_S + j;
+    return i >= 0 && i < n && (j < FF_W || i >= FF_W);
+}
+
+// sum over the stencil taps of a column point i that fall past a face, of
+// c_k times the odd continuation (period 2 (n + 1), zeros at -1 and n) of
+// the column values val(index)
+template <typename F>
+__device__ __forceinline__ double face_taps(int i, int n, F&& val) {
+    auto ext = [&](int q) {
+        const int per = 2 * (n + 1);
+        while (q < -1) q += per;
+        while (q > 2 * n) q -= per;
+        if (q == -1 || q == n) return 0.0;
+        return q > n ? -val(2 * n - q) : val(q);
+    };
+    double c = 0.0;
+#pragma unroll
+    for (int k = 1; k <= SEA_HALO; ++k) {
+        if (i - k < 0) c += kC[k] * ext(i - k);
+        if (i + k >= n) c += kC[k] * ext(i + k);
+    }
+    return c;
+}
+
+// All face slots of a column at once: out[j] = face_taps(index of slot j,
+// n, column values) for es[j] = the column value at slot j.  For n >= 10
+// the two faces are apart and a tap past a face mirrors onto the same face:
+// index d from the face takes -sum_{k >= d+2} c_k es[k - d - 2] (the point
+// at d + 1 past the face is a zero of the continuation), a fixed triangle.
+__device__ __forceinline__ void face_taps_all(int n, const double es[FF_S], double out[FF_S]) {
+    if (n >= FF_S) {
+#pragma unroll
+        for (int d = 0; d < FF_W; ++d) {
+            double lo = 0.0, hi = 0.0;
+#pragma unroll
+            for (int k = d + 2; k <= SEA_HALO; ++k) {
+                lo += kC[k] * es[k - d - 2];
+                hi += kC[k] * es[FF_S - 1 - (k - d - 2)];
+            }
+            out[d] = -lo;               // slot d: index d
+            out[FF_S - 1 - d] = -hi;    // slot 9 - d: index n - 1 - d
+        }
+        return;
+    }
+    auto val = [&](int q) {
+        const int jq = q < FF_W ? q : q - n + FF_S;
+        double e = 0.0;
+#pragma unroll
+        for (int j = 0; j < FF_S; ++j) e = j == jq ? es[j] : e;
+        return e;
+    };
+#pragma unroll
+    for (int j = 0; j < FF_S; ++j) {
+        int i;
+        out[j] = face_slot(j, n, i) ? face_taps(i, n, val) : 0.0;
+    }
+}
 
 template <int LM>
 __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a, int ax) {
@@ -420,14 +483,36 @@ __global__ __launch_bounds__(GM_BS) void k_me_guess(ExxArgs a) {
     }
 }
 
-// Multipole start on the 6-point shell inside the faces only, zero deeper
-// in (the spectral start needs the start right only where the stencil's
-// odd continuation past a face differs from its zero continuation, i.e. on
-// the 5 points next to each face).  One
-// workgroup per plane; the shell points of an inner plane (12 full rows and
-// 12 points of every other row) are enumerated densely.
+// Spectral start: the multipole start x0 on the points within 5 of a face
+// (into a.x0: the face correction and the face residual read it there), and
+// the whole multipole start into x for the pairs the sine transform skips
+// (an axis beyond 64 points).  One workgroup per plane; the face points of
+// an inner plane (10 full rows and 10 points of every other row) are
+// enumerated densely.
+template <typename F>
+__device__ __forceinline__ void for_face_points(int nx, int ny, int nz, int z, F&& f) {
+    if (z < FF_W || z >= nz - FF_W || nx <= FF_S || ny <= FF_S) {
+        for (int t = threadIdx.x; t < nx * ny; t += GM_BS) f(t % nx, t / nx);
+        return;
+    }
+    const int nfull = FF_S * nx, nside = (ny - FF_S) * FF_S;
+    for (int t = threadIdx.x; t < nfull + nside; t += GM_BS) {
+        int xx, yy;
+        if (t < nfull) {
+            const int r = t / nx;
+            xx = t % nx;
+            yy = r < FF_W ? r : ny - FF_S + r;
+        } else {
+            const int j = t - nfull, c = j % FF_S;
+            yy = FF_W + j / FF_S;
+            xx = c < FF_W ? c : nx - FF_S + c;
+        }
+        f(xx, yy);
+    }
+}
+
 template <int LM>
-__global__ __launch_bounds__(GM_BS) void k_me_shell(ExxArgs a) {
+__global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
     __shared__ double Q[SEA_NACC];
     const int pid = blockIdx.x, z = blockIdx.y;
     const sea_pair P = a.pairs[pid];
@@ -436,35 +521,134 @@ __global__ __launch_bounds__(GM_BS) void k_me_shell(ExxArgs a) {
     if (threadIdx.x < SEA_NACC) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
     __syncthreads();
     const DevCell& C = a.cells[a.pair_cell[pid]];
-    double* x = a.v + (size_t)pid * a.stride + (size_t)z * nx * ny;
-    auto me = [&](int xx, int yy) {
-        return me_start_value<LM>(Q, a.lmax, (P.lo[0] + xx) * C.h[0] - P.origin[0],
-                                  (P.lo[1] + yy) * C.h[1] - P.origin[1], (P.lo[2] + z) * C.h[2] - P.origin[2]);
+    const double dz = (P.lo[2] + z) * C.h[2] - P.origin[2];
+    const bool sp = spectral_pair(P);
+    double* out = (sp ? a.x0 : a.v) + (size_t)pid * a.stride + (size_t)z * nx * ny;
+    auto put = [&](int xx, int yy) {
+        out[yy * nx + xx] = me_start_value<LM>(Q, a.lmax, (P.lo[0] + xx) * C.h[0] - P.origin[0],
+                                               (P.lo[1] + yy) * C.h[1] - P.origin[1], dz);
     };
-    constexpr int H = SEA_HALO;
-    // full planes: the faces, thin boxes, and boxes the sine transform does
-    // not take (axes beyond 64 points keep the whole multipole start)
-    if (z < H || z >= nz - H || nx <= 2 * H || ny <= 2 * H || nx > 64 || ny > 64 || nz > 64) {
-        for (int t = threadIdx.x; t < nx * ny; t += GM_BS) x[t] = me(t % nx, t / nx);
+    if (sp) {
+        for_face_points(nx, ny, nz, z, put);
+    } else {
+        for (int t = threadIdx.x; t < nx * ny; t += GM_BS) put(t % nx, t / nx);
+    }
+}
+
+// The spectral start's two face quantities, one axis per launch.  D = A -
+// A_odd is the difference between the stencil with zero values past the
+// faces (A) and with the odd continuation the sine transform diagonalizes
+// (A_odd); per axis it lives on the 5 points next to each face and reads
+// values there only, i.e. on the same column along the axis.
+//   res = 0: the right-hand-side correction -D x0 into a.fcorr, so that
+//            A_odd^-1 (b - D x0) = x0 + A_odd^-1 (b - A x0);
+//   res = 1: after the transform (A_odd x = b - D x0), the residual
+//            r = b - A x = -D (x - x0) into bres (up to the transform's
+//            rounding, the stencil residual), and the per-workgroup sums of
+//            r^2 over the points whose last axis this is into a.fnorm.
+// A point near several faces takes an assignment from its first axis and
+// additions from the others; off the face points the arrays are not
+// written (and not read).  A workgroup takes FA_C columns, one lane per
+// face point (the 10 of a column): the column's values meet in LDS.  Lanes
+// run along x, which for the x faces means along a column's face points and
+// otherwise across columns, so the loads and stores are coalesced.
+constexpr int FA_C = 64;
+
+template <int RES>
+__global__ __launch_bounds__(GA_BS) void k_face_axis(ExxArgs a, int ax) {
+    __shared__ double es[FA_C][FF_S + 1];
+    __shared__ double red[GA_BS / 64 + 1];
+    const int pid = blockIdx.x;
+    const sea_pair P = a.pairs[pid];
+    if (!spectral_pair(P)) return;
+    const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;
+    const int n = P.n[ax], nu = P.n[u];
+    const int ncol = nu * P.n[v];
+    const int c0 = blockIdx.y * FA_C;
+    if (c0 >= ncol) {
+        if (RES && threadIdx.x == 0) a.fnorm[(size_t)pid * fnorm_parts(a.fn_gy) + DP_PG + ax * a.fn_gy + blockIdx.y] = 0.0;
         return;
     }
-    for (int t = threadIdx.x; t < nx * ny; t += GM_BS) {
-        const int xx = t % nx, yy = t / nx;
-        if (xx >= H && xx < nx - H && yy >= H && yy < ny - H) x[t] = 0.0;
-    }
-    const int nfull = 2 * H * nx, nside = (ny - 2 * H) * 2 * H;
-    for (int t = threadIdx.x; t < nfull + nside; t += GM_BS) {
-        int xx, yy;
-        if (t < nfull) {
-            const int r = t / nx;
-            xx = t % nx;
-            yy = r < H ? r : ny - 2 * H + r;
+    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const double ih2 = 1.0 / (C.h[ax] * C.h[ax]);
+    const size_t st[3] = {1, (size_t)P.n[0], (size_t)P.n[0] * P.n[1]};
+    const size_t po = (size_t)pid * a.stride;
+    // face point t of the workgroup: column c0 + cl, slot j
+    auto point = [&](int t, int& cl, int& j) {
+        if (ax == 0) {
+            cl = t / FF_S;
+            j = t % FF_S;
         } else {
-            const int j = t - nfull, c = j % (2 * H);
-            yy = H + j / (2 * H);
-            xx = c < H ? c : nx - 2 * H + c;
+            j = t / FA_C;
+            cl = t % FA_C;
         }
-        x[yy * nx + xx] = me(xx, yy);
+    };
+    auto offset = [&](int cl, int i) {
+        const int c = c0 + cl;
+        return (size_t)(c % nu) * st[u] + (size_t)(c / nu) * st[v] + (size_t)i * st[ax];
+    };
+    for (int t = threadIdx.x; t < FA_C * FF_S; t += GA_BS) {
+        int cl, j, i;
+        point(t, cl, j);
+        double e = 0.0;
+        if (c0 + cl < ncol && face_slot(j, n, i)) {
+            const size_t o = po + offset(cl, i);
+            e = RES ? a.v[o] - a.x0[o] : a.x0[o];
+        }
+        es[cl][j] = e;
+    }
+    __syncthreads();
+    double rr = 0.0;
+    double* out = RES ? a.bres : a.fcorr;
+    for (int t = threadIdx.x; t < FA_C * FF_S; t += GA_BS) {
+        int cl, j, i;
+        point(t, cl, j);
+        if (c0 + cl >= ncol || !face_slot(j, n, i)) continue;
+        double cs;
+        if (n >= FF_S) {   // the faces apart: a fixed triangle on the slot's own face
+            const int d = j < FF_W ? j : FF_S - 1 - j;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 2; k <= SEA_HALO; ++k)
+                if (k >= d + 2) acc += kC[k] * es[cl][j < FF_W ? k - d - 2 : FF_S - 1 - (k - d - 2)];
+            cs = -acc;
+        } else {
+            cs = face_taps(i, n, [&](int q) { return es[cl][q < FF_W ? q : q - n + FF_S]; });
+        }
+        const int c = c0 + cl, cu = c % nu, cv = c / nu;
+        // an earlier axis wrote this point where the column's own coordinates
+        // are near that axis's faces; a later one adds
+        bool earlier = false, later = false;
+        if (ax == 0) later = near_face(cu, P.n[1]) || near_face(cv, P.n[2]);   // column (y, z)
+        if (ax == 1) {                                                         // column (x, z)
+            earlier = near_face(cu, P.n[0]);
+            later = near_face(cv, P.n[2]);
+        }
+        if (ax == 2) earlier = near_face(cu, P.n[0]) || near_face(cv, P.n[1]); // column (x, y)
+        double* o = out + po + offset(cl, i);
+        const double w = (earlier ? *o : 0.0) - cs * ih2;
+        *o = w;
+        if (RES && !later) rr += w * w;
+    }
+    if (RES) {
+        rr = block_sum<GA_BS>(rr, red);
+        if (threadIdx.x == 0) a.fnorm[(size_t)pid * fnorm_parts(a.fn_gy) + DP_PG + ax * a.fn_gy + blockIdx.y] = rr;
+    }
+}
+
+// |b|^2 and |r|^2 of a pair from the partial sums (the transform's first
+// pass, one per workgroup, then the residual's, per axis and workgroup), in
+// a fixed order, into tile 0 of a.rnorm (the other tiles zero).
+__global__ __launch_bounds__(64) void k_face_norms(ExxArgs a) {
+    const int pid = blockIdx.x * 64 + threadIdx.x;
+    if (pid >= a.n_pairs || !spectral_pair(a.pairs[pid])) return;
+    const double* f = a.fnorm + (size_t)pid * fnorm_parts(a.fn_gy);
+    double bb = 0.0, rr = 0.0;
+    for (int k = 0; k < DP_PG; ++k) bb += f[k];
+    for (int k = 0; k < 3 * a.fn_gy; ++k) rr += f[DP_PG + k];
+    for (int t = 0; t < RZ_TILES; ++t) {
+        a.rnorm[((size_t)pid * RZ_TILES + t) * 2] = t == 0 ? bb : 0.0;
+        a.rnorm[((size_t)pid * RZ_TILES + t) * 2 + 1] = t == 0 ? rr : 0.0;
     }
 }
 
@@ -922,8 +1106,21 @@ hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_me_shell(const ExxArgs& a, int nz_max, hipStream_t s) {
-    hipLaunchKernelGGL(k_me_shell<SEA_LMAX>, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
+hipError_t launch_face_corr(const ExxArgs& a, hipStream_t s) {
+    const unsigned gy = (unsigned)a.fn_gy;
+    for (int ax = 0; ax < 3; ++ax) hipLaunchKernelGGL(k_face_axis<0>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a, ax);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_residual(const ExxArgs& a, hipStream_t s) {
+    const unsigned gy = (unsigned)a.fn_gy;
+    for (int ax = 0; ax < 3; ++ax) hipLaunchKernelGGL(k_face_axis<1>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a, ax);
+    hipLaunchKernelGGL(k_face_norms, dim3((a.n_pairs + 63) / 64), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_me_face(const ExxArgs& a, int nz_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_me_face<SEA_LMAX>, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -229,6 +229,8 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.dst_tab = spectral ? take(dst_table_doubles() * sizeof(double)) : 0;
     L.dst_mu = spectral ? take(dst_mu_doubles() * sizeof(double)) : 0;
     L.rnorm = spectral ? take(np * RZ_TILES * 2 * sizeof(double)) : 0;
+    L.x0 = spectral ? take(np * stride * sizeof(double)) : 0;
+    L.fnorm = spectral ? take(np * fnorm_parts(face_gy(nmax)) * sizeof(double)) : 0;
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
     L.csr_off = take((S.csr_off.size() + 1) * sizeof(int));
@@ -494,6 +496,12 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.queue_ctr = (int*)(base + Ly.counter);
     a.x_nonzero = ctx->opts.start != SEA_START_ZERO;
     a.bres = Ly.bres ? (double*)(base + Ly.bres) : nullptr;
+    // spectral start: x0 on the face points, -D x0 there (in the transform's
+    // scratch array), and the partial sums of the norms
+    a.x0 = Ly.x0 ? (double*)(base + Ly.x0) : nullptr;
+    a.fcorr = Ly.dst_tmp ? (double*)(base + Ly.dst_tmp) : nullptr;
+    a.fnorm = Ly.fnorm ? (double*)(base + Ly.fnorm) : nullptr;
+    a.fn_gy = face_gy(Ly.nmax);
     a.nmax = Ly.nmax;
     return a;
 }
@@ -526,15 +534,19 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         SEA_HIP_CHECK(ctx, launch_gather_moments(a, s));
         SEA_HIP_CHECK(ctx, launch_moments_final(a, f.Q_dev, s));
         timer_off(SEA_STAGE_GATHER);
+        const bool spectral = ctx->opts.start == SEA_START_SPECTRAL;
         timer_on(SEA_STAGE_BOUNDARY);
+        // spectral start: x0 on the face points first, which the boundary
+        // kernel's face correction reads
+        if (spectral) {
+            SEA_HIP_CHECK(ctx, launch_me_face(a, nz_max, s));
+            SEA_HIP_CHECK(ctx, launch_face_corr(a, s));
+        }
         SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
         timer_off(SEA_STAGE_BOUNDARY);
         if (a.x_nonzero) {
             timer_on(SEA_STAGE_GUESS);
-            if (ctx->opts.start == SEA_START_SPECTRAL)
-                SEA_HIP_CHECK(ctx, launch_me_shell(a, nz_max, s));
-            else
-                SEA_HIP_CHECK(ctx, launch_me_guess(a, s));
+            if (!spectral) SEA_HIP_CHECK(ctx, launch_me_guess(a, s));
             if (ctx->opts.start == SEA_START_LEARNED) {
                 float* x32 = (float*)(base + Ly.nnx);
                 float* y32 = (float*)(base + Ly.nny);
@@ -559,26 +571,24 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                 }
                 SEA_HIP_CHECK(ctx, launch_nn_apply(a, kNnGrid, y32, s));
             }
-            if (ctx->opts.start == SEA_START_SPECTRAL) {
-                // bres = b - A x0; x += the sine-transform correction; bres = b - A x
-                int ncol_max = 1;
-                for (const auto& p : S.pairs)
-                    if (p.n[0] <= 64 && p.n[1] <= 64 && p.n[2] <= 64) {
-                        const int m = std::max(p.n[0] * p.n[1], std::max(p.n[1] * p.n[2], p.n[0] * p.n[2]));
-                        ncol_max = std::max(ncol_max, m);
-                    }
-                const bool rzm = zm && residual_zm_lds_bytes() <= ctx->max_lds;
-                ExxArgs ar = a;
-                ar.rnorm = rzm ? (double*)(base + Ly.rnorm) : nullptr;
-                auto residual = [&]() { return rzm ? launch_residual_zm(ar, s) : launch_start_residual(a, s); };
-                SEA_HIP_CHECK(ctx, residual());
-                SEA_HIP_CHECK(ctx, launch_spectral_start(a, ncol_max, a.bres, (double*)(base + Ly.dst_tmp),
+            if (spectral) {
+                // x = A_odd^-1 (b - D x0); then, for the FP32 z-march, bres = b - A x
+                // on the face points and the norms (the FP64 kernel forms its
+                // residual itself)
+                SEA_HIP_CHECK(ctx, launch_spectral_start(a, a.bres, (double*)(base + Ly.dst_tmp),
                                                          (double*)(base + Ly.dst_tab), (double*)(base + Ly.dst_mu), s,
                                                          [&](bool begin) {
                                                              if (begin) timer_on(SEA_STAGE_DST);
                                                              else timer_off(SEA_STAGE_DST);
                                                          }));
-                SEA_HIP_CHECK(ctx, residual());
+                if (zm) {
+                    ExxArgs ar = a;
+                    ar.rnorm = (double*)(base + Ly.rnorm);
+                    ar.skip_spectral = 1;
+                    SEA_HIP_CHECK(ctx, launch_face_residual(ar, s));
+                    const bool rzm = residual_zm_lds_bytes() <= ctx->max_lds;
+                    SEA_HIP_CHECK(ctx, rzm ? launch_residual_zm(ar, s) : launch_start_residual(ar, s));
+                }
             } else if (!zm) {
                 SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
             }
@@ -588,7 +598,9 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         if (zm) {
             const int var = ctx->opts.cg_variant >= 0 ? ctx->opts.cg_variant : (ctx->cg_tuned >= 0 ? ctx->cg_tuned : 0);
             ExxArgs az = a;
-            az.start_res = ctx->opts.start == SEA_START_SPECTRAL ? 1 : 0;
+            // spectral start: bres holds b - A x on the face points of the pairs the
+            // transform took (zero elsewhere), and everywhere for the others
+            az.start_res = ctx->opts.start == SEA_START_SPECTRAL ? 2 : 0;
             az.rnorm = (az.start_res && residual_zm_lds_bytes() <= ctx->max_lds) ? (double*)(base + Ly.rnorm) : nullptr;
             SEA_HIP_CHECK(ctx, launch_cg_zm(az, var, s));
             timer_off(SEA_STAGE_CG);

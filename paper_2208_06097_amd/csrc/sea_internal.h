@@ -59,7 +59,7 @@ struct StageTimer {
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
     size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, slots, stats, csr_off, csr_ent, scal, counter;
-    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, total;
+    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, x0, fnorm, total;
     int nmax;
     int n_chunks;
     int n_zchunks;
@@ -98,6 +98,10 @@ struct ExxArgs {
     double* racah_tab;    // SEA_NMOM x 84 monomial coefficients of the Racah harmonics
     double* mom;          // n_pairs x SEA_NACC (Racah moments, dV applied)
     double* b;            // n_pairs x stride
+    double* x0;           // spectral start: the multipole start on the points within 5 of a face (nullable)
+    double* fcorr;        // spectral start: -D x0 on the face points (the transform's scratch array)
+    double* fnorm;        // spectral start: n_pairs x fnorm_parts(fn_gy) partial sums of |b|^2 and |r|^2
+    int fn_gy;            // workgroups per axis launch of the face kernels
     double* v;            // n_pairs x stride
     size_t stride;
     double* slots;        // n_slots x 3 x slot_stride elements (state precision)
@@ -112,7 +116,9 @@ struct ExxArgs {
     const int* order;     // CG queue order: pair ids by decreasing domain size (nullable)
     const int* dbox;      // per pair 12 ints: boxes where W_i and W_j take the pair
     int x_nonzero;        // v holds a start guess on entry to the CG
-    int start_res;        // FP32 z-march: bres already holds b - A x in FP64 (x kept as the FP64 start)
+    int start_res;        // FP32 z-march: bres already holds b - A x in FP64 (x kept as the FP64 start);
+                          // 2: only on the face points (near_face on some axis), zero elsewhere
+    int skip_spectral;    // residual kernels: leave out the pairs the sine transform took
     double* rnorm;        // n_pairs x RZ_TILES x 2: |b|^2, |b - A x|^2 per row tile of the FP64 residual z-march (nullable)
     double* bres;         // n_pairs x stride: b - A x0 when x_nonzero
     int nmax;             // largest domain extent over pairs and axes
@@ -163,8 +169,19 @@ hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s)
 hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s);
 hipError_t launch_cg(const ExxArgs& a, hipStream_t s);
 hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s);
-// the multipole start on the 6-point shell inside the faces, zero inside
-hipError_t launch_me_shell(const ExxArgs& a, int nz_max, hipStream_t s);
+// Spectral start (pairs with every axis <= 64): x0 on the points within 5 of
+// a face into a.x0; the full multipole start into x for the other pairs.
+hipError_t launch_me_face(const ExxArgs& a, int nz_max, hipStream_t s);
+// -D x0 into a.fcorr on the face points
+hipError_t launch_face_corr(const ExxArgs& a, hipStream_t s);
+// r = b - A x = -D (x - x0) into bres on the face points, |b|^2 and |r|^2
+// into a.rnorm, for the pairs the sine transform took
+hipError_t launch_face_residual(const ExxArgs& a, hipStream_t s);
+constexpr int DP_PG = 16;   // sine-transform workgroups per pair
+// face-kernel workgroups per axis launch (64 columns each), and partial
+// sums per pair in a.fnorm
+__host__ __device__ inline int face_gy(int nmax) { return (nmax * nmax + 63) / 64; }
+__host__ __device__ inline int fnorm_parts(int gy) { return DP_PG + 3 * gy; }
 hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s);
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s);
 hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
@@ -173,13 +190,20 @@ hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
 constexpr int RZ_TILES = 4;   // row tiles of 16 per pair in the residual z-march
 size_t residual_zm_lds_bytes();
 hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s);
-// Spectral start (k_dst.hip): x += correction from the residual r (overwritten;
-// tmp scratch of the same size); ncol_max = largest product of two axes.
+// Spectral start (k_dst.hip): x = A_odd^-1 (b + a.fcorr on the face points)
+// for the pairs with every axis <= 64 (a.fcorr is tmp, scratch of the pair
+// arrays' size; r scratch of the same size); |b|^2 partials into a.fnorm.
 size_t dst_table_doubles();
 size_t dst_mu_doubles();
-// `mark(true)` / `mark(false)` bracket the six transform passes (stage timing).
-hipError_t launch_spectral_start(const ExxArgs& a, int ncol_max, double* r, double* tmp, double* tab, double* mu,
-                                 hipStream_t s, const std::function<void(bool)>& mark);
+// `mark(true)` / `mark(false)` bracket the three transform passes (stage timing).
+hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, hipStream_t s,
+                                 const std::function<void(bool)>& mark);
+// the pairs the sine transform takes
+__host__ __device__ inline bool spectral_pair(const sea_pair& P) { return P.n[0] <= 64 && P.n[1] <= 64 && P.n[2] <= 64; }
+// points next to a face that the difference of the zero and the odd
+// continuations of the stencil reaches (index i of an axis of n points)
+constexpr int FF_W = 5;
+__host__ __device__ inline bool near_face(int i, int n) { return i < FF_W || i >= n - FF_W; }
 // z-marching CG (k_cg.hip): needs every pair with n[0], n[1] <= 64.
 bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h);
 size_t cg_zm_lds_bytes(int state_f32);
