@@ -147,3 +147,61 @@ def test_spectral_batched_equals_per_cell():
         assert np.array_equal(s1, stats[off:off + len(pairs)])
         off += len(pairs)
     ctx.close()
+
+
+def _same_pairs(opairs, pairs):
+    assert np.array_equal(opairs.ij[:, 0], pairs["i"]) and np.array_equal(opairs.ij[:, 1], pairs["j"])
+    assert np.array_equal(opairs.lo, pairs["lo"]) and np.array_equal(opairs.n, pairs["n"])
+
+
+def _oracle_true_residual(cell, opairs, k, v):
+    """|b - A v| / |b| of pair k by the oracle's own right-hand side (its
+    multipole boundary values) and stencil: its CG with no iterations."""
+    _, _, info = oracle.pair_potential(cell.phi, cell.N, cell.L, opairs, k, tol=0.0, max_iter=0,
+                                       x0=np.ascontiguousarray(v))
+    return info["rel_res"]
+
+
+def test_face_residual_matches_stencil_residual(mini):
+    """FP32 state, a tolerance every start meets: every pair stops at the
+    spectral start, and the residual the GPU reports (formed on the face
+    points only, as -D (x - x0)) must be the stencil residual of the
+    potential it returns."""
+    cell, _, pairs = mini
+    opairs = oracle.build_pairs(cell.N, cell.L, cell.centres, 6.0, 4.0)
+    _same_pairs(opairs, pairs)
+    ctx = _ctx(rel_tol=0.5, stencil_dtype=sea.SEA_F32, start=sea.SEA_START_SPECTRAL)
+    v, _, _, stats, st = ctx.pair_solve(torch.from_numpy(cell.phi).cuda(), cell.N, cell.L, pairs)
+    assert st == sea.SEA_OK and np.all(stats["iters"] == 0)
+    v = v.cpu().numpy()
+    ks = np.random.default_rng(3).choice(len(pairs), size=min(10, len(pairs)), replace=False)
+    for k in ks:
+        n = pairs["n"][k]
+        vk = v[k, :n[0] * n[1] * n[2]].reshape(n[2], n[1], n[0])
+        want = _oracle_true_residual(cell, opairs, k, vk)
+        got = float(stats["rel_res"][k])
+        print(f"pair {k}: reported {got:.4e} stencil {want:.4e}", flush=True)
+        assert abs(got - want) <= 0.02 * want + 1e-12
+    ctx.close()
+
+
+def test_cg_continues_from_the_face_residual(mini):
+    """FP32 state, tight tolerance: the CG starts from the face-points-only
+    residual and must reach the target in the oracle's stencil residual."""
+    cell, _, pairs = mini
+    opairs = oracle.build_pairs(cell.N, cell.L, cell.centres, 6.0, 4.0)
+    _same_pairs(opairs, pairs)
+    tol = 1e-10
+    ctx = _ctx(rel_tol=tol, stencil_dtype=sea.SEA_F32, start=sea.SEA_START_SPECTRAL)
+    v, _, _, stats, st = ctx.pair_solve(torch.from_numpy(cell.phi).cuda(), cell.N, cell.L, pairs)
+    assert st == sea.SEA_OK and np.all(stats["converged"] == 1)
+    print(f"iterations mean {stats['iters'].mean():.2f} max {stats['iters'].max()}", flush=True)
+    assert stats["iters"].max() > 0
+    v = v.cpu().numpy()
+    for k in np.random.default_rng(4).choice(len(pairs), size=min(6, len(pairs)), replace=False):
+        n = pairs["n"][k]
+        vk = v[k, :n[0] * n[1] * n[2]].reshape(n[2], n[1], n[0])
+        want = _oracle_true_residual(cell, opairs, k, vk)
+        print(f"pair {k}: iters {stats['iters'][k]} stencil residual {want:.3e}", flush=True)
+        assert want <= 1.5 * tol
+    ctx.close()
