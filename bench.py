@@ -32,6 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+# ACE in the timed step: M = Phi^T W, its Cholesky and the energy in FP64,
+# xi and K psi on the matrix cores in FP32 (FP32 accumulation)
+ACE_DTYPE_NAME = "f32"
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2208_06097_amd", "weights", "unet_f32cg.npy")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "c2.json")
 
@@ -91,7 +95,8 @@ FORMS = {
 
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 CG_PROFILE = os.path.join(PROFILES, "k_cg_zm_buf_xc_learned_c2.md")
-DST_PROFILE = os.path.join(PROFILES, "k_dst_mfma_spectral_c2.md")
+DST_PROFILE = os.path.join(PROFILES, "k_dst_spectral_c2.md")
+SCATTER_PROFILE = os.path.join(PROFILES, "k_scatter_spectral_c2.md")
 
 
 def measured_traffic(path, **match):
@@ -184,6 +189,7 @@ def main():
         start = {"zero": sea.SEA_START_ZERO, "multipole": sea.SEA_START_MULTIPOLE,
                  "learned": sea.SEA_START_LEARNED, "spectral": sea.SEA_START_SPECTRAL}[f["start"]]
         c = sea.Context(rel_tol=args.tol, profile=True, start=start,
+                        ace_dtype={"f64": sea.SEA_F64, "f32": sea.SEA_F32}[ACE_DTYPE_NAME],
                         stencil_dtype=sea.SEA_F32 if f["stencil"] == "f32" else sea.SEA_F64)
         if f["start"] == "learned":
             c._nn = c.nn_state(np.load(args.weights))
@@ -213,10 +219,12 @@ def main():
     if tune and tune["ms"]:
         log(f"autotune: {tune['variant']}  " + "  ".join(f"{k} {v:.1f} ms" for k, v in tune["ms"].items()))
 
+    psi_step = psi.float()
+
     def step(host=False):
         r = ctx.exx_action(phi, cell.N, cell.L, pairs, ws=ws, W=W, exx_dev=exx_dev, want_host=host)
         M, Lm, xi, fp = ctx.ace_build(phi, W, dV, ws=ws_ace)
-        Kpsi = ctx.ace_apply(xi, psi, dV, ws=ws_ace)
+        Kpsi = ctx.ace_apply(xi, psi_step, dV, ws=ws_ace)
         E_ace = ctx.ace_energy(phi, xi, dV, ws=ws_ace)
         return r, E_ace, Kpsi
 
@@ -260,17 +268,29 @@ def main():
     vxx_ms = float(np.median(vxx_steps))   # median over the timed steps (HIP events per stage)
     wbytes = 4.0 if FORMS[form]["stencil"] == "f32" else 8.0
     npts = np.prod(pairs["n"].astype(np.float64), axis=1)
+    # owner-computes scatter: per pair side (one for i == j) the potential and
+    # the partner orbital are read once at every domain point (FP64 each),
+    # and W is written once
+    sides = np.where(pairs["i"] == pairs["j"], 1.0, 2.0)
+    scatter_bytes = float(np.sum(sides * npts) * 16.0 + cell.n_occ * cell.N ** 3 * 8.0)
+    tf = np.all(pairs["n"] <= 64, axis=1)
+    dst = {"kernels": "k_dst_plane (forward), k_dst_zline, k_dst_plane (inverse)", "launches_per_action": 3,
+           "launch_ms": stages["dst"] / 3.0,
+           "bytes": float(np.sum(npts[tf]) * 16.0),
+           "flops": float(np.sum(npts[tf] * 2.0 * pairs["n"][tf].sum(axis=1))),
+           "per_unit": "per pass 16 B (one FP64 read and write) per pair-domain point; per point n_axis flops "
+                       "for each transform along an axis (the even/odd-folded sine product), forward and "
+                       "inverse along all three",
+           "traffic": measured_traffic(DST_PROFILE, form=form, n_pairs=n_pairs)}
+    dst["achieved_gbs"] = dst["bytes"] / (dst["launch_ms"] * 1e-3) / 1e9 if dst["launch_ms"] > 0 else None
+    dst["fp64_tflops"] = dst["flops"] / (3.0 * dst["launch_ms"] * 1e-3) / 1e12 if dst["launch_ms"] > 0 else None
     if FORMS[form]["start"] == "spectral":
-        # dominant kernel: the sine-transform pass (six launches per action);
-        # per launch every transformable pair's array is read and written once
-        # in FP64, 2 x axis length flops per point
-        tf = np.all(pairs["n"] <= 64, axis=1)
-        roof = {"kernel": "k_dst_mfma", "launches_per_action": 6,
-                "launch_ms": stages["dst"] / 6.0,
-                "bytes": float(np.sum(npts[tf]) * 16.0),
-                "flops": float(np.sum(npts[tf] * 2.0 * pairs["n"][tf].mean(axis=1))),
-                "per_unit": "16 B (one FP64 read and write) and 2 n_axis flops per pair-domain point per pass",
-                "traffic": measured_traffic(DST_PROFILE, form=form, n_pairs=n_pairs)}
+        # dominant kernel: the scatter (the start leaves the CG nothing to do)
+        roof = {"kernel": "k_scatter", "launches_per_action": 1, "launch_ms": stages["scatter"],
+                "bytes": scatter_bytes, "flops": None,
+                "per_unit": "per pair side 16 B (v and the partner orbital, FP64) per domain point, plus 8 B per "
+                            "W element written",
+                "traffic": measured_traffic(SCATTER_PROFILE, form=form, n_pairs=n_pairs)}
     else:
         roof = {"kernel": "k_cg_zm<float>" if FORMS[form]["stencil"] == "f32" else "k_cg_f64",
                 "launches_per_action": 1, "launch_ms": stages["cg"],
@@ -278,6 +298,13 @@ def main():
                 "per_unit": f"6 words x {int(wbytes)} B per interior point per CG iteration",
                 "traffic": measured_traffic(CG_PROFILE, cg_variant=tune["variant"] if tune else None, form=form,
                                             cg_iters_total=int(stats["iters"].sum()))}
+    # M = Phi^T W on the FP64 matrix cores: 2 N_grid N_occ^2 flops
+    ace_m_flops = 2.0 * cell.N ** 3 * cell.n_occ ** 2
+    ace_m = {"kernel": "k_nt_mfma<double> (M = Phi^T W)", "ms": stages["ace_m"], "flops": ace_m_flops,
+             "tflops": ace_m_flops / (stages["ace_m"] * 1e-3) / 1e12 if stages["ace_m"] > 0 else None,
+             "peak_tflops": FP64_MFMA_PEAK_TFLOPS}
+    if ace_m["tflops"]:
+        ace_m["frac"] = ace_m["tflops"] / FP64_MFMA_PEAK_TFLOPS
     achieved = roof["bytes"] / (roof["launch_ms"] * 1e-3) / 1e9 if roof["launch_ms"] > 0 else 0.0
     forms = {form: {"vxx_ms_per_call": vxx_ms, "cg_ms": stages["cg"], "guess_ms": stages["guess"],
                     "cg_iters_mean": float(stats["iters"].mean()), "E_xx": E, "E_ace": E_ace,
@@ -286,7 +313,7 @@ def main():
     # ACE precision sweep on this step's W: xi and K psi on the matrix cores in
     # FP32 and BF16 (M, Cholesky and energy stay FP64), errors vs the FP64 path
     # and E vs the oracle's E_xx
-    _, _, Kpsi64 = step_out
+    Kpsi64 = None
     ace = {}
     for name, adt, tdt in (("f64", sea.SEA_F64, torch.float64), ("f32", sea.SEA_F32, torch.float32),
                            ("bf16", sea.SEA_BF16, torch.bfloat16)):
@@ -298,7 +325,9 @@ def main():
         K_t = ca.ace_apply(xi_t, psi_t, dV, ws=ws_ace)
         E_t = ca.ace_energy(phi, xi_t, dV, ws=ws_ace)
         st_ms = ca.stage_times()
-        kerr = float(torch.linalg.vector_norm(K_t.double() - Kpsi64.double()) / torch.linalg.vector_norm(Kpsi64.double()))
+        if Kpsi64 is None:   # the first entry, FP64, is the reference
+            Kpsi64 = K_t.double().clone()
+        kerr = float(torch.linalg.vector_norm(K_t.double() - Kpsi64) / torch.linalg.vector_norm(Kpsi64))
         ace[name] = {"ms": {k: st_ms[k] for k in ("ace_m", "ace_chol", "ace_xi", "ace_apply")},
                      "E_ace": E_t, "dE_vs_oracle": (E_t - golden["E"]) if golden else None,
                      "Kpsi_rel_err_vs_f64": kerr}
@@ -423,11 +452,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if wbytes == 4.0 else "f64",
+        "dtype": "f32+f64" if (wbytes == 4.0 or ACE_DTYPE_NAME == "f32") else "f64",
         "data": "synthetic",
         "config": {"workload": "64-molecule water-like cell, 1.0 g/cm^3, L=23.5 bohr, 120^3 grid, 256 orbitals, "
-                               "63^3 pair domains, CG to a relative true FP64 residual; ACE (FP64) with K applied "
-                               "to 256 trial vectors",
+                               "63^3 pair domains, CG to a relative true FP64 residual; ACE with M and its "
+                               "Cholesky in FP64, xi and K psi in FP32 on the matrix cores, K applied to 256 trial "
+                               "vectors",
+                   "ace_dtype": ACE_DTYPE_NAME,
                    "form": form, "rel_tol": args.tol, "n_pairs": n_pairs,
                    "cg_variant": tune["variant"] if tune else "k_cg_f64 (generic FP64)",
                    "autotune_ms": tune["ms"] if tune else None,
@@ -439,13 +470,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": roof["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "launch_ms": roof["launch_ms"], "launches_per_action": roof["launches_per_action"],
-                     "fp64_tflops": (roof["flops"] / (roof["launch_ms"] * 1e-3) / 1e12
-                                     if roof["flops"] and roof["launch_ms"] > 0 else None),
-                     "fp64_peak_tflops": 78.6,
                      "traffic": roof["traffic"],
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes_per_launch": roof["bytes"],
-                     "per_unit": roof["per_unit"]},
+                     "per_unit": roof["per_unit"],
+                     "spectral_transform": dst if FORMS[form]["start"] == "spectral" else None,
+                     "ace_m": ace_m},
     }
     if rank == 0 and not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

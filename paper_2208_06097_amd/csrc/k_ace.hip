@@ -27,46 +27,113 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Left-looking Cholesky (lower, row-major) of A into L, one workgroup of 16
-// wavefronts: for column j, wavefront 0 forms the pivot from row j, then the
-// 16 wavefronts take the rows below it in turn, each row's dot product over
-// k < j split across the 64 lanes.  flag[0] = 1-based index of the first
-// non-positive pivot, 0 on success.
-__global__ __launch_bounds__(CH_BS) void k_cholesky(const double* __restrict__ A, int n, double* __restrict__ L,
-                                                    int* __restrict__ flag) {
-    __shared__ double piv;
+// Blocked right-looking Cholesky (lower, row-major) of A into L, in place
+// in L, blocks of CB: for each block column kb, one workgroup factors the
+// diagonal block in LDS (column by column), a grid of workgroups solves the
+// panel below it against that factor (a wavefront per row, forward
+// substitution with the row's entries on the lanes), and a grid of
+// 64 x 64 tiles subtracts the panel's rank-CB product from the lower
+// trailing matrix.  flag[0] = 1-based index of the first non-positive
+// pivot, 0 on success; every kernel stops once it is set.
+constexpr int CB = 64;
+
+__global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ A, int n, double* __restrict__ L,
+                                                   int* __restrict__ flag) {
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t == 0) flag[0] = 0;
+    if (t >= (size_t)n * n) return;
+    const int i = (int)(t / n), j = (int)(t % n);
+    L[t] = j <= i ? A[t] : 0.0;
+}
+
+__global__ __launch_bounds__(CH_BS) void k_chol_diag(int n, int kb, double* __restrict__ L, int* __restrict__ flag) {
+    __shared__ double D[CB][CB + 1];
     __shared__ int bad;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = threadIdx.x; t < n * n; t += CH_BS) L[t] = 0.0;
+    if (flag[0]) return;
+    const int nb = min(CB, n - kb);
+    for (int t = threadIdx.x; t < CB * CB; t += CH_BS) {
+        const int r = t / CB, c = t % CB;
+        D[r][c] = (r < nb && c <= r) ? L[(size_t)(kb + r) * n + kb + c] : 0.0;
+    }
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        if (wave == 0) {
-            double s = 0.0;
-            for (int k = lane; k < j; k += 64) s += L[(size_t)j * n + k] * L[(size_t)j * n + k];
-            s = wave_sum(s);
-            if (lane == 0) {
-                const double d = A[(size_t)j * n + j] - s;
-                if (d > 0.0) {
-                    piv = sqrt(d);
-                    L[(size_t)j * n + j] = piv;
-                } else {
-                    bad = j + 1;
-                }
-            }
+    for (int j = 0; j < nb; ++j) {
+        if (threadIdx.x == 0) {
+            const double d = D[j][j];
+            if (d > 0.0) D[j][j] = sqrt(d);
+            else bad = kb + j + 1;
         }
         __syncthreads();
         if (bad) break;
-        const double ljj = piv;
-        for (int i = j + 1 + wave; i < n; i += CH_BS / 64) {
-            double s = 0.0;
-            for (int k = lane; k < j; k += 64) s += L[(size_t)i * n + k] * L[(size_t)j * n + k];
-            s = wave_sum(s);
-            if (lane == 0) L[(size_t)i * n + j] = (A[(size_t)i * n + j] - s) / ljj;
+        const double djj = D[j][j];
+        for (int r = j + 1 + threadIdx.x; r < nb; r += CH_BS) D[r][j] /= djj;
+        __syncthreads();
+        const int m = nb - j - 1;   // trailing lower triangle of the block
+        for (int t = threadIdx.x; t < m * m; t += CH_BS) {
+            const int r = j + 1 + t / m, c = j + 1 + t % m;
+            if (c <= r) D[r][c] -= D[r][j] * D[c][j];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) flag[0] = bad;
+    if (bad) {
+        if (threadIdx.x == 0) flag[0] = bad;
+        return;
+    }
+    for (int t = threadIdx.x; t < nb * nb; t += CH_BS) {
+        const int r = t / nb, c = t % nb;
+        if (c <= r) L[(size_t)(kb + r) * n + kb + c] = D[r][c];
+    }
+}
+
+// rows kb + CB + 16 blockIdx.x + wave: L[i][kb..kb+CB) <- (that row) L11^-T
+__global__ __launch_bounds__(CH_BS) void k_chol_trsm(int n, int kb, double* __restrict__ L, const int* __restrict__ flag) {
+    __shared__ double D[CB][CB + 1];
+    if (flag[0]) return;
+    for (int t = threadIdx.x; t < CB * CB; t += CH_BS) {
+        const int r = t / CB, c = t % CB;
+        D[r][c] = c <= r ? L[(size_t)(kb + r) * n + kb + c] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = kb + CB + blockIdx.x * (CH_BS / 64) + wave;
+    if (i >= n) return;
+    double* row = L + (size_t)i * n + kb;
+    double a = row[lane];
+    for (int k = 0; k < CB; ++k) {
+        const double yk = __shfl(a, k, 64) / D[k][k];
+        if (lane == k) a = yk;
+        else if (lane > k) a -= D[lane][k] * yk;
+    }
+    row[lane] = a;
+}
+
+// lower 64 x 64 tiles (ti >= tc) of the trailing matrix from kb + CB on:
+// L[i][c] -= sum_m L[i][kb+m] L[c][kb+m]
+__global__ __launch_bounds__(256) void k_chol_syrk(int n, int kb, double* __restrict__ L, const int* __restrict__ flag) {
+    __shared__ double Pi[CB][CB + 1], Pc[CB][CB + 1];
+    if (flag[0]) return;
+    int ti = 0, rem = blockIdx.x;
+    while (rem > ti) {
+        rem -= ti + 1;
+        ++ti;
+    }
+    const int tc = rem;
+    const int r0 = kb + CB + ti * CB, c0 = kb + CB + tc * CB;
+    for (int t = threadIdx.x; t < CB * CB; t += 256) {
+        const int r = t / CB, m = t % CB;
+        Pi[r][m] = r0 + r < n ? L[(size_t)(r0 + r) * n + kb + m] : 0.0;
+        Pc[r][m] = c0 + r < n ? L[(size_t)(c0 + r) * n + kb + m] : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < CB * CB; t += 256) {
+        const int r = t / CB, c = t % CB;
+        const int i = r0 + r, j = c0 + c;
+        if (i >= n || j > i) continue;
+        double s = 0.0;
+#pragma unroll 8
+        for (int m = 0; m < CB; ++m) s += Pi[r][m] * Pc[c][m];
+        L[(size_t)i * n + j] -= s;
+    }
 }
 
 // X = L^{-1} (lower): workgroup c (one wavefront) forms column c by forward
@@ -237,7 +304,15 @@ hipError_t ace_symmetrize(const double* M, int n, double* Mb, hipStream_t s) {
 }
 
 hipError_t ace_cholesky(const double* A, int n, double* L, int* flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CH_BS), 0, s, A, n, L, flag);
+    hipLaunchKernelGGL(k_chol_init, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256), 0, s, A, n, L, flag);
+    for (int kb = 0; kb < n; kb += CB) {
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(CH_BS), 0, s, n, kb, L, flag);
+        const int m = n - kb - CB;
+        if (m <= 0) break;
+        hipLaunchKernelGGL(k_chol_trsm, dim3((m + CH_BS / 64 - 1) / (CH_BS / 64)), dim3(CH_BS), 0, s, n, kb, L, flag);
+        const int T = (m + CB - 1) / CB;
+        hipLaunchKernelGGL(k_chol_syrk, dim3(T * (T + 1) / 2), dim3(256), 0, s, n, kb, L, flag);
+    }
     return hipGetLastError();
 }
 

@@ -1,0 +1,179 @@
+// Owner-computes scatter of the exx action for gfx950 (Eq. 15): W_o(g) is
+// the sum over the pairs of orbital o, in pair order, of v_ij(g) times the
+// other orbital, with v_ij the pair potential inside the pair's domain and
+// its multipole expansion (Eq. 10) outside it; no atomics, so W is bitwise
+// reproducible.
+#include "exx_device.h"
+#include "harmonics.h"
+#include "sea_internal.h"
+
+namespace {
+
+// owner-computes scatter: W_o(g) = sum over o's pairs (pair order) of
+//    v_pair(g - lo) phi_other(g), every domain duplicate of g included.
+
+constexpr int SC_BS = 256;
+constexpr int SC_TX = 64, SC_TY = 4, SC_TZ = 8;
+constexpr int SC_MAXE = 512;
+
+__device__ __forceinline__ bool axis_hits(int t0, int T, int lo, int n, int N) {
+    if (n >= N) return true;
+    const int s = wrap_idx(t0 - lo, N);
+    return s < n || s + T > N;
+}
+
+// W gathered per (orbital, tile): every pair of the orbital whose W box
+// touches the tile adds v * phi_partner at the tile's points, in pair order.
+// The box is the pair's W box for this orbital's side (lo[3], n[3] in the
+// pair domain's unwrapped frame); inside the pair's domain v is the solution,
+// outside it the multipole potential of the pair (Eq. 10).
+template <int LM>
+__global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const int* __restrict__ off_all,
+                                                   const int2* __restrict__ ent) {
+    __shared__ int list[SC_MAXE];
+    __shared__ int cnt, wide;
+    const DevCell& C = a.cells[cell];
+    const int* off = off_all + C.csr_base;
+    double* __restrict__ W = C.W;
+    const int o = blockIdx.y;
+    const int tiles_x = (C.N[0] + SC_TX - 1) / SC_TX;
+    const int tiles_y = (C.N[1] + SC_TY - 1) / SC_TY;
+    const int t = blockIdx.x;
+    const int tx0 = (t % tiles_x) * SC_TX;
+    const int ty0 = ((t / tiles_x) % tiles_y) * SC_TY;
+    const int tz0 = (t / (tiles_x * tiles_y)) * SC_TZ;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int e0 = off[o], e1 = off[o + 1];
+    double acc[SC_TX * SC_TY * SC_TZ / SC_BS];
+#pragma unroll
+    for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) acc[k] = 0.0;
+    for (int c0 = e0; c0 < e1; c0 += SC_MAXE) {
+        const int c1 = min(e1, c0 + SC_MAXE);
+        // ordered compaction: thread 0 walks the entries (lists are short)
+        if (threadIdx.x == 0) {
+            int m = 0, nw = 0;
+            for (int e = c0; e < c1; ++e) {
+                const int pid = ent[e].x;
+                const int* D = a.dbox + 12 * (size_t)pid + (o == a.pairs[pid].i ? 0 : 6);
+                if (axis_hits(tx0, SC_TX, D[0], D[3], C.N[0]) && axis_hits(ty0, SC_TY, D[1], D[4], C.N[1]) &&
+                    axis_hits(tz0, SC_TZ, D[2], D[5], C.N[2])) {
+                    list[m++] = e;
+                    nw += (D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2]) ? 1 : 0;
+                }
+            }
+            cnt = m;
+            wide = nw;
+        }
+        __syncthreads();
+        const int m = cnt;
+        // fast path: this thread's column (gx, gy) and planes tz0 + k; a box no
+        // wider than the cell holds each grid point at most once, found from
+        // per-pair offsets by compare-and-subtract instead of modulo
+        static_assert(SC_TX == 64 && SC_TX * SC_TY == SC_BS, "one (x, y) column per thread");
+        const int gx = tx0 + (threadIdx.x & 63), gy = ty0 + (threadIdx.x >> 6);
+        const bool colin = gx < C.N[0] && gy < C.N[1];
+        for (int q = 0; q < m; ++q) {
+            const int2 en = ent[list[q]];
+            const sea_pair P = a.pairs[en.x];
+            const int* D = a.dbox + 12 * (size_t)en.x + (o == P.i ? 0 : 6);
+            if (D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2]) continue;   // general path below
+            // box coordinates of the tile corner (uniform), then of this column:
+            // gx < N keeps lx below 2N, so one subtraction wraps it
+            int lx = wrap_idx(tx0 - D[0], C.N[0]) + (threadIdx.x & 63);
+            int ly = wrap_idx(ty0 - D[1], C.N[1]) + (threadIdx.x >> 6);
+            lx -= (lx >= C.N[0]) ? C.N[0] : 0;
+            ly -= (ly >= C.N[1]) ? C.N[1] : 0;
+            if (!colin || lx >= D[3] || ly >= D[4]) continue;
+            const int lz0 = wrap_idx(tz0 - D[2], C.N[2]);
+            const int sx = D[0] + lx - P.lo[0], sy = D[1] + ly - P.lo[1];
+            const bool in_xy = sx >= 0 && sx < P.n[0] && sy >= 0 && sy < P.n[1];
+            const double* v = a.v + (size_t)en.x * a.stride;
+            const double* Q = a.mom + (size_t)en.x * SEA_NACC;
+            const size_t gcol = (size_t)gy * C.N[0] + gx;
+            const double* phj = nullptr;
+            const float* phj32 = nullptr;
+            if (C.phi_f32) phj32 = (const float*)C.phi + (size_t)en.y * C.Ng + gcol;
+            else phj = (const double*)C.phi + (size_t)en.y * C.Ng + gcol;
+            // all loads of the column's points first (independent, in flight
+            // together), then the multipole values of points outside the domain
+            double vv[SC_TZ], pv[SC_TZ];
+            int lzs[SC_TZ];
+            bool me[SC_TZ];
+#pragma unroll
+            for (int k = 0; k < SC_TZ; ++k) {
+                const int gz = tz0 + k;
+                int lz = lz0 + k;
+                lz -= (lz >= C.N[2]) ? C.N[2] : 0;
+                lzs[k] = lz;
+                const bool valid = gz < C.N[2] && lz < D[5];
+                const int sz = D[2] + lz - P.lo[2];
+                const bool inside = valid && in_xy && sz >= 0 && sz < P.n[2];
+                me[k] = valid && !inside;
+                const size_t go = (size_t)(valid ? gz : 0) * C.N[1] * C.N[0];
+                pv[k] = valid ? (C.phi_f32 ? (double)phj32[go] : phj[go]) : 0.0;
+                vv[k] = inside ? v[((size_t)sz * P.n[1] + sy) * P.n[0] + sx] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < SC_TZ; ++k)
+                if (me[k])
+                    vv[k] = racah_me_potential<LM>(Q, a.lmax, (D[0] + lx) * C.h[0] - P.origin[0],
+                                                   (D[1] + ly) * C.h[1] - P.origin[1],
+                                                   (D[2] + lzs[k]) * C.h[2] - P.origin[2]);
+#pragma unroll
+            for (int k = 0; k < SC_TZ; ++k) acc[k] += vv[k] * pv[k];
+        }
+        // general path: boxes wider than the cell (a grid point met several times)
+        if (wide)
+#pragma unroll
+        for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) {
+            const int lid = threadIdx.x + k * SC_BS;
+            const int gx = tx0 + lid % SC_TX, gy = ty0 + (lid / SC_TX) % SC_TY, gz = tz0 + lid / (SC_TX * SC_TY);
+            if (gx >= C.N[0] || gy >= C.N[1] || gz >= C.N[2]) continue;
+            const size_t g = ((size_t)gz * C.N[1] + gy) * C.N[0] + gx;
+            double s = acc[k];
+            for (int q = 0; q < m; ++q) {
+                const int2 en = ent[list[q]];
+                const sea_pair P = a.pairs[en.x];
+                const int* D = a.dbox + 12 * (size_t)en.x + (o == P.i ? 0 : 6);
+                if (!(D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2])) continue;   // fast path above
+                const double* v = a.v + (size_t)en.x * a.stride;
+                const double* Q = a.mom + (size_t)en.x * SEA_NACC;
+                const double ph = load_phi(C.phi, C.phi_f32, (size_t)en.y * C.Ng + g);
+                for (int lz = wrap_idx(gz - D[2], C.N[2]); lz < D[5]; lz += C.N[2])
+                    for (int ly = wrap_idx(gy - D[1], C.N[1]); ly < D[4]; ly += C.N[1])
+                        for (int lx = wrap_idx(gx - D[0], C.N[0]); lx < D[3]; lx += C.N[0]) {
+                            const int px = D[0] + lx, py = D[1] + ly, pz = D[2] + lz;  // unwrapped point
+                            const int sx = px - P.lo[0], sy = py - P.lo[1], sz = pz - P.lo[2];
+                            double val;
+                            if (sx >= 0 && sx < P.n[0] && sy >= 0 && sy < P.n[1] && sz >= 0 && sz < P.n[2])
+                                val = v[((size_t)sz * P.n[1] + sy) * P.n[0] + sx];
+                            else
+                                val = racah_me_potential<LM>(Q, a.lmax, px * C.h[0] - P.origin[0],
+                                                             py * C.h[1] - P.origin[1], pz * C.h[2] - P.origin[2]);
+                            s += val * ph;
+                        }
+            }
+            acc[k] = s;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) {
+        const int lid = threadIdx.x + k * SC_BS;
+        const int gx = tx0 + lid % SC_TX, gy = ty0 + (lid / SC_TX) % SC_TY, gz = tz0 + lid / (SC_TX * SC_TY);
+        if (gx >= C.N[0] || gy >= C.N[1] || gz >= C.N[2]) continue;
+        W[(size_t)o * C.Ng + ((size_t)gz * C.N[1] + gy) * C.N[0] + gx] = acc[k];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_scatter(const ExxArgs& a, int cell, const int* N, int n_occ, const int* csr_off, const int2* csr_ent,
+                          hipStream_t s) {
+    const int tiles = ((N[0] + SC_TX - 1) / SC_TX) * ((N[1] + SC_TY - 1) / SC_TY) * ((N[2] + SC_TZ - 1) / SC_TZ);
+    dim3 grid(tiles, n_occ);
+    hipLaunchKernelGGL(k_scatter<SEA_LMAX>, grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
+    return hipGetLastError();
+}
+

@@ -231,6 +231,31 @@ def test_ace_matrix_core_dtypes_multi_tile(dt):
     ctx.close()
 
 
+@pytest.mark.parametrize("n_occ", [64, 256, 300])
+def test_ace_cholesky_blocked_sizes(n_occ):
+    """The blocked Cholesky of M at a single block, at whole blocks and with a
+    ragged last block, against LAPACK's factor of the same M (FP64), and
+    the factor's product against M."""
+    print(f"case ace cholesky n_occ={n_occ}", flush=True)
+    rng = np.random.default_rng(n_occ)
+    N = 12
+    ng, dV = N ** 3, 0.25 ** 3
+    phi = rng.standard_normal((n_occ, ng)) / np.sqrt(ng * dV)
+    A = rng.standard_normal((n_occ, n_occ))
+    W = (A @ A.T / n_occ + np.eye(n_occ)) @ phi
+    ctx = sea.Context()
+    M, Lm, _, fp = ctx.ace_build(_dev(phi), _dev(W), dV)
+    assert fp == 0
+    Mh = M.cpu().numpy()
+    Mh = 0.5 * (Mh + Mh.T)
+    Lh = Lm.cpu().numpy()
+    want = np.linalg.cholesky(Mh)
+    assert np.max(np.abs(np.triu(Lh, 1))) == 0.0
+    assert np.max(np.abs(Lh - want)) <= 1e-11 * np.max(np.abs(want))
+    assert np.max(np.abs(Lh @ Lh.T - Mh)) <= 1e-12 * np.max(np.abs(Mh))
+    ctx.close()
+
+
 def test_ace_not_positive_definite(ctx, mini):
     cell, pl, ref, pairs = mini
     print("case ace not-PD", flush=True)
