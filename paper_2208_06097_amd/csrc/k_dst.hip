@@ -88,8 +88,7 @@ struct DstArgs {
     const double* opt;
     const double* mu;
     const double* add;    // plane pass: added to `in` on the face points (nullable)
-    double* bsum;         // plane pass: per workgroup sum of in^2 (nullable; stride fnorm_parts(fn_gy) per pair)
-    int fn_gy;
+    double* bsum;         // plane pass: per workgroup sum of in^2 (nullable; FN_PARTS per pair)
 };
 
 // Products on the FP64 matrix cores (v_mfma_f64_16x16x4f64), 4 waves per
@@ -264,7 +263,7 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
         if (threadIdx.x == 0) {
             double t = 0.0;
             for (int k = 0; k < DP_BS / 64; ++k) t += red[k];
-            d.bsum[(size_t)pid * fnorm_parts(d.fn_gy) + blockIdx.y] = t;
+            d.bsum[(size_t)pid * FN_PARTS + blockIdx.y] = t;
         }
     }
 }
@@ -399,7 +398,6 @@ hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, doubl
     d.stride = a.stride;
     d.opt = tab;
     d.mu = mu;
-    d.fn_gy = a.fn_gy;
     const dim3 grid((unsigned)a.n_pairs, DP_PG);
     mark(true);
     // planes forward: b + fcorr (in tmp) -> tmp; z lines forward, divided,

@@ -64,6 +64,16 @@ __host__ __device__ constexpr int mono_idx(int a, int b, int c) {
     for (int b2 = 0; b2 < b; ++b2) off += 7 - a - b2;
     return off + c;
 }
+// degree of the monomial at position t
+__host__ __device__ inline int mono_deg(int t) {
+    for (int a = 0; a <= 6; ++a)
+        for (int b = 0; b <= 6 - a; ++b) {
+            const int c = t - mono_idx(a, b, 0);
+            if (c >= 0 && c <= 6 - a - b) return a + b + c;
+        }
+    return -1;
+}
+
 // position of y^b z^c (b + c <= 6)
 __host__ __device__ constexpr int bc_idx(int b, int c) { return mono_idx(0, b, c); }
 
@@ -254,31 +264,126 @@ __global__ void k_moments_final(ExxArgs a, double* Q_orth) {
         M[t] = s;
     }
     __syncthreads();
-    if (k >= SEA_NACC) return;
-    double s;
-    if (k < SEA_NMOM) {
-        s = 0.0;
-        for (int t = 0; t < GC_NM; ++t) s += a.racah_tab[k * GC_NM + t] * M[t];
-    } else if (k == SEA_NMOM) {
-        s = M[GC_NM];                        // sum |rho|
-    } else if (k == SEA_NMOM + 1) {
-        s = M[0];                            // sum rho
-    } else {
-        s = M[GC_NM + 1];                    // sum |rho| r^2
+    __shared__ double Qs[SEA_NMOM];
+    if (k < SEA_NACC) {
+        double s;
+        if (k < SEA_NMOM) {
+            s = 0.0;
+            for (int t = 0; t < GC_NM; ++t) s += a.racah_tab[k * GC_NM + t] * M[t];
+        } else if (k == SEA_NMOM) {
+            s = M[GC_NM];                        // sum |rho|
+        } else if (k == SEA_NMOM + 1) {
+            s = M[0];                            // sum rho
+        } else {
+            s = M[GC_NM + 1];                    // sum |rho| r^2
+        }
+        s *= C.dV;
+        if (k < SEA_NMOM) {
+            int l = 0;
+            while ((l + 1) * (l + 1) <= k) ++l;
+            if (l > a.lmax) s = 0.0;
+            Qs[k] = s;
+        }
+        a.mom[(size_t)pid * SEA_NACC + k] = s;
+        if (Q_orth && k < SEA_NMOM) {
+            int l = 0;
+            while ((l + 1) * (l + 1) <= k) ++l;
+            const int m = k - l * l - l;
+            Q_orth[(size_t)pid * SEA_NMOM + k] = s * racah_to_orthonormal(l, m);
+        }
     }
-    s *= C.dV;
-    if (k < SEA_NMOM) {
-        int l = 0;
-        while ((l + 1) * (l + 1) <= k) ++l;
-        if (l > a.lmax) s = 0.0;
+    __syncthreads();
+    // the degree-l part of the multipole sum as a homogeneous polynomial:
+    // coefficient of monomial t (degree l) = sum over the harmonics of degree
+    // l of eps_m Q_lm times the harmonic's coefficient of t (eps_0 = 1, else 2)
+    for (int t = k; t < GC_NM; t += blockDim.x) {
+        const int l = mono_deg(t);
+        double c = 0.0;
+        for (int q = l * l; q < (l + 1) * (l + 1); ++q) c += (q == l * l + l ? 1.0 : 2.0) * Qs[q] * a.racah_tab[q * GC_NM + t];
+        a.mpoly[(size_t)pid * GC_NM + t] = c;
     }
-    a.mom[(size_t)pid * SEA_NACC + k] = s;
-    if (Q_orth && k < SEA_NMOM) {
-        int l = 0;
-        while ((l + 1) * (l + 1) <= k) ++l;
-        const int m = k - l * l - l;
-        Q_orth[(size_t)pid * SEA_NMOM + k] = s * racah_to_orthonormal(l, m);
+}
+
+// The multipole sum's homogeneous parts P_l(dx, dy, dz), l = 0..6, from the
+// pair's monomial coefficients cf (the same order as mono_idx).
+__device__ __forceinline__ void me_parts(const double* cf, double dx, double dy, double dz, double P[SEA_LMAX + 1]) {
+#pragma unroll
+    for (int l = 0; l <= SEA_LMAX; ++l) P[l] = 0.0;
+    double xa = 1.0;
+    int t = 0;
+#pragma unroll
+    for (int ea = 0; ea <= 6; ++ea) {
+        double yb = xa;
+#pragma unroll
+        for (int eb = 0; eb <= 6 - ea; ++eb) {
+            double mz = yb;
+#pragma unroll
+            for (int ec = 0; ec <= 6 - ea - eb; ++ec) {
+                P[ea + eb + ec] += cf[t++] * mz;
+                mz *= dz;
+            }
+            yb *= dy;
+        }
+        xa *= dx;
     }
+}
+
+// The multipole sum's parts along a line parallel to axis AX: with the
+// other two displacement components fixed (d[AX] is ignored), P_l(s) =
+// sum_{e <= l} q[l][e] s^e for the displacement s along AX.
+template <int AX>
+__device__ __forceinline__ void me_line_coeffs(const double* cf, const double d[3], double q[SEA_LMAX + 1][SEA_LMAX + 1]) {
+#pragma unroll
+    for (int l = 0; l <= SEA_LMAX; ++l)
+#pragma unroll
+        for (int e = 0; e <= SEA_LMAX; ++e) q[l][e] = 0.0;
+    double pw[3][7];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        pw[k][0] = 1.0;
+#pragma unroll
+        for (int e = 1; e <= 6; ++e) pw[k][e] = (k == AX) ? 1.0 : pw[k][e - 1] * d[k];
+    }
+    int t = 0;
+#pragma unroll
+    for (int ea = 0; ea <= 6; ++ea)
+#pragma unroll
+        for (int eb = 0; eb <= 6 - ea; ++eb)
+#pragma unroll
+            for (int ec = 0; ec <= 6 - ea - eb; ++ec) {
+                const int e = AX == 0 ? ea : (AX == 1 ? eb : ec);
+                q[ea + eb + ec][e] += cf[t++] * pw[0][ea] * pw[1][eb] * pw[2][ec];
+            }
+}
+
+// Multipole potential (Eq. 10) on the line: sum_l P_l(s) r^-(2l+1), r^2 = s^2 + rt2
+__device__ __forceinline__ double me_line_potential(const double q[SEA_LMAX + 1][SEA_LMAX + 1], double s, double rt2) {
+    const double rinv = 1.0 / sqrt(s * s + rt2), rinv2 = rinv * rinv;
+    double v = 0.0, pw = rinv;
+#pragma unroll
+    for (int l = 0; l <= SEA_LMAX; ++l) {
+        double p = q[l][l];
+#pragma unroll
+        for (int e = l - 1; e >= 0; --e) p = p * s + q[l][e];
+        v += p * pw;
+        pw *= rinv2;
+    }
+    return v;
+}
+
+// Multipole potential (Eq. 10) from the monomial coefficients: sum_l P_l r^-(2l+1)
+__device__ __forceinline__ double me_poly_potential(const double* cf, double dx, double dy, double dz) {
+    double P[SEA_LMAX + 1];
+    me_parts(cf, dx, dy, dz, P);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double rinv = 1.0 / sqrt(r2), rinv2 = rinv * rinv;
+    double v = 0.0, pw = rinv;
+#pragma unroll
+    for (int l = 0; l <= SEA_LMAX; ++l) {
+        v += P[l] * pw;
+        pw *= rinv2;
+    }
+    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -294,20 +399,24 @@ __global__ void k_moments_final(ExxArgs a, double* Q_orth) {
 // updates are coalesced; the x faces' targets are 6 contiguous points of a
 // row, so their updates go through LDS and out with a lane per target point.
 constexpr int GA_BS = 256;
-constexpr int FF_S = 2 * FF_W;   // face points of a column (all of it when n < 10)
-
-// slot j of a column's face points: index j (j < 5) or n - 10 + j; false
-// for slots that repeat an index or fall outside (n < 10)
-__device__ __forceinline__ bool face_slot(int j, int n, int& i) {
-    i = j < FF_W ? j : n - FF_S + j;
-    return i >= 0 && i < n && (j < FF_W || i >= FF_W);
-}
 
 // sum over the stencil taps of a column point i that fall past a face, of
 // c_k times the odd continuation (period 2 (n + 1), zeros at -1 and n) of
 // the column values val(index)
 template <typename F>
 __device__ __forceinline__ double face_taps(int i, int n, F&& val) {
+    if (n >= 2 * FF_W) {
+        // the faces apart: a tap past a face mirrors onto the same face, index
+        // d from the face taking -c_k val(k - d - 2) (d + 1 past the face is a
+        // zero of the continuation)
+        const bool low = i < FF_W;
+        const int d = low ? i : n - 1 - i;
+        double c = 0.0;
+#pragma unroll
+        for (int k = 2; k <= SEA_HALO; ++k)
+            if (k >= d + 2) c -= kC[k] * val(low ? k - d - 2 : n - 1 - (k - d - 2));
+        return c;
+    }
     auto ext = [&](int q) {
         const int per = 2 * (n + 1);
         while (q < -1) q += per;
@@ -324,46 +433,13 @@ __device__ __forceinline__ double face_taps(int i, int n, F&& val) {
     return c;
 }
 
-// All face slots of a column at once: out[j] = face_taps(index of slot j,
-// n, column values) for es[j] = the column value at slot j.  For n >= 10
-// the two faces are apart and a tap past a face mirrors onto the same face:
-// index d from the face takes -sum_{k >= d+2} c_k es[k - d - 2] (the point
-// at d + 1 past the face is a zero of the continuation), a fixed triangle.
-__device__ __forceinline__ void face_taps_all(int n, const double es[FF_S], double out[FF_S]) {
-    if (n >= FF_S) {
-#pragma unroll
-        for (int d = 0; d < FF_W; ++d) {
-            double lo = 0.0, hi = 0.0;
-#pragma unroll
-            for (int k = d + 2; k <= SEA_HALO; ++k) {
-                lo += kC[k] * es[k - d - 2];
-                hi += kC[k] * es[FF_S - 1 - (k - d - 2)];
-            }
-            out[d] = -lo;               // slot d: index d
-            out[FF_S - 1 - d] = -hi;    // slot 9 - d: index n - 1 - d
-        }
-        return;
-    }
-    auto val = [&](int q) {
-        const int jq = q < FF_W ? q : q - n + FF_S;
-        double e = 0.0;
-#pragma unroll
-        for (int j = 0; j < FF_S; ++j) e = j == jq ? es[j] : e;
-        return e;
-    };
-#pragma unroll
-    for (int j = 0; j < FF_S; ++j) {
-        int i;
-        out[j] = face_slot(j, n, i) ? face_taps(i, n, val) : 0.0;
-    }
-}
-
-template <int LM>
-__global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a, int ax) {
-    __shared__ double Q[SEA_NMOM];
+template <int AX>
+__global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
+    constexpr int ax = AX;
+    __shared__ double cf[GC_NM];
     __shared__ double tap[GA_BS][2 * SEA_HALO];
     const int pid = blockIdx.x;
-    if (threadIdx.x < SEA_NMOM) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
+    if (threadIdx.x < GC_NM) cf[threadIdx.x] = a.mpoly[(size_t)pid * GC_NM + threadIdx.x];
     __syncthreads();
     const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
@@ -386,14 +462,19 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a, int ax) {
         pos[u] = au;
         pos[v] = av;
         const size_t base = pos[u] * st[u] + pos[v] * st[v];
+        // the column's fixed displacements folded into line coefficients once
+        double dv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dv[k] = k == ax ? 0.0 : (P.lo[k] + pos[k]) * C.h[k] - P.origin[k];
+        double q[SEA_LMAX + 1][SEA_LMAX + 1];
+        me_line_coeffs<AX>(cf, dv, q);
+        const double rt2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
         for (int plus = 0; plus < 2; ++plus) {
             double g[SEA_HALO + 1];
 #pragma unroll
             for (int L = 1; L <= SEA_HALO; ++L) {
-                pos[ax] = plus ? n - 1 + L : -L;
-                g[L] = racah_me_potential<LM>(Q, a.lmax, (P.lo[0] + pos[0]) * C.h[0] - P.origin[0],
-                                              (P.lo[1] + pos[1]) * C.h[1] - P.origin[1],
-                                              (P.lo[2] + pos[2]) * C.h[2] - P.origin[2]);
+                const int pa = plus ? n - 1 + L : -L;
+                g[L] = me_line_potential(q, (P.lo[ax] + pa) * C.h[ax] - P.origin[ax], rt2);
             }
 #pragma unroll
             for (int d = 0; d < SEA_HALO; ++d) {
@@ -454,6 +535,33 @@ __device__ __forceinline__ double me_start_value(const double* Q, int lmax, doub
     return val;
 }
 
+// The same start value from the degree-l parts P_l of the multipole sum
+// (which replace the per-degree harmonic sums) at squared distance r2.
+__device__ __forceinline__ double me_start_from_parts(const double* Q, const double P[SEA_LMAX + 1], double r2) {
+    const double r2m = Q[SEA_NMOM] > 0.0 ? Q[SEA_NMOM + 2] / Q[SEA_NMOM] : 1.0;
+    const double rs = sqrt(fmax(2.0 * r2m / 3.0, 1e-6));
+    const double r = sqrt(r2);
+    if (r < 1e-12) return Q[0] * 2.0 / (rs * sqrt(kPi));
+    const double rinv = 1.0 / r, rinv2 = rinv * rinv;
+    const double damp = 1.0 - exp(-r2 / (rs * rs));
+    double val = Q[0] * erf(r / rs) * rinv;
+    double pw = rinv * rinv2, dl = damp;
+#pragma unroll
+    for (int l = 1; l <= SEA_LMAX; ++l) {
+        dl *= damp;
+        val += P[l] * pw * dl;
+        pw *= rinv2;
+    }
+    return val;
+}
+
+// ... from the pair's monomial coefficients cf
+__device__ __forceinline__ double me_start_poly(const double* cf, const double* Q, double dx, double dy, double dz) {
+    double P[SEA_LMAX + 1];
+    me_parts(cf, dx, dy, dz, P);
+    return me_start_from_parts(Q, P, dx * dx + dy * dy + dz * dz);
+}
+
 template <int LM>
 __global__ __launch_bounds__(GM_BS) void k_me_guess(ExxArgs a) {
     __shared__ double Q[SEA_NACC];
@@ -482,6 +590,8 @@ __global__ __launch_bounds__(GM_BS) void k_me_guess(ExxArgs a) {
 // (an axis beyond 64 points).  One workgroup per plane; the face points of
 // an inner plane (10 full rows and 10 points of every other row) are
 // enumerated densely.
+constexpr int FF_S = 2 * FF_W;   // face points of a line (all of it when n <= 10)
+
 template <typename F>
 __device__ __forceinline__ void for_face_points(int nx, int ny, int nz, int z, F&& f) {
     if (z < FF_W || z >= nz - FF_W || nx <= FF_S || ny <= FF_S) {
@@ -504,128 +614,121 @@ __device__ __forceinline__ void for_face_points(int nx, int ny, int nz, int z, F
     }
 }
 
-template <int LM>
-__global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
+// The whole multipole start on the planes of the pairs the sine transform
+// skips (an axis beyond 64 points).
+__global__ __launch_bounds__(GM_BS) void k_me_big(ExxArgs a) {
     __shared__ double Q[SEA_NACC];
+    __shared__ double cf[GC_NM];
     const int pid = blockIdx.x, z = blockIdx.y;
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    if (z >= nz) return;
+    if (z >= nz || spectral_pair(P)) return;
     if (threadIdx.x < SEA_NACC) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
+    if (threadIdx.x < GC_NM) cf[threadIdx.x] = a.mpoly[(size_t)pid * GC_NM + threadIdx.x];
     __syncthreads();
     const DevCell& C = a.cells[a.pair_cell[pid]];
     const double dz = (P.lo[2] + z) * C.h[2] - P.origin[2];
-    const bool sp = spectral_pair(P);
-    double* out = (sp ? a.x0 : a.v) + (size_t)pid * a.stride + (size_t)z * nx * ny;
-    auto put = [&](int xx, int yy) {
-        out[yy * nx + xx] = me_start_value<LM>(Q, a.lmax, (P.lo[0] + xx) * C.h[0] - P.origin[0],
-                                               (P.lo[1] + yy) * C.h[1] - P.origin[1], dz);
-    };
-    if (sp) {
-        for_face_points(nx, ny, nz, z, put);
-    } else {
-        for (int t = threadIdx.x; t < nx * ny; t += GM_BS) put(t % nx, t / nx);
-    }
+    double* x = a.v + (size_t)pid * a.stride + (size_t)z * nx * ny;
+    for (int t = threadIdx.x; t < nx * ny; t += GM_BS)
+        x[t] = me_start_poly(cf, Q, (P.lo[0] + t % nx) * C.h[0] - P.origin[0], (P.lo[1] + t / nx) * C.h[1] - P.origin[1],
+                             dz);
 }
 
-// The spectral start's two face quantities, one axis per launch.  D = A -
-// A_odd is the difference between the stencil with zero values past the
-// faces (A) and with the odd continuation the sine transform diagonalizes
-// (A_odd); per axis it lives on the 5 points next to each face and reads
-// values there only, i.e. on the same column along the axis.
+// Row tables: for the plane's rows y, the multipole sum's parts along x,
+// P_l(dx) = sum_{e <= l} qr[y][l (l + 1) / 2 + e] dx^e, the plane's dz and
+// the row's dy folded in once (28 coefficients a row).
+constexpr int ME_QL = (SEA_LMAX + 1) * (SEA_LMAX + 2) / 2;
+
+template <int LM>
+__global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
+    __shared__ double Q[SEA_NACC];
+    __shared__ double cf[GC_NM];
+    __shared__ double qr[64][ME_QL + 1];
+    const int pid = blockIdx.x, z = blockIdx.y;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    if (z >= nz || !spectral_pair(P)) return;
+    if (threadIdx.x < SEA_NACC) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
+    if (threadIdx.x < GC_NM) cf[threadIdx.x] = a.mpoly[(size_t)pid * GC_NM + threadIdx.x];
+    __syncthreads();
+    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const double dz = (P.lo[2] + z) * C.h[2] - P.origin[2];
+    if (threadIdx.x < ny) {   // one row a thread
+        const int y = threadIdx.x;
+        const double d[3] = {0.0, (P.lo[1] + y) * C.h[1] - P.origin[1], dz};
+        double q[SEA_LMAX + 1][SEA_LMAX + 1];
+        me_line_coeffs<0>(cf, d, q);
+#pragma unroll
+        for (int l = 0; l <= SEA_LMAX; ++l)
+#pragma unroll
+            for (int e = 0; e <= l; ++e) qr[y][l * (l + 1) / 2 + e] = q[l][e];
+    }
+    __syncthreads();
+    double* out = a.x0 + (size_t)pid * a.stride + (size_t)z * nx * ny;
+    for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
+        const double dx = (P.lo[0] + xx) * C.h[0] - P.origin[0];
+        const double dy = (P.lo[1] + yy) * C.h[1] - P.origin[1];
+        double Pl[SEA_LMAX + 1];
+#pragma unroll
+        for (int l = 0; l <= SEA_LMAX; ++l) {
+            double p = qr[yy][l * (l + 1) / 2 + l];
+#pragma unroll
+            for (int e = l - 1; e >= 0; --e) p = p * dx + qr[yy][l * (l + 1) / 2 + e];
+            Pl[l] = p;
+        }
+        out[yy * nx + xx] = me_start_from_parts(Q, Pl, dx * dx + dy * dy + dz * dz);
+    });
+}
+
+// The spectral start's two face quantities.  D = A - A_odd is the
+// difference between the stencil with zero values past the faces (A) and
+// with the odd continuation the sine transform diagonalizes (A_odd); per
+// axis it lives on the 5 points next to each face and reads values there
+// only, on the same line along the axis.
 //   res = 0: the right-hand-side correction -D x0 into a.fcorr, so that
 //            A_odd^-1 (b - D x0) = x0 + A_odd^-1 (b - A x0);
 //   res = 1: after the transform (A_odd x = b - D x0), the residual
 //            r = b - A x = -D (x - x0) into bres (up to the transform's
-//            rounding, the stencil residual), and the per-workgroup sums of
-//            r^2 over the points whose last axis this is into a.fnorm.
-// A point near several faces takes an assignment from its first axis and
-// additions from the others; off the face points the arrays are not
-// written (and not read).  A workgroup takes FA_C columns, one lane per
-// face point (the 10 of a column): the column's values meet in LDS.  Lanes
-// run along x, which for the x faces means along a column's face points and
-// otherwise across columns, so the loads and stores are coalesced.
-constexpr int FA_C = 64;
-
+//            rounding, the stencil residual), and per plane the sum of r^2
+//            into a.fnorm.
+// One workgroup per plane: the plane's face values (x0, or x - x0) meet in
+// LDS for the taps along x and y; on the planes next to a z face the taps
+// along z read their mirror planes directly.  Each face point is written
+// once with the sum over its axes; off the face points the arrays are not
+// written (and not read).
 template <int RES>
-__global__ __launch_bounds__(GA_BS) void k_face_axis(ExxArgs a, int ax) {
-    __shared__ double es[FA_C][FF_S + 1];
-    __shared__ double red[GA_BS / 64 + 1];
-    const int pid = blockIdx.x;
+__global__ __launch_bounds__(GM_BS) void k_face_plane(ExxArgs a) {
+    __shared__ double E[64][65];
+    __shared__ double red[GM_BS / 64 + 1];
+    const int pid = blockIdx.x, z = blockIdx.y;
     const sea_pair P = a.pairs[pid];
-    if (!spectral_pair(P)) return;
-    const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;
-    const int n = P.n[ax], nu = P.n[u];
-    const int ncol = nu * P.n[v];
-    const int c0 = blockIdx.y * FA_C;
-    if (c0 >= ncol) {
-        if (RES && threadIdx.x == 0) a.fnorm[(size_t)pid * fnorm_parts(a.fn_gy) + DP_PG + ax * a.fn_gy + blockIdx.y] = 0.0;
-        return;
-    }
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    if (!spectral_pair(P) || z >= nz) return;
     const DevCell& C = a.cells[a.pair_cell[pid]];
-    const double ih2 = 1.0 / (C.h[ax] * C.h[ax]);
-    const size_t st[3] = {1, (size_t)P.n[0], (size_t)P.n[0] * P.n[1]};
-    const size_t po = (size_t)pid * a.stride;
-    // face point t of the workgroup: column c0 + cl, slot j
-    auto point = [&](int t, int& cl, int& j) {
-        if (ax == 0) {
-            cl = t / FF_S;
-            j = t % FF_S;
-        } else {
-            j = t / FA_C;
-            cl = t % FA_C;
-        }
-    };
-    auto offset = [&](int cl, int i) {
-        const int c = c0 + cl;
-        return (size_t)(c % nu) * st[u] + (size_t)(c / nu) * st[v] + (size_t)i * st[ax];
-    };
-    for (int t = threadIdx.x; t < FA_C * FF_S; t += GA_BS) {
-        int cl, j, i;
-        point(t, cl, j);
-        double e = 0.0;
-        if (c0 + cl < ncol && face_slot(j, n, i)) {
-            const size_t o = po + offset(cl, i);
-            e = RES ? a.v[o] - a.x0[o] : a.x0[o];
-        }
-        es[cl][j] = e;
-    }
+    const double ihx = 1.0 / (C.h[0] * C.h[0]), ihy = 1.0 / (C.h[1] * C.h[1]), ihz = 1.0 / (C.h[2] * C.h[2]);
+    const size_t po = (size_t)pid * a.stride, npl = (size_t)nx * ny;
+    const double* x0 = a.x0 + po;
+    const double* x = a.v + po;
+    auto val = [&](size_t o) { return RES ? x[o] - x0[o] : x0[o]; };
+    const bool zf = near_face(z, nz);
+    for_face_points(nx, ny, nz, z, [&](int xx, int yy) { E[yy][xx] = val(z * npl + (size_t)yy * nx + xx); });
     __syncthreads();
     double rr = 0.0;
-    double* out = RES ? a.bres : a.fcorr;
-    for (int t = threadIdx.x; t < FA_C * FF_S; t += GA_BS) {
-        int cl, j, i;
-        point(t, cl, j);
-        if (c0 + cl >= ncol || !face_slot(j, n, i)) continue;
-        double cs;
-        if (n >= FF_S) {   // the faces apart: a fixed triangle on the slot's own face
-            const int d = j < FF_W ? j : FF_S - 1 - j;
-            double acc = 0.0;
-#pragma unroll
-            for (int k = 2; k <= SEA_HALO; ++k)
-                if (k >= d + 2) acc += kC[k] * es[cl][j < FF_W ? k - d - 2 : FF_S - 1 - (k - d - 2)];
-            cs = -acc;
-        } else {
-            cs = face_taps(i, n, [&](int q) { return es[cl][q < FF_W ? q : q - n + FF_S]; });
+    double* out = (RES ? a.bres : a.fcorr) + po;
+    for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
+        double t = 0.0;
+        if (near_face(xx, nx)) t += face_taps(xx, nx, [&](int q) { return E[yy][q]; }) * ihx;
+        if (near_face(yy, ny)) t += face_taps(yy, ny, [&](int q) { return E[q][xx]; }) * ihy;
+        if (zf) {
+            const size_t col = (size_t)yy * nx + xx;
+            t += face_taps(z, nz, [&](int q) { return val(q * npl + col); }) * ihz;
         }
-        const int c = c0 + cl, cu = c % nu, cv = c / nu;
-        // an earlier axis wrote this point where the column's own coordinates
-        // are near that axis's faces; a later one adds
-        bool earlier = false, later = false;
-        if (ax == 0) later = near_face(cu, P.n[1]) || near_face(cv, P.n[2]);   // column (y, z)
-        if (ax == 1) {                                                         // column (x, z)
-            earlier = near_face(cu, P.n[0]);
-            later = near_face(cv, P.n[2]);
-        }
-        if (ax == 2) earlier = near_face(cu, P.n[0]) || near_face(cv, P.n[1]); // column (x, y)
-        double* o = out + po + offset(cl, i);
-        const double w = (earlier ? *o : 0.0) - cs * ih2;
-        *o = w;
-        if (RES && !later) rr += w * w;
-    }
+        out[z * npl + (size_t)yy * nx + xx] = -t;
+        rr += t * t;
+    });
     if (RES) {
-        rr = block_sum<GA_BS>(rr, red);
-        if (threadIdx.x == 0) a.fnorm[(size_t)pid * fnorm_parts(a.fn_gy) + DP_PG + ax * a.fn_gy + blockIdx.y] = rr;
+        rr = block_sum<GM_BS>(rr, red);
+        if (threadIdx.x == 0) a.fnorm[(size_t)pid * FN_PARTS + DP_PG + z] = rr;
     }
 }
 
@@ -635,10 +738,10 @@ __global__ __launch_bounds__(GA_BS) void k_face_axis(ExxArgs a, int ax) {
 __global__ __launch_bounds__(64) void k_face_norms(ExxArgs a) {
     const int pid = blockIdx.x * 64 + threadIdx.x;
     if (pid >= a.n_pairs || !spectral_pair(a.pairs[pid])) return;
-    const double* f = a.fnorm + (size_t)pid * fnorm_parts(a.fn_gy);
+    const double* f = a.fnorm + (size_t)pid * FN_PARTS;
     double bb = 0.0, rr = 0.0;
     for (int k = 0; k < DP_PG; ++k) bb += f[k];
-    for (int k = 0; k < 3 * a.fn_gy; ++k) rr += f[DP_PG + k];
+    for (int k = 0; k < a.pairs[pid].n[2]; ++k) rr += f[DP_PG + k];
     for (int t = 0; t < RZ_TILES; ++t) {
         a.rnorm[((size_t)pid * RZ_TILES + t) * 2] = t == 0 ? bb : 0.0;
         a.rnorm[((size_t)pid * RZ_TILES + t) * 2 + 1] = t == 0 ? rr : 0.0;
@@ -927,12 +1030,10 @@ hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s)
 hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s) {
     (void)nz_max;
     const unsigned gy = (unsigned)(((long)a.nmax * a.nmax + GA_BS - 1) / GA_BS);
-    for (int ax = 0; ax < 3; ++ax) {
-        hipLaunchKernelGGL(k_ghost_axis<SEA_LMAX>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a, ax);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    hipLaunchKernelGGL(k_ghost_axis<0>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a);
+    hipLaunchKernelGGL(k_ghost_axis<1>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a);
+    hipLaunchKernelGGL(k_ghost_axis<2>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s) {
@@ -940,21 +1041,20 @@ hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_face_corr(const ExxArgs& a, hipStream_t s) {
-    const unsigned gy = (unsigned)a.fn_gy;
-    for (int ax = 0; ax < 3; ++ax) hipLaunchKernelGGL(k_face_axis<0>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a, ax);
+hipError_t launch_face_corr(const ExxArgs& a, int nz_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_face_plane<0>, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_face_residual(const ExxArgs& a, hipStream_t s) {
-    const unsigned gy = (unsigned)a.fn_gy;
-    for (int ax = 0; ax < 3; ++ax) hipLaunchKernelGGL(k_face_axis<1>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a, ax);
+hipError_t launch_face_residual(const ExxArgs& a, int nz_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_face_plane<1>, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
     hipLaunchKernelGGL(k_face_norms, dim3((a.n_pairs + 63) / 64), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_me_face(const ExxArgs& a, int nz_max, hipStream_t s) {
     hipLaunchKernelGGL(k_me_face<SEA_LMAX>, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
+    hipLaunchKernelGGL(k_me_big, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ namespace {
 
 constexpr int SC_BS = 256;
 constexpr int SC_TX = 64, SC_TY = 4, SC_TZ = 8;
-constexpr int SC_MAXE = 512;
+constexpr int SC_MAXE = 128;   // list entries per chunk
 
 __device__ __forceinline__ bool axis_hits(int t0, int T, int lo, int n, int N) {
     if (n >= N) return true;
@@ -31,6 +31,8 @@ template <int LM>
 __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const int* __restrict__ off_all,
                                                    const int2* __restrict__ ent) {
     __shared__ int list[SC_MAXE];
+    // per listed entry: pair, partner orbital, W box (lo, n), domain (lo, n), wide flag
+    __shared__ int meta[SC_MAXE][16];
     __shared__ int cnt, wide;
     const DevCell& C = a.cells[cell];
     const int* off = off_all + C.csr_base;
@@ -50,20 +52,47 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
     for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) acc[k] = 0.0;
     for (int c0 = e0; c0 < e1; c0 += SC_MAXE) {
         const int c1 = min(e1, c0 + SC_MAXE);
-        // ordered compaction: thread 0 walks the entries (lists are short)
-        if (threadIdx.x == 0) {
+        // ordered compaction by wavefront 0: lane k tests entry c0 + 64 s + k,
+        // hits keep their order through the ballot's prefix counts
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
             int m = 0, nw = 0;
-            for (int e = c0; e < c1; ++e) {
-                const int pid = ent[e].x;
-                const int* D = a.dbox + 12 * (size_t)pid + (o == a.pairs[pid].i ? 0 : 6);
-                if (axis_hits(tx0, SC_TX, D[0], D[3], C.N[0]) && axis_hits(ty0, SC_TY, D[1], D[4], C.N[1]) &&
-                    axis_hits(tz0, SC_TZ, D[2], D[5], C.N[2])) {
-                    list[m++] = e;
-                    nw += (D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2]) ? 1 : 0;
+            for (int b0 = c0; b0 < c1; b0 += 64) {
+                const int e = b0 + lane;
+                bool hit = false, wd = false;
+                if (e < c1) {
+                    const int pid = ent[e].x;
+                    const int* D = a.dbox + 12 * (size_t)pid + (o == a.pairs[pid].i ? 0 : 6);
+                    hit = axis_hits(tx0, SC_TX, D[0], D[3], C.N[0]) && axis_hits(ty0, SC_TY, D[1], D[4], C.N[1]) &&
+                          axis_hits(tz0, SC_TZ, D[2], D[5], C.N[2]);
+                    wd = hit && (D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2]);
                 }
+                const unsigned long long mask = __ballot(hit);
+                const unsigned long long below = lane ? (mask << (64 - lane)) : 0ull;
+                if (hit) {
+                    const int q = m + __popcll(below);
+                    const int2 en = ent[e];
+                    const sea_pair P = a.pairs[en.x];
+                    const int* D = a.dbox + 12 * (size_t)en.x + (o == P.i ? 0 : 6);
+                    list[q] = e;
+                    meta[q][0] = en.x;
+                    meta[q][1] = en.y;
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) meta[q][2 + d] = D[d];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        meta[q][8 + d] = P.lo[d];
+                        meta[q][11 + d] = P.n[d];
+                    }
+                    meta[q][14] = wd;
+                }
+                m += __popcll(mask);
+                nw += __popcll(__ballot(wd));
             }
-            cnt = m;
-            wide = nw;
+            if (lane == 0) {
+                cnt = m;
+                wide = nw;
+            }
         }
         __syncthreads();
         const int m = cnt;
@@ -74,10 +103,11 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
         const int gx = tx0 + (threadIdx.x & 63), gy = ty0 + (threadIdx.x >> 6);
         const bool colin = gx < C.N[0] && gy < C.N[1];
         for (int q = 0; q < m; ++q) {
-            const int2 en = ent[list[q]];
-            const sea_pair P = a.pairs[en.x];
-            const int* D = a.dbox + 12 * (size_t)en.x + (o == P.i ? 0 : 6);
-            if (D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2]) continue;   // general path below
+            if (meta[q][14]) continue;   // general path below
+            const int pid = meta[q][0], oth = meta[q][1];
+            const int* D = &meta[q][2];
+            const int plo[3] = {meta[q][8], meta[q][9], meta[q][10]};
+            const int pn[3] = {meta[q][11], meta[q][12], meta[q][13]};
             // box coordinates of the tile corner (uniform), then of this column:
             // gx < N keeps lx below 2N, so one subtraction wraps it
             int lx = wrap_idx(tx0 - D[0], C.N[0]) + (threadIdx.x & 63);
@@ -86,15 +116,14 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
             ly -= (ly >= C.N[1]) ? C.N[1] : 0;
             if (!colin || lx >= D[3] || ly >= D[4]) continue;
             const int lz0 = wrap_idx(tz0 - D[2], C.N[2]);
-            const int sx = D[0] + lx - P.lo[0], sy = D[1] + ly - P.lo[1];
-            const bool in_xy = sx >= 0 && sx < P.n[0] && sy >= 0 && sy < P.n[1];
-            const double* v = a.v + (size_t)en.x * a.stride;
-            const double* Q = a.mom + (size_t)en.x * SEA_NACC;
+            const int sx = D[0] + lx - plo[0], sy = D[1] + ly - plo[1];
+            const bool in_xy = sx >= 0 && sx < pn[0] && sy >= 0 && sy < pn[1];
+            const double* v = a.v + (size_t)pid * a.stride;
             const size_t gcol = (size_t)gy * C.N[0] + gx;
             const double* phj = nullptr;
             const float* phj32 = nullptr;
-            if (C.phi_f32) phj32 = (const float*)C.phi + (size_t)en.y * C.Ng + gcol;
-            else phj = (const double*)C.phi + (size_t)en.y * C.Ng + gcol;
+            if (C.phi_f32) phj32 = (const float*)C.phi + (size_t)oth * C.Ng + gcol;
+            else phj = (const double*)C.phi + (size_t)oth * C.Ng + gcol;
             // all loads of the column's points first (independent, in flight
             // together), then the multipole values of points outside the domain
             double vv[SC_TZ], pv[SC_TZ];
@@ -107,19 +136,26 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, int cell, const in
                 lz -= (lz >= C.N[2]) ? C.N[2] : 0;
                 lzs[k] = lz;
                 const bool valid = gz < C.N[2] && lz < D[5];
-                const int sz = D[2] + lz - P.lo[2];
-                const bool inside = valid && in_xy && sz >= 0 && sz < P.n[2];
+                const int sz = D[2] + lz - plo[2];
+                const bool inside = valid && in_xy && sz >= 0 && sz < pn[2];
                 me[k] = valid && !inside;
                 const size_t go = (size_t)(valid ? gz : 0) * C.N[1] * C.N[0];
                 pv[k] = valid ? (C.phi_f32 ? (double)phj32[go] : phj[go]) : 0.0;
-                vv[k] = inside ? v[((size_t)sz * P.n[1] + sy) * P.n[0] + sx] : 0.0;
+                vv[k] = inside ? v[((size_t)sz * pn[1] + sy) * pn[0] + sx] : 0.0;
             }
+            bool any_me = false;
 #pragma unroll
-            for (int k = 0; k < SC_TZ; ++k)
-                if (me[k])
-                    vv[k] = racah_me_potential<LM>(Q, a.lmax, (D[0] + lx) * C.h[0] - P.origin[0],
-                                                   (D[1] + ly) * C.h[1] - P.origin[1],
-                                                   (D[2] + lzs[k]) * C.h[2] - P.origin[2]);
+            for (int k = 0; k < SC_TZ; ++k) any_me |= me[k];
+            if (any_me) {   // the multipole value outside the domain (W boxes beyond it)
+                const double* Q = a.mom + (size_t)pid * SEA_NACC;
+                const double* org = a.pairs[pid].origin;
+#pragma unroll
+                for (int k = 0; k < SC_TZ; ++k)
+                    if (me[k])
+                        vv[k] = racah_me_potential<LM>(Q, a.lmax, (D[0] + lx) * C.h[0] - org[0],
+                                                       (D[1] + ly) * C.h[1] - org[1],
+                                                       (D[2] + lzs[k]) * C.h[2] - org[2]);
+            }
 #pragma unroll
             for (int k = 0; k < SC_TZ; ++k) acc[k] += vv[k] * pv[k];
         }

@@ -216,6 +216,7 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.cells = take(nc * sizeof(DevCell));
     L.partial = take(np * L.n_zchunks * GC_N * sizeof(double));
     L.racah_tab = take(GC_TAB * sizeof(double));
+    L.mpoly = take(np * 84 * sizeof(double));
     L.mom = take(np * SEA_NACC * sizeof(double));
     L.b = take(np * stride * sizeof(double));
     L.v = with_v ? take(np * stride * sizeof(double)) : 0;
@@ -230,7 +231,7 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.dst_mu = spectral ? take(dst_mu_doubles() * sizeof(double)) : 0;
     L.rnorm = spectral ? take(np * RZ_TILES * 2 * sizeof(double)) : 0;
     L.x0 = spectral ? take(np * stride * sizeof(double)) : 0;
-    L.fnorm = spectral ? take(np * fnorm_parts(face_gy(nmax)) * sizeof(double)) : 0;
+    L.fnorm = spectral ? take(np * FN_PARTS * sizeof(double)) : 0;
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
     L.csr_off = take((S.csr_off.size() + 1) * sizeof(int));
@@ -481,6 +482,7 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.n_chunks = Ly.n_chunks;
     a.n_zchunks = Ly.n_zchunks;
     a.racah_tab = (double*)(base + Ly.racah_tab);
+    a.mpoly = (double*)(base + Ly.mpoly);
     a.mom = (double*)(base + Ly.mom);
     a.b = (double*)(base + Ly.b);
     a.v = v_ext ? v_ext : (double*)(base + Ly.v);
@@ -501,7 +503,6 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.x0 = Ly.x0 ? (double*)(base + Ly.x0) : nullptr;
     a.fcorr = Ly.dst_tmp ? (double*)(base + Ly.dst_tmp) : nullptr;
     a.fnorm = Ly.fnorm ? (double*)(base + Ly.fnorm) : nullptr;
-    a.fn_gy = face_gy(Ly.nmax);
     a.nmax = Ly.nmax;
     return a;
 }
@@ -540,7 +541,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         // kernel's face correction reads
         if (spectral) {
             SEA_HIP_CHECK(ctx, launch_me_face(a, nz_max, s));
-            SEA_HIP_CHECK(ctx, launch_face_corr(a, s));
+            SEA_HIP_CHECK(ctx, launch_face_corr(a, nz_max, s));
         }
         SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
         timer_off(SEA_STAGE_BOUNDARY);
@@ -585,7 +586,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                     ExxArgs ar = a;
                     ar.rnorm = (double*)(base + Ly.rnorm);
                     ar.skip_spectral = 1;
-                    SEA_HIP_CHECK(ctx, launch_face_residual(ar, s));
+                    SEA_HIP_CHECK(ctx, launch_face_residual(ar, nz_max, s));
                     const bool rzm = residual_zm_lds_bytes() <= ctx->max_lds;
                     SEA_HIP_CHECK(ctx, rzm ? launch_residual_zm(ar, s) : launch_start_residual(ar, s));
                 }

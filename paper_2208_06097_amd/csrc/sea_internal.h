@@ -59,7 +59,7 @@ struct StageTimer {
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
     size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, slots, stats, csr_off, csr_ent, scal, counter;
-    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, x0, fnorm, total;
+    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, x0, fnorm, mpoly, total;
     int nmax;
     int n_chunks;
     int n_zchunks;
@@ -96,12 +96,12 @@ struct ExxArgs {
     int n_chunks;         // point chunks of GM_CHUNK (start-guess and network kernels)
     int n_zchunks;        // plane chunks of GC_ZC (moment gather)
     double* racah_tab;    // SEA_NMOM x 84 monomial coefficients of the Racah harmonics
+    double* mpoly;        // n_pairs x 84: the multipole sum's monomial coefficients per pair
     double* mom;          // n_pairs x SEA_NACC (Racah moments, dV applied)
     double* b;            // n_pairs x stride
     double* x0;           // spectral start: the multipole start on the points within 5 of a face (nullable)
     double* fcorr;        // spectral start: -D x0 on the face points (the transform's scratch array)
-    double* fnorm;        // spectral start: n_pairs x fnorm_parts(fn_gy) partial sums of |b|^2 and |r|^2
-    int fn_gy;            // workgroups per axis launch of the face kernels
+    double* fnorm;        // spectral start: n_pairs x FN_PARTS partial sums of |b|^2 and |r|^2
     double* v;            // n_pairs x stride
     size_t stride;
     double* slots;        // n_slots x 3 x slot_stride elements (state precision)
@@ -173,15 +173,14 @@ hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s);
 // a face into a.x0; the full multipole start into x for the other pairs.
 hipError_t launch_me_face(const ExxArgs& a, int nz_max, hipStream_t s);
 // -D x0 into a.fcorr on the face points
-hipError_t launch_face_corr(const ExxArgs& a, hipStream_t s);
+hipError_t launch_face_corr(const ExxArgs& a, int nz_max, hipStream_t s);
 // r = b - A x = -D (x - x0) into bres on the face points, |b|^2 and |r|^2
 // into a.rnorm, for the pairs the sine transform took
-hipError_t launch_face_residual(const ExxArgs& a, hipStream_t s);
+hipError_t launch_face_residual(const ExxArgs& a, int nz_max, hipStream_t s);
 constexpr int DP_PG = 16;   // sine-transform workgroups per pair
-// face-kernel workgroups per axis launch (64 columns each), and partial
-// sums per pair in a.fnorm
-__host__ __device__ inline int face_gy(int nmax) { return (nmax * nmax + 63) / 64; }
-__host__ __device__ inline int fnorm_parts(int gy) { return DP_PG + 3 * gy; }
+// partial sums per pair in a.fnorm: |b|^2 per sine-transform workgroup,
+// then |r|^2 per plane (at most 64 planes for the pairs the transform takes)
+constexpr int FN_PARTS = DP_PG + 64;
 hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s);
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s);
 hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
