@@ -644,6 +644,7 @@ __global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
     __shared__ double Q[SEA_NACC];
     __shared__ double cf[GC_NM];
     __shared__ double qr[64][ME_QL + 1];
+    __shared__ double E[64][65];
     const int pid = blockIdx.x, z = blockIdx.y;
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
@@ -664,7 +665,7 @@ __global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
             for (int e = 0; e <= l; ++e) qr[y][l * (l + 1) / 2 + e] = q[l][e];
     }
     __syncthreads();
-    double* out = a.x0 + (size_t)pid * a.stride + (size_t)z * nx * ny;
+    const size_t zo = (size_t)pid * a.stride + (size_t)z * nx * ny;
     for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
         const double dx = (P.lo[0] + xx) * C.h[0] - P.origin[0];
         const double dy = (P.lo[1] + yy) * C.h[1] - P.origin[1];
@@ -676,8 +677,38 @@ __global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
             for (int e = l - 1; e >= 0; --e) p = p * dx + qr[yy][l * (l + 1) / 2 + e];
             Pl[l] = p;
         }
-        out[yy * nx + xx] = me_start_from_parts(Q, Pl, dx * dx + dy * dy + dz * dz);
+        const double v = me_start_from_parts(Q, Pl, dx * dx + dy * dy + dz * dz);
+        a.x0[zo + (size_t)yy * nx + xx] = v;
+        E[yy][xx] = v;
     });
+    __syncthreads();
+    // -D x0 along x and y (the taps along z, on the planes next to a z face,
+    // follow in k_face_z once every plane's x0 is there)
+    const double ihx = 1.0 / (C.h[0] * C.h[0]), ihy = 1.0 / (C.h[1] * C.h[1]);
+    for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
+        double t = 0.0;
+        if (near_face(xx, nx)) t += face_taps(xx, nx, [&](int q) { return E[yy][q]; }) * ihx;
+        if (near_face(yy, ny)) t += face_taps(yy, ny, [&](int q) { return E[q][xx]; }) * ihy;
+        a.fcorr[zo + (size_t)yy * nx + xx] = -t;
+    });
+}
+
+// -D x0 along z added on the planes next to a z face (one workgroup per such
+// plane: z = blockIdx.y for blockIdx.y < 5, nz - 10 + blockIdx.y above).
+__global__ __launch_bounds__(GM_BS) void k_face_z(ExxArgs a) {
+    const int pid = blockIdx.x;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    if (!spectral_pair(P)) return;
+    const int z = blockIdx.y < FF_W ? (int)blockIdx.y : nz - 2 * FF_W + (int)blockIdx.y;
+    if (z < 0 || z >= nz || (blockIdx.y >= FF_W && z < FF_W)) return;   // thin boxes: every plane once
+    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const double ihz = 1.0 / (C.h[2] * C.h[2]);
+    const size_t po = (size_t)pid * a.stride, npl = (size_t)nx * ny;
+    const double* x0 = a.x0 + po;
+    double* fc = a.fcorr + po;
+    for (int t = threadIdx.x; t < (int)npl; t += GM_BS)
+        fc[z * npl + t] -= face_taps(z, nz, [&](int q) { return x0[q * npl + t]; }) * ihz;
 }
 
 // The spectral start's two face quantities.  D = A - A_odd is the
@@ -1042,7 +1073,8 @@ hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_face_corr(const ExxArgs& a, int nz_max, hipStream_t s) {
-    hipLaunchKernelGGL(k_face_plane<0>, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
+    (void)nz_max;
+    hipLaunchKernelGGL(k_face_z, dim3(a.n_pairs, 2 * FF_W), dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }
 
