@@ -93,9 +93,10 @@ def main():
             per_cell.append({"cell": k, "density": float(dens[k]), "N": c.N, "L": c.L, "pairs": len(pairs),
                              "E_xx": float(e), "iters_mean": float(s["iters"].mean()),
                              "converged": bool(np.all(s["converged"] == 1))})
+        free_b, total_b = torch.cuda.mem_get_info()
         log(f"group {g0 // args.group}: cells {grp[0]}..{grp[-1]}, {n_pairs} pairs, {t_ms:.1f} ms "
             f"({n_pairs / t_ms * 1e3:.0f} pairs/s), iters {stats['iters'].mean():.1f}, status {st}, "
-            f"inputs {t_gen:.1f} s")
+            f"inputs {t_gen:.1f} s, device memory free {free_b / 2**30:.0f} of {total_b / 2**30:.0f} GiB")
         plan.close()
         del plan, cells, tensors
         torch.cuda.empty_cache()

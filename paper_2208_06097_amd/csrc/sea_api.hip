@@ -329,12 +329,6 @@ sea_status sea_create(const sea_opts* opts, sea_ctx** out) {
     for (int k = 0; k < SEA_STAGE_COUNT; ++k)
         for (int e = 0; e < 2; ++e) ok = ok && hipEventCreate(&ctx->ev[k][e]) == hipSuccess;
     ctx->ev_ready = ok;
-    bool sok = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) == hipSuccess;
-    for (int k = 0; k < 2; ++k) {
-        sok = sok && hipEventCreateWithFlags(&ctx->fork[k], hipEventDisableTiming) == hipSuccess;
-        sok = sok && hipEventCreateWithFlags(&ctx->join[k], hipEventDisableTiming) == hipSuccess;
-    }
-    ctx->side_ready = sok;
     *out = ctx;
     return SEA_OK;
 }
@@ -343,16 +337,7 @@ sea_status sea_destroy(sea_ctx* ctx) {
     if (ctx && ctx->ev_ready)
         for (int k = 0; k < SEA_STAGE_COUNT; ++k)
             for (int e = 0; e < 2; ++e) hipEventDestroy(ctx->ev[k][e]);
-    if (ctx) {
-        for (int k = 0; k < 2; ++k) {
-            if (ctx->fork[k]) hipEventDestroy(ctx->fork[k]);
-            if (ctx->join[k]) hipEventDestroy(ctx->join[k]);
-        }
-        if (ctx->side) {
-            (void)hipStreamSynchronize(ctx->side);
-            hipStreamDestroy(ctx->side);
-        }
-    }
+
     delete ctx;
     return SEA_OK;
 }
@@ -546,7 +531,6 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         return fail(ctx, SEA_E_ARG, "SEA_F32 state needs cubic grids and pair domains with n[0], n[1] <= 64");
     int nz_max = 1;
     for (const auto& p : S.pairs) nz_max = p.n[2] > nz_max ? p.n[2] : nz_max;
-    bool finish_pending = false;
     if (n_pairs > 0) {
         timer_on(SEA_STAGE_GATHER);
         SEA_HIP_CHECK(ctx, launch_gather_moments(a, s));
@@ -554,24 +538,12 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         timer_off(SEA_STAGE_GATHER);
         const bool spectral = ctx->opts.start == SEA_START_SPECTRAL;
         timer_on(SEA_STAGE_BOUNDARY);
-        // spectral start: x0 on the face points and -D x0 there, on the side
-        // stream while the boundary fold (vector-ALU bound) runs on this one
+        // spectral start: x0 on the face points and -D x0 there first
         if (spectral) {
-            hipStream_t fs = ctx->side_ready ? ctx->side : s;
-            if (fs != s) {
-                SEA_HIP_CHECK(ctx, hipEventRecord(ctx->fork[0], s));
-                SEA_HIP_CHECK(ctx, hipStreamWaitEvent(fs, ctx->fork[0], 0));
-            }
-            SEA_HIP_CHECK(ctx, launch_me_face(a, nz_max, fs));
-            SEA_HIP_CHECK(ctx, launch_face_corr(a, nz_max, fs));
-            SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
-            if (fs != s) {
-                SEA_HIP_CHECK(ctx, hipEventRecord(ctx->join[0], fs));
-                SEA_HIP_CHECK(ctx, hipStreamWaitEvent(s, ctx->join[0], 0));
-            }
-        } else {
-            SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
+            SEA_HIP_CHECK(ctx, launch_me_face(a, nz_max, s));
+            SEA_HIP_CHECK(ctx, launch_face_corr(a, nz_max, s));
         }
+        SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
         timer_off(SEA_STAGE_BOUNDARY);
         if (a.x_nonzero) {
             timer_on(SEA_STAGE_GUESS);
@@ -633,24 +605,9 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
             az.rnorm = (az.start_res && residual_zm_lds_bytes() <= ctx->max_lds) ? (double*)(base + Ly.rnorm) : nullptr;
             SEA_HIP_CHECK(ctx, launch_cg_zm(az, var, s));
             timer_off(SEA_STAGE_CG);
-            if (f.action && ctx->side_ready) {
-                // the pair energies on the side stream while the scatter (both
-                // read the final x only) runs on this one
-                SEA_HIP_CHECK(ctx, hipEventRecord(ctx->fork[1], s));
-                SEA_HIP_CHECK(ctx, hipStreamWaitEvent(ctx->side, ctx->fork[1], 0));
-                if (prof && ctx->ev_ready) {
-                    (void)hipEventRecord(ctx->ev[SEA_STAGE_FINISH][0], ctx->side);
-                    ctx->ev_used[SEA_STAGE_FINISH] = true;
-                }
-                SEA_HIP_CHECK(ctx, launch_cg_finish(a, ctx->side));
-                if (prof && ctx->ev_ready) (void)hipEventRecord(ctx->ev[SEA_STAGE_FINISH][1], ctx->side);
-                SEA_HIP_CHECK(ctx, hipEventRecord(ctx->join[1], ctx->side));
-                finish_pending = true;
-            } else {
-                timer_on(SEA_STAGE_FINISH);
-                SEA_HIP_CHECK(ctx, launch_cg_finish(a, s));
-                timer_off(SEA_STAGE_FINISH);
-            }
+            timer_on(SEA_STAGE_FINISH);
+            SEA_HIP_CHECK(ctx, launch_cg_finish(a, s));
+            timer_off(SEA_STAGE_FINISH);
         } else {
             SEA_HIP_CHECK(ctx, launch_cg(a, s));
             timer_off(SEA_STAGE_CG);
@@ -663,7 +620,6 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                                               (const int2*)(base + Ly.csr_ent), s));
         timer_off(SEA_STAGE_SCATTER);
     }
-    if (finish_pending) SEA_HIP_CHECK(ctx, hipStreamWaitEvent(s, ctx->join[1], 0));
     timer_on(SEA_STAGE_ENERGY);
     SEA_HIP_CHECK(ctx, launch_energy_sum(a, (double*)(base + Ly.scal), f.e_dev, s));
     timer_off(SEA_STAGE_ENERGY);

@@ -38,12 +38,6 @@ struct sea_ctx {
     bool ev_ready = false;
     const void* nn_state = nullptr;   // attached network (learned start)
     int cg_tuned = -1;                // z-march variant chosen by sea_exx_autotune
-    // a second stream (default priority) for independent kernels of one call,
-    // forked from and joined back to the caller's stream by events (also
-    // inside graph capture)
-    hipStream_t side = nullptr;
-    hipEvent_t fork[2] = {}, join[2] = {};
-    bool side_ready = false;
 };
 
 // Records the begin/end event of a stage when profiling is on.
