@@ -616,7 +616,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
     if (f.action) {
         timer_on(SEA_STAGE_SCATTER);
         for (size_t c = 0; c < S.cells.size(); ++c)
-            SEA_HIP_CHECK(ctx, launch_scatter(a, (int)c, S.dev[c].N, S.dev[c].n_occ, (const int*)(base + Ly.csr_off),
+            SEA_HIP_CHECK(ctx, launch_scatter(a, S.dev[c], (const int*)(base + Ly.csr_off),
                                               (const int2*)(base + Ly.csr_ent), s));
         timer_off(SEA_STAGE_SCATTER);
     }

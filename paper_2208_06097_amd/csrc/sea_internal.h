@@ -214,8 +214,8 @@ int cg_variant_count();
 const char* cg_variant_name(int v);
 hipError_t launch_cg_zm(const ExxArgs& a, int variant, hipStream_t s);
 hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s);
-hipError_t launch_scatter(const ExxArgs& a, int cell, const int* N, int n_occ, const int* csr_off,
-                          const int2* csr_ent, hipStream_t s);
+hipError_t launch_scatter(const ExxArgs& a, const DevCell& cell, const int* csr_off, const int2* csr_ent,
+                          hipStream_t s);
 hipError_t launch_energy_sum(const ExxArgs& a, double* out_scalars, double* e_dev, hipStream_t s);
 
 // Host evaluation of the solid-harmonic recurrence (orthonormal real form).
