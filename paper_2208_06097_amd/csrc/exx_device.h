@@ -11,9 +11,20 @@ __device__ __forceinline__ int wrap_idx(int k, int N) {
     return m < 0 ? m + N : m;
 }
 
+// A pointer read from device memory (a cell record) is generic to the
+// compiler, and loads through it become flat loads, which also count on the
+// scalar-load counter and so serialize behind scalar loads; the arrays these
+// pointers address are always in global memory.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) const T*;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> as_global(const T* p) {
+    return (global_ptr<T>)p;
+}
+
 // orbital value from an FP64 or FP32 array
 __device__ __forceinline__ double load_phi(const void* phi, int f32, size_t off) {
-    return f32 ? (double)(((const float*)phi)[off]) : ((const double*)phi)[off];
+    return f32 ? (double)as_global((const float*)phi)[off] : as_global((const double*)phi)[off];
 }
 
 // Multipole potential (Eq. 10) at displacement d from the pair's monomial

@@ -37,6 +37,8 @@
 // direction p is kept, so the Krylov process is never restarted.  Residual
 // norms and dot products accumulate in FP64.  A separate kernel recomputes
 // the true residual b - A x in FP64 at exit and the pair energy.
+#include <type_traits>
+
 #include "sea_internal.h"
 
 namespace {
@@ -113,7 +115,9 @@ __device__ __forceinline__ int wrap_idx(int k, int N) {
 }
 
 __device__ __forceinline__ double load_phi(const void* phi, int f32, size_t off) {
-    return f32 ? (double)(((const float*)phi)[off]) : ((const double*)phi)[off];
+    typedef __attribute__((address_space(1))) const float gfloat;
+    typedef __attribute__((address_space(1))) const double gdouble;
+    return f32 ? (double)((gfloat*)phi)[off] : ((gdouble*)phi)[off];
 }
 
 struct Empty {};
@@ -512,20 +516,44 @@ constexpr int FIN_BS = 512;
 __global__ __launch_bounds__(FIN_BS) void k_cg_finish(ExxArgs a) {
     __shared__ double red[FIN_BS / 64 + 1];
     const int pid = blockIdx.x;
-    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const DevCell C = a.cells[a.pair_cell[pid]];   // copied: fields stay in registers
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    const int n = nx * ny * nz, nxy = nx * ny;
+    const int n = nx * ny * nz;
     const double* x = a.v + (size_t)pid * a.stride;
     const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
     double e = 0.0;
     BoxWalk wk((int)threadIdx.x, FIN_BS, nx, ny);
-    for (int id = threadIdx.x; id < n; id += FIN_BS, wk.next()) {
-        const int xx = wk.x, yy = wk.y, zz = wk.z;
-        const size_t g = ((size_t)wrap_near(P.lo[2] + zz, C.N[2]) * C.N[1] + wrap_near(P.lo[1] + yy, C.N[1])) * C.N[0] +
-                         wrap_near(P.lo[0] + xx, C.N[0]);
-        e += load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g) * x[id];
-    }
+    // FIN_U points per thread at a time, their loads issued together; one
+    // copy per orbital precision, widened at the product.  The sum runs in
+    // the same order as one point at a time.
+    constexpr int FIN_U = 4;
+    auto run = [&](auto f32) {
+        using PT = typename std::conditional<decltype(f32)::value, float, double>::type;
+        typedef __attribute__((address_space(1))) const PT gPT;
+        const gPT* ph = (const gPT*)C.phi;
+        for (int id0 = threadIdx.x; id0 < n; id0 += FIN_U * FIN_BS) {
+            PT fi[FIN_U], fj[FIN_U];
+            double xv[FIN_U];
+#pragma unroll
+            for (int k = 0; k < FIN_U; ++k) {
+                // past n the walk leaves the box along z, still a grid point
+                // after wrapping; x is then read at the box's last point
+                const size_t g = ((size_t)wrap_near(P.lo[2] + wk.z, C.N[2]) * C.N[1] + wrap_near(P.lo[1] + wk.y, C.N[1])) *
+                                     C.N[0] +
+                                 wrap_near(P.lo[0] + wk.x, C.N[0]);
+                fi[k] = ph[oi + g];
+                fj[k] = ph[oj + g];
+                xv[k] = x[min(id0 + k * FIN_BS, n - 1)];
+                wk.next();
+            }
+#pragma unroll
+            for (int k = 0; k < FIN_U; ++k)
+                if (id0 + k * FIN_BS < n) e += (double)fi[k] * (double)fj[k] * xv[k];
+        }
+    };
+    if (C.phi_f32) run(std::true_type());
+    else run(std::false_type());
     e = block_sum<FIN_BS>(e, red);
     if (threadIdx.x == 0) {
         DevStat st = a.stats[pid];

@@ -5,6 +5,8 @@
 // Pair-domain arrays (b, v and the CG state) are stored compactly as
 // [z][y][x] over the interior (n0*n1*n2 points), one array of `stride`
 // doubles per pair (b, v) or per CG slot (r, p, q).
+#include <type_traits>
+
 #include "exx_device.h"
 #include "harmonics.h"
 #include "sea_internal.h"
@@ -55,6 +57,7 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 constexpr int GM_BS = 256;
 constexpr int GM_CHUNK = 4096;
 constexpr int GC_NM = 84;   // monomials of degree <= 6
+constexpr int GC_ZB = 8;    // planes whose orbital loads the gather issues together
 static_assert(GC_NM + 2 <= GC_N, "chunk record too short");
 
 // position of x^a y^b z^c (a + b + c <= 6) in the order a, then b, then c
@@ -151,9 +154,10 @@ __global__ __launch_bounds__(GM_BS) void k_gather_cart(ExxArgs a) {
     const int z0 = blockIdx.y * GC_ZC;
     if (z0 >= nz) return;
     const int z1 = min(z0 + GC_ZC, nz);
-    const DevCell& C = a.cells[a.pair_cell[pid]];
+    // the cell record copied: its fields stay in registers across the stores to b
+    const DevCell C = a.cells[a.pair_cell[pid]];
     const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
-    double* b = a.b + (size_t)pid * a.stride;
+    double* __restrict__ b = a.b + (size_t)pid * a.stride;
     const int lane = threadIdx.x & 63, yg = threadIdx.x >> 6;
     constexpr int NG = GM_BS / 64;
     for (int t = threadIdx.x; t < GC_N; t += GM_BS) tot[t] = 0.0;
@@ -172,20 +176,40 @@ __global__ __launch_bounds__(GM_BS) void k_gather_cart(ExxArgs a) {
             const double dy = (P.lo[1] + y) * C.h[1] - P.origin[1];
             double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             double t0 = 0.0, t2 = 0.0;
-            for (int z = z0; z < z1; ++z) {
-                const size_t g = ((size_t)wrap_near(P.lo[2] + z, C.N[2]) * C.N[1] + gy) * C.N[0] + gx;
-                const double dz = (P.lo[2] + z) * C.h[2] - P.origin[2];
-                const double rho = live ? load_phi(C.phi, C.phi_f32, oi + g) * load_phi(C.phi, C.phi_f32, oj + g) : 0.0;
-                if (live) b[((size_t)z * ny + y) * nx + x] = 4.0 * kPi * rho;
-                double p = rho;
-                v[0] += p;
+            // planes in batches: the batch's loads first (in flight together),
+            // one copy per orbital precision, widened only at the product
+            auto zbatch = [&](auto f32, int zb) {
+                using PT = typename std::conditional<decltype(f32)::value, float, double>::type;
+                const global_ptr<PT> ph = as_global((const PT*)C.phi);
+                PT fi[GC_ZB], fj[GC_ZB];
 #pragma unroll
-                for (int c = 1; c < 7; ++c) {
-                    p *= dz;
-                    v[c] += p;
+                for (int k = 0; k < GC_ZB; ++k) {
+                    const int z = min(zb + k, z1 - 1);   // past z1: a repeated plane, not used
+                    const size_t g = ((size_t)wrap_near(P.lo[2] + z, C.N[2]) * C.N[1] + gy) * C.N[0] + gx;
+                    fi[k] = ph[oi + g];
+                    fj[k] = ph[oj + g];
                 }
-                t0 += fabs(rho);
-                t2 += fabs(rho) * dz * dz;
+#pragma unroll
+                for (int k = 0; k < GC_ZB; ++k) {
+                    const int z = zb + k;
+                    if (z >= z1) break;
+                    const double dz = (P.lo[2] + z) * C.h[2] - P.origin[2];
+                    const double rho = live ? (double)fi[k] * (double)fj[k] : 0.0;
+                    if (live) b[((size_t)z * ny + y) * nx + x] = 4.0 * kPi * rho;
+                    double p = rho;
+                    v[0] += p;
+#pragma unroll
+                    for (int c = 1; c < 7; ++c) {
+                        p *= dz;
+                        v[c] += p;
+                    }
+                    t0 += fabs(rho);
+                    t2 += fabs(rho) * dz * dz;
+                }
+            };
+            for (int zb = z0; zb < z1; zb += GC_ZB) {
+                if (C.phi_f32) zbatch(std::true_type(), zb);
+                else zbatch(std::false_type(), zb);
             }
             double yp = 1.0;
 #pragma unroll
