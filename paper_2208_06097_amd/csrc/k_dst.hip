@@ -141,7 +141,10 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
     const sea_pair P = d.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     if (nx > DS_N || ny > DS_N || nz > DS_N) return;   // keeps the multipole start
-    if ((int)blockIdx.y >= nz) return;
+    if ((int)blockIdx.y >= nz) {   // no plane here: the workgroup's partial sums are zero
+        if (threadIdx.x == 0 && d.bsum) d.bsum[(size_t)pid * FN_PARTS + blockIdx.y] = 0.0;
+        return;
+    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int hb = w & 1, bp = 2 * (w >> 1);

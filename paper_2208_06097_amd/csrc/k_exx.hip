@@ -13,8 +13,6 @@
 
 namespace {
 
-constexpr double kPi = 3.14159265358979323846;
-
 // O(h^12) central second-difference weights (half order 6):
 // f'' ~ h^-2 (c0 f0 + sum_k ck (f_k + f_-k)).
 __constant__ double kC[7] = {-5369.0 / 1800.0, 12.0 / 7.0,      -15.0 / 56.0,     10.0 / 189.0,

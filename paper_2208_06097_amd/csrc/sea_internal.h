@@ -177,6 +177,7 @@ hipError_t launch_face_corr(const ExxArgs& a, int nz_max, hipStream_t s);
 // r = b - A x = -D (x - x0) into bres on the face points, |b|^2 and |r|^2
 // into a.rnorm, for the pairs the sine transform took
 hipError_t launch_face_residual(const ExxArgs& a, int nz_max, hipStream_t s);
+constexpr double kPi = 3.14159265358979323846;
 constexpr int DP_PG = 16;   // sine-transform workgroups per pair
 // partial sums per pair in a.fnorm: |b|^2 per sine-transform workgroup,
 // then |r|^2 per plane (at most 64 planes for the pairs the transform takes)

@@ -90,6 +90,55 @@ def test_spectral_start_on_eps_boxes_matches_oracle():
     ctx.close()
 
 
+def test_spectral_eps_boxes_with_a_dirty_workspace():
+    """Boxes with fewer planes than the transform has workgroups per pair:
+    the idle workgroups' partial sums must be written (as zeros), not left
+    to whatever the workspace held; a workspace filled with large values
+    (0x47 bytes, 1.2e35 as doubles) would otherwise pass every start as
+    converged."""
+    cell = synth.mini(seed=7)
+    eps = 10 ** -3.5
+    print("case spectral eps boxes, dirty workspace", flush=True)
+    ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F32, start=sea.SEA_START_SPECTRAL)
+    phi = torch.from_numpy(cell.phi).cuda()
+    pairs, _ = ctx.build_pairs_eps(phi, cell.N, cell.L, eps, eps, pad=6)
+    assert pairs["n"][:, 2].min() < 16
+    ws = ctx.workspace(ctx.exx_workspace_bytes(cell.N, cell.L, cell.n_occ, pairs))
+    ws.fill_(0x47)
+    W, E, stats, st = ctx.exx_action(phi, cell.N, cell.L, pairs, ws=ws)
+    assert st == sea.SEA_OK and np.all(stats["converged"] == 1)
+    assert np.all(stats["rel_res"] <= 1e-8)
+    W2, E2, stats2, _ = ctx.exx_action(phi, cell.N, cell.L, pairs)
+    assert E == E2 and torch.equal(W, W2)
+    lo, ln = oracle.eps_boxes(cell.phi, cell.N, eps)
+    pl, _ = oracle.eps_pairs(cell.phi, cell.N, cell.L, lo, ln, eps, pad=6)
+    ref = oracle.exx(cell.phi, cell.N, cell.L, pl, tol=1e-12)
+    assert abs(E - ref.E) < 1e-6
+    ctx.close()
+
+
+def test_spectral_pair_energies_match_oracle():
+    """Pairs that converge at their spectral start (no CG iteration) keep
+    the transform's x; pair by pair, dV sum rho x must match the oracle's.
+    Six pairs of the 64-molecule cell, whose 63^3 domains converge at the
+    start."""
+    cell = synth.config2()
+    print("case spectral pair energies, 64-molecule cell", flush=True)
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, 6.0)
+    idx = (np.arange(6) * (len(pairs) // 6)).astype(np.int64)
+    sub = pairs[idx]
+    ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F32, start=sea.SEA_START_SPECTRAL)
+    phi = torch.from_numpy(cell.phi).cuda()
+    W, E, stats, st = ctx.exx_action(phi, cell.N, cell.L, sub)
+    ctx.close()
+    assert st == sea.SEA_OK
+    assert np.all(stats["iters"] == 0) and np.all(stats["converged"] == 1)
+    pl = oracle.build_pairs(cell.N, cell.L, cell.centres, 6.0, 6.0).subset(idx)
+    assert np.array_equal(pl.n, sub["n"]) and np.array_equal(pl.lo, sub["lo"])
+    ref = oracle.exx(cell.phi, cell.N, cell.L, pl, tol=1e-12)
+    assert np.max(np.abs(stats["e_ij"] - ref.e_pairs)) < 1e-9 * np.max(np.abs(ref.e_pairs))
+
+
 def test_long_domains_keep_the_multipole_start():
     """Domains of 73 points per axis (beyond the transform's 64) keep the
     multipole start: same iterations and result as SEA_START_MULTIPOLE."""
