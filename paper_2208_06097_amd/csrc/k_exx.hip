@@ -434,9 +434,14 @@ __device__ __forceinline__ double face_taps(int i, int n, F&& val) {
         const bool low = i < FF_W;
         const int d = low ? i : n - 1 - i;
         double c = 0.0;
+        // every tap reads (a tap that does not reach reads the face point
+        // with weight 0, which leaves c unchanged), so that the reads of a
+        // line are issued together rather than one branch at a time
 #pragma unroll
-        for (int k = 2; k <= SEA_HALO; ++k)
-            if (k >= d + 2) c -= kC[k] * val(low ? k - d - 2 : n - 1 - (k - d - 2));
+        for (int k = 2; k <= SEA_HALO; ++k) {
+            const int q = max(k - d - 2, 0);
+            c -= (k >= d + 2 ? kC[k] : 0.0) * val(low ? q : n - 1 - q);
+        }
         return c;
     }
     auto ext = [&](int q) {
@@ -749,9 +754,16 @@ __global__ __launch_bounds__(GM_BS) void k_face_z(ExxArgs a) {
 // along z read their mirror planes directly.  Each face point is written
 // once with the sum over its axes; off the face points the arrays are not
 // written (and not read).
+// Index of a face point of a line of n points within that line's frame (its
+// first and last FF_W points; the whole line when n <= 2 FF_W).
+__device__ __forceinline__ int frame_k(int i, int n) { return (n <= 2 * FF_W || i < FF_W) ? i : i - (n - 2 * FF_W); }
+
 template <int RES>
 __global__ __launch_bounds__(GM_BS) void k_face_plane(ExxArgs a) {
-    __shared__ double E[64][65];
+    // only the plane's frame is kept (the taps along x and y read values
+    // within FF_W of the face they cross): rows' ends and columns' ends
+    __shared__ double Ex[64][2 * FF_W + 1];
+    __shared__ double Ey[2 * FF_W][65];
     __shared__ double red[GM_BS / 64 + 1];
     const int pid = blockIdx.x, z = blockIdx.y;
     const sea_pair P = a.pairs[pid];
@@ -764,14 +776,21 @@ __global__ __launch_bounds__(GM_BS) void k_face_plane(ExxArgs a) {
     const double* x = a.v + po;
     auto val = [&](size_t o) { return RES ? x[o] - x0[o] : x0[o]; };
     const bool zf = near_face(z, nz);
-    for_face_points(nx, ny, nz, z, [&](int xx, int yy) { E[yy][xx] = val(z * npl + (size_t)yy * nx + xx); });
+    for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
+        const bool fx = near_face(xx, nx), fy = near_face(yy, ny);
+        if (fx || fy) {
+            const double v = val(z * npl + (size_t)yy * nx + xx);
+            if (fx) Ex[yy][frame_k(xx, nx)] = v;
+            if (fy) Ey[frame_k(yy, ny)][xx] = v;
+        }
+    });
     __syncthreads();
     double rr = 0.0;
     double* out = (RES ? a.bres : a.fcorr) + po;
     for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
         double t = 0.0;
-        if (near_face(xx, nx)) t += face_taps(xx, nx, [&](int q) { return E[yy][q]; }) * ihx;
-        if (near_face(yy, ny)) t += face_taps(yy, ny, [&](int q) { return E[q][xx]; }) * ihy;
+        if (near_face(xx, nx)) t += face_taps(xx, nx, [&](int q) { return Ex[yy][frame_k(q, nx)]; }) * ihx;
+        if (near_face(yy, ny)) t += face_taps(yy, ny, [&](int q) { return Ey[frame_k(q, ny)][xx]; }) * ihy;
         if (zf) {
             const size_t col = (size_t)yy * nx + xx;
             t += face_taps(z, nz, [&](int q) { return val(q * npl + col); }) * ihz;
