@@ -425,6 +425,10 @@ constexpr int GA_BS = 256;
 // sum over the stencil taps of a column point i that fall past a face, of
 // c_k times the odd continuation (period 2 (n + 1), zeros at -1 and n) of
 // the column values val(index)
+// Index of a face point of a line of n points within that line's frame (its
+// first and last FF_W points; the whole line when n <= 2 FF_W).
+__device__ __forceinline__ int frame_k(int i, int n) { return (n <= 2 * FF_W || i < FF_W) ? i : i - (n - 2 * FF_W); }
+
 template <typename F>
 __device__ __forceinline__ double face_taps(int i, int n, F&& val) {
     if (n >= 2 * FF_W) {
@@ -468,7 +472,7 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
     const int pid = blockIdx.x;
     if (threadIdx.x < GC_NM) cf[threadIdx.x] = a.mpoly[(size_t)pid * GC_NM + threadIdx.x];
     __syncthreads();
-    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const DevCell C = a.cells[a.pair_cell[pid]];   // copied: fields stay in registers across stores
     const sea_pair P = a.pairs[pid];
     const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;   // column coordinates, x first where it is one
     const int n = P.n[ax];
@@ -671,7 +675,10 @@ __global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
     __shared__ double Q[SEA_NACC];
     __shared__ double cf[GC_NM];
     __shared__ double qr[64][ME_QL + 1];
-    __shared__ double E[64][65];
+    // the plane's frame of x0 (the taps along x and y stay within FF_W of
+    // the face they cross)
+    __shared__ double Ex[64][2 * FF_W + 1];
+    __shared__ double Ey[2 * FF_W][65];
     const int pid = blockIdx.x, z = blockIdx.y;
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
@@ -679,7 +686,7 @@ __global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
     if (threadIdx.x < SEA_NACC) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
     if (threadIdx.x < GC_NM) cf[threadIdx.x] = a.mpoly[(size_t)pid * GC_NM + threadIdx.x];
     __syncthreads();
-    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const DevCell C = a.cells[a.pair_cell[pid]];   // copied: fields stay in registers across stores
     const double dz = (P.lo[2] + z) * C.h[2] - P.origin[2];
     if (threadIdx.x < ny) {   // one row a thread
         const int y = threadIdx.x;
@@ -706,7 +713,8 @@ __global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
         }
         const double v = me_start_from_parts(Q, Pl, dx * dx + dy * dy + dz * dz);
         a.x0[zo + (size_t)yy * nx + xx] = v;
-        E[yy][xx] = v;
+        if (near_face(xx, nx)) Ex[yy][frame_k(xx, nx)] = v;
+        if (near_face(yy, ny)) Ey[frame_k(yy, ny)][xx] = v;
     });
     __syncthreads();
     // -D x0 along x and y (the taps along z, on the planes next to a z face,
@@ -714,8 +722,8 @@ __global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
     const double ihx = 1.0 / (C.h[0] * C.h[0]), ihy = 1.0 / (C.h[1] * C.h[1]);
     for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
         double t = 0.0;
-        if (near_face(xx, nx)) t += face_taps(xx, nx, [&](int q) { return E[yy][q]; }) * ihx;
-        if (near_face(yy, ny)) t += face_taps(yy, ny, [&](int q) { return E[q][xx]; }) * ihy;
+        if (near_face(xx, nx)) t += face_taps(xx, nx, [&](int q) { return Ex[yy][frame_k(q, nx)]; }) * ihx;
+        if (near_face(yy, ny)) t += face_taps(yy, ny, [&](int q) { return Ey[frame_k(q, ny)][xx]; }) * ihy;
         a.fcorr[zo + (size_t)yy * nx + xx] = -t;
     });
 }
@@ -729,7 +737,7 @@ __global__ __launch_bounds__(GM_BS) void k_face_z(ExxArgs a) {
     if (!spectral_pair(P)) return;
     const int z = blockIdx.y < FF_W ? (int)blockIdx.y : nz - 2 * FF_W + (int)blockIdx.y;
     if (z < 0 || z >= nz || (blockIdx.y >= FF_W && z < FF_W)) return;   // thin boxes: every plane once
-    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const DevCell C = a.cells[a.pair_cell[pid]];   // copied: fields stay in registers across stores
     const double ihz = 1.0 / (C.h[2] * C.h[2]);
     const size_t po = (size_t)pid * a.stride, npl = (size_t)nx * ny;
     const double* x0 = a.x0 + po;
@@ -754,10 +762,6 @@ __global__ __launch_bounds__(GM_BS) void k_face_z(ExxArgs a) {
 // along z read their mirror planes directly.  Each face point is written
 // once with the sum over its axes; off the face points the arrays are not
 // written (and not read).
-// Index of a face point of a line of n points within that line's frame (its
-// first and last FF_W points; the whole line when n <= 2 FF_W).
-__device__ __forceinline__ int frame_k(int i, int n) { return (n <= 2 * FF_W || i < FF_W) ? i : i - (n - 2 * FF_W); }
-
 template <int RES>
 __global__ __launch_bounds__(GM_BS) void k_face_plane(ExxArgs a) {
     // only the plane's frame is kept (the taps along x and y read values
@@ -769,7 +773,7 @@ __global__ __launch_bounds__(GM_BS) void k_face_plane(ExxArgs a) {
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     if (!spectral_pair(P) || z >= nz) return;
-    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const DevCell C = a.cells[a.pair_cell[pid]];   // copied: fields stay in registers across stores
     const double ihx = 1.0 / (C.h[0] * C.h[0]), ihy = 1.0 / (C.h[1] * C.h[1]), ihz = 1.0 / (C.h[2] * C.h[2]);
     const size_t po = (size_t)pid * a.stride, npl = (size_t)nx * ny;
     const double* x0 = a.x0 + po;
