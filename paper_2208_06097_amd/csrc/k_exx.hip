@@ -750,20 +750,18 @@ __global__ __launch_bounds__(GM_BS) void k_face_z(ExxArgs a) {
 // difference between the stencil with zero values past the faces (A) and
 // with the odd continuation the sine transform diagonalizes (A_odd); per
 // axis it lives on the 5 points next to each face and reads values there
-// only, on the same line along the axis.
-//   res = 0: the right-hand-side correction -D x0 into a.fcorr, so that
-//            A_odd^-1 (b - D x0) = x0 + A_odd^-1 (b - A x0);
-//   res = 1: after the transform (A_odd x = b - D x0), the residual
-//            r = b - A x = -D (x - x0) into bres (up to the transform's
-//            rounding, the stencil residual), and per plane the sum of r^2
-//            into a.fnorm.
-// One workgroup per plane: the plane's face values (x0, or x - x0) meet in
-// LDS for the taps along x and y; on the planes next to a z face the taps
-// along z read their mirror planes directly.  Each face point is written
-// once with the sum over its axes; off the face points the arrays are not
-// written (and not read).
-template <int RES>
-__global__ __launch_bounds__(GM_BS) void k_face_plane(ExxArgs a) {
+// only, on the same line along the axis.  The right-hand-side correction
+// -D x0 (so that A_odd^-1 (b - D x0) = x0 + A_odd^-1 (b - A x0)) comes from
+// k_me_face and k_face_z; this kernel forms, after the transform
+// (A_odd x = b - D x0), the residual r = b - A x = -D (x - x0) into bres
+// (up to the transform's rounding, the stencil residual), and per plane the
+// sum of r^2 into a.fnorm.
+// One workgroup per plane: the plane's face values x - x0 meet in LDS for
+// the taps along x and y; on the planes next to a z face the taps along z
+// read their mirror planes directly.  Each face point is written once with
+// the sum over its axes; off the face points bres is not written (and x, x0
+// are not read).
+__global__ __launch_bounds__(GM_BS) void k_face_residual(ExxArgs a) {
     // only the plane's frame is kept (the taps along x and y read values
     // within FF_W of the face they cross): rows' ends and columns' ends
     __shared__ double Ex[64][2 * FF_W + 1];
@@ -778,7 +776,7 @@ __global__ __launch_bounds__(GM_BS) void k_face_plane(ExxArgs a) {
     const size_t po = (size_t)pid * a.stride, npl = (size_t)nx * ny;
     const double* x0 = a.x0 + po;
     const double* x = a.v + po;
-    auto val = [&](size_t o) { return RES ? x[o] - x0[o] : x0[o]; };
+    auto val = [&](size_t o) { return x[o] - x0[o]; };
     const bool zf = near_face(z, nz);
     for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
         const bool fx = near_face(xx, nx), fy = near_face(yy, ny);
@@ -790,7 +788,7 @@ __global__ __launch_bounds__(GM_BS) void k_face_plane(ExxArgs a) {
     });
     __syncthreads();
     double rr = 0.0;
-    double* out = (RES ? a.bres : a.fcorr) + po;
+    double* out = a.bres + po;
     for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
         double t = 0.0;
         if (near_face(xx, nx)) t += face_taps(xx, nx, [&](int q) { return Ex[yy][frame_k(q, nx)]; }) * ihx;
@@ -802,10 +800,8 @@ __global__ __launch_bounds__(GM_BS) void k_face_plane(ExxArgs a) {
         out[z * npl + (size_t)yy * nx + xx] = -t;
         rr += t * t;
     });
-    if (RES) {
-        rr = block_sum<GM_BS>(rr, red);
-        if (threadIdx.x == 0) a.fnorm[(size_t)pid * FN_PARTS + DP_PG + z] = rr;
-    }
+    rr = block_sum<GM_BS>(rr, red);
+    if (threadIdx.x == 0) a.fnorm[(size_t)pid * FN_PARTS + DP_PG + z] = rr;
 }
 
 // |b|^2 and |r|^2 of a pair from the partial sums (the transform's first
@@ -1124,7 +1120,7 @@ hipError_t launch_face_corr(const ExxArgs& a, int nz_max, hipStream_t s) {
 }
 
 hipError_t launch_face_residual(const ExxArgs& a, int nz_max, hipStream_t s) {
-    hipLaunchKernelGGL(k_face_plane<1>, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
+    hipLaunchKernelGGL(k_face_residual, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
     hipLaunchKernelGGL(k_face_norms, dim3((a.n_pairs + 63) / 64), dim3(64), 0, s, a);
     return hipGetLastError();
 }
