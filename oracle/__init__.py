@@ -19,12 +19,12 @@ the oracle's own reading.
 """
 from .core import (build, lib_path, fd_weights, build_pairs, real_ylm,
                    moments_points, me_eval, neg_lap_padded, cg, pair_potential,
-                   exx, cholesky, ace_build, ace_apply, ace_energy,
+                   pair_me_start, exx, cholesky, ace_build, ace_apply, ace_energy,
                    eps_boxes, eps_pairs, successive_idempotency, scdm_pivots, scdm, back_rotate,
                    qrcp_residual_norms, PairList, ExxResult, AceResult, ScdmResult)
 
 __all__ = ["build", "lib_path", "fd_weights", "build_pairs", "real_ylm",
            "moments_points", "me_eval", "neg_lap_padded", "cg",
-           "pair_potential", "exx", "cholesky", "ace_build", "ace_apply",
+           "pair_potential", "pair_me_start", "exx", "cholesky", "ace_build", "ace_apply",
            "ace_energy", "eps_boxes", "eps_pairs", "successive_idempotency", "scdm_pivots", "scdm",
            "back_rotate", "qrcp_residual_norms", "PairList", "ExxResult", "AceResult", "ScdmResult"]

@@ -61,6 +61,7 @@ def _load():
         lib.orc_cg.argtypes = [P(i32), P(d), i, P(d), P(d), d, i, P(d)]
         lib.orc_pair_potential.argtypes = [P(i32), P(d), i, P(d), P(i32), P(d), i, i, d, i,
                                            P(d), P(d), P(d), P(d)]
+        lib.orc_pair_me_start.argtypes = [P(i32), P(d), i, P(d), P(i32), P(d), i, P(d)]
         lib.orc_exx.argtypes = [P(i32), P(d), i, P(d), i, P(i32), P(d), P(i32), i, i, d, i, i,
                                 P(d), P(d), P(i32), P(d), P(d)]
         lib.orc_cholesky.argtypes = [i, P(d), P(d)]
@@ -244,6 +245,24 @@ def pair_potential(phi, N, L, pairs: PairList, k: int, tol=1e-12, max_iter=10000
         raise ValueError("bad pair")
     return v, Q, dict(iters=int(info[0]), rel_res=info[1], e=info[2], s_abs=info[3],
                       q=info[4], bnorm=info[5], status=int(info[6]))
+
+
+def pair_me_start(phi, N, L, pairs: PairList, k: int, lmax=LMAX) -> np.ndarray:
+    """Regularized multipole start v_ME of pair k on its interior (nz, ny, nx):
+    q erf(r/r_s)/r plus the l >= 1 terms of Eq. 10 damped by
+    (1 - exp(-r^2/r_s^2))^(l+1), r_s = sqrt(2<r^2>/3) from the |rho|-weighted
+    second moment about the domain origin.  The paper leaves the CG's initial
+    guess open; this is the reading the multipole and learned starts use."""
+    lib = _load()
+    N3, L3 = _grid(N, L)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    pk = np.ascontiguousarray(pairs.packed()[k])
+    org = np.ascontiguousarray(pairs.origin[k])
+    n = pairs.n[k]
+    out = np.zeros((n[2], n[1], n[0]))
+    if lib.orc_pair_me_start(_ip(N3), _dp(L3), phi.shape[0], _dp(phi), _ip(pk), _dp(org), lmax, _dp(out)):
+        raise ValueError("bad pair")
+    return out
 
 
 @dataclasses.dataclass

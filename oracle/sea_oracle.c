@@ -604,6 +604,82 @@ int orc_pair_potential(const int32_t *N, const double *L, int n_occ, const doubl
     return st;
 }
 
+/* Regularized multipole start v_ME of pair `pair` on its interior (the
+ * initial guess of the CG of Eq. 9 that the multipole and learned starts
+ * use; the paper leaves the guess open, so this follows the reading in the
+ * design notes).  The expansion of Eq. 10 diverges inside the charge; here
+ *   v_ME(p) = q erf(r / r_s) / r
+ *           + sum_{l=1..lmax} (1 - exp(-r^2 / r_s^2))^{l+1}
+ *                             4 pi / (2l+1) sum_m Q_lm Y_lm(p - o) / r^{l+1},
+ * r = |p - o|, q = h^3 sum rho, Q_lm of Eq. 11 about the domain origin o, and
+ * r_s = sqrt(2 <r^2> / 3) with <r^2> = sum |rho| r^2 / sum |rho| (the width
+ * of a spherical Gaussian charge exp(-r^2 / r_s^2), whose potential the
+ * l = 0 term then is exactly).  At r = 0 the l = 0 term is its limit
+ * 2 q / (r_s sqrt(pi)) and the damped terms vanish.  Returns -1 on bad input. */
+int orc_pair_me_start(const int32_t *N, const double *L, int n_occ, const double *phi,
+                      const int32_t *pair, const double *origin, int lmax, double *out) {
+    int i = pair[0], j = pair[1];
+    const int32_t *lo = pair + 2, *n = pair + 5;
+    if (i < 0 || j < i || j >= n_occ || n[0] < 1 || n[1] < 1 || n[2] < 1 || lmax > ORC_LMAX_CAP) return -1;
+    double h[3] = {L[0] / N[0], L[1] / N[1], L[2] / N[2]};
+    double dV = h[0] * h[1] * h[2];
+    size_t Ng = (size_t)N[0] * N[1] * N[2];
+    size_t nn = (size_t)n[0] * n[1] * n[2];
+    int nlm = (lmax + 1) * (lmax + 1);
+    double *rho = malloc(sizeof(double) * nn);
+    double Q[(ORC_LMAX_CAP + 1) * (ORC_LMAX_CAP + 1)], Y[(ORC_LMAX_CAP + 1) * (ORC_LMAX_CAP + 1)];
+    const double *pi_ = phi + (size_t)i * Ng, *pj_ = phi + (size_t)j * Ng;
+    for (int k = 0; k < nlm; ++k) Q[k] = 0.0;
+    double sabs = 0.0, m2 = 0.0, qsum = 0.0;
+    for (int z = 0; z < n[2]; ++z)
+        for (int y = 0; y < n[1]; ++y)
+            for (int x = 0; x < n[0]; ++x) {
+                size_t g = ((size_t)orc_wrap(lo[2] + z, N[2]) * N[1] + orc_wrap(lo[1] + y, N[1])) * N[0]
+                           + orc_wrap(lo[0] + x, N[0]);
+                double rv = pi_[g] * pj_[g];
+                rho[((size_t)z * n[1] + y) * n[0] + x] = rv;
+                double dx = (lo[0] + x) * h[0] - origin[0];
+                double dy = (lo[1] + y) * h[1] - origin[1];
+                double dz = (lo[2] + z) * h[2] - origin[2];
+                double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
+                sabs += fabs(rv);
+                m2 += fabs(rv) * r2;
+                qsum += rv;
+                orc_real_ylm(lmax, dx, dy, dz, Y);
+                for (int l = 0; l <= lmax; ++l) {
+                    double rl = pow(r, l);
+                    for (int m = -l; m <= l; ++m) Q[l * l + l + m] += rv * rl * Y[l * l + l + m];
+                }
+            }
+    for (int k = 0; k < nlm; ++k) Q[k] *= dV;
+    double q = dV * qsum;
+    double rs = sqrt(sabs > 0.0 ? fmax(2.0 * (m2 / sabs) / 3.0, 1e-6) : 2.0 / 3.0);
+    for (int z = 0; z < n[2]; ++z)
+        for (int y = 0; y < n[1]; ++y)
+            for (int x = 0; x < n[0]; ++x) {
+                double dx = (lo[0] + x) * h[0] - origin[0];
+                double dy = (lo[1] + y) * h[1] - origin[1];
+                double dz = (lo[2] + z) * h[2] - origin[2];
+                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                double v;
+                if (r == 0.0) {
+                    v = 2.0 * q / (rs * sqrt(ORC_PI));
+                } else {
+                    v = q * erf(r / rs) / r;
+                    double damp = 1.0 - exp(-(r * r) / (rs * rs));
+                    orc_real_ylm(lmax, dx, dy, dz, Y);
+                    for (int l = 1; l <= lmax; ++l) {
+                        double acc = 0.0;
+                        for (int m = -l; m <= l; ++m) acc += Q[l * l + l + m] * Y[l * l + l + m];
+                        v += pow(damp, l + 1) * 4.0 * ORC_PI * acc / ((2.0 * l + 1.0) * pow(r, l + 1));
+                    }
+                }
+                out[((size_t)z * n[1] + y) * n[0] + x] = v;
+            }
+    free(rho);
+    return 0;
+}
+
 /* ---------------------------------------------------------------------- */
 /* the whole action: all pairs, then the scatter in pair order             */
 /* ---------------------------------------------------------------------- */

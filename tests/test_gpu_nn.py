@@ -145,9 +145,8 @@ def samples():
 
 def test_nn_samples_match_oracle_resampling():
     """x = resample(rho/s) and t = resample((v - v_ME)/s) on 32^3 for one pair,
-    against the oracle's own pair potential and trilinear resampling; the
-    multipole guess v_ME is taken from the GPU's multipole-start solve path
-    (start residual) so only the resampling and the solve are compared."""
+    against the oracle's own pair density, pair potential (at 1e-12),
+    regularized multipole start v_ME and trilinear resampling."""
     cell = synth.mini(seed=7)
     pairs = sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, 4.0)
     pl = oracle.build_pairs(cell.N, cell.L, cell.centres, 6.0, 4.0)
@@ -166,6 +165,14 @@ def test_nn_samples_match_oracle_resampling():
     assert abs(s[k].item() / s_ref - 1) < 1e-12
     want_x = nn.resample(rho / s_ref, 32)
     assert np.max(np.abs(x[k].cpu().numpy() - want_x)) < 1e-5 * np.max(np.abs(want_x))
+    v, _, info = oracle.pair_potential(cell.phi, cell.N, cell.L, pl, k, tol=1e-12)
+    v_me = oracle.pair_me_start(cell.phi, cell.N, cell.L, pl, k)
+    want_t = nn.resample((v - v_me) / s_ref, 32)
+    err_t = np.max(np.abs(t[k].cpu().numpy() - want_t))
+    print(f"t: max |dt| {err_t:.3e} of max |t| {np.max(np.abs(want_t)):.3e}", flush=True)
+    # FP32 samples: 6e-8 relative rounding; the solves agree to 1e-12
+    assert err_t < 1e-5 * np.max(np.abs(want_t))
+    assert np.max(np.abs(want_t)) > 1e-3 * np.max(np.abs(v))    # the correction is not trivially zero
 
 
 def test_training_lowers_loss(samples):

@@ -477,3 +477,161 @@ def test_ace_eigen_scheme_closed_form():
     K1 = r1.xi.T @ r1.xi
     K2 = r2.xi.T @ r2.xi
     assert np.allclose(K1, K2, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# regularized multipole start v_ME (the CG's initial guess; the paper leaves
+# it open, the reading: q erf(r/r_s)/r plus the l >= 1 terms of Eq. 10
+# damped by (1 - exp(-r^2/r_s^2))^(l+1), r_s = sqrt(2<r^2>/3))
+
+def _on_grid_a0_self_pair(L=13.7, N=70):
+    """One a = 0 orbital centred on a grid point: its self-pair domain is
+    centred there too (origin = centre), and every moment with l >= 1
+    vanishes by the cube's symmetry up to the grid sum's spectral error."""
+    cell = synth.make_centres(1, L, N, 11, dmin=1.0)
+    cell.centres = np.full((1, 3), 35 * (L / N))
+    cell.a = np.zeros((1, 3))
+    cell = synth.fill_orbitals(cell)
+    pl = oracle.build_pairs(N, L, cell.centres, 6.0, 6.0)
+    assert np.allclose(pl.origin[0], cell.centres[0], atol=1e-12)
+    return cell, pl
+
+
+def test_me_start_self_pair_closed_form():
+    """a = 0 self pair, origin at the centre: rho is a unit Gaussian charge
+    exp(-r^2/sigma^2) / (pi sigma^2)^{3/2}, <r^2> = 3 sigma^2 / 2, so
+    r_s = sigma and v_ME = erf(r/sigma)/r exactly (the exact potential, P2),
+    2/(sigma sqrt(pi)) at the centre."""
+    cell, pl = _on_grid_a0_self_pair()
+    v = oracle.pair_me_start(cell.phi, cell.N, cell.L, pl, 0)
+    h = cell.h
+    lo, n = pl.lo[0], pl.n[0]
+    c = cell.centres[0]
+    X = (lo[0] + np.arange(n[0]))[None, None, :] * h - c[0]
+    Y = (lo[1] + np.arange(n[1]))[None, :, None] * h - c[1]
+    Z = (lo[2] + np.arange(n[2]))[:, None, None] * h - c[2]
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        want = np.where(r > 0, erf(r / SIG) / np.where(r > 0, r, 1.0), 2.0 / (SIG * math.sqrt(math.pi)))
+    assert np.max(np.abs(v - want)) < 1e-9
+    assert abs(v[n[2] // 2, n[1] // 2, n[0] // 2] - 2.0 / (SIG * math.sqrt(math.pi))) < 1e-9
+    # planted slip: r_s from <r^2> without the factor 2/3 (r_s = sigma sqrt(3/2))
+    # changes the start by far more than the bar
+    rs_bad = SIG * math.sqrt(1.5)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        bad = np.where(r > 0, erf(r / rs_bad) / np.where(r > 0, r, 1.0), 2.0 / (rs_bad * math.sqrt(math.pi)))
+    assert np.max(np.abs(bad - want)) > 1e-2
+
+
+def _general_self_pair_cell():
+    cell = synth.mini(seed=7)
+    pl = oracle.build_pairs(cell.N, cell.L, cell.centres, 6.0, 4.0)
+    k = int(np.flatnonzero(pl.ij[:, 0] == pl.ij[:, 1])[0])
+    return cell, pl, k
+
+
+def test_me_start_far_field_is_the_expansion():
+    """Far from the charge (r >> r_s) the damping is 1 to machine precision
+    and v_ME is the multipole expansion of Eq. 10 itself (pinned against the
+    direct Coulomb sum, P10), with the pair's own moments (Eq. 11)."""
+    cell, pl, _ = _general_self_pair_cell()
+    k = int(np.flatnonzero(pl.ij[:, 0] != pl.ij[:, 1])[0])   # a ≠ 0, i ≠ j: every l present
+    v = oracle.pair_me_start(cell.phi, cell.N, cell.L, pl, k)
+    _, Q, _ = oracle.pair_potential(cell.phi, cell.N, cell.L, pl, k, tol=0.0, max_iter=0)
+    assert np.max(np.abs(Q[1:])) > 1e-4 * abs(Q[0]) or abs(Q[0]) < 1e-3
+    h = cell.h
+    lo, n, o = pl.lo[k], pl.n[k], pl.origin[k]
+    for (z, y, x) in [(0, 0, 0), (n[2] - 1, 0, n[0] - 1), (0, n[1] - 1, n[0] - 1), (n[2] - 1, n[1] - 1, 0)]:
+        t = np.array([(lo[0] + x) * h, (lo[1] + y) * h, (lo[2] + z) * h])
+        want = oracle.me_eval(6, Q, o, t)
+        assert abs(v[z, y, x] - want) <= 1e-12 * abs(want)
+
+
+def test_me_start_dipole_term_vanishes_smoothly_at_the_origin():
+    """Small-r limit of the damped l = 1 term.  With Y_1m(d/r) = sqrt(3/(4 pi))
+    d_m / r the l = 1 term of Eq. 10 is sqrt(4 pi/3) (Q_1 . d) / r^3; damped
+    by (1 - e^{-r^2/r_s^2})^2 ~ r^4/r_s^4 it vanishes at the origin like
+    sqrt(4 pi/3) (Q_1 . d) r / r_s^4.  Along an axis e through the origin the
+    odd part [v(o + h e) - v(o - h e)] / 2 comes from the odd l only, and the
+    l = 3 terms are damped by a further r^4: it is the l = 1 term
+    sqrt(4 pi/3) Q_e (1 - e^{-h^2/r_s^2})^2 / h^2 to a few percent (Q_e =
+    Q_11, Q_1-1, Q_10 for x, y, z).  A damping power of l instead of l + 1
+    would make it 1/(1 - e^{-h^2/r_s^2}) times larger (8x here); a swapped
+    or sign-flipped real harmonic would put another axis's moment there."""
+    cell, pl, k = _general_self_pair_cell()
+    v = oracle.pair_me_start(cell.phi, cell.N, cell.L, pl, k)
+    _, Q, info = oracle.pair_potential(cell.phi, cell.N, cell.L, pl, k, tol=0.0, max_iter=0)
+    h = cell.h
+    lo, n, o = pl.lo[k], pl.n[k], pl.origin[k]
+    c = [int(round(o[a] / h)) - lo[a] for a in range(3)]
+    assert np.allclose((np.array(c) + lo) * h, o)
+    # r_s from the gathered density (|rho|-weighted second moment about o)
+    iz, iy, ix = (np.mod(lo[a] + np.arange(n[a]), cell.N) for a in (2, 1, 0))
+    i, j = pl.ij[k]
+    rho = cell.phi[i][np.ix_(iz, iy, ix)] * cell.phi[j][np.ix_(iz, iy, ix)]
+    X = (lo[0] + np.arange(n[0]))[None, None, :] * h - o[0]
+    Y = (lo[1] + np.arange(n[1]))[None, :, None] * h - o[1]
+    Z = (lo[2] + np.arange(n[2]))[:, None, None] * h - o[2]
+    rs = math.sqrt(2.0 / 3.0 * np.sum(np.abs(rho) * (X * X + Y * Y + Z * Z)) / np.sum(np.abs(rho)))
+    damp = 1.0 - math.exp(-h * h / rs ** 2)
+    for ax, qi in ((0, 3), (1, 1), (2, 2)):
+        assert abs(Q[qi]) > 1e-2
+        e = [0, 0, 0]
+        e[ax] = 1
+        odd = (v[c[2] + e[2], c[1] + e[1], c[0] + e[0]] - v[c[2] - e[2], c[1] - e[1], c[0] - e[0]]) / 2
+        want = math.sqrt(4 * math.pi / 3) * Q[qi] * damp ** 2 / h ** 2
+        assert abs(odd - want) <= 0.05 * abs(want)
+
+
+# --------------------------------------------------------------------------
+# successive idempotency (App. B)
+
+def _orthonormal_set(n, ng, dV, seed):
+    """n + 1 grid vectors orthonormal in <f, g> = dV sum f g."""
+    A = np.random.default_rng(seed).standard_normal((ng, n + 1))
+    Qf, _ = np.linalg.qr(A)
+    return Qf.T / np.sqrt(dV)
+
+
+def test_successive_idempotency_closed_form():
+    """One orbital of an orthonormal set rotated by theta out of the
+    occupied space (towards a vector orthogonal to it): the overlap matrix
+    is diag(cos theta, 1, ..., 1), so dI = 1 - (n - sin^2 theta)/n =
+    sin^2 theta / n.  Two orbitals rotated by theta_1, theta_2 towards two
+    such vectors: (sin^2 theta_1 + sin^2 theta_2) / n.  A rotation within
+    the occupied space leaves the projector, so dI = 0."""
+    n, ng, dV = 6, 300, 0.37
+    B = _orthonormal_set(n + 1, ng, dV, 3)     # n + 2 vectors
+    old = B[:n]
+    for th in (0.0, 0.1, 0.7, math.pi / 2):
+        new = old.copy()
+        new[2] = math.cos(th) * old[2] + math.sin(th) * B[n]
+        assert abs(oracle.successive_idempotency(new, old, dV) - math.sin(th) ** 2 / n) < 1e-13
+    t1, t2 = 0.3, 1.1
+    new = old.copy()
+    new[0] = math.cos(t1) * old[0] + math.sin(t1) * B[n]
+    new[4] = math.cos(t2) * old[4] + math.sin(t2) * B[n + 1]
+    want = (math.sin(t1) ** 2 + math.sin(t2) ** 2) / n
+    assert abs(oracle.successive_idempotency(new, old, dV) - want) < 1e-13
+    U = np.linalg.qr(np.random.default_rng(4).standard_normal((n, n)))[0]
+    assert abs(oracle.successive_idempotency(U @ old, old, dV)) < 1e-13
+
+
+def test_successive_idempotency_planted_slips_are_caught():
+    """Plausible slips in dI (the inner product without dV, or squared dV;
+    N_occ^2 in the denominator; the overlap not squared) all miss the
+    closed form sin^2 theta / n of the single-rotation case."""
+    n, ng, dV, th = 6, 300, 0.37, 0.7
+    B = _orthonormal_set(n, ng, dV, 5)
+    old = B[:n]
+    new = old.copy()
+    new[1] = math.cos(th) * old[1] + math.sin(th) * B[n]
+    want = math.sin(th) ** 2 / n
+    S = lambda d: d * (new @ old.T)                              # noqa: E731
+    slips = [1.0 - np.sum(S(1.0) ** 2) / n,                      # dV dropped
+             1.0 - np.sum(S(dV * dV) ** 2) / n,                  # dV squared
+             1.0 - np.sum(S(dV) ** 2) / n ** 2,                  # N_occ^2
+             1.0 - np.sum(np.abs(S(dV))) / n]                    # not squared
+    for s in slips:
+        assert abs(s - want) > 1e-3
+    assert abs(oracle.successive_idempotency(new, old, dV) - want) < 1e-13
