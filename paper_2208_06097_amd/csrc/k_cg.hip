@@ -244,6 +244,19 @@ struct PVsel {
     using type = F2<T>;
 };
 
+// Whether a pair's start meets the exit test |b - A x|^2 <= tol2 |b|^2,
+// from the residual sweep's norms per row tile, summed in a fixed order (the
+// residual kernel's second launch and the CG take the same decision).
+__device__ __forceinline__ bool start_meets_target(const ExxArgs& a, int pid, double tol2, double& b2, double& q2) {
+    b2 = 0.0;
+    q2 = 0.0;
+    for (int t = 0; t < RZ_TILES; ++t) {
+        b2 += a.rnorm[((size_t)pid * RZ_TILES + t) * 2];
+        q2 += a.rnorm[((size_t)pid * RZ_TILES + t) * 2 + 1];
+    }
+    return q2 == q2 && b2 == b2 && q2 <= tol2 * b2;
+}
+
 // Access to one slot array at element col0 + off, off uniform across the
 // workgroup (plane and column offsets).  BUF: raw buffer instructions with
 // the array in a buffer resource (scalar registers), the lane's column in
@@ -328,18 +341,14 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     // r64 = b on the padded grid, x = 0.  A start guess x0 (in x on entry)
     // enters as the first increment c = (T) x0, so that x and r64 = b - A x
     // stay consistent in FP64 from the start.  With start_res the start is
-    // kept in FP64 in x and r64 = b - A x comes precomputed in bres.
+    // kept in FP64 in x and r64 = b - A x comes precomputed in bres; with
+    // rnorm too, the norms of the residual sweep decide first whether the
+    // start already meets the target (bres is then not written).
     const bool sres = a.x_nonzero && a.start_res;
     const bool fold = a.x_nonzero && !a.start_res;
     if (sres && a.rnorm) {
-        // the residual pass already has both norms: a converged start needs
-        // no work here
-        double b2 = 0.0, q2 = 0.0;
-        for (int t = 0; t < RZ_TILES; ++t) {   // fixed order: deterministic
-            b2 += a.rnorm[((size_t)pid * RZ_TILES + t) * 2];
-            q2 += a.rnorm[((size_t)pid * RZ_TILES + t) * 2 + 1];
-        }
-        if (q2 == q2 && b2 == b2 && q2 <= tol2 * b2) {
+        double b2, q2;
+        if (start_meets_target(a, pid, tol2, b2, q2)) {
             if (threadIdx.x == 0) {
                 a.stats[pid].iters = 0;
                 a.stats[pid].converged = 1;
@@ -358,11 +367,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
             const int id = (zz * ny + yy) * nx + xx;
             const double bv = b[id];
             bb += bv * bv;
-            if (sres)
-                rv = (a.start_res == 2 && spectral_pair(P) && !near_face(xx, nx) && !near_face(yy, ny) &&
-                      !near_face(zz, nz)) ? 0.0 : br[id];
-            else
-                rv = bv;
+            rv = sres ? br[id] : bv;
             if (fold) c0 = (T)x[id];
             if (!sres) x[id] = 0.0;
         }
@@ -582,7 +587,6 @@ __global__ __launch_bounds__(FIN_BS) void k_start_residual(ExxArgs a) {
     const int pid = blockIdx.x;
     const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
-    if (a.skip_spectral && spectral_pair(P)) return;
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const int n = nx * ny * nz, nxy = nx * ny;
     const double ih2 = 1.0 / (C.h[0] * C.h[0]);
@@ -599,26 +603,47 @@ __global__ __launch_bounds__(FIN_BS) void k_start_residual(ExxArgs a) {
 // z-march above on FP64 planes.  A workgroup owns 16 rows (y) of one pair
 // and marches a window of 28 rows (6 more on each side, fetched again by the
 // neighbouring workgroups) so that its register queue (2 rows per thread,
-// 13 planes) fits; rows of the window outside the domain read zero.  Also
-// |b|^2 and |b - A x|^2 of the owned rows into a.rnorm[pair][tile][2].
+// 13 planes) fits; rows of the window outside the domain read zero.
+// Two launches: NORMS writes |b|^2 and |b - A x|^2 of the owned rows into
+// a.rnorm[pair][tile][2] and nothing else; WRITE stores b - A x into bres
+// for the pairs whose start does not meet the CG's exit test (from those
+// norms; the others return at once), so a start that is already converged
+// costs one read of x and b.
+// Workgroups are numbered so that the row tiles of one pair run together
+// on one XCD (workgroup k goes to XCD k mod 8): the rows a tile fetches
+// again for its neighbours' window are then served by the same L2.
 constexpr int RZ_NT = 1024;
 constexpr int RZ_COLS = 2;
 constexpr int RZ_ROWS = 16;   // rows owned per workgroup
+constexpr int RZ_XCD = 8;
 static_assert(RZ_TILES * RZ_ROWS >= 64, "row tiles cover 64 rows");
 
+__device__ __forceinline__ void rz_block(int& pid, int& tile) {
+    const int k = blockIdx.x, m = k / RZ_XCD;
+    pid = (m / RZ_TILES) * RZ_XCD + k % RZ_XCD;
+    tile = m % RZ_TILES;
+}
+
+template <bool WRITE>
 __global__ __launch_bounds__(RZ_NT) void k_residual_zm(ExxArgs a) {
     extern __shared__ unsigned char smem[];
     double* lds = reinterpret_cast<double*>(smem);
     __shared__ double red[RZ_NT / 64 + 1];
-    const int pid = blockIdx.x;
+    int pid, tile;
+    rz_block(pid, tile);
+    if (pid >= a.n_pairs) return;
     const sea_pair P = a.pairs[pid];
-    if (a.skip_spectral && spectral_pair(P)) return;   // the face residual has it
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    const int y0 = blockIdx.y * RZ_ROWS;
-    if (y0 >= ny) {
+    const int y0 = tile * RZ_ROWS;
+    if (WRITE) {
+        double b2, q2;
+        if (y0 >= ny || start_meets_target(a, pid, Delta<float>::target * Delta<float>::target * a.rel_tol * a.rel_tol,
+                                           b2, q2))
+            return;
+    } else if (y0 >= ny) {
         if (threadIdx.x == 0) {
-            a.rnorm[((size_t)pid * RZ_TILES + blockIdx.y) * 2] = 0.0;
-            a.rnorm[((size_t)pid * RZ_TILES + blockIdx.y) * 2 + 1] = 0.0;
+            a.rnorm[((size_t)pid * RZ_TILES + tile) * 2] = 0.0;
+            a.rnorm[((size_t)pid * RZ_TILES + tile) * 2 + 1] = 0.0;
         }
         return;
     }
@@ -650,16 +675,17 @@ __global__ __launch_bounds__(RZ_NT) void k_residual_zm(ExxArgs a) {
         [&](int c, int z, double s, double, double bv) {
             if (owned(c)) {
                 const double rv = bv - s;
-                r[((size_t)z * ny + grow(c)) * nx + tx] = rv;
+                if (WRITE) r[((size_t)z * ny + grow(c)) * nx + tx] = rv;
                 bb += bv * bv;
                 rr += rv * rv;
             }
         });
+    if (WRITE) return;
     bb = block_sum<RZ_NT>(bb, red);
     rr = block_sum<RZ_NT>(rr, red);
     if (threadIdx.x == 0) {
-        a.rnorm[((size_t)pid * RZ_TILES + blockIdx.y) * 2] = bb;
-        a.rnorm[((size_t)pid * RZ_TILES + blockIdx.y) * 2 + 1] = rr;
+        a.rnorm[((size_t)pid * RZ_TILES + tile) * 2] = bb;
+        a.rnorm[((size_t)pid * RZ_TILES + tile) * 2 + 1] = rr;
     }
 }
 
@@ -668,9 +694,13 @@ size_t residual_zm_lds_bytes() { return (size_t)2 * LW * LH * sizeof(double); }
 hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s) {
     if (a.n_pairs <= 0) return hipSuccess;
     const int lds = (int)residual_zm_lds_bytes();
-    hipError_t e = hipFuncSetAttribute((const void*)k_residual_zm, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    const unsigned nb = (unsigned)((a.n_pairs + RZ_XCD - 1) / RZ_XCD) * RZ_XCD * RZ_TILES;
+    hipError_t e = hipFuncSetAttribute((const void*)k_residual_zm<false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_residual_zm<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_residual_zm, dim3(a.n_pairs, RZ_TILES), dim3(RZ_NT), lds, s, a);
+    hipLaunchKernelGGL(k_residual_zm<false>, dim3(nb), dim3(RZ_NT), lds, s, a);
+    hipLaunchKernelGGL(k_residual_zm<true>, dim3(nb), dim3(RZ_NT), lds, s, a);
     return hipGetLastError();
 }
 

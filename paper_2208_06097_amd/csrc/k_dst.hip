@@ -10,10 +10,10 @@
 // each face.  With x0 the multipole start, the start is
 //   x = x0 + A_odd^-1 (b - A x0) = A_odd^-1 (b - D x0),
 // whose right-hand side the gather and the boundary kernel form (D x0 needs
-// x0 on those points only), and its residual is b - A x = -D (x - x0), again
-// a face-points-only quantity.  x leaves a residual many decades below that
-// of x0 because x0 already carries the multipole potential that sets the
-// boundary values.
+// x0 on those points only).  x leaves a residual many decades below that of
+// x0 because x0 already carries the multipole potential that sets the
+// boundary values; the CG's exit test then takes the true residual b - A x,
+// formed in FP64 by a stencil sweep over the whole domain.
 //
 // The transform along one axis is a dense product with the symmetric,
 // orthogonal matrix S_n[j][k] = sqrt(2/(n+1)) sin(pi (j+1)(k+1)/(n+1))
@@ -88,7 +88,6 @@ struct DstArgs {
     const double* opt;
     const double* mu;
     const double* add;    // plane pass: added to `in` on the face points (nullable)
-    double* bsum;         // plane pass: per workgroup sum of in^2 (nullable; FN_PARTS per pair)
 };
 
 // Products on the FP64 matrix cores (v_mfma_f64_16x16x4f64), 4 waves per
@@ -129,8 +128,7 @@ __device__ __forceinline__ void dst_ops(const double* opt, int n, int b, int lan
 // 2-D transform of every z plane of a pair, Y = S_y X S_x (X[y][x], x
 // contiguous), written in the plane's layout (the same kernel serves the
 // forward and the inverse transform: S is its own inverse).  With `add`,
-// the input is in + add on the points within 5 of a face (in elsewhere),
-// and with `bsum` the workgroup's sum of in^2 goes there.  Grid
+// the input is in + add on the points within 5 of a face (in elsewhere).  Grid
 // (pairs, DP_PG): workgroup y takes planes y, y + DP_PG, ...  The LDS array
 // holds X[y][x], then T transposed (T^T[c][y], c = 32 parity + i for the
 // x mode 2 i + parity), then Y[j][x].  Wave w: output block w % 2 of the
@@ -141,10 +139,7 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
     const sea_pair P = d.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     if (nx > DS_N || ny > DS_N || nz > DS_N) return;   // keeps the multipole start
-    if ((int)blockIdx.y >= nz) {   // no plane here: the workgroup's partial sums are zero
-        if (threadIdx.x == 0 && d.bsum) d.bsum[(size_t)pid * FN_PARTS + blockIdx.y] = 0.0;
-        return;
-    }
+    if ((int)blockIdx.y >= nz) return;   // no plane here
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int hb = w & 1, bp = 2 * (w >> 1);
@@ -175,7 +170,6 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
     const double* in = d.in + (size_t)pid * d.stride;
     double* out = d.out + (size_t)pid * d.stride;
     const double* add = d.add ? d.add + (size_t)pid * d.stride : nullptr;
-    double bsq = 0.0;
     for (int z = blockIdx.y; z < nz; z += DP_PG) {
         const size_t zo = (size_t)z * npl;
         int gk = g;
@@ -196,10 +190,7 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
                 ad[u] = (zf || near_face(xx, nx) || near_face(yy, ny)) ? add[zo + e] : 0.0;
             });
 #pragma unroll
-            for (int u = 0; u < DP_PT; ++u) {
-                bsq += val[u] * val[u];
-                val[u] += ad[u];
-            }
+            for (int u = 0; u < DP_PT; ++u) val[u] += ad[u];
         }
         __syncthreads();
         for_elems([&](int u, int, int o) { B[o] = val[u]; });
@@ -255,19 +246,6 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
         }
         __syncthreads();
         for_elems([&](int, int e, int o) { out[zo + e] = B[o]; });
-    }
-    if (d.bsum) {
-        __shared__ double red[DP_BS / 64];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) bsq += __shfl_down(bsq, off, 64);
-        __syncthreads();
-        if (lane == 0) red[w] = bsq;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int k = 0; k < DP_BS / 64; ++k) t += red[k];
-            d.bsum[(size_t)pid * FN_PARTS + blockIdx.y] = t;
-        }
     }
 }
 
@@ -389,7 +367,7 @@ size_t dst_mu_doubles() { return (size_t)mu_off(DS_N + 1); }
 // x = S^-1 ((S (b + fcorr)) ./ lambda) for every pair whose axes are all <=
 // 64 (fcorr added on the face points; it lives in tmp, scratch of the pair
 // arrays' size, which the passes then overwrite); r is scratch of the same
-// size; |b|^2 per workgroup into a.fnorm.
+// size.
 hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, hipStream_t s,
                                  const std::function<void(bool)>& mark) {
     if (a.n_pairs <= 0) return hipSuccess;
@@ -407,11 +385,9 @@ hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, doubl
     // inverse: tmp -> r; planes inverse: r -> x
     d.in = a.b;
     d.add = tmp;
-    d.bsum = a.fnorm;
     d.out = tmp;
     hipLaunchKernelGGL(k_dst_plane, grid, dim3(DP_BS), 0, s, d);
     d.add = nullptr;
-    d.bsum = nullptr;
     d.in = tmp;
     d.out = r;
     hipLaunchKernelGGL(k_dst_zline, grid, dim3(DP_BS), 0, s, d);

@@ -746,80 +746,6 @@ __global__ __launch_bounds__(GM_BS) void k_face_z(ExxArgs a) {
         fc[z * npl + t] -= face_taps(z, nz, [&](int q) { return x0[q * npl + t]; }) * ihz;
 }
 
-// The spectral start's two face quantities.  D = A - A_odd is the
-// difference between the stencil with zero values past the faces (A) and
-// with the odd continuation the sine transform diagonalizes (A_odd); per
-// axis it lives on the 5 points next to each face and reads values there
-// only, on the same line along the axis.  The right-hand-side correction
-// -D x0 (so that A_odd^-1 (b - D x0) = x0 + A_odd^-1 (b - A x0)) comes from
-// k_me_face and k_face_z; this kernel forms, after the transform
-// (A_odd x = b - D x0), the residual r = b - A x = -D (x - x0) into bres
-// (up to the transform's rounding, the stencil residual), and per plane the
-// sum of r^2 into a.fnorm.
-// One workgroup per plane: the plane's face values x - x0 meet in LDS for
-// the taps along x and y; on the planes next to a z face the taps along z
-// read their mirror planes directly.  Each face point is written once with
-// the sum over its axes; off the face points bres is not written (and x, x0
-// are not read).
-__global__ __launch_bounds__(GM_BS) void k_face_residual(ExxArgs a) {
-    // only the plane's frame is kept (the taps along x and y read values
-    // within FF_W of the face they cross): rows' ends and columns' ends
-    __shared__ double Ex[64][2 * FF_W + 1];
-    __shared__ double Ey[2 * FF_W][65];
-    __shared__ double red[GM_BS / 64 + 1];
-    const int pid = blockIdx.x, z = blockIdx.y;
-    const sea_pair P = a.pairs[pid];
-    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    if (!spectral_pair(P) || z >= nz) return;
-    const DevCell C = a.cells[a.pair_cell[pid]];   // copied: fields stay in registers across stores
-    const double ihx = 1.0 / (C.h[0] * C.h[0]), ihy = 1.0 / (C.h[1] * C.h[1]), ihz = 1.0 / (C.h[2] * C.h[2]);
-    const size_t po = (size_t)pid * a.stride, npl = (size_t)nx * ny;
-    const double* x0 = a.x0 + po;
-    const double* x = a.v + po;
-    auto val = [&](size_t o) { return x[o] - x0[o]; };
-    const bool zf = near_face(z, nz);
-    for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
-        const bool fx = near_face(xx, nx), fy = near_face(yy, ny);
-        if (fx || fy) {
-            const double v = val(z * npl + (size_t)yy * nx + xx);
-            if (fx) Ex[yy][frame_k(xx, nx)] = v;
-            if (fy) Ey[frame_k(yy, ny)][xx] = v;
-        }
-    });
-    __syncthreads();
-    double rr = 0.0;
-    double* out = a.bres + po;
-    for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
-        double t = 0.0;
-        if (near_face(xx, nx)) t += face_taps(xx, nx, [&](int q) { return Ex[yy][frame_k(q, nx)]; }) * ihx;
-        if (near_face(yy, ny)) t += face_taps(yy, ny, [&](int q) { return Ey[frame_k(q, ny)][xx]; }) * ihy;
-        if (zf) {
-            const size_t col = (size_t)yy * nx + xx;
-            t += face_taps(z, nz, [&](int q) { return val(q * npl + col); }) * ihz;
-        }
-        out[z * npl + (size_t)yy * nx + xx] = -t;
-        rr += t * t;
-    });
-    rr = block_sum<GM_BS>(rr, red);
-    if (threadIdx.x == 0) a.fnorm[(size_t)pid * FN_PARTS + DP_PG + z] = rr;
-}
-
-// |b|^2 and |r|^2 of a pair from the partial sums (the transform's first
-// pass, one per workgroup, then the residual's, per axis and workgroup), in
-// a fixed order, into tile 0 of a.rnorm (the other tiles zero).
-__global__ __launch_bounds__(64) void k_face_norms(ExxArgs a) {
-    const int pid = blockIdx.x * 64 + threadIdx.x;
-    if (pid >= a.n_pairs || !spectral_pair(a.pairs[pid])) return;
-    const double* f = a.fnorm + (size_t)pid * FN_PARTS;
-    double bb = 0.0, rr = 0.0;
-    for (int k = 0; k < DP_PG; ++k) bb += f[k];
-    for (int k = 0; k < a.pairs[pid].n[2]; ++k) rr += f[DP_PG + k];
-    for (int t = 0; t < RZ_TILES; ++t) {
-        a.rnorm[((size_t)pid * RZ_TILES + t) * 2] = t == 0 ? bb : 0.0;
-        a.rnorm[((size_t)pid * RZ_TILES + t) * 2 + 1] = t == 0 ? rr : 0.0;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // 3c. learned start: corner-aligned trilinear maps between a pair domain
 //     (n per axis) and the network grid (D per axis).  Sample k of D sits at
@@ -1116,12 +1042,6 @@ hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s) {
 hipError_t launch_face_corr(const ExxArgs& a, int nz_max, hipStream_t s) {
     (void)nz_max;
     hipLaunchKernelGGL(k_face_z, dim3(a.n_pairs, 2 * FF_W), dim3(GM_BS), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_face_residual(const ExxArgs& a, int nz_max, hipStream_t s) {
-    hipLaunchKernelGGL(k_face_residual, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
-    hipLaunchKernelGGL(k_face_norms, dim3((a.n_pairs + 63) / 64), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

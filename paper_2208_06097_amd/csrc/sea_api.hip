@@ -231,7 +231,6 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.dst_mu = spectral ? take(dst_mu_doubles() * sizeof(double)) : 0;
     L.rnorm = spectral ? take(np * RZ_TILES * 2 * sizeof(double)) : 0;
     L.x0 = spectral ? take(np * stride * sizeof(double)) : 0;
-    L.fnorm = spectral ? take(np * FN_PARTS * sizeof(double)) : 0;
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
     L.csr_off = take((S.csr_off.size() + 1) * sizeof(int));
@@ -499,11 +498,10 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.queue_ctr = (int*)(base + Ly.counter);
     a.x_nonzero = ctx->opts.start != SEA_START_ZERO;
     a.bres = Ly.bres ? (double*)(base + Ly.bres) : nullptr;
-    // spectral start: x0 on the face points, -D x0 there (in the transform's
-    // scratch array), and the partial sums of the norms
+    // spectral start: x0 on the face points and -D x0 there (in the
+    // transform's scratch array)
     a.x0 = Ly.x0 ? (double*)(base + Ly.x0) : nullptr;
     a.fcorr = Ly.dst_tmp ? (double*)(base + Ly.dst_tmp) : nullptr;
-    a.fnorm = Ly.fnorm ? (double*)(base + Ly.fnorm) : nullptr;
     a.nmax = Ly.nmax;
     return a;
 }
@@ -573,9 +571,10 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                 SEA_HIP_CHECK(ctx, launch_nn_apply(a, kNnGrid, y32, s));
             }
             if (spectral) {
-                // x = A_odd^-1 (b - D x0); then, for the FP32 z-march, bres = b - A x
-                // on the face points and the norms (the FP64 kernel forms its
-                // residual itself)
+                // x = A_odd^-1 (b - D x0); then, for the FP32 z-march, the true
+                // residual b - A x in FP64: its norms for every pair, and bres
+                // for the pairs whose start is not yet converged (the FP64
+                // kernel forms its residual itself)
                 SEA_HIP_CHECK(ctx, launch_spectral_start(a, a.bres, (double*)(base + Ly.dst_tmp),
                                                          (double*)(base + Ly.dst_tab), (double*)(base + Ly.dst_mu), s,
                                                          [&](bool begin) {
@@ -585,8 +584,6 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                 if (zm) {
                     ExxArgs ar = a;
                     ar.rnorm = (double*)(base + Ly.rnorm);
-                    ar.skip_spectral = 1;
-                    SEA_HIP_CHECK(ctx, launch_face_residual(ar, nz_max, s));
                     const bool rzm = residual_zm_lds_bytes() <= ctx->max_lds;
                     SEA_HIP_CHECK(ctx, rzm ? launch_residual_zm(ar, s) : launch_start_residual(ar, s));
                 }
@@ -599,9 +596,9 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         if (zm) {
             const int var = ctx->opts.cg_variant >= 0 ? ctx->opts.cg_variant : (ctx->cg_tuned >= 0 ? ctx->cg_tuned : 0);
             ExxArgs az = a;
-            // spectral start: bres holds b - A x on the face points of the pairs the
-            // transform took (zero elsewhere), and everywhere for the others
-            az.start_res = ctx->opts.start == SEA_START_SPECTRAL ? 2 : 0;
+            // spectral start: x is the FP64 start and bres = b - A x (rnorm: its
+            // norms decide first, and bres is only there for the pairs they fail)
+            az.start_res = ctx->opts.start == SEA_START_SPECTRAL ? 1 : 0;
             az.rnorm = (az.start_res && residual_zm_lds_bytes() <= ctx->max_lds) ? (double*)(base + Ly.rnorm) : nullptr;
             SEA_HIP_CHECK(ctx, launch_cg_zm(az, var, s));
             timer_off(SEA_STAGE_CG);

@@ -59,7 +59,7 @@ struct StageTimer {
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
     size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, slots, stats, csr_off, csr_ent, scal, counter;
-    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, x0, fnorm, mpoly, total;
+    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, x0, mpoly, total;
     int nmax;
     int n_chunks;
     int n_zchunks;
@@ -101,7 +101,6 @@ struct ExxArgs {
     double* b;            // n_pairs x stride
     double* x0;           // spectral start: the multipole start on the points within 5 of a face (nullable)
     double* fcorr;        // spectral start: -D x0 on the face points (the transform's scratch array)
-    double* fnorm;        // spectral start: n_pairs x FN_PARTS partial sums of |b|^2 and |r|^2
     double* v;            // n_pairs x stride
     size_t stride;
     double* slots;        // n_slots x 3 x slot_stride elements (state precision)
@@ -116,9 +115,7 @@ struct ExxArgs {
     const int* order;     // CG queue order: pair ids by decreasing domain size (nullable)
     const int* dbox;      // per pair 12 ints: boxes where W_i and W_j take the pair
     int x_nonzero;        // v holds a start guess on entry to the CG
-    int start_res;        // FP32 z-march: bres already holds b - A x in FP64 (x kept as the FP64 start);
-                          // 2: only on the face points (near_face on some axis), zero elsewhere
-    int skip_spectral;    // residual kernels: leave out the pairs the sine transform took
+    int start_res;        // FP32 z-march: bres already holds b - A x in FP64 (x kept as the FP64 start)
     double* rnorm;        // n_pairs x RZ_TILES x 2: |b|^2, |b - A x|^2 per row tile of the FP64 residual z-march (nullable)
     double* bres;         // n_pairs x stride: b - A x0 when x_nonzero
     int nmax;             // largest domain extent over pairs and axes
@@ -174,25 +171,21 @@ hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s);
 hipError_t launch_me_face(const ExxArgs& a, int nz_max, hipStream_t s);
 // -D x0 into a.fcorr on the face points
 hipError_t launch_face_corr(const ExxArgs& a, int nz_max, hipStream_t s);
-// r = b - A x = -D (x - x0) into bres on the face points, |b|^2 and |r|^2
-// into a.rnorm, for the pairs the sine transform took
-hipError_t launch_face_residual(const ExxArgs& a, int nz_max, hipStream_t s);
 constexpr double kPi = 3.14159265358979323846;
 constexpr int DP_PG = 16;   // sine-transform workgroups per pair
-// partial sums per pair in a.fnorm: |b|^2 per sine-transform workgroup,
-// then |r|^2 per plane (at most 64 planes for the pairs the transform takes)
-constexpr int FN_PARTS = DP_PG + 64;
 hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s);
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s);
 hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
-// b - A x in FP64 by z-march (cubic grids, nx, ny <= 64) and the two norms
-// per pair into a.rnorm.
+// b - A x in FP64 by z-march (cubic grids, nx, ny <= 64), in two launches:
+// the norms |b|^2 and |b - A x|^2 per pair into a.rnorm (nothing else
+// written), then b - A x into bres for the pairs whose start does not meet
+// the FP32 z-march CG's exit test (the others are left alone).
 constexpr int RZ_TILES = 4;   // row tiles of 16 per pair in the residual z-march
 size_t residual_zm_lds_bytes();
 hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s);
 // Spectral start (k_dst.hip): x = A_odd^-1 (b + a.fcorr on the face points)
 // for the pairs with every axis <= 64 (a.fcorr is tmp, scratch of the pair
-// arrays' size; r scratch of the same size); |b|^2 partials into a.fnorm.
+// arrays' size; r scratch of the same size).
 size_t dst_table_doubles();
 size_t dst_mu_doubles();
 // `mark(true)` / `mark(false)` bracket the three transform passes (stage timing).
