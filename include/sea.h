@@ -320,6 +320,25 @@ sea_status sea_ace_apply(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, con
                          int n_vec, const void *psi_dev, void *ws_dev, size_t ws_bytes,
                          void *out_dev);
 
+/* Allocation-free K psi, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same product and arguments as sea_ace_apply without the
+ * workspace: the library works in a static device array of
+ * SEA_NOALLOC_SCRATCH_BYTES that each GPU it runs on holds from module load
+ * until the process ends (its address is looked up once per device in
+ * sea_create).  It holds C = dV xi^T psi (n_occ x n_vec FP64) and the K-slice
+ * partials of that product (at least one slice of n_occ x n_vec FP64, more
+ * slices when there is room; the result matches sea_ace_apply to the
+ * rounding of a different slicing).  Returns SEA_E_NOMEM when
+ * 16 n_occ n_vec bytes exceed the array (n_occ = n_vec = 1448 at most).
+ * Enqueued on opts.hip_stream, no host synchronization, no allocation.
+ * Every call on one GPU shares the array and it keeps the last call's
+ * contents: calls that overlap on one GPU (another stream, another thread,
+ * another context) race.  The current device must be the context's. */
+#define SEA_NOALLOC_SCRATCH_BYTES (32u << 20)
+sea_status sea_ace_apply_noalloc(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, const void *xi_dev,
+                                 int n_vec, const void *psi_dev, void *out_dev);
+
 /* E_xx = -sum_ik <phi_i, xi_k>^2 (Eq. 19): FP64 products (xi of any
  * ace_dtype converts exactly), FP64 result on the host. */
 sea_status sea_ace_energy(sea_ctx *ctx, int64_t n_grid, int n_occ, double dV, const double *phi_dev,

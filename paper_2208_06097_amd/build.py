@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsea.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["sea_api.hip", "k_exx.hip", "k_cg.hip", "k_ace.hip", "k_nn.hip", "k_nn_mfma.hip", "k_ace_mfma.hip", "k_eps.hip", "k_scdm.hip", "k_dst.hip", "k_scatter.hip"]
+SOURCES = ["sea_api.hip", "k_exx.hip", "k_cg.hip", "k_ace.hip", "k_nn.hip", "k_nn_mfma.hip", "k_ace_mfma.hip", "k_eps.hip", "k_scdm.hip", "k_dst.hip", "k_scatter.hip", "sea_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

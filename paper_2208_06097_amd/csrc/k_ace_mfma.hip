@@ -260,19 +260,20 @@ __global__ __launch_bounds__(NT) void k_nn_mfma(const double* __restrict__ A, lo
 
 }  // namespace
 
-int ace_mfma_splits(long K, int m, int n) {
+int ace_mfma_splits(long K, int m, int n, int max_splits) {
     const long tiles = (long)((m + BM - 1) / BM) * ((n + BN - 1) / BN);
     long s = (1024 + tiles - 1) / tiles;
     const long maxs = (K + 2047) / 2048;
     if (s > maxs) s = maxs;
+    if (max_splits > 0 && s > max_splits) s = max_splits;
     if (s < 1) s = 1;
     return (int)s;
 }
 
 template <int KIND, typename TA, typename TB>
 hipError_t ace_mm_nt(const TA* A, const TB* B, int m, int n, long K, double alpha, double* part, double* C,
-                     hipStream_t s) {
-    const int splits = ace_mfma_splits(K, m, n);
+                     hipStream_t s, int max_splits) {
+    const int splits = ace_mfma_splits(K, m, n, max_splits);
     long kslice = (K + splits - 1) / splits;
     kslice = (kslice + KT - 1) / KT * KT;
     dim3 grid((n + BN - 1) / BN, (m + BM - 1) / BM, splits);
@@ -293,7 +294,8 @@ hipError_t ace_mm_nn(const double* A, long sai, long sak, const TB* B, int m, in
 }
 
 #define NT_INST(KIND, TA, TB) \
-    template hipError_t ace_mm_nt<KIND, TA, TB>(const TA*, const TB*, int, int, long, double, double*, double*, hipStream_t);
+    template hipError_t ace_mm_nt<KIND, TA, TB>(const TA*, const TB*, int, int, long, double, double*, double*, \
+                                                hipStream_t, int);
 #define NN_INST(KIND, TB, TC)                                                                                      \
     template hipError_t ace_mm_nn<KIND, TB, TC>(const double*, long, long, const TB*, int, int, long, double, TC*, \
                                                 hipStream_t);

@@ -322,6 +322,7 @@ sea_status sea_create(const sea_opts* opts, sea_ctx** out) {
         return SEA_E_HIP;
     }
     ctx->device = dev;
+    ctx->noalloc_scratch = noalloc_scratch_setup(dev);
     ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     ctx->max_lds = prop.sharedMemPerBlock;
     bool ok = true;

@@ -38,7 +38,13 @@ struct sea_ctx {
     bool ev_ready = false;
     const void* nn_state = nullptr;   // attached network (learned start)
     int cg_tuned = -1;                // z-march variant chosen by sea_exx_autotune
+    void* noalloc_scratch = nullptr;  // device address of this device's static scratch array
 };
+
+// Looks up, once per device, the device address of the static scratch array
+// of the allocation-free entry point (sea_noalloc.hip); call with `dev`
+// current.  nullptr if the lookup failed.
+void* noalloc_scratch_setup(int dev);
 
 // Records the begin/end event of a stage when profiling is on.
 struct StageTimer {

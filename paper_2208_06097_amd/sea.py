@@ -34,7 +34,12 @@ EXPORTS = [
     "sea_cg_variant_count", "sea_cg_variant_name", "sea_exx_autotune",
     "sea_nn_infer_workspace_bytes", "sea_nn_infer", "sea_eps_workspace_bytes", "sea_build_pairs_eps",
     "sea_successive_idempotency", "sea_scdm_workspace_bytes", "sea_scdm", "sea_rotate",
+    "sea_ace_apply_noalloc",
 ]
+
+# size of the library's static scratch array per GPU (SEA_NOALLOC_SCRATCH_BYTES
+# in include/sea.h), which sea_ace_apply_noalloc works in
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 # the network's layers (name, c_in, c_out, relu), in parameter order
 NN_LAYERS = [
@@ -126,6 +131,7 @@ def load() -> C.CDLL:
     lib.sea_ace_build.argtypes = [vp, C.c_int64, i, d, vp, vp, vp, sz, vp, vp, vp, P(i)]
     lib.sea_ace_apply.argtypes = [vp, C.c_int64, i, d, vp, i, vp, vp, sz, vp]
     lib.sea_ace_energy.argtypes = [vp, C.c_int64, i, d, vp, vp, vp, sz, P(d)]
+    lib.sea_ace_apply_noalloc.argtypes = [vp, C.c_int64, i, d, vp, i, vp, vp]
     lib.sea_solid_harmonics_host.argtypes = [i, d, d, d, vp]
     lib.sea_stage_times.argtypes = [vp, vp]
     lib.sea_nn_param_count.restype = C.c_size_t
@@ -482,6 +488,26 @@ class Context:
                                     ws.numel(), out.data_ptr())
         self._check(st)
         return out
+
+    def ace_apply_noalloc(self, xi, psi, dV, out=None):
+        """K psi through sea_ace_apply_noalloc: no workspace; the library
+        works in its static scratch array (calls that overlap on one GPU race)."""
+        torch = self._torch
+        n_occ = xi.shape[0]
+        n_vec = psi.shape[0]
+        ng = xi.numel() // n_occ
+        out_dtype = torch.float32 if self.opts.ace_dtype == SEA_BF16 else self._xi_torch_dtype()
+        assert psi.dtype == self._xi_torch_dtype(), "psi must be in the context's ace_dtype"
+        if out is None:
+            out = torch.empty(psi.shape, dtype=out_dtype, device=psi.device)
+        st = self.lib.sea_ace_apply_noalloc(self.h, ng, n_occ, dV, xi.data_ptr(), n_vec, psi.data_ptr(),
+                                            out.data_ptr())
+        self._check(st)
+        return out
+
+    @staticmethod
+    def noalloc_scratch_bytes() -> int:
+        return NOALLOC_SCRATCH_BYTES
 
     def ace_energy(self, phi, xi, dV, ws=None) -> float:
         n_occ = phi.shape[0]

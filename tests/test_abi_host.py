@@ -25,6 +25,13 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(sea.EXPORTS) | {"sea_version"}
 
 
+def test_noalloc_scratch_size_matches_the_header():
+    txt = open(HEADER).read()
+    m = re.search(r"#define\s+SEA_NOALLOC_SCRATCH_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", txt)
+    assert m, "SEA_NOALLOC_SCRATCH_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == sea.NOALLOC_SCRATCH_BYTES
+
+
 def test_stage_names_cover_the_stage_enum():
     txt = open(HEADER).read()
     count = int(re.search(r"SEA_STAGE_COUNT\s*=\s*(\d+)", txt).group(1))
