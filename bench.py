@@ -94,9 +94,16 @@ FORMS = {
 
 
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
-CG_PROFILE = os.path.join(PROFILES, "k_cg_zm_buf_xc_learned_c2.md")
-DST_PROFILE = os.path.join(PROFILES, "k_dst_spectral_c2.md")
-SCATTER_PROFILE = os.path.join(PROFILES, "k_scatter_spectral_c2.md")
+# rocprofv3 summaries with the FETCH_SIZE / WRITE_SIZE traffic of a kernel
+PROFILE_OF = {
+    "k_scatter": "k_scatter_spectral_c2.md",
+    "k_dst_plane": "k_dst_plane_spectral_c2.md",
+    "k_dst_zline": "k_dst_zline_spectral_c2.md",
+    "k_residual_zm": "k_residual_zm_spectral_c2.md",
+    "k_gather_cart": "k_gather_cart_spectral_c2.md",
+    "k_cg_zm": "k_cg_zm_learned_c2.md",
+    "k_cg_f64": "k_cg_f64_plain_c2.md",
+}
 
 
 def measured_traffic(path, **match):
@@ -123,6 +130,76 @@ def measured_traffic(path, **match):
     return rec["bytes_per_launch"]
 
 
+def _kernel(name, ms_per_action, launches, bytes_per_launch, per_unit, traffic=None, **extra):
+    launch_ms = ms_per_action / launches if launches else 0.0
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else 0.0
+    d = {"kernel": name, "bound": "hbm", "ms_per_action": ms_per_action, "launches_per_action": launches,
+         "launch_ms": launch_ms, "bytes": bytes_per_launch, "achieved_gbs": achieved,
+         "frac": achieved / HBM_PEAK_GBS, "per_unit": per_unit, "traffic": traffic}
+    d.update(extra)
+    return d
+
+
+def kernel_rooflines(form, stages, pairs, npts, stats, cell, n_pairs, tune, wbytes):
+    """Per-kernel HBM rooflines of one V_xx action: HIP-event stage times of
+    the kernels timed alone (ms per action), algorithmic bytes per launch,
+    and the copy-calibrated counter traffic where a summary taken on the
+    current sources and the same workload is committed."""
+    import numpy as np
+    tr = lambda k, **m: measured_traffic(os.path.join(PROFILES, PROFILE_OF[k]), form=form, n_pairs=n_pairs, **m)  # noqa: E731
+    out = {}
+    # gather: both orbitals read, b written (FP64), moments folded in registers
+    out["k_gather_cart"] = _kernel("k_gather_cart", stages["gather"], 1, float(np.sum(npts) * 24.0),
+                                   "24 B per pair-domain point (phi_i, phi_j read, b written; FP64)",
+                                   tr("k_gather_cart"), note="stage also holds the two small moment kernels")
+    # owner-computes scatter: per pair side (one for i == j) the potential and
+    # the partner orbital are read once at every domain point (FP64 each), and
+    # W is written once
+    sides = np.where(pairs["i"] == pairs["j"], 1.0, 2.0)
+    out["k_scatter"] = _kernel("k_scatter", stages["scatter"], 1,
+                               float(np.sum(sides * npts) * 16.0 + cell.n_occ * cell.N ** 3 * 8.0),
+                               "per pair side 16 B (v and the partner orbital, FP64) per domain point, plus 8 B per "
+                               "W element written (the owner orbital's load for the pair energies not counted)",
+                               tr("k_scatter"))
+    if FORMS[form]["start"] == "spectral":
+        tf = np.all(pairs["n"] <= 64, axis=1)
+        pb = float(np.sum(npts[tf]) * 16.0)
+        fl = float(np.sum(npts[tf] * pairs["n"][tf].sum(axis=1)))   # one direction of the folded product, 3 axes
+        unit = "16 B (one FP64 read and write) per pair-domain point per pass"
+        out["k_dst_plane"] = _kernel("k_dst_plane", stages["dst_plane_fwd"] + stages["dst_plane_inv"], 2, pb,
+                                     unit + " (forward and inverse 2-D transforms)", tr("k_dst_plane"))
+        out["k_dst_zline"] = _kernel("k_dst_zline", stages["dst_zline"], 1, pb,
+                                     unit + " (z transforms, division, inverse z transforms)", tr("k_dst_zline"))
+        for k in ("k_dst_plane", "k_dst_zline"):
+            # flops per launch: two folded transforms of n_axis flops per point
+            # (planes: along x and y; z lines: forward and inverse along z)
+            f = 2.0 * fl / 3.0
+            out[k]["fp64_tflops"] = f / (out[k]["launch_ms"] * 1e-3) / 1e12 if out[k]["launch_ms"] > 0 else None
+        out["k_residual_zm"] = _kernel("k_residual_zm", stages["residual"], 1, float(np.sum(npts) * 16.0),
+                                       "16 B per pair-domain point (x and b read, FP64); a second launch writes "
+                                       "b - A x only for starts that miss the target", tr("k_residual_zm"))
+    else:
+        k = "k_cg_zm" if FORMS[form]["stencil"] == "f32" else "k_cg_f64"
+        cgb = float(np.sum(stats["iters"].astype(np.float64) * 6.0 * npts * wbytes))
+        out[k] = _kernel(k if k == "k_cg_f64" else f"k_cg_zm<float, {tune['variant'] if tune else ''}>",
+                         stages["cg"], 1, cgb, f"6 words x {int(wbytes)} B per interior point per CG iteration",
+                         tr(k, cg_iters_total=int(stats["iters"].sum())))
+    return out
+
+
+def cg_roofline(form, cg_ms, stats, npts):
+    """The CG kernel of a form against the HBM roofline: 6 state words per
+    interior point per iteration (None when the form iterates nowhere)."""
+    import numpy as np
+    w = 4.0 if FORMS[form]["stencil"] == "f32" else 8.0
+    b = float(np.sum(stats["iters"].astype(np.float64) * 6.0 * npts * w))
+    if b == 0.0 or cg_ms <= 0.0:
+        return None
+    gbs = b / (cg_ms * 1e-3) / 1e9
+    return {"kernel": "k_cg_zm<float>" if w == 4.0 else "k_cg_f64", "ms": cg_ms, "bytes": b,
+            "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +217,7 @@ def main():
     ap.add_argument("--tune-pairs", type=int, default=2048, help="pairs sampled by the CG kernel autotuner")
     ap.add_argument("--cg-variant", default=None,
                     help="fixed FP32 CG kernel variant (skips the autotuner; for profiling runs)")
+    ap.add_argument("--form-calls", type=int, default=5, help="event-timed calls per other form (median)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 2 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -277,36 +355,18 @@ def main():
     vxx_ms = float(np.median(vxx_steps))   # median over the timed steps (HIP events around the call)
     wbytes = 4.0 if FORMS[form]["stencil"] == "f32" else 8.0
     npts = np.prod(pairs["n"].astype(np.float64), axis=1)
-    # owner-computes scatter: per pair side (one for i == j) the potential and
-    # the partner orbital are read once at every domain point (FP64 each),
-    # and W is written once
-    sides = np.where(pairs["i"] == pairs["j"], 1.0, 2.0)
-    scatter_bytes = float(np.sum(sides * npts) * 16.0 + cell.n_occ * cell.N ** 3 * 8.0)
-    tf = np.all(pairs["n"] <= 64, axis=1)
-    dst = {"kernels": "k_dst_plane (forward), k_dst_zline, k_dst_plane (inverse)", "launches_per_action": 3,
-           "launch_ms": stages["dst"] / 3.0,
-           "bytes": float(np.sum(npts[tf]) * 16.0),
-           "flops": float(np.sum(npts[tf] * 2.0 * pairs["n"][tf].sum(axis=1))),
-           "per_unit": "per pass 16 B (one FP64 read and write) per pair-domain point; per point n_axis flops "
-                       "for each transform along an axis (the even/odd-folded sine product), forward and "
-                       "inverse along all three",
-           "traffic": measured_traffic(DST_PROFILE, form=form, n_pairs=n_pairs)}
-    dst["achieved_gbs"] = dst["bytes"] / (dst["launch_ms"] * 1e-3) / 1e9 if dst["launch_ms"] > 0 else None
-    dst["fp64_tflops"] = dst["flops"] / (3.0 * dst["launch_ms"] * 1e-3) / 1e12 if dst["launch_ms"] > 0 else None
-    if FORMS[form]["start"] == "spectral":
-        # dominant kernel: the scatter (the start leaves the CG nothing to do)
-        roof = {"kernel": "k_scatter", "launches_per_action": 1, "launch_ms": stages["scatter"],
-                "bytes": scatter_bytes, "flops": None,
-                "per_unit": "per pair side 16 B (v and the partner orbital, FP64) per domain point, plus 8 B per "
-                            "W element written",
-                "traffic": measured_traffic(SCATTER_PROFILE, form=form, n_pairs=n_pairs)}
-    else:
-        roof = {"kernel": "k_cg_zm<float>" if FORMS[form]["stencil"] == "f32" else "k_cg_f64",
-                "launches_per_action": 1, "launch_ms": stages["cg"],
-                "bytes": float(np.sum(stats["iters"].astype(np.float64) * 6.0 * npts * wbytes)), "flops": None,
-                "per_unit": f"6 words x {int(wbytes)} B per interior point per CG iteration",
-                "traffic": measured_traffic(CG_PROFILE, cg_variant=tune["variant"] if tune else None, form=form,
-                                            cg_iters_total=int(stats["iters"].sum()))}
+    kernels = kernel_rooflines(form, stages, pairs, npts, stats, cell, n_pairs, tune, wbytes)
+    # the dominant kernel: the most time per action among the kernels timed alone
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_action"])
+    roof = kernels[dom]
+    # the whole action against the algorithmic floor of its pair solves
+    # (one pair solve: I x 6 words x n_int of CG state plus about 12 words x
+    # n_dom of gather and scatter, FP64 words; I = iterations of that pair)
+    floor_bytes = float(np.sum(stats["iters"].astype(np.float64) * 6.0 * npts * wbytes + 12.0 * npts * 8.0))
+    action = {"bytes": floor_bytes, "ms": vxx_ms, "achieved_gbs": floor_bytes / (vxx_ms * 1e-3) / 1e9,
+              "frac": floor_bytes / (vxx_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "per_unit": "per pair I x 6 words x n_int (CG state, I its iterations) + 12 FP64 words x n_dom "
+                          "(gather and scatter)"}
     # M = Phi^T W on the FP64 matrix cores: 2 N_grid N_occ^2 flops
     ace_m_flops = 2.0 * cell.N ** 3 * cell.n_occ ** 2
     ace_m = {"kernel": "k_nt_mfma<double> (M = Phi^T W)", "ms": stages["ace_m"], "flops": ace_m_flops,
@@ -314,11 +374,12 @@ def main():
              "peak_tflops": FP64_MFMA_PEAK_TFLOPS}
     if ace_m["tflops"]:
         ace_m["frac"] = ace_m["tflops"] / FP64_MFMA_PEAK_TFLOPS
-    achieved = roof["bytes"] / (roof["launch_ms"] * 1e-3) / 1e9 if roof["launch_ms"] > 0 else 0.0
-    forms = {form: {"vxx_ms_per_call": vxx_ms, "cg_ms": stages["cg"], "guess_ms": stages["guess"],
+    forms = {form: {"vxx_ms_per_call": vxx_ms, "calls": args.steps, "cg_ms": stages["cg"], "guess_ms": stages["guess"],
                     "cg_iters_mean": float(stats["iters"].mean()), "E_xx": E, "E_ace": E_ace,
                     "dE_vs_oracle": (E - golden["E"]) if golden else None,
-                    "dE_ace_vs_oracle": (E_ace - golden["E"]) if golden else None}}
+                    "dE_ace_vs_oracle": (E_ace - golden["E"]) if golden else None,
+                    "cg_kernel": cg_roofline(form, stages["cg"], stats, npts),
+                    "action_frac": action["frac"]}}
     # ACE precision sweep on this step's W: xi and K psi on the matrix cores in
     # FP32 and BF16 (M, Cholesky and energy stay FP64), errors vs the FP64 path
     # and E vs the oracle's E_xx
@@ -352,14 +413,29 @@ def main():
             pick_variant(c2, fname, [(phi, cell.N, cell.L, pairs)], ws2)
             r2 = c2.exx_action(phi, cell.N, cell.L, pairs, ws=ws2, W=W, exx_dev=exx_dev, want_host=True)
             torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            c2.exx_action(phi, cell.N, cell.L, pairs, ws=ws2, W=W, exx_dev=exx_dev, want_host=False)
-            torch.cuda.synchronize()
+            # median of form_calls calls, HIP events around each on the context's stream
+            ms_calls, cg_calls = [], []
+            for _ in range(args.form_calls):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                c2.exx_action(phi, cell.N, cell.L, pairs, ws=ws2, W=W, exx_dev=exx_dev, want_host=False)
+                e1.record()
+                e1.synchronize()
+                ms_calls.append(e0.elapsed_time(e1))
+                cg_calls.append(c2.stage_times()["cg"])
             s2 = c2.stage_times()
-            forms[fname] = {"vxx_ms_per_call": 1000 * (time.perf_counter() - t1), "cg_ms": s2["cg"],
+            vms = float(np.median(ms_calls))
+            cgms = float(np.median(cg_calls))
+            fb = float(np.sum(r2[2]["iters"].astype(np.float64) * 6.0 * npts *
+                              (4.0 if FORMS[fname]["stencil"] == "f32" else 8.0) + 12.0 * npts * 8.0))
+            forms[fname] = {"vxx_ms_per_call": vms, "calls": args.form_calls, "cg_ms": cgms,
                             "guess_ms": s2["guess"], "cg_iters_mean": float(r2[2]["iters"].mean()), "E_xx": r2[1],
-                            "dE_vs_oracle": (r2[1] - golden["E"]) if golden else None}
-            log(f"form {fname}: {forms[fname]['vxx_ms_per_call']:.1f} ms, iters {forms[fname]['cg_iters_mean']:.1f}")
+                            "dE_vs_oracle": (r2[1] - golden["E"]) if golden else None,
+                            "cg_kernel": cg_roofline(fname, cgms, r2[2], npts),
+                            "action_frac": fb / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            log(f"form {fname}: {vms:.1f} ms (median of {args.form_calls}), iters "
+                f"{forms[fname]['cg_iters_mean']:.1f}, CG kernel "
+                f"{forms[fname]['cg_kernel']['frac'] if forms[fname]['cg_kernel'] else 0:.3f} of HBM peak")
             del ws2
             c2.close()
     # the paper's own truncation (eps-driven boxes, Eq. 16-17) on the same cell, for
@@ -476,15 +552,14 @@ def main():
         "ace_precision": ace,
         "eps_rule": eps_rule,
         "sea_chain": sea_chain,
-        "roofline": {"bound": "hbm", "kernel": roof["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "launch_ms": roof["launch_ms"], "launches_per_action": roof["launches_per_action"],
-                     "traffic": roof["traffic"],
+        "roofline": {"bound": roof["bound"], "kernel": roof["kernel"], "achieved": roof["achieved_gbs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": roof["frac"], "traffic": roof["traffic"],
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "algorithmic_bytes_per_launch": roof["bytes"],
+                     "launch_ms": roof["launch_ms"], "launches_per_action": roof["launches_per_action"],
+                     "ms_per_action": roof["ms_per_action"], "algorithmic_bytes_per_launch": roof["bytes"],
                      "per_unit": roof["per_unit"],
-                     "spectral_transform": dst if FORMS[form]["start"] == "spectral" else None,
-                     "ace_m": ace_m},
+                     "choice": "the kernel with the most time per V_xx action among those timed alone",
+                     "kernels": kernels, "action": action, "ace_m": ace_m},
     }
     if rank == 0 and not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -115,12 +115,20 @@ typedef enum {
     SEA_STAGE_ACE_CHOL = 7, /* Cholesky and L^{-1}                             */
     SEA_STAGE_ACE_XI = 8,   /* xi = W L^{-T}                                   */
     SEA_STAGE_ACE_APPLY = 9,/* K psi                                           */
-    SEA_STAGE_FINISH = 10,  /* FP32 state: true FP64 residual and e_ij per pair */
+    SEA_STAGE_FINISH = 10,  /* FP32 state: e_ij (from the scatter's partials   */
+                            /* when W is formed) and the flags per pair        */
     SEA_STAGE_SCDM = 11,    /* SCDM pivoted QR, P_CC^{-1/2} and U              */
     SEA_STAGE_ROTATE = 12,  /* orbital rotation by U or U^{-1}                 */
-    SEA_STAGE_DST = 13,     /* spectral start: the six sine-transform passes   */
+    SEA_STAGE_DST = 13,     /* spectral start: the three sine-transform passes */
                             /* (inside the GUESS stage)                        */
-    SEA_STAGE_COUNT = 14
+    /* single kernels of the spectral start (inside the stages above)          */
+    SEA_STAGE_DST_PLANE_FWD = 14, /* k_dst_plane, forward 2-D transforms       */
+    SEA_STAGE_DST_ZLINE = 15,     /* k_dst_zline, z transforms and division    */
+    SEA_STAGE_DST_PLANE_INV = 16, /* k_dst_plane, inverse 2-D transforms       */
+    SEA_STAGE_RESIDUAL = 17,      /* k_residual_zm: FP64 b - A x of the start  */
+    SEA_STAGE_FACE = 18,          /* x0 and -D x0 on the face points           */
+    SEA_STAGE_FOLD = 19,          /* multipole ghost values folded into b      */
+    SEA_STAGE_COUNT = 20
 } sea_stage;
 
 /* Per-pair diagnostics (Eq. 8 and Eq. 17 quantities on the pair domain). */

@@ -516,6 +516,10 @@ __global__ __launch_bounds__(NT) void k_cg_zm(ExxArgs a) {
 }
 
 // Pair energy e_ij = dV sum rho x and the final flags, one workgroup per pair.
+// With a.epart (after the scatter) a pair whose W box of orbital i holds its
+// domain once has its energy from the scatter's partials, summed here in
+// slot order; the others (and every pair without a.epart) sum rho x over
+// the domain here.
 constexpr int FIN_BS = 512;
 
 __global__ __launch_bounds__(FIN_BS) void k_cg_finish(ExxArgs a) {
@@ -528,37 +532,43 @@ __global__ __launch_bounds__(FIN_BS) void k_cg_finish(ExxArgs a) {
     const double* x = a.v + (size_t)pid * a.stride;
     const size_t oi = (size_t)P.i * C.Ng, oj = (size_t)P.j * C.Ng;
     double e = 0.0;
-    BoxWalk wk((int)threadIdx.x, FIN_BS, nx, ny);
-    // FIN_U points per thread at a time, their loads issued together; one
-    // copy per orbital precision, widened at the product.  The sum runs in
-    // the same order as one point at a time.
-    constexpr int FIN_U = 4;
-    auto run = [&](auto f32) {
-        using PT = typename std::conditional<decltype(f32)::value, float, double>::type;
-        typedef __attribute__((address_space(1))) const PT gPT;
-        const gPT* ph = (const gPT*)C.phi;
-        for (int id0 = threadIdx.x; id0 < n; id0 += FIN_U * FIN_BS) {
-            PT fi[FIN_U], fj[FIN_U];
-            double xv[FIN_U];
+    if (a.epart && ep_takes(P, a.dbox + 12 * (size_t)pid, C.N)) {
+        const int ns = ep_slots(P, C.N);
+        const double* ep = a.epart + (size_t)pid * a.ep_stride;
+        for (int k = threadIdx.x; k < ns; k += FIN_BS) e += ep[k];
+    } else {
+        BoxWalk wk((int)threadIdx.x, FIN_BS, nx, ny);
+        // FIN_U points per thread at a time, their loads issued together; one
+        // copy per orbital precision, widened at the product.  The sum runs in
+        // the same order as one point at a time.
+        constexpr int FIN_U = 4;
+        auto run = [&](auto f32) {
+            using PT = typename std::conditional<decltype(f32)::value, float, double>::type;
+            typedef __attribute__((address_space(1))) const PT gPT;
+            const gPT* ph = (const gPT*)C.phi;
+            for (int id0 = threadIdx.x; id0 < n; id0 += FIN_U * FIN_BS) {
+                PT fi[FIN_U], fj[FIN_U];
+                double xv[FIN_U];
 #pragma unroll
-            for (int k = 0; k < FIN_U; ++k) {
-                // past n the walk leaves the box along z, still a grid point
-                // after wrapping; x is then read at the box's last point
-                const size_t g = ((size_t)wrap_near(P.lo[2] + wk.z, C.N[2]) * C.N[1] + wrap_near(P.lo[1] + wk.y, C.N[1])) *
-                                     C.N[0] +
-                                 wrap_near(P.lo[0] + wk.x, C.N[0]);
-                fi[k] = ph[oi + g];
-                fj[k] = ph[oj + g];
-                xv[k] = x[min(id0 + k * FIN_BS, n - 1)];
-                wk.next();
+                for (int k = 0; k < FIN_U; ++k) {
+                    // past n the walk leaves the box along z, still a grid point
+                    // after wrapping; x is then read at the box's last point
+                    const size_t g = ((size_t)wrap_near(P.lo[2] + wk.z, C.N[2]) * C.N[1] + wrap_near(P.lo[1] + wk.y, C.N[1])) *
+                                         C.N[0] +
+                                     wrap_near(P.lo[0] + wk.x, C.N[0]);
+                    fi[k] = ph[oi + g];
+                    fj[k] = ph[oj + g];
+                    xv[k] = x[min(id0 + k * FIN_BS, n - 1)];
+                    wk.next();
+                }
+#pragma unroll
+                for (int k = 0; k < FIN_U; ++k)
+                    if (id0 + k * FIN_BS < n) e += (double)fi[k] * (double)fj[k] * xv[k];
             }
-#pragma unroll
-            for (int k = 0; k < FIN_U; ++k)
-                if (id0 + k * FIN_BS < n) e += (double)fi[k] * (double)fj[k] * xv[k];
-        }
-    };
-    if (C.phi_f32) run(std::true_type());
-    else run(std::false_type());
+        };
+        if (C.phi_f32) run(std::true_type());
+        else run(std::false_type());
+    }
     e = block_sum<FIN_BS>(e, red);
     if (threadIdx.x == 0) {
         DevStat st = a.stats[pid];

@@ -369,7 +369,7 @@ size_t dst_mu_doubles() { return (size_t)mu_off(DS_N + 1); }
 // arrays' size, which the passes then overwrite); r is scratch of the same
 // size.
 hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, hipStream_t s,
-                                 const std::function<void(bool)>& mark) {
+                                 const std::function<void(int, bool)>& mark) {
     if (a.n_pairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_dst_tables, dim3(DS_N), dim3(DS_BS), 0, s, tab, mu);
     DstArgs d{};
@@ -380,20 +380,24 @@ hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, doubl
     d.opt = tab;
     d.mu = mu;
     const dim3 grid((unsigned)a.n_pairs, DP_PG);
-    mark(true);
     // planes forward: b + fcorr (in tmp) -> tmp; z lines forward, divided,
     // inverse: tmp -> r; planes inverse: r -> x
     d.in = a.b;
     d.add = tmp;
     d.out = tmp;
+    mark(0, true);
     hipLaunchKernelGGL(k_dst_plane, grid, dim3(DP_BS), 0, s, d);
+    mark(0, false);
     d.add = nullptr;
     d.in = tmp;
     d.out = r;
+    mark(1, true);
     hipLaunchKernelGGL(k_dst_zline, grid, dim3(DP_BS), 0, s, d);
+    mark(1, false);
     d.in = r;
     d.out = a.v;
+    mark(2, true);
     hipLaunchKernelGGL(k_dst_plane, grid, dim3(DP_BS), 0, s, d);
-    mark(false);
+    mark(2, false);
     return hipGetLastError();
 }

@@ -808,7 +808,48 @@ __global__ __launch_bounds__(NNS_BS) void k_nn_sample(ExxArgs a, int D, float* _
     out[(size_t)pid * D3 + k] = s > 0.0 ? (float)(acc / s) : 0.0f;
 }
 
-// x += s * upsample(y32) on the pair domain
+// Cubic interpolation weights along one axis: fine point k of a `to`-grid
+// sits at coarse coordinate u = k (from - 1) / (to - 1) (corners aligned);
+// the 4-point Lagrange cubic through nodes i0 - 1 .. i0 + 2 (i0 = floor(u)),
+// with the nodes past either end continued oddly (y_{-1} = 2 y_0 - y_1,
+// y_from = 2 y_{from-1} - y_{from-2}), folded into 4 weights w[q] of nodes
+// base + q.  At a node (u integer) it is that node's value.
+struct Cub {
+    int base;
+    double w[4];
+};
+
+__device__ __forceinline__ Cub cubic_at(int k, int from, int to) {
+    Cub c{0, {0.0, 0.0, 0.0, 0.0}};   // needs from >= 4 (checked at launch)
+    const double u = to > 1 ? (double)k * (double)(from - 1) / (double)(to - 1) : 0.0;
+    int i0 = (int)floor(u);
+    if (i0 > from - 2) i0 = from - 2;
+    const double f = u - i0;
+    const double wq[4] = {-f * (f - 1.0) * (f - 2.0) / 6.0, (f + 1.0) * (f - 1.0) * (f - 2.0) / 2.0,
+                          -(f + 1.0) * f * (f - 2.0) / 2.0, (f + 1.0) * f * (f - 1.0) / 6.0};
+    c.base = min(max(i0 - 1, 0), from - 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = i0 - 1 + q;
+        if (j < 0) {
+            c.w[0 - c.base] += 2.0 * wq[q];
+            c.w[1 - c.base] -= wq[q];
+        } else if (j >= from) {
+            c.w[from - 1 - c.base] += 2.0 * wq[q];
+            c.w[from - 2 - c.base] -= wq[q];
+        } else {
+            c.w[j - c.base] += wq[q];
+        }
+    }
+    return c;
+}
+
+// x += s * upsample(y32) on the pair domain: tricubic interpolation of the
+// network grid (a fine point on a coarse node takes that node's value; with
+// 63 points per axis and a 32-point network grid every other point is one).
+// A trilinear map would leave the interpolant's second differences wrong by
+// a factor of 2 at every point, a high-frequency residual the CG then has
+// to remove.
 __global__ __launch_bounds__(GM_BS) void k_nn_apply(ExxArgs a, int D, const float* __restrict__ y32) {
     const int pid = blockIdx.x;
     const DevCell& C = a.cells[a.pair_cell[pid]];
@@ -824,14 +865,20 @@ __global__ __launch_bounds__(GM_BS) void k_nn_apply(ExxArgs a, int D, const floa
     double* x = a.v + (size_t)pid * a.stride;
     for (long id = beg + threadIdx.x; id < end; id += GM_BS) {
         const int ix = (int)(id % nx), iy = (int)((id / nx) % ny), iz = (int)(id / ((long)nx * ny));
-        const Lerp lx = lerp_at(ix, D, nx), ly = lerp_at(iy, D, ny), lz = lerp_at(iz, D, nz);
+        const Cub cx = cubic_at(ix, D, nx), cy = cubic_at(iy, D, ny), cz = cubic_at(iz, D, nz);
         double acc = 0.0;
+        for (int c = 0; c < 4; ++c) {
+            if (cz.w[c] == 0.0) continue;
+            double accy = 0.0;
+            for (int b = 0; b < 4; ++b) {
+                if (cy.w[b] == 0.0) continue;
+                const float* row = y + ((size_t)(cz.base + c) * D + cy.base + b) * D + cx.base;
+                double accx = 0.0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int cx = lx.i0 + (c & 1), cy = ly.i0 + ((c >> 1) & 1), cz = lz.i0 + (c >> 2);
-            const double wgt = ((c & 1) ? lx.t : 1.0 - lx.t) * (((c >> 1) & 1) ? ly.t : 1.0 - ly.t) *
-                               ((c >> 2) ? lz.t : 1.0 - lz.t);
-            acc += wgt * (double)y[(cz * D + cy) * D + cx];
+                for (int q = 0; q < 4; ++q) accx += cx.w[q] * (double)row[q];
+                accy += cy.w[b] * accx;
+            }
+            acc += cz.w[c] * accy;
         }
         x[id] += s * acc;
     }
@@ -1058,6 +1105,7 @@ hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, 
 }
 
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s) {
+    if (D < 4) return hipErrorInvalidValue;   // the cubic map needs 4 network points per axis
     hipLaunchKernelGGL(k_nn_apply, dim3(a.n_pairs, a.n_chunks), dim3(GM_BS), 0, s, a, D, y32);
     return hipGetLastError();
 }

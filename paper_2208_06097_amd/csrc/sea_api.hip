@@ -201,6 +201,11 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.n_zchunks = (nz_max + GC_ZC - 1) / GC_ZC;
     L.n_slots = n_pairs < ctx->n_cu * 4 ? (n_pairs > 0 ? n_pairs : 1) : ctx->n_cu * 4;
     L.nmax = nmax;
+    L.ep_stride = 1;
+    for (int k = 0; k < n_pairs; ++k) {
+        const int ns = ep_slots(pairs[k], S.dev[S.pair_cell[k]].N);
+        L.ep_stride = ns > L.ep_stride ? ns : L.ep_stride;
+    }
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -231,6 +236,7 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.dst_mu = spectral ? take(dst_mu_doubles() * sizeof(double)) : 0;
     L.rnorm = spectral ? take(np * RZ_TILES * 2 * sizeof(double)) : 0;
     L.x0 = spectral ? take(np * stride * sizeof(double)) : 0;
+    L.epart = take(np * (size_t)L.ep_stride * sizeof(double));
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
     L.csr_off = take((S.csr_off.size() + 1) * sizeof(int));
@@ -504,6 +510,8 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.x0 = Ly.x0 ? (double*)(base + Ly.x0) : nullptr;
     a.fcorr = Ly.dst_tmp ? (double*)(base + Ly.dst_tmp) : nullptr;
     a.nmax = Ly.nmax;
+    a.epart = nullptr;   // set by the sequences that take the energies from the scatter
+    a.ep_stride = Ly.ep_stride;
     return a;
 }
 
@@ -523,7 +531,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
     };
     for (int k = SEA_STAGE_GATHER; k <= SEA_STAGE_ENERGY; ++k) ctx->ev_used[k] = false;
     ctx->ev_used[SEA_STAGE_FINISH] = false;
-    ctx->ev_used[SEA_STAGE_DST] = false;
+    for (int k = SEA_STAGE_DST; k <= SEA_STAGE_FOLD; ++k) ctx->ev_used[k] = false;
     const bool zm = ctx->opts.stencil_dtype == SEA_F32 && S.cubic && cg_zm_fits(S.pairs.data(), n_pairs, nullptr) &&
                     cg_zm_lds_bytes(1) <= ctx->max_lds;
     if (!zm && ctx->opts.stencil_dtype != SEA_F64)
@@ -539,10 +547,14 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         timer_on(SEA_STAGE_BOUNDARY);
         // spectral start: x0 on the face points and -D x0 there first
         if (spectral) {
+            timer_on(SEA_STAGE_FACE);
             SEA_HIP_CHECK(ctx, launch_me_face(a, nz_max, s));
             SEA_HIP_CHECK(ctx, launch_face_corr(a, nz_max, s));
+            timer_off(SEA_STAGE_FACE);
         }
+        timer_on(SEA_STAGE_FOLD);
         SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
+        timer_off(SEA_STAGE_FOLD);
         timer_off(SEA_STAGE_BOUNDARY);
         if (a.x_nonzero) {
             timer_on(SEA_STAGE_GUESS);
@@ -578,15 +590,23 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                 // kernel forms its residual itself)
                 SEA_HIP_CHECK(ctx, launch_spectral_start(a, a.bres, (double*)(base + Ly.dst_tmp),
                                                          (double*)(base + Ly.dst_tab), (double*)(base + Ly.dst_mu), s,
-                                                         [&](bool begin) {
-                                                             if (begin) timer_on(SEA_STAGE_DST);
-                                                             else timer_off(SEA_STAGE_DST);
+                                                         [&](int pass, bool begin) {
+                                                             const int st = SEA_STAGE_DST_PLANE_FWD + pass;
+                                                             if (begin) {
+                                                                 if (pass == 0) timer_on(SEA_STAGE_DST);
+                                                                 timer_on(st);
+                                                             } else {
+                                                                 timer_off(st);
+                                                                 if (pass == 2) timer_off(SEA_STAGE_DST);
+                                                             }
                                                          }));
                 if (zm) {
                     ExxArgs ar = a;
                     ar.rnorm = (double*)(base + Ly.rnorm);
                     const bool rzm = residual_zm_lds_bytes() <= ctx->max_lds;
+                    timer_on(SEA_STAGE_RESIDUAL);
                     SEA_HIP_CHECK(ctx, rzm ? launch_residual_zm(ar, s) : launch_start_residual(ar, s));
+                    timer_off(SEA_STAGE_RESIDUAL);
                 }
             } else if (!zm) {
                 SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
@@ -603,20 +623,35 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
             az.rnorm = (az.start_res && residual_zm_lds_bytes() <= ctx->max_lds) ? (double*)(base + Ly.rnorm) : nullptr;
             SEA_HIP_CHECK(ctx, launch_cg_zm(az, var, s));
             timer_off(SEA_STAGE_CG);
-            timer_on(SEA_STAGE_FINISH);
-            SEA_HIP_CHECK(ctx, launch_cg_finish(a, s));
-            timer_off(SEA_STAGE_FINISH);
+            if (!f.action) {
+                timer_on(SEA_STAGE_FINISH);
+                SEA_HIP_CHECK(ctx, launch_cg_finish(a, s));
+                timer_off(SEA_STAGE_FINISH);
+            }
         } else {
             SEA_HIP_CHECK(ctx, launch_cg(a, s));
             timer_off(SEA_STAGE_CG);
         }
     }
     if (f.action) {
+        // z-march path: the scatter also forms the pair energies' partials,
+        // which the finish pass then sums (in slot order) with the flags
+        ExxArgs ae = a;
+        bool lists_fit = true;   // every orbital's pair list fits the scatter's energy arrays
+        for (size_t k = 0; k + 1 < S.csr_off.size(); ++k)
+            lists_fit = lists_fit && S.csr_off[k + 1] - S.csr_off[k] <= SC_EP_MAXE;
+        if (zm && n_pairs > 0 && lists_fit) ae.epart = (double*)(base + Ly.epart);
         timer_on(SEA_STAGE_SCATTER);
+        if (ae.epart) SEA_HIP_CHECK(ctx, launch_epart_clear(ae, s));
         for (size_t c = 0; c < S.cells.size(); ++c)
-            SEA_HIP_CHECK(ctx, launch_scatter(a, S.dev[c], (const int*)(base + Ly.csr_off),
+            SEA_HIP_CHECK(ctx, launch_scatter(ae, S.dev[c], (const int*)(base + Ly.csr_off),
                                               (const int2*)(base + Ly.csr_ent), s));
         timer_off(SEA_STAGE_SCATTER);
+        if (zm && n_pairs > 0) {   // without ae.epart the finish sums rho x itself
+            timer_on(SEA_STAGE_FINISH);
+            SEA_HIP_CHECK(ctx, launch_cg_finish(ae, s));
+            timer_off(SEA_STAGE_FINISH);
+        }
     }
     timer_on(SEA_STAGE_ENERGY);
     SEA_HIP_CHECK(ctx, launch_energy_sum(a, (double*)(base + Ly.scal), f.e_dev, s));

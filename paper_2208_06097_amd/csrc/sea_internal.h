@@ -65,8 +65,9 @@ struct StageTimer {
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
     size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, slots, stats, csr_off, csr_ent, scal, counter;
-    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, x0, mpoly, total;
+    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, x0, mpoly, epart, total;
     int nmax;
+    int ep_stride;        // pair-energy partial slots per pair (scatter)
     int n_chunks;
     int n_zchunks;
     int n_slots;
@@ -125,7 +126,54 @@ struct ExxArgs {
     double* rnorm;        // n_pairs x RZ_TILES x 2: |b|^2, |b - A x|^2 per row tile of the FP64 residual z-march (nullable)
     double* bres;         // n_pairs x stride: b - A x0 when x_nonzero
     int nmax;             // largest domain extent over pairs and axes
+    double* epart;        // n_pairs x ep_stride pair-energy partials of the scatter (nullable: e_ij by k_cg_finish)
+    int ep_stride;        // partial slots per pair
 };
+
+// Scatter tiles (k_scatter.hip): 64 x 4 x 8 grid points of one orbital.
+constexpr int SC_TX = 64, SC_TY = 4, SC_TZ = 8;
+// longest orbital pair list whose pair energies the scatter forms
+constexpr int SC_EP_MAXE = 256;
+
+// Pair energies from the scatter.  The workgroup of orbital i of pair
+// (i, j) writes one partial of e_ij per scatter tile the pair's domain
+// meets.  It can when i's W box holds every domain point once: a box no
+// wider than the cell (in the domain's unwrapped frame) that contains the
+// domain.  D: lo[3], n[3] of the W box.
+__host__ __device__ inline bool ep_takes(const sea_pair& P, const int* D, const int* N) {
+    for (int a = 0; a < 3; ++a)
+        if (D[3 + a] > N[a] || D[a] > P.lo[a] || P.lo[a] + P.n[a] > D[a] + D[3 + a]) return false;
+    return true;
+}
+// Along an axis the tiles that n consecutive points (cyclically) meet form a
+// run from the tile of the first point; its length is at most the number
+// of tile boundaries inside the run plus one, plus one more for the cell's
+// edge when the last tile is shorter than the others.
+__host__ __device__ inline int ep_axis_slots(int n, int T, int tiles) {
+    const int s = (T + n - 2) / T + 2;
+    return s < tiles ? s : tiles;
+}
+__host__ __device__ inline int ep_slots(const sea_pair& P, const int* N) {
+    const int T[3] = {SC_TX, SC_TY, SC_TZ};
+    int s = 1;
+    for (int a = 0; a < 3; ++a) s *= ep_axis_slots(P.n[a], T[a], (N[a] + T[a] - 1) / T[a]);
+    return s;
+}
+// slot of tile tc (per-axis tile coordinates; `tiles` per axis) in pair P's run
+__host__ __device__ inline int ep_slot(const sea_pair& P, const int* N, const int* tc, const int* tiles) {
+    const int T[3] = {SC_TX, SC_TY, SC_TZ};
+    int slot = 0;
+    for (int a = 2; a >= 0; --a) {
+        int w = P.lo[a] % N[a];
+        w += w < 0 ? N[a] : 0;
+        int r = tc[a] - w / T[a];
+        r += r < 0 ? tiles[a] : 0;
+        const int sa = ep_axis_slots(P.n[a], T[a], tiles[a]);
+        if (r >= sa) return -1;
+        slot = slot * sa + r;
+    }
+    return slot;
+}
 
 // (x, y, z) of a linear index over an nx x ny box (x fastest), advanced by a
 // fixed stride with carries instead of integer divisions.
@@ -194,9 +242,10 @@ hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s);
 // arrays' size; r scratch of the same size).
 size_t dst_table_doubles();
 size_t dst_mu_doubles();
-// `mark(true)` / `mark(false)` bracket the three transform passes (stage timing).
+// `mark(pass, true)` / `mark(pass, false)` bracket each of the three
+// transform passes (0 forward planes, 1 z lines, 2 inverse planes; stage timing).
 hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, hipStream_t s,
-                                 const std::function<void(bool)>& mark);
+                                 const std::function<void(int, bool)>& mark);
 // the pairs the sine transform takes
 __host__ __device__ inline bool spectral_pair(const sea_pair& P) { return P.n[0] <= 64 && P.n[1] <= 64 && P.n[2] <= 64; }
 // points next to a face that the difference of the zero and the odd
@@ -216,6 +265,8 @@ hipError_t launch_cg_zm(const ExxArgs& a, int variant, hipStream_t s);
 hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s);
 hipError_t launch_scatter(const ExxArgs& a, const DevCell& cell, const int* csr_off, const int2* csr_ent,
                           hipStream_t s);
+// zeroes a.epart (every slot the scatter does not write must read zero)
+hipError_t launch_epart_clear(const ExxArgs& a, hipStream_t s);
 hipError_t launch_energy_sum(const ExxArgs& a, double* out_scalars, double* e_dev, hipStream_t s);
 
 // Host evaluation of the solid-harmonic recurrence (orthonormal real form).

@@ -94,7 +94,8 @@ class SeaCell(C.Structure):
 
 
 STAGES = ["gather", "boundary", "guess", "cg", "scatter", "energy", "ace_m", "ace_chol", "ace_xi",
-          "ace_apply", "finish", "scdm", "rotate", "dst"]
+          "ace_apply", "finish", "scdm", "rotate", "dst", "dst_plane_fwd", "dst_zline", "dst_plane_inv",
+          "residual", "face", "fold"]
 
 
 class SeaError(RuntimeError):

@@ -298,7 +298,10 @@ def test_c2_full_against_golden():
     ks = np.sort(np.random.default_rng(11).choice(len(pairs), size=8, replace=False))
     v, _, _, s2, st = ctx.pair_solve(phi, cell.N, cell.L, pairs[ks])
     assert st == sea.SEA_OK
-    assert np.array_equal(s2["e_ij"], stats["e_ij"][ks]) and np.array_equal(s2["rel_res"], stats["rel_res"][ks])
+    # the same solves; e_ij summed in another order (here over the domain, in
+    # the action from the scatter's per-tile partials)
+    assert np.array_equal(s2["rel_res"], stats["rel_res"][ks])
+    assert np.allclose(s2["e_ij"], stats["e_ij"][ks], rtol=1e-12, atol=0.0)
     v = v.cpu().numpy()
     sub = opairs.subset(ks)
     for q, k in enumerate(ks):
