@@ -296,6 +296,12 @@ def main():
     tune = pick_variant(ctx, form, [(phi, cell.N, cell.L, pairs)], ws)
     if tune and tune["ms"]:
         log(f"autotune: {tune['variant']}  " + "  ".join(f"{k} {v:.1f} ms" for k, v in tune["ms"].items()))
+    dst_tune = None
+    if FORMS[form]["start"] == "spectral":
+        # the sine-transform passes' variants (workgroups per pair, tile staging)
+        dst_tune = ctx.spectral_autotune([(phi, cell.N, cell.L, pairs)], sample_pairs=args.tune_pairs, ws=ws)
+        log(f"spectral autotune: {dst_tune['plane']} {dst_tune['zline']}  " +
+            "  ".join(f"{k} {v:.2f} ms" for k, v in dst_tune["ms"].items()))
 
     psi_step = psi.float()
 
@@ -547,6 +553,8 @@ def main():
                    "form": form, "rel_tol": args.tol, "n_pairs": n_pairs,
                    "cg_variant": tune["variant"] if tune else "k_cg_f64 (generic FP64)",
                    "autotune_ms": tune["ms"] if tune else None,
+                   "spectral_variants": {"plane": dst_tune["plane"], "zline": dst_tune["zline"],
+                                         "tune_ms": dst_tune["ms"]} if dst_tune else None,
                    "cg_iters_total": int(stats["iters"].sum())},
         "forms": forms,
         "ace_precision": ace,

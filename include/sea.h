@@ -275,6 +275,30 @@ const char *sea_cg_variant_name(int variant);
 sea_status sea_exx_autotune(sea_ctx *ctx, int n_cells, const sea_cell *cells, void *ws_dev, size_t ws_bytes,
                             int sample_pairs, int iters, float *ms_host, int *best);
 
+/* Kernel variants of the spectral start's sine-transform passes (one plane
+ * kernel and one z-line kernel per call): workgroups per pair and how a
+ * tile is staged; every variant computes the same sums in the same order,
+ * so results do not depend on the choice.  Indices 0 .. count-1: the plane
+ * variants first, then the z-line ones (a name starting "plane-" or
+ * "zline-"); NULL out of range. */
+int sea_spectral_variant_count(void);
+const char *sea_spectral_variant_name(int variant);
+/* Fixes the variants a context uses (plane: index among the plane
+ * variants, zline: index among the z-line variants; -1: the autotuner's
+ * choice, else the first).  SEA_E_ARG out of range. */
+sea_status sea_set_spectral_variants(sea_ctx *ctx, int plane, int zline);
+/* Autotuner of the transform passes (the timed form's schedule choice):
+ * on a strided sample of `sample_pairs` pairs of these cells, times the
+ * forward plane pass of every plane variant and the z-line pass of every
+ * z-line variant with HIP events (the second of two launches), and keeps
+ * the fastest of each as the context's choice.  ms_host
+ * (sea_spectral_variant_count() floats, nullable) receives the times;
+ * *best_plane, *best_zline (nullable) the chosen indices.  The workspace
+ * must hold sea_exx_batched_workspace_bytes of the same cells for a context
+ * with the spectral start.  Synchronizes. */
+sea_status sea_spectral_autotune(sea_ctx *ctx, int n_cells, const sea_cell *cells, void *ws_dev, size_t ws_bytes,
+                                 int sample_pairs, float *ms_host, int *best_plane, int *best_zline);
+
 /* A plan fixes the cells, pair tables and workspace once (tables are
  * uploaded at creation) and records the whole kernel sequence of the batched
  * action into a HIP graph; sea_exx_plan_launch replays it on `hip_stream`

@@ -129,11 +129,16 @@ __device__ __forceinline__ void dst_ops(const double* opt, int n, int b, int lan
 // contiguous), written in the plane's layout (the same kernel serves the
 // forward and the inverse transform: S is its own inverse).  With `add`,
 // the input is in + add on the points within 5 of a face (in elsewhere).  Grid
-// (pairs, DP_PG): workgroup y takes planes y, y + DP_PG, ...  The LDS array
+// (pairs, PG): workgroup y takes planes y, y + PG, ...  The LDS array
 // holds X[y][x], then T transposed (T^T[c][y], c = 32 parity + i for the
 // x mode 2 i + parity), then Y[j][x].  Wave w: output block w % 2 of the
 // transform, row (then column) blocks 2 (w / 2) and 2 (w / 2) + 1.
-__global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
+// Variants (the autotuner picks PG; SQ is chosen from the pairs): PG
+// workgroups per pair; SQ: every plane the call transforms is square
+// (nx = ny), so one operand set serves both axes (32 fewer registers, four
+// workgroups per CU instead of three).
+template <int PG, bool SQ>
+__global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
     __shared__ double B[DS_N * DP_LD];
     const int pid = blockIdx.x;
     const sea_pair P = d.pairs[pid];
@@ -143,9 +148,12 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int hb = w & 1, bp = 2 * (w >> 1);
-    double ex[8], ox[8], ey[8], oy[8];
+    double ex[8], ox[8];
     dst_ops(d.opt, nx, hb, lane, ex, ox);
-    dst_ops(d.opt, ny, hb, lane, ey, oy);
+    double eyb[SQ ? 1 : 8], oyb[SQ ? 1 : 8];
+    if constexpr (!SQ) dst_ops(d.opt, ny, hb, lane, eyb, oyb);
+    const double* ey = SQ ? ex : eyb;
+    const double* oy = SQ ? ox : oyb;
     // entries outside the ny x nx corner only ever meet zero table entries;
     // they start finite and stay finite
     for (int t = threadIdx.x; t < DS_N * DP_LD; t += DP_BS) B[t] = 0.0;
@@ -170,7 +178,7 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
     const double* in = d.in + (size_t)pid * d.stride;
     double* out = d.out + (size_t)pid * d.stride;
     const double* add = d.add ? d.add + (size_t)pid * d.stride : nullptr;
-    for (int z = blockIdx.y; z < nz; z += DP_PG) {
+    for (int z = blockIdx.y; z < nz; z += PG) {
         const size_t zo = (size_t)z * npl;
         int gk = g;
         asm volatile("" : "+v"(gk));   // recompute the fold addresses per plane rather than keep them all live
@@ -251,11 +259,15 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_plane(DstArgs d) {
 
 // Along z for each column (y, x): forward transform, division by the
 // eigenvalue of the mode, inverse transform; same layout in and out.  Grid
-// (pairs, DP_PG): workgroup y takes 64-column tiles y, y + DP_PG, ...  The
+// (pairs, PG): workgroup y takes 64-column tiles y, y + PG, ...  The
 // LDS array holds the tile transposed (column-major: U[c][z]), so that the
 // transform along z reads rows.  Wave w: z modes of block w % 2, columns of
 // blocks 2 (w / 2) and 2 (w / 2) + 1.
-__global__ __launch_bounds__(DP_BS, 3) void k_dst_zline(DstArgs d) {
+// Variants: PG workgroups per pair; LB: tile values loaded per batch into
+// registers before they go to LDS (16: all at once, 8: two batches, fewer
+// registers).
+template <int PG, int LB>
+__global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
     __shared__ double U[DS_TC * DP_LD];
     __shared__ double lxy[DS_TC];   // x and y parts of the eigenvalue of each tile column
     const int pid = blockIdx.x;
@@ -278,19 +290,30 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_zline(DstArgs d) {
     double* out = d.out + (size_t)pid * d.stride;
     // load element u of a thread: row a = threadIdx.x / 64 + 4 u, column threadIdx.x % 64
     const int lc = threadIdx.x % DS_TC, la = threadIdx.x / DS_TC;
-    for (int c0 = blockIdx.y * DS_TC; c0 < ncol; c0 += DP_PG * DS_TC) {
+    for (int c0 = blockIdx.y * DS_TC; c0 < ncol; c0 += PG * DS_TC) {
         int gk = g;
         asm volatile("" : "+v"(gk));   // recompute the fold addresses per tile rather than keep them all live
-        double val[DP_PT];
         const bool cl = c0 + lc < ncol;
+        static_assert(DP_PT % LB == 0, "load batches");
+        // the first batch's loads are in flight while the workgroup finishes
+        // the previous tile (the barrier), the others go straight to LDS
+        // 32-bit element offsets walked per tile (not precomputed per load and
+        // held across tiles)
+        int off = la * ncol + c0 + lc;
+        asm volatile("" : "+v"(off));
 #pragma unroll
-        for (int u = 0; u < DP_PT; ++u) {
-            const int a = la + 4 * u;
-            val[u] = (cl && a < nz) ? in[(size_t)a * ncol + c0 + lc] : 0.0;
+        for (int u0 = 0; u0 < DP_PT; u0 += LB) {
+            double val[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int a = la + 4 * (u0 + u);
+                val[u] = (cl && a < nz) ? in[off] : 0.0;
+                off += 4 * ncol;
+            }
+            if (u0 == 0) __syncthreads();
+#pragma unroll
+            for (int u = 0; u < LB; ++u) U[lc * DP_LD + la + 4 * (u0 + u)] = val[u];
         }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < DP_PT; ++u) U[lc * DP_LD + la + 4 * u] = val[u];
         if (threadIdx.x < DS_TC) {
             const int col = c0 + threadIdx.x;
             double l = 0.0;
@@ -325,7 +348,7 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_zline(DstArgs d) {
         __syncthreads();
         // divide by the eigenvalue: wave w takes columns w + 4 u, lane the mode j
         if (lane < nz) {
-#pragma unroll
+#pragma unroll 2
             for (int u = 0; u < DS_TC / 4; ++u) {
                 const int cc = w + 4 * u;
                 if (c0 + cc < ncol) U[cc * DP_LD + lane] /= lxy[cc] + lzj;
@@ -353,7 +376,7 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_zline(DstArgs d) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int j = 2 * (16 * hb + g + 4 * v) + par;
-                    if (j < nz) out[(size_t)j * ncol + col] = acc[a][par][v];
+                    if (j < nz) out[j * ncol + col] = acc[a][par][v];   // 32-bit offsets (< 64^3)
                 }
         }
     }
@@ -364,14 +387,44 @@ __global__ __launch_bounds__(DP_BS, 3) void k_dst_zline(DstArgs d) {
 size_t dst_table_doubles() { return (size_t)DS_N * DS_OPN; }
 size_t dst_mu_doubles() { return (size_t)mu_off(DS_N + 1); }
 
-// x = S^-1 ((S (b + fcorr)) ./ lambda) for every pair whose axes are all <=
-// 64 (fcorr added on the face points; it lives in tmp, scratch of the pair
-// arrays' size, which the passes then overwrite); r is scratch of the same
-// size.
-hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, hipStream_t s,
-                                 const std::function<void(int, bool)>& mark) {
-    if (a.n_pairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dst_tables, dim3(DS_N), dim3(DS_BS), 0, s, tab, mu);
+// Compiled variants of the two transform kernels, the autotuner's choices.
+namespace {
+using DstKernel = void (*)(DstArgs);
+struct PlaneVariant {
+    const char* name;
+    DstKernel gen, sq;   // general planes / every plane square
+    int pg;
+};
+struct ZlineVariant {
+    const char* name;
+    DstKernel fn;
+    int pg;
+};
+const PlaneVariant kPlaneVariants[] = {
+    {"plane-pg16", k_dst_plane<16, false>, k_dst_plane<16, true>, 16},
+    {"plane-pg8", k_dst_plane<8, false>, k_dst_plane<8, true>, 8},
+    {"plane-pg32", k_dst_plane<32, false>, k_dst_plane<32, true>, 32},
+};
+const ZlineVariant kZlineVariants[] = {
+    {"zline-pg16-lb16", k_dst_zline<16, 16>, 16},
+    {"zline-pg16-lb8", k_dst_zline<16, 8>, 16},
+    {"zline-pg32-lb16", k_dst_zline<32, 16>, 32},
+    {"zline-pg8-lb16", k_dst_zline<8, 16>, 8},
+};
+constexpr int kNumPlane = sizeof(kPlaneVariants) / sizeof(kPlaneVariants[0]);
+constexpr int kNumZline = sizeof(kZlineVariants) / sizeof(kZlineVariants[0]);
+}  // namespace
+
+int dst_variant_count() { return kNumPlane + kNumZline; }
+int dst_plane_variant_count() { return kNumPlane; }
+const char* dst_variant_name(int v) {
+    if (v >= 0 && v < kNumPlane) return kPlaneVariants[v].name;
+    if (v >= kNumPlane && v < kNumPlane + kNumZline) return kZlineVariants[v - kNumPlane].name;
+    return nullptr;
+}
+
+namespace {
+DstArgs dst_args(const ExxArgs& a, double* tab, double* mu) {
     DstArgs d{};
     d.pairs = a.pairs;
     d.cells = a.cells;
@@ -379,25 +432,65 @@ hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, doubl
     d.stride = a.stride;
     d.opt = tab;
     d.mu = mu;
-    const dim3 grid((unsigned)a.n_pairs, DP_PG);
+    return d;
+}
+void launch_plane(const DstArgs& d, int n_pairs, int pv, bool square, hipStream_t s) {
+    const PlaneVariant& V = kPlaneVariants[pv];
+    hipLaunchKernelGGL(square ? V.sq : V.gen, dim3((unsigned)n_pairs, V.pg), dim3(DP_BS), 0, s, d);
+}
+void launch_zline(const DstArgs& d, int n_pairs, int zv, hipStream_t s) {
+    const ZlineVariant& V = kZlineVariants[zv];
+    hipLaunchKernelGGL(V.fn, dim3((unsigned)n_pairs, V.pg), dim3(DP_BS), 0, s, d);
+}
+}  // namespace
+
+hipError_t launch_dst_tables(double* tab, double* mu, hipStream_t s) {
+    hipLaunchKernelGGL(k_dst_tables, dim3(DS_N), dim3(DS_BS), 0, s, tab, mu);
+    return hipGetLastError();
+}
+
+// One transform pass of a variant on every pair (autotuner): pass 0 forward
+// planes (in -> out, no face correction), 1 z lines, 2 inverse planes.
+hipError_t launch_dst_pass(const ExxArgs& a, int pass, int variant, bool square, const double* in, double* out,
+                           double* tab, double* mu, hipStream_t s) {
+    if (a.n_pairs <= 0) return hipSuccess;
+    DstArgs d = dst_args(a, tab, mu);
+    d.in = in;
+    d.out = out;
+    if (pass == 1) launch_zline(d, a.n_pairs, variant, s);
+    else launch_plane(d, a.n_pairs, variant, square, s);
+    return hipGetLastError();
+}
+
+// x = S^-1 ((S (b + fcorr)) ./ lambda) for every pair whose axes are all <=
+// 64 (fcorr added on the face points; it lives in tmp, scratch of the pair
+// arrays' size, which the passes then overwrite); r is scratch of the same
+// size.  pv, zv: plane and z-line variants; square: every pair the
+// transform takes has nx = ny.
+hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, int pv, int zv,
+                                 bool square, hipStream_t s, const std::function<void(int, bool)>& mark) {
+    if (a.n_pairs <= 0) return hipSuccess;
+    if (pv < 0 || pv >= kNumPlane || zv < 0 || zv >= kNumZline) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dst_tables, dim3(DS_N), dim3(DS_BS), 0, s, tab, mu);
+    DstArgs d = dst_args(a, tab, mu);
     // planes forward: b + fcorr (in tmp) -> tmp; z lines forward, divided,
     // inverse: tmp -> r; planes inverse: r -> x
     d.in = a.b;
     d.add = tmp;
     d.out = tmp;
     mark(0, true);
-    hipLaunchKernelGGL(k_dst_plane, grid, dim3(DP_BS), 0, s, d);
+    launch_plane(d, a.n_pairs, pv, square, s);
     mark(0, false);
     d.add = nullptr;
     d.in = tmp;
     d.out = r;
     mark(1, true);
-    hipLaunchKernelGGL(k_dst_zline, grid, dim3(DP_BS), 0, s, d);
+    launch_zline(d, a.n_pairs, zv, s);
     mark(1, false);
     d.in = r;
     d.out = a.v;
     mark(2, true);
-    hipLaunchKernelGGL(k_dst_plane, grid, dim3(DP_BS), 0, s, d);
+    launch_plane(d, a.n_pairs, pv, square, s);
     mark(2, false);
     return hipGetLastError();
 }

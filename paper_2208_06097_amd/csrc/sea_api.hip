@@ -102,7 +102,18 @@ struct CellSet {
     std::vector<int> order;  // CG queue: pair ids by decreasing interior size (ties: id order)
     std::vector<int> dbox;   // 12 per pair: W_i box, W_j box (default: the pair's domain twice)
     bool cubic = true;
+    bool square = true;      // every pair the sine transform takes has n[0] = n[1]
 };
+
+// the sine-transform kernel variants a call uses: the fixed ones, else the
+// autotuner's, else the first
+static void dst_variants(const sea_ctx* ctx, int& pv, int& zv) {
+    const int np = dst_plane_variant_count(), nzv = dst_variant_count() - np;
+    pv = ctx->dst_plane_fixed >= 0 ? ctx->dst_plane_fixed : (ctx->dst_plane_tuned >= 0 ? ctx->dst_plane_tuned : 0);
+    zv = ctx->dst_zline_fixed >= 0 ? ctx->dst_zline_fixed : (ctx->dst_zline_tuned >= 0 ? ctx->dst_zline_tuned : 0);
+    if (pv >= np) pv = 0;
+    if (zv >= nzv) zv = 0;
+}
 
 static sea_status build_cellset(sea_ctx* ctx, int n_cells, const sea_cell* cells, bool action, CellSet& S) {
     if (n_cells < 1 || !cells) return fail(ctx, SEA_E_ARG, "need n_cells >= 1 and a cell array");
@@ -173,6 +184,8 @@ static sea_status build_cellset(sea_ctx* ctx, int n_cells, const sea_cell* cells
         S.dev.push_back(D);
     }
     if ((long long)S.pairs.size() > (1LL << 30)) return fail(ctx, SEA_E_ARG, "too many pairs");
+    for (const auto& p : S.pairs)
+        if (spectral_pair(p) && p.n[0] != p.n[1]) S.square = false;
     // longest-processing-time-first queue for the persistent CG kernels
     S.order.resize(S.pairs.size());
     for (size_t k = 0; k < S.pairs.size(); ++k) S.order[k] = (int)k;
@@ -588,8 +601,11 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                 // residual b - A x in FP64: its norms for every pair, and bres
                 // for the pairs whose start is not yet converged (the FP64
                 // kernel forms its residual itself)
+                int pv = 0, zv = 0;
+                dst_variants(ctx, pv, zv);
                 SEA_HIP_CHECK(ctx, launch_spectral_start(a, a.bres, (double*)(base + Ly.dst_tmp),
-                                                         (double*)(base + Ly.dst_tab), (double*)(base + Ly.dst_mu), s,
+                                                         (double*)(base + Ly.dst_tab), (double*)(base + Ly.dst_mu), pv,
+                                                         zv, S.square, s,
                                                          [&](int pass, bool begin) {
                                                              const int st = SEA_STAGE_DST_PLANE_FWD + pass;
                                                              if (begin) {
@@ -1476,6 +1492,110 @@ extern "C" sea_status sea_build_pairs_eps(sea_ctx* ctx, const sea_grid* grid, in
 
 extern "C" int sea_cg_variant_count(void) { return cg_variant_count(); }
 extern "C" const char* sea_cg_variant_name(int v) { return cg_variant_name(v); }
+
+extern "C" int sea_spectral_variant_count(void) { return dst_variant_count(); }
+
+extern "C" const char* sea_spectral_variant_name(int v) { return dst_variant_name(v); }
+
+extern "C" sea_status sea_set_spectral_variants(sea_ctx* ctx, int plane, int zline) {
+    if (!ctx) return SEA_E_ARG;
+    const int np = dst_plane_variant_count(), nzv = dst_variant_count() - np;
+    if (plane < -1 || plane >= np || zline < -1 || zline >= nzv)
+        return fail(ctx, SEA_E_ARG, "spectral variants out of range (plane %d of %d, z line %d of %d)", plane, np,
+                    zline, nzv);
+    ctx->dst_plane_fixed = plane;
+    ctx->dst_zline_fixed = zline;
+    return SEA_OK;
+}
+
+// Strided sample of `sample_pairs` pairs of the cells, kept per cell (the
+// autotuners time their kernels on it).
+static void sample_cells(int n_cells, const sea_cell* cells, int sample_pairs, std::vector<std::vector<sea_pair>>& keep,
+                         std::vector<sea_cell>& sc) {
+    long total = 0;
+    for (int c = 0; c < n_cells; ++c) total += cells[c].n_pairs > 0 ? cells[c].n_pairs : 0;
+    const long step = total > sample_pairs ? (total + sample_pairs - 1) / sample_pairs : 1;
+    keep.assign(n_cells, {});
+    sc.assign(cells, cells + n_cells);
+    long g = 0;
+    for (int c = 0; c < n_cells; ++c) {
+        for (int k = 0; k < cells[c].n_pairs; ++k, ++g)
+            if (g % step == 0 && cells[c].pairs_host) keep[c].push_back(cells[c].pairs_host[k]);
+        sc[c].n_pairs = (int)keep[c].size();
+        sc[c].pairs_host = keep[c].data();
+    }
+}
+
+extern "C" sea_status sea_spectral_autotune(sea_ctx* ctx, int n_cells, const sea_cell* cells, void* ws_dev,
+                                            size_t ws_bytes, int sample_pairs, float* ms_host, int* best_plane,
+                                            int* best_zline) {
+    if (!ctx) return SEA_E_ARG;
+    if (!ws_dev) return fail(ctx, SEA_E_ARG, "workspace is NULL");
+    if (sample_pairs < 1) return fail(ctx, SEA_E_ARG, "need sample_pairs >= 1");
+    if (n_cells < 1 || !cells) return fail(ctx, SEA_E_ARG, "need n_cells >= 1 and a cell array");
+    std::vector<std::vector<sea_pair>> keep;
+    std::vector<sea_cell> sc;
+    sample_cells(n_cells, cells, sample_pairs, keep, sc);
+    CellSet S;
+    sea_status st = build_cellset(ctx, n_cells, sc.data(), false, S);
+    if (st != SEA_OK) return st;
+    if (S.pairs.empty()) return fail(ctx, SEA_E_ARG, "no pairs to tune on");
+    const sea_opts saved = ctx->opts;
+    ctx->opts.start = SEA_START_SPECTRAL;   // the layout with the transform's arrays
+    const ExxLayout Ly = exx_layout(ctx, S, true);
+    ctx->opts = saved;
+    if (ws_bytes < Ly.total) return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, Ly.total);
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    char* base = (char*)ws_dev;
+    st = exx_upload(ctx, S, Ly, base, s);
+    if (st != SEA_OK) return st;
+    const ExxArgs a = exx_args(ctx, S, Ly, base, nullptr);
+    double* tab = (double*)(base + Ly.dst_tab);
+    double* mu = (double*)(base + Ly.dst_mu);
+    double* tmp = (double*)(base + Ly.dst_tmp);
+    SEA_HIP_CHECK(ctx, launch_gather_moments(a, s));   // b of the sampled pairs: the passes' input
+    SEA_HIP_CHECK(ctx, launch_dst_tables(tab, mu, s));
+    hipEvent_t e0, e1;
+    SEA_HIP_CHECK(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, SEA_E_HIP, "event creation failed");
+    }
+    const int np = dst_plane_variant_count(), nv = dst_variant_count();
+    int bp = 0, bz = 0;
+    float tp = 0.0f, tz = 0.0f;
+    hipError_t err = hipSuccess;
+    for (int v = 0; v < nv && err == hipSuccess; ++v) {
+        const bool plane = v < np;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {   // rep 0 warms the code object
+            err = hipEventRecord(e0, s);
+            if (err == hipSuccess)
+                err = plane ? launch_dst_pass(a, 0, v, S.square, a.b, tmp, tab, mu, s)
+                            : launch_dst_pass(a, 1, v - np, S.square, tmp, a.bres, tab, mu, s);
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (ms_host) ms_host[v] = ms;
+        if (plane && (v == 0 || ms < tp)) {
+            tp = ms;
+            bp = v;
+        }
+        if (!plane && (v == np || ms < tz)) {
+            tz = ms;
+            bz = v - np;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(ctx, SEA_E_HIP, "spectral autotune: %s", hipGetErrorString(err));
+    ctx->dst_plane_tuned = bp;
+    ctx->dst_zline_tuned = bz;
+    if (best_plane) *best_plane = bp;
+    if (best_zline) *best_zline = bz;
+    return SEA_OK;
+}
 
 extern "C" sea_status sea_exx_autotune(sea_ctx* ctx, int n_cells, const sea_cell* cells, void* ws_dev,
                                        size_t ws_bytes, int sample_pairs, int iters, float* ms_host, int* best) {

@@ -39,6 +39,10 @@ struct sea_ctx {
     const void* nn_state = nullptr;   // attached network (learned start)
     int cg_tuned = -1;                // z-march variant chosen by sea_exx_autotune
     void* noalloc_scratch = nullptr;  // device address of this device's static scratch array
+    // sine-transform kernel variants (spectral start): the autotuner's choice
+    // and a fixed choice (-1: none; the fixed one wins)
+    int dst_plane_tuned = -1, dst_zline_tuned = -1;
+    int dst_plane_fixed = -1, dst_zline_fixed = -1;
 };
 
 // Looks up, once per device, the device address of the static scratch array
@@ -226,7 +230,6 @@ hipError_t launch_me_face(const ExxArgs& a, int nz_max, hipStream_t s);
 // -D x0 into a.fcorr on the face points
 hipError_t launch_face_corr(const ExxArgs& a, int nz_max, hipStream_t s);
 constexpr double kPi = 3.14159265358979323846;
-constexpr int DP_PG = 16;   // sine-transform workgroups per pair
 hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s);
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s);
 hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
@@ -242,10 +245,22 @@ hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s);
 // arrays' size; r scratch of the same size).
 size_t dst_table_doubles();
 size_t dst_mu_doubles();
-// `mark(pass, true)` / `mark(pass, false)` bracket each of the three
-// transform passes (0 forward planes, 1 z lines, 2 inverse planes; stage timing).
-hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, hipStream_t s,
-                                 const std::function<void(int, bool)>& mark);
+// pv, zv: variants of the plane and z-line kernels (0 <= pv <
+// dst_plane_variant_count(), 0 <= zv < dst_variant_count() - that); square:
+// every pair the transform takes has nx = ny.  `mark(pass, true)` /
+// `mark(pass, false)` bracket each of the three transform passes (0 forward
+// planes, 1 z lines, 2 inverse planes; stage timing).
+hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, int pv, int zv,
+                                 bool square, hipStream_t s, const std::function<void(int, bool)>& mark);
+// transform-kernel variants: plane variants first, then the z-line ones
+int dst_variant_count();
+int dst_plane_variant_count();
+const char* dst_variant_name(int v);
+hipError_t launch_dst_tables(double* tab, double* mu, hipStream_t s);
+// one pass (0 forward planes, 1 z lines, 2 inverse planes) of a variant on
+// every pair, in -> out (autotuner)
+hipError_t launch_dst_pass(const ExxArgs& a, int pass, int variant, bool square, const double* in, double* out,
+                           double* tab, double* mu, hipStream_t s);
 // the pairs the sine transform takes
 __host__ __device__ inline bool spectral_pair(const sea_pair& P) { return P.n[0] <= 64 && P.n[1] <= 64 && P.n[2] <= 64; }
 // points next to a face that the difference of the zero and the odd

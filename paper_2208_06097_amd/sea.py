@@ -34,7 +34,8 @@ EXPORTS = [
     "sea_cg_variant_count", "sea_cg_variant_name", "sea_exx_autotune",
     "sea_nn_infer_workspace_bytes", "sea_nn_infer", "sea_eps_workspace_bytes", "sea_build_pairs_eps",
     "sea_successive_idempotency", "sea_scdm_workspace_bytes", "sea_scdm", "sea_rotate",
-    "sea_ace_apply_noalloc",
+    "sea_ace_apply_noalloc", "sea_spectral_variant_count", "sea_spectral_variant_name",
+    "sea_set_spectral_variants", "sea_spectral_autotune",
 ]
 
 # size of the library's static scratch array per GPU (SEA_NOALLOC_SCRATCH_BYTES
@@ -155,6 +156,12 @@ def load() -> C.CDLL:
     lib.sea_cg_variant_name.argtypes = [i]
     lib.sea_cg_variant_name.restype = C.c_char_p
     lib.sea_exx_autotune.argtypes = [vp, i, vp, vp, sz, i, i, vp, P(i)]
+    lib.sea_spectral_variant_count.argtypes = []
+    lib.sea_spectral_variant_count.restype = i
+    lib.sea_spectral_variant_name.argtypes = [i]
+    lib.sea_spectral_variant_name.restype = C.c_char_p
+    lib.sea_set_spectral_variants.argtypes = [vp, i, i]
+    lib.sea_spectral_autotune.argtypes = [vp, i, vp, vp, sz, i, vp, P(i), P(i)]
     lib.sea_nn_infer_workspace_bytes.argtypes = [vp, i, P(sz)]
     lib.sea_nn_infer.argtypes = [vp, vp, i, vp, vp, vp, sz]
     lib.sea_eps_workspace_bytes.argtypes = [vp, P(SeaGrid), i, P(sz)]
@@ -399,6 +406,60 @@ class Context:
         out = {"variant": names[best.value], "ms": {n: float(t) for n, t in zip(names, ms)}, "cached": False}
         if cache:
             store[key] = {"variant": out["variant"], "ms": out["ms"]}
+            with open(cache, "w") as f:
+                json.dump(store, f, indent=1)
+        return out
+
+    def spectral_variants(self):
+        """(plane variant names, z-line variant names) of the sine-transform passes."""
+        n = self.lib.sea_spectral_variant_count()
+        names = [self.lib.sea_spectral_variant_name(v).decode() for v in range(n)]
+        return [x for x in names if x.startswith("plane-")], [x for x in names if x.startswith("zline-")]
+
+    def set_spectral_variants(self, plane=-1, zline=-1):
+        """Fix the transform variants (index or name; -1: the tuned choice)."""
+        pn, zn = self.spectral_variants()
+        plane = pn.index(plane) if isinstance(plane, str) else plane
+        zline = zn.index(zline) if isinstance(zline, str) else zline
+        self._check(self.lib.sea_set_spectral_variants(self.h, int(plane), int(zline)))
+
+    def spectral_autotune(self, cells, sample_pairs=512, ws=None, cache=None):
+        """Pick the sine-transform kernel variants of the spectral start for
+        this workload (fastest plane pass and z-line pass on a strided
+        sample of the pairs).  With ``cache`` (a JSON path) a stored choice
+        for the same device, variant set and domain shapes is reused.
+        Returns {"plane": name, "zline": name, "ms": {name: ms} or None, "cached": bool}."""
+        import json
+        torch = self._torch
+        pn, zn = self.spectral_variants()
+        shapes = sorted({tuple(int(v) for v in n) for c in cells for n in np.asarray(c[3]["n"]).reshape(-1, 3)})
+        key = "|".join([torch.cuda.get_device_name(), ",".join(pn + zn), f"sample={sample_pairs}",
+                        ";".join("x".join(map(str, t)) for t in shapes[:8])])
+        store = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                store = json.load(f)
+            hit = store.get(key)
+            if hit and hit.get("plane") in pn and hit.get("zline") in zn:
+                self.set_spectral_variants(hit["plane"], hit["zline"])
+                return {"plane": hit["plane"], "zline": hit["zline"], "ms": hit.get("ms"), "cached": True}
+        saved = self.opts.start
+        arr, _, keep = self._cells(cells, need_W=False)
+        if ws is None:
+            self.set_opts(start=SEA_START_SPECTRAL)
+            try:
+                ws = self.workspace(self.exx_batched_workspace_bytes(cells))
+            finally:
+                self.set_opts(start=saved)
+        ms = np.zeros(len(pn) + len(zn), dtype=np.float32)
+        bp, bz = C.c_int(-1), C.c_int(-1)
+        self._check(self.lib.sea_spectral_autotune(self.h, len(cells), arr, ws.data_ptr(), ws.numel(), sample_pairs,
+                                                   ms.ctypes.data, C.byref(bp), C.byref(bz)))
+        self.set_spectral_variants(-1, -1)
+        out = {"plane": pn[bp.value], "zline": zn[bz.value],
+               "ms": {n: float(t) for n, t in zip(pn + zn, ms)}, "cached": False}
+        if cache:
+            store[key] = {"plane": out["plane"], "zline": out["zline"], "ms": out["ms"]}
             with open(cache, "w") as f:
                 json.dump(store, f, indent=1)
         return out

@@ -312,3 +312,51 @@ def test_c2_full_against_golden():
         assert want <= tol
         assert abs(s2["rel_res"][q] - want) <= 1e-4 * want + 2e-13   # FP64 rounding floor of b - A x
     ctx.close()
+
+
+def test_spectral_variants_give_identical_results():
+    """Every compiled variant of the two transform kernels (workgroups per
+    pair, tile staging) computes the same sums in the same order: W, E and
+    every pair's statistics equal the default variants' bit for bit (the
+    8-molecule cell, square 63^3 domains, FP32 state)."""
+    cell = synth.config1()
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, 6.0)
+    phi = torch.from_numpy(cell.phi).cuda()
+    ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F32, start=sea.SEA_START_SPECTRAL)
+    pn, zn = ctx.spectral_variants()
+    assert len(pn) >= 2 and len(zn) >= 2
+    ctx.set_spectral_variants(0, 0)
+    W0, E0, s0, st = ctx.exx_action(phi, cell.N, cell.L, pairs)
+    W0 = W0.clone()
+    assert st == sea.SEA_OK
+    combos = [(p, 0) for p in range(1, len(pn))] + [(0, z) for z in range(1, len(zn))]
+    for p, z in combos:
+        print(f"case spectral variants {pn[p]} {zn[z]}", flush=True)
+        ctx.set_spectral_variants(p, z)
+        W, E, s1, st = ctx.exx_action(phi, cell.N, cell.L, pairs)
+        assert st == sea.SEA_OK and E == E0
+        assert torch.equal(W, W0)
+        assert np.array_equal(s1, s0)
+    ctx.close()
+
+
+def test_spectral_autotune_picks_the_fastest_and_caches(tmp_path):
+    """The transform autotuner keeps, per kernel, the variant with the least
+    measured time, and a cached choice is reused without timing."""
+    cell = synth.config1()
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, 6.0)
+    phi = torch.from_numpy(cell.phi).cuda()
+    ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F32, start=sea.SEA_START_SPECTRAL)
+    pn, zn = ctx.spectral_variants()
+    cache = str(tmp_path / "tune.json")
+    print("case spectral autotune", flush=True)
+    r = ctx.spectral_autotune([(phi, cell.N, cell.L, pairs)], sample_pairs=128, cache=cache)
+    assert not r["cached"]
+    assert all(r["ms"][n] > 0 for n in pn + zn)
+    assert r["plane"] == min(pn, key=lambda n: r["ms"][n])
+    assert r["zline"] == min(zn, key=lambda n: r["ms"][n])
+    W, E, stats, st = ctx.exx_action(phi, cell.N, cell.L, pairs)
+    assert st == sea.SEA_OK and np.all(stats["converged"] == 1)
+    r2 = ctx.spectral_autotune([(phi, cell.N, cell.L, pairs)], sample_pairs=128, cache=cache)
+    assert r2["cached"] and (r2["plane"], r2["zline"]) == (r["plane"], r["zline"])
+    ctx.close()
