@@ -8,6 +8,7 @@
 #include <new>
 
 #include "nn_internal.h"
+#include "host_geometry.h"
 #include "sea_internal.h"
 
 namespace {
@@ -36,7 +37,6 @@ sea_status fail(sea_ctx* ctx, sea_status st, const char* fmt, ...) {
             return fail(ctx, SEA_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
     } while (0)
 
-double minimg(double d, double L) { return d - L * std::nearbyint(d / L); }
 
 sea_status check_opts(sea_ctx* ctx, const sea_opts* o) {
     if (!o) return fail(ctx, SEA_E_ARG, "opts is NULL");
@@ -389,32 +389,7 @@ sea_status sea_build_pairs(const sea_grid* grid, int n_occ, const double* c, dou
     if (check_grid(nullptr, grid) != SEA_OK || n_occ < 0 || (n_occ > 0 && !c) || !n_out || cap < 0 ||
         (cap > 0 && !out) || !(r_pair >= 0.0) || !(half_width >= 0.0))
         return SEA_E_ARG;
-    int cnt = 0;
-    for (int i = 0; i < n_occ; ++i) {
-        for (int j = i; j < n_occ; ++j) {
-            double d[3], d2 = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                d[a] = minimg(c[3 * j + a] - c[3 * i + a], grid->L[a]);
-                d2 += d[a] * d[a];
-            }
-            if (i != j && !(std::sqrt(d2) < r_pair)) continue;
-            if (cnt < cap) {
-                sea_pair& p = out[cnt];
-                p.i = i;
-                p.j = j;
-                for (int a = 0; a < 3; ++a) {
-                    const double h = grid->L[a] / grid->n[a];
-                    const double m = c[3 * i + a] + 0.5 * d[a];
-                    const int kc = (int)std::floor(m / h + 0.5);
-                    const int w = (int)std::ceil(half_width / h - 1e-12);
-                    p.lo[a] = kc - w;
-                    p.n[a] = 2 * w + 1;
-                    p.origin[a] = kc * h;
-                }
-            }
-            ++cnt;
-        }
-    }
+    const int cnt = host_build_pairs(grid->n, grid->L, n_occ, c, r_pair, half_width, out, cap);
     *n_out = cnt;
     return cnt > cap ? SEA_E_NOMEM : SEA_OK;
 }
@@ -1296,75 +1271,6 @@ extern "C" sea_status sea_rotate(sea_ctx* ctx, int64_t n_grid, int n_occ, sea_dt
 
 // ---------------------------------------------------------------------------
 // epsilon-driven domains and pair screening (Eq. 16-17)
-
-namespace {
-
-// Shortest cyclic run of m[0..N) with mass >= target; among runs of that
-// length the largest mass, then the smallest start.  Direct sums, in the
-// order the runs are listed.
-void eps_run(const double* m, int N, double eps, int* lo, int* len) {
-    double T = 0.0;
-    for (int k = 0; k < N; ++k) T += m[k];
-    const double target = (1.0 - eps / 3.0) * T;
-    for (int ln = 1; ln < N; ++ln) {
-        double best = -1.0;
-        int bs = -1;
-        for (int s0 = 0; s0 < N; ++s0) {
-            double mass = 0.0;
-            for (int t = 0; t < ln; ++t) mass += m[(s0 + t) % N];
-            if (mass >= target && mass > best) {
-                best = mass;
-                bs = s0;
-            }
-        }
-        if (bs >= 0) {
-            *lo = bs;
-            *len = ln;
-            return;
-        }
-    }
-    *lo = 0;
-    *len = N;
-}
-
-// Intersection of cyclic runs [a, a+la) and [b, b+lb) on Z_N; the longer
-// piece when there are two; start unwrapped into [a, a+la).
-int cyc_intersect(int a, int la, int b, int lb, int N, int* start) {
-    if (la >= N) {
-        *start = b;
-        return lb;
-    }
-    if (lb >= N) {
-        *start = a;
-        return la;
-    }
-    int best = 0;
-    for (int k = -1; k <= 1; ++k) {
-        const int s0 = std::max(a, b + k * N);
-        const int e0 = std::min(a + la, b + k * N + lb);
-        if (e0 - s0 > best) {
-            best = e0 - s0;
-            *start = s0;
-        }
-    }
-    return best;
-}
-
-// Start of a run of length ln shifted by a multiple of N so that its centre
-// is nearest the centre of the reference run [r0, r0 + rn).
-int near_start(int lo, int ln, int r0, int rn, int N) {
-    int best = lo, bd = -1;
-    for (int k = -1; k <= 1; ++k) {
-        const int d = std::abs(2 * (lo + k * N) + ln - (2 * r0 + rn));
-        if (bd < 0 || d < bd) {
-            bd = d;
-            best = lo + k * N;
-        }
-    }
-    return best;
-}
-
-}  // namespace
 
 extern "C" sea_status sea_eps_workspace_bytes(sea_ctx* ctx, const sea_grid* grid, int n_occ, size_t* bytes) {
     if (!ctx || !bytes) return SEA_E_ARG;
