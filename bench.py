@@ -218,6 +218,7 @@ def main():
     ap.add_argument("--cg-variant", default=None,
                     help="fixed FP32 CG kernel variant (skips the autotuner; for profiling runs)")
     ap.add_argument("--form-calls", type=int, default=5, help="event-timed calls per other form (median)")
+    ap.add_argument("--metrics-jsonl", default=None, help="append per-step records and the result line here")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 2 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -229,7 +230,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2208_06097_amd import sea, synth
+    from paper_2208_06097_amd import runlog, sea, synth
 
     have_w = os.path.exists(args.weights)
     form = args.form or "spectral-f32"
@@ -337,6 +338,8 @@ def main():
         for kk, v in st_k.items():
             stage_acc[kk] += v
         vxx_steps.append(vxx_event_ms[-1])
+        runlog.append(args.metrics_jsonl, "bench_step", step=k + 1, form=form, vxx_ms=vxx_event_ms[-1],
+                      stage_ms=st_k)
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -573,6 +576,7 @@ def main():
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(cell, pairs, n_pairs)
     print(json.dumps(out), flush=True)
+    runlog.append(args.metrics_jsonl, "bench_result", **out)
     ctx.close()
 
 

@@ -23,7 +23,7 @@ import time
 
 import numpy as np
 
-from . import sea, synth
+from . import runlog, sea, synth
 
 
 def log(*a):
@@ -40,6 +40,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--replays", type=int, default=1, help="timed graph replays per group")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--metrics-jsonl", default=None, help="append per-group records here")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -94,6 +95,9 @@ def main():
                              "E_xx": float(e), "iters_mean": float(s["iters"].mean()),
                              "converged": bool(np.all(s["converged"] == 1))})
         free_b, total_b = torch.cuda.mem_get_info()
+        runlog.append(args.metrics_jsonl, "batch_group", group=g0 // args.group, cells=grp, pairs=n_pairs,
+                      gpu_ms=t_ms, replay_ms=ms, iters_mean=float(stats["iters"].mean()), status=int(st),
+                      input_s=t_gen, free_gib=free_b / 2**30)
         log(f"group {g0 // args.group}: cells {grp[0]}..{grp[-1]}, {n_pairs} pairs, {t_ms:.1f} ms "
             f"({n_pairs / t_ms * 1e3:.0f} pairs/s), iters {stats['iters'].mean():.1f}, status {st}, "
             f"inputs {t_gen:.1f} s, device memory free {free_b / 2**30:.0f} of {total_b / 2**30:.0f} GiB")

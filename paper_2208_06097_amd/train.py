@@ -11,6 +11,7 @@ Adam with a cosine learning-rate decay; the network, its backward pass and
 the optimizer all run in the library's kernels.
 
     python -m paper_2208_06097_amd.train --out weights.npy [--cells 12] [--epochs 8]
+        [--checkpoint ckpt.npz --stop-after K]   (resumable: run again to continue)
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ import time
 
 import numpy as np
 
-from . import sea, synth
+from . import runlog, sea, synth
 
 
 def log(*a):
@@ -72,7 +73,28 @@ def make_samples(ctx, cells, D=32, max_samples=None):
     return torch.cat(xs), torch.cat(ts)
 
 
-def train(ctx, x, t, epochs=8, batch=32, lr=2e-3, seed=4242, init_seed=0, max_samples=None, state=None):
+def save_checkpoint(path, state, step, epoch, gen, hist):
+    """Whole device state (FP32 parameters, BF16 copy, Adam m and v), the step
+    and epoch reached, the shuffling generator's state and the history."""
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, state=state.cpu().numpy(), step=np.int64(step), epoch=np.int64(epoch),
+             gen=gen.get_state().numpy(), hist=np.frombuffer(json.dumps(hist).encode(), dtype=np.uint8))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path):
+    import torch
+    z = np.load(path, allow_pickle=False)
+    return (torch.from_numpy(z["state"]).cuda(), int(z["step"]), int(z["epoch"]), torch.from_numpy(z["gen"]),
+            json.loads(bytes(z["hist"]).decode()))
+
+
+def train(ctx, x, t, epochs=8, batch=32, lr=2e-3, seed=4242, init_seed=0, max_samples=None, state=None,
+          checkpoint=None, stop_after=None, metrics=None):
+    """Adam with cosine decay over `epochs`.  With `checkpoint` (a .npz path)
+    the state is saved after every epoch and, when the file exists, training
+    resumes from it (same samples, same shuffles, same schedule); with
+    `stop_after` it stops after that many epochs of this call."""
     import torch
     n = x.shape[0]
     g = torch.Generator(device="cpu").manual_seed(seed)
@@ -98,12 +120,20 @@ def train(ctx, x, t, epochs=8, batch=32, lr=2e-3, seed=4242, init_seed=0, max_sa
             cnt += yb.shape[0]
         return tot / max(cnt, 1)
 
-    hist = [{"epoch": 0, "val": val_loss(), "val_rel": None}]
     tv2 = float(torch.mean(tv ** 2))
-    hist[0]["val_rel"] = hist[0]["val"] / tv2
-    log(f"epoch 0: val {hist[0]['val']:.4e} (rel {hist[0]['val_rel']:.3f})")
-    step = 0
-    for ep in range(1, epochs + 1):
+    step, ep0 = 0, 0
+    if checkpoint and os.path.exists(checkpoint):
+        state, step, ep0, gstate, hist = load_checkpoint(checkpoint)
+        g.set_state(gstate)
+        log(f"resumed from {checkpoint}: epoch {ep0}, step {step}")
+    else:
+        hist = [{"epoch": 0, "val": val_loss(), "val_rel": None}]
+        hist[0]["val_rel"] = hist[0]["val"] / tv2
+        log(f"epoch 0: val {hist[0]['val']:.4e} (rel {hist[0]['val_rel']:.3f})")
+    done = 0
+    for ep in range(ep0 + 1, epochs + 1):
+        if stop_after is not None and done >= stop_after:
+            break
         t0 = time.perf_counter()
         order = tr_idx[torch.randperm(tr_idx.numel(), generator=g).cuda()]
         tl = []
@@ -120,6 +150,10 @@ def train(ctx, x, t, epochs=8, batch=32, lr=2e-3, seed=4242, init_seed=0, max_sa
                      "seconds": time.perf_counter() - t0})
         log(f"epoch {ep}: train {hist[-1]['train']:.4e} val {v:.4e} (rel {v / tv2:.3f}) "
             f"{hist[-1]['seconds']:.1f} s")
+        runlog.append(metrics, "train_epoch", **hist[-1])
+        done += 1
+        if checkpoint:
+            save_checkpoint(checkpoint, state, step, ep, g, hist)
     return state, hist
 
 
@@ -132,6 +166,9 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--weights", default="bf16", choices=["bf16", "f32"])
+    ap.add_argument("--checkpoint", default=None, help="per-epoch checkpoint (.npz): saved, and resumed from")
+    ap.add_argument("--stop-after", type=int, default=None, help="epochs to run in this call (then checkpoint)")
+    ap.add_argument("--metrics-jsonl", default=None, help="append per-epoch records here")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -141,7 +178,8 @@ def main():
     x, t = make_samples(ctx, training_cells(args.cells), max_samples=args.max_samples)
     log(f"{x.shape[0]} samples in {time.perf_counter() - t0:.1f} s")
     state, hist = train(ctx, x, t, epochs=args.epochs, batch=args.batch, lr=args.lr,
-                        max_samples=args.max_samples)
+                        max_samples=args.max_samples, checkpoint=args.checkpoint, stop_after=args.stop_after,
+                        metrics=args.metrics_jsonl)
     params = ctx.nn_get_params(state)
     np.save(args.out, params)
     meta = {"samples": int(min(x.shape[0], args.max_samples)), "epochs": args.epochs, "batch": args.batch,
