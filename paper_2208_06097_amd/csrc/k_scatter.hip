@@ -35,6 +35,11 @@ __device__ __forceinline__ bool axis_hits(int t0, int T, int lo, int n, int N) {
 // outside it the multipole potential of the pair (Eq. 10).
 // The cell's record comes by value, so its pointers are kernel arguments:
 // uniform, and known to the compiler to address global memory.
+// GENERAL: some W box reaches beyond its pair's domain (multipole values
+// there) or is wider than the cell (points met several times); without it
+// every W box is its pair's domain, and the kernel carries neither path (nor
+// their registers).  PT: the orbitals' precision.
+template <bool GENERAL, typename PT>
 __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const DevCell C, const int* __restrict__ off_all,
                                                    const int2* __restrict__ ent) {
     __shared__ int list[SC_MAXE];
@@ -89,7 +94,7 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const DevCell C, c
                     const int* D = a.dbox + 12 * (size_t)pid + (iside ? 0 : 6);
                     hit = axis_hits(tx0, SC_TX, D[0], D[3], C.N[0]) && axis_hits(ty0, SC_TY, D[1], D[4], C.N[1]) &&
                           axis_hits(tz0, SC_TZ, D[2], D[5], C.N[2]);
-                    wd = hit && (D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2]);
+                    wd = GENERAL && hit && (D[3] > C.N[0] || D[4] > C.N[1] || D[5] > C.N[2]);
                     // the pair's energy partial of this tile: i side, a W box
                     // that holds the domain once, a tile the domain meets
                     if (hit && iside && take_e && ep_takes(P, D, C.N) &&
@@ -141,9 +146,7 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const DevCell C, c
         const int cx = threadIdx.x % SC_TX, cy = threadIdx.x / SC_TX;
         const int gx = tx0 + cx, gy = ty0 + cy;
         const bool colin = gx < C.N[0] && gy < C.N[1];
-        // one copy of the loop per orbital precision: no per-point branch on it
-        auto fast_entries = [&](auto f32) {
-            using PT = typename std::conditional<decltype(f32)::value, float, double>::type;
+        {
             const PT* __restrict__ ph = (const PT*)C.phi;
             // this orbital at the column's points (in LDS), for the energy partials
             if (n_e) {
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const DevCell C, c
                 int e[14];
 #pragma unroll
                 for (int d = 0; d < 14; ++d) e[d] = __builtin_amdgcn_readfirstlane(meta[q][d]);
-                if (__builtin_amdgcn_readfirstlane(meta[q][14])) continue;   // general path below
+                if (GENERAL && __builtin_amdgcn_readfirstlane(meta[q][14])) continue;   // general path below
                 const int eslot = __builtin_amdgcn_readfirstlane(meta[q][15]);
                 const int pid = e[0], oth = e[1];
                 const int* D = &e[2];
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const DevCell C, c
                         const bool zin = valid && sz >= 0 && sz < pn[2];
                         const bool inside = zin && in_xy;
                         ins[k] = inside;
-                        me[k] = valid && !inside;
+                        me[k] = GENERAL && valid && !inside;
                         if constexpr (std::is_same<PT, float>::value) {
                             // unconditional (a clamped plane is in bounds), so the
                             // widening is not pulled into a branch with its own wait
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const DevCell C, c
                     bool any_me = false;
 #pragma unroll
                     for (int k = 0; k < SC_TZ; ++k) any_me |= me[k];
-                    if (any_me) {   // the multipole value outside the domain (W boxes beyond it)
+                    if (GENERAL && any_me) {   // the multipole value outside the domain (W boxes beyond it)
                         const double* cf = a.mpoly + (size_t)pid * SC_NM;
                         const double* org = a.pairs[pid].origin;
 #pragma unroll
@@ -239,11 +242,9 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const DevCell C, c
                     if ((threadIdx.x & 63) == 0) ep_w[list[q] - e0][threadIdx.x >> 6] = ep;
                 }
             }
-        };
-        if (C.phi_f32) fast_entries(std::true_type());
-        else fast_entries(std::false_type());
+        }
         // general path: boxes wider than the cell (a grid point met several times)
-        if (wide)
+        if (GENERAL && wide)
 #pragma unroll
         for (int k = 0; k < SC_TX * SC_TY * SC_TZ / SC_BS; ++k) {
             const int lid = threadIdx.x + k * SC_BS;
@@ -315,7 +316,13 @@ hipError_t launch_scatter(const ExxArgs& a, const DevCell& cell, const int* csr_
     const int* N = cell.N;
     const int tiles = ((N[0] + SC_TX - 1) / SC_TX) * ((N[1] + SC_TY - 1) / SC_TY) * ((N[2] + SC_TZ - 1) / SC_TZ);
     dim3 grid(tiles, cell.n_occ);
-    hipLaunchKernelGGL(k_scatter, grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
+    if (cell.wbox_general) {
+        if (cell.phi_f32) hipLaunchKernelGGL((k_scatter<true, float>), grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
+        else hipLaunchKernelGGL((k_scatter<true, double>), grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
+    } else {
+        if (cell.phi_f32) hipLaunchKernelGGL((k_scatter<false, float>), grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
+        else hipLaunchKernelGGL((k_scatter<false, double>), grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
+    }
     return hipGetLastError();
 }
 

@@ -159,6 +159,8 @@ static sea_status build_cellset(sea_ctx* ctx, int n_cells, const sea_cell* cells
                         return fail(ctx, SEA_E_ARG, "cell %d pair %d: W box out of range", c, k);
                 }
                 S.dbox.insert(S.dbox.end(), box, box + 6);
+                for (int a2 = 0; a2 < 3; ++a2)
+                    if (box[a2] != P.lo[a2] || box[3 + a2] != P.n[a2] || box[3 + a2] > D.N[a2]) D.wbox_general = 1;
             }
         }
         D.pair_end = (int)S.pairs.size();

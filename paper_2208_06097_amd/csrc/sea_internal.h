@@ -94,6 +94,7 @@ struct DevCell {
     double* exx;          // device scalar (nullable)
     int pair_begin, pair_end;
     int csr_base;         // offset of this cell's orbital lists in the CSR arrays
+    int wbox_general;     // some W box is not its pair's domain, or is wider than the cell
 };
 
 // Arguments shared by the exx kernels (passed by value).
