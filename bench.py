@@ -102,7 +102,7 @@ PROFILE_OF = {
     "k_residual_zm": "k_residual_zm_spectral_c2.md",
     "k_gather_cart": "k_gather_cart_spectral_c2.md",
     "k_cg_zm": "k_cg_zm_learned_c2.md",
-    "k_cg_f64": "k_cg_f64_plain_c2.md",
+    "k_cg64": "k_cg64_plain_c2.md",
 }
 
 
@@ -179,10 +179,11 @@ def kernel_rooflines(form, stages, pairs, npts, stats, cell, n_pairs, tune, wbyt
                                        "16 B per pair-domain point (x and b read, FP64); a second launch writes "
                                        "b - A x only for starts that miss the target", tr("k_residual_zm"))
     else:
-        k = "k_cg_zm" if FORMS[form]["stencil"] == "f32" else "k_cg_f64"
+        k = "k_cg_zm" if FORMS[form]["stencil"] == "f32" else "k_cg64"
         cgb = float(np.sum(stats["iters"].astype(np.float64) * 6.0 * npts * wbytes))
-        out[k] = _kernel(k if k == "k_cg_f64" else f"k_cg_zm<float, {tune['variant'] if tune else ''}>",
-                         stages["cg"], 1, cgb, f"6 words x {int(wbytes)} B per interior point per CG iteration",
+        name = (f"k_cg_zm<float, {tune['variant'] if tune else ''}>" if k == "k_cg_zm" else
+                "k_cg64_init/k_cg64_sweep<0,1> (row tiles, two sweeps per iteration)")
+        out[k] = _kernel(name, stages["cg"], 1, cgb, f"6 words x {int(wbytes)} B per interior point per CG iteration",
                          tr(k, cg_iters_total=int(stats["iters"].sum())))
     return out
 
@@ -196,7 +197,7 @@ def cg_roofline(form, cg_ms, stats, npts):
     if b == 0.0 or cg_ms <= 0.0:
         return None
     gbs = b / (cg_ms * 1e-3) / 1e9
-    return {"kernel": "k_cg_zm<float>" if w == 4.0 else "k_cg_f64", "ms": cg_ms, "bytes": b,
+    return {"kernel": "k_cg_zm<float>" if w == 4.0 else "k_cg64 (row tiles)", "ms": cg_ms, "bytes": b,
             "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
 
 

@@ -307,6 +307,10 @@ sea_status sea_spectral_autotune(sea_ctx *ctx, int n_cells, const sea_cell *cell
  * waits for the last launch and copies E_xx per cell and the per-pair stats
  * (both nullable).  Stage profiling is not recorded in a plan. */
 typedef struct sea_plan sea_plan;
+/* Workspace bytes of a plan of these cells: a plan always runs the kernel
+ * sequence a graph can hold, so it needs no arrays of the FP64 row-tile CG
+ * (at most sea_exx_batched_workspace_bytes of the same cells). */
+sea_status sea_exx_plan_workspace_bytes(sea_ctx *ctx, int n_cells, const sea_cell *cells, size_t *bytes);
 sea_status sea_exx_plan_create(sea_ctx *ctx, int n_cells, const sea_cell *cells, void *ws_dev,
                                size_t ws_bytes, sea_plan **out);
 sea_status sea_exx_plan_launch(sea_plan *plan, void *hip_stream);

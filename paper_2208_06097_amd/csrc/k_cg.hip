@@ -212,9 +212,9 @@ __device__ __forceinline__ double apply_A_global(const double* __restrict__ p, i
     return s;
 }
 
-// Reliable-update trigger: replace the recursive residual by the FP64 one
-// whenever it has dropped by another factor Delta (squared here); FP64 state
-// only replaces at convergence.
+// FP32 z-march: the reliable-update trigger replaces the recursive residual
+// by the FP64 one whenever it has dropped by another factor Delta (squared
+// here).
 //
 // Exit target: the FP64 residual must reach `target` x rel_tol.  FP32 state
 // loses the Galerkin orthogonality of CG, which makes the pair energies'
@@ -224,11 +224,6 @@ __device__ __forceinline__ double apply_A_global(const double* __restrict__ p, i
 // more iterations.
 template <typename T>
 struct Delta;
-template <>
-struct Delta<double> {
-    static constexpr double v2 = 0.0;
-    static constexpr double target = 0.9;
-};
 template <>
 struct Delta<float> {
     static constexpr double v2 = 1e-2;
@@ -609,12 +604,8 @@ __global__ __launch_bounds__(FIN_BS) void k_start_residual(ExxArgs a) {
     }
 }
 
-// b - A x in FP64 for every pair of a cubic grid with nx, ny <= 64: the
-// z-march above on FP64 planes.  A workgroup owns 16 rows (y) of one pair
-// and marches a window of 28 rows (6 more on each side, fetched again by the
-// neighbouring workgroups) so that its register queue (2 rows per thread,
-// 13 planes) fits; rows of the window outside the domain read zero.
-// Two launches: NORMS writes |b|^2 and |b - A x|^2 of the owned rows into
+// b - A x in FP64 for every pair of a cubic grid with nx, ny <= 64, by the
+// row-tile march below.  Two launches: NORMS writes |b|^2 and |b - A x|^2 of the owned rows into
 // a.rnorm[pair][tile][2] and nothing else; WRITE stores b - A x into bres
 // for the pairs whose start does not meet the CG's exit test (from those
 // norms; the others return at once), so a start that is already converged
@@ -623,15 +614,77 @@ __global__ __launch_bounds__(FIN_BS) void k_start_residual(ExxArgs a) {
 // on one XCD (workgroup k goes to XCD k mod 8): the rows a tile fetches
 // again for its neighbours' window are then served by the same L2.
 constexpr int RZ_NT = 1024;
-constexpr int RZ_COLS = 2;
-constexpr int RZ_ROWS = 16;   // rows owned per workgroup
+constexpr int RZ_ROWS = 16;   // rows owned per workgroup: one per wavefront
+constexpr int RZ_WR = RZ_ROWS + 2 * SEA_HALO;   // rows of the window
 constexpr int RZ_XCD = 8;
 static_assert(RZ_TILES * RZ_ROWS >= 64, "row tiles cover 64 rows");
+static_assert(RZ_NT / 64 == RZ_ROWS && 2 * SEA_HALO <= RZ_ROWS, "a wavefront per owned row; halo rows fit");
 
 __device__ __forceinline__ void rz_block(int& pid, int& tile) {
     const int k = blockIdx.x, m = k / RZ_XCD;
     pid = (m / RZ_TILES) * RZ_XCD + k % RZ_XCD;
     tile = m % RZ_TILES;
+}
+
+// Row-tile z-march of A applied to a field f (FP64).  A workgroup owns
+// RZ_ROWS rows (y) of one pair, a wavefront per row and a lane per x, and
+// marches z over a window of RZ_WR rows (SEA_HALO more on each side, which
+// the neighbouring workgroups own).  Only the owned rows keep the 13-plane
+// register queue and form the stencil; wavefronts ty < 2 SEA_HALO also load
+// one halo row's current plane into LDS for the y taps (window row ty below
+// the tile, ty + RZ_ROWS above it).  fetch(yw, z) issues the loads of window
+// row yw at plane z, two steps before they are used (two planes of loads in
+// flight per row, so that a step's work covers the memory latency),
+// make(yw, z, F) turns them into f, pre(z) prefetches the owned point's data
+// of output plane z, out(z, A f, f, PV) consumes it.  Two LDS planes of
+// RZ_WR x 64 doubles.
+template <typename F, typename PV, typename FetchF, typename MakeF, typename PreF, typename OutF>
+__device__ __forceinline__ void rtmarch(int nz, double* lds, const SW<double>& w, FetchF&& fetch, MakeF&& make,
+                                        PreF&& pre, OutF&& out) {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int yo = ty + SEA_HALO;                          // owned row in the window
+    const bool halo = ty < 2 * SEA_HALO;
+    const int yh = ty < SEA_HALO ? ty : ty + RZ_ROWS;     // halo row in the window
+    double q[13];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) q[k] = 0.0;
+#pragma unroll
+    for (int s = 0; s < 7; ++s) q[6 + s] = make(yo, s, fetch(yo, min(s, nz)));
+    F on = fetch(yo, min(7, nz));   // the owned row's plane z + 7, fetched at step z - 1
+    F hn{}, hn2{};                   // the halo row's planes z and z + 1
+    if (halo) {
+        hn = fetch(yh, 0);
+        hn2 = fetch(yh, min(1, nz));
+    }
+    for (int z = 0; z < nz; ++z) {
+        const F nxt = on;
+        on = fetch(yo, min(z + 8, nz));
+        const F hc = hn;
+        if (halo) {
+            hn = hn2;
+            hn2 = fetch(yh, min(z + 2, nz));
+        }
+        const PV pv = pre(z);
+        double* pl = lds + (z & 1) * (LW * RZ_WR);
+        pl[yo * LW + tx] = q[6];
+        if (halo) pl[yh * LW + tx] = make(yh, z, hc);
+        lds_sync();
+        __builtin_amdgcn_sched_barrier(0);
+        const double* row = pl + yo * LW + tx;
+        double sacc = w.w[0] * q[6];
+        double u = q[6], d = q[6];
+#pragma unroll
+        for (int k = 1; k <= SEA_HALO; ++k) {
+            u = wshl1(u);
+            d = wshr1(d);
+            sacc += w.w[k] * ((u + d) + (row[k * LW] + row[-k * LW]) + (q[6 + k] + q[6 - k]));
+        }
+        out(z, sacc, q[6], pv);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) q[k] = q[k + 1];
+        q[12] = make(yo, z + 7, nxt);
+    }
 }
 
 template <bool WRITE>
@@ -645,6 +698,8 @@ __global__ __launch_bounds__(RZ_NT) void k_residual_zm(ExxArgs a) {
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const int y0 = tile * RZ_ROWS;
+    // after the row-tile CG: a pair its start stopped keeps the start's norms
+    if (!WRITE && a.cg_done && a.cg_done[pid] == 2) return;
     if (WRITE) {
         double b2, q2;
         if (y0 >= ny || start_meets_target(a, pid, Delta<float>::target * Delta<float>::target * a.rel_tol * a.rel_tol,
@@ -657,35 +712,26 @@ __global__ __launch_bounds__(RZ_NT) void k_residual_zm(ExxArgs a) {
         }
         return;
     }
-    for (int i = threadIdx.x; i < 2 * LW * LH; i += RZ_NT) lds[i] = 0.0;
     const DevCell& C = a.cells[a.pair_cell[pid]];
     const SW<double> w = make_sw<double>(1.0 / (C.h[0] * C.h[0]));
     const double* __restrict__ x = a.v + (size_t)pid * a.stride;
     const double* __restrict__ b = a.b + (size_t)pid * a.stride;
     double* __restrict__ r = a.bres + (size_t)pid * a.stride;
-    constexpr int TY = RZ_NT / 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    __syncthreads();
-    // window row yw = ty + TY c is grid row y0 - 6 + yw; rows 6..21 are owned
-    auto grow = [&](int c) { return y0 - SEA_HALO + ty + TY * c; };
-    auto owned = [&](int c) {
-        const int yw = ty + TY * c, y = grow(c);
-        return yw >= SEA_HALO && yw < SEA_HALO + RZ_ROWS && y < ny && tx < nx;
-    };
+    const int tx = threadIdx.x & 63, yown = y0 + (threadIdx.x >> 6);
+    const bool own = yown < ny && tx < nx;
     double bb = 0.0, rr = 0.0;
-    zmarch<double, double, RZ_NT, RZ_COLS, 1, double, double>(
+    rtmarch<double, double>(
         nz, lds, w,
-        [&](int c, int z) -> double {
-            const int yw = ty + TY * c, y = grow(c);
-            return (tx < nx && y >= 0 && y < ny && yw < RZ_ROWS + 2 * SEA_HALO && z < nz)
-                       ? x[((size_t)z * ny + y) * nx + tx] : 0.0;
+        [&](int yw, int z) -> double {   // window row yw is grid row y0 - SEA_HALO + yw
+            const int y = y0 - SEA_HALO + yw;
+            return (tx < nx && y >= 0 && y < ny && z < nz) ? x[(z * ny + y) * nx + tx] : 0.0;
         },
         [&](int, int, double v) -> double { return v; },
-        [&](int c, int z) -> double { return owned(c) ? b[((size_t)z * ny + grow(c)) * nx + tx] : 0.0; },
-        [&](int c, int z, double s, double, double bv) {
-            if (owned(c)) {
+        [&](int z) -> double { return own ? b[(z * ny + yown) * nx + tx] : 0.0; },
+        [&](int z, double s, double, double bv) {
+            if (own) {
                 const double rv = bv - s;
-                if (WRITE) r[((size_t)z * ny + grow(c)) * nx + tx] = rv;
+                if (WRITE) r[(z * ny + yown) * nx + tx] = rv;
                 bb += bv * bv;
                 rr += rv * rv;
             }
@@ -699,9 +745,261 @@ __global__ __launch_bounds__(RZ_NT) void k_residual_zm(ExxArgs a) {
     }
 }
 
-size_t residual_zm_lds_bytes() { return (size_t)2 * LW * LH * sizeof(double); }
+// ---------------------------------------------------------------------------
+// FP64-state CG by row tiles (the plain FP64 form of Eq. 9).  Its 13-plane
+// FP64 register queue does not fit a whole pair in one workgroup, so the
+// state of every pair (x in v, r and p in their own arrays) stays in HBM
+// and every CG sweep is one launch over all pairs and their row tiles (the
+// residual sweep's 16 owned rows, 28-row window and XCD mapping).  The
+// scalars of a pair come from per-tile partial sums, summed by every tile in
+// the same fixed order, so all tiles of a pair take the same decisions:
+//   sweep A (iteration k): rho_k = |r|^2; stop if rho_k <= tol^2 |b|^2, at
+//     max_iter or on a non-finite value; else beta = rho_k / rho_{k-1}
+//     (0 at k = 0), p = r + beta p on the window (the halo rows recomputed,
+//     the owned rows written to the other of two p arrays), <p, A p>;
+//   sweep B: alpha = rho_k / <p, A p>, x += alpha p, r -= alpha A p, |r|^2.
+// The |r|^2 partials alternate between two slots by iteration parity, so a
+// sweep never overwrites a partial another tile of its pair still reads.
+// The stop test runs on the recursive residual at 0.9 x rel_tol; the true
+// FP64 residual b - A x is formed afterwards for the reported rel_res.
+// Preconditioned (a.cg_pre, the spectral form's continuation): z = M^-1 r
+// with M = A_odd, the stencil with odd continuation past the faces, applied
+// exactly by the sine-transform passes between the sweeps; rho = <r, z>
+// takes the place of |r|^2 in alpha and beta, p = z + beta p.  M differs
+// from A only next to the faces, so few iterations remain.
+constexpr double CG64_TARGET = 0.9;
+// partial slots per row tile: |r|^2 by parity (0, 1), <p, A p> (2), |b|^2
+// (3), <r, z> by parity (4, 5; the preconditioned form's rho)
+constexpr int CG64_SLOTS = 8;
+__device__ __forceinline__ int cg64_rho_slot(const ExxArgs& a, int k) { return (a.cg_pre ? 4 : 0) + (k & 1); }
 
-hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s) {
+__device__ __forceinline__ double cg64_sum(const ExxArgs& a, int pid, int slot) {
+    double s = 0.0;
+    for (int t = 0; t < RZ_TILES; ++t) s += a.cg_part[((size_t)pid * RZ_TILES + t) * CG64_SLOTS + slot];
+    return s;
+}
+
+__global__ __launch_bounds__(RZ_NT) void k_cg64_init(ExxArgs a) {
+    extern __shared__ unsigned char smem[];
+    double* lds = reinterpret_cast<double*>(smem);
+    __shared__ double red[RZ_NT / 64 + 1];
+    int pid, tile;
+    rz_block(pid, tile);
+    if (pid >= a.n_pairs) return;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int y0 = tile * RZ_ROWS;
+    double* part = a.cg_part + ((size_t)pid * RZ_TILES + tile) * CG64_SLOTS;
+    if (a.rnorm) {   // a start whose true residual (its norms) already meets the target stops here
+        double b2, q2;
+        if (start_meets_target(a, pid, CG64_TARGET * CG64_TARGET * a.rel_tol * a.rel_tol, b2, q2)) {
+            if (tile == 0 && threadIdx.x == 0) {
+                a.cg_done[pid] = 2;   // stopped by its start: the final norms pass skips it
+                a.stats[pid].iters = 0;
+                a.stats[pid].converged = 1;
+                a.stats[pid].rel_res = b2 > 0.0 ? sqrt(q2 / b2) : 0.0;
+            }
+            return;
+        }
+    }
+    if (tile == 0 && threadIdx.x == 0) {
+        a.cg_done[pid] = 0;
+        atomicAdd(a.cg_active + a.max_iter + 1, 1);   // pairs that iterate
+    }
+    if (y0 >= ny) {
+        if (threadIdx.x == 0)
+            for (int q = 0; q < CG64_SLOTS; ++q) part[q] = 0.0;
+        return;
+    }
+    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const SW<double> w = make_sw<double>(1.0 / (C.h[0] * C.h[0]));
+    double* __restrict__ x = a.v + (size_t)pid * a.stride;
+    const double* __restrict__ b = a.b + (size_t)pid * a.stride;
+    double* __restrict__ r = a.cg_r + (size_t)pid * a.stride;
+    double* __restrict__ p = a.cg_p + (size_t)pid * a.stride;   // parity 0: read by sweep A of iteration 0
+    const int tx = threadIdx.x & 63, yown = y0 + (threadIdx.x >> 6);
+    const bool own = yown < ny && tx < nx;
+    const bool x0 = a.x_nonzero;
+    double bb = 0.0, rr = 0.0;
+    rtmarch<double, double>(
+        nz, lds, w,
+        [&](int yw, int z) -> double {
+            const int y = y0 - SEA_HALO + yw;
+            return (x0 && tx < nx && y >= 0 && y < ny && z < nz) ? x[(z * ny + y) * nx + tx] : 0.0;
+        },
+        [&](int, int, double v) -> double { return v; },
+        [&](int z) -> double { return own ? b[(z * ny + yown) * nx + tx] : 0.0; },
+        [&](int z, double s, double, double bv) {
+            if (own) {
+                const int id = (z * ny + yown) * nx + tx;
+                const double rv = bv - s;
+                r[id] = rv;
+                p[id] = rv;
+                if (!x0) x[id] = 0.0;
+                bb += bv * bv;
+                rr += rv * rv;
+            }
+        });
+    bb = block_sum<RZ_NT>(bb, red);
+    rr = block_sum<RZ_NT>(rr, red);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < CG64_SLOTS; ++q) part[q] = 0.0;
+        part[0] = rr;
+        part[3] = bb;
+    }
+}
+
+template <int SWEEP>
+__global__ __launch_bounds__(RZ_NT) void k_cg64_sweep(ExxArgs a) {
+    extern __shared__ unsigned char smem[];
+    double* lds = reinterpret_cast<double*>(smem);
+    __shared__ double red[RZ_NT / 64 + 1];
+    int pid, tile;
+    rz_block(pid, tile);
+    if (pid >= a.n_pairs || a.cg_done[pid]) return;
+    const int k = a.cg_it;
+    const double rho = cg64_sum(a, pid, cg64_rho_slot(a, k));
+    if (SWEEP == 0) {
+        const double rr = a.cg_pre ? cg64_sum(a, pid, k & 1) : rho;
+        const double bb = cg64_sum(a, pid, 3);
+        const double tol2 = CG64_TARGET * CG64_TARGET * a.rel_tol * a.rel_tol;
+        const bool nan = !(rr == rr) || !(bb == bb) || !(rho == rho);
+        if (nan || rr <= tol2 * bb || k >= a.max_iter) {
+            if (tile == 0 && threadIdx.x == 0) {
+                a.stats[pid].iters = k;
+                a.stats[pid].converged = nan ? -1 : (rr <= tol2 * bb ? 1 : 0);
+                a.stats[pid].rel_res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+                a.cg_done[pid] = 1;
+            }
+            return;
+        }
+        if (tile == 0 && threadIdx.x == 0) {
+            atomicAdd(a.cg_active + k, 1);
+            a.cg_rho[(size_t)pid * 2 + (k & 1)] = rho;
+        }
+    }
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int y0 = tile * RZ_ROWS;
+    double* part = a.cg_part + ((size_t)pid * RZ_TILES + tile) * CG64_SLOTS;
+    if (y0 >= ny) {
+        if (threadIdx.x == 0) part[SWEEP == 0 ? 2 : ((k + 1) & 1)] = 0.0;
+        return;
+    }
+    const DevCell& C = a.cells[a.pair_cell[pid]];
+    const SW<double> w = make_sw<double>(1.0 / (C.h[0] * C.h[0]));
+    double* __restrict__ x = a.v + (size_t)pid * a.stride;
+    double* __restrict__ r = a.cg_r + (size_t)pid * a.stride;
+    // p by iteration parity: sweep A of iteration k reads p_k from array
+    // k & 1 (every tile reads its window's halo rows there, owned by other
+    // tiles) and writes p_{k+1} = r + beta p_k into the other array, which
+    // sweep B then reads
+    const double* __restrict__ p_in = a.cg_p + ((size_t)(k & 1) * a.n_pairs + pid) * a.stride;
+    double* __restrict__ p = a.cg_p + ((size_t)((k + 1) & 1) * a.n_pairs + pid) * a.stride;
+    const int tx = threadIdx.x & 63, yown = y0 + (threadIdx.x >> 6);
+    const bool own = yown < ny && tx < nx;
+    auto inwin = [&](int yw, int z) {   // window row yw is grid row y0 - SEA_HALO + yw
+        const int y = y0 - SEA_HALO + yw;
+        return tx < nx && y >= 0 && y < ny && z < nz;
+    };
+    auto widx = [&](int yw, int z) { return (z * ny + y0 - SEA_HALO + yw) * nx + tx; };   // < 64^3: 32-bit
+    auto oidx = [&](int z) { return (z * ny + yown) * nx + tx; };
+    double acc = 0.0;
+    if constexpr (SWEEP == 0) {
+        // p = r + beta p (z + beta p when preconditioned) over the window (the
+        // halo rows recomputed here, the owned rows written), <p, A p> over
+        // the owned rows
+        const double beta = k > 0 ? rho / a.cg_rho[(size_t)pid * 2 + ((k - 1) & 1)] : 0.0;
+        const double* __restrict__ src = (a.cg_pre ? a.cg_z : a.cg_r) + (size_t)pid * a.stride;
+        rtmarch<F2<double>, Empty>(
+            nz, lds, w,
+            [&](int yw, int z) -> F2<double> {
+                if (!inwin(yw, z)) return F2<double>{0.0, 0.0};
+                const int id = widx(yw, z);
+                return F2<double>{src[id], p_in[id]};
+            },
+            [&](int, int, F2<double> f) -> double { return f.a + beta * f.b; },
+            [&](int) { return Empty{}; },
+            [&](int z, double s, double ctr, Empty) {
+                if (own) {
+                    p[oidx(z)] = ctr;
+                    acc += ctr * s;
+                }
+            });
+        acc = block_sum<RZ_NT>(acc, red);
+        if (threadIdx.x == 0) part[2] = acc;
+    } else {
+        // x += alpha p, r -= alpha A p, |r|^2 over the owned rows
+        const double alpha = rho / cg64_sum(a, pid, 2);
+        rtmarch<double, F2<double>>(
+            nz, lds, w,
+            [&](int yw, int z) -> double { return inwin(yw, z) ? p[widx(yw, z)] : 0.0; },
+            [&](int, int, double v) -> double { return v; },
+            [&](int z) -> F2<double> {
+                if (!own) return F2<double>{0.0, 0.0};
+                const int id = oidx(z);
+                return F2<double>{x[id], r[id]};
+            },
+            [&](int z, double s, double ctr, F2<double> xr) {
+                if (own) {
+                    const int id = oidx(z);
+                    x[id] = xr.a + alpha * ctr;
+                    const double rn = xr.b - alpha * s;
+                    r[id] = rn;
+                    acc += rn * rn;
+                }
+            });
+        acc = block_sum<RZ_NT>(acc, red);
+        if (threadIdx.x == 0) part[(k + 1) & 1] = acc;
+    }
+}
+
+// The reported residual: the true FP64 one from the residual sweep's norms.
+__global__ __launch_bounds__(64) void k_cg64_exit(ExxArgs a) {
+    const int pid = blockIdx.x * 64 + threadIdx.x;
+    if (pid >= a.n_pairs) return;
+    double b2 = 0.0, q2 = 0.0;
+    for (int t = 0; t < RZ_TILES; ++t) {
+        b2 += a.rnorm[((size_t)pid * RZ_TILES + t) * 2];
+        q2 += a.rnorm[((size_t)pid * RZ_TILES + t) * 2 + 1];
+    }
+    DevStat st = a.stats[pid];
+    st.rel_res = b2 > 0.0 ? sqrt(q2 / b2) : 0.0;
+    if (!(q2 == q2)) st.converged = -1;
+    a.stats[pid] = st;
+}
+
+// <r, z> per row tile of the pairs still iterating, into the rho slot of
+// iteration a.cg_it + 1 (the preconditioned form; a.cg_it = -1 after the init).
+__global__ __launch_bounds__(RZ_NT) void k_cg64_dot(ExxArgs a) {
+    __shared__ double red[RZ_NT / 64 + 1];
+    int pid, tile;
+    rz_block(pid, tile);
+    if (pid >= a.n_pairs || a.cg_done[pid]) return;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int y0 = tile * RZ_ROWS, y1 = min(ny, y0 + RZ_ROWS);
+    const double* __restrict__ r = a.cg_r + (size_t)pid * a.stride;
+    const double* __restrict__ z = a.cg_z + (size_t)pid * a.stride;
+    double acc = 0.0;
+    const int row = nx, rows = y1 > y0 ? y1 - y0 : 0;
+    for (int zz = 0; zz < nz; ++zz)
+        for (int q = threadIdx.x; q < rows * row; q += RZ_NT) {
+            const int id = (zz * ny + y0) * nx + q;
+            acc += r[id] * z[id];
+        }
+    acc = block_sum<RZ_NT>(acc, red);
+    if (threadIdx.x == 0)
+        a.cg_part[((size_t)pid * RZ_TILES + tile) * CG64_SLOTS + cg64_rho_slot(a, a.cg_it + 1)] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_fill_int(int* p, size_t n) {
+    for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) p[k] = 0;
+}
+
+size_t residual_zm_lds_bytes() { return (size_t)2 * LW * RZ_WR * sizeof(double); }
+
+hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s, bool write) {
     if (a.n_pairs <= 0) return hipSuccess;
     const int lds = (int)residual_zm_lds_bytes();
     const unsigned nb = (unsigned)((a.n_pairs + RZ_XCD - 1) / RZ_XCD) * RZ_XCD * RZ_TILES;
@@ -710,7 +1008,48 @@ hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s) {
         e = hipFuncSetAttribute((const void*)k_residual_zm<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_residual_zm<false>, dim3(nb), dim3(RZ_NT), lds, s, a);
-    hipLaunchKernelGGL(k_residual_zm<true>, dim3(nb), dim3(RZ_NT), lds, s, a);
+    if (write) hipLaunchKernelGGL(k_residual_zm<true>, dim3(nb), dim3(RZ_NT), lds, s, a);
+    return hipGetLastError();
+}
+
+static unsigned rz_blocks(int n_pairs) { return (unsigned)((n_pairs + RZ_XCD - 1) / RZ_XCD) * RZ_XCD * RZ_TILES; }
+
+hipError_t launch_cg64_init(const ExxArgs& a, hipStream_t s) {
+    if (a.n_pairs <= 0) return hipSuccess;
+    const int lds = (int)residual_zm_lds_bytes();
+    hipError_t e = hipFuncSetAttribute((const void*)k_cg64_init, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cg64_init, dim3(rz_blocks(a.n_pairs)), dim3(RZ_NT), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg64_sweep(const ExxArgs& a, int sweep, hipStream_t s) {
+    if (a.n_pairs <= 0) return hipSuccess;
+    const int lds = (int)residual_zm_lds_bytes();
+    const void* fn = sweep == 0 ? (const void*)k_cg64_sweep<0> : (const void*)k_cg64_sweep<1>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    if (sweep == 0) hipLaunchKernelGGL(k_cg64_sweep<0>, dim3(rz_blocks(a.n_pairs)), dim3(RZ_NT), lds, s, a);
+    else hipLaunchKernelGGL(k_cg64_sweep<1>, dim3(rz_blocks(a.n_pairs)), dim3(RZ_NT), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg64_dot(const ExxArgs& a, hipStream_t s) {
+    if (a.n_pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cg64_dot, dim3(rz_blocks(a.n_pairs)), dim3(RZ_NT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg64_exit(const ExxArgs& a, hipStream_t s) {
+    if (a.n_pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cg64_exit, dim3((a.n_pairs + 63) / 64), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned nb = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_fill_int, dim3(nb), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

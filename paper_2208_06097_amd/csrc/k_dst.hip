@@ -7,10 +7,12 @@
 // the mode sin((i+1) theta), theta = pi m / (n+1), one axis contributes
 // -(c0 + 2 sum_k ck cos(k theta)) / h^2.  The two differ only where the
 // stencil reaches past a face: D = A - A_odd lives on the 5 points next to
-// each face.  With x0 the multipole start, the start is
+// each face.  With x0 the multipole potential of Eq. 10 (the ghost values'
+// own expansion, continued inside), the start is
 //   x = x0 + A_odd^-1 (b - A x0) = A_odd^-1 (b - D x0),
-// whose right-hand side the gather and the boundary kernel form (D x0 needs
-// x0 on those points only).  x leaves a residual many decades below that of
+// whose right-hand side the gather and the boundary kernels form (D x0 needs
+// x0 on those points only, which the ghost-value kernels evaluate from the
+// same line coefficients).  x leaves a residual many decades below that of
 // x0 because x0 already carries the multipole potential that sets the
 // boundary values; the CG's exit test then takes the true residual b - A x,
 // formed in FP64 by a stencil sweep over the whole domain.
@@ -88,6 +90,7 @@ struct DstArgs {
     const double* opt;
     const double* mu;
     const double* add;    // plane pass: added to `in` on the face points (nullable)
+    const int* skip;      // pairs to leave alone (nullable)
 };
 
 // Products on the FP64 matrix cores (v_mfma_f64_16x16x4f64), 4 waves per
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
     const sea_pair P = d.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     if (nx > DS_N || ny > DS_N || nz > DS_N) return;   // keeps the multipole start
-    if ((int)blockIdx.y >= nz) return;   // no plane here
+    if ((int)blockIdx.y >= nz || (d.skip && d.skip[pid])) return;   // no plane here, or a pair left alone
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int hb = w & 1, bp = 2 * (w >> 1);
@@ -275,7 +278,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     if (nx > DS_N || ny > DS_N || nz > DS_N) return;
     const int ncol = nx * ny;
-    if ((int)blockIdx.y * DS_TC >= ncol) return;
+    if ((int)blockIdx.y * DS_TC >= ncol || (d.skip && d.skip[pid])) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int hb = w & 1, bp = 2 * (w >> 1);
@@ -459,6 +462,24 @@ hipError_t launch_dst_pass(const ExxArgs& a, int pass, int variant, bool square,
     d.out = out;
     if (pass == 1) launch_zline(d, a.n_pairs, variant, s);
     else launch_plane(d, a.n_pairs, variant, square, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_dst_solve(const ExxArgs& a, const double* r, double* z, double* tmp, double* tmp2, double* tab,
+                            double* mu, int pv, int zv, bool square, const int* skip, hipStream_t s) {
+    if (a.n_pairs <= 0) return hipSuccess;
+    if (pv < 0 || pv >= kNumPlane || zv < 0 || zv >= kNumZline) return hipErrorInvalidValue;
+    DstArgs d = dst_args(a, tab, mu);
+    d.skip = skip;
+    d.in = r;
+    d.out = tmp;
+    launch_plane(d, a.n_pairs, pv, square, s);
+    d.in = tmp;
+    d.out = tmp2;
+    launch_zline(d, a.n_pairs, zv, s);
+    d.in = tmp2;
+    d.out = z;
+    launch_plane(d, a.n_pairs, pv, square, s);
     return hipGetLastError();
 }
 

@@ -378,9 +378,20 @@ __device__ __forceinline__ void me_line_coeffs(const double* cf, const double d[
             }
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// y <- y (3 - x y^2) / 2 (each roughly doubles the correct bits, from about
+// 23 to full double precision), a handful of FMAs instead of a correctly
+// rounded square root and division.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y;
+}
+
 // Multipole potential (Eq. 10) on the line: sum_l P_l(s) r^-(2l+1), r^2 = s^2 + rt2
 __device__ __forceinline__ double me_line_potential(const double q[SEA_LMAX + 1][SEA_LMAX + 1], double s, double rt2) {
-    const double rinv = 1.0 / sqrt(s * s + rt2), rinv2 = rinv * rinv;
+    const double rinv = rsqrt_nr(s * s + rt2), rinv2 = rinv * rinv;
     double v = 0.0, pw = rinv;
 #pragma unroll
     for (int l = 0; l <= SEA_LMAX; ++l) {
@@ -464,11 +475,21 @@ __device__ __forceinline__ double face_taps(int i, int n, F&& val) {
     return c;
 }
 
-template <int AX>
+// FACE (spectral start, pairs the sine transform takes): the column also
+// evaluates the multipole potential x0 (Eq. 10, the ghost values' own
+// expansion) at its face points, the first and last FF_W points of the line
+// (all of it when n <= 2 FF_W), and adds the taps of -D x0 along this axis
+// there into a.fcorr.  The x launch writes every point within FF_W of an x
+// face; the y launch adds at the points within FF_W of an x face and writes
+// the rest of its points, the z launch likewise after x and y, so every face
+// point of the pair is set once and then summed in x, y, z order.
+template <int AX, bool FACE>
 __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
     constexpr int ax = AX;
+    constexpr int FS = 2 * FF_W;   // frame of a line
     __shared__ double cf[GC_NM];
     __shared__ double tap[GA_BS][2 * SEA_HALO];
+    __shared__ double xs[FACE ? GA_BS : 1][FS];   // x launch: a column's -D x0 (thin lines: first its x0)
     const int pid = blockIdx.x;
     if (threadIdx.x < GC_NM) cf[threadIdx.x] = a.mpoly[(size_t)pid * GC_NM + threadIdx.x];
     __syncthreads();
@@ -487,6 +508,9 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
     int au, av;
     const bool live = column(c0 + threadIdx.x, au, av);
     const bool staged = ax == 0 && n >= 2 * SEA_HALO;   // x faces, the two faces' targets disjoint
+    const bool face = FACE && spectral_pair(P);          // uniform
+    const int nf = n < FS ? n : FS;                      // frame points of the line
+    auto frame_pt = [&](int j) { return (n <= FS || j < FF_W) ? j : n - FS + j; };
     double* b = a.b + (size_t)pid * a.stride;
     if (live) {
         int pos[3];
@@ -517,6 +541,61 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
                 if (staged) tap[threadIdx.x][plus ? 2 * SEA_HALO - 1 - d : d] = acc;   // slot j: point j or n - 12 + j
                 else b[base + (size_t)p * st[ax]] += acc;
             }
+        }
+        if (FACE && face) {
+            // -D x0 at the frame points, into t (slot j: frame point j)
+            double t[FS];
+            if (n >= FS) {
+                // the faces apart: x0 at the frame points in registers, every
+                // index known at compile time; point d from a face takes
+                // sum_{k >= d + 2} c_k x0(k - d - 2) of the same face's points
+                double xf[FS];
+#pragma unroll
+                for (int j = 0; j < FS; ++j)
+                    xf[j] = me_line_potential(q, (P.lo[ax] + (j < FF_W ? j : n - FS + j)) * C.h[ax] - P.origin[ax], rt2);
+#pragma unroll
+                for (int d = 0; d < FF_W; ++d) {
+                    double lo = 0.0, hi = 0.0;
+#pragma unroll
+                    for (int k = d + 2; k <= SEA_HALO; ++k) {
+                        lo -= kC[k] * xf[k - d - 2];
+                        hi -= kC[k] * xf[FS - 1 - (k - d - 2)];
+                    }
+                    t[d] = lo * ih2;
+                    t[FS - 1 - d] = hi * ih2;
+                }
+            } else {   // a thin line: the odd continuation over the whole line (LDS)
+                for (int j = 0; j < nf; ++j)
+                    xs[threadIdx.x][j] = me_line_potential(q, (P.lo[ax] + j) * C.h[ax] - P.origin[ax], rt2);
+#pragma unroll
+                for (int j = 0; j < FS; ++j)
+                    t[j] = j < nf ? face_taps(j, n, [&](int i) { return xs[threadIdx.x][i]; }) * ih2 : 0.0;
+            }
+            if (ax == 0) {   // out through LDS below, a lane per point
+#pragma unroll
+                for (int j = 0; j < FS; ++j) xs[threadIdx.x][j] = -t[j];
+            } else {   // neighbouring lanes take neighbouring x: straight out
+                double* fc = a.fcorr + (size_t)pid * a.stride + base;
+                // set by an earlier launch: the column lies within FF_W of an
+                // x face (or, for z, of a y face)
+                const bool set_before = near_face(pos[0], P.n[0]) || (ax == 2 && near_face(pos[1], P.n[1]));
+#pragma unroll
+                for (int j = 0; j < FS; ++j) {
+                    if (j >= nf) break;
+                    double* f = fc + (size_t)frame_pt(j) * st[ax];
+                    *f = set_before ? *f - t[j] : -t[j];
+                }
+            }
+        }
+    }
+    if (FACE && face && ax == 0) {   // the x face points out through LDS, a lane per point
+        __syncthreads();
+        double* fc = a.fcorr + (size_t)pid * a.stride;
+        for (int t = threadIdx.x; t < GA_BS * FS; t += GA_BS) {
+            const int c = t / FS, j = t % FS;
+            int cu, cv;
+            if (j >= nf || !column(c0 + c, cu, cv)) continue;
+            fc[(size_t)cu * st[1] + (size_t)cv * st[2] + frame_pt(j)] = xs[c][j];
         }
     }
     if (!staged) return;
@@ -615,36 +694,6 @@ __global__ __launch_bounds__(GM_BS) void k_me_guess(ExxArgs a) {
     }
 }
 
-// Spectral start: the multipole start x0 on the points within 5 of a face
-// (into a.x0: the face correction and the face residual read it there), and
-// the whole multipole start into x for the pairs the sine transform skips
-// (an axis beyond 64 points).  One workgroup per plane; the face points of
-// an inner plane (10 full rows and 10 points of every other row) are
-// enumerated densely.
-constexpr int FF_S = 2 * FF_W;   // face points of a line (all of it when n <= 10)
-
-template <typename F>
-__device__ __forceinline__ void for_face_points(int nx, int ny, int nz, int z, F&& f) {
-    if (z < FF_W || z >= nz - FF_W || nx <= FF_S || ny <= FF_S) {
-        for (int t = threadIdx.x; t < nx * ny; t += GM_BS) f(t % nx, t / nx);
-        return;
-    }
-    const int nfull = FF_S * nx, nside = (ny - FF_S) * FF_S;
-    for (int t = threadIdx.x; t < nfull + nside; t += GM_BS) {
-        int xx, yy;
-        if (t < nfull) {
-            const int r = t / nx;
-            xx = t % nx;
-            yy = r < FF_W ? r : ny - FF_S + r;
-        } else {
-            const int j = t - nfull, c = j % FF_S;
-            yy = FF_W + j / FF_S;
-            xx = c < FF_W ? c : nx - FF_S + c;
-        }
-        f(xx, yy);
-    }
-}
-
 // The whole multipole start on the planes of the pairs the sine transform
 // skips (an axis beyond 64 points).
 __global__ __launch_bounds__(GM_BS) void k_me_big(ExxArgs a) {
@@ -663,87 +712,6 @@ __global__ __launch_bounds__(GM_BS) void k_me_big(ExxArgs a) {
     for (int t = threadIdx.x; t < nx * ny; t += GM_BS)
         x[t] = me_start_poly(cf, Q, (P.lo[0] + t % nx) * C.h[0] - P.origin[0], (P.lo[1] + t / nx) * C.h[1] - P.origin[1],
                              dz);
-}
-
-// Row tables: for the plane's rows y, the multipole sum's parts along x,
-// P_l(dx) = sum_{e <= l} qr[y][l (l + 1) / 2 + e] dx^e, the plane's dz and
-// the row's dy folded in once (28 coefficients a row).
-constexpr int ME_QL = (SEA_LMAX + 1) * (SEA_LMAX + 2) / 2;
-
-template <int LM>
-__global__ __launch_bounds__(GM_BS, 2) void k_me_face(ExxArgs a) {
-    __shared__ double Q[SEA_NACC];
-    __shared__ double cf[GC_NM];
-    __shared__ double qr[64][ME_QL + 1];
-    // the plane's frame of x0 (the taps along x and y stay within FF_W of
-    // the face they cross)
-    __shared__ double Ex[64][2 * FF_W + 1];
-    __shared__ double Ey[2 * FF_W][65];
-    const int pid = blockIdx.x, z = blockIdx.y;
-    const sea_pair P = a.pairs[pid];
-    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    if (z >= nz || !spectral_pair(P)) return;
-    if (threadIdx.x < SEA_NACC) Q[threadIdx.x] = a.mom[(size_t)pid * SEA_NACC + threadIdx.x];
-    if (threadIdx.x < GC_NM) cf[threadIdx.x] = a.mpoly[(size_t)pid * GC_NM + threadIdx.x];
-    __syncthreads();
-    const DevCell C = a.cells[a.pair_cell[pid]];   // copied: fields stay in registers across stores
-    const double dz = (P.lo[2] + z) * C.h[2] - P.origin[2];
-    if (threadIdx.x < ny) {   // one row a thread
-        const int y = threadIdx.x;
-        const double d[3] = {0.0, (P.lo[1] + y) * C.h[1] - P.origin[1], dz};
-        double q[SEA_LMAX + 1][SEA_LMAX + 1];
-        me_line_coeffs<0>(cf, d, q);
-#pragma unroll
-        for (int l = 0; l <= SEA_LMAX; ++l)
-#pragma unroll
-            for (int e = 0; e <= l; ++e) qr[y][l * (l + 1) / 2 + e] = q[l][e];
-    }
-    __syncthreads();
-    const size_t zo = (size_t)pid * a.stride + (size_t)z * nx * ny;
-    for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
-        const double dx = (P.lo[0] + xx) * C.h[0] - P.origin[0];
-        const double dy = (P.lo[1] + yy) * C.h[1] - P.origin[1];
-        double Pl[SEA_LMAX + 1];
-#pragma unroll
-        for (int l = 0; l <= SEA_LMAX; ++l) {
-            double p = qr[yy][l * (l + 1) / 2 + l];
-#pragma unroll
-            for (int e = l - 1; e >= 0; --e) p = p * dx + qr[yy][l * (l + 1) / 2 + e];
-            Pl[l] = p;
-        }
-        const double v = me_start_from_parts(Q, Pl, dx * dx + dy * dy + dz * dz);
-        a.x0[zo + (size_t)yy * nx + xx] = v;
-        if (near_face(xx, nx)) Ex[yy][frame_k(xx, nx)] = v;
-        if (near_face(yy, ny)) Ey[frame_k(yy, ny)][xx] = v;
-    });
-    __syncthreads();
-    // -D x0 along x and y (the taps along z, on the planes next to a z face,
-    // follow in k_face_z once every plane's x0 is there)
-    const double ihx = 1.0 / (C.h[0] * C.h[0]), ihy = 1.0 / (C.h[1] * C.h[1]);
-    for_face_points(nx, ny, nz, z, [&](int xx, int yy) {
-        double t = 0.0;
-        if (near_face(xx, nx)) t += face_taps(xx, nx, [&](int q) { return Ex[yy][frame_k(q, nx)]; }) * ihx;
-        if (near_face(yy, ny)) t += face_taps(yy, ny, [&](int q) { return Ey[frame_k(q, ny)][xx]; }) * ihy;
-        a.fcorr[zo + (size_t)yy * nx + xx] = -t;
-    });
-}
-
-// -D x0 along z added on the planes next to a z face (one workgroup per such
-// plane: z = blockIdx.y for blockIdx.y < 5, nz - 10 + blockIdx.y above).
-__global__ __launch_bounds__(GM_BS) void k_face_z(ExxArgs a) {
-    const int pid = blockIdx.x;
-    const sea_pair P = a.pairs[pid];
-    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    if (!spectral_pair(P)) return;
-    const int z = blockIdx.y < FF_W ? (int)blockIdx.y : nz - 2 * FF_W + (int)blockIdx.y;
-    if (z < 0 || z >= nz || (blockIdx.y >= FF_W && z < FF_W)) return;   // thin boxes: every plane once
-    const DevCell C = a.cells[a.pair_cell[pid]];   // copied: fields stay in registers across stores
-    const double ihz = 1.0 / (C.h[2] * C.h[2]);
-    const size_t po = (size_t)pid * a.stride, npl = (size_t)nx * ny;
-    const double* x0 = a.x0 + po;
-    double* fc = a.fcorr + po;
-    for (int t = threadIdx.x; t < (int)npl; t += GM_BS)
-        fc[z * npl + t] -= face_taps(z, nz, [&](int q) { return x0[q * npl + t]; }) * ihz;
 }
 
 // ---------------------------------------------------------------------------
@@ -852,7 +820,6 @@ __device__ __forceinline__ Cub cubic_at(int k, int from, int to) {
 // to remove.
 __global__ __launch_bounds__(GM_BS) void k_nn_apply(ExxArgs a, int D, const float* __restrict__ y32) {
     const int pid = blockIdx.x;
-    const DevCell& C = a.cells[a.pair_cell[pid]];
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const long n_int = (long)nx * ny * nz;
@@ -1072,12 +1039,20 @@ hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s) {
+hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s, bool face) {
     (void)nz_max;
+    if (face && !a.fcorr) return hipErrorInvalidValue;
     const unsigned gy = (unsigned)(((long)a.nmax * a.nmax + GA_BS - 1) / GA_BS);
-    hipLaunchKernelGGL(k_ghost_axis<0>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a);
-    hipLaunchKernelGGL(k_ghost_axis<1>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a);
-    hipLaunchKernelGGL(k_ghost_axis<2>, dim3(a.n_pairs, gy), dim3(GA_BS), 0, s, a);
+    const dim3 g(a.n_pairs, gy);
+    if (face) {
+        hipLaunchKernelGGL((k_ghost_axis<0, true>), g, dim3(GA_BS), 0, s, a);
+        hipLaunchKernelGGL((k_ghost_axis<1, true>), g, dim3(GA_BS), 0, s, a);
+        hipLaunchKernelGGL((k_ghost_axis<2, true>), g, dim3(GA_BS), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_ghost_axis<0, false>), g, dim3(GA_BS), 0, s, a);
+        hipLaunchKernelGGL((k_ghost_axis<1, false>), g, dim3(GA_BS), 0, s, a);
+        hipLaunchKernelGGL((k_ghost_axis<2, false>), g, dim3(GA_BS), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -1086,14 +1061,7 @@ hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_face_corr(const ExxArgs& a, int nz_max, hipStream_t s) {
-    (void)nz_max;
-    hipLaunchKernelGGL(k_face_z, dim3(a.n_pairs, 2 * FF_W), dim3(GM_BS), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_me_face(const ExxArgs& a, int nz_max, hipStream_t s) {
-    hipLaunchKernelGGL(k_me_face<SEA_LMAX>, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
+hipError_t launch_me_big(const ExxArgs& a, int nz_max, hipStream_t s) {
     hipLaunchKernelGGL(k_me_big, dim3(a.n_pairs, nz_max), dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }

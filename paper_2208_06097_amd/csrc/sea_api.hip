@@ -196,7 +196,26 @@ static sea_status build_cellset(sea_ctx* ctx, int n_cells, const sea_cell* cells
     return SEA_OK;
 }
 
-ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
+// FP64 state on the row-tile CG: cubic grids and pair domains with n[0], n[1] <= 64
+static bool cg64_tiled(const sea_ctx* ctx, const CellSet& S) {
+    return ctx->opts.stencil_dtype == SEA_F64 && S.cubic && !S.pairs.empty() &&
+           cg_zm_fits(S.pairs.data(), (int)S.pairs.size(), nullptr) && residual_zm_lds_bytes() <= ctx->max_lds;
+}
+
+// The spectral start continued by the row-tile CG preconditioned with the
+// sine transform: cubic grids and every pair taken by the transform
+static bool cg64_pcg(const sea_ctx* ctx, const CellSet& S) {
+    if (ctx->opts.start != SEA_START_SPECTRAL || !S.cubic || S.pairs.empty() ||
+        residual_zm_lds_bytes() > ctx->max_lds)
+        return false;
+    for (const auto& p : S.pairs)
+        if (!spectral_pair(p)) return false;
+    return true;
+}
+
+// `eager`: a call that runs the sequence at once (not captured in a plan),
+// which may take the row-tile CG and its state arrays
+ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v, bool eager = true) {
     ExxLayout L{};
     const int n_pairs = (int)S.pairs.size();
     const sea_pair* pairs = S.pairs.data();
@@ -249,8 +268,16 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v) {
     L.dst_tmp = spectral ? take(np * stride * sizeof(double)) : 0;
     L.dst_tab = spectral ? take(dst_table_doubles() * sizeof(double)) : 0;
     L.dst_mu = spectral ? take(dst_mu_doubles() * sizeof(double)) : 0;
-    L.rnorm = spectral ? take(np * RZ_TILES * 2 * sizeof(double)) : 0;
-    L.x0 = spectral ? take(np * stride * sizeof(double)) : 0;
+    const bool pcg = eager && cg64_pcg(ctx, S);
+    const bool tiled64 = eager && (cg64_tiled(ctx, S) || pcg);
+    L.rnorm = (spectral || tiled64) ? take(np * RZ_TILES * 2 * sizeof(double)) : 0;
+    L.cg_r = tiled64 ? take(np * stride * sizeof(double)) : 0;
+    L.cg_p = tiled64 ? take(2 * np * stride * sizeof(double)) : 0;
+    L.cg_part = tiled64 ? take(np * RZ_TILES * 8 * sizeof(double)) : 0;
+    L.cg_rho = tiled64 ? take(np * 2 * sizeof(double)) : 0;
+    L.cg_done = tiled64 ? take(np * sizeof(int)) : 0;
+    L.cg_active = tiled64 ? take(((size_t)ctx->opts.max_iter + 2) * sizeof(int)) : 0;
+    L.cg_z = pcg ? take(np * stride * sizeof(double)) : 0;
     L.epart = take(np * (size_t)L.ep_stride * sizeof(double));
     L.slots = take((size_t)L.n_slots * 4 * L.slot_stride * sizeof(double));
     L.stats = take(np * sizeof(DevStat));
@@ -357,7 +384,7 @@ sea_status sea_create(const sea_opts* opts, sea_ctx** out) {
 sea_status sea_destroy(sea_ctx* ctx) {
     if (ctx && ctx->ev_ready)
         for (int k = 0; k < SEA_STAGE_COUNT; ++k)
-            for (int e = 0; e < 2; ++e) hipEventDestroy(ctx->ev[k][e]);
+            for (int e = 0; e < 2; ++e) (void)hipEventDestroy(ctx->ev[k][e]);
 
     delete ctx;
     return SEA_OK;
@@ -419,6 +446,20 @@ sea_status sea_exx_workspace_bytes(sea_ctx* ctx, const sea_grid* grid, int n_occ
     sea_status st = build_cellset(ctx, 1, &c, true, S);
     if (st != SEA_OK) return st;
     *bytes = exx_layout(ctx, S, true).total;
+    return SEA_OK;
+}
+
+sea_status sea_exx_plan_workspace_bytes(sea_ctx* ctx, int n_cells, const sea_cell* cells, size_t* bytes) {
+    if (!ctx || !bytes) return SEA_E_ARG;
+    std::vector<sea_cell> cs(cells, cells + (n_cells > 0 && cells ? n_cells : 0));
+    for (auto& c : cs) {
+        if (!c.phi_dev) c.phi_dev = (const void*)1;  // sizing does not read buffers
+        if (!c.W_dev) c.W_dev = (double*)1;
+    }
+    CellSet S;
+    sea_status st = build_cellset(ctx, n_cells, cs.data(), true, S);
+    if (st != SEA_OK) return st;
+    *bytes = exx_layout(ctx, S, true, false).total;
     return SEA_OK;
 }
 
@@ -495,14 +536,81 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.queue_ctr = (int*)(base + Ly.counter);
     a.x_nonzero = ctx->opts.start != SEA_START_ZERO;
     a.bres = Ly.bres ? (double*)(base + Ly.bres) : nullptr;
-    // spectral start: x0 on the face points and -D x0 there (in the
-    // transform's scratch array)
-    a.x0 = Ly.x0 ? (double*)(base + Ly.x0) : nullptr;
+    // spectral start: -D x0 on the face points (in the transform's scratch
+    // array)
     a.fcorr = Ly.dst_tmp ? (double*)(base + Ly.dst_tmp) : nullptr;
     a.nmax = Ly.nmax;
     a.epart = nullptr;   // set by the sequences that take the energies from the scatter
     a.ep_stride = Ly.ep_stride;
+    a.cg_r = Ly.cg_r ? (double*)(base + Ly.cg_r) : nullptr;
+    a.cg_p = Ly.cg_p ? (double*)(base + Ly.cg_p) : nullptr;
+    a.cg_part = Ly.cg_part ? (double*)(base + Ly.cg_part) : nullptr;
+    a.cg_rho = Ly.cg_rho ? (double*)(base + Ly.cg_rho) : nullptr;
+    a.cg_done = Ly.cg_done ? (int*)(base + Ly.cg_done) : nullptr;
+    a.cg_active = Ly.cg_active ? (int*)(base + Ly.cg_active) : nullptr;
+    a.cg_z = Ly.cg_z ? (double*)(base + Ly.cg_z) : nullptr;
+    a.cg_pre = 0;
+    a.cg_it = 0;
     return a;
+}
+
+// The FP64 row-tile CG: init, then two sweeps per iteration until every pair
+// has stopped (checked from the per-iteration counters every few
+// iterations, which synchronizes), then the true residual's norms into
+// rel_res.  Preconditioned (`pre`, after a spectral start whose norms are in
+// rnorm): the init stops the pairs whose start already meets the target,
+// and z = A_odd^-1 r (three transform passes, tmp and tmp2 scratch) and
+// <r, z> follow each sweep B.
+struct Cg64Pre {
+    double *tmp, *tmp2, *tab, *mu;
+    int pv, zv;
+    bool square;
+};
+static sea_status cg64_run(sea_ctx* ctx, const ExxArgs& a0, double* rnorm, hipStream_t s, const Cg64Pre* pre) {
+    ExxArgs a = a0;
+    a.cg_pre = pre ? 1 : 0;
+    a.rnorm = pre ? rnorm : nullptr;   // start norms: which pairs the init stops
+    SEA_HIP_CHECK(ctx, launch_fill_int(a.cg_active, (size_t)a.max_iter + 2, s));
+    SEA_HIP_CHECK(ctx, launch_cg64_init(a, s));
+    if (pre) {   // every start already meets the target: nothing iterates
+        int active = 0;
+        SEA_HIP_CHECK(ctx, hipMemcpyAsync(&active, a.cg_active + a.max_iter + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+        if (active == 0) return SEA_OK;
+    }
+    auto precondition = [&](int k) -> sea_status {
+        SEA_HIP_CHECK(ctx, launch_dst_solve(a, a.cg_r, a.cg_z, pre->tmp, pre->tmp2, pre->tab, pre->mu, pre->pv,
+                                            pre->zv, pre->square, a.cg_done, s));
+        ExxArgs ad = a;
+        ad.cg_it = k;
+        SEA_HIP_CHECK(ctx, launch_cg64_dot(ad, s));
+        return SEA_OK;
+    };
+    if (pre) {
+        const sea_status st = precondition(-1);
+        if (st != SEA_OK) return st;
+    }
+    const int every = pre ? 4 : 16;
+    for (int k = 0;; ++k) {
+        a.cg_it = k;
+        SEA_HIP_CHECK(ctx, launch_cg64_sweep(a, 0, s));
+        if (k >= a.max_iter) break;
+        SEA_HIP_CHECK(ctx, launch_cg64_sweep(a, 1, s));
+        if (pre) {
+            const sea_status st = precondition(k);
+            if (st != SEA_OK) return st;
+        }
+        if (k % every == every - 1) {
+            int active = 0;
+            SEA_HIP_CHECK(ctx, hipMemcpyAsync(&active, a.cg_active + k, sizeof(int), hipMemcpyDeviceToHost, s));
+            SEA_HIP_CHECK(ctx, hipStreamSynchronize(s));
+            if (active == 0) break;
+        }
+    }
+    a.rnorm = rnorm;
+    SEA_HIP_CHECK(ctx, launch_residual_zm(a, s, false));
+    SEA_HIP_CHECK(ctx, launch_cg64_exit(a, s));
+    return SEA_OK;
 }
 
 // The whole kernel sequence of one call, on stream s (capturable).
@@ -524,6 +632,15 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
     for (int k = SEA_STAGE_DST; k <= SEA_STAGE_FOLD; ++k) ctx->ev_used[k] = false;
     const bool zm = ctx->opts.stencil_dtype == SEA_F32 && S.cubic && cg_zm_fits(S.pairs.data(), n_pairs, nullptr) &&
                     cg_zm_lds_bytes(1) <= ctx->max_lds;
+    // FP64 state: the row-tile CG, except under graph capture (its host loop
+    // checks progress), where the per-pair kernel runs
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
+    const bool nocap = cap == hipStreamCaptureStatusNone;
+    const bool tiled64 = cg64_tiled(ctx, S) && a.cg_r && nocap;
+    // the spectral start's continuation: the sine-transform-preconditioned CG
+    const bool pcg = cg64_pcg(ctx, S) && a.cg_z && nocap;
+    const bool finish = zm || tiled64 || pcg;   // pair energies and flags by k_cg_finish
     if (!zm && ctx->opts.stencil_dtype != SEA_F64)
         return fail(ctx, SEA_E_ARG, "SEA_F32 state needs cubic grids and pair domains with n[0], n[1] <= 64");
     int nz_max = 1;
@@ -535,15 +652,15 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         timer_off(SEA_STAGE_GATHER);
         const bool spectral = ctx->opts.start == SEA_START_SPECTRAL;
         timer_on(SEA_STAGE_BOUNDARY);
-        // spectral start: x0 on the face points and -D x0 there first
+        // spectral start: the full multipole start for the pairs the sine
+        // transform skips; the fold forms -D x0 on the others' face points
         if (spectral) {
             timer_on(SEA_STAGE_FACE);
-            SEA_HIP_CHECK(ctx, launch_me_face(a, nz_max, s));
-            SEA_HIP_CHECK(ctx, launch_face_corr(a, nz_max, s));
+            SEA_HIP_CHECK(ctx, launch_me_big(a, nz_max, s));
             timer_off(SEA_STAGE_FACE);
         }
         timer_on(SEA_STAGE_FOLD);
-        SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s));
+        SEA_HIP_CHECK(ctx, launch_boundary_fold(a, nz_max, s, spectral));
         timer_off(SEA_STAGE_FOLD);
         timer_off(SEA_STAGE_BOUNDARY);
         if (a.x_nonzero) {
@@ -593,21 +710,36 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                                                                  if (pass == 2) timer_off(SEA_STAGE_DST);
                                                              }
                                                          }));
-                if (zm) {
+                if (zm || pcg) {
                     ExxArgs ar = a;
                     ar.rnorm = (double*)(base + Ly.rnorm);
+                    ar.cg_done = nullptr;   // (stale flags of an earlier call)
                     const bool rzm = residual_zm_lds_bytes() <= ctx->max_lds;
                     timer_on(SEA_STAGE_RESIDUAL);
-                    SEA_HIP_CHECK(ctx, rzm ? launch_residual_zm(ar, s) : launch_start_residual(ar, s));
+                    // (the preconditioned continuation forms its residual itself)
+                    SEA_HIP_CHECK(ctx, rzm ? launch_residual_zm(ar, s, !pcg) : launch_start_residual(ar, s));
                     timer_off(SEA_STAGE_RESIDUAL);
                 }
-            } else if (!zm) {
+            } else if (!zm && !tiled64 && !pcg) {
                 SEA_HIP_CHECK(ctx, launch_start_residual(a, s));
             }
             timer_off(SEA_STAGE_GUESS);
         }
         timer_on(SEA_STAGE_CG);
-        if (zm) {
+        if (pcg) {
+            int pv = 0, zv = 0;
+            dst_variants(ctx, pv, zv);
+            const Cg64Pre pre{(double*)(base + Ly.dst_tmp), a.bres, (double*)(base + Ly.dst_tab),
+                              (double*)(base + Ly.dst_mu), pv, zv, S.square};
+            sea_status st = cg64_run(ctx, a, (double*)(base + Ly.rnorm), s, &pre);
+            if (st != SEA_OK) return st;
+            timer_off(SEA_STAGE_CG);
+            if (!f.action) {
+                timer_on(SEA_STAGE_FINISH);
+                SEA_HIP_CHECK(ctx, launch_cg_finish(a, s));
+                timer_off(SEA_STAGE_FINISH);
+            }
+        } else if (zm) {
             const int var = ctx->opts.cg_variant >= 0 ? ctx->opts.cg_variant : (ctx->cg_tuned >= 0 ? ctx->cg_tuned : 0);
             ExxArgs az = a;
             // spectral start: x is the FP64 start and bres = b - A x (rnorm: its
@@ -615,6 +747,15 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
             az.start_res = ctx->opts.start == SEA_START_SPECTRAL ? 1 : 0;
             az.rnorm = (az.start_res && residual_zm_lds_bytes() <= ctx->max_lds) ? (double*)(base + Ly.rnorm) : nullptr;
             SEA_HIP_CHECK(ctx, launch_cg_zm(az, var, s));
+            timer_off(SEA_STAGE_CG);
+            if (!f.action) {
+                timer_on(SEA_STAGE_FINISH);
+                SEA_HIP_CHECK(ctx, launch_cg_finish(a, s));
+                timer_off(SEA_STAGE_FINISH);
+            }
+        } else if (tiled64) {
+            sea_status st = cg64_run(ctx, a, (double*)(base + Ly.rnorm), s, nullptr);
+            if (st != SEA_OK) return st;
             timer_off(SEA_STAGE_CG);
             if (!f.action) {
                 timer_on(SEA_STAGE_FINISH);
@@ -633,14 +774,14 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         bool lists_fit = true;   // every orbital's pair list fits the scatter's energy arrays
         for (size_t k = 0; k + 1 < S.csr_off.size(); ++k)
             lists_fit = lists_fit && S.csr_off[k + 1] - S.csr_off[k] <= SC_EP_MAXE;
-        if (zm && n_pairs > 0 && lists_fit) ae.epart = (double*)(base + Ly.epart);
+        if (finish && n_pairs > 0 && lists_fit) ae.epart = (double*)(base + Ly.epart);
         timer_on(SEA_STAGE_SCATTER);
         if (ae.epart) SEA_HIP_CHECK(ctx, launch_epart_clear(ae, s));
         for (size_t c = 0; c < S.cells.size(); ++c)
             SEA_HIP_CHECK(ctx, launch_scatter(ae, S.dev[c], (const int*)(base + Ly.csr_off),
                                               (const int2*)(base + Ly.csr_ent), s));
         timer_off(SEA_STAGE_SCATTER);
-        if (zm && n_pairs > 0) {   // without ae.epart the finish sums rho x itself
+        if (finish && n_pairs > 0) {   // without ae.epart the finish sums rho x itself
             timer_on(SEA_STAGE_FINISH);
             SEA_HIP_CHECK(ctx, launch_cg_finish(ae, s));
             timer_off(SEA_STAGE_FINISH);
@@ -1613,7 +1754,7 @@ sea_status sea_exx_plan_create(sea_ctx* ctx, int n_cells, const sea_cell* cells,
     P->ctx = ctx;
     sea_status st = build_cellset(ctx, n_cells, cells, true, P->S);
     if (st != SEA_OK) { delete P; return st; }
-    P->Ly = exx_layout(ctx, P->S, true);
+    P->Ly = exx_layout(ctx, P->S, true, false);
     if (ws_bytes < P->Ly.total) {
         delete P;
         return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, P->Ly.total);

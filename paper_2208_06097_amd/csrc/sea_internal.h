@@ -69,7 +69,8 @@ struct StageTimer {
 // Byte layout of the exx workspace (offsets from the workspace base).
 struct ExxLayout {
     size_t pairs, pair_cell, order, dbox, cells, partial, mom, b, v, bres, slots, stats, csr_off, csr_ent, scal, counter;
-    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, x0, mpoly, epart, total;
+    size_t nnx, nny, nnact, dst_tmp, dst_tab, dst_mu, rnorm, racah_tab, mpoly, epart, cg_r, cg_p, cg_z, cg_part,
+        cg_rho, cg_done, cg_active, total;
     int nmax;
     int ep_stride;        // pair-energy partial slots per pair (scatter)
     int n_chunks;
@@ -111,7 +112,6 @@ struct ExxArgs {
     double* mpoly;        // n_pairs x 84: the multipole sum's monomial coefficients per pair
     double* mom;          // n_pairs x SEA_NACC (Racah moments, dV applied)
     double* b;            // n_pairs x stride
-    double* x0;           // spectral start: the multipole start on the points within 5 of a face (nullable)
     double* fcorr;        // spectral start: -D x0 on the face points (the transform's scratch array)
     double* v;            // n_pairs x stride
     size_t stride;
@@ -133,6 +133,16 @@ struct ExxArgs {
     int nmax;             // largest domain extent over pairs and axes
     double* epart;        // n_pairs x ep_stride pair-energy partials of the scatter (nullable: e_ij by k_cg_finish)
     int ep_stride;        // partial slots per pair
+    // FP64 row-tile CG (one launch per sweep over all pairs)
+    double* cg_r;         // n_pairs x stride: residual
+    double* cg_p;         // 2 x n_pairs x stride: search direction, by iteration parity
+    double* cg_part;      // n_pairs x RZ_TILES x 8 partial sums per row tile (k_cg.hip)
+    double* cg_z;         // n_pairs x stride: preconditioned residual (nullable)
+    int cg_pre;           // the CG is preconditioned by the sine transform (z = A_odd^-1 r)
+    double* cg_rho;       // n_pairs x 2: |r|^2 of the last two iterations
+    int* cg_done;         // n_pairs: the pair has stopped (2: by its start); null outside the row-tile CG
+    int* cg_active;       // max_iter + 2 counters: pairs still iterating at each iteration; the last, after the init
+    int cg_it;            // the iteration a sweep launch performs
 };
 
 // Scatter tiles (k_scatter.hip): 64 x 4 x 8 grid points of one orbital.
@@ -222,25 +232,41 @@ constexpr int GC_TAB = SEA_NMOM * 84;
 int exx_n_chunks(long n_int_max);
 hipError_t launch_gather_moments(const ExxArgs& a, hipStream_t s);
 hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s);
-hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s);
+// The ghost values (Eq. 10) folded into b along x, then y, then z; with
+// `face` (spectral start) also -D x0 into a.fcorr on the face points of the
+// pairs the sine transform takes, x0 the multipole potential there.
+hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s, bool face = false);
 hipError_t launch_cg(const ExxArgs& a, hipStream_t s);
 hipError_t launch_me_guess(const ExxArgs& a, hipStream_t s);
-// Spectral start (pairs with every axis <= 64): x0 on the points within 5 of
-// a face into a.x0; the full multipole start into x for the other pairs.
-hipError_t launch_me_face(const ExxArgs& a, int nz_max, hipStream_t s);
-// -D x0 into a.fcorr on the face points
-hipError_t launch_face_corr(const ExxArgs& a, int nz_max, hipStream_t s);
+// Spectral start: the whole multipole start into x for the pairs the sine
+// transform skips (an axis beyond 64 points)
+hipError_t launch_me_big(const ExxArgs& a, int nz_max, hipStream_t s);
 constexpr double kPi = 3.14159265358979323846;
 hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, int mode, hipStream_t s);
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s);
 hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
 // b - A x in FP64 by z-march (cubic grids, nx, ny <= 64), in two launches:
 // the norms |b|^2 and |b - A x|^2 per pair into a.rnorm (nothing else
-// written), then b - A x into bres for the pairs whose start does not meet
-// the FP32 z-march CG's exit test (the others are left alone).
+// written), then (with `write`) b - A x into bres for the pairs whose start
+// does not meet the FP32 z-march CG's exit test (the others are left alone).
 constexpr int RZ_TILES = 4;   // row tiles of 16 per pair in the residual z-march
 size_t residual_zm_lds_bytes();
-hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s);
+hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s, bool write = true);
+// FP64-state CG by row tiles (cubic grids, nx, ny <= 64): r = b - A x0 (or
+// b with x = 0), p = r and the norms' partials; then per iteration a.cg_it
+// sweep A (stop test; p = r + beta p; <p, A p>) and sweep B (x += alpha p,
+// r -= alpha A p, |r|^2); after the last iteration the true residual's
+// norms (launch_residual_zm) go into each pair's rel_res.
+hipError_t launch_cg64_init(const ExxArgs& a, hipStream_t s);
+hipError_t launch_cg64_sweep(const ExxArgs& a, int sweep, hipStream_t s);
+hipError_t launch_cg64_exit(const ExxArgs& a, hipStream_t s);
+// <r, z> partials of the preconditioned form (after z = A_odd^-1 r)
+hipError_t launch_cg64_dot(const ExxArgs& a, hipStream_t s);
+// z = A_odd^-1 r for the pairs not marked in `skip` (the three transform
+// passes with the context's variants; tmp, tmp2 scratch of the pair arrays' size)
+hipError_t launch_dst_solve(const ExxArgs& a, const double* r, double* z, double* tmp, double* tmp2, double* tab,
+                            double* mu, int pv, int zv, bool square, const int* skip, hipStream_t s);
+hipError_t launch_fill_int(int* p, size_t n, hipStream_t s);
 // Spectral start (k_dst.hip): x = A_odd^-1 (b + a.fcorr on the face points)
 // for the pairs with every axis <= 64 (a.fcorr is tmp, scratch of the pair
 // arrays' size; r scratch of the same size).

@@ -35,7 +35,7 @@ EXPORTS = [
     "sea_nn_infer_workspace_bytes", "sea_nn_infer", "sea_eps_workspace_bytes", "sea_build_pairs_eps",
     "sea_successive_idempotency", "sea_scdm_workspace_bytes", "sea_scdm", "sea_rotate",
     "sea_ace_apply_noalloc", "sea_spectral_variant_count", "sea_spectral_variant_name",
-    "sea_set_spectral_variants", "sea_spectral_autotune",
+    "sea_set_spectral_variants", "sea_spectral_autotune", "sea_exx_plan_workspace_bytes",
 ]
 
 # size of the library's static scratch array per GPU (SEA_NOALLOC_SCRATCH_BYTES
@@ -146,6 +146,7 @@ def load() -> C.CDLL:
     lib.sea_nn_attach.argtypes = [vp, vp]
     lib.sea_exx_nn_samples.argtypes = [vp, P(SeaGrid), i, vp, i, i, vp, vp, sz, i, vp, vp, vp, vp]
     lib.sea_exx_batched_workspace_bytes.argtypes = [vp, i, vp, P(sz)]
+    lib.sea_exx_plan_workspace_bytes.argtypes = [vp, i, vp, P(sz)]
     lib.sea_exx_action_batched.argtypes = [vp, i, vp, vp, sz, vp, vp]
     lib.sea_exx_plan_create.argtypes = [vp, i, vp, vp, sz, P(vp)]
     lib.sea_exx_plan_launch.argtypes = [vp, vp]
@@ -353,6 +354,12 @@ class Context:
         arr, _, keep = self._cells(cells, need_W=False)
         b = C.c_size_t(0)
         self._check(self.lib.sea_exx_batched_workspace_bytes(self.h, len(cells), arr, C.byref(b)))
+        return b.value
+
+    def exx_plan_workspace_bytes(self, cells) -> int:
+        arr, _, keep = self._cells(cells, need_W=False)
+        b = C.c_size_t(0)
+        self._check(self.lib.sea_exx_plan_workspace_bytes(self.h, len(cells), arr, C.byref(b)))
         return b.value
 
     def exx_action_batched(self, cells, ws=None, want_host=True):
@@ -725,7 +732,7 @@ class Plan:
         arr, self.W, self._keep = ctx._cells(cells)
         self._cells = arr
         self._n_pairs = sum(len(c[3]) for c in cells)
-        self.ws = ws if ws is not None else ctx.workspace(ctx.exx_batched_workspace_bytes(cells))
+        self.ws = ws if ws is not None else ctx.workspace(ctx.exx_plan_workspace_bytes(cells))
         h = C.c_void_p()
         ctx._check(ctx.lib.sea_exx_plan_create(ctx.h, len(cells), arr, self.ws.data_ptr(), self.ws.numel(),
                                                C.byref(h)))

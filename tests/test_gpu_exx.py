@@ -450,3 +450,32 @@ def test_cg_xc_beta_min_rejects_bad_values():
             c.set_opts(cg_xc_beta_min=bad)
         assert ei.value.status == sea.SEA_E_ARG
         c.close()
+
+
+def test_fp64_row_tile_cg_against_the_per_pair_kernel(mini):
+    """FP64 state: an eager call runs the row-tile CG (one launch per sweep
+    over all pairs), a captured plan the per-pair kernel.  Both solve every
+    pair to the same true residual: E and W against the oracle, the reported
+    residual is the true one (<= rel_tol), and the iteration counts of the
+    two CG schedules agree to a few iterations."""
+    cell, pl, ref, pairs = mini
+    print("case fp64 row-tile CG vs per-pair kernel", flush=True)
+    c = sea.Context(rel_tol=1e-8, stencil_dtype=sea.SEA_F64)
+    phi = _dev(cell.phi)
+    W1, E1, s1, st = c.exx_action(phi, cell.N, cell.L, pairs)
+    W1 = W1.clone()
+    assert st == sea.SEA_OK and np.all(s1["converged"] == 1) and np.all(s1["rel_res"] <= 1e-8)
+    plan = c.exx_plan([(phi, cell.N, cell.L, pairs)])
+    plan.launch()
+    E2, s2, st = plan.results()
+    assert st == sea.SEA_OK and np.all(s2["converged"] == 1) and np.all(s2["rel_res"] <= 1e-8)
+    W2 = plan.W[0]
+    for E, W in ((E1, W1), (E2[0], W2)):
+        assert abs(E - ref.E) < 1e-6
+        assert np.max(np.abs(W.cpu().numpy() - ref.W)) < 1e-5
+    d = np.abs(s1["iters"].astype(int) - s2["iters"].astype(int))
+    print(f"iterations row-tile {s1['iters'].mean():.1f} per-pair {s2['iters'].mean():.1f}, max diff {d.max()}",
+          flush=True)
+    assert d.max() <= 3
+    plan.close()
+    c.close()
