@@ -208,12 +208,8 @@ __global__ __launch_bounds__(NT) void k_nn_mfma(const double* __restrict__ A, lo
     using E = typename Kd::E;
     __shared__ __attribute__((aligned(16))) E As[BM * Kd::PITCH];
     __shared__ __attribute__((aligned(16))) E Bs[BN * Kd::PITCH];
-    // one grid dimension, row blocks fastest: the workgroups that read one
-    // column tile of B run together, so B (the grid-point operand) comes
-    // from HBM once
-    const int nrb = (m + BM - 1) / BM;
-    const int i0 = (int)(blockIdx.x % nrb) * BM;
-    const long j0 = (long)(blockIdx.x / nrb) * BN;
+    const long j0 = (long)blockIdx.x * BN;
+    const int i0 = blockIdx.y * BM;
     typename Kd::Acc acc[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
@@ -292,9 +288,7 @@ hipError_t ace_mm_nt(const TA* A, const TB* B, int m, int n, long K, double alph
 template <int KIND, typename TB, typename TC>
 hipError_t ace_mm_nn(const double* A, long sai, long sak, const TB* B, int m, int K, long ncol, double alpha, TC* C,
                      hipStream_t s) {
-    const long nb = (long)((m + BM - 1) / BM) * ((ncol + BN - 1) / BN);
-    if (nb > 0x7fffffffL) return hipErrorInvalidValue;
-    dim3 grid((unsigned)nb);
+    dim3 grid((unsigned)((ncol + BN - 1) / BN), (m + BM - 1) / BM);
     hipLaunchKernelGGL((k_nn_mfma<KIND, TB, TC>), grid, dim3(NT), 0, s, A, sai, sak, B, m, K, ncol, alpha, C);
     return hipGetLastError();
 }
