@@ -618,7 +618,7 @@ constexpr int RZ_ROWS = 16;   // rows owned per workgroup: one per wavefront
 constexpr int RZ_WR = RZ_ROWS + 2 * SEA_HALO;   // rows of the window
 constexpr int RZ_XCD = 8;
 static_assert(RZ_TILES * RZ_ROWS >= 64, "row tiles cover 64 rows");
-static_assert(RZ_NT / 64 == RZ_ROWS && 2 * SEA_HALO <= RZ_ROWS, "a wavefront per owned row; halo rows fit");
+static_assert(RZ_NT / 64 == RZ_ROWS, "a wavefront per owned row");
 
 __device__ __forceinline__ void rz_block(int& pid, int& tile) {
     const int k = blockIdx.x, m = k / RZ_XCD;
@@ -632,42 +632,71 @@ __device__ __forceinline__ void rz_block(int& pid, int& tile) {
 // the neighbouring workgroups own).  Only the owned rows keep the 13-plane
 // register queue and form the stencil; wavefronts ty < 2 SEA_HALO also load
 // one halo row's current plane into LDS for the y taps (window row ty below
-// the tile, ty + RZ_ROWS above it).  fetch(yw, z) issues the loads of window
-// row yw at plane z, two steps before they are used (two planes of loads in
-// flight per row, so that a step's work covers the memory latency),
-// make(yw, z, F) turns them into f, pre(z) prefetches the owned point's data
+// the tile, ty + RZ_ROWS above it; with fewer owned rows than halo rows a
+// wavefront takes two).  fetch(yw, z) issues the loads of window
+// row yw at plane z, DEPTH steps before they are used (measured: the
+// residual sweep, with one plane of output loads, runs faster at DEPTH 2;
+// the CG sweeps, with two, at DEPTH 1), make(yw, z, F) turns them into f, pre(z) prefetches the owned point's data
 // of output plane z, out(z, A f, f, PV) consumes it.  Two LDS planes of
 // RZ_WR x 64 doubles.
-template <typename F, typename PV, typename FetchF, typename MakeF, typename PreF, typename OutF>
+template <int DEPTH, typename F, typename PV, typename FetchF, typename MakeF, typename PreF, typename OutF>
 __device__ __forceinline__ void rtmarch(int nz, double* lds, const SW<double>& w, FetchF&& fetch, MakeF&& make,
                                         PreF&& pre, OutF&& out) {
+    static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
+    constexpr int HR = 2 * SEA_HALO;                           // halo rows of the window
+    constexpr int HPW = (HR + RZ_ROWS - 1) / RZ_ROWS;           // halo rows per wavefront (at most)
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int yo = ty + SEA_HALO;                          // owned row in the window
-    const bool halo = ty < 2 * SEA_HALO;
-    const int yh = ty < SEA_HALO ? ty : ty + RZ_ROWS;     // halo row in the window
+    const int yo = ty + SEA_HALO;                               // owned row in the window
+    // halo row h = ty + RZ_ROWS e (h < HR) sits at window row h below the
+    // tile and h + RZ_ROWS above it
+    auto hrow = [&](int e) { const int h = ty + RZ_ROWS * e; return h < SEA_HALO ? h : h + RZ_ROWS; };
+    auto has_h = [&](int e) { return ty + RZ_ROWS * e < HR; };
     double q[13];
 #pragma unroll
     for (int k = 0; k < 6; ++k) q[k] = 0.0;
 #pragma unroll
     for (int s = 0; s < 7; ++s) q[6 + s] = make(yo, s, fetch(yo, min(s, nz)));
-    F on = fetch(yo, min(7, nz));   // the owned row's plane z + 7, fetched at step z - 1
-    F hn{}, hn2{};                   // the halo row's planes z and z + 1
-    if (halo) {
-        hn = fetch(yh, 0);
-        hn2 = fetch(yh, min(1, nz));
+    // DEPTH 2: the owned row's plane z + 7 is fetched at step z - 1 and the
+    // halo rows' plane z at step z - 2; DEPTH 1: one step later each
+    F on{};
+    if constexpr (DEPTH == 2) on = fetch(yo, min(7, nz));
+    F hn[HPW], hn2[HPW];
+#pragma unroll
+    for (int e = 0; e < HPW; ++e) {
+        hn[e] = F{};
+        hn2[e] = F{};
+        if (has_h(e)) {
+            hn[e] = fetch(hrow(e), 0);
+            if constexpr (DEPTH == 2) hn2[e] = fetch(hrow(e), min(1, nz));
+        }
     }
     for (int z = 0; z < nz; ++z) {
-        const F nxt = on;
-        on = fetch(yo, min(z + 8, nz));
-        const F hc = hn;
-        if (halo) {
-            hn = hn2;
-            hn2 = fetch(yh, min(z + 2, nz));
+        F nxt;
+        if constexpr (DEPTH == 2) {
+            nxt = on;
+            on = fetch(yo, min(z + 8, nz));
+        } else {
+            nxt = fetch(yo, min(z + 7, nz));
+        }
+        F hc[HPW];
+#pragma unroll
+        for (int e = 0; e < HPW; ++e) {
+            hc[e] = hn[e];
+            if (has_h(e)) {
+                if constexpr (DEPTH == 2) {
+                    hn[e] = hn2[e];
+                    hn2[e] = fetch(hrow(e), min(z + 2, nz));
+                } else {
+                    hn[e] = fetch(hrow(e), min(z + 1, nz));
+                }
+            }
         }
         const PV pv = pre(z);
         double* pl = lds + (z & 1) * (LW * RZ_WR);
         pl[yo * LW + tx] = q[6];
-        if (halo) pl[yh * LW + tx] = make(yh, z, hc);
+#pragma unroll
+        for (int e = 0; e < HPW; ++e)
+            if (has_h(e)) pl[hrow(e) * LW + tx] = make(hrow(e), z, hc[e]);
         lds_sync();
         __builtin_amdgcn_sched_barrier(0);
         const double* row = pl + yo * LW + tx;
@@ -720,7 +749,7 @@ __global__ __launch_bounds__(RZ_NT) void k_residual_zm(ExxArgs a) {
     const int tx = threadIdx.x & 63, yown = y0 + (threadIdx.x >> 6);
     const bool own = yown < ny && tx < nx;
     double bb = 0.0, rr = 0.0;
-    rtmarch<double, double>(
+    rtmarch<2, double, double>(
         nz, lds, w,
         [&](int yw, int z) -> double {   // window row yw is grid row y0 - SEA_HALO + yw
             const int y = y0 - SEA_HALO + yw;
@@ -821,7 +850,7 @@ __global__ __launch_bounds__(RZ_NT) void k_cg64_init(ExxArgs a) {
     const bool own = yown < ny && tx < nx;
     const bool x0 = a.x_nonzero;
     double bb = 0.0, rr = 0.0;
-    rtmarch<double, double>(
+    rtmarch<1, double, double>(
         nz, lds, w,
         [&](int yw, int z) -> double {
             const int y = y0 - SEA_HALO + yw;
@@ -911,7 +940,7 @@ __global__ __launch_bounds__(RZ_NT) void k_cg64_sweep(ExxArgs a) {
         // the owned rows
         const double beta = k > 0 ? rho / a.cg_rho[(size_t)pid * 2 + ((k - 1) & 1)] : 0.0;
         const double* __restrict__ src = (a.cg_pre ? a.cg_z : a.cg_r) + (size_t)pid * a.stride;
-        rtmarch<F2<double>, Empty>(
+        rtmarch<1, F2<double>, Empty>(
             nz, lds, w,
             [&](int yw, int z) -> F2<double> {
                 if (!inwin(yw, z)) return F2<double>{0.0, 0.0};
@@ -931,7 +960,7 @@ __global__ __launch_bounds__(RZ_NT) void k_cg64_sweep(ExxArgs a) {
     } else {
         // x += alpha p, r -= alpha A p, |r|^2 over the owned rows
         const double alpha = rho / cg64_sum(a, pid, 2);
-        rtmarch<double, F2<double>>(
+        rtmarch<1, double, F2<double>>(
             nz, lds, w,
             [&](int yw, int z) -> double { return inwin(yw, z) ? p[widx(yw, z)] : 0.0; },
             [&](int, int, double v) -> double { return v; },

@@ -432,6 +432,7 @@ __device__ __forceinline__ double me_poly_potential(const double* cf, double dx,
 // updates are coalesced; the x faces' targets are 6 contiguous points of a
 // row, so their updates go through LDS and out with a lane per target point.
 constexpr int GA_BS = 256;
+constexpr int GA_COLS = GA_BS / 2;   // lines per workgroup (two threads each)
 
 // sum over the stencil taps of a column point i that fall past a face, of
 // c_k times the odd continuation (period 2 (n + 1), zeros at -1 and n) of
@@ -475,7 +476,11 @@ __device__ __forceinline__ double face_taps(int i, int n, F&& val) {
     return c;
 }
 
-// FACE (spectral start, pairs the sine transform takes): the column also
+// Two threads per line, one per face (side 0: the low face, 1: the high
+// face; the first and second half of the workgroup take the same GA_COLS
+// lines), each forming its face's line coefficients; a line shorter than
+// 2 SEA_HALO points, whose faces' taps overlap, is done by side 0 alone.
+// FACE (spectral start, pairs the sine transform takes): the line also
 // evaluates the multipole potential x0 (Eq. 10, the ghost values' own
 // expansion) at its face points, the first and last FF_W points of the line
 // (all of it when n <= 2 FF_W), and adds the taps of -D x0 along this axis
@@ -488,43 +493,46 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
     constexpr int ax = AX;
     constexpr int FS = 2 * FF_W;   // frame of a line
     __shared__ double cf[GC_NM];
-    __shared__ double tap[GA_BS][2 * SEA_HALO];
-    __shared__ double xs[FACE ? GA_BS : 1][FS];   // x launch: a column's -D x0 (thin lines: first its x0)
+    __shared__ double tap[GA_COLS][2 * SEA_HALO];
+    __shared__ double xs[FACE ? GA_COLS : 1][2 * FS];   // x launch: a line's -D x0; thin lines: its x0 after it
     const int pid = blockIdx.x;
     if (threadIdx.x < GC_NM) cf[threadIdx.x] = a.mpoly[(size_t)pid * GC_NM + threadIdx.x];
     __syncthreads();
     const DevCell C = a.cells[a.pair_cell[pid]];   // copied: fields stay in registers across stores
     const sea_pair P = a.pairs[pid];
-    const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;   // column coordinates, x first where it is one
+    const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;   // line coordinates, x first where it is one
     const int n = P.n[ax];
     const double ih2 = 1.0 / (C.h[ax] * C.h[ax]);
     const size_t st[3] = {1, (size_t)P.n[0], (size_t)P.n[0] * P.n[1]};
-    const int c0 = blockIdx.y * GA_BS;
+    const int c0 = blockIdx.y * GA_COLS;
+    const int lc = threadIdx.x % GA_COLS, side = threadIdx.x / GA_COLS;
     auto column = [&](int c, int& au, int& av) {
         au = c % a.nmax;
         av = c / a.nmax;
         return av < a.nmax && au < P.n[u] && av < P.n[v];
     };
     int au, av;
-    const bool live = column(c0 + threadIdx.x, au, av);
+    const bool live = column(c0 + lc, au, av);
     const bool staged = ax == 0 && n >= 2 * SEA_HALO;   // x faces, the two faces' targets disjoint
     const bool face = FACE && spectral_pair(P);          // uniform
+    const bool split = n >= 2 * SEA_HALO;                // the faces' ghost taps apart
     const int nf = n < FS ? n : FS;                      // frame points of the line
     auto frame_pt = [&](int j) { return (n <= FS || j < FF_W) ? j : n - FS + j; };
     double* b = a.b + (size_t)pid * a.stride;
-    if (live) {
+    if (live && (split || side == 0)) {
         int pos[3];
         pos[u] = au;
         pos[v] = av;
         const size_t base = pos[u] * st[u] + pos[v] * st[v];
-        // the column's fixed displacements folded into line coefficients once
+        // the line's fixed displacements folded into line coefficients once
         double dv[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) dv[k] = k == ax ? 0.0 : (P.lo[k] + pos[k]) * C.h[k] - P.origin[k];
         double q[SEA_LMAX + 1][SEA_LMAX + 1];
         me_line_coeffs<AX>(cf, dv, q);
         const double rt2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
-        for (int plus = 0; plus < 2; ++plus) {
+        // the ghost values beyond one face folded into b
+        auto fold = [&](int plus) {
             double g[SEA_HALO + 1];
 #pragma unroll
             for (int L = 1; L <= SEA_HALO; ++L) {
@@ -538,52 +546,55 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
 #pragma unroll
                 for (int k = d + 1; k <= SEA_HALO; ++k) acc += kC[k] * ih2 * g[k - d];
                 const int p = plus ? n - 1 - d : d;
-                if (staged) tap[threadIdx.x][plus ? 2 * SEA_HALO - 1 - d : d] = acc;   // slot j: point j or n - 12 + j
+                if (staged) tap[lc][plus ? 2 * SEA_HALO - 1 - d : d] = acc;   // slot j: point j or n - 12 + j
                 else b[base + (size_t)p * st[ax]] += acc;
             }
-        }
-        if (FACE && face) {
-            // -D x0 at the frame points, into t (slot j: frame point j)
-            double t[FS];
-            if (n >= FS) {
-                // the faces apart: x0 at the frame points in registers, every
-                // index known at compile time; point d from a face takes
-                // sum_{k >= d + 2} c_k x0(k - d - 2) of the same face's points
-                double xf[FS];
+        };
+        // set by an earlier launch: the line lies within FF_W of an x face
+        // (or, for z, of a y face)
+        const bool set_before = near_face(pos[0], P.n[0]) || (ax == 2 && near_face(pos[1], P.n[1]));
+        double* fc = FACE ? a.fcorr + (size_t)pid * a.stride + base : nullptr;
+        if (split) {
+            fold(side);
+            if (FACE && face) {
+                // -D x0 at this face's 5 frame points: x0 there in registers,
+                // every index known at compile time; point d from the face
+                // takes sum_{k >= d + 2} c_k x0(k - d - 2) of the same face
+                double xf[FF_W];
 #pragma unroll
-                for (int j = 0; j < FS; ++j)
-                    xf[j] = me_line_potential(q, (P.lo[ax] + (j < FF_W ? j : n - FS + j)) * C.h[ax] - P.origin[ax], rt2);
+                for (int j = 0; j < FF_W; ++j)
+                    xf[j] = me_line_potential(q, (P.lo[ax] + (side ? n - 1 - j : j)) * C.h[ax] - P.origin[ax], rt2);
 #pragma unroll
                 for (int d = 0; d < FF_W; ++d) {
-                    double lo = 0.0, hi = 0.0;
+                    double acc = 0.0;
 #pragma unroll
-                    for (int k = d + 2; k <= SEA_HALO; ++k) {
-                        lo -= kC[k] * xf[k - d - 2];
-                        hi -= kC[k] * xf[FS - 1 - (k - d - 2)];
+                    for (int k = d + 2; k <= SEA_HALO; ++k) acc -= kC[k] * xf[k - d - 2];
+                    const double t = acc * ih2;
+                    if (ax == 0) {   // out through LDS below, a lane per point
+                        xs[lc][side ? FS - 1 - d : d] = -t;
+                    } else {         // neighbouring lanes take neighbouring x: straight out
+                        double* f = fc + (size_t)(side ? n - 1 - d : d) * st[ax];
+                        *f = set_before ? *f - t : -t;
                     }
-                    t[d] = lo * ih2;
-                    t[FS - 1 - d] = hi * ih2;
                 }
-            } else {   // a thin line: the odd continuation over the whole line (LDS)
-                for (int j = 0; j < nf; ++j)
-                    xs[threadIdx.x][j] = me_line_potential(q, (P.lo[ax] + j) * C.h[ax] - P.origin[ax], rt2);
-#pragma unroll
-                for (int j = 0; j < FS; ++j)
-                    t[j] = j < nf ? face_taps(j, n, [&](int i) { return xs[threadIdx.x][i]; }) * ih2 : 0.0;
             }
-            if (ax == 0) {   // out through LDS below, a lane per point
-#pragma unroll
-                for (int j = 0; j < FS; ++j) xs[threadIdx.x][j] = -t[j];
-            } else {   // neighbouring lanes take neighbouring x: straight out
-                double* fc = a.fcorr + (size_t)pid * a.stride + base;
-                // set by an earlier launch: the column lies within FF_W of an
-                // x face (or, for z, of a y face)
-                const bool set_before = near_face(pos[0], P.n[0]) || (ax == 2 && near_face(pos[1], P.n[1]));
-#pragma unroll
-                for (int j = 0; j < FS; ++j) {
-                    if (j >= nf) break;
-                    double* f = fc + (size_t)frame_pt(j) * st[ax];
-                    *f = set_before ? *f - t[j] : -t[j];
+        } else {   // a line shorter than 2 SEA_HALO: both faces here
+            fold(0);
+            fold(1);
+            if (FACE && face) {
+                // x0 on the frame (LDS), then the taps of the odd
+                // continuation over the whole line
+                for (int j = 0; j < nf; ++j)
+                    xs[lc][FS + j] = me_line_potential(q, (P.lo[ax] + frame_pt(j)) * C.h[ax] - P.origin[ax], rt2);
+                for (int j = 0; j < nf; ++j) {
+                    const int p = frame_pt(j);
+                    const double t = face_taps(p, n, [&](int i) { return xs[lc][FS + frame_k(i, n)]; }) * ih2;
+                    if (ax == 0) {
+                        xs[lc][j] = -t;
+                    } else {
+                        double* f = fc + (size_t)p * st[ax];
+                        *f = set_before ? *f - t : -t;
+                    }
                 }
             }
         }
@@ -591,7 +602,7 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
     if (FACE && face && ax == 0) {   // the x face points out through LDS, a lane per point
         __syncthreads();
         double* fc = a.fcorr + (size_t)pid * a.stride;
-        for (int t = threadIdx.x; t < GA_BS * FS; t += GA_BS) {
+        for (int t = threadIdx.x; t < GA_COLS * FS; t += GA_BS) {
             const int c = t / FS, j = t % FS;
             int cu, cv;
             if (j >= nf || !column(c0 + c, cu, cv)) continue;
@@ -600,7 +611,7 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
     }
     if (!staged) return;
     __syncthreads();
-    for (int t = threadIdx.x; t < GA_BS * 2 * SEA_HALO; t += GA_BS) {
+    for (int t = threadIdx.x; t < GA_COLS * 2 * SEA_HALO; t += GA_BS) {
         const int c = t / (2 * SEA_HALO), j = t % (2 * SEA_HALO);
         int cu, cv;
         if (!column(c0 + c, cu, cv)) continue;
@@ -1042,7 +1053,7 @@ hipError_t launch_moments_final(const ExxArgs& a, double* Q_orth, hipStream_t s)
 hipError_t launch_boundary_fold(const ExxArgs& a, int nz_max, hipStream_t s, bool face) {
     (void)nz_max;
     if (face && !a.fcorr) return hipErrorInvalidValue;
-    const unsigned gy = (unsigned)(((long)a.nmax * a.nmax + GA_BS - 1) / GA_BS);
+    const unsigned gy = (unsigned)(((long)a.nmax * a.nmax + GA_COLS - 1) / GA_COLS);
     const dim3 g(a.n_pairs, gy);
     if (face) {
         hipLaunchKernelGGL((k_ghost_axis<0, true>), g, dim3(GA_BS), 0, s, a);

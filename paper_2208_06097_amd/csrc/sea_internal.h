@@ -148,7 +148,7 @@ struct ExxArgs {
 // Scatter tiles (k_scatter.hip): 64 x 4 x 8 grid points of one orbital.
 constexpr int SC_TX = 64, SC_TY = 4, SC_TZ = 8;
 // longest orbital pair list whose pair energies the scatter forms
-constexpr int SC_EP_MAXE = 256;
+constexpr int SC_EP_MAXE = 128;
 
 // Pair energies from the scatter.  The workgroup of orbital i of pair
 // (i, j) writes one partial of e_ij per scatter tile the pair's domain
@@ -249,7 +249,7 @@ hipError_t launch_start_residual(const ExxArgs& a, hipStream_t s);
 // the norms |b|^2 and |b - A x|^2 per pair into a.rnorm (nothing else
 // written), then (with `write`) b - A x into bres for the pairs whose start
 // does not meet the FP32 z-march CG's exit test (the others are left alone).
-constexpr int RZ_TILES = 4;   // row tiles of 16 per pair in the residual z-march
+constexpr int RZ_TILES = 4;   // row tiles of 16 rows per pair (row-tile march, k_cg.hip)
 size_t residual_zm_lds_bytes();
 hipError_t launch_residual_zm(const ExxArgs& a, hipStream_t s, bool write = true);
 // FP64-state CG by row tiles (cubic grids, nx, ny <= 64): r = b - A x0 (or

@@ -256,3 +256,31 @@ def test_learned_start_requires_network():
         cl.exx_action(torch.from_numpy(cell.phi).cuda(), cell.N, cell.L, pairs)
     assert ei.value.status == sea.SEA_E_ARG
     cl.close()
+
+
+def test_learned_beats_multipole_on_held_out_cell():
+    """The committed network on the 64-molecule cell (seed 2000, 1.0 g/cm^3;
+    the training cells are other seeds and densities): the learned start
+    needs fewer CG iterations than the multipole start it corrects, which
+    needs fewer than the zero start; all three reach the same E_xx at the
+    same true residual (FP32 state)."""
+    import os
+    weights = os.path.join(os.path.dirname(sea.__file__), "weights", "unet_f32cg.npy")
+    cell = synth.config2(with_phi=False)
+    phi = synth.fill_orbitals_device(cell, dtype=torch.float32)
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, 6.0)
+    print(f"case learned vs multipole: {len(pairs)} pairs", flush=True)
+    res = {}
+    for name, start in (("zero", sea.SEA_START_ZERO), ("multipole", sea.SEA_START_MULTIPOLE),
+                        ("learned", sea.SEA_START_LEARNED)):
+        ctx = sea.Context(rel_tol=1e-8, stencil_dtype=sea.SEA_F32, start=start)
+        if start == sea.SEA_START_LEARNED:
+            ctx.nn_attach(ctx.nn_state(np.load(weights)))
+        _, E, stats, status = ctx.exx_action(phi, cell.N, cell.L, pairs)
+        assert status == sea.SEA_OK and np.all(stats["converged"] == 1) and np.all(stats["rel_res"] <= 1e-8)
+        res[name] = (E, stats["iters"].mean())
+        print(f"{name}: mean iterations {stats['iters'].mean():.2f}  E {E:.10f}", flush=True)
+        ctx.close()
+    assert res["learned"][1] < res["multipole"][1] < res["zero"][1]
+    for name in ("multipole", "learned"):
+        assert abs(res[name][0] - res["zero"][0]) < 1e-6, name
