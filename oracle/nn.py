@@ -205,3 +205,35 @@ def resample(f, m):
         t = t.reshape(shape)
         out = (1 - t) * a + t * b
     return out
+
+
+def upsample_cubic(f, m):
+    """Tricubic map of f (a 3-D array) onto m points per axis (an int, or
+    one per axis in array order), corners aligned: the learned start's way
+    back to the pair domain.  Fine point k of an axis sits at
+    u = k (n-1)/(m-1) on the coarse axis of n points; with
+    i = min(floor(u), n-2) and t = u - i the value is the 4-point Lagrange
+    interpolant through the coarse points i-1, i, i+1, i+2, a point one
+    beyond an end taking the linear extrapolation 2 f(end) - f(end -+ 1).
+    One axis at a time."""
+    out = np.asarray(f, dtype=np.float64)
+    ms = (m,) * 3 if np.isscalar(m) else tuple(m)
+    for ax in range(3):
+        n, mm = out.shape[ax], ms[ax]
+        u = np.arange(mm) * ((n - 1) / (mm - 1))
+        i = np.minimum(np.floor(u).astype(int), n - 2)
+        t = u - i
+        # one ghost point on each side, by linear extrapolation
+        a = np.moveaxis(out, ax, 0)
+        ext = np.concatenate([(2 * a[0] - a[1])[None], a, (2 * a[-1] - a[-2])[None]], axis=0)
+        res = 0.0
+        for q in range(4):
+            # Lagrange basis of node q over the nodes at offsets -1, 0, 1, 2
+            lq = np.ones_like(t)
+            for r in range(4):
+                if r != q:
+                    lq = lq * (t - (r - 1)) / ((q - 1) - (r - 1))
+            vals = ext[i + q]            # ghost-shifted index of point i - 1 + q
+            res = res + lq.reshape((mm,) + (1,) * (vals.ndim - 1)) * vals
+        out = np.moveaxis(res, 0, ax)
+    return out

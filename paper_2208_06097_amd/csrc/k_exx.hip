@@ -807,18 +807,21 @@ __device__ __forceinline__ Cub cubic_at(int k, int from, int to) {
     const double wq[4] = {-f * (f - 1.0) * (f - 2.0) / 6.0, (f + 1.0) * (f - 1.0) * (f - 2.0) / 2.0,
                           -(f + 1.0) * f * (f - 2.0) / 2.0, (f + 1.0) * f * (f - 1.0) / 6.0};
     c.base = min(max(i0 - 1, 0), from - 4);
+    // node q of the stencil lands on point i0 - 1 + q; one beyond an end is
+    // the linear extrapolation 2 f(end) - f(end -+ 1).  Summed per output
+    // slot in node order, with compile-time slots (no indexed registers).
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int j = i0 - 1 + q;
-        if (j < 0) {
-            c.w[0 - c.base] += 2.0 * wq[q];
-            c.w[1 - c.base] -= wq[q];
-        } else if (j >= from) {
-            c.w[from - 1 - c.base] += 2.0 * wq[q];
-            c.w[from - 2 - c.base] -= wq[q];
-        } else {
-            c.w[j - c.base] += wq[q];
+    for (int m = 0; m < 4; ++m) {
+        const int idx = c.base + m;
+        double w = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = i0 - 1 + q;
+            if (j < 0) w += idx == 0 ? 2.0 * wq[q] : (idx == 1 ? -wq[q] : 0.0);
+            else if (j >= from) w += idx == from - 1 ? 2.0 * wq[q] : (idx == from - 2 ? -wq[q] : 0.0);
+            else w += j == idx ? wq[q] : 0.0;
         }
+        c.w[m] = w;
     }
     return c;
 }
@@ -837,6 +840,7 @@ __global__ __launch_bounds__(GM_BS) void k_nn_apply(ExxArgs a, int D, const floa
     const long beg = (long)blockIdx.y * GM_CHUNK;
     if (beg >= n_int) return;
     const long end = min(beg + GM_CHUNK, n_int);
+    if (nx <= 64 && ny <= 64 && nz <= 64) return;   // k_nn_apply_ring takes those
     const double s = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM];
     if (!(s > 0.0)) return;
     const float* y = y32 + (size_t)pid * D * D * D;
@@ -859,6 +863,79 @@ __global__ __launch_bounds__(GM_BS) void k_nn_apply(ExxArgs a, int D, const floa
             acc += cz.w[c] * accy;
         }
         x[id] += s * acc;
+    }
+}
+
+// The same map, separably, for pairs with every axis <= 64: a workgroup
+// takes NA_ZC output planes of one pair; each network plane it needs is
+// interpolated in x and y once into a ring of four LDS planes (FP32, the
+// network's precision), and an output plane is the cubic combination of the
+// four ring planes its z weights name.  The per-axis weights come from
+// cubic_at once per grid index, not per point.
+constexpr int NA_BS = 256;
+constexpr int NA_ZC = 16;   // output planes per workgroup
+
+__global__ __launch_bounds__(NA_BS) void k_nn_apply_ring(ExxArgs a, int D, const float* __restrict__ y32) {
+    __shared__ float U[4][64 * 64];   // network planes interpolated in x and y (ring by plane index mod 4)
+    __shared__ double wt[3][64][4];
+    __shared__ int bs[3][64];
+    const int pid = blockIdx.x;
+    const sea_pair P = a.pairs[pid];
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    if (nx > 64 || ny > 64 || nz > 64) return;   // k_nn_apply takes those
+    const int z0 = blockIdx.y * NA_ZC;
+    if (z0 >= nz) return;
+    const int z1 = min(nz, z0 + NA_ZC);
+    const double s = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM];
+    if (!(s > 0.0)) return;
+    for (int t = threadIdx.x; t < 3 * 64; t += NA_BS) {
+        const int ax = t / 64, k = t % 64;
+        const int n = ax == 0 ? nx : (ax == 1 ? ny : nz);
+        if (k < n) {
+            const Cub c = cubic_at(k, D, n);
+            bs[ax][k] = c.base;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wt[ax][k][q] = c.w[q];
+        }
+    }
+    __syncthreads();
+    const float* y = y32 + (size_t)pid * D * D * D;
+    double* x = a.v + (size_t)pid * a.stride;
+    const int npl = nx * ny;
+    int hi = -1;   // the ring holds network planes hi - 3 .. hi
+    for (int z = z0; z < z1; ++z) {
+        const int cb = bs[2][z];
+        if (cb + 3 > hi) {
+            for (int k = max(cb, hi + 1); k <= cb + 3; ++k) {   // planes the ring lacks
+                const float* yk = y + (size_t)k * D * D;
+                float* Uk = U[k & 3];
+                for (int t = threadIdx.x; t < npl; t += NA_BS) {
+                    const int ix = t % nx, iy = t / nx;
+                    const float* r0 = yk + bs[1][iy] * D + bs[0][ix];
+                    double acc = 0.0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const float* row = r0 + b * D;
+                        double ax = 0.0;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) ax += wt[0][ix][q] * (double)row[q];
+                        acc += wt[1][iy][b] * ax;
+                    }
+                    Uk[t] = (float)acc;
+                }
+            }
+            hi = cb + 3;
+            __syncthreads();
+        }
+        double* xz = x + (size_t)z * npl;
+        const double w0 = wt[2][z][0], w1 = wt[2][z][1], w2 = wt[2][z][2], w3 = wt[2][z][3];
+        const float* u0 = U[cb & 3];
+        const float* u1 = U[(cb + 1) & 3];
+        const float* u2 = U[(cb + 2) & 3];
+        const float* u3 = U[(cb + 3) & 3];
+        for (int t = threadIdx.x; t < npl; t += NA_BS)
+            xz[t] += s * (((w0 * (double)u0[t] + w1 * (double)u1[t]) + w2 * (double)u2[t]) + w3 * (double)u3[t]);
+        __syncthreads();   // before the ring's next planes overwrite these
     }
 }
 
@@ -1085,6 +1162,7 @@ hipError_t launch_nn_sample(const ExxArgs& a, int D, float* out, double* s_out, 
 
 hipError_t launch_nn_apply(const ExxArgs& a, int D, const float* y32, hipStream_t s) {
     if (D < 4) return hipErrorInvalidValue;   // the cubic map needs 4 network points per axis
+    hipLaunchKernelGGL(k_nn_apply_ring, dim3(a.n_pairs, (64 + NA_ZC - 1) / NA_ZC), dim3(NA_BS), 0, s, a, D, y32);
     hipLaunchKernelGGL(k_nn_apply, dim3(a.n_pairs, a.n_chunks), dim3(GM_BS), 0, s, a, D, y32);
     return hipGetLastError();
 }

@@ -284,3 +284,40 @@ def test_learned_beats_multipole_on_held_out_cell():
     assert res["learned"][1] < res["multipole"][1] < res["zero"][1]
     for name in ("multipole", "learned"):
         assert abs(res[name][0] - res["zero"][0]) < 1e-6, name
+
+
+@pytest.mark.parametrize("half_width", [4.0, 10.0])
+def test_learned_start_is_multipole_plus_upsampled_network(half_width):
+    """The learned start before any CG iteration (FP64 state, max_iter 0) is
+    the oracle's regularized multipole start plus s times the oracle's
+    tricubic map of the GPU network's 32^3 output, pair by pair: domains of
+    27-29 points (the separable LDS-ring kernel) and of 69 points, wider
+    than the cell (the per-point kernel)."""
+    import os
+    weights = os.path.join(os.path.dirname(sea.__file__), "weights", "unet_f32cg.npy")
+    cell = synth.mini(seed=7)
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, half_width)
+    pl = oracle.build_pairs(cell.N, cell.L, cell.centres, 6.0, half_width)
+    print(f"case learned x0, half width {half_width}: {len(pairs)} pairs, n {pairs['n'].max()}", flush=True)
+    phi = torch.from_numpy(cell.phi).cuda()
+    ctx = sea.Context(rel_tol=1e-8, stencil_dtype=sea.SEA_F64, start=sea.SEA_START_LEARNED, max_iter=0)
+    st = ctx.nn_state(np.load(weights))
+    ctx.nn_attach(st)
+    v, _, _, stats, _ = ctx.pair_solve(phi, cell.N, cell.L, pairs, want_Q=False)
+    x, _, s, _ = ctx.exx_nn_samples(phi, cell.N, cell.L, pairs)
+    y = ctx.nn_infer(st, x.contiguous()).cpu().numpy().astype(np.float64)
+    s = s.cpu().numpy()
+    v = v.cpu().numpy()
+    ctx.close()
+    assert np.all(stats["iters"] == 0)
+    for k in range(0, len(pairs), max(1, len(pairs) // 4)):
+        n = pl.n[k]
+        got = v[k, :n[0] * n[1] * n[2]].reshape(n[2], n[1], n[0])
+        corr = s[k] * nn.upsample_cubic(y[k], (n[2], n[1], n[0]))
+        want = oracle.pair_me_start(cell.phi, cell.N, cell.L, pl, k) + corr
+        err = np.max(np.abs(got - want))
+        print(f"pair {k}: n {tuple(n)} max |x0 - want| {err:.2e} of max |s up(y)| {np.max(np.abs(corr)):.2e}",
+              flush=True)
+        # FP32 network values interpolated through an FP32 ring (relative
+        # 1e-6 of the correction) plus the start's FP64 rounding
+        assert err < 1e-6 * np.max(np.abs(corr)) + 1e-10 * np.max(np.abs(want))

@@ -123,3 +123,34 @@ def test_resample_exact_on_affine_fields(n, m):
 def test_resample_63_to_32_is_subsampling():
     f = np.random.default_rng(6).standard_normal((63, 63, 63))
     assert np.array_equal(nn.resample(f, 32), f[::2, ::2, ::2])
+
+
+def test_upsample_cubic_pins():
+    """The learned start's tricubic map: coarse values kept where fine and
+    coarse points coincide (63 = 2 x 32 - 1), affine fields exact everywhere
+    (the ghost extrapolation is linear), cubic polynomials exact wherever the
+    4-point stencil stays inside the coarse grid, and a coarse delta gives
+    the textbook midpoint weights -1/16, 9/16, 9/16, -1/16."""
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((32, 32, 32))
+    g = nn.upsample_cubic(f, 63)
+    assert np.max(np.abs(g[::2, ::2, ::2] - f)) < 1e-13
+    c = np.linspace(0.0, 1.0, 32)
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    fine = np.linspace(0.0, 1.0, 63)
+    Zf, Yf, Xf = np.meshgrid(fine, fine, fine, indexing="ij")
+    aff = nn.upsample_cubic(0.5 + 2 * X - 3 * Y + 0.25 * Z, 63)
+    assert np.max(np.abs(aff - (0.5 + 2 * Xf - 3 * Yf + 0.25 * Zf))) < 1e-12
+    cub = nn.upsample_cubic(X ** 3 - 2 * Y ** 2 * Z + X * Y * Z, 63)
+    want = Xf ** 3 - 2 * Yf ** 2 * Zf + Xf * Yf * Zf
+    inner = slice(2, 61)   # fine points whose stencil has no ghost node
+    assert np.max(np.abs(cub[inner, inner, inner] - want[inner, inner, inner])) < 1e-12
+    d = np.zeros((32, 32, 32))
+    d[10, 10, 10] = 1.0
+    u = nn.upsample_cubic(d, 63)
+    line = u[20, 20, 15:26]   # fine points 15..25 along x at the delta's row and plane
+    want_line = [0, 0, -1 / 16, 0, 9 / 16, 1, 9 / 16, 0, -1 / 16, 0, 0]   # fine 20 is coarse 10
+    assert np.max(np.abs(line - np.array(want_line))) < 1e-14
+    # non-cubic target shape
+    h = nn.upsample_cubic(f[:8, :9, :10], (15, 17, 19))
+    assert h.shape == (15, 17, 19) and np.max(np.abs(h[::2, ::2, ::2] - f[:8, :9, :10])) < 1e-13
