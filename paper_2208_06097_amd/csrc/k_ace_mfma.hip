@@ -30,7 +30,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 128, BN = 128, KT = 32, NT = 256;
+constexpr int BM = 128, BN = 128, NT = 256;
 
 __device__ __forceinline__ float bf_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ uint16_t f_to_bf(float f) {
@@ -57,6 +57,9 @@ template <>
 struct Kind<ACE_F64> {
     using E = double;
     using Acc = f64x4;
+    // K staged 16 at a time: the next stage's loads held in registers stay
+    // at 16 doubles per thread (with 128 accumulator registers per lane)
+    static constexpr int KT = 16;
     static constexpr int PITCH = KT + 1;
     static constexpr int KSTEP = 4;
     // output item v of lane-group g holds tile row g + 4 v (FP64 layout)
@@ -71,6 +74,7 @@ template <>
 struct Kind<ACE_F32> {
     using E = float;
     using Acc = f32x4;
+    static constexpr int KT = 32;
     static constexpr int PITCH = KT + 1;
     static constexpr int KSTEP = 4;
     // output item v of lane-group g holds tile row 4 g + v
@@ -85,6 +89,7 @@ template <>
 struct Kind<ACE_BF16> {
     using E = uint16_t;
     using Acc = f32x4;
+    static constexpr int KT = 32;
     static constexpr int PITCH = KT + 8;  // 16-byte aligned rows
     static constexpr int KSTEP = 32;
     __device__ static int row(int g, int v) { return 4 * g + v; }
@@ -99,25 +104,39 @@ struct Kind<ACE_BF16> {
     }
 };
 
-// Multiply the staged tiles: wave (wm, wn) owns rows wm*64.., cols wn*64..
+// Multiply the staged tiles: wave (wm, wn) = (wave / 2, wave % 2) owns rows
+// wm*64.., cols wn*64..
 template <int KIND>
-__device__ __forceinline__ void tile_mma(const typename Kind<KIND>::E* As, const typename Kind<KIND>::E* Bs,
-                                         typename Kind<KIND>::Acc (&acc)[4][4]) {
+__device__ __forceinline__ void tile_step(const typename Kind<KIND>::E* As, const typename Kind<KIND>::E* Bs, int kk,
+                                          typename Kind<KIND>::Acc (&acc)[4][4]) {
     using K = Kind<KIND>;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int r = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int kk = 0; kk < KT; kk += K::KSTEP) {
+    for (int p = 0; p < 4; ++p) {
+        const typename K::E* a = As + (wm * 64 + p * 16 + r) * K::PITCH + kk;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const typename K::E* a = As + (wm * 64 + p * 16 + r) * K::PITCH + kk;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const typename K::E* b = Bs + (wn * 64 + q * 16 + r) * K::PITCH + kk;
-                acc[p][q] = K::mma(a, b, g, acc[p][q]);
-            }
+        for (int q = 0; q < 4; ++q) {
+            const typename K::E* b = Bs + (wn * 64 + q * 16 + r) * K::PITCH + kk;
+            acc[p][q] = K::mma(a, b, g, acc[p][q]);
         }
+    }
+}
+
+// FEW: two k steps at a time, so that only their operands (4 A and 4 B per
+// step) are LDS reads in flight, which saves registers for occupancy; else
+// the whole stage unrolled (measured faster where occupancy does not change)
+template <int KIND, bool FEW>
+__device__ __forceinline__ void tile_mma(const typename Kind<KIND>::E* As, const typename Kind<KIND>::E* Bs,
+                                         typename Kind<KIND>::Acc (&acc)[4][4]) {
+    using K = Kind<KIND>;
+    if constexpr (FEW) {
+#pragma unroll 2
+        for (int kk = 0; kk < K::KT; kk += K::KSTEP) tile_step<KIND>(As, Bs, kk, acc);
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < K::KT; kk += K::KSTEP) tile_step<KIND>(As, Bs, kk, acc);
     }
 }
 
@@ -126,6 +145,7 @@ __global__ __launch_bounds__(NT) void k_nt_mfma(const TA* __restrict__ A, const 
                                                 long K, long kslice, double* __restrict__ part) {
     using Kd = Kind<KIND>;
     using E = typename Kd::E;
+    constexpr int KT = Kd::KT;
     __shared__ __attribute__((aligned(16))) E As[BM * Kd::PITCH];
     __shared__ __attribute__((aligned(16))) E Bs[BN * Kd::PITCH];
     const int j0 = blockIdx.x * BN, i0 = blockIdx.y * BM;
@@ -143,14 +163,21 @@ __global__ __launch_bounds__(NT) void k_nt_mfma(const TA* __restrict__ A, const 
     constexpr int PER = BM * KT / NT;
     TA ra[PER];
     TB rb[PER];
+    // element offsets within a stage are below BM K < 2^31 (checked at
+    // launch): one uniform 64-bit base per stage and a 32-bit offset per
+    // element, shared by A and B, instead of a 64-bit address per element
+    const int Ki = (int)K;
     auto load = [&](long k0) {
+        const TA* __restrict__ Ab = A + (size_t)i0 * K + k0;
+        const TB* __restrict__ Bb = B + (size_t)j0 * K + k0;
+        const int kl = (int)(ke - k0);   // k of this stage below kl
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = threadIdx.x + NT * e;
             const int rr = idx / KT, kk = idx % KT;
-            const long k = k0 + kk;
-            ra[e] = (i0 + rr < m && k < ke) ? A[(size_t)(i0 + rr) * K + k] : TA(0);
-            rb[e] = (j0 + rr < n && k < ke) ? B[(size_t)(j0 + rr) * K + k] : TB(0);
+            const int off = rr * Ki + kk;
+            ra[e] = (i0 + rr < m && kk < kl) ? Ab[off] : TA(0);
+            rb[e] = (j0 + rr < n && kk < kl) ? Bb[off] : TB(0);
         }
     };
     if (kb < ke) load(kb);
@@ -165,7 +192,7 @@ __global__ __launch_bounds__(NT) void k_nt_mfma(const TA* __restrict__ A, const 
         }
         __syncthreads();
         if (k0 + KT < ke) load(k0 + KT);
-        tile_mma<KIND>(As, Bs, acc);
+        tile_mma<KIND, KIND == ACE_F64>(As, Bs, acc);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -206,6 +233,7 @@ __global__ __launch_bounds__(NT) void k_nn_mfma(const double* __restrict__ A, lo
                                                 TC* __restrict__ C) {
     using Kd = Kind<KIND>;
     using E = typename Kd::E;
+    constexpr int KT = Kd::KT;
     __shared__ __attribute__((aligned(16))) E As[BM * Kd::PITCH];
     __shared__ __attribute__((aligned(16))) E Bs[BN * Kd::PITCH];
     const long j0 = (long)blockIdx.x * BN;
@@ -242,7 +270,7 @@ __global__ __launch_bounds__(NT) void k_nn_mfma(const double* __restrict__ A, lo
         }
         __syncthreads();
         if (k0 + KT < K) load(k0 + KT);
-        tile_mma<KIND>(As, Bs, acc);
+        tile_mma<KIND, std::is_same<TB, double>::value>(As, Bs, acc);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -273,9 +301,10 @@ int ace_mfma_splits(long K, int m, int n, int max_splits) {
 template <int KIND, typename TA, typename TB>
 hipError_t ace_mm_nt(const TA* A, const TB* B, int m, int n, long K, double alpha, double* part, double* C,
                      hipStream_t s, int max_splits) {
+    if ((long)BM * K >= 0x7fffffffL) return hipErrorInvalidValue;   // 32-bit element offsets of a stage
     const int splits = ace_mfma_splits(K, m, n, max_splits);
     long kslice = (K + splits - 1) / splits;
-    kslice = (kslice + KT - 1) / KT * KT;
+    kslice = (kslice + Kind<KIND>::KT - 1) / Kind<KIND>::KT * Kind<KIND>::KT;
     dim3 grid((n + BN - 1) / BN, (m + BM - 1) / BM, splits);
     hipLaunchKernelGGL((k_nt_mfma<KIND, TA, TB>), grid, dim3(NT), 0, s, A, B, m, n, K, kslice, part);
     hipError_t e = hipGetLastError();
