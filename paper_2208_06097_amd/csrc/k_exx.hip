@@ -140,16 +140,30 @@ __global__ __launch_bounds__(128) void k_racah_poly(double* __restrict__ tab) {
         for (int k = 0; k < SEA_NMOM; ++k) tab[k * GC_NM + t] = P[k][t];
 }
 
-// grid (pairs, plane chunks of GC_ZC); per chunk record of GC_N doubles:
-// M_abc (84), sum |rho|, sum |rho| r^2
+// One workgroup per (pair, plane chunk of GC_ZC), in a one-dimensional
+// grid numbered so that each XCD (workgroup k runs on XCD k mod 8) takes a
+// contiguous eighth of the pair list, every chunk of a pair in turn: the
+// pairs of one orbital, which are neighbours in the list, then read its
+// values through the same L2.
+constexpr int GC_XCD = 8;
+__device__ __forceinline__ void gc_block(int n_pairs, int n_zchunks, int& pid, int& zc) {
+    const int k = blockIdx.x, x = k % GC_XCD, m = k / GC_XCD;
+    const int per = (n_pairs + GC_XCD - 1) / GC_XCD;
+    pid = x * per + m / n_zchunks;
+    zc = m % n_zchunks;
+}
+
+// per chunk record of GC_N doubles: M_abc (84), sum |rho|, sum |rho| r^2
 __global__ __launch_bounds__(GM_BS) void k_gather_cart(ExxArgs a) {
     __shared__ double red[GM_BS / 64][4][64];
     __shared__ double red2[GM_BS / 64][2][64];
     __shared__ double tot[GC_N];
-    const int pid = blockIdx.x;
+    int pid, zc;
+    gc_block(a.n_pairs, a.n_zchunks, pid, zc);
+    if (pid >= a.n_pairs) return;
     const sea_pair P = a.pairs[pid];
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    const int z0 = blockIdx.y * GC_ZC;
+    const int z0 = zc * GC_ZC;
     if (z0 >= nz) return;
     const int z1 = min(z0 + GC_ZC, nz);
     // the cell record copied: its fields stay in registers across the stores to b
@@ -266,7 +280,7 @@ __global__ __launch_bounds__(GM_BS) void k_gather_cart(ExxArgs a) {
             __syncthreads();
         }
     }
-    double* out = a.partial + ((size_t)pid * a.n_zchunks + blockIdx.y) * GC_N;
+    double* out = a.partial + ((size_t)pid * a.n_zchunks + zc) * GC_N;
     for (int t = threadIdx.x; t < GC_NM + 2; t += GM_BS) out[t] = tot[t];
 }
 
@@ -1118,7 +1132,9 @@ int exx_n_chunks(long n_int_max) { return (int)((n_int_max + GM_CHUNK - 1) / GM_
 
 hipError_t launch_gather_moments(const ExxArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_racah_poly, dim3(1), dim3(128), 0, s, a.racah_tab);
-    hipLaunchKernelGGL(k_gather_cart, dim3(a.n_pairs, a.n_zchunks), dim3(GM_BS), 0, s, a);
+    const long nb = (long)((a.n_pairs + GC_XCD - 1) / GC_XCD) * GC_XCD * a.n_zchunks;
+    if (nb > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather_cart, dim3((unsigned)nb), dim3(GM_BS), 0, s, a);
     return hipGetLastError();
 }
 
