@@ -287,6 +287,18 @@ const char *sea_spectral_variant_name(int variant);
  * variants, zline: index among the z-line variants; -1: the autotuner's
  * choice, else the first).  SEA_E_ARG out of range. */
 sea_status sea_set_spectral_variants(sea_ctx *ctx, int plane, int zline);
+/* Per-pair residual histories (diagnostics of the Eq. 9 solves).  With
+ * hist_dev set, every later exx call of this context writes, for pair k of
+ * the call and iteration t = 0 .. len, the relative residual
+ * |r_t| / |b| at hist_dev[k * (len + 1) + t] (FP64, device memory owned by
+ * the caller, n_pairs * (len + 1) doubles, n_pairs of the call): t = 0 is
+ * the start's true FP64 residual, t >= 1 the CG's recursive residual after
+ * t iterations (FP32 z-march, FP64 row tiles and their preconditioned form;
+ * the generic FP64 kernel records its exit only).  Entries after
+ * a pair's last iteration are NaN.  hist_dev NULL or len < 0 turns the
+ * recording off.  The buffer must hold the next calls' pairs; it is not
+ * checked.  SEA_E_ARG for a negative len with a non-NULL buffer. */
+sea_status sea_set_residual_history(sea_ctx *ctx, double *hist_dev, int len);
 /* Autotuner of the transform passes (the timed form's schedule choice):
  * on a strided sample of `sample_pairs` pairs of these cells, times the
  * forward plane pass of every plane variant and the z-line pass of every

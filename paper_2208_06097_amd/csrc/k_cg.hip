@@ -109,6 +109,11 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
     return r;
 }
 
+// residual history entry t of pair pid (a.hist set, t <= a.hist_len)
+__device__ __forceinline__ void hist_put(const ExxArgs& a, int pid, int t, double r2, double b2) {
+    if (a.hist && t <= a.hist_len) a.hist[(size_t)pid * (a.hist_len + 1) + t] = b2 > 0.0 ? sqrt(r2 / b2) : 0.0;
+}
+
 __device__ __forceinline__ int wrap_idx(int k, int N) {
     int m = k % N;
     return m < 0 ? m + N : m;
@@ -348,6 +353,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
                 a.stats[pid].iters = 0;
                 a.stats[pid].converged = 1;
                 a.stats[pid].rel_res = b2 > 0.0 ? sqrt(q2 / b2) : 0.0;
+                hist_put(a, pid, 0, q2, b2);
             }
             return;
         }
@@ -389,6 +395,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
     };
     double rho = 0.0, rupd = r2;
     T beta = T(0);
+    if (threadIdx.x == 0) hist_put(a, pid, 0, r2, bb);
     if (!(r2 == r2) || !(bb == bb)) conv = -1;
     else if (r2 <= tol2 * bb) conv = 1;
     else if (a.max_iter <= 0) conv = 0;
@@ -461,6 +468,7 @@ __device__ void solve_pair(const ExxArgs& a, int pid, T* lds, double* red, T* __
         const double rn2 = block_sum<NT>(racc, red);
         if constexpr (XC) pend = with_c ? T(0) : al;
         ++it;
+        if (threadIdx.x == 0) hist_put(a, pid, it, rn2, bb);
         const bool nan = !(rn2 == rn2);
         if (!nan && rn2 > tol2 * bb && rn2 > Delta<T>::v2 * rupd && it < a.max_iter) {
             beta = (T)(rn2 / rho);
@@ -827,6 +835,7 @@ __global__ __launch_bounds__(RZ_NT) void k_cg64_init(ExxArgs a) {
                 a.stats[pid].iters = 0;
                 a.stats[pid].converged = 1;
                 a.stats[pid].rel_res = b2 > 0.0 ? sqrt(q2 / b2) : 0.0;
+                hist_put(a, pid, 0, q2, b2);
             }
             return;
         }
@@ -893,6 +902,7 @@ __global__ __launch_bounds__(RZ_NT) void k_cg64_sweep(ExxArgs a) {
         const double bb = cg64_sum(a, pid, 3);
         const double tol2 = CG64_TARGET * CG64_TARGET * a.rel_tol * a.rel_tol;
         const bool nan = !(rr == rr) || !(bb == bb) || !(rho == rho);
+        if (tile == 0 && threadIdx.x == 0) hist_put(a, pid, k, rr, bb);
         if (nan || rr <= tol2 * bb || k >= a.max_iter) {
             if (tile == 0 && threadIdx.x == 0) {
                 a.stats[pid].iters = k;
@@ -1072,6 +1082,18 @@ hipError_t launch_cg64_dot(const ExxArgs& a, hipStream_t s) {
 hipError_t launch_cg64_exit(const ExxArgs& a, hipStream_t s) {
     if (a.n_pairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cg64_exit, dim3((a.n_pairs + 63) / 64), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_nan(double* __restrict__ p, size_t n) {
+    const double q = __builtin_nan("");
+    for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) p[k] = q;
+}
+
+hipError_t launch_fill_nan(double* p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned nb = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_fill_nan, dim3(nb), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -1090,6 +1090,7 @@ __global__ __launch_bounds__(CG_BS) void k_cg_f64(ExxArgs a) {
             st.s_abs = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM];
             st.q = a.mom[(size_t)pid * SEA_NACC + SEA_NMOM + 1];
             a.stats[pid] = st;
+            if (a.hist && it <= a.hist_len) a.hist[(size_t)pid * (a.hist_len + 1) + it] = rel;   // its exit only
         }
     }
 }

@@ -551,6 +551,8 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.cg_z = Ly.cg_z ? (double*)(base + Ly.cg_z) : nullptr;
     a.cg_pre = 0;
     a.cg_it = 0;
+    a.hist = ctx->hist;
+    a.hist_len = ctx->hist_len;
     return a;
 }
 
@@ -646,6 +648,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
     int nz_max = 1;
     for (const auto& p : S.pairs) nz_max = p.n[2] > nz_max ? p.n[2] : nz_max;
     if (n_pairs > 0) {
+        if (a.hist) SEA_HIP_CHECK(ctx, launch_fill_nan(a.hist, (size_t)n_pairs * (a.hist_len + 1), s));
         timer_on(SEA_STAGE_GATHER);
         SEA_HIP_CHECK(ctx, launch_gather_moments(a, s));
         SEA_HIP_CHECK(ctx, launch_moments_final(a, f.Q_dev, s));
@@ -1545,6 +1548,14 @@ extern "C" const char* sea_cg_variant_name(int v) { return cg_variant_name(v); }
 extern "C" int sea_spectral_variant_count(void) { return dst_variant_count(); }
 
 extern "C" const char* sea_spectral_variant_name(int v) { return dst_variant_name(v); }
+
+extern "C" sea_status sea_set_residual_history(sea_ctx* ctx, double* hist_dev, int len) {
+    if (!ctx) return SEA_E_ARG;
+    if (hist_dev && len < 0) return fail(ctx, SEA_E_ARG, "residual history length %d < 0", len);
+    ctx->hist = len >= 0 ? hist_dev : nullptr;
+    ctx->hist_len = ctx->hist ? len : 0;
+    return SEA_OK;
+}
 
 extern "C" sea_status sea_set_spectral_variants(sea_ctx* ctx, int plane, int zline) {
     if (!ctx) return SEA_E_ARG;

@@ -43,6 +43,9 @@ struct sea_ctx {
     // and a fixed choice (-1: none; the fixed one wins)
     int dst_plane_tuned = -1, dst_zline_tuned = -1;
     int dst_plane_fixed = -1, dst_zline_fixed = -1;
+    // per-pair residual histories (caller's device buffer; nullptr: off)
+    double* hist = nullptr;
+    int hist_len = 0;
 };
 
 // Looks up, once per device, the device address of the static scratch array
@@ -143,6 +146,8 @@ struct ExxArgs {
     int* cg_done;         // n_pairs: the pair has stopped (2: by its start); null outside the row-tile CG
     int* cg_active;       // max_iter + 2 counters: pairs still iterating at each iteration; the last, after the init
     int cg_it;            // the iteration a sweep launch performs
+    double* hist;         // n_pairs x (hist_len + 1) relative residuals per iteration (nullable)
+    int hist_len;
 };
 
 // Scatter tiles (k_scatter.hip): 64 x 4 x 8 grid points of one orbital.
@@ -267,6 +272,8 @@ hipError_t launch_cg64_dot(const ExxArgs& a, hipStream_t s);
 hipError_t launch_dst_solve(const ExxArgs& a, const double* r, double* z, double* tmp, double* tmp2, double* tab,
                             double* mu, int pv, int zv, bool square, const int* skip, hipStream_t s);
 hipError_t launch_fill_int(int* p, size_t n, hipStream_t s);
+// p[0 .. n) = NaN (the residual histories' empty entries)
+hipError_t launch_fill_nan(double* p, size_t n, hipStream_t s);
 // Spectral start (k_dst.hip): x = A_odd^-1 (b + a.fcorr on the face points)
 // for the pairs with every axis <= 64 (a.fcorr is tmp, scratch of the pair
 // arrays' size; r scratch of the same size).

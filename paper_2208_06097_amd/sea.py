@@ -36,6 +36,7 @@ EXPORTS = [
     "sea_successive_idempotency", "sea_scdm_workspace_bytes", "sea_scdm", "sea_rotate",
     "sea_ace_apply_noalloc", "sea_spectral_variant_count", "sea_spectral_variant_name",
     "sea_set_spectral_variants", "sea_spectral_autotune", "sea_exx_plan_workspace_bytes",
+    "sea_set_residual_history",
 ]
 
 # size of the library's static scratch array per GPU (SEA_NOALLOC_SCRATCH_BYTES
@@ -162,6 +163,7 @@ def load() -> C.CDLL:
     lib.sea_spectral_variant_name.argtypes = [i]
     lib.sea_spectral_variant_name.restype = C.c_char_p
     lib.sea_set_spectral_variants.argtypes = [vp, i, i]
+    lib.sea_set_residual_history.argtypes = [vp, vp, i]
     lib.sea_spectral_autotune.argtypes = [vp, i, vp, vp, sz, i, vp, P(i), P(i)]
     lib.sea_nn_infer_workspace_bytes.argtypes = [vp, i, P(sz)]
     lib.sea_nn_infer.argtypes = [vp, vp, i, vp, vp, vp, sz]
@@ -429,6 +431,20 @@ class Context:
         plane = pn.index(plane) if isinstance(plane, str) else plane
         zline = zn.index(zline) if isinstance(zline, str) else zline
         self._check(self.lib.sea_set_spectral_variants(self.h, int(plane), int(zline)))
+
+    def residual_history(self, n_pairs, length):
+        """Turns on per-pair residual histories for the next exx calls and
+        returns their buffer: (n_pairs, length + 1) FP64 on the device,
+        entry [k, t] the relative residual of pair k after t iterations
+        (NaN after its last).  length < 0 turns them off (returns None)."""
+        torch = self._torch
+        if length < 0:
+            self._check(self.lib.sea_set_residual_history(self.h, None, -1))
+            self._hist = None
+            return None
+        self._hist = torch.empty((max(n_pairs, 1), length + 1), dtype=torch.float64, device="cuda")
+        self._check(self.lib.sea_set_residual_history(self.h, self._hist.data_ptr(), int(length)))
+        return self._hist
 
     def spectral_autotune(self, cells, sample_pairs=512, ws=None, cache=None):
         """Pick the sine-transform kernel variants of the spectral start for

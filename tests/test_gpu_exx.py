@@ -479,3 +479,40 @@ def test_fp64_row_tile_cg_against_the_per_pair_kernel(mini):
     assert d.max() <= 3
     plan.close()
     c.close()
+
+
+@pytest.mark.parametrize("form", ["f64-zero", "f32-zero", "f64-spectral", "f32-multipole"])
+def test_residual_histories(mini, form):
+    """Per-pair residual histories: entry 0 is the start's true residual (1
+    for a zero start, the reported residual for a start that already meets
+    the target), entries 1 .. iters the CG's recursive residual, NaN after;
+    a history stays untouched once recording is off."""
+    cell, pl, ref, pairs = mini
+    print(f"case residual histories {form}", flush=True)
+    sdt = sea.SEA_F64 if form.startswith("f64") else sea.SEA_F32
+    start = {"zero": sea.SEA_START_ZERO, "spectral": sea.SEA_START_SPECTRAL,
+             "multipole": sea.SEA_START_MULTIPOLE}[form.split("-")[1]]
+    c = sea.Context(rel_tol=1e-8, stencil_dtype=sdt, start=start)
+    phi = _dev(cell.phi)
+    L = 600
+    hist = c.residual_history(len(pairs), L)
+    _, E, s, st = c.exx_action(phi, cell.N, cell.L, pairs)
+    assert st == sea.SEA_OK and np.all(s["converged"] == 1)
+    h = hist.cpu().numpy()
+    for k in range(len(pairs)):
+        t = int(s["iters"][k])
+        assert t <= L
+        assert np.all(np.isfinite(h[k, :t + 1])) and np.all(np.isnan(h[k, t + 1:])), k
+        if start == sea.SEA_START_ZERO:
+            assert abs(h[k, 0] - 1.0) < 1e-12
+        if t == 0:
+            assert abs(h[k, 0] - s["rel_res"][k]) <= 1e-12 * max(1.0, s["rel_res"][k])
+        else:
+            assert h[k, t] < 1e-7 and h[k, t] < h[k, 0]
+    print(f"iterations mean {s['iters'].mean():.1f}; first pair {h[0, :min(4, int(s['iters'][0]) + 1)]}", flush=True)
+    hist.fill_(7.0)
+    c.residual_history(0, -1)
+    c.exx_action(phi, cell.N, cell.L, pairs)
+    torch.cuda.synchronize()
+    assert torch.all(hist == 7.0)
+    c.close()
