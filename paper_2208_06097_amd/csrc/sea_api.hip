@@ -102,7 +102,7 @@ struct CellSet {
     std::vector<int> order;  // CG queue: pair ids by decreasing interior size (ties: id order)
     std::vector<int> dbox;   // 12 per pair: W_i box, W_j box (default: the pair's domain twice)
     bool cubic = true;
-    bool square = true;      // every pair the sine transform takes has n[0] = n[1]
+    int dst_shape = DST_SQUARE;   // DST_* bits of the pairs the sine transform takes
 };
 
 // the sine-transform kernel variants a call uses: the fixed ones, else the
@@ -187,7 +187,10 @@ static sea_status build_cellset(sea_ctx* ctx, int n_cells, const sea_cell* cells
     }
     if ((long long)S.pairs.size() > (1LL << 30)) return fail(ctx, SEA_E_ARG, "too many pairs");
     for (const auto& p : S.pairs)
-        if (spectral_pair(p) && p.n[0] != p.n[1]) S.square = false;
+        if (spectral_pair(p)) {
+            if (p.n[0] != p.n[1]) S.dst_shape &= ~DST_SQUARE;
+            S.dst_shape |= (p.n[2] & 1) ? DST_ZODD : DST_ZEVEN;
+        }
     // longest-processing-time-first queue for the persistent CG kernels
     S.order.resize(S.pairs.size());
     for (size_t k = 0; k < S.pairs.size(); ++k) S.order[k] = (int)k;
@@ -566,7 +569,7 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
 struct Cg64Pre {
     double *tmp, *tmp2, *tab, *mu;
     int pv, zv;
-    bool square;
+    int shape;
 };
 static sea_status cg64_run(sea_ctx* ctx, const ExxArgs& a0, double* rnorm, hipStream_t s, const Cg64Pre* pre) {
     ExxArgs a = a0;
@@ -582,7 +585,7 @@ static sea_status cg64_run(sea_ctx* ctx, const ExxArgs& a0, double* rnorm, hipSt
     }
     auto precondition = [&](int k) -> sea_status {
         SEA_HIP_CHECK(ctx, launch_dst_solve(a, a.cg_r, a.cg_z, pre->tmp, pre->tmp2, pre->tab, pre->mu, pre->pv,
-                                            pre->zv, pre->square, a.cg_done, s));
+                                            pre->zv, pre->shape, a.cg_done, s));
         ExxArgs ad = a;
         ad.cg_it = k;
         SEA_HIP_CHECK(ctx, launch_cg64_dot(ad, s));
@@ -702,7 +705,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
                 dst_variants(ctx, pv, zv);
                 SEA_HIP_CHECK(ctx, launch_spectral_start(a, a.bres, (double*)(base + Ly.dst_tmp),
                                                          (double*)(base + Ly.dst_tab), (double*)(base + Ly.dst_mu), pv,
-                                                         zv, S.square, s,
+                                                         zv, S.dst_shape, s,
                                                          [&](int pass, bool begin) {
                                                              const int st = SEA_STAGE_DST_PLANE_FWD + pass;
                                                              if (begin) {
@@ -733,7 +736,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
             int pv = 0, zv = 0;
             dst_variants(ctx, pv, zv);
             const Cg64Pre pre{(double*)(base + Ly.dst_tmp), a.bres, (double*)(base + Ly.dst_tab),
-                              (double*)(base + Ly.dst_mu), pv, zv, S.square};
+                              (double*)(base + Ly.dst_mu), pv, zv, S.dst_shape};
             sea_status st = cg64_run(ctx, a, (double*)(base + Ly.rnorm), s, &pre);
             if (st != SEA_OK) return st;
             timer_off(SEA_STAGE_CG);
@@ -1631,8 +1634,8 @@ extern "C" sea_status sea_spectral_autotune(sea_ctx* ctx, int n_cells, const sea
         for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {   // rep 0 warms the code object
             err = hipEventRecord(e0, s);
             if (err == hipSuccess)
-                err = plane ? launch_dst_pass(a, 0, v, S.square, a.b, tmp, tab, mu, s)
-                            : launch_dst_pass(a, 1, v - np, S.square, tmp, a.bres, tab, mu, s);
+                err = plane ? launch_dst_pass(a, 0, v, S.dst_shape, a.b, tmp, tab, mu, s)
+                            : launch_dst_pass(a, 1, v - np, S.dst_shape, tmp, a.bres, tab, mu, s);
             if (err == hipSuccess) err = hipEventRecord(e1, s);
             if (err == hipSuccess) err = hipEventSynchronize(e1);
             if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);

@@ -270,22 +270,26 @@ hipError_t launch_cg64_dot(const ExxArgs& a, hipStream_t s);
 // z = A_odd^-1 r for the pairs not marked in `skip` (the three transform
 // passes with the context's variants; tmp, tmp2 scratch of the pair arrays' size)
 hipError_t launch_dst_solve(const ExxArgs& a, const double* r, double* z, double* tmp, double* tmp2, double* tab,
-                            double* mu, int pv, int zv, bool square, const int* skip, hipStream_t s);
+                            double* mu, int pv, int zv, int shape, const int* skip, hipStream_t s);
 hipError_t launch_fill_int(int* p, size_t n, hipStream_t s);
 // p[0 .. n) = NaN (the residual histories' empty entries)
 hipError_t launch_fill_nan(double* p, size_t n, hipStream_t s);
+// Shape bits of the pairs the sine transform takes: every one has nx = ny;
+// some has an odd nz; some has an even nz (the z-line kernels of each kind
+// launched only when needed).
+enum { DST_SQUARE = 1, DST_ZODD = 2, DST_ZEVEN = 4 };
 // Spectral start (k_dst.hip): x = A_odd^-1 (b + a.fcorr on the face points)
 // for the pairs with every axis <= 64 (a.fcorr is tmp, scratch of the pair
 // arrays' size; r scratch of the same size).
 size_t dst_table_doubles();
 size_t dst_mu_doubles();
 // pv, zv: variants of the plane and z-line kernels (0 <= pv <
-// dst_plane_variant_count(), 0 <= zv < dst_variant_count() - that); square:
-// every pair the transform takes has nx = ny.  `mark(pass, true)` /
+// dst_plane_variant_count(), 0 <= zv < dst_variant_count() - that); shape:
+// DST_* bits of the pairs the transform takes.  `mark(pass, true)` /
 // `mark(pass, false)` bracket each of the three transform passes (0 forward
 // planes, 1 z lines, 2 inverse planes; stage timing).
 hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, int pv, int zv,
-                                 bool square, hipStream_t s, const std::function<void(int, bool)>& mark);
+                                 int shape, hipStream_t s, const std::function<void(int, bool)>& mark);
 // transform-kernel variants: plane variants first, then the z-line ones
 int dst_variant_count();
 int dst_plane_variant_count();
@@ -293,7 +297,7 @@ const char* dst_variant_name(int v);
 hipError_t launch_dst_tables(double* tab, double* mu, hipStream_t s);
 // one pass (0 forward planes, 1 z lines, 2 inverse planes) of a variant on
 // every pair, in -> out (autotuner)
-hipError_t launch_dst_pass(const ExxArgs& a, int pass, int variant, bool square, const double* in, double* out,
+hipError_t launch_dst_pass(const ExxArgs& a, int pass, int variant, int shape, const double* in, double* out,
                            double* tab, double* mu, hipStream_t s);
 // the pairs the sine transform takes
 __host__ __device__ inline bool spectral_pair(const sea_pair& P) { return P.n[0] <= 64 && P.n[1] <= 64 && P.n[2] <= 64; }
