@@ -625,6 +625,18 @@ constexpr int RZ_NT = 1024;
 constexpr int RZ_ROWS = 16;   // rows owned per workgroup: one per wavefront
 constexpr int RZ_WR = RZ_ROWS + 2 * SEA_HALO;   // rows of the window
 constexpr int RZ_XCD = 8;
+#ifndef SEA_RZ_PRE
+#define SEA_RZ_PRE 2
+#endif
+#ifndef SEA_RZ_DEPTH
+#define SEA_RZ_DEPTH 2
+#endif
+#ifndef SEA_CG64_DEPTH
+#define SEA_CG64_DEPTH 1
+#endif
+constexpr int RZ_PRE = SEA_RZ_PRE;           // steps ahead that the owned point's data is loaded
+constexpr int RZ_DEPTH = SEA_RZ_DEPTH;       // steps ahead that the residual sweep fetches x
+constexpr int CG64_DEPTH = SEA_CG64_DEPTH;   // the same for the CG sweeps
 static_assert(RZ_TILES * RZ_ROWS >= 64, "row tiles cover 64 rows");
 static_assert(RZ_NT / 64 == RZ_ROWS, "a wavefront per owned row");
 
@@ -644,13 +656,16 @@ __device__ __forceinline__ void rz_block(int& pid, int& tile) {
 // wavefront takes two).  fetch(yw, z) issues the loads of window
 // row yw at plane z, DEPTH steps before they are used (measured: the
 // residual sweep, with one plane of output loads, runs faster at DEPTH 2;
-// the CG sweeps, with two, at DEPTH 1), make(yw, z, F) turns them into f, pre(z) prefetches the owned point's data
-// of output plane z, out(z, A f, f, PV) consumes it.  Two LDS planes of
+// the CG sweeps, with two, at DEPTH 1), make(yw, z, F) turns them into f,
+// pre(z) loads the owned point's data of output plane z (z < nz), PRE steps
+// before out(z, A f, f, PV) consumes it (issued with the step's other loads,
+// so that its latency is not paid at the step's end).  Two LDS planes of
 // RZ_WR x 64 doubles.
-template <int DEPTH, typename F, typename PV, typename FetchF, typename MakeF, typename PreF, typename OutF>
+template <int DEPTH, int PRE, typename F, typename PV, typename FetchF, typename MakeF, typename PreF, typename OutF>
 __device__ __forceinline__ void rtmarch(int nz, double* lds, const SW<double>& w, FetchF&& fetch, MakeF&& make,
                                         PreF&& pre, OutF&& out) {
-    static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
+    static_assert(DEPTH >= 1 && DEPTH <= 4, "prefetch depth");
+    static_assert(PRE >= 0 && PRE <= 4, "output data prefetch depth");
     constexpr int HR = 2 * SEA_HALO;                           // halo rows of the window
     constexpr int HPW = (HR + RZ_ROWS - 1) / RZ_ROWS;           // halo rows per wavefront (at most)
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -664,42 +679,49 @@ __device__ __forceinline__ void rtmarch(int nz, double* lds, const SW<double>& w
     for (int k = 0; k < 6; ++k) q[k] = 0.0;
 #pragma unroll
     for (int s = 0; s < 7; ++s) q[6 + s] = make(yo, s, fetch(yo, min(s, nz)));
-    // DEPTH 2: the owned row's plane z + 7 is fetched at step z - 1 and the
-    // halo rows' plane z at step z - 2; DEPTH 1: one step later each
-    F on{};
-    if constexpr (DEPTH == 2) on = fetch(yo, min(7, nz));
-    F hn[HPW], hn2[HPW];
+    // the owned row's plane z + 7 is fetched at step z + 1 - DEPTH (DEPTH 1:
+    // in the step that uses it, at its end) and the halo rows' plane z at
+    // step z - DEPTH
+    F oq[DEPTH > 1 ? DEPTH - 1 : 1];
 #pragma unroll
-    for (int e = 0; e < HPW; ++e) {
-        hn[e] = F{};
-        hn2[e] = F{};
-        if (has_h(e)) {
-            hn[e] = fetch(hrow(e), 0);
-            if constexpr (DEPTH == 2) hn2[e] = fetch(hrow(e), min(1, nz));
-        }
-    }
+    for (int i = 0; i + 1 < DEPTH; ++i) oq[i] = fetch(yo, min(7 + i, nz));
+    F hq[HPW][DEPTH];
+#pragma unroll
+    for (int e = 0; e < HPW; ++e)
+#pragma unroll
+        for (int i = 0; i < DEPTH; ++i) hq[e][i] = has_h(e) ? fetch(hrow(e), min(i, nz)) : F{};
+    PV pq[PRE > 0 ? PRE : 1];
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) pq[i] = pre(min(i, nz - 1));
     for (int z = 0; z < nz; ++z) {
         F nxt;
-        if constexpr (DEPTH == 2) {
-            nxt = on;
-            on = fetch(yo, min(z + 8, nz));
-        } else {
+        if constexpr (DEPTH == 1) {
             nxt = fetch(yo, min(z + 7, nz));
+        } else {
+            nxt = oq[0];
+#pragma unroll
+            for (int i = 0; i + 2 < DEPTH; ++i) oq[i] = oq[i + 1];
+            oq[DEPTH - 2] = fetch(yo, min(z + 6 + DEPTH, nz));
         }
         F hc[HPW];
 #pragma unroll
         for (int e = 0; e < HPW; ++e) {
-            hc[e] = hn[e];
+            hc[e] = hq[e][0];
             if (has_h(e)) {
-                if constexpr (DEPTH == 2) {
-                    hn[e] = hn2[e];
-                    hn2[e] = fetch(hrow(e), min(z + 2, nz));
-                } else {
-                    hn[e] = fetch(hrow(e), min(z + 1, nz));
-                }
+#pragma unroll
+                for (int i = 0; i + 1 < DEPTH; ++i) hq[e][i] = hq[e][i + 1];
+                hq[e][DEPTH - 1] = fetch(hrow(e), min(z + DEPTH, nz));
             }
         }
-        const PV pv = pre(z);
+        PV pv;
+        if constexpr (PRE == 0) {
+            pv = pre(z);
+        } else {
+            pv = pq[0];
+#pragma unroll
+            for (int i = 0; i + 1 < PRE; ++i) pq[i] = pq[i + 1];
+            pq[PRE - 1] = pre(min(z + PRE, nz - 1));   // (past the last plane: the last again, unused)
+        }
         double* pl = lds + (z & 1) * (LW * RZ_WR);
         pl[yo * LW + tx] = q[6];
 #pragma unroll
@@ -757,7 +779,7 @@ __global__ __launch_bounds__(RZ_NT) void k_residual_zm(ExxArgs a) {
     const int tx = threadIdx.x & 63, yown = y0 + (threadIdx.x >> 6);
     const bool own = yown < ny && tx < nx;
     double bb = 0.0, rr = 0.0;
-    rtmarch<2, double, double>(
+    rtmarch<RZ_DEPTH, RZ_PRE, double, double>(
         nz, lds, w,
         [&](int yw, int z) -> double {   // window row yw is grid row y0 - SEA_HALO + yw
             const int y = y0 - SEA_HALO + yw;
@@ -859,7 +881,7 @@ __global__ __launch_bounds__(RZ_NT) void k_cg64_init(ExxArgs a) {
     const bool own = yown < ny && tx < nx;
     const bool x0 = a.x_nonzero;
     double bb = 0.0, rr = 0.0;
-    rtmarch<1, double, double>(
+    rtmarch<CG64_DEPTH, RZ_PRE, double, double>(
         nz, lds, w,
         [&](int yw, int z) -> double {
             const int y = y0 - SEA_HALO + yw;
@@ -950,7 +972,7 @@ __global__ __launch_bounds__(RZ_NT) void k_cg64_sweep(ExxArgs a) {
         // the owned rows
         const double beta = k > 0 ? rho / a.cg_rho[(size_t)pid * 2 + ((k - 1) & 1)] : 0.0;
         const double* __restrict__ src = (a.cg_pre ? a.cg_z : a.cg_r) + (size_t)pid * a.stride;
-        rtmarch<1, F2<double>, Empty>(
+        rtmarch<CG64_DEPTH, 0, F2<double>, Empty>(
             nz, lds, w,
             [&](int yw, int z) -> F2<double> {
                 if (!inwin(yw, z)) return F2<double>{0.0, 0.0};
@@ -970,7 +992,7 @@ __global__ __launch_bounds__(RZ_NT) void k_cg64_sweep(ExxArgs a) {
     } else {
         // x += alpha p, r -= alpha A p, |r|^2 over the owned rows
         const double alpha = rho / cg64_sum(a, pid, 2);
-        rtmarch<1, double, F2<double>>(
+        rtmarch<CG64_DEPTH, RZ_PRE, double, F2<double>>(
             nz, lds, w,
             [&](int yw, int z) -> double { return inwin(yw, z) ? p[widx(yw, z)] : 0.0; },
             [&](int, int, double v) -> double { return v; },

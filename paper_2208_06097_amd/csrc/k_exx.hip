@@ -538,6 +538,24 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
         pos[u] = au;
         pos[v] = av;
         const size_t base = pos[u] * st[u] + pos[v] * st[v];
+        // set by an earlier launch: the line lies within FF_W of an x face
+        // (or, for z, of a y face)
+        const bool set_before = near_face(pos[0], P.n[0]) || (ax == 2 && near_face(pos[1], P.n[1]));
+        double* fc = FACE ? a.fcorr + (size_t)pid * a.stride + base : nullptr;
+        // y and z faces of a long line: the b values this face's taps update
+        // (and the -D x0 values an earlier launch set there), loaded before
+        // the multipole work so that their latency overlaps it; the points
+        // are distinct, so the updates need not wait for one another
+        const bool pre = split && !staged;
+        double bpre[SEA_HALO], fpre[FF_W];
+        if (pre) {
+#pragma unroll
+            for (int d = 0; d < SEA_HALO; ++d) bpre[d] = b[base + (size_t)(side ? n - 1 - d : d) * st[ax]];
+            if (FACE && face && set_before) {
+#pragma unroll
+                for (int d = 0; d < FF_W; ++d) fpre[d] = fc[(size_t)(side ? n - 1 - d : d) * st[ax]];
+            }
+        }
         // the line's fixed displacements folded into line coefficients once
         double dv[3];
 #pragma unroll
@@ -561,13 +579,10 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
                 for (int k = d + 1; k <= SEA_HALO; ++k) acc += kC[k] * ih2 * g[k - d];
                 const int p = plus ? n - 1 - d : d;
                 if (staged) tap[lc][plus ? 2 * SEA_HALO - 1 - d : d] = acc;   // slot j: point j or n - 12 + j
+                else if (pre) b[base + (size_t)p * st[ax]] = bpre[d] + acc;
                 else b[base + (size_t)p * st[ax]] += acc;
             }
         };
-        // set by an earlier launch: the line lies within FF_W of an x face
-        // (or, for z, of a y face)
-        const bool set_before = near_face(pos[0], P.n[0]) || (ax == 2 && near_face(pos[1], P.n[1]));
-        double* fc = FACE ? a.fcorr + (size_t)pid * a.stride + base : nullptr;
         if (split) {
             fold(side);
             if (FACE && face) {
@@ -587,8 +602,7 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
                     if (ax == 0) {   // out through LDS below, a lane per point
                         xs[lc][side ? FS - 1 - d : d] = -t;
                     } else {         // neighbouring lanes take neighbouring x: straight out
-                        double* f = fc + (size_t)(side ? n - 1 - d : d) * st[ax];
-                        *f = set_before ? *f - t : -t;
+                        fc[(size_t)(side ? n - 1 - d : d) * st[ax]] = set_before ? fpre[d] - t : -t;
                     }
                 }
             }
@@ -625,12 +639,27 @@ __global__ __launch_bounds__(GA_BS) void k_ghost_axis(ExxArgs a) {
     }
     if (!staged) return;
     __syncthreads();
-    for (int t = threadIdx.x; t < GA_COLS * 2 * SEA_HALO; t += GA_BS) {
+    // every b value first (distinct points: the loads need not wait for the
+    // stores), then the sums
+    constexpr int NU = GA_COLS * 2 * SEA_HALO / GA_BS;
+    static_assert(NU * GA_BS == GA_COLS * 2 * SEA_HALO, "whole rounds of updates");
+    double bv[NU];
+    size_t off[NU];
+    bool ok[NU];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        const int t = threadIdx.x + i * GA_BS;
         const int c = t / (2 * SEA_HALO), j = t % (2 * SEA_HALO);
         int cu, cv;
-        if (!column(c0 + c, cu, cv)) continue;
+        ok[i] = column(c0 + c, cu, cv);
         const int p = j < SEA_HALO ? j : n - 2 * SEA_HALO + j;
-        b[(size_t)cu * st[1] + (size_t)cv * st[2] + p] += tap[c][j];
+        off[i] = (size_t)cu * st[1] + (size_t)cv * st[2] + p;
+        bv[i] = ok[i] ? b[off[i]] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        const int t = threadIdx.x + i * GA_BS;
+        if (ok[i]) b[off[i]] = bv[i] + tap[t / (2 * SEA_HALO)][t % (2 * SEA_HALO)];
     }
 }
 
