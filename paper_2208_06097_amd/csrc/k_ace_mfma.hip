@@ -31,6 +31,21 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BM = 128, BN = 128, NT = 256;
+// Workgroups are handed to the 8 XCDs (each with its own L2) in turn.  The
+// workgroups that read the same operand tiles (NT: the output tiles of one
+// K slice; NN: the row blocks of one column tile of the grid-point operand)
+// are given consecutive places in one XCD's sequence, so that they run there
+// together and the second read of a tile comes from that L2.
+constexpr int ACE_XCD = 8;
+__host__ __device__ inline long xcd_grid(long groups, int per_group) {
+    return (groups + ACE_XCD - 1) / ACE_XCD * ACE_XCD * per_group;
+}
+// workgroup k -> (group, member): group g's members on XCD g % ACE_XCD
+__device__ __forceinline__ void xcd_block(int per_group, long& group, int& member) {
+    const long k = blockIdx.x, x = k % ACE_XCD, mseq = k / ACE_XCD;
+    member = (int)(mseq % per_group);
+    group = (mseq / per_group) * ACE_XCD + x;
+}
 
 __device__ __forceinline__ float bf_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ uint16_t f_to_bf(float f) {
@@ -142,14 +157,20 @@ __device__ __forceinline__ void tile_mma(const typename Kind<KIND>::E* As, const
 
 template <int KIND, typename TA, typename TB>
 __global__ __launch_bounds__(NT) void k_nt_mfma(const TA* __restrict__ A, const TB* __restrict__ B, int m, int n,
-                                                long K, long kslice, double* __restrict__ part) {
+                                                long K, long kslice, int splits, double* __restrict__ part) {
     using Kd = Kind<KIND>;
     using E = typename Kd::E;
     constexpr int KT = Kd::KT;
     __shared__ __attribute__((aligned(16))) E As[BM * Kd::PITCH];
     __shared__ __attribute__((aligned(16))) E Bs[BN * Kd::PITCH];
-    const int j0 = blockIdx.x * BN, i0 = blockIdx.y * BM;
-    const long kb = (long)blockIdx.z * kslice;
+    // group: K slice; member: output tile
+    const int tn = (n + BN - 1) / BN, tm = (m + BM - 1) / BM;
+    long slice;
+    int tile;
+    xcd_block(tn * tm, slice, tile);
+    if (slice >= splits) return;   // padding of the last XCD round (an empty slice still writes its zeros)
+    const long kb = slice * kslice;
+    const int j0 = (tile % tn) * BN, i0 = (tile / tn) * BM;
     const long ke = min(K, kb + kslice);
     typename Kd::Acc acc[4][4];
 #pragma unroll
@@ -196,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_nt_mfma(const TA* __restrict__ A, const 
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    double* P = part + (size_t)blockIdx.z * m * n;
+    double* P = part + (size_t)slice * m * n;
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -236,8 +257,13 @@ __global__ __launch_bounds__(NT) void k_nn_mfma(const double* __restrict__ A, lo
     constexpr int KT = Kd::KT;
     __shared__ __attribute__((aligned(16))) E As[BM * Kd::PITCH];
     __shared__ __attribute__((aligned(16))) E Bs[BN * Kd::PITCH];
-    const long j0 = (long)blockIdx.x * BN;
-    const int i0 = blockIdx.y * BM;
+    // group: column tile of B; member: row block
+    long jt;
+    int ib;
+    xcd_block((m + BM - 1) / BM, jt, ib);
+    const long j0 = jt * BN;
+    if (j0 >= ncol) return;   // padding of the last XCD round
+    const int i0 = ib * BM;
     typename Kd::Acc acc[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
@@ -305,8 +331,10 @@ hipError_t ace_mm_nt(const TA* A, const TB* B, int m, int n, long K, double alph
     const int splits = ace_mfma_splits(K, m, n, max_splits);
     long kslice = (K + splits - 1) / splits;
     kslice = (kslice + Kind<KIND>::KT - 1) / Kind<KIND>::KT * Kind<KIND>::KT;
-    dim3 grid((n + BN - 1) / BN, (m + BM - 1) / BM, splits);
-    hipLaunchKernelGGL((k_nt_mfma<KIND, TA, TB>), grid, dim3(NT), 0, s, A, B, m, n, K, kslice, part);
+    const long nb = xcd_grid(splits, ((n + BN - 1) / BN) * ((m + BM - 1) / BM));
+    if (nb > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_nt_mfma<KIND, TA, TB>), dim3((unsigned)nb), dim3(NT), 0, s, A, B, m, n, K, kslice, splits,
+                       part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int mn = m * n;
@@ -317,8 +345,10 @@ hipError_t ace_mm_nt(const TA* A, const TB* B, int m, int n, long K, double alph
 template <int KIND, typename TB, typename TC>
 hipError_t ace_mm_nn(const double* A, long sai, long sak, const TB* B, int m, int K, long ncol, double alpha, TC* C,
                      hipStream_t s) {
-    dim3 grid((unsigned)((ncol + BN - 1) / BN), (m + BM - 1) / BM);
-    hipLaunchKernelGGL((k_nn_mfma<KIND, TB, TC>), grid, dim3(NT), 0, s, A, sai, sak, B, m, K, ncol, alpha, C);
+    const long nb = xcd_grid((ncol + BN - 1) / BN, (m + BM - 1) / BM);
+    if (nb > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_nn_mfma<KIND, TB, TC>), dim3((unsigned)nb), dim3(NT), 0, s, A, sai, sak, B, m, K, ncol, alpha,
+                       C);
     return hipGetLastError();
 }
 
