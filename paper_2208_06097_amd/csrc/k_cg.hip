@@ -64,9 +64,6 @@ __device__ __forceinline__ SW<T> make_sw(double ih2) {
     return w;
 }
 
-// LDS-only barrier: waits for this thread's LDS traffic, not for global loads
-// in flight, then synchronizes the workgroup.
-__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Wavefront shifts by one lane with zero fill at the edge (DPP wave_shl:1 /
 // wave_shr:1).  The stencil only uses sums f(x+k) + f(x-k), so it does not

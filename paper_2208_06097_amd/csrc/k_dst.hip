@@ -296,6 +296,15 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
     const double* in = d.in + (size_t)pid * d.stride;
     double* out = d.out + (size_t)pid * d.stride;
     const double* add = d.add ? d.add + (size_t)pid * d.stride : nullptr;
+    // the face correction of plane zz at this thread's elements (0 elsewhere)
+    auto load_add = [&](int zz, double ad[DP_PT]) {
+        const size_t zo = (size_t)zz * npl;
+        const bool zf = near_face(zz, nz);
+        for_elems([&](int u, int e, int o) {
+            const int yy = o / DP_LD, xx = o % DP_LD;
+            ad[u] = (zf || near_face(xx, nx) || near_face(yy, ny)) ? add[zo + e] : 0.0;
+        });
+    };
     for (int z = blockIdx.y; z < nz; z += PG) {
         const size_t zo = (size_t)z * npl;
         int gk = g, Nxk = Nx, Nyk = Ny;
@@ -312,22 +321,18 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
             double ad[DP_PT];
 #pragma unroll
             for (int u = 0; u < DP_PT; ++u) ad[u] = 0.0;
-            const bool zf = near_face(z, nz);
-            for_elems([&](int u, int e, int o) {
-                const int yy = o / DP_LD, xx = o % DP_LD;
-                ad[u] = (zf || near_face(xx, nx) || near_face(yy, ny)) ? add[zo + e] : 0.0;
-            });
+            load_add(z, ad);
 #pragma unroll
             for (int u = 0; u < DP_PT; ++u) val[u] += ad[u];
         }
-        __syncthreads();
+        lds_sync();
         for_elems([&](int u, int, int o) { B[o] = val[u]; });
-        __syncthreads();
+        lds_sync();
         // T = X S_x, written transposed (row c: an x mode, see xmode)
         if (fx) {   // rows y of block w, every x mode
             dst_f64x4 acc[4];
             dst_xform2<true>(B + (16 * w + r) * DP_LD, nx, gk, ex, acc);
-            __syncthreads();
+            lds_sync();
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -346,7 +351,7 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
                     acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(m, ox[kk], acc[a][1], 0, 0, 0);
                     if (a == 1 && (kk & 1)) __builtin_amdgcn_sched_barrier(0);   // bounds the reads in flight
                 }
-            __syncthreads();
+            lds_sync();
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -355,12 +360,12 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
                     for (int v = 0; v < 4; ++v)
                         B[(32 * par + 16 * hb + r) * DP_LD + 16 * (bp + a) + g + 4 * v] = acc[a][par][v];
         }
-        __syncthreads();
+        lds_sync();
         // Y = S_y T into B[y mode][x mode]
         if (fy) {   // rows c of block w, every y mode
             dst_f64x4 acc[4];
             dst_xform2<false>(B + (16 * w + r) * DP_LD, ny, gk, ey, acc);
-            __syncthreads();
+            lds_sync();
             const int xm = xmode(16 * w + r, Nxk);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -383,7 +388,7 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
                     acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(oy[kk], m, acc[a][1], 0, 0, 0);
                     if (a == 1 && (kk & 1)) __builtin_amdgcn_sched_barrier(0);
                 }
-            __syncthreads();
+            lds_sync();
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 const int xm = xmode(16 * (bp + a) + r, Nxk);
@@ -396,7 +401,7 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
                     }
             }
         }
-        __syncthreads();
+        lds_sync();
         for_elems([&](int, int e, int o) { out[zo + e] = B[o]; });
     }
 }
@@ -469,7 +474,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
                 val[u] = (cl && a < nz) ? in[off] : 0.0;
                 off += 4 * ncol;
             }
-            if (u0 == 0) __syncthreads();
+            if (u0 == 0) lds_sync();
 #pragma unroll
             for (int u = 0; u < LB; ++u) U[lc * DP_LD + la + 4 * (u0 + u)] = val[u];
         }
@@ -482,7 +487,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
             }
             lxy[threadIdx.x] = l;
         }
-        __syncthreads();
+        lds_sync();
         if constexpr (F2) {
             // forward, divided by the eigenvalue into the same row (mode j at
             // position j), inverse; the row is this lane's column
@@ -522,7 +527,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
                     acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(oz[kk], m, acc[a][1], 0, 0, 0);
                     if (a == 1 && (kk & 1)) __builtin_amdgcn_sched_barrier(0);
                 }
-            __syncthreads();
+            lds_sync();
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -530,7 +535,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
                         U[(16 * (bp + a) + r) * DP_LD + 2 * (16 * hb + g + 4 * v) + par] = acc[a][par][v];
-            __syncthreads();
+            lds_sync();
             // divide by the eigenvalue: wave w takes columns w + 4 u, lane the mode j
             if (lane < nz) {
 #pragma unroll 2
@@ -539,7 +544,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
                     if (c0 + cc < ncol) U[cc * DP_LD + lane] /= lxy[cc] + lzj;
                 }
             }
-            __syncthreads();
+            lds_sync();
 #pragma unroll
             for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = dst_f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(GM_BS) void k_gather_cart(ExxArgs a) {
                 red2[yg][0][lane] = s0;
                 red2[yg][1][lane] = s2;
             }
-            __syncthreads();
+            lds_sync();   // (not a fence: the stores of b need not complete here)
             const int q = 4 * ph + yg;
             int bb = 0, c = q;
             while (c > 6 - bb) {
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(GM_BS) void k_gather_cart(ExxArgs a) {
                     tot[GC_NM + 1] += S2;
                 }
             }
-            __syncthreads();
+            lds_sync();
         }
     }
     double* out = a.partial + ((size_t)pid * a.n_zchunks + zc) * GC_N;

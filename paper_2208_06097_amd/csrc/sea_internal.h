@@ -305,6 +305,10 @@ __host__ __device__ inline bool spectral_pair(const sea_pair& P) { return P.n[0]
 // continuations of the stencil reaches (index i of an axis of n points)
 constexpr int FF_W = 5;
 __host__ __device__ inline bool near_face(int i, int n) { return i < FF_W || i >= n - FF_W; }
+// LDS-only barrier: waits for this thread's LDS traffic, not for global loads
+// or stores in flight (which __syncthreads, a workgroup-scope fence, waits
+// for), then synchronizes the workgroup.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 // z-marching CG (k_cg.hip): needs every pair with n[0], n[1] <= 64.
 bool cg_zm_fits(const sea_pair* pairs, int n_pairs, const double* h);
 size_t cg_zm_lds_bytes(int state_f32);
