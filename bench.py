@@ -304,6 +304,9 @@ def main():
         dst_tune = ctx.spectral_autotune([(phi, cell.N, cell.L, pairs)], sample_pairs=args.tune_pairs, ws=ws)
         log(f"spectral autotune: {dst_tune['plane']} {dst_tune['zline']}  " +
             "  ".join(f"{k} {v:.2f} ms" for k, v in dst_tune["ms"].items()))
+    # the scatter's schedule (workgroup order); it writes W, which the steps overwrite
+    sc_tune = ctx.scatter_autotune([(phi, cell.N, cell.L, pairs, W)], ws=ws)
+    log(f"scatter autotune: {sc_tune['variant']}  " + "  ".join(f"{k} {v:.2f} ms" for k, v in sc_tune["ms"].items()))
 
     psi_step = psi.float()
 
@@ -559,6 +562,7 @@ def main():
                    "autotune_ms": tune["ms"] if tune else None,
                    "spectral_variants": {"plane": dst_tune["plane"], "zline": dst_tune["zline"],
                                          "tune_ms": dst_tune["ms"]} if dst_tune else None,
+                   "scatter_variant": {"variant": sc_tune["variant"], "tune_ms": sc_tune["ms"]},
                    "cg_iters_total": int(stats["iters"].sum())},
         "forms": forms,
         "ace_precision": ace,

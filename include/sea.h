@@ -287,6 +287,25 @@ const char *sea_spectral_variant_name(int variant);
  * variants, zline: index among the z-line variants; -1: the autotuner's
  * choice, else the first).  SEA_E_ARG out of range. */
 sea_status sea_set_spectral_variants(sea_ctx *ctx, int plane, int zline);
+/* Schedules of the owner-computes scatter of W (Eq. 13-14): the order in
+ * which its (orbital, tile) workgroups run, which sets what the GPU's L2
+ * caches share; every variant computes the same sums in the same order, so
+ * results do not depend on the choice.  Names for 0 .. count-1, NULL out of
+ * range. */
+int sea_scatter_variant_count(void);
+const char *sea_scatter_variant_name(int variant);
+/* Fixes the scatter schedule of a context (-1: the autotuner's choice,
+ * else the first).  SEA_E_ARG out of range. */
+sea_status sea_set_scatter_variant(sea_ctx *ctx, int variant);
+/* Autotuner of the scatter schedule: for these cells (every pair; pair
+ * potentials set to zero in the workspace, which must hold
+ * sea_exx_batched_workspace_bytes of the same cells), times one scatter of
+ * every variant with HIP events (the second of two launches) and keeps the
+ * fastest as the context's choice.  The cells' W_dev (required) are
+ * overwritten.  ms_host (sea_scatter_variant_count() floats, nullable)
+ * receives the times, *best (nullable) the chosen index.  Synchronizes. */
+sea_status sea_scatter_autotune(sea_ctx *ctx, int n_cells, const sea_cell *cells, void *ws_dev, size_t ws_bytes,
+                                float *ms_host, int *best);
 /* Per-pair residual histories (diagnostics of the Eq. 9 solves).  With
  * hist_dev set, every later exx call of this context writes, for pair k of
  * the call and iteration t = 0 .. len, the relative residual

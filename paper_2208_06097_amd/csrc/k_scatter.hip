@@ -22,24 +22,22 @@ constexpr int SC_BS = 256;
 constexpr int SC_MAXE = 128;   // list entries per chunk
 constexpr int SC_NM = 84;      // monomial coefficients of a pair's multipole sum
 
-// (orbital, tile) of this workgroup.  0: the tiles of one orbital in turn;
-// 1: the orbitals of one tile in turn; 2: as 1 within each XCD (workgroup k
-// runs on XCD k mod 8), which owns every eighth tile, so that the owners of
-// a tile share that XCD's L2 for the partner orbitals and pair potentials
-// they read there.  Measured on the 64-molecule cell: 4.80, 6.22 and 4.56
-// ms per launch; 2 is built (SEA_SCATTER_ORDER selects another).
-#ifndef SEA_SCATTER_ORDER
-#define SEA_SCATTER_ORDER 2
-#endif
-constexpr int SC_ORDER = SEA_SCATTER_ORDER;
+// (orbital, tile) of this workgroup, by the order of the workgroups (the
+// schedule; the autotuner's variants).  0: the tiles of one orbital in
+// turn; 1: the orbitals of one tile in turn; 2: as 1 within each XCD
+// (workgroup k runs on XCD k mod 8), which owns every eighth tile, so that
+// the owners of a tile share that XCD's L2 for the partner orbitals and pair
+// potentials they read there.  Measured on the 64-molecule cell: 4.80, 6.22
+// and 4.56 ms per launch; 0 and 2 are compiled.
 constexpr int SC_XCD = 8;
 
+template <int ORDER>
 __device__ __forceinline__ void sc_block(int n_tiles, int n_occ, int& o, int& t) {
     const int k = blockIdx.x;
-    if constexpr (SC_ORDER == 0) {
+    if constexpr (ORDER == 0) {
         t = k % n_tiles;
         o = k / n_tiles;
-    } else if constexpr (SC_ORDER == 1) {
+    } else if constexpr (ORDER == 1) {
         o = k % n_occ;
         t = k / n_occ;
     } else {
@@ -48,8 +46,8 @@ __device__ __forceinline__ void sc_block(int n_tiles, int n_occ, int& o, int& t)
         t = (m / n_occ) * SC_XCD + x;
     }
 }
-__host__ inline long sc_grid(int n_tiles, int n_occ) {
-    return SC_ORDER == 2 ? (long)((n_tiles + SC_XCD - 1) / SC_XCD) * SC_XCD * n_occ : (long)n_tiles * n_occ;
+__host__ inline long sc_grid(int order, int n_tiles, int n_occ) {
+    return order == 2 ? (long)((n_tiles + SC_XCD - 1) / SC_XCD) * SC_XCD * n_occ : (long)n_tiles * n_occ;
 }
 
 __device__ __forceinline__ bool axis_hits(int t0, int T, int lo, int n, int N) {
@@ -69,7 +67,7 @@ __device__ __forceinline__ bool axis_hits(int t0, int T, int lo, int n, int N) {
 // there) or is wider than the cell (points met several times); without it
 // every W box is its pair's domain, and the kernel carries neither path (nor
 // their registers).  PT: the orbitals' precision.
-template <bool GENERAL, typename PT>
+template <bool GENERAL, typename PT, int ORDER>
 __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const DevCell C, const int* __restrict__ off_all,
                                                    const int2* __restrict__ ent) {
     __shared__ int list[SC_MAXE];
@@ -90,7 +88,7 @@ __global__ __launch_bounds__(SC_BS) void k_scatter(ExxArgs a, const DevCell C, c
     const int tiles_y = (C.N[1] + SC_TY - 1) / SC_TY;
     const int n_tiles = tiles_x * tiles_y * ((C.N[2] + SC_TZ - 1) / SC_TZ);
     int o, t;
-    sc_block(n_tiles, C.n_occ, o, t);
+    sc_block<ORDER>(n_tiles, C.n_occ, o, t);
     if (t >= n_tiles) return;
     const int tx0 = (t % tiles_x) * SC_TX;
     const int ty0 = ((t / tiles_x) % tiles_y) * SC_TY;
@@ -344,19 +342,40 @@ hipError_t launch_epart_clear(const ExxArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const ExxArgs& a, const DevCell& cell, const int* csr_off, const int2* csr_ent, hipStream_t s) {
+namespace {
+using ScatterKernel = void (*)(ExxArgs, const DevCell, const int*, const int2*);
+struct ScatterVariant {
+    const char* name;
+    int order;
+    ScatterKernel k[2][2];   // [general W boxes][FP32 orbitals]
+};
+template <int ORDER>
+ScatterVariant scatter_variant(const char* name) {
+    return {name,
+            ORDER,
+            {{k_scatter<false, double, ORDER>, k_scatter<false, float, ORDER>},
+             {k_scatter<true, double, ORDER>, k_scatter<true, float, ORDER>}}};
+}
+const ScatterVariant kScatterVariants[] = {
+    scatter_variant<2>("scatter-xcd-owners"),
+    scatter_variant<0>("scatter-orbital-tiles"),
+};
+constexpr int kNumScatter = sizeof(kScatterVariants) / sizeof(kScatterVariants[0]);
+}  // namespace
+
+int scatter_variant_count() { return kNumScatter; }
+const char* scatter_variant_name(int v) { return v >= 0 && v < kNumScatter ? kScatterVariants[v].name : nullptr; }
+
+hipError_t launch_scatter(const ExxArgs& a, const DevCell& cell, const int* csr_off, const int2* csr_ent, int variant,
+                          hipStream_t s) {
+    if (variant < 0 || variant >= kNumScatter) return hipErrorInvalidValue;
+    const ScatterVariant& V = kScatterVariants[variant];
     const int* N = cell.N;
     const int tiles = ((N[0] + SC_TX - 1) / SC_TX) * ((N[1] + SC_TY - 1) / SC_TY) * ((N[2] + SC_TZ - 1) / SC_TZ);
-    const long nb = sc_grid(tiles, cell.n_occ);
+    const long nb = sc_grid(V.order, tiles, cell.n_occ);
     if (nb > 0x7fffffffL) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)nb);
-    if (cell.wbox_general) {
-        if (cell.phi_f32) hipLaunchKernelGGL((k_scatter<true, float>), grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
-        else hipLaunchKernelGGL((k_scatter<true, double>), grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
-    } else {
-        if (cell.phi_f32) hipLaunchKernelGGL((k_scatter<false, float>), grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
-        else hipLaunchKernelGGL((k_scatter<false, double>), grid, dim3(SC_BS), 0, s, a, cell, csr_off, csr_ent);
-    }
+    hipLaunchKernelGGL(V.k[cell.wbox_general ? 1 : 0][cell.phi_f32 ? 1 : 0], dim3((unsigned)nb), dim3(SC_BS), 0, s, a,
+                       cell, csr_off, csr_ent);
     return hipGetLastError();
 }
 

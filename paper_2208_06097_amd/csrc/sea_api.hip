@@ -115,6 +115,12 @@ static void dst_variants(const sea_ctx* ctx, int& pv, int& zv) {
     if (zv >= nzv) zv = 0;
 }
 
+// the scatter's schedule: the fixed one, else the autotuner's, else the first
+static int scatter_variant(const sea_ctx* ctx) {
+    const int v = ctx->scatter_fixed >= 0 ? ctx->scatter_fixed : (ctx->scatter_tuned >= 0 ? ctx->scatter_tuned : 0);
+    return v < scatter_variant_count() ? v : 0;
+}
+
 static sea_status build_cellset(sea_ctx* ctx, int n_cells, const sea_cell* cells, bool action, CellSet& S) {
     if (n_cells < 1 || !cells) return fail(ctx, SEA_E_ARG, "need n_cells >= 1 and a cell array");
     S = CellSet{};
@@ -785,7 +791,7 @@ static sea_status exx_enqueue(sea_ctx* ctx, const CellSet& S, const ExxLayout& L
         if (ae.epart) SEA_HIP_CHECK(ctx, launch_epart_clear(ae, s));
         for (size_t c = 0; c < S.cells.size(); ++c)
             SEA_HIP_CHECK(ctx, launch_scatter(ae, S.dev[c], (const int*)(base + Ly.csr_off),
-                                              (const int2*)(base + Ly.csr_ent), s));
+                                              (const int2*)(base + Ly.csr_ent), scatter_variant(ctx), s));
         timer_off(SEA_STAGE_SCATTER);
         if (finish && n_pairs > 0) {   // without ae.epart the finish sums rho x itself
             timer_on(SEA_STAGE_FINISH);
@@ -1560,6 +1566,18 @@ extern "C" sea_status sea_set_residual_history(sea_ctx* ctx, double* hist_dev, i
     return SEA_OK;
 }
 
+extern "C" int sea_scatter_variant_count(void) { return scatter_variant_count(); }
+
+extern "C" const char* sea_scatter_variant_name(int v) { return scatter_variant_name(v); }
+
+extern "C" sea_status sea_set_scatter_variant(sea_ctx* ctx, int variant) {
+    if (!ctx) return SEA_E_ARG;
+    if (variant < -1 || variant >= scatter_variant_count())
+        return fail(ctx, SEA_E_ARG, "scatter variant %d out of range (%d variants)", variant, scatter_variant_count());
+    ctx->scatter_fixed = variant;
+    return SEA_OK;
+}
+
 extern "C" sea_status sea_set_spectral_variants(sea_ctx* ctx, int plane, int zline) {
     if (!ctx) return SEA_E_ARG;
     const int np = dst_plane_variant_count(), nzv = dst_variant_count() - np;
@@ -1657,6 +1675,64 @@ extern "C" sea_status sea_spectral_autotune(sea_ctx* ctx, int n_cells, const sea
     ctx->dst_zline_tuned = bz;
     if (best_plane) *best_plane = bp;
     if (best_zline) *best_zline = bz;
+    return SEA_OK;
+}
+
+extern "C" sea_status sea_scatter_autotune(sea_ctx* ctx, int n_cells, const sea_cell* cells, void* ws_dev,
+                                           size_t ws_bytes, float* ms_host, int* best) {
+    if (!ctx) return SEA_E_ARG;
+    if (!ws_dev) return fail(ctx, SEA_E_ARG, "workspace is NULL");
+    if (n_cells < 1 || !cells) return fail(ctx, SEA_E_ARG, "need n_cells >= 1 and a cell array");
+    CellSet S;
+    sea_status st = build_cellset(ctx, n_cells, cells, true, S);   // (the scatter writes W)
+    if (st != SEA_OK) return st;
+    if (S.pairs.empty()) return fail(ctx, SEA_E_ARG, "no pairs to tune on");
+    const ExxLayout Ly = exx_layout(ctx, S, true);
+    if (ws_bytes < Ly.total) return fail(ctx, SEA_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, Ly.total);
+    hipStream_t s = (hipStream_t)ctx->opts.hip_stream;
+    char* base = (char*)ws_dev;
+    st = exx_upload(ctx, S, Ly, base, s);
+    if (st != SEA_OK) return st;
+    ExxArgs a = exx_args(ctx, S, Ly, base, nullptr);
+    // pair potentials of zero (the scatter's time does not depend on them),
+    // and the pair energies' partials when the action takes them there
+    SEA_HIP_CHECK(ctx, hipMemsetAsync(a.v, 0, sizeof(double) * a.stride * S.pairs.size(), s));
+    bool lists_fit = true;
+    for (size_t k = 0; k + 1 < S.csr_off.size(); ++k) lists_fit = lists_fit && S.csr_off[k + 1] - S.csr_off[k] <= SC_EP_MAXE;
+    if (lists_fit) a.epart = (double*)(base + Ly.epart);
+    hipEvent_t e0, e1;
+    SEA_HIP_CHECK(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, SEA_E_HIP, "event creation failed");
+    }
+    const int nv = scatter_variant_count();
+    int arg = 0;
+    float tbest = 0.0f;
+    hipError_t err = hipSuccess;
+    for (int v = 0; v < nv && err == hipSuccess; ++v) {
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {   // rep 0 warms the code object
+            err = hipEventRecord(e0, s);
+            if (err == hipSuccess && a.epart) err = launch_epart_clear(a, s);
+            for (size_t c = 0; c < S.cells.size() && err == hipSuccess; ++c)
+                err = launch_scatter(a, S.dev[c], (const int*)(base + Ly.csr_off), (const int2*)(base + Ly.csr_ent), v,
+                                     s);
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (ms_host) ms_host[v] = ms;
+        if (v == 0 || ms < tbest) {
+            tbest = ms;
+            arg = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(ctx, SEA_E_HIP, "scatter autotune: %s", hipGetErrorString(err));
+    ctx->scatter_tuned = arg;
+    if (best) *best = arg;
     return SEA_OK;
 }
 

@@ -43,6 +43,7 @@ struct sea_ctx {
     // and a fixed choice (-1: none; the fixed one wins)
     int dst_plane_tuned = -1, dst_zline_tuned = -1;
     int dst_plane_fixed = -1, dst_zline_fixed = -1;
+    int scatter_tuned = -1, scatter_fixed = -1;
     // per-pair residual histories (caller's device buffer; nullptr: off)
     double* hist = nullptr;
     int hist_len = 0;
@@ -320,7 +321,10 @@ int cg_variant_count();
 const char* cg_variant_name(int v);
 hipError_t launch_cg_zm(const ExxArgs& a, int variant, hipStream_t s);
 hipError_t launch_cg_finish(const ExxArgs& a, hipStream_t s);
-hipError_t launch_scatter(const ExxArgs& a, const DevCell& cell, const int* csr_off, const int2* csr_ent,
+// the scatter's compiled schedules (workgroup orders), the autotuner's choices
+int scatter_variant_count();
+const char* scatter_variant_name(int v);
+hipError_t launch_scatter(const ExxArgs& a, const DevCell& cell, const int* csr_off, const int2* csr_ent, int variant,
                           hipStream_t s);
 // zeroes a.epart (every slot the scatter does not write must read zero)
 hipError_t launch_epart_clear(const ExxArgs& a, hipStream_t s);

@@ -36,7 +36,8 @@ EXPORTS = [
     "sea_successive_idempotency", "sea_scdm_workspace_bytes", "sea_scdm", "sea_rotate",
     "sea_ace_apply_noalloc", "sea_spectral_variant_count", "sea_spectral_variant_name",
     "sea_set_spectral_variants", "sea_spectral_autotune", "sea_exx_plan_workspace_bytes",
-    "sea_set_residual_history",
+    "sea_set_residual_history", "sea_scatter_variant_count", "sea_scatter_variant_name",
+    "sea_set_scatter_variant", "sea_scatter_autotune",
 ]
 
 # size of the library's static scratch array per GPU (SEA_NOALLOC_SCRATCH_BYTES
@@ -165,6 +166,12 @@ def load() -> C.CDLL:
     lib.sea_set_spectral_variants.argtypes = [vp, i, i]
     lib.sea_set_residual_history.argtypes = [vp, vp, i]
     lib.sea_spectral_autotune.argtypes = [vp, i, vp, vp, sz, i, vp, P(i), P(i)]
+    lib.sea_scatter_variant_count.argtypes = []
+    lib.sea_scatter_variant_count.restype = i
+    lib.sea_scatter_variant_name.argtypes = [i]
+    lib.sea_scatter_variant_name.restype = C.c_char_p
+    lib.sea_set_scatter_variant.argtypes = [vp, i]
+    lib.sea_scatter_autotune.argtypes = [vp, i, vp, vp, sz, vp, P(i)]
     lib.sea_nn_infer_workspace_bytes.argtypes = [vp, i, P(sz)]
     lib.sea_nn_infer.argtypes = [vp, vp, i, vp, vp, vp, sz]
     lib.sea_eps_workspace_bytes.argtypes = [vp, P(SeaGrid), i, P(sz)]
@@ -431,6 +438,31 @@ class Context:
         plane = pn.index(plane) if isinstance(plane, str) else plane
         zline = zn.index(zline) if isinstance(zline, str) else zline
         self._check(self.lib.sea_set_spectral_variants(self.h, int(plane), int(zline)))
+
+    def scatter_variants(self):
+        """Names of the scatter's schedules (workgroup orders)."""
+        return [self.lib.sea_scatter_variant_name(v).decode() for v in range(self.lib.sea_scatter_variant_count())]
+
+    def set_scatter_variant(self, variant=-1):
+        """Fix the scatter schedule (index or name; -1: the tuned choice)."""
+        names = self.scatter_variants()
+        variant = names.index(variant) if isinstance(variant, str) else variant
+        self._check(self.lib.sea_set_scatter_variant(self.h, int(variant)))
+
+    def scatter_autotune(self, cells, ws=None):
+        """Time one scatter of every schedule on these cells and keep the
+        fastest.  The cells' W (allocated where None) are overwritten.
+        Returns {"variant": name, "ms": {name: ms}}."""
+        names = self.scatter_variants()
+        arr, Ws, keep = self._cells(cells, need_W=True)
+        if ws is None:
+            ws = self.workspace(self.exx_batched_workspace_bytes(cells))
+        ms = np.zeros(len(names), dtype=np.float32)
+        best = C.c_int(-1)
+        self._check(self.lib.sea_scatter_autotune(self.h, len(cells), arr, ws.data_ptr(), ws.numel(), ms.ctypes.data,
+                                                  C.byref(best)))
+        self.set_scatter_variant(-1)
+        return {"variant": names[best.value], "ms": {n: float(t) for n, t in zip(names, ms)}}
 
     def residual_history(self, n_pairs, length):
         """Turns on per-pair residual histories for the next exx calls and

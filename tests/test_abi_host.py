@@ -38,6 +38,23 @@ def test_stage_names_cover_the_stage_enum():
     assert len(sea.STAGES) == count
 
 
+def test_kernel_variant_names():
+    """The schedule and kernel variants the autotuners choose among have
+    distinct names, NULL past the end (host code only)."""
+    lib = ctypes.CDLL(sea.LIB_PATH)
+    for count, name in (("sea_scatter_variant_count", "sea_scatter_variant_name"),
+                        ("sea_spectral_variant_count", "sea_spectral_variant_name"),
+                        ("sea_cg_variant_count", "sea_cg_variant_name")):
+        getattr(lib, count).restype = ctypes.c_int
+        getattr(lib, name).restype = ctypes.c_char_p
+        getattr(lib, name).argtypes = [ctypes.c_int]
+        n = getattr(lib, count)()
+        assert n >= 2, count
+        names = [getattr(lib, name)(v) for v in range(n)]
+        assert all(names) and len(set(names)) == n, names
+        assert getattr(lib, name)(n) is None and getattr(lib, name)(-1) is None
+
+
 def test_struct_layouts():
     assert sea.PAIR_DTYPE.itemsize == 56
     assert sea.STAT_DTYPE.itemsize == 40

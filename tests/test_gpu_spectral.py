@@ -388,6 +388,36 @@ def test_spectral_variants_give_identical_results():
     ctx.close()
 
 
+def test_scatter_autotune_picks_the_fastest_and_schedules_agree():
+    """The scatter's schedules (workgroup orders) compute the same sums in
+    the same order: W, E and every pair's statistics equal bit for bit
+    whichever runs; the autotuner keeps the one with the least measured
+    time (8-molecule cell, FP32 state, spectral start)."""
+    cell = synth.config1()
+    pairs = sea.build_pairs(cell.N, cell.L, cell.centres, 6.0, 6.0)
+    phi = torch.from_numpy(cell.phi).cuda()
+    ctx = _ctx(rel_tol=1e-8, stencil_dtype=sea.SEA_F32, start=sea.SEA_START_SPECTRAL)
+    names = ctx.scatter_variants()
+    assert len(names) >= 2
+    res = []
+    for v in names:
+        print(f"case scatter schedule {v}", flush=True)
+        ctx.set_scatter_variant(v)
+        W, E, st_, s = ctx.exx_action(phi, cell.N, cell.L, pairs)
+        assert s == sea.SEA_OK
+        res.append((W.clone(), E, st_))
+    for W, E, st_ in res[1:]:
+        assert E == res[0][1] and torch.equal(W, res[0][0]) and np.array_equal(st_, res[0][2])
+    ctx.set_scatter_variant(-1)
+    r = ctx.scatter_autotune([(phi, cell.N, cell.L, pairs)])
+    print(f"scatter autotune: {r}", flush=True)
+    assert all(r["ms"][n] > 0 for n in names)
+    assert r["variant"] == min(names, key=lambda n: r["ms"][n])
+    W, E, st_, s = ctx.exx_action(phi, cell.N, cell.L, pairs)
+    assert s == sea.SEA_OK and E == res[0][1] and torch.equal(W, res[0][0])
+    ctx.close()
+
+
 def test_spectral_autotune_picks_the_fastest_and_caches(tmp_path):
     """The transform autotuner keeps, per kernel, the variant with the least
     measured time, and a cached choice is reused without timing."""
