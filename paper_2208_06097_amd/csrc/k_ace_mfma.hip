@@ -7,6 +7,8 @@
 //                 slices in FP64 (M = dV Phi^T W, dV xi^T psi, dV Phi^T xi).
 //   NN (small K): C = alpha A B, A: m x K (FP64, small), B: K x ncol,
 //                 ncol = grid points (xi = L^-1 W, K psi = -C^T xi).
+//                 Persistent workgroups walk the column tiles with the
+//                 next tile's first K stage loaded during the last stage.
 //
 // Operand kinds: FP64 -> v_mfma_f64_16x16x4f64 (FP64 accumulation);
 // FP32 -> v_mfma_f32_16x16x4f32 and BF16 -> v_mfma_f32_16x16x32_bf16, both
@@ -19,6 +21,7 @@
 // Result lanes: column = lane % 16; the row of item v is 4 (lane / 16) + v
 // for the FP32-accumulating instructions and lane / 16 + 4 v for the FP64
 // one (measured on gfx950).
+#include <algorithm>
 #include <type_traits>
 
 #include "k_ace.h"
@@ -248,68 +251,108 @@ __device__ __forceinline__ float store_as<float>(double v) { return (float)v; }
 template <>
 __device__ __forceinline__ uint16_t store_as<uint16_t>(double v) { return f_to_bf((float)v); }
 
+// Persistent: `slots` workgroups per (XCD, row block), all resident at once.
+// Workgroup k runs on XCD x = k % 8; with q = k / 8 it takes row block
+// q % (row blocks) and slot s = q / (row blocks), and walks the column tiles
+// jt = (s + i slots) 8 + x, i = 0, 1, ..., so that the row blocks of one
+// column tile run together on one XCD (the second read of the tile comes
+// from that L2).  The first K stage of the next column tile is loaded
+// during the last stage of the current one: the pipeline does not drain
+// between tiles (K is short here: the orbital count).
+//
+// Two workgroups per CU asked of the compiler: it then keeps the
+// accumulators in VGPRs within 256 registers (the FP64 kind otherwise
+// takes 194 VGPRs + 128 AGPRs and runs one workgroup per CU); three spill.
 template <int KIND, typename TB, typename TC>
-__global__ __launch_bounds__(NT) void k_nn_mfma(const double* __restrict__ A, long sai, long sak,
+__global__ __launch_bounds__(NT, 2) void k_nn_mfma(const double* __restrict__ A, long sai, long sak,
                                                 const TB* __restrict__ B, int m, int K, long ncol, double alpha,
-                                                TC* __restrict__ C) {
+                                                TC* __restrict__ C, int slots) {
     using Kd = Kind<KIND>;
     using E = typename Kd::E;
     constexpr int KT = Kd::KT;
     __shared__ __attribute__((aligned(16))) E As[BM * Kd::PITCH];
     __shared__ __attribute__((aligned(16))) E Bs[BN * Kd::PITCH];
-    // group: column tile of B; member: row block
-    long jt;
-    int ib;
-    xcd_block((m + BM - 1) / BM, jt, ib);
-    const long j0 = jt * BN;
-    if (j0 >= ncol) return;   // padding of the last XCD round
-    const int i0 = ib * BM;
+    const int per = (m + BM - 1) / BM;
+    const int x = blockIdx.x % ACE_XCD, mseq = blockIdx.x / ACE_XCD;
+    const int i0 = (mseq % per) * BM;
+    const long ntile = (ncol + BN - 1) / BN, jstep = (long)slots * ACE_XCD;
+    long jt = (long)(mseq / per) * ACE_XCD + x;
+    if (jt >= ntile) return;
+    const int nst = K > 0 ? (K + KT - 1) / KT : 1;   // K = 0: one stage of zeros
     typename Kd::Acc acc[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[p][q] = typename Kd::Acc{0, 0, 0, 0};
-    // Same pipeline as the NT kernel.  A (small, cache-resident): row
+    // Same stage layout as the NT kernel.  A (small, cache-resident): row
     // idx / KT, k idx % KT; B: 128 consecutive threads read one grid row.
     constexpr int PER = BM * KT / NT;
     double ra[PER];
     TB rb[PER];
-    auto load = [&](int k0) {
+    // Element e of a thread: A row rr0 + e NT/KT, k kk; B row kr0 + e NT/BN,
+    // column jj.  Its address is a uniform base for (stage, e) plus a 32-bit
+    // offset of the thread's own (the same for every e); the thread index is
+    // taken opaque in each call, so that nothing of it is held in registers
+    // across the tile loop.
+    auto load = [&](long j0, int k0) {
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        const int rr0 = t / KT, kk = t % KT, kr0 = t / BN, jj = t % BN;
+        const int oa = rr0 * (int)sai + kk * (int)sak, ob = kr0 * (int)ncol + jj;
+        const int kl = K - k0, il = m - i0;
+        const long jl = ncol - j0;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            const int idx = threadIdx.x + NT * e;
-            const int rr = idx / KT, kk = idx % KT;
-            ra[e] = (i0 + rr < m && k0 + kk < K) ? A[(i0 + rr) * sai + (long)(k0 + kk) * sak] : 0.0;
-            const int jj = idx % BN, kr = idx / BN;
-            const long j = j0 + jj;
-            rb[e] = (j < ncol && k0 + kr < K) ? B[(size_t)(k0 + kr) * ncol + j] : TB(0);
+            const double* __restrict__ Ae = A + i0 * sai + (long)k0 * sak + (long)e * (NT / KT) * sai;
+            const TB* __restrict__ Be = B + (size_t)(k0 + e * (NT / BN)) * ncol + j0;
+            ra[e] = (rr0 + e * (NT / KT) < il && kk < kl) ? Ae[oa] : 0.0;
+            rb[e] = (jj < jl && kr0 + e * (NT / BN) < kl) ? Be[ob] : TB(0);
         }
     };
-    load(0);
-    for (int k0 = 0; k0 < K; k0 += KT) {
-        __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    load(jt * BN, 0);
+    for (int st = 0;;) {
+        // LDS-only barriers: the loads in flight cross them (their
+        // registers are waited for where they are staged)
+        lds_sync();
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = threadIdx.x + NT * e;
             As[(idx / KT) * Kd::PITCH + idx % KT] = Kd::cvt(ra[e]);
             Bs[(idx % BN) * Kd::PITCH + idx / BN] = Kd::cvt(rb[e]);
         }
-        __syncthreads();
-        if (k0 + KT < K) load(k0 + KT);
+        lds_sync();
+        long jn = jt;
+        int sn = st + 1;
+        if (sn == nst) {
+            sn = 0;
+            jn = jt + jstep;
+        }
+        if (jn < ntile) load(jn * BN, sn * KT);
         tile_mma<KIND, std::is_same<TB, double>::value>(As, Bs, acc);
+        if (sn == 0) {
+            int lane = threadIdx.x & 63;
+            asm volatile("" : "+v"(lane));
+            const int ib = i0 + wm * 64, il = m - ib;
+            const long jb = jt * BN + wn * 64, jl = ncol - jb;
+            TC* __restrict__ Cb = C + (size_t)ib * ncol + jb;
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = p * 16 + Kd::row(lane >> 4, v), j = q * 16 + (lane & 15);
+                        if (i < il && j < jl) Cb[(size_t)i * ncol + j] = store_as<TC>(alpha * (double)acc[p][q][v]);
+                    }
+                    acc[p][q] = typename Kd::Acc{0, 0, 0, 0};
+                }
+            if (jn >= ntile) break;
+        }
+        jt = jn;
+        st = sn;
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = i0 + wm * 64 + p * 16 + Kd::row(lane >> 4, v);
-                const long j = j0 + wn * 64 + q * 16 + (lane & 15);
-                if (i < m && j < ncol) C[(size_t)i * ncol + j] = store_as<TC>(alpha * (double)acc[p][q][v]);
-            }
 }
 
 }  // namespace
@@ -345,10 +388,33 @@ hipError_t ace_mm_nt(const TA* A, const TB* B, int m, int n, long K, double alph
 template <int KIND, typename TB, typename TC>
 hipError_t ace_mm_nn(const double* A, long sai, long sak, const TB* B, int m, int K, long ncol, double alpha, TC* C,
                      hipStream_t s) {
-    const long nb = xcd_grid((ncol + BN - 1) / BN, (m + BM - 1) / BM);
+    if (m <= 0 || ncol <= 0) return hipSuccess;
+    // resident workgroups per CU of this instantiation and the CU count, once
+    static int occ = 0, n_cu = 0;
+    if (occ <= 0) {
+        int dev = 0, o = 0, c = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_nn_mfma<KIND, TB, TC>, NT, 0);
+        if (e != hipSuccess) return e;
+        if (o < 1 || c < 1) return hipErrorInvalidValue;
+        n_cu = c;
+        occ = o;
+    }
+    const int per = (m + BM - 1) / BM;
+    const long ntile = (ncol + BN - 1) / BN;
+    // as many slots as stay resident (at least one), no more than the tiles need
+    long slots = (long)n_cu * occ / ((long)ACE_XCD * per);
+    slots = std::max(1L, std::min(slots, (ntile + ACE_XCD - 1) / ACE_XCD));
+    const long nb = slots * ACE_XCD * per;
     if (nb > 0x7fffffffL) return hipErrorInvalidValue;
+    // a thread's 32-bit offsets: A rows below NT / KT, k below KT; B rows 0, 1
+    constexpr int KT = Kind<KIND>::KT;
+    if (sai < 0 || sak < 0 || (long)(NT / KT) * sai + (long)KT * sak >= 0x7fffffffL ||
+        2 * ncol + BN >= 0x7fffffffL)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_nn_mfma<KIND, TB, TC>), dim3((unsigned)nb), dim3(NT), 0, s, A, sai, sak, B, m, K, ncol, alpha,
-                       C);
+                       C, (int)slots);
     return hipGetLastError();
 }
 
