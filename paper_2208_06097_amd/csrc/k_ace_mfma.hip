@@ -124,7 +124,7 @@ struct Kind<ACE_BF16> {
 
 // Multiply the staged tiles: wave (wm, wn) = (wave / 2, wave % 2) owns rows
 // wm*64.., cols wn*64..
-template <int KIND>
+template <int KIND, int PITCH = Kind<KIND>::PITCH>
 __device__ __forceinline__ void tile_step(const typename Kind<KIND>::E* As, const typename Kind<KIND>::E* Bs, int kk,
                                           typename Kind<KIND>::Acc (&acc)[4][4]) {
     using K = Kind<KIND>;
@@ -133,10 +133,10 @@ __device__ __forceinline__ void tile_step(const typename Kind<KIND>::E* As, cons
     const int r = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-        const typename K::E* a = As + (wm * 64 + p * 16 + r) * K::PITCH + kk;
+        const typename K::E* a = As + (wm * 64 + p * 16 + r) * PITCH + kk;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const typename K::E* b = Bs + (wn * 64 + q * 16 + r) * K::PITCH + kk;
+            const typename K::E* b = Bs + (wn * 64 + q * 16 + r) * PITCH + kk;
             acc[p][q] = K::mma(a, b, g, acc[p][q]);
         }
     }
@@ -144,17 +144,18 @@ __device__ __forceinline__ void tile_step(const typename Kind<KIND>::E* As, cons
 
 // FEW: two k steps at a time, so that only their operands (4 A and 4 B per
 // step) are LDS reads in flight, which saves registers for occupancy; else
-// the whole stage unrolled (measured faster where occupancy does not change)
-template <int KIND, bool FEW>
+// the whole stage unrolled (measured faster where occupancy does not change).
+// KT, PITCH: the stage depth and LDS row pitch, if not the kind's own.
+template <int KIND, bool FEW, int KT = Kind<KIND>::KT, int PITCH = Kind<KIND>::PITCH>
 __device__ __forceinline__ void tile_mma(const typename Kind<KIND>::E* As, const typename Kind<KIND>::E* Bs,
                                          typename Kind<KIND>::Acc (&acc)[4][4]) {
     using K = Kind<KIND>;
     if constexpr (FEW) {
 #pragma unroll 2
-        for (int kk = 0; kk < K::KT; kk += K::KSTEP) tile_step<KIND>(As, Bs, kk, acc);
+        for (int kk = 0; kk < KT; kk += K::KSTEP) tile_step<KIND, PITCH>(As, Bs, kk, acc);
     } else {
 #pragma unroll
-        for (int kk = 0; kk < K::KT; kk += K::KSTEP) tile_step<KIND>(As, Bs, kk, acc);
+        for (int kk = 0; kk < KT; kk += K::KSTEP) tile_step<KIND, PITCH>(As, Bs, kk, acc);
     }
 }
 
@@ -263,15 +264,27 @@ __device__ __forceinline__ uint16_t store_as<uint16_t>(double v) { return f_to_b
 // Two workgroups per CU asked of the compiler: it then keeps the
 // accumulators in VGPRs within 256 registers (the FP64 kind otherwise
 // takes 194 VGPRs + 128 AGPRs and runs one workgroup per CU); three spill.
+#ifndef SEA_NN32_KT
+#define SEA_NN32_KT 16
+#endif
+#ifndef SEA_NN32_MINB
+#define SEA_NN32_MINB 3
+#endif
+template <int KIND>
+constexpr int nn_kt() { return KIND == ACE_F32 ? SEA_NN32_KT : Kind<KIND>::KT; }
+template <int KIND>
+constexpr int nn_pitch() { return nn_kt<KIND>() == Kind<KIND>::KT ? Kind<KIND>::PITCH : nn_kt<KIND>() + 1; }
+template <int KIND>
+constexpr int nn_minb() { return KIND == ACE_F32 ? SEA_NN32_MINB : 2; }
 template <int KIND, typename TB, typename TC>
-__global__ __launch_bounds__(NT, 2) void k_nn_mfma(const double* __restrict__ A, long sai, long sak,
+__global__ __launch_bounds__(NT, nn_minb<KIND>()) void k_nn_mfma(const double* __restrict__ A, long sai, long sak,
                                                 const TB* __restrict__ B, int m, int K, long ncol, double alpha,
                                                 TC* __restrict__ C, int slots) {
     using Kd = Kind<KIND>;
     using E = typename Kd::E;
-    constexpr int KT = Kd::KT;
-    __shared__ __attribute__((aligned(16))) E As[BM * Kd::PITCH];
-    __shared__ __attribute__((aligned(16))) E Bs[BN * Kd::PITCH];
+    constexpr int KT = nn_kt<KIND>(), PITCH = nn_pitch<KIND>();
+    __shared__ __attribute__((aligned(16))) E As[BM * PITCH];
+    __shared__ __attribute__((aligned(16))) E Bs[BN * PITCH];
     const int per = (m + BM - 1) / BM;
     const int x = blockIdx.x % ACE_XCD, mseq = blockIdx.x / ACE_XCD;
     const int i0 = (mseq % per) * BM;
@@ -319,8 +332,8 @@ __global__ __launch_bounds__(NT, 2) void k_nn_mfma(const double* __restrict__ A,
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = threadIdx.x + NT * e;
-            As[(idx / KT) * Kd::PITCH + idx % KT] = Kd::cvt(ra[e]);
-            Bs[(idx % BN) * Kd::PITCH + idx / BN] = Kd::cvt(rb[e]);
+            As[(idx / KT) * PITCH + idx % KT] = Kd::cvt(ra[e]);
+            Bs[(idx % BN) * PITCH + idx / BN] = Kd::cvt(rb[e]);
         }
         lds_sync();
         long jn = jt;
@@ -330,7 +343,7 @@ __global__ __launch_bounds__(NT, 2) void k_nn_mfma(const double* __restrict__ A,
             jn = jt + jstep;
         }
         if (jn < ntile) load(jn * BN, sn * KT);
-        tile_mma<KIND, std::is_same<TB, double>::value>(As, Bs, acc);
+        tile_mma<KIND, std::is_same<TB, double>::value, KT, PITCH>(As, Bs, acc);
         if (sn == 0) {
             int lane = threadIdx.x & 63;
             asm volatile("" : "+v"(lane));
@@ -409,7 +422,7 @@ hipError_t ace_mm_nn(const double* A, long sai, long sak, const TB* B, int m, in
     const long nb = slots * ACE_XCD * per;
     if (nb > 0x7fffffffL) return hipErrorInvalidValue;
     // a thread's 32-bit offsets: A rows below NT / KT, k below KT; B rows 0, 1
-    constexpr int KT = Kind<KIND>::KT;
+    constexpr int KT = nn_kt<KIND>();
     if (sai < 0 || sak < 0 || (long)(NT / KT) * sai + (long)KT * sak >= 0x7fffffffL ||
         2 * ncol + BN >= 0x7fffffffL)
         return hipErrorInvalidValue;
