@@ -16,7 +16,8 @@
 // type are rounded to the operand kind while they are staged in LDS.
 //
 // Tiling: 256 threads, a 128 x 128 output block, four wavefronts of 64 x 64
-// (4 x 4 tiles of 16 x 16), K staged 32 at a time as [row][k] in LDS.
+// (4 x 4 tiles of 16 x 16), K staged as [row][k] in LDS (FP64 16 at a time,
+// FP32 32 at a time in the NT product and 16 in the NN one, BF16 32).
 // Operand lanes: A row = lane % 16, B column = lane % 16, k block = lane / 16.
 // Result lanes: column = lane % 16; the row of item v is 4 (lane / 16) + v
 // for the FP32-accumulating instructions and lane / 16 + 4 v for the FP64
@@ -261,21 +262,16 @@ __device__ __forceinline__ uint16_t store_as<uint16_t>(double v) { return f_to_b
 // during the last stage of the current one: the pipeline does not drain
 // between tiles (K is short here: the orbital count).
 //
-// Two workgroups per CU asked of the compiler: it then keeps the
-// accumulators in VGPRs within 256 registers (the FP64 kind otherwise
-// takes 194 VGPRs + 128 AGPRs and runs one workgroup per CU); three spill.
-#ifndef SEA_NN32_KT
-#define SEA_NN32_KT 16
-#endif
-#ifndef SEA_NN32_MINB
-#define SEA_NN32_MINB 3
-#endif
+// Workgroups per CU asked of the compiler, which then keeps the
+// accumulators in VGPRs: FP64 and BF16 two (the FP64 kind otherwise takes
+// 194 VGPRs + 128 AGPRs and runs one workgroup per CU; three spill); FP32
+// three, with K staged 16 at a time (32 at a time spills at three).
 template <int KIND>
-constexpr int nn_kt() { return KIND == ACE_F32 ? SEA_NN32_KT : Kind<KIND>::KT; }
+constexpr int nn_kt() { return KIND == ACE_F32 ? 16 : Kind<KIND>::KT; }
 template <int KIND>
 constexpr int nn_pitch() { return nn_kt<KIND>() == Kind<KIND>::KT ? Kind<KIND>::PITCH : nn_kt<KIND>() + 1; }
 template <int KIND>
-constexpr int nn_minb() { return KIND == ACE_F32 ? SEA_NN32_MINB : 2; }
+constexpr int nn_minb() { return KIND == ACE_F32 ? 3 : 2; }
 template <int KIND, typename TB, typename TC>
 __global__ __launch_bounds__(NT, nn_minb<KIND>()) void k_nn_mfma(const double* __restrict__ A, long sai, long sak,
                                                 const TB* __restrict__ B, int m, int K, long ncol, double alpha,
