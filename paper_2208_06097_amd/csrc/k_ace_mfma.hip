@@ -398,18 +398,22 @@ template <int KIND, typename TB, typename TC>
 hipError_t ace_mm_nn(const double* A, long sai, long sak, const TB* B, int m, int K, long ncol, double alpha, TC* C,
                      hipStream_t s) {
     if (m <= 0 || ncol <= 0) return hipSuccess;
-    // resident workgroups per CU of this instantiation and the CU count, once
-    static int occ = 0, n_cu = 0;
-    if (occ <= 0) {
+    // resident workgroups per CU of this instantiation and the CU count,
+    // queried once per process (a thread-safe static initialization)
+    struct Fill {
+        hipError_t err;
+        int occ, n_cu;
+    };
+    static const Fill fill = [] {
         int dev = 0, o = 0, c = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_nn_mfma<KIND, TB, TC>, NT, 0);
-        if (e != hipSuccess) return e;
-        if (o < 1 || c < 1) return hipErrorInvalidValue;
-        n_cu = c;
-        occ = o;
-    }
+        if (e == hipSuccess && (o < 1 || c < 1)) e = hipErrorInvalidValue;
+        return Fill{e, o, c};
+    }();
+    if (fill.err != hipSuccess) return fill.err;
+    const int occ = fill.occ, n_cu = fill.n_cu;
     const int per = (m + BM - 1) / BM;
     const long ntile = (ncol + BN - 1) / BN;
     // as many slots as stay resident (at least one), no more than the tiles need
