@@ -235,7 +235,10 @@ def test_ace_matrix_core_dtypes_multi_tile(dt):
 def test_ace_cholesky_blocked_sizes(n_occ):
     """The blocked Cholesky of M at a single block, at whole blocks and with a
     ragged last block, against LAPACK's factor of the same M (FP64), and
-    the factor's product against M."""
+    the factor's product against M.  Also xi and K psi against the oracle:
+    1 to 3 row blocks of the short-K product over 14 column tiles (fewer
+    than two per XCD, so that some persistent workgroups take one tile and
+    some none)."""
     print(f"case ace cholesky n_occ={n_occ}", flush=True)
     rng = np.random.default_rng(n_occ)
     N = 12
@@ -244,8 +247,15 @@ def test_ace_cholesky_blocked_sizes(n_occ):
     A = rng.standard_normal((n_occ, n_occ))
     W = (A @ A.T / n_occ + np.eye(n_occ)) @ phi
     ctx = sea.Context()
-    M, Lm, _, fp = ctx.ace_build(_dev(phi), _dev(W), dV)
+    M, Lm, xi, fp = ctx.ace_build(_dev(phi), _dev(W), dV)
     assert fp == 0
+    want_ace = oracle.ace_build(phi, W, dV)
+    xi_h = xi.cpu().numpy()
+    assert np.max(np.abs(xi_h - want_ace.xi)) <= 1e-10 * np.max(np.abs(want_ace.xi))
+    psi = rng.standard_normal((70, ng)) / np.sqrt(ng * dV)
+    K = ctx.ace_apply(xi, _dev(psi), dV).cpu().numpy()
+    Kw = oracle.ace_apply(want_ace.xi, psi, dV)
+    assert np.max(np.abs(K - Kw)) <= 1e-10 * np.max(np.abs(Kw))
     Mh = M.cpu().numpy()
     Mh = 0.5 * (Mh + Mh.T)
     Lh = Lm.cpu().numpy()
