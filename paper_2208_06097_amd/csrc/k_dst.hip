@@ -121,12 +121,14 @@ struct DstArgs {
     const sea_pair* pairs;
     const DevCell* cells;
     const int* pair_cell;
-    size_t stride;
+    size_t stride;        // pair layout (b, x, the face corrections)
+    size_t pstride;       // the padded intermediates
     const double* in;
     double* out;
     const double* opt;
     const double* mu;
-    const double* add;    // plane pass: added to `in` on the face points (nullable)
+    const double* add;    // plane pass: added to `in` on the face points (nullable, pair layout)
+    int in_pad, out_pad;  // plane pitch of in / out: dst_plane_pitch(nx*ny, pad)
     const int* skip;      // pairs to leave alone (nullable)
     int pair0;            // z-line pass: first pair of the launch (long calls run in chunks)
 };
@@ -293,8 +295,8 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
             }
         }
     };
-    const double* in = d.in + (size_t)pid * d.stride;
-    double* out = d.out + (size_t)pid * d.stride;
+    const double* in = d.in + (size_t)pid * (d.in_pad ? d.pstride : d.stride);
+    double* out = d.out + (size_t)pid * (d.out_pad ? d.pstride : d.stride);
     const double* add = d.add ? d.add + (size_t)pid * d.stride : nullptr;
     // the face correction of plane zz at this thread's elements (0 elsewhere)
     auto load_add = [&](int zz, double ad[DP_PT]) {
@@ -305,8 +307,11 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
             ad[u] = (zf || near_face(xx, nx) || near_face(yy, ny)) ? add[zo + e] : 0.0;
         });
     };
+    const int pin = dst_plane_pitch(npl, d.in_pad), pout = dst_plane_pitch(npl, d.out_pad);
     for (int z = blockIdx.y; z < nz; z += PG) {
-        const size_t zo = (size_t)z * npl;
+        // the plane's uniform bases; elements by 32-bit offsets from them
+        const double* __restrict__ inz = in + (size_t)z * pin;
+        double* __restrict__ outz = out + (size_t)z * pout;
         int gk = g, Nxk = Nx, Nyk = Ny;
         // recompute the fold addresses and the output modes per plane rather
         // than keep them all live
@@ -315,7 +320,7 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
 #pragma unroll
         for (int u = 0; u < DP_PT; ++u) {
             const int e = threadIdx.x + u * DP_BS;
-            val[u] = e < npl ? in[zo + e] : 0.0;
+            val[u] = e < npl ? inz[e] : 0.0;
         }
         if (add) {   // the face correction, its loads in flight with the plane's
             double ad[DP_PT];
@@ -402,7 +407,7 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
             }
         }
         lds_sync();
-        for_elems([&](int, int e, int o) { out[zo + e] = B[o]; });
+        for_elems([&](int, int e, int o) { outz[e] = B[o]; });
     }
 }
 
@@ -428,6 +433,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
     if (nx > DS_N || ny > DS_N || nz > DS_N) return;
     const int ncol = nx * ny;
     if (tg * DS_TC >= ncol || (d.skip && d.skip[pid]) || ((nz & 1) != 0) != F2) return;
+    const int pin = dst_plane_pitch(ncol, d.in_pad), pout = dst_plane_pitch(ncol, d.out_pad);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int hb = w & 1, bp = 2 * (w >> 1);
@@ -448,8 +454,8 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
     const double lzj = lane < nz ? d.mu[mu_off(nz) + lane] * ihz : 0.0;   // z part for mode j = lane
     __shared__ double lzs[F2 ? DS_N : 1];   // the same by mode, for the second-level fold
     if (F2 && threadIdx.x < DS_N) lzs[threadIdx.x] = lzj;   // (read after the first tile's barrier)
-    const double* in = d.in + (size_t)pid * d.stride;
-    double* out = d.out + (size_t)pid * d.stride;
+    const double* in = d.in + (size_t)pid * (d.in_pad ? d.pstride : d.stride);
+    double* out = d.out + (size_t)pid * (d.out_pad ? d.pstride : d.stride);
     // load element u of a thread: row a = threadIdx.x / 64 + 4 u, column threadIdx.x % 64
     const int lc = threadIdx.x % DS_TC, la = threadIdx.x / DS_TC;
     for (int c0 = tg * DS_TC; c0 < ncol; c0 += PG * DS_TC) {
@@ -463,7 +469,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
         // the previous tile (the barrier), the others go straight to LDS
         // 32-bit element offsets walked per tile (not precomputed per load and
         // held across tiles)
-        int off = la * ncol + c0 + lc;
+        int off = la * pin + c0 + lc;
         asm volatile("" : "+v"(off));
 #pragma unroll
         for (int u0 = 0; u0 < DP_PT; u0 += LB) {
@@ -472,7 +478,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
             for (int u = 0; u < LB; ++u) {
                 const int a = la + 4 * (u0 + u);
                 val[u] = (cl && a < nz) ? in[off] : 0.0;
-                off += 4 * ncol;
+                off += 4 * pin;
             }
             if (u0 == 0) lds_sync();
 #pragma unroll
@@ -510,7 +516,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int j = dst_mode2(q, gk + 4 * v, Nzk);
-                        if (j >= 0) out[j * ncol + col] = dst_val2(acc, q, v);   // 32-bit offsets (< 64^3)
+                        if (j >= 0) out[j * pout + col] = dst_val2(acc, q, v);   // 32-bit offsets (< 2^31)
                     }
             }
         } else {
@@ -566,7 +572,7 @@ __global__ __launch_bounds__(DP_BS, 4) void k_dst_zline(DstArgs d) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int j = 2 * (16 * hb + g + 4 * v) + par;
-                        if (j < nz) out[j * ncol + col] = acc[a][par][v];   // 32-bit offsets (< 64^3)
+                        if (j < nz) out[j * pout + col] = acc[a][par][v];   // 32-bit offsets (< 2^31)
                     }
             }
         }
@@ -621,6 +627,7 @@ DstArgs dst_args(const ExxArgs& a, double* tab, double* mu) {
     d.cells = a.cells;
     d.pair_cell = a.pair_cell;
     d.stride = a.stride;
+    d.pstride = a.pstride;
     d.opt = tab;
     d.mu = mu;
     return d;
@@ -656,6 +663,8 @@ hipError_t launch_dst_pass(const ExxArgs& a, int pass, int variant, int shape, c
     DstArgs d = dst_args(a, tab, mu);
     d.in = in;
     d.out = out;
+    d.in_pad = pass != 0;   // the layouts of the spectral start's passes
+    d.out_pad = pass != 2;
     if (pass == 1) launch_zline(d, a.n_pairs, variant, shape, s);
     else launch_plane(d, a.n_pairs, variant, shape, s);
     return hipGetLastError();
@@ -669,20 +678,25 @@ hipError_t launch_dst_solve(const ExxArgs& a, const double* r, double* z, double
     d.skip = skip;
     d.in = r;
     d.out = tmp;
+    d.out_pad = 1;
     launch_plane(d, a.n_pairs, pv, shape, s);
     d.in = tmp;
     d.out = tmp2;
+    d.in_pad = 1;
     launch_zline(d, a.n_pairs, zv, shape, s);
     d.in = tmp2;
     d.out = z;
+    d.out_pad = 0;
     launch_plane(d, a.n_pairs, pv, shape, s);
     return hipGetLastError();
 }
 
 // x = S^-1 ((S (b + fcorr)) ./ lambda) for every pair whose axes are all <=
 // 64 (fcorr added on the face points; it lives in tmp, scratch of the pair
-// arrays' size, which the passes then overwrite); r is scratch of the same
-// size.  pv, zv: plane and z-line variants; shape: DST_* bits of the pairs the
+// arrays' size, which the z-line pass then overwrites); r is scratch of the
+// same size.  The intermediate arrays have padded planes (whole 128-byte
+// lines): the forward planes write r, the z lines r -> tmp, the inverse
+// planes tmp -> x.  pv, zv: plane and z-line variants; shape: DST_* bits of the pairs the
 // transform takes.
 hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, double* tab, double* mu, int pv, int zv,
                                  int shape, hipStream_t s, const std::function<void(int, bool)>& mark) {
@@ -690,22 +704,25 @@ hipError_t launch_spectral_start(const ExxArgs& a, double* r, double* tmp, doubl
     if (pv < 0 || pv >= kNumPlane || zv < 0 || zv >= kNumZline) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_dst_tables, dim3(DS_N), dim3(DS_BS), 0, s, tab, mu);
     DstArgs d = dst_args(a, tab, mu);
-    // planes forward: b + fcorr (in tmp) -> tmp; z lines forward, divided,
-    // inverse: tmp -> r; planes inverse: r -> x
+    // planes forward: b + fcorr (in tmp) -> r; z lines forward, divided,
+    // inverse: r -> tmp; planes inverse: tmp -> x
     d.in = a.b;
     d.add = tmp;
-    d.out = tmp;
+    d.out = r;
+    d.out_pad = 1;
     mark(0, true);
     launch_plane(d, a.n_pairs, pv, shape, s);
     mark(0, false);
     d.add = nullptr;
-    d.in = tmp;
-    d.out = r;
+    d.in = r;
+    d.out = tmp;
+    d.in_pad = 1;
     mark(1, true);
     launch_zline(d, a.n_pairs, zv, shape, s);
     mark(1, false);
-    d.in = r;
+    d.in = tmp;
     d.out = a.v;
+    d.out_pad = 0;
     mark(2, true);
     launch_plane(d, a.n_pairs, pv, shape, s);
     mark(2, false);

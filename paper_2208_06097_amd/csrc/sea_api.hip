@@ -230,14 +230,19 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v, bool eag
     const sea_pair* pairs = S.pairs.data();
     size_t stride = 1;
     int nz_max = 1, nmax = 1;
+    size_t pstride = 1;
     for (int k = 0; k < n_pairs; ++k) {
-        size_t n = (size_t)pairs[k].n[0] * pairs[k].n[1] * pairs[k].n[2];
+        const size_t n = (size_t)pairs[k].n[0] * pairs[k].n[1] * pairs[k].n[2];
         if (n > stride) stride = n;
+        // the nz planes at the sine-transform passes' padded pitch
+        const size_t pn = (size_t)dst_plane_pitch(pairs[k].n[0] * pairs[k].n[1], 1) * pairs[k].n[2];
+        if (pn > pstride) pstride = pn;
         nz_max = pairs[k].n[2] > nz_max ? pairs[k].n[2] : nz_max;
         for (int d = 0; d < 3; ++d) nmax = pairs[k].n[d] > nmax ? pairs[k].n[d] : nmax;
     }
     stride = (stride + 31) / 32 * 32;
     L.stride = stride;
+    L.pstride = std::max(stride, (pstride + 31) / 32 * 32);
     L.slot_stride = (size_t)64 * 64 * (nz_max + 1);
     if (L.slot_stride < stride) L.slot_stride = stride;
     L.n_chunks = exx_n_chunks((long)stride);
@@ -273,8 +278,8 @@ ExxLayout exx_layout(const sea_ctx* ctx, const CellSet& S, bool with_v, bool eag
     // residual update)
     const bool spectral = ctx->opts.start == SEA_START_SPECTRAL;
     L.bres = ((ctx->opts.start != SEA_START_ZERO && ctx->opts.stencil_dtype == SEA_F64) || spectral)
-                 ? take(np * stride * sizeof(double)) : 0;
-    L.dst_tmp = spectral ? take(np * stride * sizeof(double)) : 0;
+                 ? take(np * L.pstride * sizeof(double)) : 0;   // also a sine-transform intermediate
+    L.dst_tmp = spectral ? take(np * L.pstride * sizeof(double)) : 0;
     L.dst_tab = spectral ? take(dst_table_doubles() * sizeof(double)) : 0;
     L.dst_mu = spectral ? take(dst_mu_doubles() * sizeof(double)) : 0;
     const bool pcg = eager && cg64_pcg(ctx, S);
@@ -534,6 +539,7 @@ static ExxArgs exx_args(sea_ctx* ctx, const CellSet& S, const ExxLayout& Ly, cha
     a.b = (double*)(base + Ly.b);
     a.v = v_ext ? v_ext : (double*)(base + Ly.v);
     a.stride = Ly.stride;
+    a.pstride = Ly.pstride;
     a.slots = (double*)(base + Ly.slots);
     a.slot_stride = Ly.slot_stride;
     a.n_slots = Ly.n_slots;

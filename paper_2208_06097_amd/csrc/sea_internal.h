@@ -81,6 +81,7 @@ struct ExxLayout {
     int n_zchunks;
     int n_slots;
     size_t stride;        // doubles per pair-domain array (max interior size)
+    size_t pstride;       // doubles per pair of the sine-transform intermediates (padded planes)
     size_t slot_stride;   // elements per CG slot array
 };
 
@@ -119,6 +120,7 @@ struct ExxArgs {
     double* fcorr;        // spectral start: -D x0 on the face points (the transform's scratch array)
     double* v;            // n_pairs x stride
     size_t stride;
+    size_t pstride;       // per pair of the sine-transform intermediates (dst_plane_pitch planes)
     double* slots;        // n_slots x 3 x slot_stride elements (state precision)
     size_t slot_stride;   // elements per slot array (64 x 64 x max nz for the z-march)
     int n_slots;
@@ -279,6 +281,11 @@ hipError_t launch_fill_nan(double* p, size_t n, hipStream_t s);
 // some has an odd nz; some has an even nz (the z-line kernels of each kind
 // launched only when needed).
 enum { DST_SQUARE = 1, DST_ZODD = 2, DST_ZEVEN = 4 };
+// Plane pitch (doubles) of the sine-transform passes' intermediate arrays:
+// each z plane of nx*ny points padded to whole 128-byte lines (pad = 1), or
+// the pair layout itself (pad = 0).  The intermediates' per-pair stride
+// (pstride) leaves room for nz padded planes.
+__host__ __device__ inline int dst_plane_pitch(int npl, int pad) { return pad ? (npl + 15) & ~15 : npl; }
 // Spectral start (k_dst.hip): x = A_odd^-1 (b + a.fcorr on the face points)
 // for the pairs with every axis <= 64 (a.fcorr is tmp, scratch of the pair
 // arrays' size; r scratch of the same size).
