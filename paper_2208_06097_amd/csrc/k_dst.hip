@@ -128,7 +128,9 @@ struct DstArgs {
     const double* opt;
     const double* mu;
     const double* add;    // plane pass: added to `in` on the face points (nullable, pair layout)
-    int in_pad, out_pad;  // plane pitch of in / out: dst_plane_pitch(nx*ny, pad)
+    int in_pad, out_pad;  // plane pitch of in / out: dst_plane_pitch(nx*ny, pad); a plane
+                          // pass with out_pad is the forward one (pair layout in, padded
+                          // out), without it the inverse (padded in, pair layout out)
     const int* skip;      // pairs to leave alone (nullable)
     int pair0;            // z-line pass: first pair of the launch (long calls run in chunks)
 };
@@ -242,7 +244,9 @@ __device__ __forceinline__ void dst_xform2(const double* row, int n, int g, cons
 // workgroups per pair; SQ: every plane the call transforms is square
 // (nx = ny), so one operand set serves both axes (32 fewer registers, four
 // workgroups per CU instead of three).
-template <int PG, bool SQ>
+// FWD: the forward pass (pair layout in, padded planes out); else the
+// inverse (padded in, pair layout out)
+template <int PG, bool SQ, bool FWD>
 __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
     __shared__ double B[DS_N * DP_LD];
     const int pid = blockIdx.x;
@@ -295,8 +299,8 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
             }
         }
     };
-    const double* in = d.in + (size_t)pid * (d.in_pad ? d.pstride : d.stride);
-    double* out = d.out + (size_t)pid * (d.out_pad ? d.pstride : d.stride);
+    const double* in = d.in + (size_t)pid * (FWD ? d.stride : d.pstride);
+    double* out = d.out + (size_t)pid * (FWD ? d.pstride : d.stride);
     const double* add = d.add ? d.add + (size_t)pid * d.stride : nullptr;
     // the face correction of plane zz at this thread's elements (0 elsewhere)
     auto load_add = [&](int zz, double ad[DP_PT]) {
@@ -307,7 +311,7 @@ __global__ __launch_bounds__(DP_BS, SQ ? 4 : 3) void k_dst_plane(DstArgs d) {
             ad[u] = (zf || near_face(xx, nx) || near_face(yy, ny)) ? add[zo + e] : 0.0;
         });
     };
-    const int pin = dst_plane_pitch(npl, d.in_pad), pout = dst_plane_pitch(npl, d.out_pad);
+    const int pin = dst_plane_pitch(npl, !FWD), pout = dst_plane_pitch(npl, FWD);
     for (int z = blockIdx.y; z < nz; z += PG) {
         // the plane's uniform bases; elements by 32-bit offsets from them
         const double* __restrict__ inz = in + (size_t)z * pin;
@@ -589,7 +593,7 @@ namespace {
 using DstKernel = void (*)(DstArgs);
 struct PlaneVariant {
     const char* name;
-    DstKernel gen, sq;   // general planes / every plane square
+    DstKernel gen, sq, gen_inv, sq_inv;   // general planes / every plane square; forward, inverse
     int pg;
 };
 struct ZlineVariant {
@@ -598,9 +602,12 @@ struct ZlineVariant {
     int pg;
 };
 const PlaneVariant kPlaneVariants[] = {
-    {"plane-pg16", k_dst_plane<16, false>, k_dst_plane<16, true>, 16},
-    {"plane-pg8", k_dst_plane<8, false>, k_dst_plane<8, true>, 8},
-    {"plane-pg32", k_dst_plane<32, false>, k_dst_plane<32, true>, 32},
+    {"plane-pg16", k_dst_plane<16, false, true>, k_dst_plane<16, true, true>, k_dst_plane<16, false, false>,
+     k_dst_plane<16, true, false>, 16},
+    {"plane-pg8", k_dst_plane<8, false, true>, k_dst_plane<8, true, true>, k_dst_plane<8, false, false>,
+     k_dst_plane<8, true, false>, 8},
+    {"plane-pg32", k_dst_plane<32, false, true>, k_dst_plane<32, true, true>, k_dst_plane<32, false, false>,
+     k_dst_plane<32, true, false>, 32},
 };
 const ZlineVariant kZlineVariants[] = {
     {"zline-pg16-lb16", k_dst_zline<16, 16, false>, k_dst_zline<16, 16, true>, 16},
@@ -634,7 +641,10 @@ DstArgs dst_args(const ExxArgs& a, double* tab, double* mu) {
 }
 void launch_plane(const DstArgs& d, int n_pairs, int pv, int shape, hipStream_t s) {
     const PlaneVariant& V = kPlaneVariants[pv];
-    hipLaunchKernelGGL((shape & DST_SQUARE) ? V.sq : V.gen, dim3((unsigned)n_pairs, V.pg), dim3(DP_BS), 0, s, d);
+    const bool sq = (shape & DST_SQUARE) != 0;
+    // the forward pass writes the padded planes, the inverse reads them
+    const DstKernel k = d.out_pad ? (sq ? V.sq : V.gen) : (sq ? V.sq_inv : V.gen_inv);
+    hipLaunchKernelGGL(k, dim3((unsigned)n_pairs, V.pg), dim3(DP_BS), 0, s, d);
 }
 void launch_zline(const DstArgs& d, int n_pairs, int zv, int shape, hipStream_t s) {
     const ZlineVariant& V = kZlineVariants[zv];
